@@ -1,0 +1,291 @@
+"""TEST INFRASTRUCTURE ONLY: ctypes wrapper of the FP64 CPU oracle.
+
+Only tests/, the smoke check and the benchmark's CPU-baseline leg may import
+this module.  It loads ``oracle/libfsoracle.so`` (built from ``fsoracle.c`` by
+``build_oracle()``), takes the same plain parameter dict as the GPU library,
+and returns numpy arrays.  It imports nothing from the GPU package.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsoracle.so")
+SOURCES = ["fsoracle.c", "fsoracle_adj.c"]
+
+PUSH, BOUNDARY, INJECT, DEPOSIT, FIELD = 1, 2, 4, 8, 16
+ALL = 31
+WALL = {"open": 0, "faux_shock": 1, "specular": 2}
+XBC = {"box": 0, "periodic": 1}
+SHAPE = {"cic": 1, "tsc": 2, 1: 1, 2: 2}
+
+
+def build_oracle(force: bool = False) -> str:
+    """Compile the oracle with gcc (plain -O2, no FP contraction)."""
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    if not force and os.path.exists(LIB_PATH):
+        newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(HERE, "fsoracle.h")])
+        if os.path.getmtime(LIB_PATH) >= newest:
+            return LIB_PATH
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fPIC", "-shared",
+           "-o", LIB_PATH + ".tmp"] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class OraCfg(C.Structure):
+    _fields_ = [
+        ("dx", C.c_double), ("dt", C.c_double),
+        ("u_sh", C.c_double), ("beta_i", C.c_double), ("beta_e", C.c_double),
+        ("gamma_e", C.c_double), ("theta_deg", C.c_double), ("r", C.c_double),
+        ("n_cr", C.c_double), ("cr_w", C.c_double), ("alpha_cr", C.c_double),
+        ("j_ext", C.c_double),
+        ("n_floor", C.c_double), ("eta", C.c_double), ("mode_amp", C.c_double),
+        ("v_max", C.c_double),
+        ("seed", C.c_uint64),
+        ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("ppc", C.c_int32), ("ppc_cr", C.c_int32), ("shape", C.c_int32),
+        ("deposit_mode", C.c_int32),
+        ("wall_th", C.c_int32), ("wall_cr", C.c_int32), ("xbc", C.c_int32),
+        ("n_sub", C.c_int32),
+        ("n_modes", C.c_int32), ("inject", C.c_int32), ("replay", C.c_int32),
+        ("pad0", C.c_int32),
+    ]
+
+
+class OraStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "incident", "reflected", "transmitted", "open_removed", "escaped",
+        "injected_th", "injected_cr", "saturated", "out_of_range")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+def make_cfg(p: dict, deposit_mode: str = "fixed") -> OraCfg:
+    c = OraCfg()
+    for k in ("dx", "dt", "u_sh", "beta_i", "beta_e", "gamma_e", "theta_deg", "r", "n_cr",
+              "cr_w", "alpha_cr", "j_ext", "n_floor", "eta", "mode_amp", "v_max"):
+        setattr(c, k, float(p[k]))
+    c.seed = int(p["seed"])
+    for k in ("dim", "nx", "ny", "nz", "ppc", "ppc_cr", "n_sub", "n_modes"):
+        setattr(c, k, int(p[k]))
+    c.shape = SHAPE[p["shape"]]
+    c.deposit_mode = 0 if deposit_mode == "fixed" else 1
+    c.wall_th = WALL[p["wall_th"]]
+    c.wall_cr = WALL[p["wall_cr"]]
+    c.xbc = XBC[p["xbc"]]
+    c.inject = 1 if p.get("inject", True) else 0
+    return c
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build_oracle()
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.ora_new.restype = vp
+        L.ora_new.argtypes = [C.POINTER(OraCfg)]
+        L.ora_free.argtypes = [vp]
+        L.ora_init.argtypes = [vp, vp]
+        L.ora_step.argtypes = [vp, i32, C.POINTER(OraStats)]
+        for f in ("ora_count",):
+            getattr(L, f).restype = i64
+            getattr(L, f).argtypes = [vp, i32]
+        for f in ("ora_next_id", "ora_get_step"):
+            getattr(L, f).restype = i64
+            getattr(L, f).argtypes = [vp]
+        L.ora_set_clock.argtypes = [vp, i64, i64]
+        L.ora_set_particles.argtypes = [vp, i32, i64, vp, vp, vp, vp]
+        L.ora_get_particles.argtypes = [vp, i32, vp, vp, vp, vp]
+        for f in ("ora_set_B", "ora_get_B", "ora_set_E", "ora_get_E", "ora_get_Bbar",
+                  "ora_profile", "ora_diag", "ora_sizes", "ora_fixed_point"):
+            getattr(L, f).argtypes = [vp, vp]
+        L.ora_compute_E.argtypes = [vp]
+        for f in ("ora_get_moments", "ora_get_cmoments", "ora_set_moments"):
+            getattr(L, f).argtypes = [vp, i32, vp]
+        L.ora_get_fluid.argtypes = [vp, vp, vp]
+        L.ora_loss.restype = dp
+        L.ora_loss.argtypes = [vp]
+        L.ora_wall_list.argtypes = [C.POINTER(OraCfg), i64, i32, i64, vp, vp, vp, vp, vp]
+        L.ora_philox.argtypes = [vp, C.c_uint64, C.c_uint64, vp]
+        L.ora_inject_counts.argtypes = [C.POINTER(OraCfg), i64, vp]
+        L.ora_record.argtypes = [vp, i32]
+        if hasattr(L, "ora_adjoint"):
+            L.ora_adjoint.argtypes = [C.POINTER(OraCfg), vp, i32, i32, vp, vp, vp]
+            L.ora_replay_loss.argtypes = [C.POINTER(OraCfg), vp, i32, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def philox(ctr, key):
+    """Philox4x64-10 block for a 4-word counter and 2-word key (uint64)."""
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint64))
+    out = np.zeros(4, dtype=np.uint64)
+    lib().ora_philox(_p(c), int(key[0]), int(key[1]), _p(out))
+    return out
+
+
+def inject_counts(p: dict, step: int):
+    out = np.zeros(2, dtype=np.int64)
+    lib().ora_inject_counts(C.byref(make_cfg(p)), int(step), _p(out))
+    return int(out[0]), int(out[1])
+
+
+def wall_list(p: dict, step: int, species: int, ids, delta, v):
+    """Apply the wall to a list of crossers; returns (outcome, v_new, xi_new)."""
+    ids = np.ascontiguousarray(ids, dtype=np.uint64)
+    delta = np.ascontiguousarray(delta, dtype=np.float64)
+    v = np.ascontiguousarray(np.array(v, dtype=np.float64).reshape(-1, 3))
+    n = len(ids)
+    xi = np.zeros(n)
+    out = np.zeros(n, dtype=np.int32)
+    lib().ora_wall_list(C.byref(make_cfg(p)), int(step), int(species), n, _p(ids), _p(delta),
+                        _p(v), _p(xi), _p(out))
+    return out, v, xi
+
+
+class Oracle:
+    """One FP64 simulation box held by the C oracle."""
+
+    def __init__(self, p: dict, deposit_mode: str = "fixed"):
+        self.p = dict(p)
+        self.cfg = make_cfg(p, deposit_mode)
+        self.h = lib().ora_new(C.byref(self.cfg))
+        if not self.h:
+            raise ValueError("oracle rejected the configuration")
+        s = np.zeros(6, dtype=np.int64)
+        lib().ora_sizes(self.h, _p(s))
+        self.nxn, self.ndx, self.nyc, self.nzc, self.ncent, self.nnode = (int(x) for x in s)
+        fp = np.zeros(3, dtype=np.int32)
+        lib().ora_fixed_point(self.h, _p(fp))
+        self.b, self.sv, self.SW = (int(x) for x in fp)
+        self.ndep = self.ndx * self.nyc * self.nzc
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().ora_free(h)
+            self.h = None
+
+    # --- evolution -------------------------------------------------------
+    def init(self, amps=None):
+        a = None
+        if amps is not None:
+            a = np.ascontiguousarray(amps, dtype=np.float64)
+        return lib().ora_init(self.h, _p(a) if a is not None else None)
+
+    def step(self, flags: int = ALL) -> dict:
+        st = OraStats()
+        lib().ora_step(self.h, int(flags), C.byref(st))
+        return st.as_dict()
+
+    def compute_E(self):
+        lib().ora_compute_E(self.h)
+
+    # --- state -----------------------------------------------------------
+    @property
+    def step_index(self) -> int:
+        return int(lib().ora_get_step(self.h))
+
+    @property
+    def next_id(self) -> int:
+        return int(lib().ora_next_id(self.h))
+
+    def set_clock(self, step: int, next_id: int):
+        lib().ora_set_clock(self.h, int(step), int(next_id))
+
+    def count(self, species: int = 0) -> int:
+        return int(lib().ora_count(self.h, species))
+
+    def particles(self, species: int = 0) -> dict:
+        n = self.count(species)
+        cell = np.zeros((n, 3), dtype=np.int64)
+        off = np.zeros((n, 3))
+        v = np.zeros((n, 3))
+        ids = np.zeros(n, dtype=np.uint64)
+        if n:
+            lib().ora_get_particles(self.h, species, _p(cell), _p(off), _p(v), _p(ids))
+        return dict(cell=cell, off=off, v=v, id=ids)
+
+    def set_particles(self, species: int, cell, off, v, ids):
+        cell = np.ascontiguousarray(np.asarray(cell, dtype=np.int64).reshape(-1, 3))
+        off = np.ascontiguousarray(np.asarray(off, dtype=np.float64).reshape(-1, 3))
+        v = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1, 3))
+        ids = np.ascontiguousarray(ids, dtype=np.uint64)
+        lib().ora_set_particles(self.h, species, len(ids), _p(cell), _p(off), _p(v), _p(ids))
+
+    def B(self):
+        out = np.zeros((self.ncent, 3))
+        lib().ora_get_B(self.h, _p(out))
+        return out
+
+    def set_B(self, B):
+        B = np.ascontiguousarray(np.asarray(B, dtype=np.float64).reshape(self.ncent, 3))
+        lib().ora_set_B(self.h, _p(B))
+
+    def E(self):
+        out = np.zeros((self.nnode, 3))
+        lib().ora_get_E(self.h, _p(out))
+        return out
+
+    def set_E(self, E):
+        E = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(self.nnode, 3))
+        lib().ora_set_E(self.h, _p(E))
+
+    def Bbar(self):
+        out = np.zeros((self.nnode, 3))
+        lib().ora_get_Bbar(self.h, _p(out))
+        return out
+
+    def moments(self, species: int = 0):
+        out = np.zeros((self.ndep, 4), dtype=np.int64)
+        lib().ora_get_moments(self.h, species, _p(out))
+        return out
+
+    def set_moments(self, species: int, m):
+        m = np.ascontiguousarray(np.asarray(m, dtype=np.int64).reshape(self.ndep, 4))
+        lib().ora_set_moments(self.h, species, _p(m))
+
+    def cmoments(self, species: int = 0):
+        out = np.zeros((self.ndep, 4))
+        lib().ora_get_cmoments(self.h, species, _p(out))
+        return out
+
+    def fluid(self):
+        n = np.zeros(self.nnode)
+        g = np.zeros((self.nnode, 3))
+        lib().ora_get_fluid(self.h, _p(n), _p(g))
+        return n, g
+
+    def profile(self):
+        out = np.zeros(int(self.p["nx"]))
+        lib().ora_profile(self.h, _p(out))
+        return out
+
+    def loss(self) -> float:
+        return float(lib().ora_loss(self.h))
+
+    def diag(self) -> dict:
+        out = np.zeros(8)
+        lib().ora_diag(self.h, _p(out))
+        keys = ("field_energy", "kinetic_th", "kinetic_cr", "n_th", "n_cr", "loss",
+                "max_divB", "bperp2")
+        return dict(zip(keys, (float(x) for x in out)))
+
+    def record(self, on: bool = True):
+        lib().ora_record(self.h, 1 if on else 0)

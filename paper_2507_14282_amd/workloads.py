@@ -1,0 +1,74 @@
+"""Workload definitions: raw parameter sets of the synthetic runs.
+
+Pure data, no arithmetic of the method: each preset is a plain dict of the
+physical and numerical parameters of one run, shaped like the paper's 1D/2D/3D
+faux-shock runs (Table 1 lists box sizes, M_A, dt, theta_Bn, n_cr/n_g and
+p_iso for Runs A and B).  The GPU library binding and the CPU oracle both take
+such a dict; each derives everything else (u2 = u_sh/r, injection rates,
+macro-particle weights, fixed-point format) on its own.
+
+Units are the paper's (Sec. 2): lengths in d_i, time in 1/Omega_ci, speeds in
+v_A, fields in B0, densities in n_g.  The flow enters at x = 0 and moves in +x
+toward the faux-shock wall at x = L.
+"""
+
+from __future__ import annotations
+
+import copy
+
+# Defaults shared by every preset (a parameter missing from a preset takes this).
+DEFAULTS = dict(
+    dim=1, nx=64, ny=1, nz=1, dx=0.5, dt=0.005,
+    ppc=16, ppc_cr=16, shape="cic",
+    u_sh=20.0, beta_i=1.0, beta_e=1.0, gamma_e=5.0 / 3.0,
+    theta_deg=0.0, r=4.0,
+    n_cr=0.0, cr_w=89.44271909999159, alpha_cr=1.0, j_ext=0.0,
+    wall_th="faux_shock", wall_cr="faux_shock", xbc="box",
+    n_floor=0.05, eta=0.0, n_sub=1, v_max=1024.0,
+    seed=1000, n_modes=0, mode_amp=1e-3, inject=True,
+    precision=32, steps=10,
+)
+
+# cr_w is the CR speed in the downstream frame, sqrt(20) u_sh, so that the CR
+# kinetic energy m cr_w^2 / 2 is ten times m u_sh^2 (written out as a literal
+# for each Mach number; Run A of the paper uses p_iso / m = 5 u_sh).
+PRESETS = {
+    # 1D3V FP64 parity box: 512 cells, 64 ppc, FS acting on the thermal ions.
+    "cfg1": dict(dim=1, nx=512, dx=0.5, dt=0.005, ppc=64, u_sh=20.0, beta_i=1.0,
+                 theta_deg=0.0, n_cr=0.0, wall_th="faux_shock", seed=1001,
+                 precision=64, steps=1000),
+    # 1D3V FP32: 32768 cells, 1024 ppc, TSC, CRs at 1% density from the wall.
+    "cfg2": dict(dim=1, nx=32768, dx=0.5, dt=0.0025, ppc=1024, ppc_cr=1024,
+                 shape="tsc", u_sh=20.0, beta_i=1.0, theta_deg=0.0, n_cr=0.01,
+                 cr_w=89.44271909999159, wall_th="open", wall_cr="faux_shock",
+                 seed=1002, precision=32, steps=20000),
+    # 2D3V FP32: 8192 x 512 cells, 16 ppc, M_A = 30, CRs from the wall.
+    "cfg3": dict(dim=2, nx=8192, ny=512, dx=0.5, dt=0.002, ppc=16, ppc_cr=16,
+                 u_sh=30.0, beta_i=1.0, theta_deg=0.0, n_cr=0.01,
+                 cr_w=134.16407864998737, wall_th="open", wall_cr="faux_shock",
+                 seed=1003, precision=32, steps=5000),
+    # 3D3V FP32: 1024 x 192 x 192 cells, 8 ppc, theta_Bn = 45 deg.
+    "cfg4": dict(dim=3, nx=1024, ny=192, nz=192, dx=1.0, dt=0.005, ppc=8,
+                 u_sh=20.0, beta_i=1.0, theta_deg=45.0, n_cr=0.0,
+                 wall_th="faux_shock", seed=1004, precision=32, steps=2000),
+    # 1D3V adjoint run: 2048 cells, 256 ppc, CRs, 64 seeded Fourier modes.
+    "cfg5": dict(dim=1, nx=2048, dx=0.5, dt=0.005, ppc=256, ppc_cr=256,
+                 u_sh=20.0, beta_i=1.0, theta_deg=0.0, n_cr=0.01,
+                 cr_w=89.44271909999159, wall_th="open", wall_cr="faux_shock",
+                 n_modes=64, mode_amp=1e-3, seed=1005, precision=32, steps=400),
+}
+
+
+def preset(name: str, **overrides) -> dict:
+    """Full parameter dict of a named preset, with overrides applied."""
+    p = copy.deepcopy(DEFAULTS)
+    p.update(PRESETS[name])
+    p.update(overrides)
+    return p
+
+
+def params(**kw) -> dict:
+    """Parameter dict from the defaults with the given overrides."""
+    p = copy.deepcopy(DEFAULTS)
+    p.update(kw)
+    return p
