@@ -1,0 +1,209 @@
+/*
+ * fshybrid.h -- C ABI of the MI355X (gfx950) library for the data-parallel
+ * hot path of the faux-shock hybrid particle-in-cell method
+ * (Simon, Caprioli, Haggerty & Reville 2025, "A 'Faux-Shock' Method for
+ * Hybrid Simulations of Astrophysical Shocks").
+ *
+ * One time step is: kinetic-ion Boris push with E/B gather, the faux-shock
+ * (FS) wall that transmits each crossing ion or reflects it with a
+ * downstream-isotropic kick (return probability of eq. 1, Sec. 2), thermal
+ * injection at x = 0 and cosmic-ray (CR) injection at the wall (Sec. 2),
+ * fixed-point moment deposition, and the massless-electron Ohm's-law E plus
+ * Faraday B update of the hybrid model (Sec. 2, first paragraph after
+ * Table 1).
+ *
+ * Conventions
+ *  - Units are the paper's (Sec. 2): d_i, 1/Omega_ci, v_A, B0, n_g; q/m = 1.
+ *    The upstream plasma enters at x = 0 and flows in +x toward the FS wall
+ *    at x = L = nx*dx; y and z are periodic.
+ *  - Every call returns an int status: FS_OK (0) or a negative FS_E* code.
+ *    fs_last_error() gives a static description of the last error.
+ *  - All work is enqueued on the hipStream_t passed in (NULL = default
+ *    stream).  Statistics are valid once the stream has been synchronised;
+ *    calls that take an fs_step_stats* synchronise the stream themselves.
+ *  - Ownership: the caller allocates (e.g. with torch) and owns every
+ *    particle, field and moment buffer, with the sizes fs_layout() reports,
+ *    and passes raw device pointers.  The library owns only the handle and
+ *    its scratch (crosser lists, field stage buffers, counters), freed by
+ *    fs_destroy().  The library never reallocates caller memory.
+ *  - Errors FS_EINVAL, FS_ECAPACITY and FS_EIDOVERFLOW are detected on the
+ *    host before any work is enqueued: the state is unchanged.  FS_ENUMERIC
+ *    (NaN, velocity-code saturation), FS_ETILE (a tile or crosser list
+ *    overflowed on the device) and FS_EDEVICE (HIP error) leave the state
+ *    undefined: restore a checkpoint.
+ */
+#ifndef FSHYBRID_H
+#define FSHYBRID_H
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FS_OK           0
+#define FS_EINVAL      -1   /* bad configuration or argument (state unchanged) */
+#define FS_ECAPACITY   -2   /* caller buffer too small (state unchanged) */
+#define FS_EIDOVERFLOW -3   /* particle ids would pass 2^32 - 1 (state unchanged) */
+#define FS_ENUMERIC    -4   /* NaN or saturated velocity code (state undefined) */
+#define FS_EDEVICE     -5   /* HIP runtime error (state undefined) */
+#define FS_ETILE       -6   /* device-side tile / crosser overflow (state undefined) */
+
+/* wall policy per species: what happens to an ion that reaches x >= L */
+#define FS_WALL_OPEN        0   /* leaves the box (thermal ions in the paper, Sec. 2) */
+#define FS_WALL_FAUX_SHOCK  1   /* eq. (1) return probability + downstream-isotropic kick */
+#define FS_WALL_SPECULAR    2   /* mirror reflection (reflecting-wall variant) */
+
+#define FS_XBC_BOX       0      /* inflow at x = 0, wall at x = L */
+#define FS_XBC_PERIODIC  1      /* periodic x (test boxes) */
+
+/* fs_step flags */
+#define FS_PUSH    1u   /* gather + Boris + move + boundaries + FS wall */
+#define FS_INJECT  4u   /* thermal injection at x = 0, CR injection at x = L */
+#define FS_DEPOSIT 8u   /* fixed-point moments at the new positions */
+#define FS_FIELD  16u   /* SSP-RK3 Faraday update with frozen moments, then Ohm */
+#define FS_ALL    (FS_PUSH | FS_INJECT | FS_DEPOSIT | FS_FIELD)
+
+/* Run configuration.  Field meaning follows the paper's Table 1 and Sec. 2:
+ * u_sh is the upstream flow speed in the shock frame, r the compression
+ * ratio (u2 = u_sh / r, eq. 1), n_cr the CR density in units of n_g, cr_w
+ * the CR speed in the downstream frame at injection, alpha_cr a multiplier
+ * on the CR macro-particle weight (the "CR current" parameter), j_ext a
+ * rigid external current along x, v_max the largest speed the run expects
+ * (it sets the fixed-point velocity scale, see fs_layout_info.sv_bits).
+ * Field order is mirrored by the Python binding. */
+typedef struct fs_config {
+    double dx, dt;
+    double u_sh, beta_i, beta_e, gamma_e, theta_deg, r;
+    double n_cr, cr_w, alpha_cr, j_ext;
+    double n_floor, eta, mode_amp, v_max;
+    double cap_factor_th, cap_factor_cr;   /* tile capacity / mean occupancy */
+    uint64_t seed;
+    int32_t dim, nx, ny, nz;
+    int32_t ppc, ppc_cr, shape, precision;  /* shape 1 = CIC, 2 = TSC; precision 32 or 64 */
+    int32_t wall_th, wall_cr, xbc, n_sub;
+    int32_t n_modes, inject, pad0, pad1;
+} fs_config;
+
+/* Sizes the caller must allocate, reported by fs_layout(). */
+typedef struct fs_layout_info {
+    int64_t ncent;          /* cell centres: B lives here, 3 planar FP64 arrays */
+    int64_t nnode;          /* field nodes: E and the gather grid live here */
+    int64_t ndep;           /* deposit nodes (field nodes + TSC ghosts in x) */
+    int64_t nxn, ndx, nyc, nzc;
+    int64_t ntiles;
+    int64_t tile_cap[2];    /* particle slots per tile, per species */
+    int64_t capacity[2];    /* ntiles * tile_cap: slots per particle buffer */
+    int64_t buf_bytes[2];   /* bytes of one particle buffer (two are needed) */
+    int64_t gather_bytes;   /* bytes of the gather grid */
+    int32_t tile[3], ntile[3];
+    int32_t b_bits, sv_bits, sw_bits;   /* fixed-point format */
+    int32_t cell_bits[3];   /* packed cell index: bit widths of x, y, z */
+    int32_t real_bytes;     /* 4 (FP32 mode) or 8 (FP64 mode) */
+    int32_t pad;
+} fs_layout_info;
+
+/* Particles of one species.  Each of the two buffers holds, in this order,
+ * sections of `capacity` entries, each section starting on a 256-byte
+ * boundary:
+ *   int32  cell      packed cell index: ix | iy << cell_bits[0] |
+ *                    iz << (cell_bits[0] + cell_bits[1])
+ *   real   off[d]    in-cell offset in [0, 1), one section per dimension
+ *   real   v[3]      velocity (v^{n-1/2} before a step, v^{n+1/2} after)
+ *   uint32 id        unique particle id (keys the wall's random numbers)
+ * Slots [t*tile_cap, t*tile_cap + tile_count[t]) of buffer `cur` hold the
+ * live particles of tile t; fs_step writes the other buffer and flips cur. */
+typedef struct fs_particles {
+    void*    buf[2];
+    int32_t* tile_count[2]; /* device, ntiles entries each */
+    int64_t* count;         /* device, live particles (updated by fs_step) */
+    int64_t  capacity;
+    int64_t  tile_cap;
+    int32_t  cur;
+    int32_t  species;       /* 0 thermal ions, 1 CRs */
+} fs_particles;
+
+/* Grid state, all device pointers owned by the caller. */
+typedef struct fs_fields {
+    double*  B;        /* centres: 3 planar arrays of ncent (Bx, By, Bz) */
+    double*  E;        /* nodes: 3 planar arrays of nnode, E^n (FP64) */
+    void*    gather;   /* nodes: nnode x 8 reals (Ex Ey Ez 0 Bbarx Bbary Bbarz 0) */
+    int64_t* mom[2];   /* per species: ndep x 4 int64 (R, Gx, Gy, Gz) */
+} fs_fields;
+
+typedef struct fs_step_stats {
+    int64_t incident, reflected, transmitted, open_removed, escaped;
+    int64_t injected_th, injected_cr, saturated, out_of_range;
+    int64_t count[2];      /* live particles per species after the step */
+    int64_t next_id;
+    int32_t flags;         /* device error bits (1 tile overflow, 2 crosser
+                              overflow, 4 NaN, 8 saturation) */
+    int32_t pad;
+} fs_step_stats;
+
+typedef struct fs_handle fs_handle;
+
+/* Validates cfg and fills *out with the buffer sizes of the run. */
+int fs_layout(const fs_config* cfg, fs_layout_info* out);
+
+/* Creates a handle (validates cfg, allocates library scratch). */
+int fs_create(const fs_config* cfg, fs_handle** out);
+void fs_destroy(fs_handle* h);
+const char* fs_last_error(const fs_handle* h);
+
+/* Loads the box (Sec. 2): B = B0 (cos theta, sin theta, 0) plus n_modes
+ * Fourier modes of amplitude amps[m] (device pointer, or NULL for mode_amp)
+ * with Philox phases; ppc thermal ions per cell with uniform offsets and a
+ * drifting Maxwellian (u_sh, sqrt(beta_i/2)); ids cell-major; deposits the
+ * moments and computes E^0 by Ohm's law.  Resets the step clock. */
+int fs_init_plasma(fs_handle* h, fs_particles* sp, fs_fields* f, const double* amps,
+                   hipStream_t s);
+
+/* One step (or the sub-steps selected by flags) from step index `step`.
+ * With stats != NULL the stream is synchronised and device errors are
+ * returned; otherwise the call is fully asynchronous. */
+int fs_step(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t flags,
+            fs_step_stats* st, hipStream_t s);
+
+/* Deposits both species' moments from the current particles (overwrites). */
+int fs_deposit_moments(fs_handle* h, const fs_particles* sp, fs_fields* f, hipStream_t s);
+
+/* FS wall (eq. 1, Sec. 2) applied to a caller list of n crossers (device
+ * arrays): id, delta = overshoot beyond x = L in cells, v (3 x n planar,
+ * FP64, overwritten for reflected ions).  outcome[i] = 1 reflect, 0
+ * transmit; xi_new[i] = new x in cells for reflected ions. */
+int fs_apply_faux_shock(fs_handle* h, int32_t species, int64_t step, int64_t n,
+                        const uint32_t* id, const double* delta, double* v,
+                        int32_t* outcome, double* xi_new, hipStream_t s);
+
+/* Faraday update with SSP-RK3 (moments frozen) and the final Ohm's law:
+ * B^n -> B^{n+1}, E^{n+1}, gather grid. */
+int fs_field_update(fs_handle* h, fs_fields* f, hipStream_t s);
+
+/* E and the gather grid from the current B and moments (Ohm's law only). */
+int fs_refresh_fields(fs_handle* h, fs_fields* f, hipStream_t s);
+
+/* Host-side state access (tests, checkpoints of small runs).  Arrays are
+ * host memory: cell3 int64 (n x 3), off3 and v3 double (n x 3), id uint64.
+ * fs_read_particles with cell3 == NULL only reports the count in *n. */
+int fs_load_particles(fs_handle* h, fs_particles* sp, int64_t n, const int64_t* cell3,
+                      const double* off3, const double* v3, const uint64_t* id, hipStream_t s);
+int fs_read_particles(fs_handle* h, const fs_particles* sp, int64_t* n, int64_t* cell3,
+                      double* off3, double* v3, uint64_t* id, hipStream_t s);
+
+/* Step clock and id counter kept by the handle. */
+int fs_set_clock(fs_handle* h, int64_t next_id);
+int64_t fs_next_id(const fs_handle* h);
+
+/* Diagnostics (FP64, deterministic): out[8] = field energy, kinetic energy
+ * of thermal ions and CRs, particle counts, precursor loss
+ * sum_{x >= L/2} (By^2 + Bz^2), max |div B| over interior nodes, total
+ * By^2 + Bz^2.  prof (optional, device, nx) = sum over y, z of By^2 + Bz^2. */
+int fs_diagnostics(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out8,
+                   double* prof, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

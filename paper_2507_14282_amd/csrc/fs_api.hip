@@ -1,0 +1,824 @@
+// fs_api.hip -- host runtime and C ABI of the faux-shock hybrid library.
+//
+// Owns the handle (configuration, derived layout, library scratch) and
+// enqueues the kernels of fs_kernels.h / fs_field.h on the caller's stream.
+// See include/fshybrid.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fs_field.h"
+#include "fshybrid.h"
+
+using namespace fsk;
+
+struct fs_handle {
+    fs_config cfg;
+    fs_layout_info L;
+    Geo G;
+    FieldGeo F;
+    int64_t next_id = 0;
+    bool has_cr = false;
+    unsigned long long* ctr = nullptr;       // device counters
+    unsigned long long* ctr_host = nullptr;  // pinned mirror
+    XList xl[2];
+    void* xl_mem[2] = {nullptr, nullptr};
+    double* B1 = nullptr;
+    double* B2 = nullptr;
+    double* Etmp = nullptr;
+    double* fluid = nullptr;
+    double* phase = nullptr;
+    double* part = nullptr;
+    int64_t npart = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(fs_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    g_err = msg;
+    return code;
+}
+
+int hip_check(fs_handle* h, hipError_t e, const char* what) {
+    if (e == hipSuccess) return FS_OK;
+    return fail(h, FS_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+int bits_for(int64_t n) {
+    int b = 1;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+// s_v = 23 - ceil(log2 v_max): the largest expected speed maps just under 2^23.
+int sv_for(double v_max) {
+    int e;
+    double m = frexp(v_max, &e);
+    if (m == 0.5) e -= 1;
+    return 23 - e;
+}
+
+void tile_shape(int dim, int t[3]) {
+    if (dim == 1) { t[0] = TileShape<1>::X; t[1] = 1; t[2] = 1; }
+    else if (dim == 2) { t[0] = TileShape<2>::X; t[1] = TileShape<2>::Y; t[2] = 1; }
+    else { t[0] = TileShape<3>::X; t[1] = TileShape<3>::Y; t[2] = TileShape<3>::Z; }
+}
+
+int lds_bytes(int dim, int shape, int rb, bool gather) {
+    int t[3];
+    tile_shape(dim, t);
+    int w = shape == 2 ? 3 : 1;
+    int gx = t[0] + w, gy = dim >= 2 ? t[1] + w : 1, gz = dim >= 3 ? t[2] + w : 1;
+    int dx = t[0] + 2 + w, dy = dim >= 2 ? t[1] + 2 + w : 1, dz = dim >= 3 ? t[2] + 2 + w : 1;
+    return (gather ? 8 * rb * gx * gy * gz : 0) + 32 * dx * dy * dz;
+}
+
+int compute_layout(const fs_config* c, fs_layout_info* L, std::string& err) {
+    std::memset(L, 0, sizeof(*L));
+    if (c->dim < 1 || c->dim > 3) { err = "dim must be 1, 2 or 3"; return FS_EINVAL; }
+    if (c->shape != 1 && c->shape != 2) { err = "shape must be 1 (CIC) or 2 (TSC)"; return FS_EINVAL; }
+    if (c->precision != 32 && c->precision != 64) { err = "precision must be 32 or 64"; return FS_EINVAL; }
+    if (c->xbc != FS_XBC_BOX && c->xbc != FS_XBC_PERIODIC) { err = "bad x boundary"; return FS_EINVAL; }
+    if (c->nx < 2 * c->shape + 2) { err = "nx too small"; return FS_EINVAL; }
+    if (c->dim >= 2 && c->ny < 2) { err = "ny must be >= 2"; return FS_EINVAL; }
+    if (c->dim >= 3 && c->nz < 2) { err = "nz must be >= 2"; return FS_EINVAL; }
+    if (!(c->dx > 0) || !(c->dt > 0)) { err = "dx and dt must be positive"; return FS_EINVAL; }
+    if (c->ppc < 0 || c->ppc_cr < 0) { err = "ppc must be non-negative"; return FS_EINVAL; }
+    if (!(c->v_max > 0)) { err = "v_max must be positive"; return FS_EINVAL; }
+    if (!(c->r > 0)) { err = "compression ratio must be positive"; return FS_EINVAL; }
+    if (c->n_sub < 1) { err = "n_sub must be >= 1"; return FS_EINVAL; }
+    for (int w : {c->wall_th, c->wall_cr})
+        if (w < FS_WALL_OPEN || w > FS_WALL_SPECULAR) { err = "bad wall policy"; return FS_EINVAL; }
+    if (c->n_modes < 0) { err = "n_modes must be >= 0"; return FS_EINVAL; }
+    const bool has_cr = c->n_cr > 0.0;
+    if (has_cr && c->ppc_cr < 1) { err = "ppc_cr must be >= 1 with CRs"; return FS_EINVAL; }
+    int t[3];
+    tile_shape(c->dim, t);
+    L->tile[0] = t[0]; L->tile[1] = t[1]; L->tile[2] = t[2];
+    L->nyc = c->dim >= 2 ? c->ny : 1;
+    L->nzc = c->dim >= 3 ? c->nz : 1;
+    L->nxn = c->xbc == FS_XBC_PERIODIC ? c->nx : c->nx + 1;
+    const int g = (c->xbc == FS_XBC_BOX && c->shape == 2) ? 1 : 0;
+    L->ndx = L->nxn + 2 * g;
+    L->ncent = (int64_t)c->nx * L->nyc * L->nzc;
+    L->nnode = L->nxn * L->nyc * L->nzc;
+    L->ndep = L->ndx * L->nyc * L->nzc;
+    L->ntile[0] = (c->nx + t[0] - 1) / t[0];
+    L->ntile[1] = (int32_t)((L->nyc + t[1] - 1) / t[1]);
+    L->ntile[2] = (int32_t)((L->nzc + t[2] - 1) / t[2]);
+    L->ntiles = (int64_t)L->ntile[0] * L->ntile[1] * L->ntile[2];
+    L->cell_bits[0] = bits_for(c->nx);
+    L->cell_bits[1] = c->dim >= 2 ? bits_for(c->ny) : 0;
+    L->cell_bits[2] = c->dim >= 3 ? bits_for(c->nz) : 0;
+    if (L->cell_bits[0] + L->cell_bits[1] + L->cell_bits[2] > 31) { err = "grid too large for a packed int32 cell"; return FS_EINVAL; }
+    const int64_t cells = (int64_t)t[0] * t[1] * t[2];
+    const int rb = c->precision == 64 ? 8 : 4;
+    L->real_bytes = rb;
+    double cf0 = c->cap_factor_th > 0 ? c->cap_factor_th : 2.0;
+    double cf1 = c->cap_factor_cr > 0 ? c->cap_factor_cr : 4.0;
+    L->tile_cap[0] = round_up(std::max<int64_t>((int64_t)std::ceil(cf0 * c->ppc * cells), c->ppc * cells + 64), 64);
+    L->tile_cap[1] = has_cr ? round_up(std::max<int64_t>((int64_t)std::ceil(cf1 * c->ppc_cr * cells), 64), 64) : 0;
+    for (int s = 0; s < 2; ++s) {
+        L->capacity[s] = L->ntiles * L->tile_cap[s];
+        int64_t cap = L->capacity[s];
+        int64_t bytes = round_up(cap * 4, 256) + c->dim * round_up(cap * rb, 256) + 3 * round_up(cap * rb, 256) +
+                        round_up(cap * 4, 256);
+        L->buf_bytes[s] = cap ? bytes : 0;
+    }
+    if (L->tile_cap[0] > INT32_MAX || L->tile_cap[1] > INT32_MAX) { err = "tile capacity too large"; return FS_EINVAL; }
+    L->gather_bytes = L->nnode * 8 * rb;
+    static const int cic[4] = {0, 22, 11, 7}, tsc[4] = {0, 10, 5, 3};
+    L->b_bits = c->shape == 2 ? tsc[c->dim] : cic[c->dim];
+    L->sv_bits = sv_for(c->v_max);
+    L->sw_bits = c->shape == 2 ? c->dim * (2 * L->b_bits + 1) : c->dim * L->b_bits;
+    if (lds_bytes(c->dim, c->shape, rb, true) > 160 * 1024) { err = "tile does not fit in LDS"; return FS_EINVAL; }
+    return FS_OK;
+}
+
+void inject_counts(const fs_config& c, int64_t step, int64_t& th, int64_t& cr) {
+    th = cr = 0;
+    if (c.xbc != FS_XBC_BOX || !c.inject) return;
+    double F = (double)c.ppc * c.u_sh * c.dt / c.dx;
+    if (F > 0.0) th = (int64_t)(std::floor(F * (double)(step + 1)) - std::floor(F * (double)step));
+    double u2 = c.u_sh / c.r;
+    if (c.n_cr > 0.0 && c.wall_cr == FS_WALL_FAUX_SHOCK && c.cr_w > u2) {
+        double Fc = (double)c.ppc_cr * (c.cr_w - u2) * c.dt / (2.0 * c.dx);
+        cr = (int64_t)(std::floor(Fc * (double)(step + 1)) - std::floor(Fc * (double)step));
+    }
+}
+
+template <typename R> PBuf<R> sections(void* base, int64_t cap, int dim) {
+    char* p = static_cast<char*>(base);
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) {
+        char* q = p + off;
+        off += round_up(bytes, 256);
+        return q;
+    };
+    PBuf<R> b;
+    b.cell = reinterpret_cast<int32_t*>(take(cap * 4));
+    for (int d = 0; d < 3; ++d) b.off[d] = d < dim ? reinterpret_cast<R*>(take(cap * sizeof(R))) : nullptr;
+    for (int c = 0; c < 3; ++c) b.v[c] = reinterpret_cast<R*>(take(cap * sizeof(R)));
+    b.id = reinterpret_cast<uint32_t*>(take(cap * 4));
+    return b;
+}
+
+// Dynamic LDS above the default limit must be requested per kernel.
+template <typename K> void allow_lds(K kernel, size_t bytes) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)bytes);
+}
+
+unsigned grid_for(int64_t n, int block = 256) { return (unsigned)std::max<int64_t>(1, (n + block - 1) / block); }
+
+int policy_of(const fs_handle* h, int s) { return s == 0 ? h->cfg.wall_th : h->cfg.wall_cr; }
+
+void zero_u64(void* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_u64<<<std::min<unsigned>(grid_for(n), 4096u), 256, 0, s>>>(static_cast<unsigned long long*>(p), 0ull, n);
+}
+void zero_i32(int32_t* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_fill_i32<<<std::min<unsigned>(grid_for(n), 4096u), 256, 0, s>>>(p, 0, n);
+}
+
+// ------------------------------------------------------------------------
+// field update (FP64)
+// ------------------------------------------------------------------------
+template <typename R> void field_update(fs_handle* h, fs_fields* f, hipStream_t s, bool rk) {
+    const long nn = h->L.nnode, nc = h->L.ncent;
+    const unsigned gn = grid_for(nn), gc = grid_for(nc);
+    k_fluid<<<gn, 256, 0, s>>>(h->F, reinterpret_cast<const long long*>(f->mom[0]),
+                              reinterpret_cast<const long long*>(h->has_cr ? f->mom[1] : f->mom[0]), h->fluid, nn);
+    if (rk) {
+        const double hs = h->cfg.dt / (double)h->cfg.n_sub;
+        for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
+            k_ohm<R><<<gn, 256, 0, s>>>(h->F, f->B, h->fluid, h->Etmp, nullptr, nn, nc);
+            k_faraday<<<gc, 256, 0, s>>>(h->F, h->Etmp, f->B, f->B, h->B1, 0.0, 1.0, hs, nn, nc);
+            k_ohm<R><<<gn, 256, 0, s>>>(h->F, h->B1, h->fluid, h->Etmp, nullptr, nn, nc);
+            k_faraday<<<gc, 256, 0, s>>>(h->F, h->Etmp, f->B, h->B1, h->B2, 0.75, 0.25, hs, nn, nc);
+            k_ohm<R><<<gn, 256, 0, s>>>(h->F, h->B2, h->fluid, h->Etmp, nullptr, nn, nc);
+            k_faraday<<<gc, 256, 0, s>>>(h->F, h->Etmp, f->B, h->B2, f->B, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc);
+        }
+    }
+    k_ohm<R><<<gn, 256, 0, s>>>(h->F, f->B, h->fluid, f->E, static_cast<R*>(f->gather), nn, nc);
+}
+
+// ------------------------------------------------------------------------
+// one step, templated on precision, dimensionality and shape
+// ------------------------------------------------------------------------
+template <typename R, int D, int S>
+int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t flags, hipStream_t s) {
+    const bool push = flags & FS_PUSH, inj = flags & FS_INJECT, dep = flags & FS_DEPOSIT, fld = flags & FS_FIELD;
+    const int nsp = h->has_cr ? 2 : 1;
+    const fs_config& c = h->cfg;
+    int64_t cth = 0, ccr = 0;
+    if (inj) inject_counts(c, step, cth, ccr);
+    const int64_t ntr = h->L.nyc * h->L.nzc;
+    const int64_t ninj = (cth + ccr) * ntr;
+    if (h->next_id + ninj > (int64_t)UINT32_MAX + 1) return fail(h, FS_EIDOVERFLOW, "particle ids would overflow 32 bits");
+    Geo G = h->G;
+    zero_u64(h->ctr, C_N, s);
+    if (dep)
+        for (int k = 0; k < nsp; ++k) zero_u64(f->mom[k], 4 * h->L.ndep, s);
+    using X = Extent<D, S>;
+    const size_t lds_push = sizeof(R) * 8 * X::GN + (dep ? 32 * X::DN : 0);
+    if (push) {
+        for (int k = 0; k < nsp; ++k) {
+            zero_i32(sp[k].tile_count[sp[k].cur ^ 1], h->L.ntiles, s);
+            zero_i32(h->xl[k].count, 1, s);
+        }
+        for (int k = 0; k < nsp; ++k) {
+            fs_particles& P = sp[k];
+            PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
+            PBuf<R> out = sections<R>(P.buf[P.cur ^ 1], P.capacity, D);
+            auto* mom = reinterpret_cast<unsigned long long*>(f->mom[k]);
+            if (dep) allow_lds(k_push<R, D, S, true>, lds_push);
+            else allow_lds(k_push<R, D, S, false>, lds_push);
+            if (dep)
+                k_push<R, D, S, true><<<(unsigned)h->L.ntiles, 256, lds_push, s>>>(
+                    G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, static_cast<const R*>(f->gather),
+                    mom, h->xl[k], h->ctr, policy_of(h, k), k);
+            else
+                k_push<R, D, S, false><<<(unsigned)h->L.ntiles, 256, lds_push, s>>>(
+                    G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, static_cast<const R*>(f->gather),
+                    mom, h->xl[k], h->ctr, policy_of(h, k), k);
+        }
+        if (c.xbc == FS_XBC_BOX) {
+            for (int k = 0; k < nsp; ++k) {
+                if (policy_of(h, k) == FS_WALL_OPEN) continue;
+                fs_particles& P = sp[k];
+                PBuf<R> out = sections<R>(P.buf[P.cur ^ 1], P.capacity, D);
+                unsigned gw = std::min<unsigned>(grid_for(h->xl[k].cap), 1024u);
+                auto* mom = reinterpret_cast<unsigned long long*>(f->mom[k]);
+                if (dep)
+                    k_wall<R, D, S, true><<<gw, 256, 0, s>>>(G, h->xl[k], out, P.tile_count[P.cur ^ 1], P.tile_cap, mom,
+                                                            h->ctr, policy_of(h, k), k, (uint64_t)step);
+                else
+                    k_wall<R, D, S, false><<<gw, 256, 0, s>>>(G, h->xl[k], out, P.tile_count[P.cur ^ 1], P.tile_cap, mom,
+                                                             h->ctr, policy_of(h, k), k, (uint64_t)step);
+            }
+        }
+    }
+    if (inj && ninj > 0) {
+        fs_particles& P0 = sp[0];
+        const int t0 = push ? P0.cur ^ 1 : P0.cur;
+        PBuf<R> o0 = sections<R>(P0.buf[t0], P0.capacity, D);
+        PBuf<R> o1 = o0;
+        int32_t* c1 = P0.tile_count[t0];
+        int64_t cap1 = P0.tile_cap;
+        unsigned long long* m1 = reinterpret_cast<unsigned long long*>(f->mom[0]);
+        if (h->has_cr) {
+            fs_particles& P1 = sp[1];
+            const int t1 = push ? P1.cur ^ 1 : P1.cur;
+            o1 = sections<R>(P1.buf[t1], P1.capacity, D);
+            c1 = P1.tile_count[t1];
+            cap1 = P1.tile_cap;
+            m1 = reinterpret_cast<unsigned long long*>(f->mom[1]);
+        }
+        auto* m0 = reinterpret_cast<unsigned long long*>(f->mom[0]);
+        if (dep && push)
+            k_inject<R, D, S, true><<<grid_for(ninj), 256, 0, s>>>(G, o0, P0.tile_count[t0], P0.tile_cap, m0, o1, c1, cap1, m1,
+                                                                  h->ctr, (uint64_t)step, h->next_id, cth, ccr, ntr);
+        else
+            k_inject<R, D, S, false><<<grid_for(ninj), 256, 0, s>>>(G, o0, P0.tile_count[t0], P0.tile_cap, m0, o1, c1, cap1, m1,
+                                                                   h->ctr, (uint64_t)step, h->next_id, cth, ccr, ntr);
+    }
+    if (push)
+        for (int k = 0; k < nsp; ++k) sp[k].cur ^= 1;
+    if (dep && !push) {
+        const size_t lds_dep = 32 * X::DN;
+        for (int k = 0; k < nsp; ++k) {
+            fs_particles& P = sp[k];
+            PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
+            allow_lds(k_deposit<R, D, S>, lds_dep);
+            k_deposit<R, D, S><<<(unsigned)h->L.ntiles, 256, lds_dep, s>>>(
+                G, in, P.tile_count[P.cur], P.tile_cap, reinterpret_cast<unsigned long long*>(f->mom[k]), h->ctr);
+        }
+    }
+    if (fld) field_update<R>(h, f, s, true);
+    k_count_update<<<1, 64, 0, s>>>(sp[0].count, h->has_cr ? sp[1].count : nullptr, h->ctr);
+    h->next_id += ninj;
+    int rc = hip_check(h, hipGetLastError(), "kernel launch");
+    if (rc) return rc;
+    return hip_check(h, hipMemcpyAsync(h->ctr_host, h->ctr, C_N * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+                     "stats copy");
+}
+
+template <typename R, int D>
+int init_impl(fs_handle* h, fs_particles* sp, fs_fields* f, const double* amps, hipStream_t s) {
+    const fs_config& c = h->cfg;
+    const long nc = h->L.ncent;
+    if (c.n_modes > 0) k_phases<<<grid_for(c.n_modes), 256, 0, s>>>(c.seed, c.n_modes, h->phase);
+    k_init_B<<<grid_for(nc), 256, 0, s>>>(h->F, c.n_modes, amps, c.mode_amp, h->phase, (double)c.nx * c.dx, f->B, nc);
+    const long np = nc * (long)c.ppc;
+    fs_particles& P = sp[0];
+    P.cur = 0;
+    PBuf<R> out = sections<R>(P.buf[0], P.capacity, D);
+    if (np > 0) k_init_particles<R, D><<<grid_for(np), 256, 0, s>>>(h->G, out, P.tile_cap, c.ppc, np);
+    k_init_counts<D><<<grid_for(h->L.ntiles), 256, 0, s>>>(h->G, P.tile_count[0], c.ppc);
+    k_set_i64<<<1, 1, 0, s>>>(P.count, np);
+    if (h->has_cr) {
+        sp[1].cur = 0;
+        zero_i32(sp[1].tile_count[0], h->L.ntiles, s);
+        k_set_i64<<<1, 1, 0, s>>>(sp[1].count, 0);
+    }
+    h->next_id = np;
+    return FS_OK;
+}
+
+template <typename R, int D, int S> int deposit_impl(fs_handle* h, const fs_particles* sp, fs_fields* f, hipStream_t s) {
+    using X = Extent<D, S>;
+    const int nsp = h->has_cr ? 2 : 1;
+    zero_u64(h->ctr, C_N, s);
+    for (int k = 0; k < nsp; ++k) {
+        zero_u64(f->mom[k], 4 * h->L.ndep, s);
+        const fs_particles& P = sp[k];
+        PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
+        allow_lds(k_deposit<R, D, S>, 32 * X::DN);
+        k_deposit<R, D, S><<<(unsigned)h->L.ntiles, 256, 32 * X::DN, s>>>(
+            h->G, in, P.tile_count[P.cur], P.tile_cap, reinterpret_cast<unsigned long long*>(f->mom[k]), h->ctr);
+    }
+    return hip_check(h, hipGetLastError(), "deposit launch");
+}
+
+// Dispatch a templated implementation on (precision, dim, shape).
+#define FS_DISPATCH(h, CALL)                                                           \
+    do {                                                                               \
+        const int _d = (h)->cfg.dim, _s = (h)->cfg.shape;                              \
+        if ((h)->cfg.precision == 32) {                                                \
+            using R = float;                                                           \
+            if (_d == 1 && _s == 1) { constexpr int D = 1, S = 1; return CALL; }       \
+            if (_d == 1 && _s == 2) { constexpr int D = 1, S = 2; return CALL; }       \
+            if (_d == 2 && _s == 1) { constexpr int D = 2, S = 1; return CALL; }       \
+            if (_d == 2 && _s == 2) { constexpr int D = 2, S = 2; return CALL; }       \
+            if (_d == 3 && _s == 1) { constexpr int D = 3, S = 1; return CALL; }       \
+            if (_d == 3 && _s == 2) { constexpr int D = 3, S = 2; return CALL; }       \
+        } else {                                                                       \
+            using R = double;                                                          \
+            if (_d == 1 && _s == 1) { constexpr int D = 1, S = 1; return CALL; }       \
+            if (_d == 1 && _s == 2) { constexpr int D = 1, S = 2; return CALL; }       \
+            if (_d == 2 && _s == 1) { constexpr int D = 2, S = 1; return CALL; }       \
+            if (_d == 2 && _s == 2) { constexpr int D = 2, S = 2; return CALL; }       \
+            if (_d == 3 && _s == 1) { constexpr int D = 3, S = 1; return CALL; }       \
+            if (_d == 3 && _s == 2) { constexpr int D = 3, S = 2; return CALL; }       \
+        }                                                                              \
+        return fail(h, FS_EINVAL, "unsupported configuration");                        \
+    } while (0)
+
+int check_particles(fs_handle* h, const fs_particles* sp) {
+    const int nsp = h->has_cr ? 2 : 1;
+    for (int k = 0; k < nsp; ++k) {
+        const fs_particles& P = sp[k];
+        if (!P.buf[0] || !P.buf[1] || !P.tile_count[0] || !P.tile_count[1] || !P.count)
+            return fail(h, FS_EINVAL, "particle buffer pointer is NULL");
+        if (P.capacity < h->L.capacity[k] || P.tile_cap != h->L.tile_cap[k])
+            return fail(h, FS_ECAPACITY, "particle buffer smaller than fs_layout reports");
+        if (P.cur != 0 && P.cur != 1) return fail(h, FS_EINVAL, "cur must be 0 or 1");
+    }
+    return FS_OK;
+}
+
+int check_fields(fs_handle* h, const fs_fields* f) {
+    if (!f || !f->B || !f->E || !f->gather || !f->mom[0] || (h->has_cr && !f->mom[1]))
+        return fail(h, FS_EINVAL, "field pointer is NULL");
+    return FS_OK;
+}
+
+}  // namespace
+
+// ==========================================================================
+// C ABI
+// ==========================================================================
+extern "C" {
+
+int fs_layout(const fs_config* cfg, fs_layout_info* out) {
+    if (!cfg || !out) return fail(nullptr, FS_EINVAL, "NULL argument");
+    std::string err;
+    int rc = compute_layout(cfg, out, err);
+    if (rc) g_err = err;
+    return rc;
+}
+
+int fs_create(const fs_config* cfg, fs_handle** out) {
+    if (!cfg || !out) return fail(nullptr, FS_EINVAL, "NULL argument");
+    *out = nullptr;
+    fs_handle* h = new fs_handle();
+    h->cfg = *cfg;
+    std::string err;
+    int rc = compute_layout(cfg, &h->L, err);
+    if (rc) { g_err = err; delete h; return rc; }
+    const fs_config& c = h->cfg;
+    h->has_cr = c.n_cr > 0.0;
+    Geo& G = h->G;
+    G.dim = c.dim; G.nx = c.nx; G.nyc = (int)h->L.nyc; G.nzc = (int)h->L.nzc;
+    G.nxn = (int)h->L.nxn; G.ndx = (int)h->L.ndx; G.g = (int)((h->L.ndx - h->L.nxn) / 2);
+    G.xbc = c.xbc;
+    G.ntx = h->L.ntile[0]; G.nty = h->L.ntile[1]; G.ntz = h->L.ntile[2]; G.ntiles = (int)h->L.ntiles;
+    G.bx = h->L.cell_bits[0]; G.by = h->L.cell_bits[1];
+    G.b = h->L.b_bits; G.sv = h->L.sv_bits; G.mclamp = c.shape;
+    G.dt = c.dt; G.dx = c.dx; G.u_sh = c.u_sh; G.u2 = c.u_sh / c.r; G.sigma = std::sqrt(0.5 * c.beta_i);
+    G.cr_w = c.cr_w; G.dtdx = c.dt / c.dx; G.seed = c.seed;
+    FieldGeo& F = h->F;
+    F.dim = c.dim; F.nx = c.nx; F.nyc = G.nyc; F.nzc = G.nzc; F.nxn = G.nxn; F.ndx = G.ndx; F.g = G.g;
+    F.xbc = c.xbc; F.mclamp = c.shape; F.dx = c.dx;
+    const double th = c.theta_deg * (kTwoPi / 360.0);
+    F.B0[0] = std::cos(th); F.B0[1] = std::sin(th); F.B0[2] = 0.0;
+    F.n_floor = c.n_floor; F.beta_e = c.beta_e; F.gamma_e = c.gamma_e; F.eta = c.eta; F.j_ext = c.j_ext;
+    F.wth = c.ppc > 0 ? 1.0 / (double)c.ppc : 0.0;
+    F.wcr = h->has_cr ? c.alpha_cr * c.n_cr / (double)c.ppc_cr : 0.0;
+    F.scR = std::ldexp(1.0, -h->L.sw_bits);
+    F.scG = std::ldexp(1.0, -(h->L.sw_bits + h->L.sv_bits));
+    F.has_cr = h->has_cr ? 1 : 0;
+
+    auto dmalloc = [&](void** p, size_t bytes) -> bool {
+        return hipMalloc(p, std::max<size_t>(bytes, 256)) == hipSuccess;
+    };
+    bool ok = true;
+    ok = ok && dmalloc((void**)&h->ctr, C_N * sizeof(unsigned long long));
+    ok = ok && hipHostMalloc((void**)&h->ctr_host, C_N * sizeof(unsigned long long), hipHostMallocDefault) == hipSuccess;
+    const long nc = h->L.ncent, nn = h->L.nnode;
+    ok = ok && dmalloc((void**)&h->B1, 3 * nc * sizeof(double));
+    ok = ok && dmalloc((void**)&h->B2, 3 * nc * sizeof(double));
+    ok = ok && dmalloc((void**)&h->Etmp, 3 * nn * sizeof(double));
+    ok = ok && dmalloc((void**)&h->fluid, 5 * nn * sizeof(double));
+    ok = ok && dmalloc((void**)&h->phase, (c.n_modes + 1) * sizeof(double));
+    h->npart = std::max<int64_t>(grid_for(nc), h->L.ntiles) * 4;
+    ok = ok && dmalloc((void**)&h->part, h->npart * sizeof(double));
+    // crosser lists: a generous bound on the ions that can reach the wall in one step
+    for (int k = 0; k < 2 && ok; ++k) {
+        int64_t ppc = k == 0 ? c.ppc : c.ppc_cr;
+        int64_t cap = (k == 1 && !h->has_cr) ? 64 : h->L.nyc * h->L.nzc * std::max<int64_t>(ppc, 1) * 8 + 4096;
+        size_t bytes = 256 + 3 * round_up(cap * 8, 256) + round_up(3 * cap * 8, 256) + 3 * round_up(cap * 4, 256);
+        ok = dmalloc(&h->xl_mem[k], bytes);
+        if (!ok) break;
+        char* p = static_cast<char*>(h->xl_mem[k]);
+        XList& x = h->xl[k];
+        x.cap = cap;
+        x.count = reinterpret_cast<int32_t*>(p); p += 256;
+        x.delta = reinterpret_cast<double*>(p); p += round_up(cap * 8, 256);
+        x.oy = reinterpret_cast<double*>(p); p += round_up(cap * 8, 256);
+        x.oz = reinterpret_cast<double*>(p); p += round_up(cap * 8, 256);
+        x.v = reinterpret_cast<double*>(p); p += round_up(3 * cap * 8, 256);
+        x.id = reinterpret_cast<uint32_t*>(p); p += round_up(cap * 4, 256);
+        x.cy = reinterpret_cast<int32_t*>(p); p += round_up(cap * 4, 256);
+        x.cz = reinterpret_cast<int32_t*>(p);
+    }
+    if (!ok) {
+        fs_destroy(h);
+        return fail(nullptr, FS_EDEVICE, "device allocation of library scratch failed");
+    }
+    *out = h;
+    return FS_OK;
+}
+
+void fs_destroy(fs_handle* h) {
+    if (!h) return;
+    hipFree(h->ctr);
+    if (h->ctr_host) hipHostFree(h->ctr_host);
+    hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->phase); hipFree(h->part);
+    for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
+    delete h;
+}
+
+const char* fs_last_error(const fs_handle* h) {
+    if (h && !h->err.empty()) return h->err.c_str();
+    return g_err.c_str();
+}
+
+int fs_init_plasma(fs_handle* h, fs_particles* sp, fs_fields* f, const double* amps, hipStream_t s) {
+    if (!h || !sp || !f) return fail(h, FS_EINVAL, "NULL argument");
+    int rc = check_particles(h, sp);
+    if (!rc) rc = check_fields(h, f);
+    if (rc) return rc;
+    if ((int64_t)h->L.ncent * h->cfg.ppc > (int64_t)UINT32_MAX) return fail(h, FS_EIDOVERFLOW, "too many particles for 32-bit ids");
+    auto init = [&]() -> int { FS_DISPATCH(h, (init_impl<R, D>(h, sp, f, amps, s))); };
+    rc = init();
+    if (rc) return rc;
+    rc = fs_deposit_moments(h, sp, f, s);
+    if (rc) return rc;
+    return fs_refresh_fields(h, f, s);
+}
+
+int fs_step(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t flags, fs_step_stats* st, hipStream_t s) {
+    if (!h || !sp || !f) return fail(h, FS_EINVAL, "NULL argument");
+    if (flags & ~FS_ALL) return fail(h, FS_EINVAL, "unknown step flags");
+    if (step < 0) return fail(h, FS_EINVAL, "negative step");
+    int rc = check_particles(h, sp);
+    if (!rc) rc = check_fields(h, f);
+    if (rc) return rc;
+    auto run = [&]() -> int { FS_DISPATCH(h, (step_impl<R, D, S>(h, sp, f, step, flags, s))); };
+    rc = run();
+    if (rc) return rc;
+    if (!st) return FS_OK;
+    rc = hip_check(h, hipStreamSynchronize(s), "stream synchronise");
+    if (rc) return rc;
+    const unsigned long long* c = h->ctr_host;
+    std::memset(st, 0, sizeof(*st));
+    st->incident = (int64_t)c[C_INC];
+    st->reflected = (int64_t)c[C_REFL];
+    st->transmitted = (int64_t)c[C_TRANS];
+    st->open_removed = (int64_t)c[C_OPEN];
+    st->escaped = (int64_t)c[C_ESC];
+    st->injected_th = (int64_t)c[C_INJ_TH];
+    st->injected_cr = (int64_t)c[C_INJ_CR];
+    st->saturated = (int64_t)c[C_SAT];
+    st->out_of_range = (int64_t)c[C_OOR];
+    st->flags = (int32_t)c[C_FLAGS];
+    st->next_id = h->next_id;
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        rc = hip_check(h, hipMemcpy(&st->count[k], sp[k].count, sizeof(int64_t), hipMemcpyDeviceToHost), "count copy");
+        if (rc) return rc;
+    }
+    if (st->flags & (F_TILE | F_XLIST)) return fail(h, FS_ETILE, "a tile bin or the crosser list overflowed");
+    if (st->flags & (F_NAN | F_SAT)) return fail(h, FS_ENUMERIC, "NaN or saturated velocity code in the deposit");
+    return FS_OK;
+}
+
+int fs_deposit_moments(fs_handle* h, const fs_particles* sp, fs_fields* f, hipStream_t s) {
+    if (!h || !sp || !f) return fail(h, FS_EINVAL, "NULL argument");
+    int rc = check_particles(h, sp);
+    if (!rc) rc = check_fields(h, f);
+    if (rc) return rc;
+    auto run = [&]() -> int { FS_DISPATCH(h, (deposit_impl<R, D, S>(h, sp, f, s))); };
+    return run();
+}
+
+int fs_field_update(fs_handle* h, fs_fields* f, hipStream_t s) {
+    if (!h) return fail(h, FS_EINVAL, "NULL handle");
+    int rc = check_fields(h, f);
+    if (rc) return rc;
+    if (h->cfg.precision == 32) field_update<float>(h, f, s, true);
+    else field_update<double>(h, f, s, true);
+    return hip_check(h, hipGetLastError(), "field update launch");
+}
+
+int fs_refresh_fields(fs_handle* h, fs_fields* f, hipStream_t s) {
+    if (!h) return fail(h, FS_EINVAL, "NULL handle");
+    int rc = check_fields(h, f);
+    if (rc) return rc;
+    if (h->cfg.precision == 32) field_update<float>(h, f, s, false);
+    else field_update<double>(h, f, s, false);
+    return hip_check(h, hipGetLastError(), "field refresh launch");
+}
+
+}  // extern "C"
+
+namespace {
+__global__ void k_wall_list(Geo G, int policy, uint64_t step, int64_t n, const uint32_t* id, const double* delta,
+                            double* v, int32_t* outcome, double* xi_new) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double vin[3] = {v[i], v[n + i], v[2 * n + i]}, vout[3], back = 0.0;
+    int r = 0;
+    if (policy == FS_WALL_FAUX_SHOCK) r = faux_shock_event(G.seed, step, id[i], G.u2, delta[i], vin, vout, back);
+    else if (policy == FS_WALL_SPECULAR) {
+        vout[0] = -vin[0]; vout[1] = vin[1]; vout[2] = vin[2];
+        back = delta[i];
+        r = 1;
+    }
+    outcome[i] = r;
+    if (r) {
+        v[i] = vout[0]; v[n + i] = vout[1]; v[2 * n + i] = vout[2];
+        xi_new[i] = (double)G.nx - back;
+    } else {
+        xi_new[i] = 0.0;
+    }
+}
+}  // namespace
+
+extern "C" {
+
+int fs_apply_faux_shock(fs_handle* h, int32_t species, int64_t step, int64_t n, const uint32_t* id, const double* delta,
+                        double* v, int32_t* outcome, double* xi_new, hipStream_t s) {
+    if (!h) return fail(h, FS_EINVAL, "NULL handle");
+    if (species < 0 || species > 1 || n < 0) return fail(h, FS_EINVAL, "bad species or count");
+    if (n == 0) return FS_OK;
+    if (!id || !delta || !v || !outcome || !xi_new) return fail(h, FS_EINVAL, "NULL array");
+    k_wall_list<<<grid_for(n), 256, 0, s>>>(h->G, policy_of(h, species), (uint64_t)step, n, id, delta, v, outcome, xi_new);
+    return hip_check(h, hipGetLastError(), "wall launch");
+}
+
+int fs_set_clock(fs_handle* h, int64_t next_id) {
+    if (!h || next_id < 0) return fail(h, FS_EINVAL, "bad argument");
+    h->next_id = next_id;
+    return FS_OK;
+}
+
+int64_t fs_next_id(const fs_handle* h) { return h ? h->next_id : -1; }
+
+}  // extern "C"
+
+// --------------------------------------------------------------------------
+// host-side state access
+// --------------------------------------------------------------------------
+namespace {
+
+template <typename R, int D>
+int load_impl(fs_handle* h, fs_particles* sp, int64_t n, const int64_t* cell3, const double* off3, const double* v3,
+              const uint64_t* id, hipStream_t s) {
+    fs_particles& P = *sp;
+    const int64_t cap = P.tile_cap, ntiles = h->L.ntiles;
+    std::vector<int32_t> counts(ntiles, 0);
+    std::vector<int64_t> slot(n);
+    std::vector<int32_t> tile(n);
+    const int* T = h->L.tile;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t x = cell3[3 * i], y = cell3[3 * i + 1], z = cell3[3 * i + 2];
+        if (x < 0 || x >= h->cfg.nx || y < 0 || y >= h->L.nyc || z < 0 || z >= h->L.nzc)
+            return fail(h, FS_EINVAL, "particle cell out of the box");
+        for (int d = 0; d < 3; ++d)
+            if (!(off3[3 * i + d] >= 0.0 && off3[3 * i + d] < 1.0)) return fail(h, FS_EINVAL, "offset outside [0, 1)");
+        if (id[i] > UINT32_MAX) return fail(h, FS_EIDOVERFLOW, "id does not fit 32 bits");
+        int t = (int)(x / T[0] + h->L.ntile[0] * (y / T[1] + (int64_t)h->L.ntile[1] * (z / T[2])));
+        tile[i] = t;
+        slot[i] = counts[t]++;
+        if (counts[t] > cap) return fail(h, FS_ECAPACITY, "too many particles in one tile");
+    }
+    const int64_t C = P.capacity;
+    std::vector<int32_t> hcell(C, 0);
+    std::vector<uint32_t> hid(C, 0);
+    std::vector<R> hoff[3], hv[3];
+    for (int d = 0; d < D; ++d) hoff[d].assign(C, (R)0);
+    for (int c = 0; c < 3; ++c) hv[c].assign(C, (R)0);
+    const int bx = h->L.cell_bits[0], by = h->L.cell_bits[1];
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t dst = (int64_t)tile[i] * cap + slot[i];
+        hcell[dst] = (int32_t)(cell3[3 * i] | (cell3[3 * i + 1] << bx) | (cell3[3 * i + 2] << (bx + by)));
+        for (int d = 0; d < D; ++d) {
+            R o = (R)off3[3 * i + d];
+            hoff[d][dst] = o >= (R)1 ? std::nextafter((R)1, (R)0) : o;
+        }
+        for (int c = 0; c < 3; ++c) hv[c][dst] = (R)v3[3 * i + c];
+        hid[dst] = (uint32_t)id[i];
+    }
+    PBuf<R> b = sections<R>(P.buf[P.cur], C, D);
+    hipError_t e = hipMemcpyAsync(b.cell, hcell.data(), C * 4, hipMemcpyHostToDevice, s);
+    for (int d = 0; d < D && e == hipSuccess; ++d)
+        e = hipMemcpyAsync(b.off[d], hoff[d].data(), C * sizeof(R), hipMemcpyHostToDevice, s);
+    for (int c = 0; c < 3 && e == hipSuccess; ++c)
+        e = hipMemcpyAsync(b.v[c], hv[c].data(), C * sizeof(R), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b.id, hid.data(), C * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P.tile_count[P.cur], counts.data(), ntiles * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P.count, &n, sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return hip_check(h, e, "particle upload");
+}
+
+template <typename R, int D>
+int read_impl(fs_handle* h, const fs_particles* sp, int64_t* n_out, int64_t* cell3, double* off3, double* v3, uint64_t* id,
+              hipStream_t s) {
+    const fs_particles& P = *sp;
+    const int64_t ntiles = h->L.ntiles;
+    std::vector<int32_t> counts(ntiles);
+    hipError_t e = hipMemcpyAsync(counts.data(), P.tile_count[P.cur], ntiles * 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_check(h, e, "count copy");
+    std::vector<int64_t> offs(ntiles);
+    int64_t tot = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        offs[t] = tot;
+        tot += std::min<int64_t>(counts[t], P.tile_cap);
+    }
+    if (!cell3) { *n_out = tot; return FS_OK; }
+    if (*n_out < tot) { *n_out = tot; return fail(h, FS_ECAPACITY, "host arrays too small"); }
+    *n_out = tot;
+    if (tot == 0) return FS_OK;
+    char* dmem = nullptr;
+    size_t bytes = ntiles * 8 + tot * (24 + 24 + 24 + 8) + 1024;
+    e = hipMalloc(&dmem, bytes);
+    if (e != hipSuccess) return hip_check(h, e, "readback scratch");
+    int64_t* doffs = reinterpret_cast<int64_t*>(dmem);
+    int64_t* dcell = reinterpret_cast<int64_t*>(dmem + round_up(ntiles * 8, 256));
+    double* doff = reinterpret_cast<double*>(reinterpret_cast<char*>(dcell) + round_up(tot * 24, 256));
+    double* dv = reinterpret_cast<double*>(reinterpret_cast<char*>(doff) + round_up(tot * 24, 256));
+    uint64_t* did = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(dv) + round_up(tot * 24, 256));
+    if (reinterpret_cast<char*>(did) + tot * 8 > dmem + bytes) {
+        hipFree(dmem);
+        bytes = round_up(ntiles * 8, 256) + 3 * round_up(tot * 24, 256) + round_up(tot * 8, 256);
+        if (hipMalloc(&dmem, bytes) != hipSuccess) return fail(h, FS_EDEVICE, "readback scratch");
+        doffs = reinterpret_cast<int64_t*>(dmem);
+        dcell = reinterpret_cast<int64_t*>(dmem + round_up(ntiles * 8, 256));
+        doff = reinterpret_cast<double*>(reinterpret_cast<char*>(dcell) + round_up(tot * 24, 256));
+        dv = reinterpret_cast<double*>(reinterpret_cast<char*>(doff) + round_up(tot * 24, 256));
+        did = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(dv) + round_up(tot * 24, 256));
+    }
+    e = hipMemcpyAsync(doffs, offs.data(), ntiles * 8, hipMemcpyHostToDevice, s);
+    PBuf<R> b = sections<R>(P.buf[P.cur], P.capacity, D);
+    if (e == hipSuccess) {
+        k_compact<R, D><<<(unsigned)ntiles, 256, 0, s>>>(h->G, b, P.tile_count[P.cur], doffs, P.tile_cap, dcell, doff, dv, did);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(cell3, dcell, tot * 24, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(off3, doff, tot * 24, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(v3, dv, tot * 24, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(id, did, tot * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(dmem);
+    return hip_check(h, e, "particle readback");
+}
+
+#define FS_DISPATCH_RD(h, CALL)                                                  \
+    do {                                                                         \
+        const int _d = (h)->cfg.dim;                                             \
+        if ((h)->cfg.precision == 32) {                                          \
+            using R = float;                                                     \
+            if (_d == 1) { constexpr int D = 1; return CALL; }                   \
+            if (_d == 2) { constexpr int D = 2; return CALL; }                   \
+            if (_d == 3) { constexpr int D = 3; return CALL; }                   \
+        } else {                                                                 \
+            using R = double;                                                    \
+            if (_d == 1) { constexpr int D = 1; return CALL; }                   \
+            if (_d == 2) { constexpr int D = 2; return CALL; }                   \
+            if (_d == 3) { constexpr int D = 3; return CALL; }                   \
+        }                                                                        \
+        return fail(h, FS_EINVAL, "unsupported configuration");                  \
+    } while (0)
+
+template <typename R> int diag_impl(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out, double* prof,
+                                    hipStream_t s) {
+    const long nc = h->L.ncent;
+    const unsigned gb = grid_for(nc);
+    k_diag_field<<<gb, 256, 0, s>>>(h->F, f->B, nc, h->part);
+    std::vector<double> part(4 * (size_t)gb);
+    hipError_t e = hipMemcpyAsync(part.data(), h->part, part.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_check(h, e, "diagnostics");
+    double b2 = 0, bp = 0, loss = 0, dv = 0;
+    for (unsigned i = 0; i < gb; ++i) {
+        b2 += part[4 * i]; bp += part[4 * i + 1]; loss += part[4 * i + 2]; dv = std::max(dv, part[4 * i + 3]);
+    }
+    const double dV = std::pow(h->cfg.dx, (double)h->cfg.dim);
+    out[0] = 0.5 * b2 * dV;
+    const int nsp = h->has_cr ? 2 : 1;
+    for (int k = 0; k < 2; ++k) {
+        out[1 + k] = 0.0;
+        out[3 + k] = 0.0;
+        if (k >= nsp) continue;
+        const fs_particles& P = sp[k];
+        PBuf<R> b = sections<R>(P.buf[P.cur], P.capacity, h->cfg.dim);
+        k_diag_kin<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(b, P.tile_count[P.cur], P.tile_cap, h->part);
+        std::vector<double> kp(h->L.ntiles);
+        int64_t cnt = 0;
+        e = hipMemcpyAsync(kp.data(), h->part, kp.size() * 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(&cnt, P.count, 8, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_check(h, e, "diagnostics");
+        double ke = 0;
+        for (double x : kp) ke += x;
+        const double w = k == 0 ? h->F.wth : h->F.wcr;
+        out[1 + k] = 0.5 * w * ke * dV;
+        out[3 + k] = (double)cnt;
+    }
+    out[5] = loss;
+    out[6] = dv;
+    out[7] = bp;
+    if (prof) {
+        k_profile<<<grid_for(h->cfg.nx), 256, 0, s>>>(h->F, f->B, nc, prof);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_check(h, e, "profile");
+    }
+    return FS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fs_load_particles(fs_handle* h, fs_particles* sp, int64_t n, const int64_t* cell3, const double* off3,
+                      const double* v3, const uint64_t* id, hipStream_t s) {
+    if (!h || !sp || n < 0) return fail(h, FS_EINVAL, "bad argument");
+    if (n > 0 && (!cell3 || !off3 || !v3 || !id)) return fail(h, FS_EINVAL, "NULL array");
+    if (sp->species == 1 && !h->has_cr) return fail(h, FS_EINVAL, "run has no CR species");
+    const fs_particles& P = *sp;
+    if (!P.buf[0] || !P.tile_count[0] || !P.count) return fail(h, FS_EINVAL, "NULL particle buffer");
+    if (P.tile_cap != h->L.tile_cap[sp->species] || P.capacity < h->L.capacity[sp->species])
+        return fail(h, FS_ECAPACITY, "particle buffer smaller than fs_layout reports");
+    FS_DISPATCH_RD(h, (load_impl<R, D>(h, sp, n, cell3, off3, v3, id, s)));
+}
+
+int fs_read_particles(fs_handle* h, const fs_particles* sp, int64_t* n, int64_t* cell3, double* off3, double* v3,
+                      uint64_t* id, hipStream_t s) {
+    if (!h || !sp || !n) return fail(h, FS_EINVAL, "bad argument");
+    if (cell3 && (!off3 || !v3 || !id)) return fail(h, FS_EINVAL, "NULL array");
+    FS_DISPATCH_RD(h, (read_impl<R, D>(h, sp, n, cell3, off3, v3, id, s)));
+}
+
+int fs_diagnostics(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out8, double* prof, hipStream_t s) {
+    if (!h || !sp || !f || !out8) return fail(h, FS_EINVAL, "bad argument");
+    if (h->cfg.precision == 32) return diag_impl<float>(h, sp, f, out8, prof, s);
+    return diag_impl<double>(h, sp, f, out8, prof, s);
+}
+
+}  // extern "C"

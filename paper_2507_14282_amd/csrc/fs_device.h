@@ -1,0 +1,205 @@
+// fs_device.h -- device-side building blocks of the faux-shock hybrid step
+// for gfx950: counter-based random numbers, shape functions, the fixed-point
+// deposit format, the Boris rotation and the faux-shock wall event.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fsk {
+
+// Random-number streams: the key of every Philox draw is (seed, stream).
+constexpr uint64_t kStreamInit = 1, kStreamInjectTh = 2, kStreamInjectCr = 3,
+                   kStreamWall = 4, kStreamFourier = 5;
+constexpr int kVsat = 8388607;            // 2^23 - 1: largest velocity code
+constexpr double kTwoPi = 6.283185307179586;
+
+// Compile-time tile shapes (cells per tile) per dimensionality.  A tile is
+// the unit of work of one workgroup: its particles, its gather stencil and
+// its deposit accumulators all live in LDS.
+template <int D> struct TileShape;
+template <> struct TileShape<1> { static constexpr int X = 32, Y = 1, Z = 1; };
+template <> struct TileShape<2> { static constexpr int X = 16, Y = 8, Z = 1; };
+template <> struct TileShape<3> { static constexpr int X = 8, Y = 8, Z = 8; };
+
+// Shape-function stencil relative to the particle's cell c: CIC touches
+// nodes c, c+1; TSC touches the nearest node and its neighbours, i.e. some
+// three of c-1 .. c+2.
+template <int S> struct Stencil;
+template <> struct Stencil<1> { static constexpr int LO = 0, HI = 1, N = 2; };
+template <> struct Stencil<2> { static constexpr int LO = 1, HI = 2, N = 3; };
+
+// LDS extents of one tile: GX.. for the gather grid (the tile's cells plus
+// the stencil), DX.. for the deposit accumulators (one extra cell of halo on
+// each side so ions that left the tile by one cell still deposit in LDS).
+template <int D, int S> struct Extent {
+    static constexpr int TX = TileShape<D>::X, TY = TileShape<D>::Y, TZ = TileShape<D>::Z;
+    static constexpr int W = Stencil<S>::LO + Stencil<S>::HI;
+    static constexpr int GX = TX + W, GY = D >= 2 ? TY + W : 1, GZ = D >= 3 ? TZ + W : 1;
+    static constexpr int DX = TX + 2 + W, DY = D >= 2 ? TY + 2 + W : 1, DZ = D >= 3 ? TZ + 2 + W : 1;
+    static constexpr int GN = GX * GY * GZ, DN = DX * DY * DZ;
+};
+
+// Philox4x64-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
+// 64x64->128-bit products, key advanced by the Weyl constants each round.
+__device__ __forceinline__ void philox(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                       uint64_t k0, uint64_t k1, uint64_t out[4]) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = 0xD2E7470EE14C6C93ull, m1 = 0xCA5A826395121157ull;
+        uint64_t lo0 = m0 * c0, hi0 = __umul64hi(m0, c0);
+        uint64_t lo1 = m1 * c2, hi1 = __umul64hi(m1, c2);
+        uint64_t y0 = hi1 ^ c1 ^ k0, y2 = hi0 ^ c3 ^ k1;
+        c0 = y0; c1 = lo1; c2 = y2; c3 = lo0;
+        k0 += 0x9E3779B97F4A7C15ull;
+        k1 += 0xBB67AE8584CAA73Bull;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// Top 53 bits to a double in the open interval (0, 1), exactly.
+__device__ __forceinline__ double unit(uint64_t r) {
+    return ((double)(r >> 11) + 0.5) * 0x1.0p-53;
+}
+
+__device__ __forceinline__ void draw4(uint64_t seed, uint64_t stream, uint64_t c0, uint64_t c1,
+                                      uint64_t c2, double u[4]) {
+    uint64_t r[4];
+    philox(c0, c1, c2, 0, seed, stream, r);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) u[i] = unit(r[i]);
+}
+
+// Box-Muller pair.
+__device__ __forceinline__ void box_muller(double a, double b, double& n1, double& n2) {
+    double rad = sqrt(-2.0 * log(a));
+    n1 = rad * cos(kTwoPi * b);
+    n2 = rad * sin(kTwoPi * b);
+}
+
+template <typename R> __device__ __forceinline__ R below_one();
+template <> __device__ __forceinline__ float below_one<float>() { return 0x1.fffffep-1f; }
+template <> __device__ __forceinline__ double below_one<double>() { return 0x1.fffffffffffffp-1; }
+
+// Offset stored in the particle's precision, kept strictly below 1.
+template <typename R> __device__ __forceinline__ R to_offset(double o) {
+    R r = (R)o;
+    return r >= (R)1 ? below_one<R>() : r;
+}
+
+// Real-valued 1D shape weights for the gather.  `rel` is the first node
+// relative to the cell index.
+template <typename R, int S> __device__ __forceinline__ void weights_real(R o, int& rel, R w[3]) {
+    if constexpr (S == 1) {
+        rel = 0; w[0] = (R)1 - o; w[1] = o; w[2] = (R)0;
+    } else {
+        R xi = o;
+        rel = -1;
+        if (o >= (R)0.5) { xi = o - (R)1; rel = 0; }
+        R a = (R)0.5 - xi, b = (R)0.5 + xi;
+        w[0] = (R)0.5 * a * a;
+        w[1] = (R)0.75 - xi * xi;
+        w[2] = (R)0.5 * b * b;
+    }
+}
+
+// Integer 1D weights of the fixed-point deposit: the offset is quantised to
+// q = floor(o 2^b + 1/2) (exact in the storage precision), and the weights
+// of the CIC / TSC stencil are integers summing exactly to 2^b (CIC) or
+// 2^(2b+1) (TSC).
+template <typename R, int S> __device__ __forceinline__ void weights_int(R o, int b, int& rel, int w[3]) {
+    int one = 1 << b;
+    int q = (int)floor(o * (R)one + (R)0.5);
+    if constexpr (S == 1) {
+        rel = 0; w[0] = one - q; w[1] = q; w[2] = 0;
+    } else {
+        int half = one >> 1, d = q;
+        rel = -1;
+        if (q > half) { d = q - one; rel = 0; }
+        w[0] = (half - d) * (half - d);
+        w[2] = (half + d) * (half + d);
+        w[1] = (1 << (2 * b + 1)) - w[0] - w[2];
+    }
+}
+
+// Velocity code rint(v 2^sv), saturated to the 24-bit signed range so that
+// weight x code is a single 24x24 -> 48-bit product.  Returns the saturation
+// / NaN status in bits (8 = saturated, 4 = NaN).
+template <typename R> __device__ __forceinline__ int vcode(R v, int sv, int& status) {
+    if (v != v) { status |= 4; return 0; }
+    R t = rint(ldexp(v, sv));
+    if (t > (R)kVsat) { status |= 8; return kVsat; }
+    if (t < -(R)kVsat) { status |= 8; return -kVsat; }
+    return (int)t;
+}
+
+// Exact weight x velocity-code product via the 24-bit multiplier pair.
+__device__ __forceinline__ long long mul24(int w, int q) {
+    w = (w << 8) >> 8;
+    q = (q << 8) >> 8;
+    return (long long)w * (long long)q;
+}
+
+// Boris rotation with half electric kicks (q/m = 1): v^{n-1/2} -> v^{n+1/2}.
+template <typename R> __device__ __forceinline__ void boris(R v[3], const R E[3], const R B[3], R h) {
+    R vm[3], t[3], s[3], vp[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { vm[d] = v[d] + h * E[d]; t[d] = h * B[d]; }
+    R tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    R f = (R)2 / ((R)1 + tt);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s[d] = f * t[d];
+    vp[0] = vm[0] + (vm[1] * t[2] - vm[2] * t[1]);
+    vp[1] = vm[1] + (vm[2] * t[0] - vm[0] * t[2]);
+    vp[2] = vm[2] + (vm[0] * t[1] - vm[1] * t[0]);
+    v[0] = vm[0] + (vp[1] * s[2] - vp[2] * s[1]) + h * E[0];
+    v[1] = vm[1] + (vp[2] * s[0] - vp[0] * s[2]) + h * E[1];
+    v[2] = vm[2] + (vp[0] * s[1] - vp[1] * s[0]) + h * E[2];
+}
+
+// Faux-shock event (eq. 1 of the paper with the speed measured in the
+// downstream frame).  The reflect/transmit decision is sqrt-free FP64 with a
+// fixed operation order and no contraction, so any two IEEE implementations
+// agree bit for bit: with m = max(U1, U2), reflect iff
+// |w|^2 > (u2 (1 + m) / (1 - m))^2, which happens with probability
+// ((1 - u2/|w|) / (1 + u2/|w|))^2.  A reflected ion keeps |w| and leaves
+// with direction cosine mu' = a + (1 - a) sqrt(U3), a = u2/|w|, azimuth
+// 2 pi U4 (the flux of an isotropic downstream population that outruns the
+// flow).  Returns 1 on reflection, with the new velocity and the distance
+// (cells) the ion travels back from x = L during the rest of the step.
+__device__ __noinline__ int faux_shock_event(uint64_t seed, uint64_t step, uint32_t id, double u2,
+                                             double delta, const double v[3], double vout[3],
+                                             double& back) {
+#pragma clang fp contract(off)
+    double wx = v[0] - u2, wy = v[1], wz = v[2];
+    double w2 = wx * wx + wy * wy + wz * wz;
+    double U[4];
+    draw4(seed, kStreamWall, step, (uint64_t)id, 0, U);
+    double m = U[0] > U[1] ? U[0] : U[1];
+    double T = u2 * (1.0 + m) / (1.0 - m);
+    if (!(w2 > T * T)) return 0;
+    double wabs = sqrt(w2);
+    double a = u2 / wabs;
+    double mu = a + (1.0 - a) * sqrt(U[2]);
+    double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double phi = kTwoPi * U[3];
+    vout[0] = u2 - wabs * mu;
+    vout[1] = wabs * st * cos(phi);
+    vout[2] = wabs * st * sin(phi);
+    back = v[0] > 0.0 ? delta * (-vout[0]) / v[0] : 0.0;
+    return 1;
+}
+
+// Workgroup index -> tile, so that the workgroups the hardware hands to one
+// XCD (round robin over 8) get a contiguous run of tiles and share its L2.
+__device__ __forceinline__ int xcd_tile(int bid, int n) {
+    int per = n >> 3, rem = n & 7, x = bid & 7, l = bid >> 3;
+    return x * per + (x < rem ? x : rem) + l;
+}
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+    if (i < 0) { i += n; if (i < 0) i = ((i % n) + n) % n; }
+    else if (i >= n) { i -= n; if (i >= n) i %= n; }
+    return i;
+}
+
+}  // namespace fsk
