@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark of the faux-shock hybrid step on one MI355X.
+
+Workload: the 3D3V FP32 faux-shock box, 1024 x 192 x 192 cells of 1 d_i,
+8 thermal ions per cell (3.02e8 ions), M_A = 20 (u_sh = 20 v_A), beta = 1,
+theta_Bn = 45 deg, y/z periodic, FS wall at x = L acting on the thermal
+ions, int64 fixed-point moments, FP64 Ohm/Faraday field update.  Synthetic
+Philox-seeded initial load, no external data.
+
+A timed step is the whole step: push (gather + Boris + move + boundaries +
+fused deposit), FS wall, injection and the FP64 field update.  `value` is
+ion particle-updates per second over that whole step with everything
+resident in HBM.  The line also carries the push-kernel roofline (live HIP
+event timing on the library's stream) and the CPU oracle timed on a bounded
+slab of the same workload on this host.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def push_bytes(np_live, L):
+    """Algorithmic HBM bytes of one launch of the fused push kernel: the ion
+    state read and written once (int32 cell, 3 fp32 offsets, 3 fp32
+    velocities, uint32 id = 32 B each way), the FP32 E/Bbar of every node read
+    once (24 B) and the four int64 moments of every node written once (32 B)."""
+    return np_live * 64 + int(L.nnode) * 24 + int(L.ndep) * 32
+
+
+def traffic_from_profiles(kernel_hash):
+    """HBM bytes per push launch measured with rocprofv3 counters, if the
+    committed measurement was taken on the kernel source as it is now."""
+    path = os.path.join(ROOT, "profiles", "push3d_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256") != kernel_hash:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("fs_device.h", "fs_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2507_14282_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def cpu_baseline(params, seconds):
+    """The FP64 oracle on a 64 x 48 x 48 slab of the same workload (same ppc,
+    flow, wall and field update), timed over whole steps for about `seconds`."""
+    from oracle import oracle as O
+    p = dict(params, nx=64, ny=48, nz=48)
+    o = O.Oracle(p)
+    o.init()
+    done, pu, t0 = 0, 0, time.perf_counter()
+    while True:
+        n = o.count(0)
+        o.step()
+        pu += n
+        done += 1
+        el = time.perf_counter() - t0
+        if done >= 2 and el >= seconds:
+            break
+    return {"value": pu / el, "unit": "particle-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 oracle, whole steps, 64x48x48 slab at 8 ppc ({n} ions), {done} steps, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="cfg4")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        msg = (f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+               "(the multi-GPU x-slab decomposition is design only)")
+        print(msg, file=sys.stderr)
+        print(json.dumps({"error": msg, "n_gpus": args.gpus}))
+        return 2
+
+    import torch
+    from paper_2507_14282_amd import fshybrid as F
+    from paper_2507_14282_amd import workloads as W
+
+    p = W.preset(args.workload)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    for s in range(args.warmup):
+        sim.step(s, stats=False)
+    torch.cuda.synchronize()
+    n0 = sim.count(0) + (sim.count(1) if sim.has_cr else 0)
+    sim.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sim.step(args.warmup + k, stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, nrec = sim.timing_read()
+    n1 = sim.count(0) + (sim.count(1) if sim.has_cr else 0)
+    st = sim.step(args.warmup + args.steps, stats=True)   # error flags of a final, untimed step
+    elapsed = t1 - t0
+    np_avg = 0.5 * (n0 + n1)
+    value = np_avg * args.steps / elapsed
+    push_ms = ms[0] / max(nrec[0], 1)
+    region_ms = (ms[0] + ms[1] + ms[2]) / max(nrec[0], 1)
+    alg = push_bytes(np_avg, sim.L)
+    achieved = alg / (push_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(kernel_source_hash())
+    out = {
+        "metric": "ion particle-updates/sec (push+deposit+FS wall) 3D at 1 GPU; adjoint/fwd time",
+        "value": value,
+        "unit": "particle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (Philox-seeded drifting Maxwellian load, no external data)",
+        "config": {
+            "workload": f"3D3V FP32 faux-shock box {p['nx']}x{p['ny']}x{p['nz']} cells dx={p['dx']} d_i, "
+                        f"{p['ppc']} ppc, M_A={p['u_sh']:g}, beta={p['beta_i']:g}, theta_Bn={p['theta_deg']:g} deg",
+            "ions": int(np_avg),
+            "step": "push+wall+inject+deposit (FP32 particles, int64 moments) + FP64 SSP-RK3 field update",
+            "parallelism": "single GPU",
+        },
+        "phases_ms_per_step": {
+            "push_deposit": push_ms, "wall": ms[1] / max(nrec[1], 1), "inject": ms[2] / max(nrec[2], 1),
+            "field": ms[3] / max(nrec[3], 1), "step_events": ms[4] / max(nrec[4], 1)},
+        "push_deposit_wall_pu_per_s": np_avg / (region_ms * 1e-3),
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_push<float,3,CIC,deposit>", "alg_bytes_per_launch": alg,
+            "avg_launch_ms": push_ms,
+        },
+        "final_step_flags": st["flags"],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -112,11 +112,15 @@ typedef struct fs_layout_info {
  *   real   off[d]    in-cell offset in [0, 1), one section per dimension
  *   real   v[3]      velocity (v^{n-1/2} before a step, v^{n+1/2} after)
  *   uint32 id        unique particle id (keys the wall's random numbers)
- * Slots [t*tile_cap, t*tile_cap + tile_count[t]) of buffer `cur` hold the
- * live particles of tile t; fs_step writes the other buffer and flips cur. */
+ * Tile t owns slots [t*tile_cap, (t+1)*tile_cap) of each buffer.  Its live
+ * particles are the bottom run [0, lo) and the top run [tile_cap - hi,
+ * tile_cap) of that range, with lo = tile_count[t] and hi =
+ * tile_count[ntiles + t]: the tile's own stayers are written bottom-up, ions
+ * arriving from elsewhere (neighbour tiles, the wall, injection) top-down.
+ * fs_step writes the other buffer and flips cur. */
 typedef struct fs_particles {
     void*    buf[2];
-    int32_t* tile_count[2]; /* device, ntiles entries each */
+    int32_t* tile_count[2]; /* device, 2 * ntiles entries each (lo, then hi) */
     int64_t* count;         /* device, live particles (updated by fs_step) */
     int64_t  capacity;
     int64_t  tile_cap;
@@ -202,6 +206,16 @@ int64_t fs_next_id(const fs_handle* h);
  * By^2 + Bz^2.  prof (optional, device, nx) = sum over y, z of By^2 + Bz^2. */
 int fs_diagnostics(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out8,
                    double* prof, hipStream_t s);
+
+/* Phase timing with HIP events recorded on the caller's stream (benchmark
+ * support).  While enabled, every fs_step records an event pair around each
+ * phase: 0 = push kernels (gather, Boris, move, boundaries, fused deposit),
+ * 1 = wall kernels, 2 = injection, 3 = field update, 4 = the whole step.
+ * fs_timing_read synchronises the stream, writes the summed milliseconds and
+ * the number of recorded intervals per phase (5 entries each) and clears the
+ * record.  At most 4096 steps are recorded between reads. */
+int fs_timing_enable(fs_handle* h, int32_t on);
+int fs_timing_read(fs_handle* h, double* ms5, int64_t* n5, hipStream_t s);
 
 #ifdef __cplusplus
 }

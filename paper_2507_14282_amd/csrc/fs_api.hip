@@ -36,6 +36,11 @@ struct fs_handle {
     double* part = nullptr;
     int64_t npart = 0;
     std::string err;
+    // phase timing: pool of event pairs recorded on the caller's stream
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_phase;
+    size_t ev_used = 0;
 };
 
 namespace {
@@ -81,7 +86,7 @@ int lds_bytes(int dim, int shape, int rb, bool gather) {
     int w = shape == 2 ? 3 : 1;
     int gx = t[0] + w, gy = dim >= 2 ? t[1] + w : 1, gz = dim >= 3 ? t[2] + w : 1;
     int dx = t[0] + 2 + w, dy = dim >= 2 ? t[1] + 2 + w : 1, dz = dim >= 3 ? t[2] + 2 + w : 1;
-    return (gather ? 8 * rb * gx * gy * gz : 0) + 32 * dx * dy * dz;
+    return (gather ? 6 * rb * gx * gy * gz : 0) + 32 * dx * dy * dz;  // upper bound of both deposit paths
 }
 
 int compute_layout(const fs_config* c, fs_layout_info* L, std::string& err) {
@@ -180,6 +185,22 @@ template <typename K> void allow_lds(K kernel, size_t bytes) {
                               (int)bytes);
 }
 
+constexpr size_t kMaxTimed = 4096 * 8;
+
+// Records an event pair bracketing one phase; returns the index of the pair
+// or -1 when timing is off or the pool is exhausted.
+int timing_begin(fs_handle* h, int phase, hipStream_t s) {
+    if (!h->timing || h->ev_used + 2 > h->ev_pool.size()) return -1;
+    int k = (int)h->ev_used;
+    h->ev_used += 2;
+    h->ev_phase[k / 2] = phase;
+    (void)hipEventRecord(h->ev_pool[k], s);
+    return k;
+}
+void timing_end(fs_handle* h, int k, hipStream_t s) {
+    if (k >= 0) (void)hipEventRecord(h->ev_pool[k + 1], s);
+}
+
 unsigned grid_for(int64_t n, int block = 256) { return (unsigned)std::max<int64_t>(1, (n + block - 1) / block); }
 
 int policy_of(const fs_handle* h, int s) { return s == 0 ? h->cfg.wall_th : h->cfg.wall_cr; }
@@ -196,23 +217,31 @@ void zero_i32(int32_t* p, int64_t n, hipStream_t s) {
 // ------------------------------------------------------------------------
 // field update (FP64)
 // ------------------------------------------------------------------------
-template <typename R> void field_update(fs_handle* h, fs_fields* f, hipStream_t s, bool rk) {
+template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hipStream_t s, bool rk) {
     const long nn = h->L.nnode, nc = h->L.ncent;
-    const unsigned gn = grid_for(nn), gc = grid_for(nc);
-    k_fluid<<<gn, 256, 0, s>>>(h->F, reinterpret_cast<const long long*>(f->mom[0]),
-                              reinterpret_cast<const long long*>(h->has_cr ? f->mom[1] : f->mom[0]), h->fluid, nn);
+    const dim3 blk(kFX, kFY, 1);
+    const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
+    const dim3 gc((unsigned)((h->cfg.nx + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
+    k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(f->mom[0]),
+                               reinterpret_cast<const long long*>(h->has_cr ? f->mom[1] : f->mom[0]), h->fluid, nn);
     if (rk) {
         const double hs = h->cfg.dt / (double)h->cfg.n_sub;
         for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
-            k_ohm<R><<<gn, 256, 0, s>>>(h->F, f->B, h->fluid, h->Etmp, nullptr, nn, nc);
-            k_faraday<<<gc, 256, 0, s>>>(h->F, h->Etmp, f->B, f->B, h->B1, 0.0, 1.0, hs, nn, nc);
-            k_ohm<R><<<gn, 256, 0, s>>>(h->F, h->B1, h->fluid, h->Etmp, nullptr, nn, nc);
-            k_faraday<<<gc, 256, 0, s>>>(h->F, h->Etmp, f->B, h->B1, h->B2, 0.75, 0.25, hs, nn, nc);
-            k_ohm<R><<<gn, 256, 0, s>>>(h->F, h->B2, h->fluid, h->Etmp, nullptr, nn, nc);
-            k_faraday<<<gc, 256, 0, s>>>(h->F, h->Etmp, f->B, h->B2, f->B, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc);
+            k_ohm<R, D><<<gn, blk, 0, s>>>(h->F, f->B, h->fluid, h->Etmp, nullptr, nn, nc);
+            k_faraday<D><<<gc, blk, 0, s>>>(h->F, h->Etmp, f->B, f->B, h->B1, 0.0, 1.0, hs, nn, nc);
+            k_ohm<R, D><<<gn, blk, 0, s>>>(h->F, h->B1, h->fluid, h->Etmp, nullptr, nn, nc);
+            k_faraday<D><<<gc, blk, 0, s>>>(h->F, h->Etmp, f->B, h->B1, h->B2, 0.75, 0.25, hs, nn, nc);
+            k_ohm<R, D><<<gn, blk, 0, s>>>(h->F, h->B2, h->fluid, h->Etmp, nullptr, nn, nc);
+            k_faraday<D><<<gc, blk, 0, s>>>(h->F, h->Etmp, f->B, h->B2, f->B, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc);
         }
     }
-    k_ohm<R><<<gn, 256, 0, s>>>(h->F, f->B, h->fluid, f->E, static_cast<R*>(f->gather), nn, nc);
+    k_ohm<R, D><<<gn, blk, 0, s>>>(h->F, f->B, h->fluid, f->E, static_cast<R*>(f->gather), nn, nc);
+}
+
+template <typename R> void field_update(fs_handle* h, fs_fields* f, hipStream_t s, bool rk) {
+    if (h->cfg.dim == 1) field_update_d<R, 1>(h, f, s, rk);
+    else if (h->cfg.dim == 2) field_update_d<R, 2>(h, f, s, rk);
+    else field_update_d<R, 3>(h, f, s, rk);
 }
 
 // ------------------------------------------------------------------------
@@ -229,16 +258,18 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
     const int64_t ninj = (cth + ccr) * ntr;
     if (h->next_id + ninj > (int64_t)UINT32_MAX + 1) return fail(h, FS_EIDOVERFLOW, "particle ids would overflow 32 bits");
     Geo G = h->G;
+    const int t_step = timing_begin(h, 4, s);
     zero_u64(h->ctr, C_N, s);
     if (dep)
         for (int k = 0; k < nsp; ++k) zero_u64(f->mom[k], 4 * h->L.ndep, s);
     using X = Extent<D, S>;
-    const size_t lds_push = sizeof(R) * 8 * X::GN + (dep ? 32 * X::DN : 0);
+    const size_t lds_push = PushLds<R, D, S>::bytes(dep);
     if (push) {
         for (int k = 0; k < nsp; ++k) {
-            zero_i32(sp[k].tile_count[sp[k].cur ^ 1], h->L.ntiles, s);
+            zero_i32(sp[k].tile_count[sp[k].cur ^ 1], 2 * h->L.ntiles, s);
             zero_i32(h->xl[k].count, 1, s);
         }
+        const int t_push = timing_begin(h, 0, s);
         for (int k = 0; k < nsp; ++k) {
             fs_particles& P = sp[k];
             PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
@@ -255,6 +286,8 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
                     G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, static_cast<const R*>(f->gather),
                     mom, h->xl[k], h->ctr, policy_of(h, k), k);
         }
+        timing_end(h, t_push, s);
+        const int t_wall = timing_begin(h, 1, s);
         if (c.xbc == FS_XBC_BOX) {
             for (int k = 0; k < nsp; ++k) {
                 if (policy_of(h, k) == FS_WALL_OPEN) continue;
@@ -270,7 +303,9 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
                                                              h->ctr, policy_of(h, k), k, (uint64_t)step);
             }
         }
+        timing_end(h, t_wall, s);
     }
+    const int t_inj = timing_begin(h, 2, s);
     if (inj && ninj > 0) {
         fs_particles& P0 = sp[0];
         const int t0 = push ? P0.cur ^ 1 : P0.cur;
@@ -295,6 +330,7 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
             k_inject<R, D, S, false><<<grid_for(ninj), 256, 0, s>>>(G, o0, P0.tile_count[t0], P0.tile_cap, m0, o1, c1, cap1, m1,
                                                                    h->ctr, (uint64_t)step, h->next_id, cth, ccr, ntr);
     }
+    timing_end(h, t_inj, s);
     if (push)
         for (int k = 0; k < nsp; ++k) sp[k].cur ^= 1;
     if (dep && !push) {
@@ -307,8 +343,16 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
                 G, in, P.tile_count[P.cur], P.tile_cap, reinterpret_cast<unsigned long long*>(f->mom[k]), h->ctr);
         }
     }
-    if (fld) field_update<R>(h, f, s, true);
+    if (fld) {
+        const int t_fld = timing_begin(h, 3, s);
+        field_update<R>(h, f, s, true);
+        timing_end(h, t_fld, s);
+    }
+    if (push || inj)
+        for (int k = 0; k < nsp; ++k)
+            k_check_bins<<<grid_for(h->L.ntiles), 256, 0, s>>>(sp[k].tile_count[sp[k].cur], (int)h->L.ntiles, sp[k].tile_cap, h->ctr);
     k_count_update<<<1, 64, 0, s>>>(sp[0].count, h->has_cr ? sp[1].count : nullptr, h->ctr);
+    timing_end(h, t_step, s);
     h->next_id += ninj;
     int rc = hip_check(h, hipGetLastError(), "kernel launch");
     if (rc) return rc;
@@ -331,7 +375,7 @@ int init_impl(fs_handle* h, fs_particles* sp, fs_fields* f, const double* amps, 
     k_set_i64<<<1, 1, 0, s>>>(P.count, np);
     if (h->has_cr) {
         sp[1].cur = 0;
-        zero_i32(sp[1].tile_count[0], h->L.ntiles, s);
+        zero_i32(sp[1].tile_count[0], 2 * h->L.ntiles, s);
         k_set_i64<<<1, 1, 0, s>>>(sp[1].count, 0);
     }
     h->next_id = np;
@@ -485,6 +529,7 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
 
 void fs_destroy(fs_handle* h) {
     if (!h) return;
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     hipFree(h->ctr);
     if (h->ctr_host) hipHostFree(h->ctr_host);
     hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->phase); hipFree(h->part);
@@ -618,6 +663,36 @@ int fs_set_clock(fs_handle* h, int64_t next_id) {
 
 int64_t fs_next_id(const fs_handle* h) { return h ? h->next_id : -1; }
 
+int fs_timing_enable(fs_handle* h, int32_t on) {
+    if (!h) return fail(h, FS_EINVAL, "NULL handle");
+    if (on && h->ev_pool.empty()) {
+        h->ev_pool.resize(kMaxTimed);
+        h->ev_phase.assign(kMaxTimed / 2, 0);
+        for (auto& e : h->ev_pool)
+            if (hipEventCreate(&e) != hipSuccess) return fail(h, FS_EDEVICE, "event creation failed");
+    }
+    h->timing = on != 0;
+    h->ev_used = 0;
+    return FS_OK;
+}
+
+int fs_timing_read(fs_handle* h, double* ms5, int64_t* n5, hipStream_t s) {
+    if (!h || !ms5 || !n5) return fail(h, FS_EINVAL, "bad argument");
+    for (int i = 0; i < 5; ++i) { ms5[i] = 0.0; n5[i] = 0; }
+    int rc = hip_check(h, hipStreamSynchronize(s), "stream synchronise");
+    if (rc) return rc;
+    for (size_t k = 0; k + 1 < h->ev_used; k += 2) {
+        float ms = 0.f;
+        rc = hip_check(h, hipEventElapsedTime(&ms, h->ev_pool[k], h->ev_pool[k + 1]), "event timing");
+        if (rc) return rc;
+        int ph = h->ev_phase[k / 2];
+        ms5[ph] += ms;
+        n5[ph] += 1;
+    }
+    h->ev_used = 0;
+    return FS_OK;
+}
+
 }  // extern "C"
 
 // --------------------------------------------------------------------------
@@ -630,7 +705,7 @@ int load_impl(fs_handle* h, fs_particles* sp, int64_t n, const int64_t* cell3, c
               const uint64_t* id, hipStream_t s) {
     fs_particles& P = *sp;
     const int64_t cap = P.tile_cap, ntiles = h->L.ntiles;
-    std::vector<int32_t> counts(ntiles, 0);
+    std::vector<int32_t> counts(2 * ntiles, 0);
     std::vector<int64_t> slot(n);
     std::vector<int32_t> tile(n);
     const int* T = h->L.tile;
@@ -670,7 +745,7 @@ int load_impl(fs_handle* h, fs_particles* sp, int64_t n, const int64_t* cell3, c
     for (int c = 0; c < 3 && e == hipSuccess; ++c)
         e = hipMemcpyAsync(b.v[c], hv[c].data(), C * sizeof(R), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b.id, hid.data(), C * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(P.tile_count[P.cur], counts.data(), ntiles * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(P.tile_count[P.cur], counts.data(), 2 * ntiles * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(P.count, &n, sizeof(int64_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return hip_check(h, e, "particle upload");
@@ -681,15 +756,15 @@ int read_impl(fs_handle* h, const fs_particles* sp, int64_t* n_out, int64_t* cel
               hipStream_t s) {
     const fs_particles& P = *sp;
     const int64_t ntiles = h->L.ntiles;
-    std::vector<int32_t> counts(ntiles);
-    hipError_t e = hipMemcpyAsync(counts.data(), P.tile_count[P.cur], ntiles * 4, hipMemcpyDeviceToHost, s);
+    std::vector<int32_t> counts(2 * ntiles);
+    hipError_t e = hipMemcpyAsync(counts.data(), P.tile_count[P.cur], 2 * ntiles * 4, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_check(h, e, "count copy");
     std::vector<int64_t> offs(ntiles);
     int64_t tot = 0;
     for (int64_t t = 0; t < ntiles; ++t) {
         offs[t] = tot;
-        tot += std::min<int64_t>(counts[t], P.tile_cap);
+        tot += std::min<int64_t>((int64_t)counts[t] + counts[ntiles + t], P.tile_cap);
     }
     if (!cell3) { *n_out = tot; return FS_OK; }
     if (*n_out < tot) { *n_out = tot; return fail(h, FS_ECAPACITY, "host arrays too small"); }
@@ -768,7 +843,7 @@ template <typename R> int diag_impl(fs_handle* h, const fs_particles* sp, const 
         if (k >= nsp) continue;
         const fs_particles& P = sp[k];
         PBuf<R> b = sections<R>(P.buf[P.cur], P.capacity, h->cfg.dim);
-        k_diag_kin<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(b, P.tile_count[P.cur], P.tile_cap, h->part);
+        k_diag_kin<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(b, P.tile_count[P.cur], (int)h->L.ntiles, P.tile_cap, h->part);
         std::vector<double> kp(h->L.ntiles);
         int64_t cnt = 0;
         e = hipMemcpyAsync(kp.data(), h->part, kp.size() * 8, hipMemcpyDeviceToHost, s);

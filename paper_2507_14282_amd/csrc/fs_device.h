@@ -19,7 +19,7 @@ constexpr double kTwoPi = 6.283185307179586;
 template <int D> struct TileShape;
 template <> struct TileShape<1> { static constexpr int X = 32, Y = 1, Z = 1; };
 template <> struct TileShape<2> { static constexpr int X = 16, Y = 8, Z = 1; };
-template <> struct TileShape<3> { static constexpr int X = 8, Y = 8, Z = 8; };
+template <> struct TileShape<3> { static constexpr int X = 8, Y = 8, Z = 4; };
 
 // Shape-function stencil relative to the particle's cell c: CIC touches
 // nodes c, c+1; TSC touches the nearest node and its neighbours, i.e. some

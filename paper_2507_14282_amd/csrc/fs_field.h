@@ -33,21 +33,25 @@ __device__ __forceinline__ double centre_B(const double* __restrict__ B, const F
     return B[(long)c * nc + i + (long)F.nx * (j + (long)F.nyc * k)];
 }
 
+// Launch shape of the field kernels: 64 x 4 threads over (x, y), one z per
+// block layer, so every thread knows its (i, j, k) without any division.
+constexpr int kFX = 64, kFY = 4;
+
 // Ion density / flux at the field nodes from both species' integer moments,
 // boundary-filled, floored, plus the rigid external current, and the
 // electron pressure p_e = (beta_e / 2) n_e^gamma_e.
 __global__ __launch_bounds__(256) void k_fluid(FieldGeo F, const long long* __restrict__ m0,
                                                const long long* __restrict__ m1, double* __restrict__ fl,
                                                long nnode) {
-    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nnode) return;
-    int i = (int)(n % F.nxn);
-    long rest = n / F.nxn;
+    int i = blockIdx.x * kFX + threadIdx.x;
+    const int j = blockIdx.y * kFY + threadIdx.y, k = blockIdx.z;
+    if (i >= F.nxn || j >= F.nyc) return;
+    const long n = i + (long)F.nxn * (j + (long)F.nyc * k);
     if (F.xbc == 0) {
         if (i < F.mclamp) i = F.mclamp;
         if (i > F.nx - F.mclamp) i = F.nx - F.mclamp;
     }
-    long dn = (long)(i + F.g) + (long)F.ndx * rest;
+    const long dn = (long)(i + F.g) + (long)F.ndx * (j + (long)F.nyc * k);
     double dens = F.wth * ((double)m0[4 * dn] * F.scR);
     double G[3];
 #pragma unroll
@@ -74,52 +78,64 @@ __device__ __forceinline__ long fnode(const FieldGeo& F, int i, int j, int k) {
 }
 
 // Ohm's law at every node: E = (-Gamma x Bbar + J x Bbar - grad p_e)/n_e + eta J
-// with J = curl B (centre -> node).  `final_` also writes the gather grid
-// (E and Bbar in the particle precision) and the FP64 E state.
-template <typename R>
+// with Bbar the mean of the 2^D centres around the node and J = curl B from
+// their differences.  With `gather` set it also writes E and Bbar in the
+// particle precision for the push.
+template <typename R, int D>
 __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restrict__ B, const double* __restrict__ fl,
                                              double* __restrict__ E, R* __restrict__ gather, long nnode, long ncent) {
-    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nnode) return;
-    const int i = (int)(n % F.nxn);
-    const int j = (int)((n / F.nxn) % F.nyc);
-    const int k = (int)(n / ((long)F.nxn * F.nyc));
-    const int D = F.dim;
-    const int nb = D >= 2 ? 2 : 1, nc = D >= 3 ? 2 : 1;
-    double bb[3] = {0, 0, 0}, dBx[3] = {0, 0, 0}, dBy[3] = {0, 0, 0}, dBz[3] = {0, 0, 0};
+    const int i = blockIdx.x * kFX + threadIdx.x;
+    const int j = blockIdx.y * kFY + threadIdx.y, k = blockIdx.z;
+    if (i >= F.nxn || j >= F.nyc) return;
+    const long n = i + (long)F.nxn * (j + (long)F.nyc * k);
+    constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
+    // C[a][b][c] = B at centre (i-1+a, j-1+b, k-1+c)
+    double C[2][NB][NC][3];
+#pragma unroll
     for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < nb; ++b)
-            for (int c = 0; c < nc; ++c)
 #pragma unroll
-                for (int d = 0; d < 3; ++d) bb[d] += centre_B(B, F, ncent, i - 1 + a, j - 1 + b, k - 1 + c, d);
-    const double inv = 1.0 / (double)(2 * nb * nc);
+        for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) bb[d] *= inv;
-    for (int b = 0; b < nb; ++b)
-        for (int c = 0; c < nc; ++c)
-#pragma unroll
-            for (int d = 0; d < 3; ++d)
-                dBx[d] += centre_B(B, F, ncent, i, j - 1 + b, k - 1 + c, d) -
-                          centre_B(B, F, ncent, i - 1, j - 1 + b, k - 1 + c, d);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) dBx[d] = dBx[d] / (double)(nb * nc) / F.dx;
-    if (D >= 2) {
-        for (int a = 0; a < 2; ++a)
-            for (int c = 0; c < nc; ++c)
+            for (int c = 0; c < NC; ++c)
 #pragma unroll
                 for (int d = 0; d < 3; ++d)
-                    dBy[d] += centre_B(B, F, ncent, i - 1 + a, j, k - 1 + c, d) -
-                              centre_B(B, F, ncent, i - 1 + a, j - 1, k - 1 + c, d);
+                    C[a][b][c][d] = centre_B(B, F, ncent, i - 1 + a, D >= 2 ? j - 1 + b : 0, D >= 3 ? k - 1 + c : 0, d);
+    double bb[3] = {0, 0, 0}, dBx[3] = {0, 0, 0}, dBy[3] = {0, 0, 0}, dBz[3] = {0, 0, 0};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) dBy[d] = dBy[d] / (double)(2 * nc) / F.dx;
-    }
-    if (D >= 3) {
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) bb[d] += C[a][b][c][d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) bb[d] *= 1.0 / (double)(2 * NB * NC);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) dBx[d] += C[1][b][c][d] - C[0][b][c][d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dBx[d] = dBx[d] / (double)(NB * NC) / F.dx;
+    if constexpr (D >= 2) {
+#pragma unroll
         for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dBy[d] += C[a][1][c][d] - C[a][0][c][d];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dBy[d] = dBy[d] / (double)(2 * NC) / F.dx;
+    }
+    if constexpr (D >= 3) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    dBz[d] += centre_B(B, F, ncent, i - 1 + a, j - 1 + b, k, d) -
-                              centre_B(B, F, ncent, i - 1 + a, j - 1 + b, k - 1, d);
+                for (int d = 0; d < 3; ++d) dBz[d] += C[a][b][1][d] - C[a][b][0][d];
 #pragma unroll
         for (int d = 0; d < 3; ++d) dBz[d] = dBz[d] / 4.0 / F.dx;
     }
@@ -127,8 +143,8 @@ __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restric
     const double* pe = fl + nnode;
     double gp[3] = {0, 0, 0};
     gp[0] = (pe[fnode(F, i + 1, j, k)] - pe[fnode(F, i - 1, j, k)]) / (2.0 * F.dx);
-    if (D >= 2) gp[1] = (pe[fnode(F, i, j + 1, k)] - pe[fnode(F, i, j - 1, k)]) / (2.0 * F.dx);
-    if (D >= 3) gp[2] = (pe[fnode(F, i, j, k + 1)] - pe[fnode(F, i, j, k - 1)]) / (2.0 * F.dx);
+    if constexpr (D >= 2) gp[1] = (pe[fnode(F, i, j + 1, k)] - pe[fnode(F, i, j - 1, k)]) / (2.0 * F.dx);
+    if constexpr (D >= 3) gp[2] = (pe[fnode(F, i, j, k + 1)] - pe[fnode(F, i, j, k - 1)]) / (2.0 * F.dx);
     const double ne = fl[n];
     const double G[3] = {fl[2 * nnode + n], fl[3 * nnode + n], fl[4 * nnode + n]};
     double num[3];
@@ -148,43 +164,54 @@ __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restric
     }
 }
 
-// One SSP-RK3 stage at every centre: Bout = c0 Bn + c1 (Bin - h curl E).
+// One SSP-RK3 stage at every centre: Bout = c0 Bn + c1 (Bin - h curl E),
+// with curl E from the 2^D nodes around the centre.
+template <int D>
 __global__ __launch_bounds__(256) void k_faraday(FieldGeo F, const double* __restrict__ E, const double* __restrict__ Bn,
                                                  const double* __restrict__ Bin, double* __restrict__ Bout,
                                                  double c0, double c1, double h, long nnode, long ncent) {
-    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= ncent) return;
-    const int i = (int)(n % F.nx);
-    const int j = (int)((n / F.nx) % F.nyc);
-    const int k = (int)(n / ((long)F.nx * F.nyc));
-    const int D = F.dim;
-    const int nb = D >= 2 ? 2 : 1, nc = D >= 3 ? 2 : 1;
+    const int i = blockIdx.x * kFX + threadIdx.x;
+    const int j = blockIdx.y * kFY + threadIdx.y, k = blockIdx.z;
+    if (i >= F.nx || j >= F.nyc) return;
+    const long n = i + (long)F.nx * (j + (long)F.nyc * k);
+    constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
+    double P[2][NB][NC][3];   // E at node (i+a, j+b, k+c)
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                long q = fnode(F, i + a, j + b, k + c);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) P[a][b][c][d] = E[(long)d * nnode + q];
+            }
     double dEx[3] = {0, 0, 0}, dEy[3] = {0, 0, 0}, dEz[3] = {0, 0, 0};
-    for (int b = 0; b < nb; ++b)
-        for (int c = 0; c < nc; ++c) {
-            long p1 = fnode(F, i + 1, j + b, k + c), p0 = fnode(F, i, j + b, k + c);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) dEx[d] += E[(long)d * nnode + p1] - E[(long)d * nnode + p0];
-        }
+    for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) dEx[d] = dEx[d] / (double)(nb * nc) / F.dx;
-    if (D >= 2) {
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) dEx[d] += P[1][b][c][d] - P[0][b][c][d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dEx[d] = dEx[d] / (double)(NB * NC) / F.dx;
+    if constexpr (D >= 2) {
+#pragma unroll
         for (int a = 0; a < 2; ++a)
-            for (int c = 0; c < nc; ++c) {
-                long p1 = fnode(F, i + a, j + 1, k + c), p0 = fnode(F, i + a, j, k + c);
 #pragma unroll
-                for (int d = 0; d < 3; ++d) dEy[d] += E[(long)d * nnode + p1] - E[(long)d * nnode + p0];
-            }
+            for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int d = 0; d < 3; ++d) dEy[d] = dEy[d] / (double)(2 * nc) / F.dx;
+                for (int d = 0; d < 3; ++d) dEy[d] += P[a][1][c][d] - P[a][0][c][d];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dEy[d] = dEy[d] / (double)(2 * NC) / F.dx;
     }
-    if (D >= 3) {
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                long p1 = fnode(F, i + a, j + b, k + 1), p0 = fnode(F, i + a, j + b, k);
+    if constexpr (D >= 3) {
 #pragma unroll
-                for (int d = 0; d < 3; ++d) dEz[d] += E[(long)d * nnode + p1] - E[(long)d * nnode + p0];
-            }
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dEz[d] += P[a][b][1][d] - P[a][b][0][d];
 #pragma unroll
         for (int d = 0; d < 3; ++d) dEz[d] = dEz[d] / 4.0 / F.dx;
     }
@@ -265,6 +292,7 @@ __global__ void k_init_counts(Geo G, int32_t* cnt, int ppc) {
     using T = TileShape<D>;
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= G.ntiles) return;
+    cnt[G.ntiles + t] = 0;
     int tx = t % G.ntx, ty = (t / G.ntx) % G.nty, tz = t / (G.ntx * G.nty);
     int ex = min(T::X, G.nx - tx * T::X);
     int ey = D >= 2 ? min(T::Y, G.nyc - ty * T::Y) : 1;
@@ -299,9 +327,10 @@ template <typename R, int D>
 __global__ void k_compact(Geo G, PBuf<R> in, const int32_t* cnt, const int64_t* offs, int64_t cap,
                           int64_t* cell3, double* off3, double* v3, uint64_t* id) {
     int tile = blockIdx.x;
-    int n = min(cnt[tile], (int)cap);
+    int lo = cnt[tile];
+    int n = min(lo + cnt[G.ntiles + tile], (int)cap);
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        long src = (long)tile * cap + i;
+        long src = bin_slot(tile, cap, lo, i);
         long dst = offs[tile] + i;
         int32_t pc = in.cell[src];
         cell3[3 * dst] = cell_x(pc, G);
@@ -382,13 +411,14 @@ __global__ __launch_bounds__(256) void k_diag_field(FieldGeo F, const double* __
 
 // Per-tile kinetic energy sums (sum of |v|^2) in FP64.
 template <typename R>
-__global__ __launch_bounds__(256) void k_diag_kin(PBuf<R> in, const int32_t* cnt, int64_t cap, double* part) {
+__global__ __launch_bounds__(256) void k_diag_kin(PBuf<R> in, const int32_t* cnt, int ntiles, int64_t cap, double* part) {
     __shared__ double sh[256];
     int tile = blockIdx.x;
-    int n = min(cnt[tile], (int)cap);
+    int lo = cnt[tile];
+    int n = min(lo + cnt[ntiles + tile], (int)cap);
     double s = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        long src = (long)tile * cap + i;
+        long src = bin_slot(tile, cap, lo, i);
         double a = in.v[0][src], b = in.v[1][src], c = in.v[2][src];
         s += a * a + b * b + c * c;
     }

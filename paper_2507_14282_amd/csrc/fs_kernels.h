@@ -125,11 +125,12 @@ __device__ __forceinline__ void deposit_one(unsigned long long* lds, int bx0, in
                 unsigned long long gy = (unsigned long long)mul24(W, vq[1]);
                 unsigned long long gz = (unsigned long long)mul24(W, vq[2]);
                 if (in_lds) {
-                    unsigned long long* p = lds + 4 * ((lz + c) * X::DY * X::DX + (ly + b) * X::DX + (lx + a));
-                    atomicAdd(p + 0, r);
-                    atomicAdd(p + 1, gx);
-                    atomicAdd(p + 2, gy);
-                    atomicAdd(p + 3, gz);
+                    // planar [moment][node]: lanes at different nodes hit different banks
+                    unsigned long long* p = lds + ((lz + c) * X::DY * X::DX + (ly + b) * X::DX + (lx + a));
+                    atomicAdd(p, r);
+                    atomicAdd(p + X::DN, gx);
+                    atomicAdd(p + 2 * X::DN, gy);
+                    atomicAdd(p + 3 * X::DN, gz);
                 } else {
                     long gi = dep_index(cx + rx + a, D >= 2 ? cy + ry + b : 0, D >= 3 ? cz + rz + c : 0, G);
                     if (gi < 0) { oor = 1; continue; }
@@ -160,16 +161,18 @@ __device__ __forceinline__ int deposit_particle(unsigned long long* lds, int bx0
     return status;
 }
 
-// Flush of a tile's LDS accumulators: one global 64-bit atomic per non-zero
-// (node, moment).  Integer addition makes the result independent of order.
+// Flush of a tile's LDS accumulators (planar [moment][node]): one global
+// 64-bit atomic per non-zero (node, moment), issued node-major so that a
+// wave's atomics cover consecutive addresses.  Integer addition makes the
+// result independent of order.
 template <int D, int S>
 __device__ __forceinline__ void flush_tile(const unsigned long long* lds, unsigned long long* mom,
                                            const Geo& G, int bx0, int by0, int bz0, int& oor) {
     using X = Extent<D, S>;
     for (int l = threadIdx.x; l < X::DN * 4; l += blockDim.x) {
-        unsigned long long val = lds[l];
-        if (val == 0ull) continue;
         int node = l >> 2, m = l & 3;
+        unsigned long long val = lds[m * X::DN + node];
+        if (val == 0ull) continue;
         int lx = node % X::DX, ly = (node / X::DX) % X::DY, lz = node / (X::DX * X::DY);
         long gi = dep_index(bx0 + lx, D >= 2 ? by0 + ly : 0, D >= 3 ? bz0 + lz : 0, G);
         if (gi < 0) { oor = 1; continue; }
@@ -188,9 +191,61 @@ __device__ __forceinline__ void wave_add(unsigned long long* ctr, int v) {
 }
 
 // ---------------------------------------------------------------------------
+// Split tile bins.  The live ions of tile t in a buffer occupy
+// [t*cap, t*cap + lo) (written bottom-up by the tile's own workgroup, which
+// counts its stayers in LDS) and [t*cap + cap - hi, t*cap + cap) (filled
+// top-down through a global counter by everyone else: ions arriving from a
+// neighbour tile, reflected at the wall or injected).  counts[t] = lo,
+// counts[ntiles + t] = hi.  lo + hi > cap is an overflow.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long bin_slot(int tile, int64_t cap, int lo, int i) {
+    return (long)tile * cap + (i < lo ? i : (long)cap - 1 - (i - lo));
+}
+
+// Reserves a top-down slot of tile `dest`; returns -1 when the bin is full.
+__device__ __forceinline__ long bin_push_top(int32_t* counts, int ntiles, int dest, int64_t cap) {
+    int k = atomicAdd(counts + ntiles + dest, 1);
+    return k < cap ? (long)dest * cap + (cap - 1 - k) : -1;
+}
+
+template <typename R> struct alignas(2 * sizeof(R)) Pair { R x, y; };
+
+// LDS plan of the fused kernel: the gather stencil as three planar arrays
+// of component pairs (Ex,Ey) (Ez,Bx) (By,Bz), then the planar int64 moment
+// accumulators of the tile's deposit box, then one stayer counter.
+template <typename R, int D, int S> struct PushLds {
+    using X = Extent<D, S>;
+    static constexpr size_t a16(size_t x) { return (x + 15) / 16 * 16; }
+    static constexpr size_t gather = a16(3 * sizeof(Pair<R>) * X::GN);
+    static constexpr size_t dep = a16(32 * X::DN);
+    static constexpr size_t off_dep = gather, off_misc = gather + dep;
+    static constexpr size_t bytes(bool d) { return gather + (d ? dep : 0) + 16; }
+    static_assert(off_dep % 16 == 0 && off_misc % 16 == 0, "LDS regions must be aligned");
+};
+
+template <typename R, int D> struct Ion {
+    int32_t cell;
+    R o[3];
+    R v[3];
+    uint32_t id;
+};
+
+template <typename R, int D>
+__device__ __forceinline__ void load_ion(const PBuf<R>& in, long src, Ion<R, D>& p) {
+    p.cell = in.cell[src];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p.o[d] = d < D ? in.off[d][src] : (R)0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p.v[c] = in.v[c][src];
+    p.id = in.id[src];
+}
+
+// ---------------------------------------------------------------------------
 // The fused hot kernel: per tile, gather E/Bbar from LDS, Boris, move, apply
-// the open / periodic boundaries, list wall crossers, deposit the moments in
-// LDS and write each ion to the bin of its destination tile.
+// the open / periodic boundaries, list wall crossers, deposit the moments
+// (LDS int64 atomics into the tile's deposit box, one cell of halo; ions
+// that moved further go straight to the global grid) and write each ion to
+// the bin of its destination tile.
 // ---------------------------------------------------------------------------
 template <typename R, int D, int S, bool DEP>
 __global__ __launch_bounds__(256) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
@@ -200,11 +255,13 @@ __global__ __launch_bounds__(256) void k_push(Geo G, PBuf<R> in, PBuf<R> out, co
                                               int species) {
     using X = Extent<D, S>;
     using T = TileShape<D>;
+    using L = PushLds<R, D, S>;
     constexpr int LO = Stencil<S>::LO;
     constexpr int N = Stencil<S>::N;
     extern __shared__ __align__(16) unsigned char smem[];
-    R* sg = reinterpret_cast<R*>(smem);
-    unsigned long long* sd = reinterpret_cast<unsigned long long*>(smem + sizeof(R) * 8 * X::GN);
+    Pair<R>* sg = reinterpret_cast<Pair<R>*>(smem);
+    unsigned long long* sd = reinterpret_cast<unsigned long long*>(smem + L::off_dep);
+    int* s_stay = reinterpret_cast<int*>(smem + (DEP ? L::off_misc : L::off_dep));
 
     const int tile = xcd_tile(blockIdx.x, G.ntiles);
     const int tx = tile % G.ntx;
@@ -214,47 +271,48 @@ __global__ __launch_bounds__(256) void k_push(Geo G, PBuf<R> in, PBuf<R> out, co
     const int gx0 = x0 - LO, gy0 = D >= 2 ? y0 - LO : 0, gz0 = D >= 3 ? z0 - LO : 0;
     const int dx0 = x0 - 1 - LO, dy0 = D >= 2 ? y0 - 1 - LO : 0, dz0 = D >= 3 ? z0 - 1 - LO : 0;
 
-    // stage the gather stencil of the tile
     for (int l = threadIdx.x; l < X::GN; l += blockDim.x) {
         int lx = l % X::GX, ly = (l / X::GX) % X::GY, lz = l / (X::GX * X::GY);
         long gi = gather_index(gx0 + lx, gy0 + ly, gz0 + lz, G);
         const R* src = gather + 8 * gi;
-        R* dst = sg + 8 * l;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) dst[q] = src[q];
+        sg[l] = Pair<R>{src[0], src[1]};
+        sg[X::GN + l] = Pair<R>{src[2], src[4]};
+        sg[2 * X::GN + l] = Pair<R>{src[5], src[6]};
     }
     if constexpr (DEP)
         for (int l = threadIdx.x; l < X::DN * 4; l += blockDim.x) sd[l] = 0ull;
+    if (threadIdx.x == 0) *s_stay = 0;
     __syncthreads();
 
-    const int n = min(cnt_in[tile], (int)cap);
-    const long base = (long)tile * cap;
+    const int lo_in = cnt_in[tile], hi_in = cnt_in[G.ntiles + tile];
+    int status = (lo_in + hi_in > cap) ? F_TILE : 0;
+    const int n = min(lo_in + hi_in, (int)cap);
     const R h = (R)(0.5 * G.dt);
     const R dtdx = (R)G.dtdx;
-    int oor = 0, status = 0;
+    int oor = 0, nesc = 0, nopen = 0;
     const int lane = __lane_id();
 
+    Ion<R, D> cur;
+    if (n > 0) load_ion<R, D>(in, bin_slot(tile, cap, lo_in, min((int)threadIdx.x, n - 1)), cur);
     for (int i0 = 0; i0 < n; i0 += blockDim.x) {
         const int i = i0 + threadIdx.x;
         const bool valid = i < n;
-        const long src = base + (valid ? i : 0);
-        int32_t pc = in.cell[src];
-        R o[3] = {0, 0, 0}, v[3];
-#pragma unroll
-        for (int d = 0; d < D; ++d) o[d] = in.off[d][src];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = in.v[c][src];
-        uint32_t pid = in.id[src];
-        int cx = cell_x(pc, G), cy = D >= 2 ? cell_y(pc, G) : 0, cz = D >= 3 ? cell_z(pc, G) : 0;
+        // prefetch the next ion of this lane while the current one is pushed
+        Ion<R, D> nxt;
+        const int inext = i + blockDim.x;
+        if (i0 + (int)blockDim.x < n) load_ion<R, D>(in, bin_slot(tile, cap, lo_in, min(inext, n - 1)), nxt);
 
-        // gather E^n, Bbar^n from the staged stencil
+        int cx = cell_x(cur.cell, G), cy = D >= 2 ? cell_y(cur.cell, G) : 0, cz = D >= 3 ? cell_z(cur.cell, G) : 0;
+        R o[3] = {cur.o[0], cur.o[1], cur.o[2]};
+        R v[3] = {cur.v[0], cur.v[1], cur.v[2]};
+
+        // gather E^n, Bbar^n from the staged stencil; a binned ion always
+        // lies in its tile, the clamp only guards against a corrupt state
         R wx[3], wy[3] = {1, 0, 0}, wz[3] = {1, 0, 0};
         int rx, ry = 0, rz = 0;
         weights_real<R, S>(o[0], rx, wx);
         if constexpr (D >= 2) weights_real<R, S>(o[1], ry, wy);
         if constexpr (D >= 3) weights_real<R, S>(o[2], rz, wz);
-        // a binned ion always lies in its tile; clamp so that a corrupt state
-        // can never index outside the staged stencil
         const bool inside = (unsigned)(cx - x0) < (unsigned)T::X && (D < 2 || (unsigned)(cy - y0) < (unsigned)T::Y) &&
                             (D < 3 || (unsigned)(cz - z0) < (unsigned)T::Z);
         if (valid && !inside) oor = 1;
@@ -271,9 +329,10 @@ __global__ __launch_bounds__(256) void k_push(Geo G, PBuf<R> in, PBuf<R> out, co
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
                     R W = wx[a] * wyz;
-                    const R* s = sg + 8 * (((lz + c) * X::GY + (ly + b)) * X::GX + (lx + a));
-                    E[0] += W * s[0]; E[1] += W * s[1]; E[2] += W * s[2];
-                    B[0] += W * s[4]; B[1] += W * s[5]; B[2] += W * s[6];
+                    const int l = ((lz + c) * X::GY + (ly + b)) * X::GX + (lx + a);
+                    const Pair<R> p0 = sg[l], p1 = sg[X::GN + l], p2 = sg[2 * X::GN + l];
+                    E[0] += W * p0.x; E[1] += W * p0.y; E[2] += W * p1.x;
+                    B[0] += W * p1.y; B[1] += W * p2.x; B[2] += W * p2.y;
                 }
             }
         boris<R>(v, E, B, h);
@@ -295,14 +354,14 @@ __global__ __launch_bounds__(256) void k_push(Geo G, PBuf<R> in, PBuf<R> out, co
         if (G.xbc == 1) wxc = wrapi(nc[0], G.nx);
         else if (nc[0] >= G.nx) kind = policy == 0 ? 3 : 1;
         else if (nc[0] < 0) kind = 2;
-        int wyc = D >= 2 ? wrapi(nc[1], G.nyc) : 0;
-        int wzc = D >= 3 ? wrapi(nc[2], G.nzc) : 0;
+        const int wyc = D >= 2 ? wrapi(nc[1], G.nyc) : 0;
+        const int wzc = D >= 3 ? wrapi(nc[2], G.nzc) : 0;
         if (!valid) kind = 4;
 
         if (kind == 1) {
             int slot = atomicAdd(xl.count, 1);
             if (slot < xl.cap) {
-                xl.id[slot] = pid;
+                xl.id[slot] = cur.id;
                 xl.delta[slot] = (double)(nc[0] - G.nx) + (double)o[0];
                 xl.cy[slot] = wyc;
                 xl.cz[slot] = wzc;
@@ -315,50 +374,65 @@ __global__ __launch_bounds__(256) void k_push(Geo G, PBuf<R> in, PBuf<R> out, co
                 status |= F_XLIST;
             }
         }
-        wave_add(ctr + C_ESC, kind == 2);
-        wave_add(ctr + C_OPEN, kind == 3);
-        wave_add(ctr + (species == 0 ? C_REM0 : C_REM1), kind == 2 || kind == 3);
+        nesc += kind == 2;
+        nopen += kind == 3;
 
         if constexpr (DEP) {
             if (kind == 0)
                 status |= deposit_particle<R, D, S>(sd, dx0, dy0, dz0, mom, G, nc[0], nc[1], nc[2], o, v, oor);
         }
 
-        // write to the destination tile's bin; ions staying in this tile get
-        // one wave-aggregated slot reservation
+        // write to the destination tile's bin: stayers bottom-up through one
+        // LDS counter per wave, others top-down through the global counter
         const int dest = kind == 0 ? tile_of<D>(wxc, wyc, wzc, G) : -1;
         const bool stay = dest == tile;
         const unsigned long long sm = __ballot(stay);
-        int slot = -1;
+        long dst = -1;
         if (sm) {
             int leader = (int)__ffsll((long long)sm) - 1;
             int s0 = 0;
-            if (lane == leader) s0 = atomicAdd(cnt_out + tile, (int)__popcll(sm));
+            if (lane == leader) s0 = atomicAdd(s_stay, (int)__popcll(sm));
             s0 = __shfl(s0, leader);
-            if (stay) slot = s0 + (int)__popcll(sm & ((1ull << lane) - 1ull));
+            if (stay) {
+                int slot = s0 + (int)__popcll(sm & ((1ull << lane) - 1ull));
+                dst = slot < cap ? (long)tile * cap + slot : -1;
+            }
         }
-        if (kind == 0 && !stay) slot = atomicAdd(cnt_out + dest, 1);
+        if (kind == 0 && !stay) dst = bin_push_top(cnt_out, G.ntiles, dest, cap);
         if (kind == 0) {
-            if (slot < cap) {
-                long dst = (long)dest * cap + slot;
+            if (dst >= 0) {
                 out.cell[dst] = pack_cell(wxc, wyc, wzc, G);
 #pragma unroll
                 for (int d = 0; d < D; ++d) out.off[d][dst] = o[d];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) out.v[c][dst] = v[c];
-                out.id[dst] = pid;
+                out.id[dst] = cur.id;
             } else {
                 status |= F_TILE;
             }
         }
+        cur = nxt;
     }
-    if constexpr (DEP) {
-        __syncthreads();
-        flush_tile<D, S>(sd, mom, G, dx0, dy0, dz0, oor);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int ns = *s_stay;
+        cnt_out[tile] = min(ns, (int)cap);
+        if (ns > cap) status |= F_TILE;
     }
+    if constexpr (DEP) flush_tile<D, S>(sd, mom, G, dx0, dy0, dz0, oor);
+    wave_add(ctr + C_ESC, nesc);
+    wave_add(ctr + C_OPEN, nopen);
+    wave_add(ctr + (species == 0 ? C_REM0 : C_REM1), nesc + nopen);
     wave_add(ctr + C_SAT, (status & F_SAT) ? 1 : 0);
     wave_add(ctr + C_OOR, oor);
     if (status) atomicOr(reinterpret_cast<unsigned int*>(ctr + C_FLAGS), (unsigned int)status);
+}
+
+// Overflow check of every bin after all writers of a step.
+__global__ void k_check_bins(const int32_t* counts, int ntiles, int64_t cap, unsigned long long* ctr) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ntiles && (long)counts[t] + counts[ntiles + t] > cap)
+        atomicOr(reinterpret_cast<unsigned int*>(ctr + C_FLAGS), (unsigned int)F_TILE);
 }
 
 // ---------------------------------------------------------------------------
@@ -405,9 +479,8 @@ __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int3
         R vr[3] = {(R)vout[0], (R)vout[1], (R)vout[2]};
         int cy = xl.cy[i], cz = xl.cz[i];
         int dest = tile_of<D>(cx, cy, cz, G);
-        int slot = atomicAdd(cnt_out + dest, 1);
-        if (slot >= cap) { status |= F_TILE; continue; }
-        long dst = (long)dest * cap + slot;
+        long dst = bin_push_top(cnt_out, G.ntiles, dest, cap);
+        if (dst < 0) { status |= F_TILE; continue; }
         out.cell[dst] = pack_cell(cx, cy, cz, G);
 #pragma unroll
         for (int d = 0; d < D; ++d) out.off[d][dst] = o[d];
@@ -478,14 +551,13 @@ __global__ __launch_bounds__(256) void k_inject(Geo G, PBuf<R> out0, int32_t* cn
     int64_t cap = cr ? cap1 : cap0;
     unsigned long long* mom = cr ? mom1 : mom0;
     int dest = tile_of<D>(cx, cy, cz, G);
-    int slot = atomicAdd(cnt + dest, 1);
+    long dst = bin_push_top(cnt, G.ntiles, dest, cap);
     atomicAdd(ctr + (cr ? C_ADD1 : C_ADD0), 1ull);
     atomicAdd(ctr + (cr ? C_INJ_CR : C_INJ_TH), 1ull);
-    if (slot >= cap) {
+    if (dst < 0) {
         atomicOr(reinterpret_cast<unsigned int*>(ctr + C_FLAGS), (unsigned int)F_TILE);
         return;
     }
-    long dst = (long)dest * cap + slot;
     out.cell[dst] = pack_cell(cx, cy, cz, G);
 #pragma unroll
     for (int d = 0; d < D; ++d) out.off[d][dst] = o[d];
@@ -515,11 +587,11 @@ __global__ __launch_bounds__(256) void k_deposit(Geo G, PBuf<R> in, const int32_
     const int dx0 = tx * T::X - 1 - LO, dy0 = D >= 2 ? ty * T::Y - 1 - LO : 0, dz0 = D >= 3 ? tz * T::Z - 1 - LO : 0;
     for (int l = threadIdx.x; l < X::DN * 4; l += blockDim.x) sd[l] = 0ull;
     __syncthreads();
-    const int n = min(cnt[tile], (int)cap);
-    const long base = (long)tile * cap;
+    const int lo = cnt[tile];
+    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
     int status = 0, oor = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        long src = base + i;
+        long src = bin_slot(tile, cap, lo, i);
         int32_t pc = in.cell[src];
         R o[3] = {0, 0, 0}, v[3];
 #pragma unroll

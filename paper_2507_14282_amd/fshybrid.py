@@ -120,6 +120,8 @@ def library():
         L.fs_next_id.argtypes = [vp]
         L.fs_next_id.restype = i64
         L.fs_diagnostics.argtypes = [vp, P, F, vp, vp, vp]
+        L.fs_timing_enable.argtypes = [vp, i32]
+        L.fs_timing_read.argtypes = [vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -128,7 +130,8 @@ def exported_symbols():
     """Names of the C entry points the binding expects the library to export."""
     return ["fs_layout", "fs_create", "fs_destroy", "fs_last_error", "fs_init_plasma", "fs_step",
             "fs_deposit_moments", "fs_apply_faux_shock", "fs_field_update", "fs_refresh_fields",
-            "fs_load_particles", "fs_read_particles", "fs_set_clock", "fs_next_id", "fs_diagnostics"]
+            "fs_load_particles", "fs_read_particles", "fs_set_clock", "fs_next_id", "fs_diagnostics",
+            "fs_timing_enable", "fs_timing_read"]
 
 
 def make_config(p: dict) -> FsConfig:
@@ -184,7 +187,7 @@ class Simulation:
         for s in range(2):
             nb = int(L.buf_bytes[s]) if (s == 0 or self.has_cr) else 0
             bufs = [torch.empty(max(nb, 256), dtype=torch.uint8, device=dev) for _ in range(2)]
-            cnts = [torch.zeros(int(L.ntiles), dtype=torch.int32, device=dev) for _ in range(2)]
+            cnts = [torch.zeros(2 * int(L.ntiles), dtype=torch.int32, device=dev) for _ in range(2)]
             count = torch.zeros(1, dtype=torch.int64, device=dev)
             self._keep += bufs + cnts + [count]
             self.counts.append(count)
@@ -326,6 +329,16 @@ class Simulation:
 
     def set_moments(self, species: int, m):
         self.mom[species].copy_(torch.as_tensor(np.asarray(m, dtype=np.int64), device=self.device))
+
+    def timing(self, on: bool = True):
+        self._check(self.lib.fs_timing_enable(self.h, 1 if on else 0))
+
+    def timing_read(self):
+        """(ms, n) per phase: push, wall, inject, field, whole step."""
+        ms = np.zeros(5)
+        n = np.zeros(5, dtype=np.int64)
+        self._check(self.lib.fs_timing_read(self.h, ms.ctypes.data, n.ctypes.data, self.stream))
+        return ms, n
 
     def diagnostics(self) -> dict:
         out = np.zeros(8)
