@@ -221,21 +221,43 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
     const long nn = h->L.nnode, nc = h->L.ncent;
     const dim3 blk(kFX, kFY, 1);
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
-    const dim3 gc((unsigned)((h->cfg.nx + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
     k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(f->mom[0]),
                                reinterpret_cast<const long long*>(h->has_cr ? f->mom[1] : f->mom[0]), h->fluid, nn);
+    const double hs = h->cfg.dt / (double)h->cfg.n_sub;
+    if constexpr (D == 3) {
+        // z-marching kernels: 32 x 8 columns over runs of at most 32 z planes
+        const int gx = (h->cfg.nx + ZMarch::X - 1) / ZMarch::X, gxo = (int)((h->L.nxn + ZMarch::X - 1) / ZMarch::X);
+        const int gy = (int)((h->L.nyc + ZMarch::Y - 1) / ZMarch::Y);
+        const int zc = (int)std::min<int64_t>(h->L.nzc, 32), gz = (int)((h->L.nzc + zc - 1) / zc);
+        if (rk) {
+            const unsigned nb = (unsigned)(gx * gy * gz);
+            for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
+                k_stage3<<<nb, 256, 0, s>>>(h->F, f->B, f->B, h->B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy, zc);
+                k_stage3<<<nb, 256, 0, s>>>(h->F, h->B1, f->B, h->B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy, zc);
+                k_stage3<<<nb, 256, 0, s>>>(h->F, h->B2, f->B, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy,
+                                            zc);
+            }
+        }
+        k_ohm3<R><<<(unsigned)(gxo * gy * gz), 256, 0, s>>>(h->F, f->B, h->fluid, f->E, static_cast<R*>(f->gather), nn,
+                                                           nc, gxo, gy, zc);
+        return;
+    }
+    using FB = FieldBlock<D>;
+    const int gy = (int)((h->L.nyc + FB::Y - 1) / FB::Y), gz = (int)((h->L.nzc + FB::Z - 1) / FB::Z);
     if (rk) {
-        const double hs = h->cfg.dt / (double)h->cfg.n_sub;
+        const int gx = (h->cfg.nx + FB::X - 1) / FB::X;
+        const unsigned nb = (unsigned)(gx * gy * gz);
         for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
-            k_ohm<R, D><<<gn, blk, 0, s>>>(h->F, f->B, h->fluid, h->Etmp, nullptr, nn, nc);
-            k_faraday<D><<<gc, blk, 0, s>>>(h->F, h->Etmp, f->B, f->B, h->B1, 0.0, 1.0, hs, nn, nc);
-            k_ohm<R, D><<<gn, blk, 0, s>>>(h->F, h->B1, h->fluid, h->Etmp, nullptr, nn, nc);
-            k_faraday<D><<<gc, blk, 0, s>>>(h->F, h->Etmp, f->B, h->B1, h->B2, 0.75, 0.25, hs, nn, nc);
-            k_ohm<R, D><<<gn, blk, 0, s>>>(h->F, h->B2, h->fluid, h->Etmp, nullptr, nn, nc);
-            k_faraday<D><<<gc, blk, 0, s>>>(h->F, h->Etmp, f->B, h->B2, f->B, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc);
+            // SSP-RK3 (Shu-Osher): B1 = B + h F(B); B2 = 3/4 B + 1/4 (B1 + h F(B1));
+            // B <- 1/3 B + 2/3 (B2 + h F(B2)); the last stage writes in place
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, f->B, f->B, h->B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy);
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, h->B1, f->B, h->B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy);
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, h->B2, f->B, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy);
         }
     }
-    k_ohm<R, D><<<gn, blk, 0, s>>>(h->F, f->B, h->fluid, f->E, static_cast<R*>(f->gather), nn, nc);
+    const int gxo = (int)((h->L.nxn + FB::X - 1) / FB::X);
+    k_ohm<R, D><<<(unsigned)(gxo * gy * gz), 256, 0, s>>>(h->F, f->B, h->fluid, f->E, static_cast<R*>(f->gather), nn, nc,
+                                                        gxo, gy);
 }
 
 template <typename R> void field_update(fs_handle* h, fs_fields* f, hipStream_t s, bool rk) {
@@ -476,7 +498,7 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     G.cr_w = c.cr_w; G.dtdx = c.dt / c.dx; G.seed = c.seed;
     FieldGeo& F = h->F;
     F.dim = c.dim; F.nx = c.nx; F.nyc = G.nyc; F.nzc = G.nzc; F.nxn = G.nxn; F.ndx = G.ndx; F.g = G.g;
-    F.xbc = c.xbc; F.mclamp = c.shape; F.dx = c.dx;
+    F.xbc = c.xbc; F.mclamp = c.shape; F.dx = c.dx; F.rdx = 1.0 / c.dx;
     const double th = c.theta_deg * (kTwoPi / 360.0);
     F.B0[0] = std::cos(th); F.B0[1] = std::sin(th); F.B0[2] = 0.0;
     F.n_floor = c.n_floor; F.beta_e = c.beta_e; F.gamma_e = c.gamma_e; F.eta = c.eta; F.j_ext = c.j_ext;

@@ -16,7 +16,7 @@ namespace fsk {
 
 struct FieldGeo {
     int dim, nx, nyc, nzc, nxn, ndx, g, xbc, mclamp;
-    double dx, B0[3];
+    double dx, rdx, B0[3];
     double n_floor, beta_e, gamma_e, eta, j_ext;
     double wth, wcr, scR, scG;    // species weights and fixed-point scales
     int has_cr;
@@ -77,30 +77,101 @@ __device__ __forceinline__ long fnode(const FieldGeo& F, int i, int j, int k) {
     return (long)i + (long)F.nxn * (j + (long)F.nyc * k);
 }
 
-// Ohm's law at every node: E = (-Gamma x Bbar + J x Bbar - grad p_e)/n_e + eta J
-// with Bbar the mean of the 2^D centres around the node and J = curl B from
-// their differences.  With `gather` set it also writes E and Bbar in the
-// particle precision for the push.
-template <typename R, int D>
-__global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restrict__ B, const double* __restrict__ fl,
-                                             double* __restrict__ E, R* __restrict__ gather, long nnode, long ncent) {
-    const int i = blockIdx.x * kFX + threadIdx.x;
-    const int j = blockIdx.y * kFY + threadIdx.y, k = blockIdx.z;
-    if (i >= F.nxn || j >= F.nyc) return;
-    const long n = i + (long)F.nxn * (j + (long)F.nyc * k);
+// Block shape (cells) of the tiled field kernels, and the LDS tiles one
+// block stages: B at centres x0-1 .. x0+X (and likewise in y, z where the
+// dimension exists), E at nodes x0 .. x0+X, p_e at nodes x0-1 .. x0+X+1.
+template <int D> struct FieldBlock;
+template <> struct FieldBlock<1> { static constexpr int X = 256, Y = 1, Z = 1; };
+template <> struct FieldBlock<2> { static constexpr int X = 32, Y = 8, Z = 1; };
+template <> struct FieldBlock<3> { static constexpr int X = 16, Y = 4, Z = 4; };
+
+template <int D> struct FieldTile {
+    using FB = FieldBlock<D>;
+    static constexpr int OY = D >= 2 ? 1 : 0, OZ = D >= 3 ? 1 : 0;
+    static constexpr int CX = FB::X + 2, CY = FB::Y + 2 * OY, CZ = FB::Z + 2 * OZ;
+    static constexpr int NX = FB::X + 1, NY = FB::Y + OY, NZ = FB::Z + OZ;
+    static constexpr int PX = FB::X + 3, PY = FB::Y + 3 * OY, PZ = FB::Z + 3 * OZ;
+    static constexpr int CN = CX * CY * CZ, NN = NX * NY * NZ, PN = PX * PY * PZ;
+    static_assert(FB::X * FB::Y * FB::Z == 256, "one centre per thread");
+};
+
+// Stage the block's B (centres, ghost rules in x) and p_e (nodes, clamped in
+// x for the box) into LDS.  Every load of the block is issued before the
+// first LDS store, so each thread keeps a dozen HBM requests in flight.
+template <int D>
+__device__ __forceinline__ void stage_tiles(const FieldGeo& F, const double* __restrict__ B,
+                                            const double* __restrict__ pe, long ncent, int x0, int y0, int z0,
+                                            double (*sB)[FieldTile<D>::CN], double* sP) {
+    using T = FieldTile<D>;
+    constexpr int IC = (T::CN + 255) / 256, IP = (T::PN + 255) / 256;
+    double vb[IC][3], vp[IP];
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+        const int l = threadIdx.x + 256 * it;
+        vb[it][0] = vb[it][1] = vb[it][2] = 0.0;
+        if (it + 1 < IC || l < T::CN) {
+            const int lx = l % T::CX, r = l / T::CX, ly = r % T::CY, lz = r / T::CY;
+            int i = x0 - 1 + lx;
+            const int j = D >= 2 ? wrapi(y0 - 1 + ly, F.nyc) : 0, k = D >= 3 ? wrapi(z0 - 1 + lz, F.nzc) : 0;
+            if (F.xbc == 1) i = wrapi(i, F.nx);
+            else if (i >= F.nx) i = F.nx - 1;
+            if (i < 0) {
+                vb[it][0] = F.B0[0]; vb[it][1] = F.B0[1]; vb[it][2] = F.B0[2];
+            } else {
+                const long q = i + (long)F.nx * (j + (long)F.nyc * k);
+                vb[it][0] = B[q]; vb[it][1] = B[ncent + q]; vb[it][2] = B[2 * ncent + q];
+            }
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IP; ++it) {
+        const int l = threadIdx.x + 256 * it;
+        vp[it] = 0.0;
+        if (it + 1 < IP || l < T::PN) {
+            const int lx = l % T::PX, r = l / T::PX, ly = r % T::PY, lz = r / T::PY;
+            int i = x0 - 1 + lx;
+            const int j = D >= 2 ? wrapi(y0 - 1 + ly, F.nyc) : 0, k = D >= 3 ? wrapi(z0 - 1 + lz, F.nzc) : 0;
+            if (F.xbc == 1) i = wrapi(i, F.nx);
+            else i = i < 0 ? 0 : (i > F.nx ? F.nx : i);
+            vp[it] = pe[i + (long)F.nxn * (j + (long)F.nyc * k)];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IC; ++it) {
+        const int l = threadIdx.x + 256 * it;
+        if (it + 1 < IC || l < T::CN) { sB[0][l] = vb[it][0]; sB[1][l] = vb[it][1]; sB[2][l] = vb[it][2]; }
+    }
+#pragma unroll
+    for (int it = 0; it < IP; ++it) {
+        const int l = threadIdx.x + 256 * it;
+        if (it + 1 < IP || l < T::PN) sP[l] = vp[it];
+    }
+}
+
+// Block -> tile of the field grid, XCD-aware: the blocks one XCD receives
+// (round robin over 8) cover a contiguous run of tiles, x fastest, so the
+// halos they share stay in that XCD's L2.
+__device__ __forceinline__ void field_block(int gx, int gy, int& bx, int& by, int& bz) {
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    bx = t % gx;
+    const int r = t / gx;
+    by = r % gy;
+    bz = r / gy;
+}
+
+// Ohm's law at one node: E = (-Gamma x Bbar + J x Bbar - grad p_e)/n_e
+// + eta J, with Bbar the mean of the 2^D surrounding centres
+// (C[a][b][c] = B at centre (x-1+a, y-1+b, z-1+c)), J = curl B from their
+// transverse-averaged differences, and dp the central p_e differences across
+// the node (zero along absent dimensions).
+template <int D>
+__device__ __forceinline__ void ohm_core(const FieldGeo& F, const double (&C)[2][D >= 2 ? 2 : 1][D >= 3 ? 2 : 1][3],
+                                         const double dp[3], double ne, const double G[3], double e[3],
+                                         double bb[3]) {
     constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
-    // C[a][b][c] = B at centre (i-1+a, j-1+b, k-1+c)
-    double C[2][NB][NC][3];
+    double dBx[3] = {0, 0, 0}, dBy[3] = {0, 0, 0}, dBz[3] = {0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-#pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    C[a][b][c][d] = centre_B(B, F, ncent, i - 1 + a, D >= 2 ? j - 1 + b : 0, D >= 3 ? k - 1 + c : 0, d);
-    double bb[3] = {0, 0, 0}, dBx[3] = {0, 0, 0}, dBy[3] = {0, 0, 0}, dBz[3] = {0, 0, 0};
+    for (int d = 0; d < 3; ++d) bb[d] = 0.0;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -118,7 +189,7 @@ __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restric
 #pragma unroll
             for (int d = 0; d < 3; ++d) dBx[d] += C[1][b][c][d] - C[0][b][c][d];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) dBx[d] = dBx[d] / (double)(NB * NC) / F.dx;
+    for (int d = 0; d < 3; ++d) dBx[d] = dBx[d] * (1.0 / (double)(NB * NC)) * F.rdx;
     if constexpr (D >= 2) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
@@ -127,7 +198,7 @@ __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restric
 #pragma unroll
                 for (int d = 0; d < 3; ++d) dBy[d] += C[a][1][c][d] - C[a][0][c][d];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) dBy[d] = dBy[d] / (double)(2 * NC) / F.dx;
+        for (int d = 0; d < 3; ++d) dBy[d] = dBy[d] * (1.0 / (double)(2 * NC)) * F.rdx;
     }
     if constexpr (D >= 3) {
 #pragma unroll
@@ -137,73 +208,134 @@ __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restric
 #pragma unroll
                 for (int d = 0; d < 3; ++d) dBz[d] += C[a][b][1][d] - C[a][b][0][d];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) dBz[d] = dBz[d] / 4.0 / F.dx;
+        for (int d = 0; d < 3; ++d) dBz[d] = dBz[d] * 0.25 * F.rdx;
     }
     const double J[3] = {dBy[2] - dBz[1], dBz[0] - dBx[2], dBx[1] - dBy[0]};
-    const double* pe = fl + nnode;
-    double gp[3] = {0, 0, 0};
-    gp[0] = (pe[fnode(F, i + 1, j, k)] - pe[fnode(F, i - 1, j, k)]) / (2.0 * F.dx);
-    if constexpr (D >= 2) gp[1] = (pe[fnode(F, i, j + 1, k)] - pe[fnode(F, i, j - 1, k)]) / (2.0 * F.dx);
-    if constexpr (D >= 3) gp[2] = (pe[fnode(F, i, j, k + 1)] - pe[fnode(F, i, j, k - 1)]) / (2.0 * F.dx);
-    const double ne = fl[n];
-    const double G[3] = {fl[2 * nnode + n], fl[3 * nnode + n], fl[4 * nnode + n]};
+    const double h2 = 0.5 * F.rdx;
+    const double gp[3] = {dp[0] * h2, dp[1] * h2, dp[2] * h2};
+    const double rne = 1.0 / ne;
     double num[3];
     num[0] = -(G[1] * bb[2] - G[2] * bb[1]) + (J[1] * bb[2] - J[2] * bb[1]) - gp[0];
     num[1] = -(G[2] * bb[0] - G[0] * bb[2]) + (J[2] * bb[0] - J[0] * bb[2]) - gp[1];
     num[2] = -(G[0] * bb[1] - G[1] * bb[0]) + (J[0] * bb[1] - J[1] * bb[0]) - gp[2];
-    double e[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        e[d] = num[d] / ne + F.eta * J[d];
-        E[(long)d * nnode + n] = e[d];
-    }
-    if (gather) {
-        R* gp8 = gather + 8 * n;
-        gp8[0] = (R)e[0]; gp8[1] = (R)e[1]; gp8[2] = (R)e[2]; gp8[3] = (R)0;
-        gp8[4] = (R)bb[0]; gp8[5] = (R)bb[1]; gp8[6] = (R)bb[2]; gp8[7] = (R)0;
-    }
+    for (int d = 0; d < 3; ++d) e[d] = num[d] * rne + F.eta * J[d];
 }
 
-// One SSP-RK3 stage at every centre: Bout = c0 Bn + c1 (Bin - h curl E),
-// with curl E from the 2^D nodes around the centre.
+// Ohm's law at the node of local tile position (lx, ly, lz), global node
+// index n, from the block's LDS tiles.
 template <int D>
-__global__ __launch_bounds__(256) void k_faraday(FieldGeo F, const double* __restrict__ E, const double* __restrict__ Bn,
-                                                 const double* __restrict__ Bin, double* __restrict__ Bout,
-                                                 double c0, double c1, double h, long nnode, long ncent) {
-    const int i = blockIdx.x * kFX + threadIdx.x;
-    const int j = blockIdx.y * kFY + threadIdx.y, k = blockIdx.z;
-    if (i >= F.nx || j >= F.nyc) return;
-    const long n = i + (long)F.nx * (j + (long)F.nyc * k);
+__device__ __forceinline__ void ohm_tile(const FieldGeo& F, const double (*sB)[FieldTile<D>::CN],
+                                         const double* sP, const double* __restrict__ fl, long nnode, long n,
+                                         int lx, int ly, int lz, double e[3], double bb[3]) {
+    using T = FieldTile<D>;
     constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
-    double P[2][NB][NC][3];   // E at node (i+a, j+b, k+c)
+    double C[2][NB][NC][3];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                long q = fnode(F, i + a, j + b, k + c);
+                const int l = (lx + a) + T::CX * ((ly + b) + T::CY * (lz + c));
 #pragma unroll
-                for (int d = 0; d < 3; ++d) P[a][b][c][d] = E[(long)d * nnode + q];
+                for (int d = 0; d < 3; ++d) C[a][b][c][d] = sB[d][l];
             }
+    auto P = [&](int ex, int ey, int ez) {
+        return sP[(lx + 1 + ex) + T::PX * ((ly + T::OY + ey) + T::PY * (lz + T::OZ + ez))];
+    };
+    double dp[3] = {P(1, 0, 0) - P(-1, 0, 0), 0.0, 0.0};
+    if constexpr (D >= 2) dp[1] = P(0, 1, 0) - P(0, -1, 0);
+    if constexpr (D >= 3) dp[2] = P(0, 0, 1) - P(0, 0, -1);
+    const double G[3] = {fl[2 * nnode + n], fl[3 * nnode + n], fl[4 * nnode + n]};
+    ohm_core<D>(F, C, dp, fl[n], G, e, bb);
+}
+
+// Ohm's law at every node of the block, writing E (FP64) and E, Bbar in the
+// particle precision into the gather grid.  Grid: nodes in x, centres in y/z.
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restrict__ B, const double* __restrict__ fl,
+                                             double* __restrict__ E, R* __restrict__ gather, long nnode, long ncent,
+                                             int gx, int gy) {
+    using T = FieldTile<D>;
+    using FB = FieldBlock<D>;
+    __shared__ double sB[3][T::CN];
+    __shared__ double sP[T::PN];
+    int bx, by, bz;
+    field_block(gx, gy, bx, by, bz);
+    const int x0 = bx * FB::X, y0 = by * FB::Y, z0 = bz * FB::Z;
+    stage_tiles<D>(F, B, fl + nnode, ncent, x0, y0, z0, sB, sP);
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int tx = t % FB::X, ty = (t / FB::X) % FB::Y, tz = t / (FB::X * FB::Y);
+    const int i = x0 + tx, j = y0 + ty, k = z0 + tz;
+    if (i >= F.nxn || j >= F.nyc || k >= F.nzc) return;
+    const long n = i + (long)F.nxn * (j + (long)F.nyc * k);
+    double e[3], bb[3];
+    ohm_tile<D>(F, sB, sP, fl, nnode, n, tx, ty, tz, e, bb);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) E[(long)d * nnode + n] = e[d];
+    R* g8 = gather + 8 * n;
+    g8[0] = (R)e[0]; g8[1] = (R)e[1]; g8[2] = (R)e[2]; g8[3] = (R)0;
+    g8[4] = (R)bb[0]; g8[5] = (R)bb[1]; g8[6] = (R)bb[2]; g8[7] = (R)0;
+}
+
+// One SSP-RK3 stage, fused: E = Ohm(Bin) at the block's nodes (its centres
+// plus one node of halo) into LDS, then Bout = c0 Bn + c1 (Bin - h curl E)
+// at the block's centres.  Neither E nor a second copy of Bin goes through
+// HBM.  With c0 == 0, Bn is not read.
+template <int D>
+__global__ __launch_bounds__(256) void k_stage(FieldGeo F, const double* __restrict__ Bin, const double* __restrict__ Bn,
+                                               double* __restrict__ Bout, const double* __restrict__ fl, double c0,
+                                               double c1, double h, long nnode, long ncent, int gx, int gy) {
+    using T = FieldTile<D>;
+    using FB = FieldBlock<D>;
+    __shared__ double sB[3][T::CN];
+    __shared__ double sP[T::PN];
+    __shared__ double sE[3][T::NN];
+    int bx, by, bz;
+    field_block(gx, gy, bx, by, bz);
+    const int x0 = bx * FB::X, y0 = by * FB::Y, z0 = bz * FB::Z;
+    stage_tiles<D>(F, Bin, fl + nnode, ncent, x0, y0, z0, sB, sP);
+    __syncthreads();
+    for (int l = threadIdx.x; l < T::NN; l += 256) {
+        const int lx = l % T::NX, r = l / T::NX, ly = r % T::NY, lz = r / T::NY;
+        int i = x0 + lx;
+        const int j = D >= 2 ? wrapi(y0 + ly, F.nyc) : 0, k = D >= 3 ? wrapi(z0 + lz, F.nzc) : 0;
+        double e[3] = {0, 0, 0}, bb[3];
+        // nodes past the box are read only by centres that do not exist
+        if (F.xbc == 1 || i <= F.nx) {
+            if (F.xbc == 1) i = wrapi(i, F.nx);
+            const long n = i + (long)F.nxn * (j + (long)F.nyc * k);
+            ohm_tile<D>(F, sB, sP, fl, nnode, n, lx, ly, lz, e, bb);
+        }
+        sE[0][l] = e[0]; sE[1][l] = e[1]; sE[2][l] = e[2];
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int tx = t % FB::X, ty = (t / FB::X) % FB::Y, tz = t / (FB::X * FB::Y);
+    const int i = x0 + tx, j = y0 + ty, k = z0 + tz;
+    if (i >= F.nx || j >= F.nyc || k >= F.nzc) return;
+    constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
     double dEx[3] = {0, 0, 0}, dEy[3] = {0, 0, 0}, dEz[3] = {0, 0, 0};
+    auto at = [&](int a, int b, int c) { return (tx + a) + T::NX * ((ty + b) + T::NY * (tz + c)); };
 #pragma unroll
     for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) dEx[d] += P[1][b][c][d] - P[0][b][c][d];
+            for (int d = 0; d < 3; ++d) dEx[d] += sE[d][at(1, b, c)] - sE[d][at(0, b, c)];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) dEx[d] = dEx[d] / (double)(NB * NC) / F.dx;
+    for (int d = 0; d < 3; ++d) dEx[d] = dEx[d] * (1.0 / (double)(NB * NC)) * F.rdx;
     if constexpr (D >= 2) {
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
-                for (int d = 0; d < 3; ++d) dEy[d] += P[a][1][c][d] - P[a][0][c][d];
+                for (int d = 0; d < 3; ++d) dEy[d] += sE[d][at(a, 1, c)] - sE[d][at(a, 0, c)];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) dEy[d] = dEy[d] / (double)(2 * NC) / F.dx;
+        for (int d = 0; d < 3; ++d) dEy[d] = dEy[d] * (1.0 / (double)(2 * NC)) * F.rdx;
     }
     if constexpr (D >= 3) {
 #pragma unroll
@@ -211,16 +343,298 @@ __global__ __launch_bounds__(256) void k_faraday(FieldGeo F, const double* __res
 #pragma unroll
             for (int b = 0; b < 2; ++b)
 #pragma unroll
-                for (int d = 0; d < 3; ++d) dEz[d] += P[a][b][1][d] - P[a][b][0][d];
+                for (int d = 0; d < 3; ++d) dEz[d] += sE[d][at(a, b, 1)] - sE[d][at(a, b, 0)];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) dEz[d] = dEz[d] / 4.0 / F.dx;
+        for (int d = 0; d < 3; ++d) dEz[d] = dEz[d] * 0.25 * F.rdx;
     }
     const double rhs[3] = {-(dEy[2] - dEz[1]), -(dEz[0] - dEx[2]), -(dEx[1] - dEy[0])};
+    const long n = i + (long)F.nx * (j + (long)F.nyc * k);
+    const int lc = (tx + 1) + T::CX * ((ty + T::OY) + T::CY * (tz + T::OZ));
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        long q = (long)d * ncent + n;
-        double s = Bin[q] + h * rhs[d];
-        Bout[q] = c0 == 0.0 ? c1 * s : c0 * Bn[q] + c1 * s;
+        const long q = (long)d * ncent + n;
+        const double sv = sB[d][lc] + h * rhs[d];
+        Bout[q] = c0 == 0.0 ? c1 * sv : c0 * Bn[q] + c1 * sv;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3D field kernels that march through z.  A 32 x 8 block in (x, y) walks a
+// run of z planes and keeps rings of B centre planes (3), p_e node planes
+// (3) and E node planes (2) in LDS, so each value comes from HBM about once
+// per column (halo 1.3x in x/y, none in z) instead of once per face of a
+// small 3D tile.
+// ---------------------------------------------------------------------------
+struct ZMarch {
+    static constexpr int X = 32, Y = 8;
+    static constexpr int CX = X + 2, CY = Y + 2, CN = CX * CY;   // centres x0-1 .. x0+X
+    static constexpr int PX = X + 3, PY = Y + 3, PN = PX * PY;   // p_e at nodes x0-1 .. x0+X+1
+    static constexpr int NX = X + 1, NY = Y + 1, NN = NX * NY;   // nodes x0 .. x0+X
+    static constexpr int IC = (CN + 255) / 256, IP = (PN + 255) / 256, IN = (NN + 255) / 256;
+};
+
+// Block -> (x0, y0, z range), XCD-aware over (x, y, z-run) with x fastest.
+__device__ __forceinline__ void zm_block(int gx, int gy, int zc, int nzc, int& x0, int& y0, int& zs, int& ze) {
+    const int t = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    x0 = (t % gx) * ZMarch::X;
+    const int r = t / gx;
+    y0 = (r % gy) * ZMarch::Y;
+    zs = (r / gy) * zc;
+    ze = min(zs + zc, nzc);
+}
+
+// Registers of one thread's share of a B centre plane / p_e node plane.
+struct ZPlane {
+    double b[ZMarch::IC][3];
+    double p[ZMarch::IP];
+};
+
+__device__ __forceinline__ void zm_fetch_B(const FieldGeo& F, const double* __restrict__ B, long ncent, int x0, int y0,
+                                           int k, ZPlane& r) {
+    using Z = ZMarch;
+    k = wrapi(k, F.nzc);
+#pragma unroll
+    for (int it = 0; it < Z::IC; ++it) {
+        const int l = threadIdx.x + 256 * it;
+        r.b[it][0] = r.b[it][1] = r.b[it][2] = 0.0;
+        if (it + 1 < Z::IC || l < Z::CN) {
+            int i = x0 - 1 + l % Z::CX;
+            const int j = wrapi(y0 - 1 + l / Z::CX, F.nyc);
+            if (F.xbc == 1) i = wrapi(i, F.nx);
+            else if (i >= F.nx) i = F.nx - 1;
+            if (i < 0) {
+                r.b[it][0] = F.B0[0]; r.b[it][1] = F.B0[1]; r.b[it][2] = F.B0[2];
+            } else {
+                const long q = i + (long)F.nx * (j + (long)F.nyc * k);
+                r.b[it][0] = B[q]; r.b[it][1] = B[ncent + q]; r.b[it][2] = B[2 * ncent + q];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void zm_fetch_P(const FieldGeo& F, const double* __restrict__ pe, int x0, int y0, int k,
+                                           ZPlane& r) {
+    using Z = ZMarch;
+    k = wrapi(k, F.nzc);
+#pragma unroll
+    for (int it = 0; it < Z::IP; ++it) {
+        const int l = threadIdx.x + 256 * it;
+        r.p[it] = 0.0;
+        if (it + 1 < Z::IP || l < Z::PN) {
+            int i = x0 - 1 + l % Z::PX;
+            const int j = wrapi(y0 - 1 + l / Z::PX, F.nyc);
+            if (F.xbc == 1) i = wrapi(i, F.nx);
+            else i = i < 0 ? 0 : (i > F.nx ? F.nx : i);
+            r.p[it] = pe[i + (long)F.nxn * (j + (long)F.nyc * k)];
+        }
+    }
+}
+
+__device__ __forceinline__ void zm_store_B(const ZPlane& r, double (*sB)[ZMarch::CN]) {
+#pragma unroll
+    for (int it = 0; it < ZMarch::IC; ++it) {
+        const int l = threadIdx.x + 256 * it;
+        if (it + 1 < ZMarch::IC || l < ZMarch::CN) { sB[0][l] = r.b[it][0]; sB[1][l] = r.b[it][1]; sB[2][l] = r.b[it][2]; }
+    }
+}
+
+__device__ __forceinline__ void zm_store_P(const ZPlane& r, double* sP) {
+#pragma unroll
+    for (int it = 0; it < ZMarch::IP; ++it) {
+        const int l = threadIdx.x + 256 * it;
+        if (it + 1 < ZMarch::IP || l < ZMarch::PN) sP[l] = r.p[it];
+    }
+}
+
+// n_e and Gamma at one node, fetched ahead of the LDS phase that uses them.
+struct ZFluid {
+    double ne, G[3];
+    long n;
+    bool ok;
+};
+
+// Node (x0 + lx, y0 + ly, k); nodes past the box are never read, flagged !ok.
+__device__ __forceinline__ void zm_fetch_fluid(const FieldGeo& F, const double* __restrict__ fl, long nnode, int x0,
+                                               int y0, int k, int lx, int ly, ZFluid& f) {
+    int i = x0 + lx;
+    f.ok = F.xbc == 1 || i <= F.nx;
+    f.ne = 1.0; f.G[0] = f.G[1] = f.G[2] = 0.0; f.n = 0;
+    if (!f.ok) return;
+    if (F.xbc == 1) i = wrapi(i, F.nx);
+    f.n = i + (long)F.nxn * (wrapi(y0 + ly, F.nyc) + (long)F.nyc * wrapi(k, F.nzc));
+    f.ne = fl[f.n];
+    f.G[0] = fl[2 * nnode + f.n]; f.G[1] = fl[3 * nnode + f.n]; f.G[2] = fl[4 * nnode + f.n];
+}
+
+// Ohm's law at local node (lx, ly) of the plane whose centre planes below /
+// above sit in sB0 / sB1 and whose p_e planes below / at / above in
+// sP0 / sP1 / sP2.
+__device__ __forceinline__ void zm_ohm(const FieldGeo& F, const double (*sB0)[ZMarch::CN],
+                                       const double (*sB1)[ZMarch::CN], const double* sP0, const double* sP1,
+                                       const double* sP2, const ZFluid& f, int lx, int ly, double e[3], double bb[3]) {
+    using Z = ZMarch;
+    double C[2][2][2][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int l = (lx + a) + Z::CX * (ly + b);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) { C[a][b][0][d] = sB0[d][l]; C[a][b][1][d] = sB1[d][l]; }
+        }
+    const int pc = (lx + 1) + Z::PX * (ly + 1);
+    const double dp[3] = {sP1[pc + 1] - sP1[pc - 1], sP1[pc + Z::PX] - sP1[pc - Z::PX], sP2[pc] - sP0[pc]};
+    ohm_core<3>(F, C, dp, f.ne, f.G, e, bb);
+}
+
+// One SSP-RK3 stage in 3D (see k_stage), marching through z.
+__global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __restrict__ Bin,
+                                                const double* __restrict__ Bn, double* __restrict__ Bout,
+                                                const double* __restrict__ fl, double c0, double c1, double h,
+                                                long nnode, long ncent, int gx, int gy, int zc) {
+    using Z = ZMarch;
+    __shared__ double sB[3][3][Z::CN];
+    __shared__ double sP[3][Z::PN];
+    __shared__ double sE[2][3][Z::NN];
+    int x0, y0, zs, ze;
+    zm_block(gx, gy, zc, F.nzc, x0, y0, zs, ze);
+    const double* pe = fl + nnode;
+    const int t = threadIdx.x, tx = t % Z::X, ty = t / Z::X;
+    const int ci = x0 + tx, cj = y0 + ty;
+    const bool own = ci < F.nx && cj < F.nyc;
+    ZPlane pl;
+    ZFluid fn[Z::IN];
+
+    // E at node plane k into sE[slot], ring positions of its B / p_e planes given
+    auto node_plane = [&](int slot, int b0, int b1, int p0, int p1, int p2) {
+#pragma unroll
+        for (int it = 0; it < Z::IN; ++it) {
+            const int l = t + 256 * it;
+            if (it + 1 < Z::IN || l < Z::NN) {
+                double e[3] = {0, 0, 0}, bb[3];
+                if (fn[it].ok) zm_ohm(F, sB[b0], sB[b1], sP[p0], sP[p1], sP[p2], fn[it], l % Z::NX, l / Z::NX, e, bb);
+                sE[slot][0][l] = e[0]; sE[slot][1][l] = e[1]; sE[slot][2][l] = e[2];
+            }
+        }
+    };
+    auto fetch_fluid = [&](int k) {
+#pragma unroll
+        for (int it = 0; it < Z::IN; ++it) {
+            const int l = t + 256 * it;
+            fn[it].ok = false;
+            if (it + 1 < Z::IN || l < Z::NN) zm_fetch_fluid(F, fl, nnode, x0, y0, k, l % Z::NX, l / Z::NX, fn[it]);
+        }
+    };
+
+    // prologue: B planes zs-1, zs; p_e planes zs-1 .. zs+1; E at node plane zs
+    zm_fetch_B(F, Bin, ncent, x0, y0, zs - 1, pl);
+    zm_fetch_P(F, pe, x0, y0, zs - 1, pl);
+    zm_store_B(pl, sB[0]);
+    zm_store_P(pl, sP[0]);
+    zm_fetch_B(F, Bin, ncent, x0, y0, zs, pl);
+    zm_fetch_P(F, pe, x0, y0, zs, pl);
+    zm_store_B(pl, sB[1]);
+    zm_store_P(pl, sP[1]);
+    zm_fetch_P(F, pe, x0, y0, zs + 1, pl);
+    fetch_fluid(zs);
+    zm_store_P(pl, sP[2]);
+    __syncthreads();
+    node_plane(0, 0, 1, 0, 1, 2);
+    __syncthreads();
+
+    for (int k = zs; k < ze; ++k) {
+        const int r = k - zs;
+        // global loads of the next planes, then into their ring slots
+        zm_fetch_B(F, Bin, ncent, x0, y0, k + 1, pl);
+        zm_fetch_P(F, pe, x0, y0, k + 2, pl);
+        fetch_fluid(k + 1);
+        double bn[3] = {0, 0, 0};
+        const long q = ci + (long)F.nx * (cj + (long)F.nyc * k);
+        if (own && c0 != 0.0) { bn[0] = Bn[q]; bn[1] = Bn[ncent + q]; bn[2] = Bn[2 * ncent + q]; }
+        zm_store_B(pl, sB[(r + 2) % 3]);
+        zm_store_P(pl, sP[r % 3]);
+        __syncthreads();
+        node_plane((r + 1) & 1, (r + 1) % 3, (r + 2) % 3, (r + 1) % 3, (r + 2) % 3, r % 3);
+        __syncthreads();
+        if (own) {
+            const double(*E0)[Z::NN] = sE[r & 1];
+            const double(*E1)[Z::NN] = sE[(r + 1) & 1];
+            double dEx[3] = {0, 0, 0}, dEy[3] = {0, 0, 0}, dEz[3] = {0, 0, 0};
+            auto at = [&](int a, int b) { return (tx + a) + Z::NX * (ty + b); };
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    dEx[d] += (E0[d][at(1, b)] - E0[d][at(0, b)]) + (E1[d][at(1, b)] - E1[d][at(0, b)]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    dEy[d] += (E0[d][at(a, 1)] - E0[d][at(a, 0)]) + (E1[d][at(a, 1)] - E1[d][at(a, 0)]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) dEz[d] += E1[d][at(a, b)] - E0[d][at(a, b)];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                dEx[d] = dEx[d] * 0.25 * F.rdx;
+                dEy[d] = dEy[d] * 0.25 * F.rdx;
+                dEz[d] = dEz[d] * 0.25 * F.rdx;
+            }
+            const double rhs[3] = {-(dEy[2] - dEz[1]), -(dEz[0] - dEx[2]), -(dEx[1] - dEy[0])};
+            const int lc = (tx + 1) + Z::CX * (ty + 1);
+            const double(*Bk)[Z::CN] = sB[(r + 1) % 3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const double sv = Bk[d][lc] + h * rhs[d];
+                Bout[(long)d * ncent + q] = c0 == 0.0 ? c1 * sv : c0 * bn[d] + c1 * sv;
+            }
+        }
+    }
+}
+
+// Final Ohm's law in 3D (see k_ohm), marching through node planes.
+template <typename R>
+__global__ __launch_bounds__(256) void k_ohm3(FieldGeo F, const double* __restrict__ B, const double* __restrict__ fl,
+                                              double* __restrict__ E, R* __restrict__ gather, long nnode, long ncent,
+                                              int gx, int gy, int zc) {
+    using Z = ZMarch;
+    __shared__ double sB[2][3][Z::CN];
+    __shared__ double sP[3][Z::PN];
+    int x0, y0, zs, ze;
+    zm_block(gx, gy, zc, F.nzc, x0, y0, zs, ze);
+    const double* pe = fl + nnode;
+    const int t = threadIdx.x, tx = t % Z::X, ty = t / Z::X;
+    const bool own = x0 + tx < F.nxn && y0 + ty < F.nyc;
+    ZPlane pl;
+    zm_fetch_B(F, B, ncent, x0, y0, zs - 1, pl);
+    zm_fetch_P(F, pe, x0, y0, zs - 1, pl);
+    zm_store_B(pl, sB[0]);
+    zm_store_P(pl, sP[0]);
+    zm_fetch_P(F, pe, x0, y0, zs, pl);
+    zm_store_P(pl, sP[1]);
+    for (int k = zs; k < ze; ++k) {
+        const int r = k - zs;
+        zm_fetch_B(F, B, ncent, x0, y0, k, pl);
+        zm_fetch_P(F, pe, x0, y0, k + 1, pl);
+        ZFluid f;
+        f.ok = false;
+        if (own) zm_fetch_fluid(F, fl, nnode, x0, y0, k, tx, ty, f);
+        zm_store_B(pl, sB[(r + 1) & 1]);
+        zm_store_P(pl, sP[(r + 2) % 3]);
+        __syncthreads();
+        if (own) {
+            double e[3], bb[3];
+            zm_ohm(F, sB[r & 1], sB[(r + 1) & 1], sP[r % 3], sP[(r + 1) % 3], sP[(r + 2) % 3], f, tx, ty, e, bb);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) E[(long)d * nnode + f.n] = e[d];
+            R* g8 = gather + 8 * f.n;
+            g8[0] = (R)e[0]; g8[1] = (R)e[1]; g8[2] = (R)e[2]; g8[3] = (R)0;
+            g8[4] = (R)bb[0]; g8[5] = (R)bb[1]; g8[6] = (R)bb[2]; g8[7] = (R)0;
+        }
+        __syncthreads();
     }
 }
 
