@@ -300,11 +300,11 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
             if (dep) allow_lds(k_push<R, D, S, true>, lds_push);
             else allow_lds(k_push<R, D, S, false>, lds_push);
             if (dep)
-                k_push<R, D, S, true><<<(unsigned)h->L.ntiles, 256, lds_push, s>>>(
+                k_push<R, D, S, true><<<(unsigned)h->L.ntiles, PUSH_THREADS, lds_push, s>>>(
                     G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, static_cast<const R*>(f->gather),
                     mom, h->xl[k], h->ctr, policy_of(h, k), k);
             else
-                k_push<R, D, S, false><<<(unsigned)h->L.ntiles, 256, lds_push, s>>>(
+                k_push<R, D, S, false><<<(unsigned)h->L.ntiles, PUSH_THREADS, lds_push, s>>>(
                     G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, static_cast<const R*>(f->gather),
                     mom, h->xl[k], h->ctr, policy_of(h, k), k);
         }

@@ -5,6 +5,13 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#ifndef DEP_HALO
+#define DEP_HALO 1
+#endif
+#ifndef PUSH_THREADS
+#define PUSH_THREADS 512
+#endif
+
 namespace fsk {
 
 // Random-number streams: the key of every Philox draw is (seed, stream).
@@ -34,8 +41,9 @@ template <> struct Stencil<2> { static constexpr int LO = 1, HI = 2, N = 3; };
 template <int D, int S> struct Extent {
     static constexpr int TX = TileShape<D>::X, TY = TileShape<D>::Y, TZ = TileShape<D>::Z;
     static constexpr int W = Stencil<S>::LO + Stencil<S>::HI;
+    static constexpr int H = DEP_HALO;   // halo cells of the deposit box on each side
     static constexpr int GX = TX + W, GY = D >= 2 ? TY + W : 1, GZ = D >= 3 ? TZ + W : 1;
-    static constexpr int DX = TX + 2 + W, DY = D >= 2 ? TY + 2 + W : 1, DZ = D >= 3 ? TZ + 2 + W : 1;
+    static constexpr int DX = TX + 2 * H + W, DY = D >= 2 ? TY + 2 * H + W : 1, DZ = D >= 3 ? TZ + 2 * H + W : 1;
     static constexpr int GN = GX * GY * GZ, DN = DX * DY * DZ;
 };
 

@@ -251,6 +251,18 @@ __device__ __forceinline__ void ohm_tile(const FieldGeo& F, const double (*sB)[F
     ohm_core<D>(F, C, dp, fl[n], G, e, bb);
 }
 
+// One node of the gather grid (Ex Ey Ez 0 Bbarx Bbary Bbarz 0) in the particle
+// precision, as two 4-vector stores.
+template <typename R> struct Vec4;
+template <> struct Vec4<float> { using T = float4; };
+template <> struct Vec4<double> { using T = double4; };
+template <typename R> __device__ __forceinline__ void store_gather(R* g8, const double e[3], const double bb[3]) {
+    using V = typename Vec4<R>::T;
+    V* v = reinterpret_cast<V*>(g8);
+    v[0] = V{(R)e[0], (R)e[1], (R)e[2], (R)0};
+    v[1] = V{(R)bb[0], (R)bb[1], (R)bb[2], (R)0};
+}
+
 // Ohm's law at every node of the block, writing E (FP64) and E, Bbar in the
 // particle precision into the gather grid.  Grid: nodes in x, centres in y/z.
 template <typename R, int D>
@@ -275,9 +287,7 @@ __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restric
     ohm_tile<D>(F, sB, sP, fl, nnode, n, tx, ty, tz, e, bb);
 #pragma unroll
     for (int d = 0; d < 3; ++d) E[(long)d * nnode + n] = e[d];
-    R* g8 = gather + 8 * n;
-    g8[0] = (R)e[0]; g8[1] = (R)e[1]; g8[2] = (R)e[2]; g8[3] = (R)0;
-    g8[4] = (R)bb[0]; g8[5] = (R)bb[1]; g8[6] = (R)bb[2]; g8[7] = (R)0;
+    store_gather(gather + 8 * n, e, bb);
 }
 
 // One SSP-RK3 stage, fused: E = Ohm(Bin) at the block's nodes (its centres
@@ -493,7 +503,7 @@ __global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __rest
                                                 const double* __restrict__ fl, double c0, double c1, double h,
                                                 long nnode, long ncent, int gx, int gy, int zc) {
     using Z = ZMarch;
-    __shared__ double sB[3][3][Z::CN];
+    __shared__ double sB[2][3][Z::CN];
     __shared__ double sP[3][Z::PN];
     __shared__ double sE[2][3][Z::NN];
     int x0, y0, zs, ze;
@@ -540,21 +550,26 @@ __global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __rest
     zm_store_P(pl, sP[2]);
     __syncthreads();
     node_plane(0, 0, 1, 0, 1, 2);
+    const int lc = (tx + 1) + Z::CX * (ty + 1);
+    // this thread's own centre of plane k, read from the ring before its slot is reused
+    double bk[3] = {sB[1][0][lc], sB[1][1][lc], sB[1][2][lc]};
     __syncthreads();
 
     for (int k = zs; k < ze; ++k) {
         const int r = k - zs;
-        // global loads of the next planes, then into their ring slots
+        // global loads of the next planes, then into their ring slots: B plane
+        // k+1 replaces k-1, p_e plane k+2 replaces k-1
         zm_fetch_B(F, Bin, ncent, x0, y0, k + 1, pl);
         zm_fetch_P(F, pe, x0, y0, k + 2, pl);
         fetch_fluid(k + 1);
         double bn[3] = {0, 0, 0};
         const long q = ci + (long)F.nx * (cj + (long)F.nyc * k);
         if (own && c0 != 0.0) { bn[0] = Bn[q]; bn[1] = Bn[ncent + q]; bn[2] = Bn[2 * ncent + q]; }
-        zm_store_B(pl, sB[(r + 2) % 3]);
+        zm_store_B(pl, sB[r & 1]);
         zm_store_P(pl, sP[r % 3]);
         __syncthreads();
-        node_plane((r + 1) & 1, (r + 1) % 3, (r + 2) % 3, (r + 1) % 3, (r + 2) % 3, r % 3);
+        node_plane((r + 1) & 1, (r + 1) & 1, r & 1, (r + 1) % 3, (r + 2) % 3, r % 3);
+        const double bk1[3] = {sB[r & 1][0][lc], sB[r & 1][1][lc], sB[r & 1][2][lc]};
         __syncthreads();
         if (own) {
             const double(*E0)[Z::NN] = sE[r & 1];
@@ -584,14 +599,14 @@ __global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __rest
                 dEz[d] = dEz[d] * 0.25 * F.rdx;
             }
             const double rhs[3] = {-(dEy[2] - dEz[1]), -(dEz[0] - dEx[2]), -(dEx[1] - dEy[0])};
-            const int lc = (tx + 1) + Z::CX * (ty + 1);
-            const double(*Bk)[Z::CN] = sB[(r + 1) % 3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const double sv = Bk[d][lc] + h * rhs[d];
+                const double sv = bk[d] + h * rhs[d];
                 Bout[(long)d * ncent + q] = c0 == 0.0 ? c1 * sv : c0 * bn[d] + c1 * sv;
             }
         }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) bk[d] = bk1[d];
     }
 }
 
@@ -630,9 +645,7 @@ __global__ __launch_bounds__(256) void k_ohm3(FieldGeo F, const double* __restri
             zm_ohm(F, sB[r & 1], sB[(r + 1) & 1], sP[r % 3], sP[(r + 1) % 3], sP[(r + 2) % 3], f, tx, ty, e, bb);
 #pragma unroll
             for (int d = 0; d < 3; ++d) E[(long)d * nnode + f.n] = e[d];
-            R* g8 = gather + 8 * f.n;
-            g8[0] = (R)e[0]; g8[1] = (R)e[1]; g8[2] = (R)e[2]; g8[3] = (R)0;
-            g8[4] = (R)bb[0]; g8[5] = (R)bb[1]; g8[6] = (R)bb[2]; g8[7] = (R)0;
+            store_gather(gather + 8 * f.n, e, bb);
         }
         __syncthreads();
     }
@@ -671,6 +684,11 @@ __global__ void k_init_B(FieldGeo F, int n_modes, const double* __restrict__ amp
 
 // ppc thermal ions per cell, ids cell-major; each lands in a fixed slot of
 // its tile (local cell index * ppc + q), so no atomics are needed.
+__device__ __forceinline__ long gcd_l(long a, long b) {
+    while (b != 0) { long t = a % b; a = b; b = t; }
+    return a;
+}
+
 template <typename R, int D>
 __global__ __launch_bounds__(256) void k_init_particles(Geo G, PBuf<R> out, int64_t cap, int ppc, long np) {
     using T = TileShape<D>;
@@ -690,7 +708,15 @@ __global__ __launch_bounds__(256) void k_init_particles(Geo G, PBuf<R> out, int6
     int tx = tile % G.ntx, ty = (tile / G.ntx) % G.nty, tz = tile / (G.ntx * G.nty);
     int ex = min(T::X, G.nx - tx * T::X), ey = min(T::Y, G.nyc - ty * T::Y);
     int lc = (cx - tx * T::X) + ex * ((cy - ty * T::Y) + ey * (cz - tz * T::Z));
-    long dst = (long)tile * cap + (long)lc * ppc + q;
+    // Slot within the tile bin: a stride permutation of (cell, q) order.  The
+    // order of ions in a bin is arbitrary; a scattered one keeps the lanes of
+    // a wave in different cells, as the ion order becomes after a few hundred
+    // steps of flow anyway, so that they rarely hit one LDS address together.
+    const int ez = D >= 3 ? min(T::Z, G.nzc - tz * T::Z) : 1;
+    const long nt = (long)ex * (D >= 2 ? ey : 1) * ez * ppc;
+    long m = ((long)(0.6180339887 * (double)nt)) | 1;
+    while (gcd_l(m, nt) != 1) m += 2;
+    long dst = (long)tile * cap + ((long)(lc * ppc + q) * m) % nt;
     out.cell[dst] = pack_cell(cx, cy, cz, G);
     out.off[0][dst] = to_offset<R>(U[0]);
     if constexpr (D >= 2) out.off[1][dst] = to_offset<R>(U[1]);
