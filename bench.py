@@ -49,6 +49,65 @@ def traffic_from_profiles(kernel_hash):
     return d.get("bytes_per_launch")
 
 
+def copy_calibration():
+    """A plain device copy of 1 GiB, three times: what FETCH_SIZE and
+    WRITE_SIZE read for a kernel of known traffic."""
+    import torch
+    n = 256 * 1024 * 1024
+    a = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied 3 x 1 GiB", flush=True)
+
+
+def _counter(dirname, counter, name_part):
+    """Per-dispatch values of one counter for kernels whose name contains
+    `name_part`, from a rocprofv3 --output-format csv directory."""
+    import csv
+    import glob
+    out = {}
+    for f in glob.glob(os.path.join(dirname, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
+                out[int(r["Dispatch_Id"])] = out.get(int(r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+    return [out[k] for k in sorted(out)]
+
+
+def write_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, command):
+    """HBM bytes per launch of the fused 3D push kernel from two counter runs
+    (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the same
+    counter reads for the 1 GiB copy; written with the hash of the kernel
+    source it was measured on."""
+    kern = "k_push<float, 3, 1, true>"
+    f = _counter(fetch_dir, "FETCH_SIZE", kern)
+    w = _counter(write_dir, "WRITE_SIZE", kern)
+    cf = _counter(copy_fetch_dir, "FETCH_SIZE", "copy")
+    cw = _counter(copy_write_dir, "WRITE_SIZE", "copy")
+    if not (f and w and cf and cw):
+        raise SystemExit("missing counter values")
+    gib = float(1 << 30)
+    kf = gib / (max(cf) * 1024.0)   # bytes per counted byte, from the copy's reads
+    kw = gib / (max(cw) * 1024.0)
+    fetch = sum(f) / len(f) * 1024.0 * kf
+    write = sum(w) / len(w) * 1024.0 * kw
+    d = {"kernel": kern, "workload": "cfg4 3D box 1024x192x192, 8 ppc",
+         "dispatches": [len(f), len(w)],
+         "fetch_kib_per_dispatch": sum(f) / len(f), "write_kib_per_dispatch": sum(w) / len(w),
+         "copy_fetch_kib_per_gib": max(cf), "copy_write_kib_per_gib": max(cw),
+         "fetch_scale": kf, "write_scale": kw,
+         "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+         "bytes_per_launch": fetch + write,
+         "kernel_source_sha256": kernel_source_hash(), "command": command}
+    path = os.path.join(ROOT, "profiles", "push3d_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1)
+    print(json.dumps(d))
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -86,7 +145,18 @@ def main():
     ap.add_argument("--workload", default="cfg4")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 1 GiB copy used to scale the HBM byte counters")
+    ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write profiles/push3d_traffic.json from four rocprofv3 counter directories")
+    ap.add_argument("--traffic-command", default="", help="command line recorded with --write-traffic")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return 0
+    if args.write_traffic:
+        write_traffic(*args.write_traffic, command=args.traffic_command)
+        return 0
     if args.gpus != 1:
         msg = (f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
                "(the multi-GPU x-slab decomposition is design only)")
