@@ -81,6 +81,21 @@ void     ora_philox(const uint64_t ctr[4], uint64_t k0, uint64_t k1, uint64_t ou
 int      ora_inject_counts(const ora_cfg* cfg, int64_t step, int64_t* out2);
 int      ora_record(ora_sim* s, int32_t on);
 
+/* Reverse mode (fsoracle_adj.c): loss = sum over centres i >= nx/2 of
+ * By^2 + Bz^2 after nsteps continuous-deposit steps, and its gradient
+ * grad[0] = d/du_sh, grad[1] = d/dalpha_cr, grad[1+m] = d/dA_m (m = 1..n_modes),
+ * with every discrete decision of the forward run held fixed. */
+int      ora_adjoint(const ora_cfg* cfg, const double* amps, int64_t nsteps, double* loss, double* grad);
+/* Single transposes, for finite-difference pins. */
+void     ora_adj_boris(const double v[3], const double E[3], const double B[3], double dt, const double lo[3],
+                       double out[3], double lv[3], double lE[3], double lB[3]);
+void     ora_adj_kick(const ora_cfg* cfg, int64_t step, uint64_t id, const double v[3], double delta, double u2,
+                      double lxo, const double lvo[3], double out4[4], double lin5[5]);
+void     ora_adj_ohm(const ora_cfg* cfg, const double* B, const double* fn, const double* fg, const double* lE,
+                     double* E, double* lB, double* lfn, double* lfg);
+void     ora_adj_rk3(const ora_cfg* cfg, const double* B, const double* fn, const double* fg, double* Bout,
+                     double* lB, double* lfn, double* lfg);
+
 #ifdef __cplusplus
 }
 #endif

@@ -121,9 +121,13 @@ def lib():
         L.ora_philox.argtypes = [vp, C.c_uint64, C.c_uint64, vp]
         L.ora_inject_counts.argtypes = [C.POINTER(OraCfg), i64, vp]
         L.ora_record.argtypes = [vp, i32]
-        if hasattr(L, "ora_adjoint"):
-            L.ora_adjoint.argtypes = [C.POINTER(OraCfg), vp, i32, i32, vp, vp, vp]
-            L.ora_replay_loss.argtypes = [C.POINTER(OraCfg), vp, i32, vp, vp, vp]
+        pc = C.POINTER(OraCfg)
+        L.ora_adjoint.restype = C.c_int
+        L.ora_adjoint.argtypes = [pc, vp, i64, vp, vp]
+        L.ora_adj_boris.argtypes = [vp, vp, vp, dp, vp, vp, vp, vp, vp]
+        L.ora_adj_kick.argtypes = [pc, i64, C.c_uint64, vp, dp, dp, dp, vp, vp, vp]
+        L.ora_adj_ohm.argtypes = [pc, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.ora_adj_rk3.argtypes = [pc, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -289,3 +293,78 @@ class Oracle:
 
     def record(self, on: bool = True):
         lib().ora_record(self.h, 1 if on else 0)
+
+
+# --- reverse mode (fsoracle_adj.c) ------------------------------------------
+def _amps(p: dict, amps):
+    if amps is None:
+        return np.full(int(p["n_modes"]), float(p["mode_amp"]))
+    return np.ascontiguousarray(amps, dtype=np.float64)
+
+
+def adjoint(p: dict, nsteps: int, amps=None):
+    """Loss (precursor magnetic energy after `nsteps` continuous-deposit
+    steps) and its gradient [d/du_sh, d/dalpha_cr, d/dA_1 .. d/dA_M]."""
+    cfg = make_cfg(p, "continuous")
+    a = _amps(p, amps)
+    loss = np.zeros(1)
+    grad = np.zeros(2 + int(p["n_modes"]))
+    rc = lib().ora_adjoint(C.byref(cfg), _p(a) if a.size else None, int(nsteps), _p(loss), _p(grad))
+    if rc != 0:
+        raise ValueError("oracle adjoint rejected the configuration")
+    return float(loss[0]), grad
+
+
+def forward_loss(p: dict, nsteps: int, amps=None):
+    """The same loss from a plain forward run (continuous deposit), with the
+    per-step event counts so a finite-difference caller can check that no
+    discrete decision changed."""
+    o = Oracle(p, "continuous")
+    o.init(_amps(p, amps) if int(p["n_modes"]) else None)
+    events = []
+    for _ in range(nsteps):
+        st = o.step()
+        events.append((st["incident"], st["reflected"], st["transmitted"], st["open_removed"],
+                       st["escaped"], st["injected_th"], st["injected_cr"], o.count(0), o.count(1)))
+    return o.loss(), events
+
+
+def adj_boris(v, E, B, dt, lam_out):
+    v, E, B, lo = (np.ascontiguousarray(x, dtype=np.float64) for x in (v, E, B, lam_out))
+    out, lv, lE, lB = (np.zeros(3) for _ in range(4))
+    lib().ora_adj_boris(_p(v), _p(E), _p(B), float(dt), _p(lo), _p(out), _p(lv), _p(lE), _p(lB))
+    return out, lv, lE, lB
+
+
+def adj_kick(p: dict, step: int, pid: int, v, delta: float, u2: float, lam_x: float, lam_v):
+    """FS kick of a reflected particle and its transpose: returns
+    (x', v'), and the adjoints of (x_pre, v_pre, u2)."""
+    cfg = make_cfg(p)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    lv = np.ascontiguousarray(lam_v, dtype=np.float64)
+    out, lin = np.zeros(4), np.zeros(5)
+    lib().ora_adj_kick(C.byref(cfg), int(step), int(pid), _p(v), float(delta), float(u2), float(lam_x),
+                       _p(lv), _p(out), _p(lin))
+    return out, lin
+
+
+def adj_ohm(p: dict, B, fn, fg, lam_E):
+    """E = Ohm(B, fn, fg) at every node and the transpose applied to lam_E."""
+    cfg = make_cfg(p, "continuous")
+    B, fn, fg, lE = (np.ascontiguousarray(x, dtype=np.float64) for x in (B, fn, fg, lam_E))
+    E = np.zeros_like(lE)
+    lB, lfn, lfg = np.zeros_like(B), np.zeros_like(fn), np.zeros_like(fg)
+    lib().ora_adj_ohm(C.byref(cfg), _p(B), _p(fn), _p(fg), _p(lE), _p(E), _p(lB), _p(lfn), _p(lfg))
+    return E, lB, lfn, lfg
+
+
+def adj_rk3(p: dict, B, fn, fg, lam_out):
+    """One SSP-RK3 field update and its transpose applied to lam_out."""
+    cfg = make_cfg(p, "continuous")
+    B, fn, fg = (np.ascontiguousarray(x, dtype=np.float64) for x in (B, fn, fg))
+    lB = np.array(lam_out, dtype=np.float64)
+    Bo = np.zeros_like(B)
+    lfn, lfg = np.zeros_like(fn), np.zeros_like(fg)
+    lib().ora_adj_rk3(C.byref(cfg), _p(B), _p(fn), _p(fg), _p(Bo), _p(lB), _p(lfn), _p(lfg))
+    return Bo, lB, lfn, lfg
+
