@@ -83,7 +83,11 @@ typedef struct fs_config {
     int32_t dim, nx, ny, nz;
     int32_t ppc, ppc_cr, shape, precision;  /* shape 1 = CIC, 2 = TSC; precision 32 or 64 */
     int32_t wall_th, wall_cr, xbc, n_sub;
-    int32_t n_modes, inject, pad0, pad1;
+    int32_t n_modes, inject;
+    int32_t deposit_mode;   /* 0: int64 fixed point (bit-reproducible); 1: real
+                               weights, FP64 sums (the differentiable variant the
+                               adjoint needs; moments then hold doubles) */
+    int32_t pad1;
 } fs_config;
 
 /* Sizes the caller must allocate, reported by fs_layout(). */
@@ -206,6 +210,62 @@ int64_t fs_next_id(const fs_handle* h);
  * By^2 + Bz^2.  prof (optional, device, nx) = sum over y, z of By^2 + Bz^2. */
 int fs_diagnostics(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out8,
                    double* prof, hipStream_t s);
+
+/* ---------------------------------------------------------------------
+ * Reverse mode.  The derivative is that of the continuous-deposit step
+ * (deposit_mode 1) with every discrete decision of the forward run held
+ * fixed: cells, FS reflections (the eq. 1 decision of Sec. 2), removals,
+ * injection counts, the density floor.  The FS kick after a reflection is
+ * differentiated, including through u2 = u_sh / r.  Gradients are those of
+ * a scalar loss of the final state with respect to u_sh, alpha_cr (the CR
+ * macro-weight multiplier) and the initial Fourier amplitudes.
+ * --------------------------------------------------------------------- */
+
+/* What a recorded step writes.  refl (device, nid bytes, indexed by
+ * particle id) is cleared by the call and set to 1 for every ion the FS wall
+ * reflects during the step; id0 receives the first id the step can inject
+ * (the injected ions are id0, id0 + 1, ..., thermal first).  nid must exceed
+ * every id the run will hand out. */
+typedef struct fs_record {
+    uint8_t* refl;
+    int64_t  nid;
+    int64_t  id0;
+} fs_record;
+
+/* Adjoint state (device arrays owned by the caller).  Particle adjoints are
+ * in the particle precision and indexed by particle id: x[d] (d < dim; dL
+ * per cell of position) and v[3], nid entries each, both species sharing the
+ * id space; an id not alive at the step holds zero.  Grid adjoints are FP64
+ * planar: lB (3 x ncent) = dL/dB at the centres, lE (6 x nnode) = dL/d(Ex,
+ * Ey, Ez, Bbarx, Bbary, Bbarz) of the gather grid. */
+typedef struct fs_adjoint {
+    void*   x[3];
+    void*   v[3];
+    int64_t nid;
+    double* lB;
+    double* lE;
+} fs_adjoint;
+
+/* One full step (deposit_mode 1 only) that also fills *rec.  Same contract
+ * as fs_step with flags = FS_ALL. */
+int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec,
+                   fs_step_stats* st, hipStream_t s);
+
+/* Reverse of step `step` (n -> n+1, run by fs_step_record with record
+ * *rec).  sp_n / f_n: particles (buf[cur], tile_count[cur]) and fields (B,
+ * gather grid) before the step; sp_n1 / f_n1: particles and B after it.
+ * *lam holds on entry the adjoints after the step (particles, lB, lE of
+ * B^{n+1} and E^{n+1}) and on exit those before it (B^n, E^n).  grads
+ * (device, 2 + n_modes doubles) accumulates dL/du_sh and dL/dalpha_cr. */
+int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n, const fs_particles* sp_n1,
+                    const fs_fields* f_n1, const fs_record* rec, int64_t step, fs_adjoint* lam, double* grads,
+                    hipStream_t s);
+
+/* Reverse of fs_init_plasma: E^0 = Ohm(B^0, moments of the initial load),
+ * the initial velocities (v_x = u_sh + sigma n) and the Fourier modes of
+ * B^0.  Adds to dL/du_sh, dL/dalpha_cr and grads[1 + m] = dL/dA_m. */
+int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, fs_adjoint* lam, double* grads,
+                    hipStream_t s);
 
 /* Phase timing with HIP events recorded on the caller's stream (benchmark
  * support).  While enabled, every fs_step records an event pair around each

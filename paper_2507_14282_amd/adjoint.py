@@ -1,0 +1,203 @@
+"""Reverse mode of the faux-shock step on the GPU, with checkpointing.
+
+The loss is the precursor magnetic energy after N steps,
+L = sum over cell centres with i >= nx/2 of (B_y^2 + B_z^2), and the
+gradient is taken with respect to the upstream flow speed u_sh, the CR
+macro-weight multiplier alpha_cr and the amplitudes of the seeded Fourier
+modes of the initial field (the paper's Sec. 2 set-up: the flow speed sets
+u2 = u_sh / r at the FS wall; the CR current drives the Bell instability that
+fills the precursor).  The derivative is that of the continuous-deposit step
+with every discrete decision of the forward run held fixed (pathwise, common
+random numbers).
+
+Everything numeric runs in the library (``fs_step_record``,
+``fs_adjoint_step``, ``fs_adjoint_init``); this module owns the buffers and
+the schedule: a forward pass that keeps a checkpoint every K steps, and a
+reverse pass that re-runs each K-step segment from its checkpoint with
+recording and walks it backwards.  Particle adjoints are indexed by particle
+id, so a re-run segment may place ions in other bin slots than the first
+run did.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import fshybrid as F
+
+
+class _State:
+    """A saved particle/field state: the live buffer and tile counts of each
+    species, B, E, the gather grid and the id counter."""
+
+    def __init__(self, sim: F.Simulation, nsp: int):
+        self.buf, self.cnt, self.count = [], [], []
+        for k in range(nsp):
+            cur = int(sim.sp[k].cur)
+            self.buf.append(sim.bufs[k][cur].clone())
+            self.cnt.append(sim.cnts[k][cur].clone())
+            self.count.append(sim.counts[k].clone())
+        self.B = sim.B.clone()
+        self.E = sim.E.clone()
+        self.gather = sim.gather.clone()
+        self.next_id = sim.next_id
+
+    def restore(self, sim: F.Simulation):
+        for k in range(len(self.buf)):
+            cur = int(sim.sp[k].cur)
+            sim.bufs[k][cur].copy_(self.buf[k])
+            sim.cnts[k][cur].copy_(self.cnt[k])
+            sim.counts[k].copy_(self.count[k])
+        sim.B.copy_(self.B)
+        sim.E.copy_(self.E)
+        sim.gather.copy_(self.gather)
+        sim.set_clock(self.next_id)
+
+    def particles(self, sim: F.Simulation):
+        """fs_particles structs pointing at the saved buffers."""
+        sp = (F.FsParticles * 2)()
+        for k in range(2):
+            kk = min(k, len(self.buf) - 1)
+            P = sp[k]
+            P.buf[0] = P.buf[1] = self.buf[kk].data_ptr()
+            P.tile_count[0] = P.tile_count[1] = self.cnt[kk].data_ptr()
+            P.count = self.count[kk].data_ptr()
+            P.capacity = int(sim.L.capacity[k])
+            P.tile_cap = int(sim.L.tile_cap[k])
+            P.cur = 0
+            P.species = k
+        return sp
+
+    def fields(self, sim: F.Simulation) -> F.FsFields:
+        f = F.FsFields()
+        f.B, f.E, f.gather = self.B.data_ptr(), self.E.data_ptr(), self.gather.data_ptr()
+        f.mom[0], f.mom[1] = sim.mom[0].data_ptr(), sim.mom[1].data_ptr()
+        return f
+
+
+class AdjointRun:
+    """Forward and reverse passes of N steps of one configuration.
+
+    p: parameter dict (the deposit is forced to the continuous mode);
+    nsteps: N; K: checkpoint interval.
+    """
+
+    def __init__(self, p: dict, nsteps: int, K: int = 20, device: str | torch.device = "cuda:0"):
+        self.p = dict(p, deposit_mode="continuous")
+        self.nsteps = int(nsteps)
+        self.K = max(1, int(K))
+        self.device = torch.device(device)
+        self.sim = None
+        self.checkpoints = {}
+
+    # --- forward ----------------------------------------------------------
+    def forward(self, u_sh: float, alpha_cr: float, amps) -> float:
+        p = dict(self.p, u_sh=float(u_sh), alpha_cr=float(alpha_cr))
+        self.p_run = p
+        sim = F.Simulation(p, self.device)
+        self.sim = sim
+        self.nsp = 2 if sim.has_cr else 1
+        a = None
+        if int(p["n_modes"]) > 0:
+            a = torch.as_tensor(np.asarray(amps, dtype=np.float64), device=self.device)
+        sim.init_plasma(a)
+        self.checkpoints = {}
+        for n in range(self.nsteps):
+            if n % self.K == 0:
+                self.checkpoints[n] = _State(sim, self.nsp)
+            sim.step(n, stats=False)
+        self.nid = sim.next_id
+        return float(self.loss_value())
+
+    def loss_value(self) -> torch.Tensor:
+        nx = int(self.p["nx"])
+        B = self.sim.B.view(3, -1, nx)
+        return (B[1, :, nx // 2:] ** 2 + B[2, :, nx // 2:] ** 2).sum()
+
+    # --- reverse ----------------------------------------------------------
+    def _alloc_lambda(self):
+        sim = self.sim
+        dim = int(self.p["dim"])
+        nid = max(self.nid, 1)
+        lam = F.FsAdjoint()
+        self._lam_keep = []
+        for d in range(3):
+            vv = torch.zeros(nid, dtype=sim.real, device=self.device)
+            lam.v[d] = vv.data_ptr()
+            self._lam_keep.append(vv)
+            if d < dim:
+                xv = torch.zeros(nid, dtype=sim.real, device=self.device)
+                lam.x[d] = xv.data_ptr()
+                self._lam_keep.append(xv)
+            else:
+                lam.x[d] = None
+        lam.nid = nid
+        self.lB = torch.zeros(3, int(sim.L.ncent), dtype=torch.float64, device=self.device)
+        self.lE = torch.zeros(6, int(sim.L.nnode), dtype=torch.float64, device=self.device)
+        lam.lB, lam.lE = self.lB.data_ptr(), self.lE.data_ptr()
+        self.lam = lam
+
+    def backward(self) -> np.ndarray:
+        """Gradient [dL/du_sh, dL/dalpha_cr, dL/dA_1 .. dL/dA_M] of the last
+        forward pass."""
+        sim = self.sim
+        lib, stream = sim.lib, sim.stream
+        nx = int(self.p["nx"])
+        self._alloc_lambda()
+        B = sim.B.view(3, -1, nx)
+        lBv = self.lB.view(3, -1, nx)
+        lBv[1, :, nx // 2:] = 2.0 * B[1, :, nx // 2:]
+        lBv[2, :, nx // 2:] = 2.0 * B[2, :, nx // 2:]
+        grads = torch.zeros(2 + int(self.p["n_modes"]), dtype=torch.float64, device=self.device)
+        gptr = C.c_void_p(grads.data_ptr())
+        refl = [torch.zeros(self.lam.nid, dtype=torch.uint8, device=self.device) for _ in range(self.K)]
+        for s0 in sorted(self.checkpoints, reverse=True):
+            s1 = min(s0 + self.K, self.nsteps)
+            self.checkpoints[s0].restore(sim)
+            tape, recs = [], []
+            for j, n in enumerate(range(s0, s1)):
+                tape.append(_State(sim, self.nsp))
+                rec = F.FsRecord()
+                rec.refl, rec.nid = refl[j].data_ptr(), self.lam.nid
+                sim.step_record(n, rec)
+                recs.append(rec)
+            tape.append(_State(sim, self.nsp))
+            for j in range(s1 - s0 - 1, -1, -1):
+                a, b = tape[j], tape[j + 1]
+                f_n, f_n1 = a.fields(sim), b.fields(sim)
+                rc = lib.fs_adjoint_step(sim.h, a.particles(sim), C.byref(f_n), b.particles(sim), C.byref(f_n1),
+                                         C.byref(recs[j]), s0 + j, C.byref(self.lam), gptr, stream)
+                sim._check(rc)
+            if s0 == 0:
+                a = tape[0]
+                f0 = a.fields(sim)
+                rc = lib.fs_adjoint_init(sim.h, a.particles(sim), C.byref(f0), C.byref(self.lam), gptr, stream)
+                sim._check(rc)
+            del tape, recs
+        torch.cuda.synchronize(self.device)
+        return grads.cpu().numpy()
+
+
+class PrecursorEnergy(torch.autograd.Function):
+    """L(u_sh, alpha_cr, amps) = precursor magnetic energy after N steps;
+    ``backward`` runs the checkpointed reverse pass of the library."""
+
+    @staticmethod
+    def forward(ctx, u_sh, alpha_cr, amps, run: AdjointRun):
+        loss = run.forward(float(u_sh), float(alpha_cr), amps.detach().cpu().numpy())
+        ctx.run = run
+        ctx.dtype = amps.dtype
+        return torch.tensor(loss, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, g):
+        gr = torch.as_tensor(ctx.run.backward(), dtype=torch.float64) * g
+        return gr[0], gr[1], gr[2:].to(ctx.dtype), None
+
+
+def precursor_energy(u_sh, alpha_cr, amps, run: AdjointRun):
+    """Differentiable entry point: ``precursor_energy(u, a, A, run).backward()``."""
+    return PrecursorEnergy.apply(u_sh, alpha_cr, amps, run)

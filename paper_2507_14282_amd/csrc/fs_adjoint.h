@@ -1,0 +1,659 @@
+// fs_adjoint.h -- reverse-mode (adjoint) kernels of the faux-shock hybrid step.
+//
+// The derivative is that of the continuous-deposit step (real shape weights,
+// FP64 moments) with every discrete decision of the forward run held fixed:
+// the cell of each ion, FS reflections (the eq. 1 decision), removals,
+// injection counts and the density floor.  The FS kick that follows a
+// reflection is differentiated, including its dependence on u2 = u_sh / r.
+//
+// One reverse step n+1 -> n, given the adjoints lam(B^{n+1}), lam(E^{n+1}),
+// lam(Bbar^{n+1}) and the particle adjoints lam(x^{n+1}), lam(v^{n+1/2}):
+//   final Ohm^T -> SSP-RK3^T (stages recomputed) -> fluid^T -> deposit^T ->
+//   injection^T -> (FS kick^T) -> move^T -> Boris^T -> gather^T.
+// Particle adjoints are stored in the particle precision and indexed by
+// particle id (ids are unique and never reused, so the adjoint of an ion
+// keeps its place whatever bin slot the ion occupies; an ion removed by a
+// step simply has zero adjoint from then on).  Grid adjoints are FP64.  The
+// push pass accumulates per tile in LDS (FP64 atomics) and flushes once per
+// node.
+#pragma once
+#include "fs_field.h"
+
+namespace fsk {
+
+// Planar particle adjoints indexed by particle id: x[d] (d < D, per cell
+// of position) and v[3], nid entries each.
+template <typename R> struct PLam {
+    R* x[3];
+    R* v[3];
+    int64_t nid;
+};
+
+// Real shape weights in FP64 and their derivatives d/d(offset).
+template <int S> __device__ __forceinline__ void weights_dw(double o, int& rel, double w[3], double dw[3]) {
+    if constexpr (S == 1) {
+        rel = 0; w[0] = 1.0 - o; w[1] = o; w[2] = 0.0;
+        dw[0] = -1.0; dw[1] = 1.0; dw[2] = 0.0;
+    } else {
+        double xi = o;
+        rel = -1;
+        if (o >= 0.5) { xi = o - 1.0; rel = 0; }
+        w[0] = 0.5 * (0.5 - xi) * (0.5 - xi);
+        w[1] = 0.75 - xi * xi;
+        w[2] = 0.5 * (0.5 + xi) * (0.5 + xi);
+        dw[0] = -(0.5 - xi); dw[1] = -2.0 * xi; dw[2] = 0.5 + xi;
+    }
+}
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3]) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// Transpose of the Boris map v^{n-1/2} -> v^{n+1/2} (half-step h = dt/2):
+// lo = lam(v^{n+1/2}) -> lam(v^{n-1/2}), lam(E), lam(B).
+__device__ __forceinline__ void boris_vjp(const double v[3], const double E[3], const double B[3], double h,
+                                          const double lo[3], double lv[3], double lE[3], double lB[3]) {
+    double vm[3], t[3], s[3], vp[3], c1[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { vm[d] = v[d] + h * E[d]; t[d] = h * B[d]; }
+    const double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+    const double den = 1.0 + tt;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s[d] = 2.0 * t[d] / den;
+    cross3(vm, t, c1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vp[d] = vm[d] + c1[d];
+    double lvp[3], ls[3], lt[3], tmp[3];
+    cross3(s, lo, lvp);
+    cross3(lo, vp, ls);
+    cross3(t, lvp, tmp);
+    double lvm[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lvm[d] = lo[d] + lvp[d] + tmp[d];
+    cross3(lvp, vm, lt);
+    const double ts = t[0] * ls[0] + t[1] * ls[1] + t[2] * ls[2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lt[d] += 2.0 * ls[d] / den - 4.0 * t[d] * ts / (den * den);
+        lB[d] = h * lt[d];
+        lv[d] = lvm[d];
+        lE[d] = h * lo[d] + h * lvm[d];
+    }
+}
+
+// Transpose of the FS kick of a reflected ion (reading of the kick in the
+// paper's Sec. 2: |w| kept, mu' = a + (1 - a) sqrt(U3), azimuth 2 pi U4,
+// re-entry at x' = nx + delta v'_x / v_x).  Inputs: pre-wall velocity v,
+// overshoot delta (cells), lam(x'), lam(v').  Outputs lam(delta) (= lam of
+// the pre-wall x), lam(v) and the u2 adjoint.
+__device__ __forceinline__ void kick_vjp(uint64_t seed, uint64_t step, uint32_t id, double u2, double nx,
+                                         const double v[3], double delta, double lx, const double lvo[3],
+                                         double& lxpre, double lv[3], double& lu2) {
+    const double wv[3] = {v[0] - u2, v[1], v[2]};
+    const double wabs = sqrt(wv[0] * wv[0] + wv[1] * wv[1] + wv[2] * wv[2]);
+    double U[4];
+    draw4(seed, kStreamWall, step, (uint64_t)id, 0, U);
+    const double a = u2 / wabs, su = sqrt(U[2]);
+    const double mu = a + (1.0 - a) * su;
+    const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    const double phi = kTwoPi * U[3], cp = cos(phi), sp = sin(phi);
+    const double vox = u2 - wabs * mu;
+    double lvox = lvo[0];
+    double ldelta = 0.0, lvx_direct = 0.0;
+    const double xnew = nx - (v[0] > 0.0 ? delta * (-vox) / v[0] : 0.0);
+    if (v[0] > 0.0 && xnew < nx) {
+        ldelta = lx * vox / v[0];
+        lvox += lx * delta / v[0];
+        lvx_direct = -lx * delta * vox / (v[0] * v[0]);
+    }
+    lxpre = ldelta;
+    double lu = lvox;
+    double lwabs = -mu * lvox + st * (cp * lvo[1] + sp * lvo[2]);
+    double lmu = -wabs * lvox;
+    const double lst = wabs * (cp * lvo[1] + sp * lvo[2]);
+    if (st > 0.0) lmu += -mu / st * lst;
+    const double la = lmu * (1.0 - su);
+    lu += la / wabs;
+    lwabs += -la * u2 / (wabs * wabs);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lv[d] = lwabs * wv[d] / wabs;
+    lu += -lv[0];
+    lv[0] += lvx_direct;
+    lu2 = lu;
+}
+
+// Sum of a per-thread double over the block, added to *out by one lane.
+__device__ __forceinline__ void block_add(double v, double* out) {
+    __shared__ double red[32];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if (__lane_id() == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < nw; ++i) s += red[i];
+        if (s != 0.0) unsafeAtomicAdd(out, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Particle passes
+// ---------------------------------------------------------------------------
+
+// Deposit transpose over the live particles of one buffer (the state at
+// n+1): lam(x) += sum_nodes dW/dx (lam_R + lam_G . v), lam(v) += sum W lam_G,
+// added to the adjoints of the ions' ids.
+template <typename R, int D, int S>
+__global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
+                                                     const double* __restrict__ lM, PLam<R> lam) {
+    constexpr int N = Stencil<S>::N;
+    constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
+    const int tile = blockIdx.x;
+    const int lo = cnt[tile];
+    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const long src = bin_slot(tile, cap, lo, i);
+        const int32_t pc = in.cell[src];
+        const int cx = cell_x(pc, G), cy = D >= 2 ? cell_y(pc, G) : 0, cz = D >= 3 ? cell_z(pc, G) : 0;
+        double w[3][3], dw[3][3];
+        int rel[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            w[d][0] = 1.0; w[d][1] = w[d][2] = 0.0;
+            dw[d][0] = dw[d][1] = dw[d][2] = 0.0;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) weights_dw<S>((double)in.off[d][src], rel[d], w[d], dw[d]);
+        const double v[3] = {(double)in.v[0][src], (double)in.v[1][src], (double)in.v[2][src]};
+        double gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < NZ; ++c)
+#pragma unroll
+            for (int b = 0; b < NY; ++b)
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    const long gi = dep_index(cx + rel[0] + a, D >= 2 ? cy + rel[1] + b : 0,
+                                              D >= 3 ? cz + rel[2] + c : 0, G);
+                    if (gi < 0) continue;
+                    const double* m = lM + 4 * gi;
+                    const double lm = m[0] + m[1] * v[0] + m[2] * v[1] + m[3] * v[2];
+                    const double W = w[0][a] * w[1][b] * w[2][c];
+                    gx[0] += dw[0][a] * w[1][b] * w[2][c] * lm;
+                    if (D >= 2) gx[1] += w[0][a] * dw[1][b] * w[2][c] * lm;
+                    if (D >= 3) gx[2] += w[0][a] * w[1][b] * dw[2][c] * lm;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) gv[d] += W * m[1 + d];
+                }
+        const int64_t id = in.id[src];
+        if (id >= lam.nid) continue;
+#pragma unroll
+        for (int d = 0; d < D; ++d) lam.x[d][id] = (R)((double)lam.x[d][id] + gx[d]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lam.v[d][id] = (R)((double)lam.v[d][id] + gv[d]);
+    }
+}
+
+// u_sh adjoint of the ions injected during the step (reading of the
+// injection: thermal v_x = |u_sh + sigma n1| entering at x = v_x U0 dt/dx;
+// CRs with |w| = cr_w, mu = a + (1 - a) sqrt(U2), a = u2 / |w|, entering at
+// x = nx - |v_x| U0 dt/dx).  The step's ids are id0 + g, thermal first.
+template <typename R>
+__global__ __launch_bounds__(256) void k_inject_adj(Geo G, PLam<R> lam, uint64_t step, int64_t id0, int64_t nth,
+                                                    int64_t ncr, double* grads) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    const int64_t id = id0 + g;
+    if (g < nth + ncr && id < lam.nid) {
+        const bool cr = g >= nth;
+        const double dtdx = G.dt / G.dx;
+        const double lx = (double)lam.x[0][id];
+        const double lv[3] = {(double)lam.v[0][id], (double)lam.v[1][id], (double)lam.v[2][id]};
+        double U[4];
+        if (!cr) {
+            double V[4], n1, n2;
+            draw4(G.seed, kStreamInjectTh, step, (uint64_t)id, 0, U);
+            draw4(G.seed, kStreamInjectTh, step, (uint64_t)id, 1, V);
+            box_muller(V[0], V[1], n1, n2);
+            const double vx = G.u_sh + G.sigma * n1;
+            const double sg = vx >= 0.0 ? 1.0 : -1.0;
+            const double xi = fabs(vx) * U[0] * dtdx;
+            acc = lv[0] * sg + (xi < (double)G.nx ? lx * sg * U[0] * dtdx : 0.0);
+        } else {
+            draw4(G.seed, kStreamInjectCr, step, (uint64_t)id, 0, U);
+            const double a = G.u2 / G.cr_w, su = sqrt(U[2]);
+            const double mu = a + (1.0 - a) * su;
+            const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+            const double phi = kTwoPi * U[3];
+            const double vx = G.u2 - G.cr_w * mu;
+            const double dmu = (1.0 - su) / G.cr_w;
+            const double dvx = 1.0 - G.cr_w * dmu;
+            const double dst = st > 0.0 ? -mu / st * dmu : 0.0;
+            const double sg = vx >= 0.0 ? 1.0 : -1.0;
+            const double xi = (double)G.nx - fabs(vx) * U[0] * dtdx;
+            const double dxi = xi < (double)G.nx ? -sg * dvx * U[0] * dtdx : 0.0;
+            acc = (lv[0] * dvx + lv[1] * G.cr_w * cos(phi) * dst + lv[2] * G.cr_w * sin(phi) * dst + lx * dxi) * G.rinv;
+        }
+    }
+    block_add(acc, grads);
+}
+
+// u_sh adjoint of the initial load (v_x = u_sh + sigma n1 for every thermal ion).
+template <typename R>
+__global__ __launch_bounds__(256) void k_init_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
+                                                  PLam<R> lam, double* grads) {
+    const int tile = blockIdx.x;
+    const int lo = cnt[tile];
+    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t id = in.id[bin_slot(tile, cap, lo, i)];
+        if (id < lam.nid) acc += (double)lam.v[0][id];
+    }
+    block_add(acc, grads);
+}
+
+// Push transpose over the live particles of the state at n: recompute the
+// gather, Boris and move as the forward step did, undo the FS kick for the
+// ions the step recorded as reflected, then the move, Boris and the gather.
+// The adjoint of each ion is read and written in place (it holds the value
+// after the step on entry and before it on exit); an ion the step removed
+// has a zero adjoint and contributes nothing.  lam(E^n), lam(Bbar^n) (6
+// planar FP64 arrays of nnode) accumulate per tile in LDS.
+template <typename R, int D, int S>
+__global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
+                                                  const R* __restrict__ gather, const uint8_t* __restrict__ refl_of,
+                                                  PLam<R> lam, double* __restrict__ lEB, long nnode, uint64_t step,
+                                                  double* grads) {
+    using X = Extent<D, S>;
+    using T = TileShape<D>;
+    constexpr int LO = Stencil<S>::LO, N = Stencil<S>::N;
+    constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
+    __shared__ double sl[6 * X::GN];
+    const int tile = blockIdx.x;
+    const int tx = tile % G.ntx;
+    const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
+    const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
+    const int gx0 = tx * T::X - LO, gy0 = D >= 2 ? ty * T::Y - LO : 0, gz0 = D >= 3 ? tz * T::Z - LO : 0;
+    for (int l = threadIdx.x; l < 6 * X::GN; l += blockDim.x) sl[l] = 0.0;
+    __syncthreads();
+    const int lo = cnt[tile];
+    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
+    const R hR = (R)(0.5 * G.dt);
+    const R dtdxR = (R)G.dtdx;
+    const double hD = 0.5 * G.dt, dtdx = G.dtdx;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const long src = bin_slot(tile, cap, lo, i);
+        const int64_t id = in.id[src];
+        if (id >= lam.nid) continue;
+        // adjoint of the ion after the step
+        double lx[3] = {0, 0, 0}, lv[3];
+        bool any = false;
+#pragma unroll
+        for (int d = 0; d < D; ++d) { lx[d] = (double)lam.x[d][id]; any |= lx[d] != 0.0; }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) { lv[d] = (double)lam.v[d][id]; any |= lv[d] != 0.0; }
+        if (!any) continue;   // removed by the step (or no influence): stays zero
+        const bool refl = refl_of[id] != 0;
+        const int32_t pc = in.cell[src];
+        const int cx = cell_x(pc, G), cy = D >= 2 ? cell_y(pc, G) : 0, cz = D >= 3 ? cell_z(pc, G) : 0;
+        R o[3] = {0, 0, 0}, v[3];
+#pragma unroll
+        for (int d = 0; d < D; ++d) o[d] = in.off[d][src];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = in.v[c][src];
+        // the forward gather and Boris, in the particle precision
+        R wx[3], wy[3] = {1, 0, 0}, wz[3] = {1, 0, 0};
+        int rx, ry = 0, rz = 0;
+        weights_real<R, S>(o[0], rx, wx);
+        if constexpr (D >= 2) weights_real<R, S>(o[1], ry, wy);
+        if constexpr (D >= 3) weights_real<R, S>(o[2], rz, wz);
+        R E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < NZ; ++c)
+#pragma unroll
+            for (int b = 0; b < NY; ++b) {
+                const R wyz = wy[b] * wz[c];
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    const R W = wx[a] * wyz;
+                    const R* g8 = gather + 8 * gather_index(cx + rx + a, cy + ry + b, cz + rz + c, G);
+                    E[0] += W * g8[0]; E[1] += W * g8[1]; E[2] += W * g8[2];
+                    B[0] += W * g8[4]; B[1] += W * g8[5]; B[2] += W * g8[6];
+                }
+            }
+        R v1[3] = {v[0], v[1], v[2]};
+        boris<R>(v1, E, B, hR);
+        if (refl) {
+            // overshoot as the forward move computed it
+            R xi = o[0] + v1[0] * dtdxR;
+            R fl = floor(xi);
+            int ncx = cx + (int)fl;
+            R ox = xi - fl;
+            if (ox >= (R)1) { ox = (R)0; ncx += 1; }
+            const double delta = (double)(ncx - G.nx) + (double)ox;
+            const double vp[3] = {(double)v1[0], (double)v1[1], (double)v1[2]};
+            double lxpre, lvpre[3], lu2;
+            kick_vjp(G.seed, step, (uint32_t)id, G.u2, (double)G.nx, vp, delta, lx[0], lv, lxpre, lvpre, lu2);
+            acc += lu2 * G.rinv;
+            lx[0] = lxpre;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) lv[d] = lvpre[d];
+        }
+        // move: x^{n+1} = x^n + v^{n+1/2} dt/dx
+#pragma unroll
+        for (int d = 0; d < D; ++d) lv[d] += lx[d] * dtdx;
+        const double vd[3] = {(double)v[0], (double)v[1], (double)v[2]};
+        const double Ed[3] = {(double)E[0], (double)E[1], (double)E[2]};
+        const double Bd[3] = {(double)B[0], (double)B[1], (double)B[2]};
+        double lv0[3], lE[3], lB[3];
+        boris_vjp(vd, Ed, Bd, hD, lv, lv0, lE, lB);
+        // gather transpose
+        double w[3][3], dw[3][3];
+        int rel[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            w[d][0] = 1.0; w[d][1] = w[d][2] = 0.0;
+            dw[d][0] = dw[d][1] = dw[d][2] = 0.0;
+        }
+#pragma unroll
+        for (int d = 0; d < D; ++d) weights_dw<S>((double)o[d], rel[d], w[d], dw[d]);
+        const int lx0 = min(max(cx - gx0 + rel[0], 0), X::GX - N);
+        const int ly0 = D >= 2 ? min(max(cy - gy0 + rel[1], 0), X::GY - N) : 0;
+        const int lz0 = D >= 3 ? min(max(cz - gz0 + rel[2], 0), X::GZ - N) : 0;
+#pragma unroll
+        for (int c = 0; c < NZ; ++c)
+#pragma unroll
+            for (int b = 0; b < NY; ++b)
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    const R* g8 = gather + 8 * gather_index(cx + rel[0] + a, cy + rel[1] + b, cz + rel[2] + c, G);
+                    const double dot = (double)g8[0] * lE[0] + (double)g8[1] * lE[1] + (double)g8[2] * lE[2] +
+                                       (double)g8[4] * lB[0] + (double)g8[5] * lB[1] + (double)g8[6] * lB[2];
+                    const double W = w[0][a] * w[1][b] * w[2][c];
+                    lx[0] += dw[0][a] * w[1][b] * w[2][c] * dot;
+                    if (D >= 2) lx[1] += w[0][a] * dw[1][b] * w[2][c] * dot;
+                    if (D >= 3) lx[2] += w[0][a] * w[1][b] * dw[2][c] * dot;
+                    const int l = ((lz0 + c) * X::GY + (ly0 + b)) * X::GX + (lx0 + a);
+                    atomicAdd(&sl[l], W * lE[0]);
+                    atomicAdd(&sl[X::GN + l], W * lE[1]);
+                    atomicAdd(&sl[2 * X::GN + l], W * lE[2]);
+                    atomicAdd(&sl[3 * X::GN + l], W * lB[0]);
+                    atomicAdd(&sl[4 * X::GN + l], W * lB[1]);
+                    atomicAdd(&sl[5 * X::GN + l], W * lB[2]);
+                }
+#pragma unroll
+        for (int d = 0; d < D; ++d) lam.x[d][id] = (R)lx[d];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lam.v[d][id] = (R)lv0[d];
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < X::GN; l += blockDim.x) {
+        const int lx = l % X::GX, ly = (l / X::GX) % X::GY, lz = l / (X::GX * X::GY);
+        const long gi = gather_index(gx0 + lx, gy0 + ly, gz0 + lz, G);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const double val = sl[k * X::GN + l];
+            if (val != 0.0) unsafeAtomicAdd(lEB + (long)k * nnode + gi, val);
+        }
+    }
+    block_add(acc, grads);
+}
+
+// ---------------------------------------------------------------------------
+// Field passes (FP64, one thread per node or centre)
+// ---------------------------------------------------------------------------
+
+// Storage index of centre (i, j, k) under the ghost rules, -1 for the
+// inflow ghost that holds B0.
+__device__ __forceinline__ long centre_index(const FieldGeo& F, int i, int j, int k) {
+    j = wrapi(j, F.nyc);
+    k = wrapi(k, F.nzc);
+    if (F.xbc == 1) i = wrapi(i, F.nx);
+    else if (i < 0) return -1;
+    else if (i >= F.nx) i = F.nx - 1;
+    return i + (long)F.nx * (j + (long)F.nyc * k);
+}
+
+// Transpose of Ohm's law at every node: (lam_E, lam_Bbar) -> lam_B (centres,
+// added atomically) and lam of the fluid arrays (n_e, p_e, Gx, Gy, Gz at the
+// nodes, added).  fl is the forward fluid state the E was computed from.
+template <int D>
+__global__ __launch_bounds__(256) void k_ohm_adj(FieldGeo F, const double* __restrict__ B, const double* __restrict__ fl,
+                                                 const double* __restrict__ lE, const double* __restrict__ lBb,
+                                                 double* __restrict__ lB, double* __restrict__ lfl, long nnode,
+                                                 long ncent) {
+    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nnode) return;
+    const int i = (int)(n % F.nxn);
+    const long rest = n / F.nxn;
+    const int j = (int)(rest % F.nyc), k = (int)(rest / F.nyc);
+    constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
+    double C[2][NB][NC][3];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d)
+                    C[a][b][c][d] = centre_B(B, F, ncent, i - 1 + a, D >= 2 ? j - 1 + b : 0, D >= 3 ? k - 1 + c : 0, d);
+    double bb[3] = {0, 0, 0}, dBx[3] = {0, 0, 0}, dBy[3] = {0, 0, 0}, dBz[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) bb[d] += C[a][b][c][d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) bb[d] *= 1.0 / (double)(2 * NB * NC);
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) dBx[d] += C[1][b][c][d] - C[0][b][c][d];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dBx[d] *= (1.0 / (double)(NB * NC)) * F.rdx;
+    if constexpr (D >= 2) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dBy[d] += C[a][1][c][d] - C[a][0][c][d];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dBy[d] *= (1.0 / (double)(2 * NC)) * F.rdx;
+    }
+    if constexpr (D >= 3) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) dBz[d] += C[a][b][1][d] - C[a][b][0][d];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dBz[d] *= 0.25 * F.rdx;
+    }
+    const double J[3] = {dBy[2] - dBz[1], dBz[0] - dBx[2], dBx[1] - dBy[0]};
+    const double* pe = fl + nnode;
+    const long nxp = fnode(F, i + 1, j, k), nxm = fnode(F, i - 1, j, k);
+    double gp[3] = {(pe[nxp] - pe[nxm]) * 0.5 * F.rdx, 0.0, 0.0};
+    long nyp = 0, nym = 0, nzp = 0, nzm = 0;
+    if constexpr (D >= 2) {
+        nyp = fnode(F, i, j + 1, k); nym = fnode(F, i, j - 1, k);
+        gp[1] = (pe[nyp] - pe[nym]) * 0.5 * F.rdx;
+    }
+    if constexpr (D >= 3) {
+        nzp = fnode(F, i, j, k + 1); nzm = fnode(F, i, j, k - 1);
+        gp[2] = (pe[nzp] - pe[nzm]) * 0.5 * F.rdx;
+    }
+    const double ne = fl[n];
+    const double Gm[3] = {fl[2 * nnode + n], fl[3 * nnode + n], fl[4 * nnode + n]};
+    double c1[3], c2[3], num[3];
+    cross3(Gm, bb, c1);
+    cross3(J, bb, c2);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) num[d] = -c1[d] + c2[d] - gp[d];
+    // E = num / ne + eta J
+    double lnum[3], lJ[3], lbb[3], tmp[3];
+    double lne = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double le = lE[(long)d * nnode + n];
+        lnum[d] = le / ne;
+        lne -= num[d] * le / (ne * ne);
+        lJ[d] = F.eta * le;
+        lbb[d] = lBb ? lBb[(long)d * nnode + n] : 0.0;
+    }
+    cross3(bb, lnum, tmp);
+    double lG[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { lG[d] = -tmp[d]; lJ[d] += tmp[d]; }
+    const double dv[3] = {J[0] - Gm[0], J[1] - Gm[1], J[2] - Gm[2]};
+    cross3(lnum, dv, tmp);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lbb[d] += tmp[d];
+    // fluid adjoints: n_e and Gamma belong to this node only, p_e to the neighbours
+    lfl[n] += lne;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lfl[(long)(2 + d) * nnode + n] += lG[d];
+    double* lpe = lfl + nnode;
+    const double h2 = 0.5 * F.rdx;
+    unsafeAtomicAdd(lpe + nxp, -lnum[0] * h2);
+    unsafeAtomicAdd(lpe + nxm, lnum[0] * h2);
+    if constexpr (D >= 2) {
+        unsafeAtomicAdd(lpe + nyp, -lnum[1] * h2);
+        unsafeAtomicAdd(lpe + nym, lnum[1] * h2);
+    }
+    if constexpr (D >= 3) {
+        unsafeAtomicAdd(lpe + nzp, -lnum[2] * h2);
+        unsafeAtomicAdd(lpe + nzm, lnum[2] * h2);
+    }
+    // J and Bbar back to the centres
+    double ldBx[3] = {0, 0, 0}, ldBy[3] = {0, 0, 0}, ldBz[3] = {0, 0, 0};
+    ldBy[2] += lJ[0]; ldBz[1] -= lJ[0];
+    ldBz[0] += lJ[1]; ldBx[2] -= lJ[1];
+    ldBx[1] += lJ[2]; ldBy[0] -= lJ[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const long q = centre_index(F, i - 1 + a, D >= 2 ? j - 1 + b : 0, D >= 3 ? k - 1 + c : 0);
+                if (q < 0) continue;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    double s = lbb[d] * (1.0 / (double)(2 * NB * NC));
+                    s += (a == 1 ? 1.0 : -1.0) * ldBx[d] * (1.0 / (double)(NB * NC)) * F.rdx;
+                    if (D >= 2) s += (b == 1 ? 1.0 : -1.0) * ldBy[d] * (1.0 / (double)(2 * NC)) * F.rdx;
+                    if (D >= 3) s += (c == 1 ? 1.0 : -1.0) * ldBz[d] * 0.25 * F.rdx;
+                    unsafeAtomicAdd(lB + (long)d * ncent + q, s);
+                }
+            }
+}
+
+// Transpose of F(B) = -curl E (nodes -> centres): lam_E at every node
+// gathered from the centres that use it.
+template <int D>
+__global__ __launch_bounds__(256) void k_faraday_adj(FieldGeo F, const double* __restrict__ lF, double* __restrict__ lE,
+                                                     long nnode, long ncent) {
+    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nnode) return;
+    const int i = (int)(n % F.nxn);
+    const long rest = n / F.nxn;
+    const int j = (int)(rest % F.nyc), k = (int)(rest / F.nyc);
+    constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
+    double acc[3] = {0, 0, 0};
+    // node (i, j, k) = centre (ci + a, cj + b, ck + c) for a, b, c in {0, 1}
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                int ci = i - a;
+                const int cj = D >= 2 ? wrapi(j - b, F.nyc) : 0, ck = D >= 3 ? wrapi(k - c, F.nzc) : 0;
+                if (F.xbc == 1) ci = wrapi(ci, F.nx);
+                else if (ci < 0 || ci >= F.nx) continue;
+                const long q = ci + (long)F.nx * (cj + (long)F.nyc * ck);
+                const double l0 = lF[q], l1 = lF[ncent + q], l2 = lF[2 * ncent + q];
+                const double ldEx[3] = {0.0, -l2, l1}, ldEy[3] = {l2, 0.0, -l0}, ldEz[3] = {-l1, l0, 0.0};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    double s = (a == 1 ? 1.0 : -1.0) * ldEx[d] * (1.0 / (double)(NB * NC)) * F.rdx;
+                    if (D >= 2) s += (b == 1 ? 1.0 : -1.0) * ldEy[d] * (1.0 / (double)(2 * NC)) * F.rdx;
+                    if (D >= 3) s += (c == 1 ? 1.0 : -1.0) * ldEz[d] * 0.25 * F.rdx;
+                    acc[d] += s;
+                }
+            }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lE[(long)d * nnode + n] = acc[d];
+}
+
+// Transpose of the fluid moments (continuous deposit): lam of (n_e, p_e,
+// Gamma) at the nodes -> lam of the per-species moment sums (R, Gx, Gy, Gz)
+// at the deposit nodes (the boundary fill maps several nodes onto one), and
+// the alpha_cr adjoint (the CR weight is alpha_cr n_cr / ppc_cr).
+__global__ __launch_bounds__(256) void k_fluid_adj(FieldGeo F, const double* __restrict__ m0, const double* __restrict__ m1,
+                                                   const double* __restrict__ lfl, double* __restrict__ lM0,
+                                                   double* __restrict__ lM1, long nnode, double dwcr, double* grads) {
+    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    double acc = 0.0;
+    if (n < nnode) {
+        int i = (int)(n % F.nxn);
+        const long rest = n / F.nxn;
+        if (F.xbc == 0) {
+            if (i < F.mclamp) i = F.mclamp;
+            if (i > F.nx - F.mclamp) i = F.nx - F.mclamp;
+        }
+        const long dn = (long)(i + F.g) + (long)F.ndx * rest;
+        double dens = F.wth * m0[4 * dn];
+        if (F.has_cr) dens += F.wcr * m1[4 * dn];
+        double ld = 0.0;
+        if (dens > F.n_floor)
+            ld = lfl[n] + lfl[nnode + n] * 0.5 * F.beta_e * F.gamma_e * pow(dens, F.gamma_e - 1.0);
+        const double lg[3] = {lfl[2 * nnode + n], lfl[3 * nnode + n], lfl[4 * nnode + n]};
+        unsafeAtomicAdd(lM0 + 4 * dn, F.wth * ld);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) unsafeAtomicAdd(lM0 + 4 * dn + 1 + d, F.wth * lg[d]);
+        if (F.has_cr) {
+            unsafeAtomicAdd(lM1 + 4 * dn, F.wcr * ld);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) unsafeAtomicAdd(lM1 + 4 * dn + 1 + d, F.wcr * lg[d]);
+            acc = dwcr * (m1[4 * dn] * ld + m1[4 * dn + 1] * lg[0] + m1[4 * dn + 2] * lg[1] + m1[4 * dn + 3] * lg[2]);
+        }
+    }
+    block_add(acc, grads);
+}
+
+// out = a x + b y (b y skipped when y is null).
+__global__ void k_axpby(double* __restrict__ out, double a, const double* __restrict__ x, double b,
+                        const double* __restrict__ y, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+// Amplitude adjoints of the initial modes: dB_y = A cos(k_m x + phi_m),
+// dB_z = A sin(k_m x + phi_m) at every centre, one block per mode.
+__global__ __launch_bounds__(256) void k_amps_adj(FieldGeo F, const double* __restrict__ lB, const double* __restrict__ phase,
+                                                  double Lx, long ncent, double* grads) {
+    const int m = blockIdx.x + 1;
+    double acc = 0.0;
+    for (long q = threadIdx.x; q < ncent; q += blockDim.x) {
+        const int i = (int)(q % F.nx);
+        const double x = ((double)i + 0.5) * F.dx;
+        const double ph = kTwoPi * (double)m * x / Lx + phase[m];
+        acc += lB[ncent + q] * cos(ph) + lB[2 * ncent + q] * sin(ph);
+    }
+    block_add(acc, grads + 1 + m);
+}
+
+}  // namespace fsk

@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "fs_field.h"
+#include "fs_adjoint.h"
 #include "fshybrid.h"
 
 using namespace fsk;
@@ -35,6 +35,14 @@ struct fs_handle {
     double* phase = nullptr;
     double* part = nullptr;
     int64_t npart = 0;
+    // reverse-mode scratch (deposit_mode 1 only)
+    double* amom[2] = {nullptr, nullptr};   // moments recomputed for the reverse step
+    double* alM[2] = {nullptr, nullptr};    // their adjoints
+    double* afl = nullptr;                  // fluid state of the reverse step
+    double* alfl = nullptr;                 // its adjoint
+    double* al[4] = {nullptr, nullptr, nullptr, nullptr};  // RK3 stage adjoints l0, l1, l2, lF
+    double* aBs = nullptr;                  // B at the start of each RK substep
+    double* alE = nullptr;                  // curl transpose output at the nodes
     std::string err;
     // phase timing: pool of event pairs recorded on the caller's stream
     bool timing = false;
@@ -103,6 +111,7 @@ int compute_layout(const fs_config* c, fs_layout_info* L, std::string& err) {
     if (!(c->v_max > 0)) { err = "v_max must be positive"; return FS_EINVAL; }
     if (!(c->r > 0)) { err = "compression ratio must be positive"; return FS_EINVAL; }
     if (c->n_sub < 1) { err = "n_sub must be >= 1"; return FS_EINVAL; }
+    if (c->deposit_mode != 0 && c->deposit_mode != 1) { err = "deposit_mode must be 0 or 1"; return FS_EINVAL; }
     for (int w : {c->wall_th, c->wall_cr})
         if (w < FS_WALL_OPEN || w > FS_WALL_SPECULAR) { err = "bad wall policy"; return FS_EINVAL; }
     if (c->n_modes < 0) { err = "n_modes must be >= 0"; return FS_EINVAL; }
@@ -270,8 +279,27 @@ template <typename R> void field_update(fs_handle* h, fs_fields* f, hipStream_t 
 // one step, templated on precision, dimensionality and shape
 // ------------------------------------------------------------------------
 template <typename R, int D, int S>
-int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t flags, hipStream_t s) {
-    const bool push = flags & FS_PUSH, inj = flags & FS_INJECT, dep = flags & FS_DEPOSIT, fld = flags & FS_FIELD;
+void deposit_continuous(fs_handle* h, const fs_particles* sp, double* const mom[2], hipStream_t s) {
+    using X = Extent<D, S>;
+    const size_t lds = 32 * X::DN;
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        const fs_particles& P = sp[k];
+        PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
+        zero_u64(reinterpret_cast<unsigned long long*>(mom[k]), 4 * h->L.ndep, s);
+        allow_lds(k_deposit_c<R, D, S>, lds);
+        k_deposit_c<R, D, S><<<(unsigned)h->L.ntiles, 256, lds, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap, mom[k],
+                                                                    h->ctr);
+    }
+}
+
+template <typename R, int D, int S>
+int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t flags, hipStream_t s,
+              const fs_record* rec = nullptr) {
+    const bool push = flags & FS_PUSH, inj = flags & FS_INJECT, fld = flags & FS_FIELD;
+    const bool cont = h->cfg.deposit_mode == 1;
+    // the continuous deposit runs as its own pass after the particles have moved
+    const bool dep = (flags & FS_DEPOSIT) && !cont;
+    const bool cdep = (flags & FS_DEPOSIT) && cont;
     const int nsp = h->has_cr ? 2 : 1;
     const fs_config& c = h->cfg;
     int64_t cth = 0, ccr = 0;
@@ -317,12 +345,13 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
                 PBuf<R> out = sections<R>(P.buf[P.cur ^ 1], P.capacity, D);
                 unsigned gw = std::min<unsigned>(grid_for(h->xl[k].cap), 1024u);
                 auto* mom = reinterpret_cast<unsigned long long*>(f->mom[k]);
+                uint8_t* rd = rec ? rec->refl : nullptr;
                 if (dep)
                     k_wall<R, D, S, true><<<gw, 256, 0, s>>>(G, h->xl[k], out, P.tile_count[P.cur ^ 1], P.tile_cap, mom,
-                                                            h->ctr, policy_of(h, k), k, (uint64_t)step);
+                                                            h->ctr, policy_of(h, k), k, (uint64_t)step, rd);
                 else
                     k_wall<R, D, S, false><<<gw, 256, 0, s>>>(G, h->xl[k], out, P.tile_count[P.cur ^ 1], P.tile_cap, mom,
-                                                             h->ctr, policy_of(h, k), k, (uint64_t)step);
+                                                             h->ctr, policy_of(h, k), k, (uint64_t)step, rd);
             }
         }
         timing_end(h, t_wall, s);
@@ -355,6 +384,10 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
     timing_end(h, t_inj, s);
     if (push)
         for (int k = 0; k < nsp; ++k) sp[k].cur ^= 1;
+    if (cdep) {
+        double* const mom[2] = {reinterpret_cast<double*>(f->mom[0]), h->has_cr ? reinterpret_cast<double*>(f->mom[1]) : nullptr};
+        deposit_continuous<R, D, S>(h, sp, mom, s);
+    }
     if (dep && !push) {
         const size_t lds_dep = 32 * X::DN;
         for (int k = 0; k < nsp; ++k) {
@@ -408,6 +441,11 @@ template <typename R, int D, int S> int deposit_impl(fs_handle* h, const fs_part
     using X = Extent<D, S>;
     const int nsp = h->has_cr ? 2 : 1;
     zero_u64(h->ctr, C_N, s);
+    if (h->cfg.deposit_mode == 1) {
+        double* const mom[2] = {reinterpret_cast<double*>(f->mom[0]), h->has_cr ? reinterpret_cast<double*>(f->mom[1]) : nullptr};
+        deposit_continuous<R, D, S>(h, sp, mom, s);
+        return hip_check(h, hipGetLastError(), "deposit launch");
+    }
     for (int k = 0; k < nsp; ++k) {
         zero_u64(f->mom[k], 4 * h->L.ndep, s);
         const fs_particles& P = sp[k];
@@ -417,6 +455,166 @@ template <typename R, int D, int S> int deposit_impl(fs_handle* h, const fs_part
             h->G, in, P.tile_count[P.cur], P.tile_cap, reinterpret_cast<unsigned long long*>(f->mom[k]), h->ctr);
     }
     return hip_check(h, hipGetLastError(), "deposit launch");
+}
+
+// ------------------------------------------------------------------------
+// reverse mode
+// ------------------------------------------------------------------------
+// One SSP-RK3 stage Bout = c0 Bn + c1 (Bin + h F(Bin)) with fluid state fl.
+template <int D>
+void stage_launch(fs_handle* h, const double* Bin, const double* Bn, double* Bout, const double* fl, double c0,
+                  double c1, double hs, hipStream_t s) {
+    const long nn = h->L.nnode, nc = h->L.ncent;
+    if constexpr (D == 3) {
+        const int gx = (h->cfg.nx + ZMarch::X - 1) / ZMarch::X;
+        const int gy = (int)((h->L.nyc + ZMarch::Y - 1) / ZMarch::Y);
+        const int zc = (int)std::min<int64_t>(h->L.nzc, 32), gz = (int)((h->L.nzc + zc - 1) / zc);
+        k_stage3<<<(unsigned)(gx * gy * gz), 256, 0, s>>>(h->F, Bin, Bn, Bout, fl, c0, c1, hs, nn, nc, gx, gy, zc);
+    } else {
+        using FB = FieldBlock<D>;
+        const int gx = (h->cfg.nx + FB::X - 1) / FB::X;
+        const int gy = (int)((h->L.nyc + FB::Y - 1) / FB::Y), gz = (int)((h->L.nzc + FB::Z - 1) / FB::Z);
+        k_stage<D><<<(unsigned)(gx * gy * gz), 256, 0, s>>>(h->F, Bin, Bn, Bout, fl, c0, c1, hs, nn, nc, gx, gy);
+    }
+}
+
+template <typename R> PLam<R> plam(const fs_adjoint* a, int D) {
+    PLam<R> L;
+    for (int d = 0; d < 3; ++d) {
+        L.x[d] = d < D ? static_cast<R*>(a->x[d]) : nullptr;
+        L.v[d] = static_cast<R*>(a->v[d]);
+    }
+    L.nid = a->nid;
+    return L;
+}
+
+void axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t s) {
+    k_axpby<<<grid_for(n), 256, 0, s>>>(out, a, x, b, y, n);
+}
+
+// Moments and fluid state of a particle state, into the reverse scratch.
+template <typename R, int D, int S> void fluid_of(fs_handle* h, const fs_particles* sp, hipStream_t s) {
+    deposit_continuous<R, D, S>(h, sp, h->amom, s);
+    const dim3 blk(kFX, kFY, 1);
+    const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
+    k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(h->amom[0]),
+                               reinterpret_cast<const long long*>(h->has_cr ? h->amom[1] : h->amom[0]), h->afl,
+                               h->L.nnode);
+}
+
+// lam_B += (dF/dB)^T lF and lam_fl += (dF/dfl)^T lF for F(B) = -curl Ohm(B, fl).
+template <int D>
+void rhs_adj(fs_handle* h, const double* B, const double* lF, double* lB, hipStream_t s) {
+    const long nn = h->L.nnode, nc = h->L.ncent;
+    k_faraday_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, lF, h->alE, nn, nc);
+    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, B, h->afl, h->alE, nullptr, lB, h->alfl, nn, nc);
+}
+
+// Transpose of the SSP-RK3 field update from B^n with the fluid state in
+// h->afl: lam_B (in: lam(B^{n+1}), out: lam(B^n)); fluid adjoints added to
+// h->alfl.  The stages are recomputed.
+template <int D> void rk3_adj(fs_handle* h, const double* Bn, double* lB, hipStream_t s) {
+    const long N = 3 * h->L.ncent;
+    const int ns = h->cfg.n_sub;
+    const double hs = h->cfg.dt / (double)ns;
+    double* Bs = h->aBs;
+    (void)hipMemcpyAsync(Bs, Bn, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    for (int sub = 0; sub + 1 < ns; ++sub) {
+        double* B0 = Bs + (size_t)sub * N;
+        stage_launch<D>(h, B0, B0, h->B1, h->afl, 0.0, 1.0, hs, s);
+        stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
+        stage_launch<D>(h, h->B2, B0, B0 + N, h->afl, 1.0 / 3.0, 2.0 / 3.0, hs, s);
+    }
+    double *l0 = h->al[0], *l1 = h->al[1], *l2 = h->al[2], *lF = h->al[3];
+    for (int sub = ns - 1; sub >= 0; --sub) {
+        double* B0 = Bs + (size_t)sub * N;
+        stage_launch<D>(h, B0, B0, h->B1, h->afl, 0.0, 1.0, hs, s);
+        stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
+        // B3 = 1/3 B0 + 2/3 (B2 + h F(B2))
+        axpby(l0, 1.0 / 3.0, lB, 0.0, nullptr, N, s);
+        axpby(l2, 2.0 / 3.0, lB, 0.0, nullptr, N, s);
+        axpby(lF, 2.0 / 3.0 * hs, lB, 0.0, nullptr, N, s);
+        rhs_adj<D>(h, h->B2, lF, l2, s);
+        // B2 = 3/4 B0 + 1/4 (B1 + h F(B1))
+        axpby(l0, 1.0, l0, 0.75, l2, N, s);
+        axpby(l1, 0.25, l2, 0.0, nullptr, N, s);
+        axpby(lF, 0.25 * hs, l2, 0.0, nullptr, N, s);
+        rhs_adj<D>(h, h->B1, lF, l1, s);
+        // B1 = B0 + h F(B0)
+        axpby(l0, 1.0, l0, 1.0, l1, N, s);
+        axpby(lF, hs, l1, 0.0, nullptr, N, s);
+        rhs_adj<D>(h, B0, lF, l0, s);
+        (void)hipMemcpyAsync(lB, l0, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    }
+}
+
+// Fluid and deposit transposes: lam of the fluid state in h->alfl -> the
+// particle adjoints of the state whose moments are in h->amom.
+template <typename R, int D, int S>
+void moments_adj(fs_handle* h, const fs_particles* sp, const fs_adjoint* lam, double* grads, hipStream_t s) {
+    const long nn = h->L.nnode;
+    for (int k = 0; k < 2; ++k) zero_u64(reinterpret_cast<unsigned long long*>(h->alM[k]), 4 * h->L.ndep, s);
+    const double dwcr = h->has_cr ? h->cfg.n_cr / (double)h->cfg.ppc_cr : 0.0;
+    k_fluid_adj<<<grid_for(nn), 256, 0, s>>>(h->F, h->amom[0], h->has_cr ? h->amom[1] : h->amom[0], h->alfl, h->alM[0],
+                                             h->alM[1], nn, dwcr, grads + 1);
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        const fs_particles& P = sp[k];
+        PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
+        k_deposit_adj<R, D, S><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
+                                                                     h->alM[k], plam<R>(lam, D));
+    }
+}
+
+template <typename R, int D, int S>
+int adjoint_step_impl(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n, const fs_particles* sp_n1,
+                      const fs_fields* f_n1, const fs_record* rec, int64_t step, fs_adjoint* lam, double* grads,
+                      hipStream_t s) {
+    const long nn = h->L.nnode, nc = h->L.ncent;
+    // fluid state the step's field update used: moments of the particles after it
+    fluid_of<R, D, S>(h, sp_n1, s);
+    zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
+    // final Ohm, then the RK3 update
+    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, f_n1->B, h->afl, lam->lE, lam->lE + 3 * nn, lam->lB, h->alfl, nn, nc);
+    rk3_adj<D>(h, f_n->B, lam->lB, s);
+    // fluid and deposit at n+1, into the particle adjoints after the step
+    moments_adj<R, D, S>(h, sp_n1, lam, grads, s);
+    // ions injected by the step
+    int64_t cth = 0, ccr = 0;
+    inject_counts(h->cfg, step, cth, ccr);
+    const int64_t ntr = h->L.nyc * h->L.nzc, nth = cth * ntr, ncr = ccr * ntr;
+    if (nth + ncr > 0)
+        k_inject_adj<R><<<grid_for(nth + ncr), 256, 0, s>>>(h->G, plam<R>(lam, D), (uint64_t)step, rec->id0, nth, ncr,
+                                                           grads);
+    // push, wall and gather of the ions that lived before the step
+    zero_u64(reinterpret_cast<unsigned long long*>(lam->lE), 6 * nn, s);
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        const fs_particles& P = sp_n[k];
+        PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
+        k_push_adj<R, D, S><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
+                                                                  static_cast<const R*>(f_n->gather), rec->refl,
+                                                                  plam<R>(lam, D), lam->lE, nn, (uint64_t)step, grads);
+    }
+    return hip_check(h, hipGetLastError(), "adjoint step launch");
+}
+
+template <typename R, int D, int S>
+int adjoint_init_impl(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, fs_adjoint* lam, double* grads,
+                      hipStream_t s) {
+    const long nn = h->L.nnode, nc = h->L.ncent;
+    fluid_of<R, D, S>(h, sp0, s);
+    zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
+    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, f0->B, h->afl, lam->lE, lam->lE + 3 * nn, lam->lB, h->alfl, nn, nc);
+    moments_adj<R, D, S>(h, sp0, lam, grads, s);
+    const fs_particles& P = sp0[0];
+    PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
+    k_init_adj<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap, plam<R>(lam, D),
+                                                        grads);
+    const fs_config& c = h->cfg;
+    if (c.n_modes > 0) {
+        k_phases<<<grid_for(c.n_modes), 256, 0, s>>>(c.seed, c.n_modes, h->phase);
+        k_amps_adj<<<(unsigned)c.n_modes, 256, 0, s>>>(h->F, lam->lB, h->phase, (double)c.nx * c.dx, nc, grads);
+    }
+    return hip_check(h, hipGetLastError(), "adjoint init launch");
 }
 
 // Dispatch a templated implementation on (precision, dim, shape).
@@ -495,7 +693,7 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     G.bx = h->L.cell_bits[0]; G.by = h->L.cell_bits[1];
     G.b = h->L.b_bits; G.sv = h->L.sv_bits; G.mclamp = c.shape;
     G.dt = c.dt; G.dx = c.dx; G.u_sh = c.u_sh; G.u2 = c.u_sh / c.r; G.sigma = std::sqrt(0.5 * c.beta_i);
-    G.cr_w = c.cr_w; G.dtdx = c.dt / c.dx; G.seed = c.seed;
+    G.cr_w = c.cr_w; G.dtdx = c.dt / c.dx; G.seed = c.seed; G.rinv = 1.0 / c.r;
     FieldGeo& F = h->F;
     F.dim = c.dim; F.nx = c.nx; F.nyc = G.nyc; F.nzc = G.nzc; F.nxn = G.nxn; F.ndx = G.ndx; F.g = G.g;
     F.xbc = c.xbc; F.mclamp = c.shape; F.dx = c.dx; F.rdx = 1.0 / c.dx;
@@ -507,6 +705,7 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     F.scR = std::ldexp(1.0, -h->L.sw_bits);
     F.scG = std::ldexp(1.0, -(h->L.sw_bits + h->L.sv_bits));
     F.has_cr = h->has_cr ? 1 : 0;
+    F.cont = c.deposit_mode == 1 ? 1 : 0;
 
     auto dmalloc = [&](void** p, size_t bytes) -> bool {
         return hipMalloc(p, std::max<size_t>(bytes, 256)) == hipSuccess;
@@ -522,6 +721,18 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     ok = ok && dmalloc((void**)&h->phase, (c.n_modes + 1) * sizeof(double));
     h->npart = std::max<int64_t>(grid_for(nc), h->L.ntiles) * 4;
     ok = ok && dmalloc((void**)&h->part, h->npart * sizeof(double));
+    if (c.deposit_mode == 1) {
+        const long nd = h->L.ndep;
+        for (int k = 0; k < 2 && ok; ++k) {
+            ok = ok && dmalloc((void**)&h->amom[k], 4 * nd * sizeof(double));
+            ok = ok && dmalloc((void**)&h->alM[k], 4 * nd * sizeof(double));
+        }
+        ok = ok && dmalloc((void**)&h->afl, 5 * nn * sizeof(double));
+        ok = ok && dmalloc((void**)&h->alfl, 5 * nn * sizeof(double));
+        for (int k = 0; k < 4 && ok; ++k) ok = ok && dmalloc((void**)&h->al[k], 3 * nc * sizeof(double));
+        ok = ok && dmalloc((void**)&h->aBs, (size_t)c.n_sub * 3 * nc * sizeof(double));
+        ok = ok && dmalloc((void**)&h->alE, 3 * nn * sizeof(double));
+    }
     // crosser lists: a generous bound on the ions that can reach the wall in one step
     for (int k = 0; k < 2 && ok; ++k) {
         int64_t ppc = k == 0 ? c.ppc : c.ppc_cr;
@@ -556,6 +767,9 @@ void fs_destroy(fs_handle* h) {
     if (h->ctr_host) hipHostFree(h->ctr_host);
     hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->phase); hipFree(h->part);
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
+    for (int k = 0; k < 2; ++k) { hipFree(h->amom[k]); hipFree(h->alM[k]); }
+    hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->alE);
+    for (int k = 0; k < 4; ++k) hipFree(h->al[k]);
     delete h;
 }
 
@@ -578,14 +792,15 @@ int fs_init_plasma(fs_handle* h, fs_particles* sp, fs_fields* f, const double* a
     return fs_refresh_fields(h, f, s);
 }
 
-int fs_step(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t flags, fs_step_stats* st, hipStream_t s) {
+static int step_common(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t flags, fs_step_stats* st,
+                       hipStream_t s, const fs_record* rec) {
     if (!h || !sp || !f) return fail(h, FS_EINVAL, "NULL argument");
     if (flags & ~FS_ALL) return fail(h, FS_EINVAL, "unknown step flags");
     if (step < 0) return fail(h, FS_EINVAL, "negative step");
     int rc = check_particles(h, sp);
     if (!rc) rc = check_fields(h, f);
     if (rc) return rc;
-    auto run = [&]() -> int { FS_DISPATCH(h, (step_impl<R, D, S>(h, sp, f, step, flags, s))); };
+    auto run = [&]() -> int { FS_DISPATCH(h, (step_impl<R, D, S>(h, sp, f, step, flags, s, rec))); };
     rc = run();
     if (rc) return rc;
     if (!st) return FS_OK;
@@ -611,6 +826,66 @@ int fs_step(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t
     if (st->flags & (F_TILE | F_XLIST)) return fail(h, FS_ETILE, "a tile bin or the crosser list overflowed");
     if (st->flags & (F_NAN | F_SAT)) return fail(h, FS_ENUMERIC, "NaN or saturated velocity code in the deposit");
     return FS_OK;
+}
+
+int fs_step(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t flags, fs_step_stats* st, hipStream_t s) {
+    return step_common(h, sp, f, step, flags, st, s, nullptr);
+}
+
+int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec, fs_step_stats* st,
+                   hipStream_t s) {
+    if (!h || !rec || !rec->refl) return fail(h, FS_EINVAL, "NULL argument");
+    if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "a recorded step needs deposit_mode 1");
+    int64_t cth = 0, ccr = 0;
+    inject_counts(h->cfg, step, cth, ccr);
+    const int64_t ninj = (cth + ccr) * h->L.nyc * h->L.nzc;
+    if (h->next_id + ninj > rec->nid) return fail(h, FS_ECAPACITY, "record smaller than the ids the step hands out");
+    int rc = hip_check(h, hipMemsetAsync(rec->refl, 0, (size_t)rec->nid, s), "record clear");
+    if (rc) return rc;
+    rec->id0 = h->next_id;
+    return step_common(h, sp, f, step, FS_ALL, st, s, rec);
+}
+
+static int check_adjoint(fs_handle* h, const fs_adjoint* lam) {
+    if (!lam || !lam->lB || !lam->lE) return fail(h, FS_EINVAL, "NULL adjoint array");
+    for (int d = 0; d < 3; ++d)
+        if ((d < h->cfg.dim && !lam->x[d]) || !lam->v[d]) return fail(h, FS_EINVAL, "NULL particle adjoint array");
+    if (lam->nid < h->next_id) return fail(h, FS_ECAPACITY, "particle adjoint arrays smaller than the id range");
+    return FS_OK;
+}
+
+int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n, const fs_particles* sp_n1,
+                    const fs_fields* f_n1, const fs_record* rec, int64_t step, fs_adjoint* lam, double* grads,
+                    hipStream_t s) {
+    if (!h || !sp_n || !f_n || !sp_n1 || !f_n1 || !rec || !rec->refl || !lam || !grads)
+        return fail(h, FS_EINVAL, "NULL argument");
+    if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
+    if (!f_n->B || !f_n->gather || !f_n1->B) return fail(h, FS_EINVAL, "NULL field array");
+    if (step < 0) return fail(h, FS_EINVAL, "negative step");
+    int64_t cth = 0, ccr = 0;
+    inject_counts(h->cfg, step, cth, ccr);
+    if (rec->id0 + (cth + ccr) * h->L.nyc * h->L.nzc > lam->nid || rec->nid > lam->nid)
+        return fail(h, FS_ECAPACITY, "particle adjoint arrays smaller than the id range");
+    int rc = check_adjoint(h, lam);
+    if (!rc) rc = check_particles(h, sp_n);
+    if (!rc) rc = check_particles(h, sp_n1);
+    if (rc) return rc;
+    auto run = [&]() -> int {
+        FS_DISPATCH(h, (adjoint_step_impl<R, D, S>(h, sp_n, f_n, sp_n1, f_n1, rec, step, lam, grads, s)));
+    };
+    return run();
+}
+
+int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, fs_adjoint* lam, double* grads,
+                    hipStream_t s) {
+    if (!h || !sp0 || !f0 || !lam || !grads) return fail(h, FS_EINVAL, "NULL argument");
+    if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
+    if (!f0->B) return fail(h, FS_EINVAL, "NULL field array");
+    int rc = check_adjoint(h, lam);
+    if (!rc) rc = check_particles(h, sp0);
+    if (rc) return rc;
+    auto run = [&]() -> int { FS_DISPATCH(h, (adjoint_init_impl<R, D, S>(h, sp0, f0, lam, grads, s))); };
+    return run();
 }
 
 int fs_deposit_moments(fs_handle* h, const fs_particles* sp, fs_fields* f, hipStream_t s) {

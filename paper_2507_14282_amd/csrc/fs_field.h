@@ -20,6 +20,7 @@ struct FieldGeo {
     double n_floor, beta_e, gamma_e, eta, j_ext;
     double wth, wcr, scR, scG;    // species weights and fixed-point scales
     int has_cr;
+    int cont;                     // moments hold FP64 sums (continuous deposit)
 };
 
 // B component c at centre (i, j, k), ghost rules in x, periodic in y/z.
@@ -52,14 +53,27 @@ __global__ __launch_bounds__(256) void k_fluid(FieldGeo F, const long long* __re
         if (i > F.nx - F.mclamp) i = F.nx - F.mclamp;
     }
     const long dn = (long)(i + F.g) + (long)F.ndx * (j + (long)F.nyc * k);
-    double dens = F.wth * ((double)m0[4 * dn] * F.scR);
-    double G[3];
+    double dens, G[3];
+    if (F.cont) {
+        const double* d0 = reinterpret_cast<const double*>(m0);
+        const double* d1 = reinterpret_cast<const double*>(m1);
+        dens = F.wth * d0[4 * dn];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) G[c] = F.wth * ((double)m0[4 * dn + 1 + c] * F.scG);
-    if (F.has_cr) {
-        dens += F.wcr * ((double)m1[4 * dn] * F.scR);
+        for (int c = 0; c < 3; ++c) G[c] = F.wth * d0[4 * dn + 1 + c];
+        if (F.has_cr) {
+            dens += F.wcr * d1[4 * dn];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) G[c] += F.wcr * ((double)m1[4 * dn + 1 + c] * F.scG);
+            for (int c = 0; c < 3; ++c) G[c] += F.wcr * d1[4 * dn + 1 + c];
+        }
+    } else {
+        dens = F.wth * ((double)m0[4 * dn] * F.scR);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) G[c] = F.wth * ((double)m0[4 * dn + 1 + c] * F.scG);
+        if (F.has_cr) {
+            dens += F.wcr * ((double)m1[4 * dn] * F.scR);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) G[c] += F.wcr * ((double)m1[4 * dn + 1 + c] * F.scG);
+        }
     }
     double ne = fmax(dens, F.n_floor);
     fl[n] = ne;

@@ -26,7 +26,7 @@ struct Geo {
     int bx, by;                   // packed cell bit widths for x and y
     int b, sv;                    // fixed-point position / velocity bits
     int mclamp;                   // boundary node moment fill distance (shape order)
-    double dt, dx, u_sh, u2, sigma, cr_w, dtdx;
+    double dt, dx, u_sh, u2, sigma, cr_w, dtdx, rinv;
     uint64_t seed;
 };
 
@@ -442,7 +442,7 @@ __global__ void k_check_bins(const int32_t* counts, int ntiles, int64_t cap, uns
 template <typename R, int D, int S, bool DEP>
 __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int32_t* cnt_out, int64_t cap,
                                               unsigned long long* mom, unsigned long long* ctr,
-                                              int policy, int species, uint64_t step) {
+                                              int policy, int species, uint64_t step, uint8_t* refl_rec) {
     int ncross = *xl.count;
     if (ncross > xl.cap) ncross = (int)xl.cap;
     int status = 0, oor = 0;
@@ -487,6 +487,7 @@ __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int3
 #pragma unroll
         for (int c = 0; c < 3; ++c) out.v[c][dst] = vr[c];
         out.id[dst] = pid;
+        if (refl_rec != nullptr) refl_rec[pid] = 1;   // step record: this ion was reflected
         if constexpr (DEP) status |= deposit_particle<R, D, S>(nullptr, 0, 0, 0, mom, G, cx, cy, cz, o, vr, oor);
     }
     if (status & F_SAT) atomicAdd(ctr + C_SAT, 1ull);
@@ -568,6 +569,94 @@ __global__ __launch_bounds__(256) void k_inject(Geo G, PBuf<R> out0, int32_t* cn
     if (status & F_SAT) atomicAdd(ctr + C_SAT, 1ull);
     if (oor) atomicAdd(ctr + C_OOR, 1ull);
     if (status) atomicOr(reinterpret_cast<unsigned int*>(ctr + C_FLAGS), (unsigned int)status);
+}
+
+// ---------------------------------------------------------------------------
+// Continuous deposit (the differentiable variant of the step): real shape
+// weights in FP64, R = sum W and G = sum W v per node, FP64 atomics.  The
+// moment grids then hold doubles.
+// ---------------------------------------------------------------------------
+template <typename R, int D, int S>
+__device__ __forceinline__ void deposit_particle_c(double* lds, int bx0, int by0, int bz0, double* mom, const Geo& G,
+                                                   int cx, int cy, int cz, const R* o, const R* v, int& oor) {
+    using X = Extent<D, S>;
+    constexpr int N = Stencil<S>::N;
+    constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
+    double wx[3], wy[3] = {1, 0, 0}, wz[3] = {1, 0, 0};
+    int rx, ry = 0, rz = 0;
+    weights_real<double, S>((double)o[0], rx, wx);
+    if constexpr (D >= 2) weights_real<double, S>((double)o[1], ry, wy);
+    if constexpr (D >= 3) weights_real<double, S>((double)o[2], rz, wz);
+    const double vd[3] = {(double)v[0], (double)v[1], (double)v[2]};
+    int lx = cx + rx - bx0, ly = D >= 2 ? cy + ry - by0 : 0, lz = D >= 3 ? cz + rz - bz0 : 0;
+    bool in_lds = lds != nullptr && lx >= 0 && lx + N <= X::DX;
+    if constexpr (D >= 2) in_lds = in_lds && ly >= 0 && ly + N <= X::DY;
+    if constexpr (D >= 3) in_lds = in_lds && lz >= 0 && lz + N <= X::DZ;
+#pragma unroll
+    for (int c = 0; c < NZ; ++c)
+#pragma unroll
+        for (int b = 0; b < NY; ++b)
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                const double W = wx[a] * wy[b] * wz[c];
+                if (in_lds) {
+                    double* p = lds + ((lz + c) * X::DY * X::DX + (ly + b) * X::DX + (lx + a));
+                    atomicAdd(p, W);
+                    atomicAdd(p + X::DN, W * vd[0]);
+                    atomicAdd(p + 2 * X::DN, W * vd[1]);
+                    atomicAdd(p + 3 * X::DN, W * vd[2]);
+                } else {
+                    long gi = dep_index(cx + rx + a, D >= 2 ? cy + ry + b : 0, D >= 3 ? cz + rz + c : 0, G);
+                    if (gi < 0) { oor = 1; continue; }
+                    double* p = mom + 4 * gi;
+                    unsafeAtomicAdd(p, W);
+                    unsafeAtomicAdd(p + 1, W * vd[0]);
+                    unsafeAtomicAdd(p + 2, W * vd[1]);
+                    unsafeAtomicAdd(p + 3, W * vd[2]);
+                }
+            }
+}
+
+template <typename R, int D, int S>
+__global__ __launch_bounds__(256) void k_deposit_c(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
+                                                   double* __restrict__ mom, unsigned long long* __restrict__ ctr) {
+    using X = Extent<D, S>;
+    using T = TileShape<D>;
+    constexpr int LO = Stencil<S>::LO;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* sd = reinterpret_cast<double*>(smem);
+    const int tile = xcd_tile(blockIdx.x, G.ntiles);
+    const int tx = tile % G.ntx;
+    const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
+    const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
+    const int dx0 = tx * T::X - X::H - LO, dy0 = D >= 2 ? ty * T::Y - X::H - LO : 0, dz0 = D >= 3 ? tz * T::Z - X::H - LO : 0;
+    for (int l = threadIdx.x; l < X::DN * 4; l += blockDim.x) sd[l] = 0.0;
+    __syncthreads();
+    const int lo = cnt[tile];
+    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
+    int oor = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        long src = bin_slot(tile, cap, lo, i);
+        int32_t pc = in.cell[src];
+        R o[3] = {0, 0, 0}, v[3];
+#pragma unroll
+        for (int d = 0; d < D; ++d) o[d] = in.off[d][src];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = in.v[c][src];
+        deposit_particle_c<R, D, S>(sd, dx0, dy0, dz0, mom, G, cell_x(pc, G), D >= 2 ? cell_y(pc, G) : 0,
+                                    D >= 3 ? cell_z(pc, G) : 0, o, v, oor);
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < X::DN * 4; l += blockDim.x) {
+        int node = l >> 2, m = l & 3;
+        double val = sd[m * X::DN + node];
+        if (val == 0.0) continue;
+        int lx = node % X::DX, ly = (node / X::DX) % X::DY, lz = node / (X::DX * X::DY);
+        long gi = dep_index(dx0 + lx, D >= 2 ? dy0 + ly : 0, D >= 3 ? dz0 + lz : 0, G);
+        if (gi < 0) { oor = 1; continue; }
+        unsafeAtomicAdd(mom + 4 * gi + m, val);
+    }
+    if (oor) atomicAdd(ctr + C_OOR, 1ull);
 }
 
 // Standalone deposit of the live particles of every tile.

@@ -47,7 +47,7 @@ class FsConfig(C.Structure):
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("ppc", C.c_int32), ("ppc_cr", C.c_int32), ("shape", C.c_int32), ("precision", C.c_int32),
         ("wall_th", C.c_int32), ("wall_cr", C.c_int32), ("xbc", C.c_int32), ("n_sub", C.c_int32),
-        ("n_modes", C.c_int32), ("inject", C.c_int32), ("pad0", C.c_int32), ("pad1", C.c_int32),
+        ("n_modes", C.c_int32), ("inject", C.c_int32), ("deposit_mode", C.c_int32), ("pad1", C.c_int32),
     ]
 
 
@@ -90,6 +90,17 @@ class FsStats(C.Structure):
         return d
 
 
+class FsRecord(C.Structure):
+    _fields_ = [("refl", C.c_void_p), ("nid", C.c_int64), ("id0", C.c_int64)]
+
+
+class FsAdjoint(C.Structure):
+    _fields_ = [("x", C.c_void_p * 3), ("v", C.c_void_p * 3), ("nid", C.c_int64), ("lB", C.c_void_p),
+                ("lE", C.c_void_p)]
+
+
+DEPOSIT_MODE = {"fixed": 0, "continuous": 1, 0: 0, 1: 1}
+
 _lib = None
 
 
@@ -122,6 +133,10 @@ def library():
         L.fs_diagnostics.argtypes = [vp, P, F, vp, vp, vp]
         L.fs_timing_enable.argtypes = [vp, i32]
         L.fs_timing_read.argtypes = [vp, vp, vp, vp]
+        R, A = C.POINTER(FsRecord), C.POINTER(FsAdjoint)
+        L.fs_step_record.argtypes = [vp, P, F, i64, R, C.POINTER(FsStats), vp]
+        L.fs_adjoint_step.argtypes = [vp, P, F, P, F, R, i64, A, vp, vp]
+        L.fs_adjoint_init.argtypes = [vp, P, F, A, vp, vp]
         _lib = L
     return _lib
 
@@ -131,7 +146,7 @@ def exported_symbols():
     return ["fs_layout", "fs_create", "fs_destroy", "fs_last_error", "fs_init_plasma", "fs_step",
             "fs_deposit_moments", "fs_apply_faux_shock", "fs_field_update", "fs_refresh_fields",
             "fs_load_particles", "fs_read_particles", "fs_set_clock", "fs_next_id", "fs_diagnostics",
-            "fs_timing_enable", "fs_timing_read"]
+            "fs_timing_enable", "fs_timing_read", "fs_step_record", "fs_adjoint_step", "fs_adjoint_init"]
 
 
 def make_config(p: dict) -> FsConfig:
@@ -150,6 +165,7 @@ def make_config(p: dict) -> FsConfig:
     c.wall_cr = WALL[p["wall_cr"]]
     c.xbc = XBC[p["xbc"]]
     c.inject = 1 if p.get("inject", True) else 0
+    c.deposit_mode = DEPOSIT_MODE[p.get("deposit_mode", "fixed")]
     return c
 
 
@@ -183,6 +199,7 @@ class Simulation:
         self.has_cr = float(p["n_cr"]) > 0.0
         self._keep = []
         self.counts = []
+        self.bufs, self.cnts = [], []     # per species: the two particle buffers and their tile counts
         self.sp = (FsParticles * 2)()
         for s in range(2):
             nb = int(L.buf_bytes[s]) if (s == 0 or self.has_cr) else 0
@@ -191,6 +208,8 @@ class Simulation:
             count = torch.zeros(1, dtype=torch.int64, device=dev)
             self._keep += bufs + cnts + [count]
             self.counts.append(count)
+            self.bufs.append(bufs)
+            self.cnts.append(cnts)
             P = self.sp[s]
             P.buf[0], P.buf[1] = bufs[0].data_ptr(), bufs[1].data_ptr()
             P.tile_count[0], P.tile_count[1] = cnts[0].data_ptr(), cnts[1].data_ptr()
@@ -240,6 +259,15 @@ class Simulation:
         st = FsStats() if stats else None
         rc = self.lib.fs_step(self.h, self.sp, C.byref(self.f), int(step), int(flags),
                               C.byref(st) if st is not None else None, self.stream)
+        self._check(rc)
+        return st.as_dict() if st is not None else None
+
+    def step_record(self, step: int, rec: "FsRecord", stats: bool = False):
+        """Full step that writes the record the reverse sweep needs
+        (continuous deposit mode only)."""
+        st = FsStats() if stats else None
+        rc = self.lib.fs_step_record(self.h, self.sp, C.byref(self.f), int(step), C.byref(rec),
+                                     C.byref(st) if st is not None else None, self.stream)
         self._check(rc)
         return st.as_dict() if st is not None else None
 

@@ -30,11 +30,32 @@ def test_library_exports_every_declared_symbol():
         assert n in names
 
 
+def header_arity():
+    """Number of parameters of every fs_* function declared in the header."""
+    txt = open(os.path.join(ROOT, "include", "fshybrid.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(fs_[a-z_0-9]+)\s*\(([^;{]*?)\)\s*;", txt, flags=re.S):
+        args = m.group(2).strip()
+        out[m.group(1)] = 0 if args in ("", "void") else args.count(",") + 1
+    return out
+
+
+def test_binding_argument_counts_match_header():
+    lib = F.library()
+    ar = header_arity()
+    assert len(ar) >= 20
+    for name, n in ar.items():
+        assert len(getattr(lib, name).argtypes) == n, name
+
+
 def test_struct_sizes_match_header():
     # sizes of the C structs as laid out by the compiler for the ABI
     assert C.sizeof(F.FsConfig) == 18 * 8 + 8 + 16 * 4
     assert C.sizeof(F.FsParticles) == 5 * 8 + 2 * 8 + 2 * 4
     assert C.sizeof(F.FsFields) == 5 * 8
+    assert C.sizeof(F.FsRecord) == 3 * 8
+    assert C.sizeof(F.FsAdjoint) == 9 * 8
 
 
 @pytest.mark.parametrize("name", ["cfg1", "cfg2", "cfg3", "cfg4", "cfg5"])
