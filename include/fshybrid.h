@@ -253,7 +253,9 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
 
 /* Reverse of step `step` (n -> n+1, run by fs_step_record with record
  * *rec).  sp_n / f_n: particles (buf[cur], tile_count[cur]) and fields (B,
- * gather grid) before the step; sp_n1 / f_n1: particles and B after it.
+ * gather grid) before the step; sp_n1 / f_n1: particles, B and the moment
+ * grids after it (f_n1->mom as the recorded step left them, or NULL to
+ * deposit them again).
  * *lam holds on entry the adjoints after the step (particles, lB, lE of
  * B^{n+1} and E^{n+1}) and on exit those before it (B^n, E^n).  grads
  * (device, 2 + n_modes doubles) accumulates dL/du_sh and dL/dalpha_cr. */
@@ -263,7 +265,8 @@ int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n
 
 /* Reverse of fs_init_plasma: E^0 = Ohm(B^0, moments of the initial load),
  * the initial velocities (v_x = u_sh + sigma n) and the Fourier modes of
- * B^0.  Adds to dL/du_sh, dL/dalpha_cr and grads[1 + m] = dL/dA_m. */
+ * B^0 (f0->mom: moments of the initial load, or NULL to deposit them).
+ * Adds to dL/du_sh, dL/dalpha_cr and grads[1 + m] = dL/dA_m. */
 int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, fs_adjoint* lam, double* grads,
                     hipStream_t s);
 

@@ -30,41 +30,34 @@ from . import fshybrid as F
 
 
 class _State:
-    """A saved particle/field state: the live buffer and tile counts of each
-    species, B, E, the gather grid and the id counter."""
+    """One particle/field state held in tensors of its own: per species the
+    particle buffer and its tile counts, B, E, the gather grid, the moment
+    grids and the id counter.  Either a copy of a simulation's current state
+    (checkpoints) or an empty slot a recorded step writes into directly."""
 
-    def __init__(self, sim: F.Simulation, nsp: int):
-        self.buf, self.cnt, self.count = [], [], []
+    def __init__(self, sim: F.Simulation, nsp: int, copy: bool = True):
+        def take(t):
+            return t.clone() if copy else torch.empty_like(t)
+        self.buf, self.cnt = [], []
         for k in range(nsp):
             cur = int(sim.sp[k].cur)
-            self.buf.append(sim.bufs[k][cur].clone())
-            self.cnt.append(sim.cnts[k][cur].clone())
-            self.count.append(sim.counts[k].clone())
-        self.B = sim.B.clone()
-        self.E = sim.E.clone()
-        self.gather = sim.gather.clone()
-        self.next_id = sim.next_id
-
-    def restore(self, sim: F.Simulation):
-        for k in range(len(self.buf)):
-            cur = int(sim.sp[k].cur)
-            sim.bufs[k][cur].copy_(self.buf[k])
-            sim.cnts[k][cur].copy_(self.cnt[k])
-            sim.counts[k].copy_(self.count[k])
-        sim.B.copy_(self.B)
-        sim.E.copy_(self.E)
-        sim.gather.copy_(self.gather)
-        sim.set_clock(self.next_id)
+            self.buf.append(take(sim.bufs[k][cur]))
+            self.cnt.append(take(sim.cnts[k][cur]))
+        self.B = take(sim.B)
+        self.E = take(sim.E)
+        self.gather = take(sim.gather)
+        self.mom = [take(m) for m in sim.mom[:nsp]]
+        self.next_id = sim.next_id if copy else -1
 
     def particles(self, sim: F.Simulation):
-        """fs_particles structs pointing at the saved buffers."""
+        """fs_particles structs pointing at this state's buffers."""
         sp = (F.FsParticles * 2)()
         for k in range(2):
             kk = min(k, len(self.buf) - 1)
             P = sp[k]
             P.buf[0] = P.buf[1] = self.buf[kk].data_ptr()
             P.tile_count[0] = P.tile_count[1] = self.cnt[kk].data_ptr()
-            P.count = self.count[kk].data_ptr()
+            P.count = sim.counts[kk].data_ptr()
             P.capacity = int(sim.L.capacity[k])
             P.tile_cap = int(sim.L.tile_cap[k])
             P.cur = 0
@@ -74,8 +67,26 @@ class _State:
     def fields(self, sim: F.Simulation) -> F.FsFields:
         f = F.FsFields()
         f.B, f.E, f.gather = self.B.data_ptr(), self.E.data_ptr(), self.gather.data_ptr()
-        f.mom[0], f.mom[1] = sim.mom[0].data_ptr(), sim.mom[1].data_ptr()
+        f.mom[0] = self.mom[0].data_ptr()
+        f.mom[1] = self.mom[1].data_ptr() if len(self.mom) > 1 else None
         return f
+
+
+def _recorded_step(sim: F.Simulation, n: int, a: _State, b: _State, rec: F.FsRecord):
+    """Step n from state a into state b without copying particles: the
+    step reads a's buffers and writes b's (the field update works in place,
+    so B and the gather grid of a are first copied into b)."""
+    b.B.copy_(a.B)
+    b.gather.copy_(a.gather)
+    b.E.copy_(a.E)
+    sp = a.particles(sim)
+    for k in range(len(a.buf)):
+        sp[k].buf[1] = b.buf[k].data_ptr()
+        sp[k].tile_count[1] = b.cnt[k].data_ptr()
+    f = b.fields(sim)
+    rc = sim.lib.fs_step_record(sim.h, sp, C.byref(f), int(n), C.byref(rec), None, sim.stream)
+    sim._check(rc)
+    b.next_id = sim.next_id
 
 
 class AdjointRun:
@@ -154,17 +165,18 @@ class AdjointRun:
         grads = torch.zeros(2 + int(self.p["n_modes"]), dtype=torch.float64, device=self.device)
         gptr = C.c_void_p(grads.data_ptr())
         refl = [torch.zeros(self.lam.nid, dtype=torch.uint8, device=self.device) for _ in range(self.K)]
+        slots = [_State(sim, self.nsp, copy=False) for _ in range(self.K)]
         for s0 in sorted(self.checkpoints, reverse=True):
             s1 = min(s0 + self.K, self.nsteps)
-            self.checkpoints[s0].restore(sim)
-            tape, recs = [], []
+            ck = self.checkpoints[s0]
+            sim.set_clock(ck.next_id)
+            tape, recs = [ck], []
             for j, n in enumerate(range(s0, s1)):
-                tape.append(_State(sim, self.nsp))
                 rec = F.FsRecord()
                 rec.refl, rec.nid = refl[j].data_ptr(), self.lam.nid
-                sim.step_record(n, rec)
+                _recorded_step(sim, n, tape[j], slots[j], rec)
+                tape.append(slots[j])
                 recs.append(rec)
-            tape.append(_State(sim, self.nsp))
             for j in range(s1 - s0 - 1, -1, -1):
                 a, b = tape[j], tape[j + 1]
                 f_n, f_n1 = a.fields(sim), b.fields(sim)

@@ -140,21 +140,36 @@ __device__ __forceinline__ void block_add(double v, double* out) {
 }
 
 // ---------------------------------------------------------------------------
-// Particle passes
+// Particle passes.  A tile's ions may be spread over `split` workgroups
+// (consecutive blocks), each taking a contiguous share of the bin, so that
+// few large tiles still fill the chip.
 // ---------------------------------------------------------------------------
+struct TileShare {
+    int tile, begin, end;
+};
+__device__ __forceinline__ TileShare tile_share(const int32_t* cnt, int ntiles, int64_t cap, int split) {
+    TileShare t;
+    t.tile = blockIdx.x / split;
+    const int part = blockIdx.x % split;
+    const int n = min(cnt[t.tile] + cnt[ntiles + t.tile], (int)cap);
+    const int chunk = (n + split - 1) / split;
+    t.begin = min(n, part * chunk);
+    t.end = min(n, t.begin + chunk);
+    return t;
+}
 
 // Deposit transpose over the live particles of one buffer (the state at
 // n+1): lam(x) += sum_nodes dW/dx (lam_R + lam_G . v), lam(v) += sum W lam_G,
 // added to the adjoints of the ions' ids.
 template <typename R, int D, int S>
 __global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
-                                                     const double* __restrict__ lM, PLam<R> lam) {
+                                                     const double* __restrict__ lM, PLam<R> lam, int split) {
     constexpr int N = Stencil<S>::N;
     constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
-    const int tile = blockIdx.x;
+    const TileShare ts = tile_share(cnt, G.ntiles, cap, split);
+    const int tile = ts.tile;
     const int lo = cnt[tile];
-    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = ts.begin + threadIdx.x; i < ts.end; i += blockDim.x) {
         const long src = bin_slot(tile, cap, lo, i);
         const int32_t pc = in.cell[src];
         const int cx = cell_x(pc, G), cy = D >= 2 ? cell_y(pc, G) : 0, cz = D >= 3 ? cell_z(pc, G) : 0;
@@ -266,13 +281,14 @@ template <typename R, int D, int S>
 __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
                                                   const R* __restrict__ gather, const uint8_t* __restrict__ refl_of,
                                                   PLam<R> lam, double* __restrict__ lEB, long nnode, uint64_t step,
-                                                  double* grads) {
+                                                  double* grads, int split) {
     using X = Extent<D, S>;
     using T = TileShape<D>;
     constexpr int LO = Stencil<S>::LO, N = Stencil<S>::N;
     constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
     __shared__ double sl[6 * X::GN];
-    const int tile = blockIdx.x;
+    const TileShare ts = tile_share(cnt, G.ntiles, cap, split);
+    const int tile = ts.tile;
     const int tx = tile % G.ntx;
     const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
     const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
@@ -280,12 +296,11 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
     for (int l = threadIdx.x; l < 6 * X::GN; l += blockDim.x) sl[l] = 0.0;
     __syncthreads();
     const int lo = cnt[tile];
-    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
     const R hR = (R)(0.5 * G.dt);
     const R dtdxR = (R)G.dtdx;
     const double hD = 0.5 * G.dt, dtdx = G.dtdx;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = ts.begin + threadIdx.x; i < ts.end; i += blockDim.x) {
         const long src = bin_slot(tile, cap, lo, i);
         const int64_t id = in.id[src];
         if (id >= lam.nid) continue;
@@ -634,11 +649,37 @@ __global__ __launch_bounds__(256) void k_fluid_adj(FieldGeo F, const double* __r
     block_add(acc, grads);
 }
 
-// out = a x + b y (b y skipped when y is null).
-__global__ void k_axpby(double* __restrict__ out, double a, const double* __restrict__ x, double b,
-                        const double* __restrict__ y, long n) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
-        out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+// The vector updates of the SSP-RK3 transpose (Shu-Osher form
+// B1 = B0 + h F(B0), B2 = 3/4 B0 + 1/4 (B1 + h F(B1)),
+// B3 = 1/3 B0 + 2/3 (B2 + h F(B2))), one pass each.
+// stage 3: l0 = lam/3, l2 = 2 lam/3, lF = 2 h lam/3
+__global__ void k_rk_adj3(double* __restrict__ l0, double* __restrict__ l2, double* __restrict__ lF,
+                          const double* __restrict__ lam, double h, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double v = lam[i];
+        l0[i] = v * (1.0 / 3.0);
+        l2[i] = v * (2.0 / 3.0);
+        lF[i] = v * (2.0 / 3.0) * h;
+    }
+}
+// stage 2: l0 += 3/4 l2, l1 = l2/4, lF = h l2/4
+__global__ void k_rk_adj2(double* __restrict__ l0, double* __restrict__ l1, double* __restrict__ lF,
+                          const double* __restrict__ l2, double h, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double v = l2[i];
+        l0[i] += 0.75 * v;
+        l1[i] = 0.25 * v;
+        lF[i] = 0.25 * h * v;
+    }
+}
+// stage 1: l0 += l1, lF = h l1
+__global__ void k_rk_adj1(double* __restrict__ l0, double* __restrict__ lF, const double* __restrict__ l1, double h,
+                          long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double v = l1[i];
+        l0[i] += v;
+        lF[i] = h * v;
+    }
 }
 
 // Amplitude adjoints of the initial modes: dB_y = A cos(k_m x + phi_m),

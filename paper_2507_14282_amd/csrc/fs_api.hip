@@ -68,6 +68,10 @@ int hip_check(fs_handle* h, hipError_t e, const char* what) {
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
+// Workgroups per tile for the per-particle passes that may split a bin: about
+// 2048 slots each, at most 16.
+int split_of(int64_t tile_cap) { return (int)std::max<int64_t>(1, std::min<int64_t>(16, tile_cap / 2048)); }
+
 int bits_for(int64_t n) {
     int b = 1;
     while ((int64_t(1) << b) < n) ++b;
@@ -287,8 +291,9 @@ void deposit_continuous(fs_handle* h, const fs_particles* sp, double* const mom[
         PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
         zero_u64(reinterpret_cast<unsigned long long*>(mom[k]), 4 * h->L.ndep, s);
         allow_lds(k_deposit_c<R, D, S>, lds);
-        k_deposit_c<R, D, S><<<(unsigned)h->L.ntiles, 256, lds, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap, mom[k],
-                                                                    h->ctr);
+        const int sp_ = split_of(P.tile_cap);
+        k_deposit_c<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, lds, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
+                                                                            mom[k], h->ctr, sp_);
     }
 }
 
@@ -488,13 +493,17 @@ template <typename R> PLam<R> plam(const fs_adjoint* a, int D) {
     return L;
 }
 
-void axpby(double* out, double a, const double* x, double b, const double* y, long n, hipStream_t s) {
-    k_axpby<<<grid_for(n), 256, 0, s>>>(out, a, x, b, y, n);
-}
-
-// Moments and fluid state of a particle state, into the reverse scratch.
-template <typename R, int D, int S> void fluid_of(fs_handle* h, const fs_particles* sp, hipStream_t s) {
-    deposit_continuous<R, D, S>(h, sp, h->amom, s);
+// Moments and fluid state of a particle state, into the reverse scratch:
+// the moments are copied from `mom` (the caller's grids of that state) when
+// given, otherwise deposited again.
+template <typename R, int D, int S>
+void fluid_of(fs_handle* h, const fs_particles* sp, int64_t* const* mom, hipStream_t s) {
+    if (mom && mom[0] && (!h->has_cr || mom[1])) {
+        for (int k = 0; k < (h->has_cr ? 2 : 1); ++k)
+            (void)hipMemcpyAsync(h->amom[k], mom[k], 4 * h->L.ndep * sizeof(double), hipMemcpyDeviceToDevice, s);
+    } else {
+        deposit_continuous<R, D, S>(h, sp, h->amom, s);
+    }
     const dim3 blk(kFX, kFY, 1);
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
     k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(h->amom[0]),
@@ -530,19 +539,15 @@ template <int D> void rk3_adj(fs_handle* h, const double* Bn, double* lB, hipStr
         double* B0 = Bs + (size_t)sub * N;
         stage_launch<D>(h, B0, B0, h->B1, h->afl, 0.0, 1.0, hs, s);
         stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
+        const unsigned g = grid_for(N);
         // B3 = 1/3 B0 + 2/3 (B2 + h F(B2))
-        axpby(l0, 1.0 / 3.0, lB, 0.0, nullptr, N, s);
-        axpby(l2, 2.0 / 3.0, lB, 0.0, nullptr, N, s);
-        axpby(lF, 2.0 / 3.0 * hs, lB, 0.0, nullptr, N, s);
+        k_rk_adj3<<<g, 256, 0, s>>>(l0, l2, lF, lB, hs, N);
         rhs_adj<D>(h, h->B2, lF, l2, s);
         // B2 = 3/4 B0 + 1/4 (B1 + h F(B1))
-        axpby(l0, 1.0, l0, 0.75, l2, N, s);
-        axpby(l1, 0.25, l2, 0.0, nullptr, N, s);
-        axpby(lF, 0.25 * hs, l2, 0.0, nullptr, N, s);
+        k_rk_adj2<<<g, 256, 0, s>>>(l0, l1, lF, l2, hs, N);
         rhs_adj<D>(h, h->B1, lF, l1, s);
         // B1 = B0 + h F(B0)
-        axpby(l0, 1.0, l0, 1.0, l1, N, s);
-        axpby(lF, hs, l1, 0.0, nullptr, N, s);
+        k_rk_adj1<<<g, 256, 0, s>>>(l0, lF, l1, hs, N);
         rhs_adj<D>(h, B0, lF, l0, s);
         (void)hipMemcpyAsync(lB, l0, N * sizeof(double), hipMemcpyDeviceToDevice, s);
     }
@@ -560,8 +565,9 @@ void moments_adj(fs_handle* h, const fs_particles* sp, const fs_adjoint* lam, do
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         const fs_particles& P = sp[k];
         PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
-        k_deposit_adj<R, D, S><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
-                                                                     h->alM[k], plam<R>(lam, D));
+        const int sp_ = split_of(P.tile_cap);
+        k_deposit_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
+                                                                             h->alM[k], plam<R>(lam, D), sp_);
     }
 }
 
@@ -571,7 +577,7 @@ int adjoint_step_impl(fs_handle* h, const fs_particles* sp_n, const fs_fields* f
                       hipStream_t s) {
     const long nn = h->L.nnode, nc = h->L.ncent;
     // fluid state the step's field update used: moments of the particles after it
-    fluid_of<R, D, S>(h, sp_n1, s);
+    fluid_of<R, D, S>(h, sp_n1, f_n1->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
     // final Ohm, then the RK3 update
     k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, f_n1->B, h->afl, lam->lE, lam->lE + 3 * nn, lam->lB, h->alfl, nn, nc);
@@ -590,9 +596,10 @@ int adjoint_step_impl(fs_handle* h, const fs_particles* sp_n, const fs_fields* f
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         const fs_particles& P = sp_n[k];
         PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
-        k_push_adj<R, D, S><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
-                                                                  static_cast<const R*>(f_n->gather), rec->refl,
-                                                                  plam<R>(lam, D), lam->lE, nn, (uint64_t)step, grads);
+        const int sp_ = split_of(P.tile_cap);
+        k_push_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
+            h->G, in, P.tile_count[P.cur], P.tile_cap, static_cast<const R*>(f_n->gather), rec->refl, plam<R>(lam, D),
+            lam->lE, nn, (uint64_t)step, grads, sp_);
     }
     return hip_check(h, hipGetLastError(), "adjoint step launch");
 }
@@ -601,7 +608,7 @@ template <typename R, int D, int S>
 int adjoint_init_impl(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, fs_adjoint* lam, double* grads,
                       hipStream_t s) {
     const long nn = h->L.nnode, nc = h->L.ncent;
-    fluid_of<R, D, S>(h, sp0, s);
+    fluid_of<R, D, S>(h, sp0, f0->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
     k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, f0->B, h->afl, lam->lE, lam->lE + 3 * nn, lam->lB, h->alfl, nn, nc);
     moments_adj<R, D, S>(h, sp0, lam, grads, s);

@@ -619,13 +619,15 @@ __device__ __forceinline__ void deposit_particle_c(double* lds, int bx0, int by0
 
 template <typename R, int D, int S>
 __global__ __launch_bounds__(256) void k_deposit_c(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
-                                                   double* __restrict__ mom, unsigned long long* __restrict__ ctr) {
+                                                   double* __restrict__ mom, unsigned long long* __restrict__ ctr,
+                                                   int split) {
     using X = Extent<D, S>;
     using T = TileShape<D>;
     constexpr int LO = Stencil<S>::LO;
     extern __shared__ __align__(16) unsigned char smem[];
     double* sd = reinterpret_cast<double*>(smem);
-    const int tile = xcd_tile(blockIdx.x, G.ntiles);
+    // a tile's ions may be spread over `split` consecutive workgroups
+    const int tile = blockIdx.x / split, part = blockIdx.x % split;
     const int tx = tile % G.ntx;
     const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
     const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
@@ -634,8 +636,9 @@ __global__ __launch_bounds__(256) void k_deposit_c(Geo G, PBuf<R> in, const int3
     __syncthreads();
     const int lo = cnt[tile];
     const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
+    const int chunk = (n + split - 1) / split, i0 = min(n, part * chunk), i1 = min(n, i0 + chunk);
     int oor = 0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
         long src = bin_slot(tile, cap, lo, i);
         int32_t pc = in.cell[src];
         R o[3] = {0, 0, 0}, v[3];
