@@ -108,6 +108,44 @@ def write_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, command)
     print(json.dumps(d))
 
 
+def adjoint_timing(steps=400, K=20):
+    """Forward and checkpointed reverse pass of the 1D adjoint workload
+    (2048 cells, dx = 0.5, 256 ppc plus CRs, 64 seeded Fourier modes, FP32
+    particles): wall time of each pass, and their ratio (the reverse pass
+    includes re-running every K-step segment from its checkpoint)."""
+    import numpy as np
+    import torch
+    from paper_2507_14282_amd import adjoint as A
+    from paper_2507_14282_amd import workloads as W
+    p = W.preset("cfg5")
+    amps = np.full(p["n_modes"], p["mode_amp"])
+    warm = A.AdjointRun(p, K, K=K)
+    warm.forward(p["u_sh"], p["alpha_cr"], amps)
+    warm.backward()
+    del warm
+    run = A.AdjointRun(p, steps, K=K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = run.forward(p["u_sh"], p["alpha_cr"], amps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g = run.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {
+        "workload": f"1D3V adjoint box {p['nx']} cells dx={p['dx']} d_i, {p['ppc']} ppc + CRs "
+                    f"(n_cr={p['n_cr']}), {p['n_modes']} Fourier modes, {steps} steps, checkpoint every {K}",
+        "loss": "precursor sum(By^2+Bz^2) over x in [L/2, L]",
+        "params": "u_sh, alpha_cr, 64 amplitudes",
+        "dtype": "f32 particles / f64 fields",
+        "fwd_ms_per_step": (t1 - t0) / steps * 1e3,
+        "adj_ms_per_step": (t2 - t1) / steps * 1e3,
+        "adjoint_over_forward": (t2 - t1) / (t1 - t0),
+        "loss_value": loss,
+        "grad_u_sh": float(g[0]), "grad_alpha_cr": float(g[1]), "grad_amps_norm": float(np.linalg.norm(g[2:])),
+    }
+
+
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -150,6 +188,8 @@ def main():
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/push3d_traffic.json from four rocprofv3 counter directories")
     ap.add_argument("--traffic-command", default="", help="command line recorded with --write-traffic")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
+    ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint/forward measurement")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
@@ -167,6 +207,10 @@ def main():
     import torch
     from paper_2507_14282_amd import fshybrid as F
     from paper_2507_14282_amd import workloads as W
+
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_timing()}))
+        return 0
 
     p = W.preset(args.workload)
     sim = F.Simulation(p, "cuda:0")
@@ -225,6 +269,10 @@ def main():
         },
         "final_step_flags": st["flags"],
     }
+    if not args.no_adjoint:
+        del sim
+        torch.cuda.empty_cache()
+        out["adjoint"] = adjoint_timing()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out))
