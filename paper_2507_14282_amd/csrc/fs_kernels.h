@@ -446,6 +446,7 @@ __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int3
     int ncross = *xl.count;
     if (ncross > xl.cap) ncross = (int)xl.cap;
     int status = 0, oor = 0;
+    int n_inc = 0, n_trans = 0, n_refl = 0, n_esc = 0;   // summed per wave at the end
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ncross; i += gridDim.x * blockDim.x) {
         uint32_t pid = xl.id[i];
         double v[3] = {xl.v[i], xl.v[xl.cap + i], xl.v[2 * xl.cap + i]};
@@ -458,21 +459,19 @@ __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int3
             back = xl.delta[i];
             refl = 1;
         }
-        atomicAdd(ctr + C_INC, 1ull);
+        ++n_inc;
         if (!refl) {
-            atomicAdd(ctr + C_TRANS, 1ull);
-            atomicAdd(ctr + (species == 0 ? C_REM0 : C_REM1), 1ull);
+            ++n_trans;
             continue;
         }
-        atomicAdd(ctr + C_REFL, 1ull);
+        ++n_refl;
         double xi = (double)G.nx - back;
         double fl = floor(xi);
         int cx = (int)fl;
         double ox = xi - fl;
         if (cx >= G.nx) { cx = G.nx - 1; ox = 1.0; }
         if (cx < 0) {
-            atomicAdd(ctr + C_ESC, 1ull);
-            atomicAdd(ctr + (species == 0 ? C_REM0 : C_REM1), 1ull);
+            ++n_esc;
             continue;
         }
         R o[3] = {to_offset<R>(ox), (R)xl.oy[i], (R)xl.oz[i]};
@@ -490,6 +489,11 @@ __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int3
         if (refl_rec != nullptr) refl_rec[pid] = 1;   // step record: this ion was reflected
         if constexpr (DEP) status |= deposit_particle<R, D, S>(nullptr, 0, 0, 0, mom, G, cx, cy, cz, o, vr, oor);
     }
+    wave_add(ctr + C_INC, n_inc);
+    wave_add(ctr + C_TRANS, n_trans);
+    wave_add(ctr + C_REFL, n_refl);
+    wave_add(ctr + C_ESC, n_esc);
+    wave_add(ctr + (species == 0 ? C_REM0 : C_REM1), n_trans + n_esc);
     if (status & F_SAT) atomicAdd(ctr + C_SAT, 1ull);
     if (oor) atomicAdd(ctr + C_OOR, 1ull);
     if (status) atomicOr(reinterpret_cast<unsigned int*>(ctr + C_FLAGS), (unsigned int)status);
@@ -507,6 +511,12 @@ __global__ __launch_bounds__(256) void k_inject(Geo G, PBuf<R> out0, int32_t* cn
                                                 int64_t cnt_th, int64_t cnt_cr, int64_t ntr) {
     const int64_t nth = cnt_th * ntr, ncr = cnt_cr * ntr;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // per-wave totals of the step counters (one atomic per wave, not per ion)
+    const int is_th = g < nth, is_cr = g >= nth && g < nth + ncr;
+    wave_add(ctr + C_ADD0, is_th);
+    wave_add(ctr + C_INJ_TH, is_th);
+    wave_add(ctr + C_ADD1, is_cr);
+    wave_add(ctr + C_INJ_CR, is_cr);
     if (g >= nth + ncr) return;
     int status = 0, oor = 0;
     const bool cr = g >= nth;
@@ -553,8 +563,6 @@ __global__ __launch_bounds__(256) void k_inject(Geo G, PBuf<R> out0, int32_t* cn
     unsigned long long* mom = cr ? mom1 : mom0;
     int dest = tile_of<D>(cx, cy, cz, G);
     long dst = bin_push_top(cnt, G.ntiles, dest, cap);
-    atomicAdd(ctr + (cr ? C_ADD1 : C_ADD0), 1ull);
-    atomicAdd(ctr + (cr ? C_INJ_CR : C_INJ_TH), 1ull);
     if (dst < 0) {
         atomicOr(reinterpret_cast<unsigned int*>(ctr + C_FLAGS), (unsigned int)F_TILE);
         return;
