@@ -989,3 +989,53 @@ void ora_diag(const ora_sim* s, double* out)
 }
 
 int ora_record(ora_sim* s, int32_t on) { s->recording = on; s->nev = 0; return 0; }
+
+/* ------------------------------------------------------------------ */
+/* sampled evaluation (checks of large runs one particle / node at a   */
+/* time)                                                                */
+/* ------------------------------------------------------------------ */
+/* Gather, Boris and move (readings R3, R4: the push of push_species,
+ * without boundaries) of n given particles in given node fields E3, Bb3
+ * (nnode x 3, interleaved). */
+int ora_push_sample(const ora_cfg* cfg, const double* E3, const double* Bb3, int64_t n, const int64_t* cell3,
+                    const double* off3, const double* v3, int64_t* cell_out3, double* off_out3, double* v_out3)
+{
+    if (cfg->dim < 1 || cfg->dim > 3 || (cfg->shape != 1 && cfg->shape != 2)) return -1;
+    ora_sim s;
+    memset(&s, 0, sizeof(s));
+    s.c = *cfg;
+    s.nyc = cfg->dim >= 2 ? cfg->ny : 1;
+    s.nzc = cfg->dim >= 3 ? cfg->nz : 1;
+    s.nxn = cfg->xbc == ORA_XBC_PERIODIC ? cfg->nx : cfg->nx + 1;
+    s.E = (double*)E3;
+    s.Bb = (double*)Bb3;
+    s.sp[0].n = n;
+    s.sp[0].cap = n;
+    s.sp[0].c = cell_out3;
+    s.sp[0].o = off_out3;
+    s.sp[0].v = v_out3;
+    memcpy(cell_out3, cell3, (size_t)(3 * n) * sizeof(int64_t));
+    memcpy(off_out3, off3, (size_t)(3 * n) * sizeof(double));
+    memcpy(v_out3, v3, (size_t)(3 * n) * sizeof(double));
+    push_species(&s, 0);
+    return 0;
+}
+
+/* Ohm's law (reading R5) at n given nodes (node3: i, j, k) from centre
+ * field B3 (ncent x 3, interleaved) and the fixed-point moments of both
+ * species (ndep x 4; M1 may be NULL without CRs): E and Bbar (n x 3). */
+int ora_ohm_sample(const ora_cfg* cfg, const double* B3, const int64_t* M0, const int64_t* M1, int64_t n,
+                   const int64_t* node3, double* E_out3, double* Bb_out3)
+{
+    ora_sim* s = ora_new(cfg);
+    if (!s) return -1;
+    ora_set_B(s, B3);
+    ora_set_moments(s, 0, M0);
+    if (M1) ora_set_moments(s, 1, M1);
+    fluid_from_moments(s);
+    for (int64_t q = 0; q < n; ++q)
+        ohm_node(s, s->B, node3[3 * q], node3[3 * q + 1], node3[3 * q + 2], &E_out3[3 * q], &Bb_out3[3 * q]);
+    ora_free(s);
+    return 0;
+}
+

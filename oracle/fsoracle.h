@@ -81,6 +81,15 @@ void     ora_philox(const uint64_t ctr[4], uint64_t k0, uint64_t k1, uint64_t ou
 int      ora_inject_counts(const ora_cfg* cfg, int64_t step, int64_t* out2);
 int      ora_record(ora_sim* s, int32_t on);
 
+/* Sampled evaluation for large runs: the push (gather, Boris, move; no
+ * boundaries) of given particles in given node fields (E3, Bb3: nnode x 3),
+ * and Ohm's law at given nodes (node3: i, j, k) from B (ncent x 3) and the
+ * fixed-point moments (M1 may be NULL). */
+int      ora_push_sample(const ora_cfg* cfg, const double* E3, const double* Bb3, int64_t n, const int64_t* cell3,
+                         const double* off3, const double* v3, int64_t* cell_out3, double* off_out3, double* v_out3);
+int      ora_ohm_sample(const ora_cfg* cfg, const double* B3, const int64_t* M0, const int64_t* M1, int64_t n,
+                        const int64_t* node3, double* E_out3, double* Bb_out3);
+
 /* Reverse mode (fsoracle_adj.c): loss = sum over centres i >= nx/2 of
  * By^2 + Bz^2 after nsteps continuous-deposit steps, and its gradient
  * grad[0] = d/du_sh, grad[1] = d/dalpha_cr, grad[1+m] = d/dA_m (m = 1..n_modes),

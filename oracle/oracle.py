@@ -122,6 +122,8 @@ def lib():
         L.ora_inject_counts.argtypes = [C.POINTER(OraCfg), i64, vp]
         L.ora_record.argtypes = [vp, i32]
         pc = C.POINTER(OraCfg)
+        L.ora_push_sample.argtypes = [pc, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        L.ora_ohm_sample.argtypes = [pc, vp, vp, vp, i64, vp, vp, vp]
         L.ora_adjoint.restype = C.c_int
         L.ora_adjoint.argtypes = [pc, vp, i64, vp, vp]
         L.ora_adj_boris.argtypes = [vp, vp, vp, dp, vp, vp, vp, vp, vp]
@@ -367,4 +369,36 @@ def adj_rk3(p: dict, B, fn, fg, lam_out):
     lfn, lfg = np.zeros_like(fn), np.zeros_like(fg)
     lib().ora_adj_rk3(C.byref(cfg), _p(B), _p(fn), _p(fg), _p(Bo), _p(lB), _p(lfn), _p(lfg))
     return Bo, lB, lfn, lfg
+
+
+# --- sampled evaluation -------------------------------------------------------
+def push_sample(p: dict, E3, Bb3, cell3, off3, v3):
+    """Gather + Boris + move of given particles (no boundaries) in given
+    node fields (nnode x 3 each); returns (cell3, off3, v3) after the push."""
+    cfg = make_cfg(p)
+    E3, Bb3 = (np.ascontiguousarray(x, dtype=np.float64) for x in (E3, Bb3))
+    cell3 = np.ascontiguousarray(cell3, dtype=np.int64)
+    off3, v3 = (np.ascontiguousarray(x, dtype=np.float64) for x in (off3, v3))
+    n = len(cell3)
+    co, oo, vo = np.zeros((n, 3), dtype=np.int64), np.zeros((n, 3)), np.zeros((n, 3))
+    rc = lib().ora_push_sample(C.byref(cfg), _p(E3), _p(Bb3), n, _p(cell3), _p(off3), _p(v3), _p(co), _p(oo), _p(vo))
+    if rc:
+        raise ValueError("oracle rejected the configuration")
+    return co, oo, vo
+
+
+def ohm_sample(p: dict, B3, M0, M1, nodes3):
+    """E and Bbar at given nodes from B (ncent x 3) and fixed-point moments."""
+    cfg = make_cfg(p)
+    B3 = np.ascontiguousarray(B3, dtype=np.float64)
+    M0 = np.ascontiguousarray(M0, dtype=np.int64)
+    M1 = None if M1 is None else np.ascontiguousarray(M1, dtype=np.int64)
+    nodes3 = np.ascontiguousarray(nodes3, dtype=np.int64)
+    n = len(nodes3)
+    E, Bb = np.zeros((n, 3)), np.zeros((n, 3))
+    rc = lib().ora_ohm_sample(C.byref(cfg), _p(B3), _p(M0), _p(M1) if M1 is not None else None, n, _p(nodes3),
+                              _p(E), _p(Bb))
+    if rc:
+        raise ValueError("oracle rejected the configuration")
+    return E, Bb
 

@@ -327,6 +327,31 @@ class Simulation:
                                                    off.ctypes.data, v.ctypes.data, ids.ctypes.data, self.stream))
         return dict(cell=cell, off=off, v=v, id=ids)
 
+    def sections(self, species: int = 0, which: int | None = None) -> dict:
+        """Views of one particle buffer's sections (the layout fshybrid.h
+        documents: cell, off[dim], v[3], id, each on a 256-byte boundary):
+        cell and id as int32, off and v in the particle precision."""
+        cur = int(self.sp[species].cur) if which is None else int(which)
+        buf = self.bufs[species][cur]
+        cap = int(self.L.capacity[species])
+        rb = 8 if self.real == torch.float64 else 4
+        dim = int(self.p["dim"])
+        out, pos = {}, 0
+
+        def take(nbytes, dtype):
+            nonlocal pos
+            t = buf[pos:pos + nbytes].view(dtype)
+            pos += (nbytes + 255) // 256 * 256
+            return t
+
+        out["cell"] = take(cap * 4, torch.int32)
+        out["off"] = [take(cap * rb, self.real) for _ in range(dim)]
+        out["v"] = [take(cap * rb, self.real) for _ in range(3)]
+        out["id"] = take(cap * 4, torch.int32)
+        out["counts"] = self.cnts[species][cur]
+        out["tile_cap"] = int(self.L.tile_cap[species])
+        return out
+
     def count(self, species: int = 0) -> int:
         return int(self.counts[species].item())
 

@@ -1,0 +1,171 @@
+"""Parity at the full benchmark sizes, in the launch configuration the
+benchmark times (FP32 particles, fixed-point moments, FP64 fields).
+
+At these sizes the oracle cannot run the whole box, so the checks are
+  * sampled: the ions of a few interior tiles are pushed one by one by the
+    oracle (gather, Boris, move) in the GPU's own gather grid, promoted to
+    FP64, and compared with where the GPU step put them (matched by id);
+    Ohm's law at sampled nodes is evaluated by the oracle from the GPU's B
+    and moment grids and compared with the GPU's E;
+  * exact properties of the whole box: the fixed-point charge and first
+    moment of the deposit of each species (sum of R over all nodes = N 2^sw,
+    sum of G = 2^sw times the sum of the ions' velocity codes, as integers,
+    with 2^sw the fixed-point weight of one ion) and div B at round-off.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2507_14282_amd import fshybrid as F
+from paper_2507_14282_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def live_slots(sec, tiles):
+    """Global slots of the live ions of the given tiles."""
+    cnt = sec["counts"].cpu().numpy()
+    cap = sec["tile_cap"]
+    nt = len(cnt) // 2
+    out = []
+    for t in tiles:
+        lo, hi = int(cnt[t]), int(cnt[nt + t])
+        out.append(t * cap + np.arange(lo))
+        out.append(t * cap + cap - hi + np.arange(hi))
+    return np.concatenate(out)
+
+
+def read_ions(sim, sec, slots):
+    dim = int(sim.p["dim"])
+    idx = torch.as_tensor(slots, device=sim.device)
+    L = sim.L
+    cell = sec["cell"][idx].cpu().numpy().astype(np.int64)
+    bx, by = int(L.cell_bits[0]), int(L.cell_bits[1])
+    c3 = np.zeros((len(slots), 3), dtype=np.int64)
+    c3[:, 0] = cell & ((1 << bx) - 1)
+    if dim >= 2:
+        c3[:, 1] = (cell >> bx) & ((1 << by) - 1)
+    if dim >= 3:
+        c3[:, 2] = cell >> (bx + by)
+    off = np.zeros((len(slots), 3))
+    for d in range(dim):
+        off[:, d] = sec["off"][d][idx].double().cpu().numpy()
+    v = np.stack([sec["v"][c][idx].double().cpu().numpy() for c in range(3)], axis=1)
+    ids = sec["id"][idx].cpu().numpy().view(np.uint32).astype(np.int64)
+    return c3, off, v, ids
+
+
+def tile_coords(L, t):
+    ntx, nty = int(L.ntile[0]), int(L.ntile[1])
+    return t % ntx, (t // ntx) % nty, t // (ntx * nty)
+
+
+def neighbours(L, t, dim):
+    ntx, nty, ntz = (int(x) for x in L.ntile)
+    tx, ty, tz = tile_coords(L, t)
+    out = []
+    for dz in ((-1, 0, 1) if dim >= 3 else (0,)):
+        for dy in ((-1, 0, 1) if dim >= 2 else (0,)):
+            for dx in (-1, 0, 1):
+                x, y, z = tx + dx, (ty + dy) % nty, (tz + dz) % ntz
+                if 0 <= x < ntx:
+                    out.append(x + ntx * (y + nty * z))
+    return sorted(set(out))
+
+
+def live_mask(sec, L):
+    cnt = sec["counts"].to(torch.int64)
+    nt = int(L.ntiles)
+    cap = sec["tile_cap"]
+    j = torch.arange(cap, device=cnt.device)[None, :]
+    return ((j < cnt[:nt, None]) | (j >= cap - cnt[nt:, None])).reshape(-1)
+
+
+@pytest.mark.parametrize("name", ["cfg4", "cfg3", "cfg2"])
+def test_full_size_step_sampled_parity(name):
+    p = W.preset(name)
+    dim = int(p["dim"])
+    print(f"full-size {name}: dim {dim}, {p['nx']}x{p['ny']}x{p['nz']}, ppc {p['ppc']}", flush=True)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    for s in range(2):
+        sim.step(s, stats=False)
+    torch.cuda.synchronize()
+    L = sim.L
+    rng = np.random.default_rng(7)
+    ntx = int(L.ntile[0])
+    tiles = []
+    while len(tiles) < 4:
+        t = int(rng.integers(int(L.ntiles)))
+        if 2 <= tile_coords(L, t)[0] <= ntx - 3 and t not in tiles:
+            tiles.append(t)
+    sec0 = sim.sections(0)
+    slots = live_slots(sec0, tiles)
+    if len(slots) > 20000:
+        slots = rng.choice(slots, 20000, replace=False)
+    c0, o0, v0, id0 = read_ions(sim, sec0, slots)
+    g = sim.gather.double().cpu().numpy()
+    E3, Bb3 = np.ascontiguousarray(g[:, 0:3]), np.ascontiguousarray(g[:, 4:7])
+    del g
+    st = sim.step(2)
+    assert st["flags"] == 0 and st["saturated"] == 0 and st["out_of_range"] == 0, st
+    torch.cuda.synchronize()
+
+    # --- sampled push against the oracle -------------------------------------
+    sec1 = sim.sections(0)
+    near = sorted({u for t in tiles for u in neighbours(L, t, dim)})
+    c1, o1, v1, id1 = read_ions(sim, sec1, live_slots(sec1, near))
+    where = {int(i): k for k, i in enumerate(id1)}
+    ce, oe, ve = O.push_sample(p, E3, Bb3, c0, o0, v0)
+    got = np.array([where.get(int(i), -1) for i in id0])
+    assert np.all(got >= 0), "a sampled interior ion went missing"
+    cg, og, vg = c1[got], o1[got], v1[got]
+    vt = np.max(np.abs(ve))
+    assert np.max(np.abs(vg - ve)) <= 1e-5 * vt, np.max(np.abs(vg - ve)) / vt
+    wrap = np.array([int(p["nx"]), int(p["ny"]) if dim >= 2 else 1, int(p["nz"]) if dim >= 3 else 1])
+    for d in range(dim):
+        # positions in cells (cell + FP32 offset): compare the continuous x, so a
+        # cell index that differs only across a boundary is not an error
+        xg, xe = cg[:, d] + og[:, d], ce[:, d] + oe[:, d]
+        dx = np.abs(((xg - xe) + wrap[d] / 2) % wrap[d] - wrap[d] / 2)
+        assert np.max(dx) <= 1e-5, (d, np.max(dx))
+    print(f"  sampled push: {len(id0)} ions, max |dv|/|v| = {np.max(np.abs(vg - ve)) / vt:.2e}", flush=True)
+
+    # --- exact deposit identities over the whole box --------------------------
+    # every ion's integer weights sum to 2^sw over its stencil (sw = D b for
+    # CIC, D (2b + 1) for TSC), so sum R = N 2^sw and sum G = 2^sw sum v_q
+    sw = int(L.sw_bits)
+    sv = int(L.sv_bits)
+    vmax = (1 << 23) - 1
+    for spc in range(2 if sim.has_cr else 1):
+        sec = sim.sections(spc)
+        mask = live_mask(sec, L)
+        n_live = int(mask.sum().item())
+        assert n_live == sim.count(spc)
+        M = sim.mom[spc]
+        assert int(M[:, 0].sum().item()) == n_live << sw, spc
+        for c in range(3):
+            vq = torch.round(sec["v"][c].float() * float(1 << sv)).clamp(-vmax, vmax).to(torch.int64)
+            qsum = int(vq[mask].sum().item())
+            msum = int(M[:, 1 + c].sum().item()) % (1 << 64)
+            assert msum == (qsum << sw) % (1 << 64), (spc, c)
+            del vq
+        del mask
+
+    # --- sampled Ohm's law and div B --------------------------------------------
+    nn = int(L.nnode)
+    k = np.stack([rng.integers(0, int(L.nxn), 400), rng.integers(0, int(L.nyc), 400),
+                  rng.integers(0, int(L.nzc), 400)], axis=1)
+    k[:4, 0] = [0, 1, int(p["nx"]) - 1, int(p["nx"])]
+    n_idx = k[:, 0] + int(L.nxn) * (k[:, 1] + int(L.nyc) * k[:, 2])
+    Eg = sim.E.cpu().numpy()[:, n_idx].T
+    B3 = np.ascontiguousarray(sim.B.cpu().numpy().T)
+    M0 = sim.mom[0].cpu().numpy()
+    M1 = sim.mom[1].cpu().numpy() if sim.has_cr else None
+    Ee, _ = O.ohm_sample(p, B3, M0, M1, k)
+    assert np.max(np.abs(Eg - Ee)) <= 1e-12 * np.max(np.abs(Ee)), np.max(np.abs(Eg - Ee))
+    d = sim.diagnostics()
+    assert d["max_divB"] < 1e-12
+    print(f"  sampled Ohm: {len(k)} nodes of {nn}, max |dE| = {np.max(np.abs(Eg - Ee)):.2e}", flush=True)
