@@ -64,6 +64,29 @@ def copy_calibration():
     print("copied 3 x 1 GiB", flush=True)
 
 
+def copy_bandwidth():
+    """Achieved HBM bandwidth of a plain 2 GiB device-to-device copy (read +
+    write bytes over the event-timed duration), the practical ceiling a
+    streaming kernel can reach on this GPU."""
+    import torch
+    n = 512 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def _counter(dirname, counter, name_part):
     """Per-dispatch values of one counter for kernels whose name contains
     `name_part`, from a rocprofv3 --output-format csv directory."""
@@ -237,6 +260,9 @@ def main():
     alg = push_bytes(np_avg, sim.L)
     achieved = alg / (push_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(kernel_source_hash())
+    del sim
+    torch.cuda.empty_cache()
+    copy_gbs = copy_bandwidth()
     out = {
         "metric": "ion particle-updates/sec (push+deposit+FS wall) 3D at 1 GPU; adjoint/fwd time",
         "value": value,
@@ -266,12 +292,11 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_push<float,3,CIC,deposit>", "alg_bytes_per_launch": alg,
             "avg_launch_ms": push_ms,
+            "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
         },
         "final_step_flags": st["flags"],
     }
     if not args.no_adjoint:
-        del sim
-        torch.cuda.empty_cache()
         out["adjoint"] = adjoint_timing()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)

@@ -8,6 +8,9 @@
 #ifndef DEP_HALO
 #define DEP_HALO 1
 #endif
+#ifndef DEP_HALO_T
+#define DEP_HALO_T 0
+#endif
 #ifndef PUSH_THREADS
 #define PUSH_THREADS 512
 #endif
@@ -26,7 +29,7 @@ constexpr double kTwoPi = 6.283185307179586;
 template <int D> struct TileShape;
 template <> struct TileShape<1> { static constexpr int X = 32, Y = 1, Z = 1; };
 template <> struct TileShape<2> { static constexpr int X = 16, Y = 8, Z = 1; };
-template <> struct TileShape<3> { static constexpr int X = 8, Y = 8, Z = 4; };
+template <> struct TileShape<3> { static constexpr int X = 16, Y = 8, Z = 4; };
 
 // Shape-function stencil relative to the particle's cell c: CIC touches
 // nodes c, c+1; TSC touches the nearest node and its neighbours, i.e. some
@@ -36,14 +39,19 @@ template <> struct Stencil<1> { static constexpr int LO = 0, HI = 1, N = 2; };
 template <> struct Stencil<2> { static constexpr int LO = 1, HI = 2, N = 3; };
 
 // LDS extents of one tile: GX.. for the gather grid (the tile's cells plus
-// the stencil), DX.. for the deposit accumulators (one extra cell of halo on
-// each side so ions that left the tile by one cell still deposit in LDS).
+// the stencil), DX.. for the deposit accumulators (HX, HY, HZ extra cells of
+// halo on each side, so ions that left the tile by that much still deposit in
+// LDS; the rest deposit straight into the global grid).  The flow is along x,
+// so in 3D only x gets a halo: transverse crossers are rare, and the smaller
+// box leaves room in LDS for three 512-thread workgroups per CU.
 template <int D, int S> struct Extent {
     static constexpr int TX = TileShape<D>::X, TY = TileShape<D>::Y, TZ = TileShape<D>::Z;
     static constexpr int W = Stencil<S>::LO + Stencil<S>::HI;
-    static constexpr int H = DEP_HALO;   // halo cells of the deposit box on each side
+    static constexpr int HX = DEP_HALO;
+    static constexpr int HY = D >= 3 ? DEP_HALO_T : (D >= 2 ? DEP_HALO : 0);
+    static constexpr int HZ = D >= 3 ? DEP_HALO_T : 0;
     static constexpr int GX = TX + W, GY = D >= 2 ? TY + W : 1, GZ = D >= 3 ? TZ + W : 1;
-    static constexpr int DX = TX + 2 * H + W, DY = D >= 2 ? TY + 2 * H + W : 1, DZ = D >= 3 ? TZ + 2 * H + W : 1;
+    static constexpr int DX = TX + 2 * HX + W, DY = D >= 2 ? TY + 2 * HY + W : 1, DZ = D >= 3 ? TZ + 2 * HZ + W : 1;
     static constexpr int GN = GX * GY * GZ, DN = DX * DY * DZ;
 };
 

@@ -269,7 +269,7 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(Geo G, PBuf<R> in, PBuf<R
     const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
     const int x0 = tx * T::X, y0 = ty * T::Y, z0 = tz * T::Z;
     const int gx0 = x0 - LO, gy0 = D >= 2 ? y0 - LO : 0, gz0 = D >= 3 ? z0 - LO : 0;
-    const int dx0 = x0 - X::H - LO, dy0 = D >= 2 ? y0 - X::H - LO : 0, dz0 = D >= 3 ? z0 - X::H - LO : 0;
+    const int dx0 = x0 - X::HX - LO, dy0 = D >= 2 ? y0 - X::HY - LO : 0, dz0 = D >= 3 ? z0 - X::HZ - LO : 0;
 
     for (int l = threadIdx.x; l < X::GN; l += blockDim.x) {
         int lx = l % X::GX, ly = (l / X::GX) % X::GY, lz = l / (X::GX * X::GY);
@@ -639,7 +639,7 @@ __global__ __launch_bounds__(256) void k_deposit_c(Geo G, PBuf<R> in, const int3
     const int tx = tile % G.ntx;
     const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
     const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
-    const int dx0 = tx * T::X - X::H - LO, dy0 = D >= 2 ? ty * T::Y - X::H - LO : 0, dz0 = D >= 3 ? tz * T::Z - X::H - LO : 0;
+    const int dx0 = tx * T::X - X::HX - LO, dy0 = D >= 2 ? ty * T::Y - X::HY - LO : 0, dz0 = D >= 3 ? tz * T::Z - X::HZ - LO : 0;
     for (int l = threadIdx.x; l < X::DN * 4; l += blockDim.x) sd[l] = 0.0;
     __syncthreads();
     const int lo = cnt[tile];
@@ -684,7 +684,7 @@ __global__ __launch_bounds__(256) void k_deposit(Geo G, PBuf<R> in, const int32_
     const int tx = tile % G.ntx;
     const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
     const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
-    const int dx0 = tx * T::X - X::H - LO, dy0 = D >= 2 ? ty * T::Y - X::H - LO : 0, dz0 = D >= 3 ? tz * T::Z - X::H - LO : 0;
+    const int dx0 = tx * T::X - X::HX - LO, dy0 = D >= 2 ? ty * T::Y - X::HY - LO : 0, dz0 = D >= 3 ? tz * T::Z - X::HZ - LO : 0;
     for (int l = threadIdx.x; l < X::DN * 4; l += blockDim.x) sd[l] = 0ull;
     __syncthreads();
     const int lo = cnt[tile];
