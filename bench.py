@@ -131,6 +131,49 @@ def write_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, command)
     print(json.dumps(d))
 
 
+# Peak LDS atomic rate used as the roofline of the deposit: 32 banks of 4 B
+# per CU, so at most 16 lanes of 64-bit atomics per clock per CU, over 256
+# CUs at 2.4 GHz.
+LDS_U64_ATOMIC_PEAK = 16 * 256 * 2.4e9
+ATOMIC_COUNTERS = ("SQ_INSTS_LDS_ATOMIC", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_ADDR_CONFLICT",
+                   "SQ_WAVES", "TCC_ATOMIC_sum", "TA_FLAT_ATOMIC_WAVEFRONTS_sum")
+
+
+def write_atomics(pmc_dir, command):
+    """Atomic counts per launch of the fused 3D push kernel from one rocprofv3
+    --pmc run of ATOMIC_COUNTERS: LDS atomic wave-instructions (the deposit
+    into the tile box), LDS bank / address conflict cycles, and L2 atomic
+    requests (the flush of the box into the global moment grid and the
+    deposits of ions outside the box)."""
+    kern = "k_push<float, 3, 1, true>"
+    d = {"kernel": kern, "workload": "cfg4 3D box 1024x192x192, 8 ppc", "counters": {}}
+    for c in ATOMIC_COUNTERS:
+        v = _counter(pmc_dir, c.replace("_sum", "") if c.endswith("_sum") else c, kern)
+        if not v:
+            v = _counter(pmc_dir, c, kern)
+        if not v:
+            raise SystemExit(f"missing counter {c}")
+        d["counters"][c] = {"per_dispatch": sum(v) / len(v), "dispatches": len(v)}
+    d["kernel_source_sha256"] = kernel_source_hash()
+    d["command"] = command
+    path = os.path.join(ROOT, "profiles", "push3d_atomics.json")
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1)
+    print(json.dumps(d))
+
+
+def atomics_from_profiles(kernel_hash):
+    path = os.path.join(ROOT, "profiles", "push3d_atomics.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256") != kernel_hash:
+        return None
+    return {k: v["per_dispatch"] for k, v in d["counters"].items()}
+
+
 def adjoint_timing(steps=400, K=20):
     """Forward and checkpointed reverse pass of the 1D adjoint workload
     (2048 cells, dx = 0.5, 256 ppc plus CRs, 64 seeded Fourier modes, FP32
@@ -211,6 +254,8 @@ def main():
     ap.add_argument("--write-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/push3d_traffic.json from four rocprofv3 counter directories")
     ap.add_argument("--traffic-command", default="", help="command line recorded with --write-traffic")
+    ap.add_argument("--write-atomics", metavar="PMC_DIR",
+                    help="write profiles/push3d_atomics.json from a rocprofv3 run of the atomic counters")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
     ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint/forward measurement")
     args = ap.parse_args()
@@ -219,6 +264,9 @@ def main():
         return 0
     if args.write_traffic:
         write_traffic(*args.write_traffic, command=args.traffic_command)
+        return 0
+    if args.write_atomics:
+        write_atomics(args.write_atomics, command=args.traffic_command)
         return 0
     if args.gpus != 1:
         msg = (f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -260,6 +308,23 @@ def main():
     alg = push_bytes(np_avg, sim.L)
     achieved = alg / (push_ms * 1e-3) / 1e9
     traffic = traffic_from_profiles(kernel_source_hash())
+    pmc = atomics_from_profiles(kernel_source_hash())
+    # LDS atomics of the deposit: 8 CIC corners x 4 moments per ion
+    lds_ops = 32.0 * np_avg
+    atomics = {
+        "lds_u64_lane_ops_per_launch": lds_ops,
+        "lds_rate": lds_ops / (push_ms * 1e-3), "lds_peak": LDS_U64_ATOMIC_PEAK, "unit": "lane-ops/s",
+        "lds_frac": lds_ops / (push_ms * 1e-3) / LDS_U64_ATOMIC_PEAK,
+        "pmc": None,
+    }
+    if pmc:
+        atomics["pmc"] = {
+            "lds_atomic_wave_instructions": pmc["SQ_INSTS_LDS_ATOMIC"],
+            "lds_bank_conflict_cycles": pmc["SQ_LDS_BANK_CONFLICT"],
+            "lds_addr_conflict_cycles": pmc["SQ_LDS_ADDR_CONFLICT"],
+            "l2_atomic_requests": pmc["TCC_ATOMIC_sum"],
+            "l2_atomic_rate": pmc["TCC_ATOMIC_sum"] / (push_ms * 1e-3),
+        }
     del sim
     torch.cuda.empty_cache()
     copy_gbs = copy_bandwidth()
@@ -294,6 +359,7 @@ def main():
             "avg_launch_ms": push_ms,
             "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
         },
+        "atomics": atomics,
         "final_step_flags": st["flags"],
     }
     if not args.no_adjoint:

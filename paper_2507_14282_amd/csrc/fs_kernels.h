@@ -112,6 +112,38 @@ __device__ __forceinline__ void deposit_one(unsigned long long* lds, int bx0, in
     bool in_lds = lds != nullptr && lx >= 0 && lx + N <= X::DX;
     if constexpr (D >= 2) in_lds = in_lds && ly >= 0 && ly + N <= X::DY;
     if constexpr (D >= 3) in_lds = in_lds && lz >= 0 && lz + N <= X::DZ;
+    if constexpr (N == 2) {
+        if (in_lds) {
+            // CIC: each lane walks the corners of its cell in an order set by
+            // its lane bits (corner k is visited as k xor f), so two lanes in
+            // the same cell update different nodes in the same instruction
+            // instead of serialising on one address.
+            const int lane = __lane_id();
+            const int fa = lane & 1, fb = D >= 2 ? (lane >> 1) & 1 : 0, fc = D >= 3 ? (lane >> 2) & 1 : 0;
+            const int ux[2] = {fa ? wx[1] : wx[0], fa ? wx[0] : wx[1]};
+            const int uy[2] = {fb ? wy[1] : wy[0], fb ? wy[0] : wy[1]};
+            const int uz[2] = {fc ? wz[1] : wz[0], fc ? wz[0] : wz[1]};
+            const int sx = fa ? -1 : 1, sy = fb ? -X::DX : X::DX, sz = fc ? -X::DX * X::DY : X::DX * X::DY;
+            const int base = ((lz + fc) * X::DY + (ly + fb)) * X::DX + (lx + fa);
+#pragma unroll
+            for (int c = 0; c < NZ; ++c) {
+#pragma unroll
+                for (int b = 0; b < NY; ++b) {
+                    const int wyz = D >= 3 ? __umul24(uy[b], uz[c]) : (D >= 2 ? uy[b] : 1);
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        const int W = D >= 2 ? __umul24(ux[a], wyz) : ux[a];
+                        unsigned long long* p = lds + (base + a * sx + b * sy + c * sz);
+                        atomicAdd(p, (unsigned long long)W);
+                        atomicAdd(p + X::DN, (unsigned long long)mul24(W, vq[0]));
+                        atomicAdd(p + 2 * X::DN, (unsigned long long)mul24(W, vq[1]));
+                        atomicAdd(p + 3 * X::DN, (unsigned long long)mul24(W, vq[2]));
+                    }
+                }
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int c = 0; c < NZ; ++c) {
 #pragma unroll
