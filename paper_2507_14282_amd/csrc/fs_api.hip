@@ -140,6 +140,12 @@ int compute_layout(const fs_config* c, fs_layout_info* L, std::string& err) {
     L->cell_bits[1] = c->dim >= 2 ? bits_for(c->ny) : 0;
     L->cell_bits[2] = c->dim >= 3 ? bits_for(c->nz) : 0;
     if (L->cell_bits[0] + L->cell_bits[1] + L->cell_bits[2] > 31) { err = "grid too large for a packed int32 cell"; return FS_EINVAL; }
+    // device index arithmetic uses 24-bit products and 32-bit node indices
+    if (L->ndx >= (1 << 24) || L->nyc * L->nzc >= (1 << 24) || L->ndep >= INT32_MAX ||
+        L->ntile[0] >= (1 << 24) || (int64_t)L->ntile[1] * L->ntile[2] >= (1 << 24)) {
+        err = "grid too large for 32-bit node indices";
+        return FS_EINVAL;
+    }
     const int64_t cells = (int64_t)t[0] * t[1] * t[2];
     const int rb = c->precision == 64 ? 8 : 4;
     L->real_bytes = rb;

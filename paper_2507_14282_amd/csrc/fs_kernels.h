@@ -65,12 +65,13 @@ __device__ __forceinline__ int32_t pack_cell(int x, int y, int z, const Geo& G) 
     return x | (y << G.bx) | (z << (G.bx + G.by));
 }
 
+// Tile of a (wrapped, non-negative) cell.
 template <int D> __device__ __forceinline__ int tile_of(int x, int y, int z, const Geo& G) {
     using T = TileShape<D>;
-    int t = x / T::X;
-    if constexpr (D >= 2) t += G.ntx * (y / T::Y);
-    if constexpr (D >= 3) t += G.ntx * G.nty * (z / T::Z);
-    return t;
+    unsigned r = 0;
+    if constexpr (D >= 3) r = (unsigned)z / T::Z;
+    if constexpr (D >= 2) r = (unsigned)y / T::Y + __umul24(G.nty, r);
+    return (int)((unsigned)x / T::X + __umul24(G.ntx, r));
 }
 
 // Global deposit-grid index of node (i, j, k) (unwrapped), or -1 if it lies
@@ -83,7 +84,9 @@ __device__ __forceinline__ long dep_index(int i, int j, int k, const Geo& G) {
     }
     j = wrapi(j, G.nyc);
     k = wrapi(k, G.nzc);
-    return (long)i + (long)G.ndx * ((long)j + (long)G.nyc * k);
+    // the layout keeps ndx and nyc*nzc below 2^24 and the grid below 2^31
+    // nodes, so the index is exact in 24-bit products
+    return (long)(i + (int)__umul24(G.ndx, j + (int)__umul24(G.nyc, k)));
 }
 
 // Field-node index for a gather: x clamped to the physical nodes in the box,
@@ -93,7 +96,7 @@ __device__ __forceinline__ long gather_index(int i, int j, int k, const Geo& G) 
     else { i = i < 0 ? 0 : i; i = i > G.nx ? G.nx : i; }
     j = wrapi(j, G.nyc);
     k = wrapi(k, G.nzc);
-    return (long)i + (long)G.nxn * ((long)j + (long)G.nyc * k);
+    return (long)(i + (int)__umul24(G.nxn, j + (int)__umul24(G.nyc, k)));
 }
 
 // Adds one particle's fixed-point moments at (unwrapped) cell (cx, cy, cz)
