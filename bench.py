@@ -27,6 +27,59 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def push_bytes_dim(n_ions, L, dim, nsp):
+    """Algorithmic HBM bytes of one step's push launches in FP32: every ion's
+    state read and written once (int32 cell, D fp32 offsets, 3 fp32
+    velocities, uint32 id), and per species launch the gather grid read once
+    (24 B per node) and the int64 moments written once (32 B per node)."""
+    return n_ions * 2 * (20 + 4 * dim) + nsp * (int(L.nnode) * 24 + int(L.ndep) * 32)
+
+
+def workload_throughput(name, steps, warmup):
+    """Whole-step and push+deposit throughput of one preset, with the push
+    roofline as for the 3D box (used for the 1D and 2D boxes)."""
+    import torch
+    from paper_2507_14282_amd import fshybrid as F
+    from paper_2507_14282_amd import workloads as W
+    p = W.preset(name)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    for s in range(warmup):
+        sim.step(s, stats=False)
+    torch.cuda.synchronize()
+    nsp = 2 if sim.has_cr else 1
+    count = lambda: sum(sim.count(k) for k in range(nsp))
+    n0 = count()
+    sim.timing(True)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        sim.step(warmup + k, stats=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, nrec = sim.timing_read()
+    n1 = count()
+    st = sim.step(warmup + steps, stats=True)
+    nav = 0.5 * (n0 + n1)
+    push_ms = ms[0] / max(nrec[0], 1)
+    dim = int(p["dim"])
+    alg = push_bytes_dim(nav, sim.L, dim, nsp)
+    ach = alg / (push_ms * 1e-3) / 1e9
+    out = {
+        "workload": f"{dim}D3V FP32 {p['nx']}x{p['ny']}x{p['nz']} cells dx={p['dx']} d_i, {p['ppc']} ppc"
+                    + (f" + CRs n_cr={p['n_cr']:g}" if sim.has_cr else "") + f", {p['shape']}, M_A={p['u_sh']:g}",
+        "ions": int(nav), "steps": steps, "warmup": warmup,
+        "ms_per_step": (t1 - t0) / steps * 1e3,
+        "pu_per_s": nav * steps / (t1 - t0),
+        "push_deposit_ms": push_ms,
+        "field_ms": ms[3] / max(nrec[3], 1),
+        "push_alg_bytes_per_step": alg, "push_GBs": ach, "push_frac_of_hbm_peak": ach / HBM_PEAK_GBS,
+        "final_step_flags": st["flags"],
+    }
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def push_bytes(np_live, L):
     """Algorithmic HBM bytes of one launch of the fused push kernel: the ion
     state read and written once (int32 cell, 3 fp32 offsets, 3 fp32
@@ -257,6 +310,7 @@ def main():
     ap.add_argument("--write-atomics", metavar="PMC_DIR",
                     help="write profiles/push3d_atomics.json from a rocprofv3 run of the atomic counters")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
+    ap.add_argument("--no-other", action="store_true", help="skip the 1D and 2D workload lines")
     ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint/forward measurement")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -362,6 +416,9 @@ def main():
         "atomics": atomics,
         "final_step_flags": st["flags"],
     }
+    if not args.no_other:
+        out["other_workloads"] = {"1D cfg2": workload_throughput("cfg2", 100, 10),
+                                  "2D cfg3": workload_throughput("cfg3", 50, 10)}
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
     if not args.no_cpu_baseline:

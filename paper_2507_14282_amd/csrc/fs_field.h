@@ -23,6 +23,13 @@ struct FieldGeo {
     int cont;                     // moments hold FP64 sums (continuous deposit)
 };
 
+// Linear index i + sx (j + sy k) of a wrapped grid point.  The layout keeps
+// sx and sy * nzc below 2^24 and every grid below 2^31 points, so 24-bit
+// products are exact.
+__device__ __forceinline__ long lin(int i, int j, int k, int sx, int sy) {
+    return (long)(i + (int)__umul24(sx, j + (int)__umul24(sy, k)));
+}
+
 // B component c at centre (i, j, k), ghost rules in x, periodic in y/z.
 __device__ __forceinline__ double centre_B(const double* __restrict__ B, const FieldGeo& F, long nc,
                                            int i, int j, int k, int c) {
@@ -31,7 +38,7 @@ __device__ __forceinline__ double centre_B(const double* __restrict__ B, const F
     if (F.xbc == 1) i = wrapi(i, F.nx);
     else if (i < 0) return F.B0[c];
     else if (i >= F.nx) i = F.nx - 1;
-    return B[(long)c * nc + i + (long)F.nx * (j + (long)F.nyc * k)];
+    return B[(long)c * nc + lin(i, j, k, F.nx, F.nyc)];
 }
 
 // Launch shape of the field kernels: 64 x 4 threads over (x, y), one z per
@@ -47,32 +54,36 @@ __global__ __launch_bounds__(256) void k_fluid(FieldGeo F, const long long* __re
     int i = blockIdx.x * kFX + threadIdx.x;
     const int j = blockIdx.y * kFY + threadIdx.y, k = blockIdx.z;
     if (i >= F.nxn || j >= F.nyc) return;
-    const long n = i + (long)F.nxn * (j + (long)F.nyc * k);
+    const long n = lin(i, j, k, F.nxn, F.nyc);
     if (F.xbc == 0) {
         if (i < F.mclamp) i = F.mclamp;
         if (i > F.nx - F.mclamp) i = F.nx - F.mclamp;
     }
-    const long dn = (long)(i + F.g) + (long)F.ndx * (j + (long)F.nyc * k);
+    const long dn = lin(i + F.g, j, k, F.ndx, F.nyc);
+    // one node's four moments are 32 contiguous bytes: two 16-byte loads
     double dens, G[3];
     if (F.cont) {
-        const double* d0 = reinterpret_cast<const double*>(m0);
-        const double* d1 = reinterpret_cast<const double*>(m1);
-        dens = F.wth * d0[4 * dn];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) G[c] = F.wth * d0[4 * dn + 1 + c];
+        const double2* d0 = reinterpret_cast<const double2*>(m0) + 2 * dn;
+        const double2 a = d0[0], b = d0[1];
+        dens = F.wth * a.x;
+        G[0] = F.wth * a.y; G[1] = F.wth * b.x; G[2] = F.wth * b.y;
         if (F.has_cr) {
-            dens += F.wcr * d1[4 * dn];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) G[c] += F.wcr * d1[4 * dn + 1 + c];
+            const double2* d1 = reinterpret_cast<const double2*>(m1) + 2 * dn;
+            const double2 c = d1[0], d = d1[1];
+            dens += F.wcr * c.x;
+            G[0] += F.wcr * c.y; G[1] += F.wcr * d.x; G[2] += F.wcr * d.y;
         }
     } else {
-        dens = F.wth * ((double)m0[4 * dn] * F.scR);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) G[c] = F.wth * ((double)m0[4 * dn + 1 + c] * F.scG);
+        const longlong2* q0 = reinterpret_cast<const longlong2*>(m0) + 2 * dn;
+        const longlong2 a = q0[0], b = q0[1];
+        dens = F.wth * ((double)a.x * F.scR);
+        G[0] = F.wth * ((double)a.y * F.scG); G[1] = F.wth * ((double)b.x * F.scG); G[2] = F.wth * ((double)b.y * F.scG);
         if (F.has_cr) {
-            dens += F.wcr * ((double)m1[4 * dn] * F.scR);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) G[c] += F.wcr * ((double)m1[4 * dn + 1 + c] * F.scG);
+            const longlong2* q1 = reinterpret_cast<const longlong2*>(m1) + 2 * dn;
+            const longlong2 c = q1[0], d = q1[1];
+            dens += F.wcr * ((double)c.x * F.scR);
+            G[0] += F.wcr * ((double)c.y * F.scG); G[1] += F.wcr * ((double)d.x * F.scG);
+            G[2] += F.wcr * ((double)d.y * F.scG);
         }
     }
     double ne = fmax(dens, F.n_floor);
@@ -88,7 +99,7 @@ __device__ __forceinline__ long fnode(const FieldGeo& F, int i, int j, int k) {
     else { i = i < 0 ? 0 : i; i = i > F.nx ? F.nx : i; }
     j = wrapi(j, F.nyc);
     k = wrapi(k, F.nzc);
-    return (long)i + (long)F.nxn * (j + (long)F.nyc * k);
+    return lin(i, j, k, F.nxn, F.nyc);
 }
 
 // Block shape (cells) of the tiled field kernels, and the LDS tiles one
@@ -132,7 +143,7 @@ __device__ __forceinline__ void stage_tiles(const FieldGeo& F, const double* __r
             if (i < 0) {
                 vb[it][0] = F.B0[0]; vb[it][1] = F.B0[1]; vb[it][2] = F.B0[2];
             } else {
-                const long q = i + (long)F.nx * (j + (long)F.nyc * k);
+                const long q = lin(i, j, k, F.nx, F.nyc);
                 vb[it][0] = B[q]; vb[it][1] = B[ncent + q]; vb[it][2] = B[2 * ncent + q];
             }
         }
@@ -147,7 +158,7 @@ __device__ __forceinline__ void stage_tiles(const FieldGeo& F, const double* __r
             const int j = D >= 2 ? wrapi(y0 - 1 + ly, F.nyc) : 0, k = D >= 3 ? wrapi(z0 - 1 + lz, F.nzc) : 0;
             if (F.xbc == 1) i = wrapi(i, F.nx);
             else i = i < 0 ? 0 : (i > F.nx ? F.nx : i);
-            vp[it] = pe[i + (long)F.nxn * (j + (long)F.nyc * k)];
+            vp[it] = pe[lin(i, j, k, F.nxn, F.nyc)];
         }
     }
 #pragma unroll
@@ -296,7 +307,7 @@ __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restric
     const int tx = t % FB::X, ty = (t / FB::X) % FB::Y, tz = t / (FB::X * FB::Y);
     const int i = x0 + tx, j = y0 + ty, k = z0 + tz;
     if (i >= F.nxn || j >= F.nyc || k >= F.nzc) return;
-    const long n = i + (long)F.nxn * (j + (long)F.nyc * k);
+    const long n = lin(i, j, k, F.nxn, F.nyc);
     double e[3], bb[3];
     ohm_tile<D>(F, sB, sP, fl, nnode, n, tx, ty, tz, e, bb);
 #pragma unroll
@@ -330,7 +341,7 @@ __global__ __launch_bounds__(256) void k_stage(FieldGeo F, const double* __restr
         // nodes past the box are read only by centres that do not exist
         if (F.xbc == 1 || i <= F.nx) {
             if (F.xbc == 1) i = wrapi(i, F.nx);
-            const long n = i + (long)F.nxn * (j + (long)F.nyc * k);
+            const long n = lin(i, j, k, F.nxn, F.nyc);
             ohm_tile<D>(F, sB, sP, fl, nnode, n, lx, ly, lz, e, bb);
         }
         sE[0][l] = e[0]; sE[1][l] = e[1]; sE[2][l] = e[2];
@@ -372,7 +383,7 @@ __global__ __launch_bounds__(256) void k_stage(FieldGeo F, const double* __restr
         for (int d = 0; d < 3; ++d) dEz[d] = dEz[d] * 0.25 * F.rdx;
     }
     const double rhs[3] = {-(dEy[2] - dEz[1]), -(dEz[0] - dEx[2]), -(dEx[1] - dEy[0])};
-    const long n = i + (long)F.nx * (j + (long)F.nyc * k);
+    const long n = lin(i, j, k, F.nx, F.nyc);
     const int lc = (tx + 1) + T::CX * ((ty + T::OY) + T::CY * (tz + T::OZ));
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -429,7 +440,7 @@ __device__ __forceinline__ void zm_fetch_B(const FieldGeo& F, const double* __re
             if (i < 0) {
                 r.b[it][0] = F.B0[0]; r.b[it][1] = F.B0[1]; r.b[it][2] = F.B0[2];
             } else {
-                const long q = i + (long)F.nx * (j + (long)F.nyc * k);
+                const long q = lin(i, j, k, F.nx, F.nyc);
                 r.b[it][0] = B[q]; r.b[it][1] = B[ncent + q]; r.b[it][2] = B[2 * ncent + q];
             }
         }
@@ -449,7 +460,7 @@ __device__ __forceinline__ void zm_fetch_P(const FieldGeo& F, const double* __re
             const int j = wrapi(y0 - 1 + l / Z::PX, F.nyc);
             if (F.xbc == 1) i = wrapi(i, F.nx);
             else i = i < 0 ? 0 : (i > F.nx ? F.nx : i);
-            r.p[it] = pe[i + (long)F.nxn * (j + (long)F.nyc * k)];
+            r.p[it] = pe[lin(i, j, k, F.nxn, F.nyc)];
         }
     }
 }
@@ -485,7 +496,7 @@ __device__ __forceinline__ void zm_fetch_fluid(const FieldGeo& F, const double* 
     f.ne = 1.0; f.G[0] = f.G[1] = f.G[2] = 0.0; f.n = 0;
     if (!f.ok) return;
     if (F.xbc == 1) i = wrapi(i, F.nx);
-    f.n = i + (long)F.nxn * (wrapi(y0 + ly, F.nyc) + (long)F.nyc * wrapi(k, F.nzc));
+    f.n = lin(i, wrapi(y0 + ly, F.nyc), wrapi(k, F.nzc), F.nxn, F.nyc);
     f.ne = fl[f.n];
     f.G[0] = fl[2 * nnode + f.n]; f.G[1] = fl[3 * nnode + f.n]; f.G[2] = fl[4 * nnode + f.n];
 }
@@ -577,7 +588,7 @@ __global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __rest
         zm_fetch_P(F, pe, x0, y0, k + 2, pl);
         fetch_fluid(k + 1);
         double bn[3] = {0, 0, 0};
-        const long q = ci + (long)F.nx * (cj + (long)F.nyc * k);
+        const long q = lin(ci, cj, k, F.nx, F.nyc);
         if (own && c0 != 0.0) { bn[0] = Bn[q]; bn[1] = Bn[ncent + q]; bn[2] = Bn[2 * ncent + q]; }
         zm_store_B(pl, sB[r & 1]);
         zm_store_P(pl, sP[r % 3]);
