@@ -290,15 +290,50 @@ def cpu_baseline(params, seconds):
         el = time.perf_counter() - t0
         if done >= 2 and el >= seconds:
             break
-    return {"value": pu / el, "unit": "particle-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 oracle, whole steps, 64x48x48 slab at 8 ppc ({n} ions), {done} steps, {el:.1f} s"}
+    out = {"value": pu / el, "unit": "particle-updates/s", "cores": 1, "kind": "oracle",
+           "sample": f"FP64 oracle, whole steps, 64x48x48 slab at 8 ppc ({n} ions), {done} steps, {el:.1f} s",
+           "host": {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "threads_used": 1}}
+    from paper_2507_14282_amd import workloads as W
+    # context: the 1D FP64 parity box, and the oracle's own forward/adjoint
+    # pair on the 1D adjoint workload (10 steps each)
+    o = O.Oracle(W.preset("cfg1"))
+    o.init()
+    done, pu, t0 = 0, 0, time.perf_counter()
+    while time.perf_counter() - t0 < 0.3 * seconds:
+        pu += o.count(0)
+        o.step()
+        done += 1
+    el = time.perf_counter() - t0
+    p5 = W.preset("cfg5")
+    t0 = time.perf_counter()
+    O.forward_loss(p5, 10)
+    t1 = time.perf_counter()
+    O.adjoint(p5, 10)
+    t2 = time.perf_counter()
+    out["other"] = {
+        "1D FP64 box 512 cells, 64 ppc": {"value": pu / el, "unit": "particle-updates/s", "steps": done},
+        "adjoint workload, 10 steps": {"forward_s": t1 - t0, "forward_plus_adjoint_s": t2 - t1,
+                                       "reverse_over_forward": (t2 - t1) / (t1 - t0) - 1.0},
+    }
+    return out
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="cfg4")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
