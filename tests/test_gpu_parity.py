@@ -254,7 +254,7 @@ def test_full_step_fp32_one_step(dim):
         mg, mo = sim.moments(sp).astype(np.float64), o.moments(sp).astype(np.float64)
         assert rel(mg, mo) < 1e-5
     assert rel(sim.get_B(), o.B()) < 1e-5
-    assert rel(sim.get_E(), o.E()) < 1e-4
+    assert rel(sim.get_E(), o.E()) < 1e-5
 
 
 def test_injection_matches_oracle():
