@@ -147,6 +147,49 @@ __device__ __forceinline__ void deposit_one(unsigned long long* lds, int bx0, in
             return;
         }
     }
+    if constexpr (N == 3) {
+        if (in_lds) {
+            // TSC: the same idea with the three corners per axis visited in
+            // an order rotated by the lane's base-3 digits
+            const int lane = __lane_id();
+            const int ra = lane % 3, rb = D >= 2 ? (lane / 3) % 3 : 0, rc = D >= 3 ? (lane / 9) % 3 : 0;
+            int ux[3], uy[3] = {1, 0, 0}, uz[3] = {1, 0, 0}, ox[3], oy[3] = {0, 0, 0}, oz[3] = {0, 0, 0};
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int k = a + ra >= 3 ? a + ra - 3 : a + ra;
+                ux[a] = k == 0 ? wx[0] : (k == 1 ? wx[1] : wx[2]);
+                ox[a] = k;
+                if constexpr (D >= 2) {
+                    const int kb = a + rb >= 3 ? a + rb - 3 : a + rb;
+                    uy[a] = kb == 0 ? wy[0] : (kb == 1 ? wy[1] : wy[2]);
+                    oy[a] = kb * X::DX;
+                }
+                if constexpr (D >= 3) {
+                    const int kc = a + rc >= 3 ? a + rc - 3 : a + rc;
+                    uz[a] = kc == 0 ? wz[0] : (kc == 1 ? wz[1] : wz[2]);
+                    oz[a] = kc * X::DX * X::DY;
+                }
+            }
+            const int base = (lz * X::DY + ly) * X::DX + lx;
+#pragma unroll
+            for (int c = 0; c < NZ; ++c) {
+#pragma unroll
+                for (int b = 0; b < NY; ++b) {
+                    const int wyz = D >= 3 ? __umul24(uy[b], uz[c]) : (D >= 2 ? uy[b] : 1);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const int W = D >= 2 ? __umul24(ux[a], wyz) : ux[a];
+                        unsigned long long* p = lds + (base + ox[a] + oy[b] + oz[c]);
+                        atomicAdd(p, (unsigned long long)W);
+                        atomicAdd(p + X::DN, (unsigned long long)mul24(W, vq[0]));
+                        atomicAdd(p + 2 * X::DN, (unsigned long long)mul24(W, vq[1]));
+                        atomicAdd(p + 3 * X::DN, (unsigned long long)mul24(W, vq[2]));
+                    }
+                }
+            }
+            return;
+        }
+    }
 #pragma unroll
     for (int c = 0; c < NZ; ++c) {
 #pragma unroll
