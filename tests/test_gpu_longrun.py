@@ -76,3 +76,28 @@ def test_long_run_spectra_and_db2_profile_within_2_percent(case):
         r = np.abs(hg - ho) / ho
         print(f"  species {sp}: {len(ho)} speed bins of ~{int(ho.mean())} ions, max rel diff {r.max():.2e}", flush=True)
         assert r.max() <= 0.02, (sp, hg, ho)
+
+
+def test_full_3d_workload_runs_its_2000_steps_within_capacity():
+    """The benchmark box (1024 x 192 x 192 cells, 8 ppc, FS wall) over the
+    2000 steps of its workload: no bin, crosser-list or velocity-code
+    overflow, every bin below 90% of its capacity (reflected ions pile up
+    near the wall), and div B at round-off throughout."""
+    import torch
+    p = W.preset("cfg4")
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    nt, cap = int(sim.L.ntiles), int(sim.L.tile_cap[0])
+    worst = 0
+    for s in range(2000):
+        st = sim.step(s, stats=(s % 250 == 249))
+        if st is None:
+            continue
+        assert st["flags"] == 0 and st["saturated"] == 0 and st["out_of_range"] == 0, (s, st)
+        c = sim.sections(0)["counts"].to(torch.int64)
+        worst = max(worst, int((c[:nt] + c[nt:]).max().item()))
+        d = sim.diagnostics()
+        print(f"  step {s + 1}: ions {sim.count(0)}, fullest bin {worst}/{cap}, max div B {d['max_divB']:.2e}",
+              flush=True)
+        assert d["max_divB"] < 1e-12
+    assert worst < 0.9 * cap
