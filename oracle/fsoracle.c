@@ -50,6 +50,11 @@
  *     offset q = floor(off 2^b + 1/2), an exact partition of unity; velocity
  *     codes rint(v 2^s_v) saturated at 2^23-1 with s_v = 23 - ceil(log2
  *     v_max) for the run's largest expected speed v_max; int64 sums.
+ *  R10 x boundaries of the box: the ghost centre at x = -1 holds B0, the one
+ *     at nx copies the last cell; the inflow node x = 0 carries the motional
+ *     field of the unperturbed upstream plasma, E = -u_sh x_hat x B0 (the
+ *     plasma the boundary injects), not Ohm's law against the ghost: with
+ *     the latter a 2D perturbation grows without bound at the boundary.
  */
 #include "fsoracle.h"
 #include <stdlib.h>
@@ -702,6 +707,13 @@ static void ohm_node(const ora_sim* s, const double* B, int64_t i, int64_t j, in
     num[1] = -(G[2] * bb[0] - G[0] * bb[2]) + (J[2] * bb[0] - J[0] * bb[2]) - gp[1];
     num[2] = -(G[0] * bb[1] - G[1] * bb[0]) + (J[0] * bb[1] - J[1] * bb[0]) - gp[2];
     for (int d = 0; d < 3; ++d) E[d] = num[d] / ne + s->c.eta * J[d];
+    /* Reading R10: the inflow node x = 0 of the box carries the motional
+     * field of the unperturbed upstream plasma, E = -u_sh x_hat x B0. */
+    if (s->c.xbc != ORA_XBC_PERIODIC && i == 0) {
+        E[0] = 0.0;
+        E[1] = s->c.u_sh * s->B0[2];
+        E[2] = -s->c.u_sh * s->B0[1];
+    }
 }
 
 static void ohm_all(const ora_sim* s, const double* B, double* E, double* Bb)

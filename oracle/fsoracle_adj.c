@@ -48,6 +48,7 @@ typedef struct {
     int64_t nx, nyc, nzc, nxn, ndx, g, ncent, nnode, ndep;
     int mclamp;
     double B0[3], u2, h2dx;
+    double* lu_inflow;   /* where dL/du_sh of the inflow-node field is added, or NULL */
 } geo;
 
 typedef struct {
@@ -83,7 +84,11 @@ static void geo_init(geo* G, const ora_cfg* c)
     G->B0[0] = cos(th); G->B0[1] = sin(th); G->B0[2] = 0.0;
     G->u2 = c->u_sh / c->r;
     G->h2dx = 1.0 / (2.0 * c->dx);
+    G->lu_inflow = NULL;
 }
+
+/* The inflow node x = 0 of the box (reading R10). */
+static int inflow_node(const geo* G, int64_t i) { return G->c.xbc != ORA_XBC_PERIODIC && i == 0; }
 
 /* ---------------------------------------------------------------------- */
 /* index rules (readings R3, R9)                                          */
@@ -391,6 +396,12 @@ static void ohm_fw(const geo* G, const double* B, const double* fn, const double
     ohm_parts P;
     ohm_eval(G, B, fn, fg, i, j, k, &P);
     for (int d = 0; d < 3; ++d) { E[d] = P.num[d] / P.ne + G->c.eta * P.J[d]; bb[d] = P.bb[d]; }
+    if (inflow_node(G, i)) {
+        /* E = -u_sh x_hat x B0 */
+        E[0] = 0.0;
+        E[1] = G->c.u_sh * G->B0[2];
+        E[2] = -G->c.u_sh * G->B0[1];
+    }
 }
 
 /* Transpose of Ohm at one node: (lam_E, lam_Bbar) -> lam_B (centres),
@@ -403,6 +414,13 @@ static void ohm_vjp_node(const geo* G, const double* B, const double* fn, const 
     ohm_parts P;
     ohm_eval(G, B, fn, fg, i, j, k, &P);
     double ne = P.ne;
+    /* at the inflow node E depends on u_sh only: lam_E goes there and
+     * nowhere else (lam_Bbar still reaches the centres) */
+    static const double lE0[3] = {0, 0, 0};
+    if (inflow_node(G, i)) {
+        if (G->lu_inflow) *G->lu_inflow += lE[1] * G->B0[2] - lE[2] * G->B0[1];
+        lE = lE0;
+    }
     /* E = num / ne + eta J */
     double lnum[3], lJ[3], lbb[3], lG[3], lgp[3], tmp[3];
     double lne = 0.0;
@@ -785,6 +803,7 @@ int ora_adjoint(const ora_cfg* cfg, const double* amps, int64_t nsteps, double* 
     for (int k = 0; k < 2; ++k) lM[k] = (double*)calloc((size_t)(4 * G.ndep), sizeof(double));
     char* alive = (char*)calloc((size_t)nid, 1);
     double lu = 0.0, la = 0.0;
+    G.lu_inflow = &lu;
 
     /* loss and its seed */
     double L = 0.0;

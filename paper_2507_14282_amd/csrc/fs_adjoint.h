@@ -439,8 +439,8 @@ __device__ __forceinline__ long centre_index(const FieldGeo& F, int i, int j, in
 template <int D>
 __global__ __launch_bounds__(256) void k_ohm_adj(FieldGeo F, const double* __restrict__ B, const double* __restrict__ fl,
                                                  const double* __restrict__ lE, const double* __restrict__ lBb,
-                                                 double* __restrict__ lB, double* __restrict__ lfl, long nnode,
-                                                 long ncent) {
+                                                 double* __restrict__ lB, double* __restrict__ lfl, double* grads,
+                                                 long nnode, long ncent) {
     const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nnode) return;
     const int i = (int)(n % F.nxn);
@@ -516,12 +516,18 @@ __global__ __launch_bounds__(256) void k_ohm_adj(FieldGeo F, const double* __res
     cross3(J, bb, c2);
 #pragma unroll
     for (int d = 0; d < 3; ++d) num[d] = -c1[d] + c2[d] - gp[d];
-    // E = num / ne + eta J
+    // E = num / ne + eta J; at the inflow node E = -u_sh x_hat x B0, so its
+    // adjoint goes to u_sh alone (lam_Bbar still reaches the centres)
+    const bool inflow = inflow_node(F, i);
+    if (inflow) {
+        const double le_y = lE[nnode + n], le_z = lE[2 * nnode + n];
+        unsafeAtomicAdd(grads, le_y * F.B0[2] - le_z * F.B0[1]);
+    }
     double lnum[3], lJ[3], lbb[3], tmp[3];
     double lne = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double le = lE[(long)d * nnode + n];
+        const double le = inflow ? 0.0 : lE[(long)d * nnode + n];
         lnum[d] = le / ne;
         lne -= num[d] * le / (ne * ne);
         lJ[d] = F.eta * le;

@@ -519,16 +519,16 @@ void fluid_of(fs_handle* h, const fs_particles* sp, int64_t* const* mom, hipStre
 
 // lam_B += (dF/dB)^T lF and lam_fl += (dF/dfl)^T lF for F(B) = -curl Ohm(B, fl).
 template <int D>
-void rhs_adj(fs_handle* h, const double* B, const double* lF, double* lB, hipStream_t s) {
+void rhs_adj(fs_handle* h, const double* B, const double* lF, double* lB, double* grads, hipStream_t s) {
     const long nn = h->L.nnode, nc = h->L.ncent;
     k_faraday_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, lF, h->alE, nn, nc);
-    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, B, h->afl, h->alE, nullptr, lB, h->alfl, nn, nc);
+    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, B, h->afl, h->alE, nullptr, lB, h->alfl, grads, nn, nc);
 }
 
 // Transpose of the SSP-RK3 field update from B^n with the fluid state in
 // h->afl: lam_B (in: lam(B^{n+1}), out: lam(B^n)); fluid adjoints added to
 // h->alfl.  The stages are recomputed.
-template <int D> void rk3_adj(fs_handle* h, const double* Bn, double* lB, hipStream_t s) {
+template <int D> void rk3_adj(fs_handle* h, const double* Bn, double* lB, double* grads, hipStream_t s) {
     const long N = 3 * h->L.ncent;
     const int ns = h->cfg.n_sub;
     const double hs = h->cfg.dt / (double)ns;
@@ -548,13 +548,13 @@ template <int D> void rk3_adj(fs_handle* h, const double* Bn, double* lB, hipStr
         const unsigned g = grid_for(N);
         // B3 = 1/3 B0 + 2/3 (B2 + h F(B2))
         k_rk_adj3<<<g, 256, 0, s>>>(l0, l2, lF, lB, hs, N);
-        rhs_adj<D>(h, h->B2, lF, l2, s);
+        rhs_adj<D>(h, h->B2, lF, l2, grads, s);
         // B2 = 3/4 B0 + 1/4 (B1 + h F(B1))
         k_rk_adj2<<<g, 256, 0, s>>>(l0, l1, lF, l2, hs, N);
-        rhs_adj<D>(h, h->B1, lF, l1, s);
+        rhs_adj<D>(h, h->B1, lF, l1, grads, s);
         // B1 = B0 + h F(B0)
         k_rk_adj1<<<g, 256, 0, s>>>(l0, lF, l1, hs, N);
-        rhs_adj<D>(h, B0, lF, l0, s);
+        rhs_adj<D>(h, B0, lF, l0, grads, s);
         (void)hipMemcpyAsync(lB, l0, N * sizeof(double), hipMemcpyDeviceToDevice, s);
     }
 }
@@ -586,8 +586,9 @@ int adjoint_step_impl(fs_handle* h, const fs_particles* sp_n, const fs_fields* f
     fluid_of<R, D, S>(h, sp_n1, f_n1->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
     // final Ohm, then the RK3 update
-    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, f_n1->B, h->afl, lam->lE, lam->lE + 3 * nn, lam->lB, h->alfl, nn, nc);
-    rk3_adj<D>(h, f_n->B, lam->lB, s);
+    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, f_n1->B, h->afl, lam->lE, lam->lE + 3 * nn, lam->lB, h->alfl, grads,
+                                              nn, nc);
+    rk3_adj<D>(h, f_n->B, lam->lB, grads, s);
     // fluid and deposit at n+1, into the particle adjoints after the step
     moments_adj<R, D, S>(h, sp_n1, lam, grads, s);
     // ions injected by the step
@@ -616,7 +617,8 @@ int adjoint_init_impl(fs_handle* h, const fs_particles* sp0, const fs_fields* f0
     const long nn = h->L.nnode, nc = h->L.ncent;
     fluid_of<R, D, S>(h, sp0, f0->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
-    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, f0->B, h->afl, lam->lE, lam->lE + 3 * nn, lam->lB, h->alfl, nn, nc);
+    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, f0->B, h->afl, lam->lE, lam->lE + 3 * nn, lam->lB, h->alfl, grads,
+                                              nn, nc);
     moments_adj<R, D, S>(h, sp0, lam, grads, s);
     const fs_particles& P = sp0[0];
     PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
@@ -713,6 +715,7 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     const double th = c.theta_deg * (kTwoPi / 360.0);
     F.B0[0] = std::cos(th); F.B0[1] = std::sin(th); F.B0[2] = 0.0;
     F.n_floor = c.n_floor; F.beta_e = c.beta_e; F.gamma_e = c.gamma_e; F.eta = c.eta; F.j_ext = c.j_ext;
+    F.u_sh = c.u_sh;
     F.wth = c.ppc > 0 ? 1.0 / (double)c.ppc : 0.0;
     F.wcr = h->has_cr ? c.alpha_cr * c.n_cr / (double)c.ppc_cr : 0.0;
     F.scR = std::ldexp(1.0, -h->L.sw_bits);

@@ -17,11 +17,22 @@ namespace fsk {
 struct FieldGeo {
     int dim, nx, nyc, nzc, nxn, ndx, g, xbc, mclamp;
     double dx, rdx, B0[3];
-    double n_floor, beta_e, gamma_e, eta, j_ext;
+    double n_floor, beta_e, gamma_e, eta, j_ext, u_sh;
     double wth, wcr, scR, scG;    // species weights and fixed-point scales
     int has_cr;
     int cont;                     // moments hold FP64 sums (continuous deposit)
 };
+
+// The inflow node x = 0 of the box carries the motional field of the
+// unperturbed upstream plasma, E = -u_sh x_hat x B0, in place of Ohm's law
+// evaluated against the fixed ghost centre (which lets 2D perturbations grow
+// at the boundary).
+__device__ __forceinline__ bool inflow_node(const FieldGeo& F, int i) { return F.xbc == 0 && i == 0; }
+__device__ __forceinline__ void inflow_E(const FieldGeo& F, double e[3]) {
+    e[0] = 0.0;
+    e[1] = F.u_sh * F.B0[2];
+    e[2] = -F.u_sh * F.B0[1];
+}
 
 // Linear index i + sx (j + sy k) of a wrapped grid point.  The layout keeps
 // sx and sy * nzc below 2^24 and every grid below 2^31 points, so 24-bit
@@ -310,6 +321,7 @@ __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restric
     const long n = lin(i, j, k, F.nxn, F.nyc);
     double e[3], bb[3];
     ohm_tile<D>(F, sB, sP, fl, nnode, n, tx, ty, tz, e, bb);
+    if (inflow_node(F, i)) inflow_E(F, e);
 #pragma unroll
     for (int d = 0; d < 3; ++d) E[(long)d * nnode + n] = e[d];
     store_gather(gather + 8 * n, e, bb);
@@ -343,6 +355,7 @@ __global__ __launch_bounds__(256) void k_stage(FieldGeo F, const double* __restr
             if (F.xbc == 1) i = wrapi(i, F.nx);
             const long n = lin(i, j, k, F.nxn, F.nyc);
             ohm_tile<D>(F, sB, sP, fl, nnode, n, lx, ly, lz, e, bb);
+            if (inflow_node(F, i)) inflow_E(F, e);
         }
         sE[0][l] = e[0]; sE[1][l] = e[1]; sE[2][l] = e[2];
     }
@@ -547,7 +560,10 @@ __global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __rest
             const int l = t + 256 * it;
             if (it + 1 < Z::IN || l < Z::NN) {
                 double e[3] = {0, 0, 0}, bb[3];
-                if (fn[it].ok) zm_ohm(F, sB[b0], sB[b1], sP[p0], sP[p1], sP[p2], fn[it], l % Z::NX, l / Z::NX, e, bb);
+                if (fn[it].ok) {
+                    zm_ohm(F, sB[b0], sB[b1], sP[p0], sP[p1], sP[p2], fn[it], l % Z::NX, l / Z::NX, e, bb);
+                    if (inflow_node(F, x0 + l % Z::NX)) inflow_E(F, e);
+                }
                 sE[slot][0][l] = e[0]; sE[slot][1][l] = e[1]; sE[slot][2][l] = e[2];
             }
         }
@@ -668,6 +684,7 @@ __global__ __launch_bounds__(256) void k_ohm3(FieldGeo F, const double* __restri
         if (own) {
             double e[3], bb[3];
             zm_ohm(F, sB[r & 1], sB[(r + 1) & 1], sP[r % 3], sP[(r + 1) % 3], sP[(r + 2) % 3], f, tx, ty, e, bb);
+            if (inflow_node(F, x0 + tx)) inflow_E(F, e);
 #pragma unroll
             for (int d = 0; d < 3; ++d) E[(long)d * nnode + f.n] = e[d];
             store_gather(gather + 8 * f.n, e, bb);

@@ -38,10 +38,13 @@ PRESETS = {
                  theta_deg=0.0, n_cr=0.0, wall_th="faux_shock", seed=1001,
                  precision=64, steps=1000),
     # 1D3V FP32: 32768 cells, 1024 ppc, TSC, CRs at 1% density from the wall.
+    # Over its 20000 steps the CR-driven precursor compresses the thermal
+    # plasma in front of the wall to about twice the mean tile load, so the
+    # thermal bins get four times the mean (the default is two).
     "cfg2": dict(dim=1, nx=32768, dx=0.5, dt=0.0025, ppc=1024, ppc_cr=1024,
                  shape="tsc", u_sh=20.0, beta_i=1.0, theta_deg=0.0, n_cr=0.01,
                  cr_w=89.44271909999159, wall_th="open", wall_cr="faux_shock",
-                 seed=1002, precision=32, steps=20000),
+                 seed=1002, precision=32, steps=20000, cap_factor_th=4.0),
     # 2D3V FP32: 8192 x 512 cells, 16 ppc, M_A = 30, CRs from the wall.
     "cfg3": dict(dim=2, nx=8192, ny=512, dx=0.5, dt=0.002, ppc=16, ppc_cr=16,
                  u_sh=30.0, beta_i=1.0, theta_deg=0.0, n_cr=0.01,
