@@ -124,12 +124,13 @@ def test_inflow_boundary_stays_quiet_in_2d():
     assert np.isfinite(edge) and edge < max(0.5, 2.0 * interior)
 
 
-@pytest.mark.parametrize("name,nsteps", [("cfg2", 20000), ("cfg3", 5000)])
+@pytest.mark.parametrize("name,nsteps", [("cfg1", 1000), ("cfg2", 20000), ("cfg3", 5000)])
 def test_workload_runs_its_full_length(name, nsteps):
-    """The 1D and 2D workloads over the number of steps they are specified
-    for: no bin, crosser-list or velocity-code overflow (the 1D precursor
-    compresses the thermal plasma in front of the wall to about twice the
-    mean tile load), every bin below 90% of capacity."""
+    """The 1D (FP64 parity; FP32 TSC with CRs) and 2D workloads over the
+    number of steps they are specified for: no bin, crosser-list or
+    velocity-code overflow (the 1D precursor compresses the thermal plasma
+    in front of the wall to about twice the mean tile load), every bin below
+    90% of capacity."""
     import torch
     p = W.preset(name)
     sim = F.Simulation(p, "cuda:0")
