@@ -559,11 +559,13 @@ __global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __rest
         for (int it = 0; it < Z::IN; ++it) {
             const int l = t + 256 * it;
             if (it + 1 < Z::IN || l < Z::NN) {
-                double e[3] = {0, 0, 0}, bb[3];
-                if (fn[it].ok) {
-                    zm_ohm(F, sB[b0], sB[b1], sP[p0], sP[p1], sP[p2], fn[it], l % Z::NX, l / Z::NX, e, bb);
-                    if (inflow_node(F, x0 + l % Z::NX)) inflow_E(F, e);
-                }
+                // nodes flagged !ok keep the motional field: the inflow node
+                // needs exactly that, nodes past the box are never read (this
+                // costs fewer registers than overwriting the inflow node after
+                // Ohm's law)
+                double e[3], bb[3];
+                inflow_E(F, e);
+                if (fn[it].ok) zm_ohm(F, sB[b0], sB[b1], sP[p0], sP[p1], sP[p2], fn[it], l % Z::NX, l / Z::NX, e, bb);
                 sE[slot][0][l] = e[0]; sE[slot][1][l] = e[1]; sE[slot][2][l] = e[2];
             }
         }
@@ -574,6 +576,7 @@ __global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __rest
             const int l = t + 256 * it;
             fn[it].ok = false;
             if (it + 1 < Z::IN || l < Z::NN) zm_fetch_fluid(F, fl, nnode, x0, y0, k, l % Z::NX, l / Z::NX, fn[it]);
+            if (inflow_node(F, x0 + l % Z::NX)) fn[it].ok = false;   // motional field, not Ohm's law
         }
     };
 
@@ -603,9 +606,6 @@ __global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __rest
         zm_fetch_B(F, Bin, ncent, x0, y0, k + 1, pl);
         zm_fetch_P(F, pe, x0, y0, k + 2, pl);
         fetch_fluid(k + 1);
-        double bn[3] = {0, 0, 0};
-        const long q = lin(ci, cj, k, F.nx, F.nyc);
-        if (own && c0 != 0.0) { bn[0] = Bn[q]; bn[1] = Bn[ncent + q]; bn[2] = Bn[2 * ncent + q]; }
         zm_store_B(pl, sB[r & 1]);
         zm_store_P(pl, sP[r % 3]);
         __syncthreads();
@@ -613,6 +613,11 @@ __global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __rest
         const double bk1[3] = {sB[r & 1][0][lc], sB[r & 1][1][lc], sB[r & 1][2][lc]};
         __syncthreads();
         if (own) {
+            // Bn is read here rather than ahead of the node plane: held across
+            // Ohm's law its registers cost the kernel a wave per SIMD
+            double bn[3] = {0, 0, 0};
+            const long q = lin(ci, cj, k, F.nx, F.nyc);
+            if (c0 != 0.0) { bn[0] = Bn[q]; bn[1] = Bn[ncent + q]; bn[2] = Bn[2 * ncent + q]; }
             const double(*E0)[Z::NN] = sE[r & 1];
             const double(*E1)[Z::NN] = sE[(r + 1) & 1];
             double dEx[3] = {0, 0, 0}, dEy[3] = {0, 0, 0}, dEz[3] = {0, 0, 0};

@@ -34,9 +34,11 @@ DEFAULTS = dict(
 # for each Mach number; Run A of the paper uses p_iso / m = 5 u_sh).
 PRESETS = {
     # 1D3V FP64 parity box: 512 cells, 64 ppc, FS acting on the thermal ions.
+    # Ions the wall reflects pile up in front of it (the last tile reaches
+    # ~1.8 times the mean load within the 1000 steps), hence four-fold bins.
     "cfg1": dict(dim=1, nx=512, dx=0.5, dt=0.005, ppc=64, u_sh=20.0, beta_i=1.0,
                  theta_deg=0.0, n_cr=0.0, wall_th="faux_shock", seed=1001,
-                 precision=64, steps=1000),
+                 precision=64, steps=1000, cap_factor_th=4.0),
     # 1D3V FP32: 32768 cells, 1024 ppc, TSC, CRs at 1% density from the wall.
     # Over its 20000 steps the CR-driven precursor compresses the thermal
     # plasma in front of the wall to about twice the mean tile load, so the
