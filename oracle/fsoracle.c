@@ -55,6 +55,19 @@
  *     field of the unperturbed upstream plasma, E = -u_sh x_hat x B0 (the
  *     plasma the boundary injects), not Ohm's law against the ghost: with
  *     the latter a 2D perturbation grows without bound at the boundary.
+ *  R11 relativistic mode (the dHybridR push the paper runs with, Sec. 2),
+ *     switched on by c_light = c / v_A > 0.  The velocity arrays then hold
+ *     the four-velocity u = gamma v (momentum per unit mass), gamma =
+ *     sqrt(1 + |u|^2 / c^2).  Push: half electric kick on u, rotation with
+ *     t = (dt/2) B / gamma(u^-) (the relativistic Boris rotation), half
+ *     kick, move with v = u / gamma.  Deposit: the flux uses v = u / gamma.
+ *     Wall: eq. (1) and the R7 kick act in the downstream rest frame,
+ *     reached by an exact Lorentz boost along x with speed u2; |w| is the
+ *     speed in that frame, the kick keeps it.  Thermal loading and
+ *     injection sample the R8 drifting Maxwellian in velocity and convert
+ *     to u; CRs get the R8 downstream-frame speed cr_w, boosted to the lab.
+ *     Kinetic energy is (gamma - 1) c^2 = |u|^2 / (gamma + 1) per mass.  The
+ *     field update is unchanged.  c_light = 0 is the non-relativistic R4.
  */
 #include "fsoracle.h"
 #include <stdlib.h>
@@ -134,6 +147,35 @@ static void normals(double ua, double ub, double* n1, double* n2)
 static int64_t wrapi(int64_t i, int64_t n) { int64_t r = i % n; return r < 0 ? r + n : r; }
 
 /* ------------------------------------------------------------------ */
+/* relativistic mode (reading R11)                                      */
+/* ------------------------------------------------------------------ */
+static int relativistic(const ora_cfg* c) { return c->c_light > 0.0; }
+
+/* Lorentz factor of the four-velocity u (momentum per unit mass). */
+static double lorentz_u(const ora_cfg* c, const double u[3])
+{
+    double cc = c->c_light * c->c_light;
+    return sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / cc);
+}
+
+/* Velocity of a particle from its stored velocity variable: u / gamma in
+ * relativistic mode, the stored velocity itself otherwise. */
+static void velocity_of(const ora_cfg* c, const double u[3], double v[3])
+{
+    if (!relativistic(c)) { for (int d = 0; d < 3; ++d) v[d] = u[d]; return; }
+    double g = lorentz_u(c, u);
+    for (int d = 0; d < 3; ++d) v[d] = u[d] / g;
+}
+
+/* Four-velocity of a particle moving with velocity v, |v| < c. */
+static void four_velocity(const ora_cfg* c, const double v[3], double u[3])
+{
+    double cc = c->c_light * c->c_light;
+    double g = 1.0 / sqrt(1.0 - (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / cc);
+    for (int d = 0; d < 3; ++d) u[d] = g * v[d];
+}
+
+/* ------------------------------------------------------------------ */
 /* construction                                                         */
 /* ------------------------------------------------------------------ */
 static int default_bits(int dim, int shape)
@@ -157,6 +199,15 @@ ora_sim* ora_new(const ora_cfg* cfg)
 {
     if (cfg->dim < 1 || cfg->dim > 3 || cfg->nx < 4 || cfg->shape < 1 || cfg->shape > 2) return NULL;
     if (!(cfg->v_max > 0.0)) return NULL;
+    if (cfg->c_light < 0.0 || cfg->c_light != cfg->c_light) return NULL;
+    if (relativistic(cfg)) {
+        /* every sampled velocity below c: a Box-Muller normal is at most
+         * sqrt(2 * 54 ln 2) < 8.66 in size, three of them < 15 */
+        double sig = sqrt(0.5 * cfg->beta_i);
+        if (!(cfg->u_sh + 15.0 * sig < cfg->c_light)) return NULL;
+        if (!(cfg->u_sh / cfg->r < cfg->c_light)) return NULL;
+        if (cfg->n_cr > 0.0 && !(cfg->cr_w < cfg->c_light)) return NULL;
+    }
     ora_sim* s = (ora_sim*)calloc(1, sizeof(ora_sim));
     s->c = *cfg;
     if (s->c.n_sub < 1) s->c.n_sub = 1;
@@ -331,11 +382,19 @@ static void gather(const ora_sim* s, const int64_t c[3], const double o[3], doub
             }
 }
 
-/* Boris: half electric kick, magnetic rotation, half electric kick (q/m=1). */
-static void boris(double v[3], const double E[3], const double B[3], double dt)
+/* Boris: half electric kick, magnetic rotation, half electric kick (q/m=1).
+ * In relativistic mode v is the four-velocity and the rotation vector is
+ * divided by the Lorentz factor after the first half kick (reading R11). */
+static void boris(const ora_cfg* c, double v[3], const double E[3], const double B[3], double dt)
 {
     double h = 0.5 * dt, vm[3], t[3], sv[3], vp[3], vq[3];
-    for (int d = 0; d < 3; ++d) { vm[d] = v[d] + h * E[d]; t[d] = h * B[d]; }
+    for (int d = 0; d < 3; ++d) vm[d] = v[d] + h * E[d];
+    if (relativistic(c)) {
+        double g = lorentz_u(c, vm);
+        for (int d = 0; d < 3; ++d) t[d] = h * B[d] / g;
+    } else {
+        for (int d = 0; d < 3; ++d) t[d] = h * B[d];
+    }
     double tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
     for (int d = 0; d < 3; ++d) sv[d] = 2.0 * t[d] / (1.0 + tt);
     vp[0] = vm[0] + (vm[1] * t[2] - vm[2] * t[1]);
@@ -357,9 +416,11 @@ static void push_species(ora_sim* s, int k)
         double* v = &p->v[3 * i];
         double E[3], B[3];
         gather(s, c, o, E, B);
-        boris(v, E, B, s->c.dt);
+        boris(&s->c, v, E, B, s->c.dt);
+        double vel[3];
+        velocity_of(&s->c, v, vel);
         for (int d = 0; d < s->c.dim; ++d) {
-            double xi = o[d] + v[d] * dtdx;
+            double xi = o[d] + vel[d] * dtdx;
             double fl = floor(xi);
             c[d] += (int64_t)fl;
             o[d] = xi - fl;
@@ -371,11 +432,49 @@ static void push_species(ora_sim* s, int k)
 /* ------------------------------------------------------------------ */
 /* faux-shock wall (eq. 1, readings R6-R7)                              */
 /* ------------------------------------------------------------------ */
+/* Reading R11's event: eq. (1) and the R7 kick in the downstream rest
+ * frame.  u is the lab four-velocity.  The boost along x with speed u2
+ * (Lorentz factor g2) gives the downstream four-velocity W and Lorentz
+ * factor Gam; the speed there is |w| = |W| / Gam.  The kick keeps |W|, so
+ * Gam and |w| too, and turns W into the R7 direction; the inverse boost
+ * takes it back to the lab.  The decision is FP64 in this fixed order. */
+static int wall_event_rel(const ora_cfg* c, int64_t step, uint64_t id, double delta,
+                          const double u[3], double uout[3], double* back)
+{
+    double cc = c->c_light * c->c_light;
+    double u2 = c->u_sh / c->r;
+    double gam = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) / cc);
+    double g2 = 1.0 / sqrt(1.0 - (u2 * u2) / cc);
+    double Gam = g2 * (gam - u2 * u[0] / cc);
+    double Wx = g2 * (u[0] - u2 * gam), Wy = u[1], Wz = u[2];
+    double W2 = Wx * Wx + Wy * Wy + Wz * Wz;
+    double w2 = W2 / (Gam * Gam);
+    double U[4];
+    draw(c, ORA_STREAM_WALL, step, id, 0, U);
+    double m = U[0] > U[1] ? U[0] : U[1];
+    double T = u2 * (1.0 + m) / (1.0 - m);
+    if (!(w2 > T * T)) return 0;
+    double Wabs = sqrt(W2);
+    double a = u2 / (Wabs / Gam);
+    double mu = a + (1.0 - a) * sqrt(U[2]);
+    double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double phi = ORA_TWO_PI * U[3];
+    double Wxn = -Wabs * mu;
+    uout[0] = g2 * (Wxn + u2 * Gam);
+    uout[1] = Wabs * st * cos(phi);
+    uout[2] = Wabs * st * sin(phi);
+    double gn = g2 * (Gam + u2 * Wxn / cc);
+    double vx = u[0] / gam, vxn = uout[0] / gn;
+    *back = vx > 0.0 ? delta * (-vxn) / vx : 0.0;
+    return 1;
+}
+
 /* Returns 1 (reflect) or 0 (transmit).  On reflection writes the new
  * velocity and how far (in cells) the particle travels back from x = L. */
 static int wall_event(const ora_cfg* c, int64_t step, uint64_t id, double delta,
                       const double v[3], double vout[3], double* back)
 {
+    if (relativistic(c)) return wall_event_rel(c, step, id, delta, v, vout, back);
     double u2 = c->u_sh / c->r;
     double wx = v[0] - u2, wy = v[1], wz = v[2];
     double w2 = wx * wx + wy * wy + wz * wz;
@@ -523,6 +622,7 @@ static void inject(ora_sim* s, ora_stats* st)
                 int64_t c[3] = {(int64_t)fl, t % s->nyc, t / s->nyc};
                 double o[3] = {xi - fl, s->c.dim >= 2 ? U[1] : 0.0, s->c.dim >= 3 ? U[2] : 0.0};
                 if (c[0] >= s->c.nx) { c[0] = s->c.nx - 1; o[0] = nextafter(1.0, 0.0); }
+                if (relativistic(&s->c)) four_velocity(&s->c, v, v);
                 sp_append(&s->sp[0], c, o, v, id);
             }
         s->next_id += nt * cnt[0];
@@ -541,7 +641,19 @@ static void inject(ora_sim* s, ora_stats* st)
                 double stt = sqrt(fmax(0.0, 1.0 - mu * mu));
                 double phi = ORA_TWO_PI * U[3];
                 double v[3] = {u2 - wabs * mu, wabs * stt * cos(phi), wabs * stt * sin(phi)};
-                double xi = (double)s->c.nx - fabs(v[0]) * U[0] * s->c.dt / s->c.dx;
+                double vx = v[0];
+                if (relativistic(&s->c)) {
+                    /* downstream four-velocity of speed wabs, boosted to the lab */
+                    double cc = s->c.c_light * s->c.c_light;
+                    double g2 = 1.0 / sqrt(1.0 - (u2 * u2) / cc);
+                    double Gw = 1.0 / sqrt(1.0 - (wabs * wabs) / cc);
+                    double Wabs = Gw * wabs, Wx = -Wabs * mu;
+                    v[0] = g2 * (Wx + u2 * Gw);
+                    v[1] = Wabs * stt * cos(phi);
+                    v[2] = Wabs * stt * sin(phi);
+                    vx = v[0] / (g2 * (Gw + u2 * Wx / cc));
+                }
+                double xi = (double)s->c.nx - fabs(vx) * U[0] * s->c.dt / s->c.dx;
                 double fl = floor(xi);
                 int64_t c[3] = {(int64_t)fl, t % s->nyc, t / s->nyc};
                 double o[3] = {xi - fl, s->c.dim >= 2 ? U[1] : 0.0, s->c.dim >= 3 ? V[0] : 0.0};
@@ -586,7 +698,8 @@ static void deposit_species(ora_sim* s, int k, ora_stats* st)
     for (int64_t i = 0; i < p->n; ++i) {
         const int64_t* c = &p->c[3 * i];
         const double* o = &p->o[3 * i];
-        const double* v = &p->v[3 * i];
+        double v[3];
+        velocity_of(&s->c, &p->v[3 * i], v);
         int64_t first[3] = {0, 0, 0}, wi[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
         double wr[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
         int np[3] = {1, 1, 1};
@@ -838,6 +951,7 @@ int ora_init(ora_sim* s, const double* amps)
             int64_t c[3] = {i, j, kk};
             double o[3] = {U[0], s->c.dim >= 2 ? U[1] : 0.0, s->c.dim >= 3 ? U[2] : 0.0};
             double v[3] = {s->c.u_sh + sig * n1, sig * n2, sig * n3};
+            if (relativistic(&s->c)) four_velocity(&s->c, v, v);
             sp_append(&s->sp[0], c, o, v, id);
         }
     }
@@ -962,9 +1076,13 @@ void ora_diag(const ora_sim* s, double* out)
     for (int k = 0; k < 2; ++k) {
         double ke = 0.0;
         const ora_sp* p = &s->sp[k];
-        for (int64_t i = 0; i < p->n; ++i)
-            ke += p->v[3 * i] * p->v[3 * i] + p->v[3 * i + 1] * p->v[3 * i + 1] + p->v[3 * i + 2] * p->v[3 * i + 2];
-        out[1 + k] = 0.5 * species_weight(s, k) * ke * dV;
+        for (int64_t i = 0; i < p->n; ++i) {
+            const double* u = &p->v[3 * i];
+            double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+            /* (gamma - 1) c^2 = |u|^2 / (gamma + 1); |v|^2 / 2 without c */
+            ke += relativistic(&s->c) ? uu / (lorentz_u(&s->c, u) + 1.0) : 0.5 * uu;
+        }
+        out[1 + k] = species_weight(s, k) * ke * dV;
         out[3 + k] = (double)p->n;
     }
     out[5] = ora_loss(s);

@@ -33,6 +33,7 @@ typedef struct ora_cfg {
     double u_sh, beta_i, beta_e, gamma_e, theta_deg, r;
     double n_cr, cr_w, alpha_cr, j_ext;
     double n_floor, eta, mode_amp, v_max;
+    double c_light;   /* c / v_A; 0: non-relativistic (reading R4), > 0: reading R11 */
     uint64_t seed;
     int32_t dim, nx, ny, nz;
     int32_t ppc, ppc_cr, shape, deposit_mode; /* shape 1 CIC 2 TSC; deposit 0 fixed point, 1 continuous */

@@ -774,6 +774,8 @@ static double inject_vjp(const geo* G, int k, int64_t step, uint64_t id, const d
 /* ---------------------------------------------------------------------- */
 int ora_adjoint(const ora_cfg* cfg, const double* amps, int64_t nsteps, double* loss, double* grad)
 {
+    /* the reverse sweep covers the non-relativistic push only */
+    if (cfg->c_light != 0.0) return -1;
     ora_cfg c = *cfg;
     c.deposit_mode = 1;
     if (c.n_sub < 1) c.n_sub = 1;

@@ -47,7 +47,7 @@ class OraCfg(C.Structure):
         ("n_cr", C.c_double), ("cr_w", C.c_double), ("alpha_cr", C.c_double),
         ("j_ext", C.c_double),
         ("n_floor", C.c_double), ("eta", C.c_double), ("mode_amp", C.c_double),
-        ("v_max", C.c_double),
+        ("v_max", C.c_double), ("c_light", C.c_double),
         ("seed", C.c_uint64),
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("ppc", C.c_int32), ("ppc_cr", C.c_int32), ("shape", C.c_int32),
@@ -73,6 +73,7 @@ def make_cfg(p: dict, deposit_mode: str = "fixed") -> OraCfg:
     for k in ("dx", "dt", "u_sh", "beta_i", "beta_e", "gamma_e", "theta_deg", "r", "n_cr",
               "cr_w", "alpha_cr", "j_ext", "n_floor", "eta", "mode_amp", "v_max"):
         setattr(c, k, float(p[k]))
+    c.c_light = float(p.get("c_light", 0.0))
     c.seed = int(p["seed"])
     for k in ("dim", "nx", "ny", "nz", "ppc", "ppc_cr", "n_sub", "n_modes"):
         setattr(c, k, int(p[k]))

@@ -25,6 +25,7 @@ DEFAULTS = dict(
     n_cr=0.0, cr_w=89.44271909999159, alpha_cr=1.0, j_ext=0.0,
     wall_th="faux_shock", wall_cr="faux_shock", xbc="box",
     n_floor=0.05, eta=0.0, n_sub=1, v_max=1024.0,
+    c_light=0.0,   # c / v_A; 0 is the non-relativistic push, > 0 the relativistic one
     seed=1000, n_modes=0, mode_amp=1e-3, inject=True,
     precision=32, steps=10,
 )
