@@ -35,13 +35,14 @@ def push_bytes_dim(n_ions, L, dim, nsp):
     return n_ions * 2 * (20 + 4 * dim) + nsp * (int(L.nnode) * 24 + int(L.ndep) * 32)
 
 
-def workload_throughput(name, steps, warmup):
+def workload_throughput(name, steps, warmup, **overrides):
     """Whole-step and push+deposit throughput of one preset, with the push
-    roofline as for the 3D box (used for the 1D and 2D boxes)."""
+    roofline as for the 3D box (used for the 1D and 2D boxes, and for the
+    relativistic push)."""
     import torch
     from paper_2507_14282_amd import fshybrid as F
     from paper_2507_14282_amd import workloads as W
-    p = W.preset(name)
+    p = W.preset(name, **overrides)
     sim = F.Simulation(p, "cuda:0")
     sim.init_plasma()
     for s in range(warmup):
@@ -66,7 +67,8 @@ def workload_throughput(name, steps, warmup):
     ach = alg / (push_ms * 1e-3) / 1e9
     out = {
         "workload": f"{dim}D3V FP32 {p['nx']}x{p['ny']}x{p['nz']} cells dx={p['dx']} d_i, {p['ppc']} ppc"
-                    + (f" + CRs n_cr={p['n_cr']:g}" if sim.has_cr else "") + f", {p['shape']}, M_A={p['u_sh']:g}",
+                    + (f" + CRs n_cr={p['n_cr']:g}" if sim.has_cr else "") + f", {p['shape']}, M_A={p['u_sh']:g}"
+                    + (f", relativistic c/v_A={p['c_light']:g}" if p.get("c_light", 0) > 0 else ""),
         "ions": int(nav), "steps": steps, "warmup": warmup,
         "ms_per_step": (t1 - t0) / steps * 1e3,
         "pu_per_s": nav * steps / (t1 - t0),
@@ -345,7 +347,7 @@ def main():
     ap.add_argument("--write-atomics", metavar="PMC_DIR",
                     help="write profiles/push3d_atomics.json from a rocprofv3 run of the atomic counters")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
-    ap.add_argument("--no-other", action="store_true", help="skip the 1D and 2D workload lines")
+    ap.add_argument("--no-other", action="store_true", help="skip the 1D, 2D and relativistic workload lines")
     ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint/forward measurement")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -452,8 +454,13 @@ def main():
         "final_step_flags": st["flags"],
     }
     if not args.no_other:
-        out["other_workloads"] = {"1D cfg2": workload_throughput("cfg2", 100, 10),
-                                  "2D cfg3": workload_throughput("cfg3", 50, 10)}
+        out["other_workloads"] = {
+            "1D cfg2": workload_throughput("cfg2", 100, 10),
+            "2D cfg3": workload_throughput("cfg3", 50, 10),
+            # the relativistic push at the paper's c / v_A = 1000 (Run A)
+            "2D cfg3 relativistic": workload_throughput("cfg3", 50, 10, c_light=1000.0),
+            "3D cfg4 relativistic": workload_throughput("cfg4", 30, 10, c_light=1000.0),
+        }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
     if not args.no_cpu_baseline:

@@ -79,6 +79,13 @@ typedef struct fs_config {
     double n_cr, cr_w, alpha_cr, j_ext;
     double n_floor, eta, mode_amp, v_max;
     double cap_factor_th, cap_factor_cr;   /* tile capacity / mean occupancy */
+    double c_light;         /* c / v_A.  0: non-relativistic push, velocity arrays
+                               hold v.  > 0: relativistic push (the dHybridR code
+                               of the paper's 2D runs, Sec. 2), velocity arrays
+                               hold the four-velocity u = gamma v; it must exceed
+                               every sampled speed (u_sh + 15 sqrt(beta_i / 2),
+                               u_sh / r, cr_w with CRs) or FS_EINVAL.  The
+                               adjoint entry points refuse it (FS_EINVAL). */
     uint64_t seed;
     int32_t dim, nx, ny, nz;
     int32_t ppc, ppc_cr, shape, precision;  /* shape 1 = CIC, 2 = TSC; precision 32 or 64 */

@@ -121,6 +121,16 @@ int compute_layout(const fs_config* c, fs_layout_info* L, std::string& err) {
     if (c->n_modes < 0) { err = "n_modes must be >= 0"; return FS_EINVAL; }
     const bool has_cr = c->n_cr > 0.0;
     if (has_cr && c->ppc_cr < 1) { err = "ppc_cr must be >= 1 with CRs"; return FS_EINVAL; }
+    if (!(c->c_light >= 0.0)) { err = "c_light must be >= 0"; return FS_EINVAL; }
+    if (c->c_light > 0.0) {
+        // every sampled speed below c: a Box-Muller normal stays below 8.66,
+        // so a thermal velocity below u_sh + 15 sigma
+        if (!(c->u_sh + 15.0 * std::sqrt(0.5 * c->beta_i) < c->c_light) || !(c->u_sh / c->r < c->c_light) ||
+            (has_cr && !(c->cr_w < c->c_light))) {
+            err = "c_light must exceed every sampled speed";
+            return FS_EINVAL;
+        }
+    }
     int t[3];
     tile_shape(c->dim, t);
     L->tile[0] = t[0]; L->tile[1] = t[1]; L->tile[2] = t[2];
@@ -336,16 +346,15 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
             PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
             PBuf<R> out = sections<R>(P.buf[P.cur ^ 1], P.capacity, D);
             auto* mom = reinterpret_cast<unsigned long long*>(f->mom[k]);
-            if (dep) allow_lds(k_push<R, D, S, true>, lds_push);
-            else allow_lds(k_push<R, D, S, false>, lds_push);
-            if (dep)
-                k_push<R, D, S, true><<<(unsigned)h->L.ntiles, PUSH_THREADS, lds_push, s>>>(
+            auto launch = [&](auto kern) {
+                allow_lds(kern, lds_push);
+                kern<<<(unsigned)h->L.ntiles, PUSH_THREADS, lds_push, s>>>(
                     G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, static_cast<const R*>(f->gather),
                     mom, h->xl[k], h->ctr, policy_of(h, k), k);
-            else
-                k_push<R, D, S, false><<<(unsigned)h->L.ntiles, PUSH_THREADS, lds_push, s>>>(
-                    G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, static_cast<const R*>(f->gather),
-                    mom, h->xl[k], h->ctr, policy_of(h, k), k);
+            };
+            const bool rel = h->cfg.c_light > 0.0;
+            if (dep) rel ? launch(k_push<R, D, S, true, true>) : launch(k_push<R, D, S, true, false>);
+            else rel ? launch(k_push<R, D, S, false, true>) : launch(k_push<R, D, S, false, false>);
         }
         timing_end(h, t_push, s);
         const int t_wall = timing_begin(h, 1, s);
@@ -709,6 +718,7 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     G.b = h->L.b_bits; G.sv = h->L.sv_bits; G.mclamp = c.shape;
     G.dt = c.dt; G.dx = c.dx; G.u_sh = c.u_sh; G.u2 = c.u_sh / c.r; G.sigma = std::sqrt(0.5 * c.beta_i);
     G.cr_w = c.cr_w; G.dtdx = c.dt / c.dx; G.seed = c.seed; G.rinv = 1.0 / c.r;
+    G.c_light = c.c_light; G.ic2 = c.c_light > 0.0 ? 1.0 / (c.c_light * c.c_light) : 0.0;
     FieldGeo& F = h->F;
     F.dim = c.dim; F.nx = c.nx; F.nyc = G.nyc; F.nzc = G.nzc; F.nxn = G.nxn; F.ndx = G.ndx; F.g = G.g;
     F.xbc = c.xbc; F.mclamp = c.shape; F.dx = c.dx; F.rdx = 1.0 / c.dx;
@@ -876,6 +886,7 @@ int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n
     if (!h || !sp_n || !f_n || !sp_n1 || !f_n1 || !rec || !rec->refl || !lam || !grads)
         return fail(h, FS_EINVAL, "NULL argument");
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
+    if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
     if (!f_n->B || !f_n->gather || !f_n1->B) return fail(h, FS_EINVAL, "NULL field array");
     if (step < 0) return fail(h, FS_EINVAL, "negative step");
     int64_t cth = 0, ccr = 0;
@@ -896,6 +907,7 @@ int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, 
                     hipStream_t s) {
     if (!h || !sp0 || !f0 || !lam || !grads) return fail(h, FS_EINVAL, "NULL argument");
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
+    if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
     if (!f0->B) return fail(h, FS_EINVAL, "NULL field array");
     int rc = check_adjoint(h, lam);
     if (!rc) rc = check_particles(h, sp0);
@@ -940,7 +952,7 @@ __global__ void k_wall_list(Geo G, int policy, uint64_t step, int64_t n, const u
     if (i >= n) return;
     double vin[3] = {v[i], v[n + i], v[2 * n + i]}, vout[3], back = 0.0;
     int r = 0;
-    if (policy == FS_WALL_FAUX_SHOCK) r = faux_shock_event(G.seed, step, id[i], G.u2, delta[i], vin, vout, back);
+    if (policy == FS_WALL_FAUX_SHOCK) r = faux_shock_event(G.seed, step, id[i], G.u2, G.c_light, delta[i], vin, vout, back);
     else if (policy == FS_WALL_SPECULAR) {
         vout[0] = -vin[0]; vout[1] = vin[1]; vout[2] = vin[2];
         back = delta[i];
@@ -1156,7 +1168,8 @@ template <typename R> int diag_impl(fs_handle* h, const fs_particles* sp, const 
         if (k >= nsp) continue;
         const fs_particles& P = sp[k];
         PBuf<R> b = sections<R>(P.buf[P.cur], P.capacity, h->cfg.dim);
-        k_diag_kin<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(b, P.tile_count[P.cur], (int)h->L.ntiles, P.tile_cap, h->part);
+        k_diag_kin<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(b, P.tile_count[P.cur], (int)h->L.ntiles, P.tile_cap,
+                                                            h->G.ic2, h->part);
         std::vector<double> kp(h->L.ntiles);
         int64_t cnt = 0;
         e = hipMemcpyAsync(kp.data(), h->part, kp.size() * 8, hipMemcpyDeviceToHost, s);
@@ -1166,7 +1179,7 @@ template <typename R> int diag_impl(fs_handle* h, const fs_particles* sp, const 
         double ke = 0;
         for (double x : kp) ke += x;
         const double w = k == 0 ? h->F.wth : h->F.wcr;
-        out[1 + k] = 0.5 * w * ke * dV;
+        out[1 + k] = w * ke * dV;
         out[3 + k] = (double)cnt;
     }
     out[5] = loss;

@@ -148,6 +148,39 @@ template <typename R> __device__ __forceinline__ int vcode(R v, int sv, int& sta
     return (int)t;
 }
 
+// Velocity of an ion from its stored velocity variable: u / gamma in
+// relativistic mode (ic2 = 1/c^2 > 0), the stored velocity when ic2 = 0.
+template <typename R> __device__ __forceinline__ void lab_velocity(const R u[3], R ic2, R v[3]) {
+    if (ic2 != (R)0) {
+        const R ig = (R)1 / sqrt((R)1 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic2);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[d] = u[d] * ig;
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[d] = u[d];
+    }
+}
+
+// Velocity codes of the deposit from the stored velocity variable.  In
+// relativistic mode the velocity u / gamma is formed in FP64 whatever the
+// particle precision, so that the code is that of the exact velocity of the
+// stored u (an FP32 quotient would move codes by one), in a fixed order
+// without contraction: g = sqrt(1 + ((a a + b b) + c c) / c^2), code of a / g.
+template <typename R> __device__ __forceinline__ void velocity_codes(const R u[3], double ic2, int sv, int& status,
+                                                                     int vq[3]) {
+    if (ic2 != 0.0) {
+#pragma clang fp contract(off)
+        const double a = (double)u[0], b = (double)u[1], c = (double)u[2];
+        const double g = sqrt(1.0 + (a * a + b * b + c * c) * ic2);
+        vq[0] = vcode<double>(a / g, sv, status);
+        vq[1] = vcode<double>(b / g, sv, status);
+        vq[2] = vcode<double>(c / g, sv, status);
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) vq[d] = vcode<R>(u[d], sv, status);
+    }
+}
+
 // Exact weight x velocity-code product via the 24-bit multiplier pair.
 __device__ __forceinline__ long long mul24(int w, int q) {
     w = (w << 8) >> 8;
@@ -156,10 +189,17 @@ __device__ __forceinline__ long long mul24(int w, int q) {
 }
 
 // Boris rotation with half electric kicks (q/m = 1): v^{n-1/2} -> v^{n+1/2}.
-template <typename R> __device__ __forceinline__ void boris(R v[3], const R E[3], const R B[3], R h) {
+// Relativistic mode (ic2 = 1/c^2 > 0): v is the four-velocity u and the
+// rotation vector is divided by the Lorentz factor sqrt(1 + |u^-|^2 / c^2)
+// after the first half kick; ic2 = 0 is the non-relativistic rotation.
+template <typename R> __device__ __forceinline__ void boris(R v[3], const R E[3], const R B[3], R h, R ic2) {
     R vm[3], t[3], s[3], vp[3];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) { vm[d] = v[d] + h * E[d]; t[d] = h * B[d]; }
+    for (int d = 0; d < 3; ++d) vm[d] = v[d] + h * E[d];
+    R hb = h;
+    if (ic2 != (R)0) hb = h / sqrt((R)1 + (vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2]) * ic2);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) t[d] = hb * B[d];
     R tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
     R f = (R)2 / ((R)1 + tt);
 #pragma unroll
@@ -182,10 +222,45 @@ template <typename R> __device__ __forceinline__ void boris(R v[3], const R E[3]
 // 2 pi U4 (the flux of an isotropic downstream population that outruns the
 // flow).  Returns 1 on reflection, with the new velocity and the distance
 // (cells) the ion travels back from x = L during the rest of the step.
-__device__ __noinline__ int faux_shock_event(uint64_t seed, uint64_t step, uint32_t id, double u2,
+//
+// Relativistic mode (c_light > 0): v and vout are four-velocities and the
+// event happens in the downstream rest frame, reached by the exact Lorentz
+// boost along x with speed u2 (factor g2).  There the four-velocity is W,
+// the Lorentz factor Gam and the speed |w| = |W| / Gam, which enters the
+// same decision; the kick keeps |W| (so Gam and |w|) and the inverse boost
+// returns to the lab.  The decision arithmetic follows a fixed order (with
+// IEEE square roots), so two implementations agree bit for bit.
+__device__ __noinline__ int faux_shock_event(uint64_t seed, uint64_t step, uint32_t id, double u2, double c_light,
                                              double delta, const double v[3], double vout[3],
                                              double& back) {
 #pragma clang fp contract(off)
+    if (c_light > 0.0) {
+        const double cc = c_light * c_light;
+        const double gam = sqrt(1.0 + (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / cc);
+        const double g2 = 1.0 / sqrt(1.0 - (u2 * u2) / cc);
+        const double Gam = g2 * (gam - u2 * v[0] / cc);
+        const double Wx = g2 * (v[0] - u2 * gam), Wy = v[1], Wz = v[2];
+        const double W2 = Wx * Wx + Wy * Wy + Wz * Wz;
+        const double w2 = W2 / (Gam * Gam);
+        double U[4];
+        draw4(seed, kStreamWall, step, (uint64_t)id, 0, U);
+        const double m = U[0] > U[1] ? U[0] : U[1];
+        const double T = u2 * (1.0 + m) / (1.0 - m);
+        if (!(w2 > T * T)) return 0;
+        const double Wabs = sqrt(W2);
+        const double a = u2 / (Wabs / Gam);
+        const double mu = a + (1.0 - a) * sqrt(U[2]);
+        const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+        const double phi = kTwoPi * U[3];
+        const double Wxn = -Wabs * mu;
+        vout[0] = g2 * (Wxn + u2 * Gam);
+        vout[1] = Wabs * st * cos(phi);
+        vout[2] = Wabs * st * sin(phi);
+        const double gn = g2 * (Gam + u2 * Wxn / cc);
+        const double vx = v[0] / gam, vxn = vout[0] / gn;
+        back = vx > 0.0 ? delta * (-vxn) / vx : 0.0;
+        return 1;
+    }
     double wx = v[0] - u2, wy = v[1], wz = v[2];
     double w2 = wx * wx + wy * wy + wz * wz;
     double U[4];

@@ -768,9 +768,15 @@ __global__ __launch_bounds__(256) void k_init_particles(Geo G, PBuf<R> out, int6
     out.off[0][dst] = to_offset<R>(U[0]);
     if constexpr (D >= 2) out.off[1][dst] = to_offset<R>(U[1]);
     if constexpr (D >= 3) out.off[2][dst] = to_offset<R>(U[2]);
-    out.v[0][dst] = (R)(G.u_sh + G.sigma * n1);
-    out.v[1][dst] = (R)(G.sigma * n2);
-    out.v[2][dst] = (R)(G.sigma * n3);
+    double v[3] = {G.u_sh + G.sigma * n1, G.sigma * n2, G.sigma * n3};
+    if (G.c_light > 0.0) {   // relativistic mode: store the four-velocity
+        const double g = 1.0 / sqrt(1.0 - (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / (G.c_light * G.c_light));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] *= g;
+    }
+    out.v[0][dst] = (R)v[0];
+    out.v[1][dst] = (R)v[1];
+    out.v[2][dst] = (R)v[2];
     out.id[dst] = (uint32_t)id;
 }
 
@@ -898,7 +904,10 @@ __global__ __launch_bounds__(256) void k_diag_field(FieldGeo F, const double* __
 
 // Per-tile kinetic energy sums (sum of |v|^2) in FP64.
 template <typename R>
-__global__ __launch_bounds__(256) void k_diag_kin(PBuf<R> in, const int32_t* cnt, int ntiles, int64_t cap, double* part) {
+// Kinetic energy per unit mass summed over a tile: |v|^2 / 2, or in
+// relativistic mode (gamma - 1) c^2 = |u|^2 / (gamma + 1).
+__global__ __launch_bounds__(256) void k_diag_kin(PBuf<R> in, const int32_t* cnt, int ntiles, int64_t cap, double ic2,
+                                                  double* part) {
     __shared__ double sh[256];
     int tile = blockIdx.x;
     int lo = cnt[tile];
@@ -907,7 +916,8 @@ __global__ __launch_bounds__(256) void k_diag_kin(PBuf<R> in, const int32_t* cnt
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         long src = bin_slot(tile, cap, lo, i);
         double a = in.v[0][src], b = in.v[1][src], c = in.v[2][src];
-        s += a * a + b * b + c * c;
+        const double uu = a * a + b * b + c * c;
+        s += ic2 != 0.0 ? uu / (sqrt(1.0 + uu * ic2) + 1.0) : 0.5 * uu;
     }
     double t = block_sum(s, sh);
     if (threadIdx.x == 0) part[tile] = t;

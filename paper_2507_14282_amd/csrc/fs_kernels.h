@@ -27,6 +27,7 @@ struct Geo {
     int b, sv;                    // fixed-point position / velocity bits
     int mclamp;                   // boundary node moment fill distance (shape order)
     double dt, dx, u_sh, u2, sigma, cr_w, dtdx, rinv;
+    double c_light, ic2;          // c / v_A and 1 / c^2; both 0 without relativity
     uint64_t seed;
 };
 
@@ -224,7 +225,9 @@ __device__ __forceinline__ void deposit_one(unsigned long long* lds, int bx0, in
 }
 
 // Integer weights + velocity codes of a particle and its deposit.
-template <typename R, int D, int S>
+// REL false: the caller knows the run is non-relativistic (v is the
+// velocity); true: the run's 1/c^2 decides at run time.
+template <typename R, int D, int S, bool REL = true>
 __device__ __forceinline__ int deposit_particle(unsigned long long* lds, int bx0, int by0, int bz0,
                                                 unsigned long long* mom, const Geo& G, int cx, int cy,
                                                 int cz, const R* o, const R* v, int& oor) {
@@ -233,8 +236,7 @@ __device__ __forceinline__ int deposit_particle(unsigned long long* lds, int bx0
     if constexpr (D >= 2) weights_int<R, S>(o[1], G.b, ry, wy);
     if constexpr (D >= 3) weights_int<R, S>(o[2], G.b, rz, wz);
     int status = 0, vq[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) vq[d] = vcode<R>(v[d], G.sv, status);
+    velocity_codes<R>(v, REL ? G.ic2 : 0.0, G.sv, status, vq);
     deposit_one<D, S>(lds, bx0, by0, bz0, mom, G, cx, cy, cz, wx, wy, wz, rx, ry, rz, vq, oor);
     return status;
 }
@@ -319,13 +321,15 @@ __device__ __forceinline__ void load_ion(const PBuf<R>& in, long src, Ion<R, D>&
 }
 
 // ---------------------------------------------------------------------------
+// REL selects the relativistic push at compile time: a run-time switch would
+// cost the non-relativistic kernel registers (and occupancy) it never uses.
 // The fused hot kernel: per tile, gather E/Bbar from LDS, Boris, move, apply
 // the open / periodic boundaries, list wall crossers, deposit the moments
 // (LDS int64 atomics into the tile's deposit box, one cell of halo; ions
 // that moved further go straight to the global grid) and write each ion to
 // the bin of its destination tile.
 // ---------------------------------------------------------------------------
-template <typename R, int D, int S, bool DEP>
+template <typename R, int D, int S, bool DEP, bool REL>
 __global__ __launch_bounds__(PUSH_THREADS) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
                                               int32_t* __restrict__ cnt_out, int64_t cap,
                                               const R* __restrict__ gather, unsigned long long* __restrict__ mom,
@@ -367,6 +371,7 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(Geo G, PBuf<R> in, PBuf<R
     const int n = min(lo_in + hi_in, (int)cap);
     const R h = (R)(0.5 * G.dt);
     const R dtdx = (R)G.dtdx;
+    const R ic2 = REL ? (R)G.ic2 : (R)0;
     int oor = 0, nesc = 0, nopen = 0;
     const int lane = __lane_id();
 
@@ -413,13 +418,16 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(Geo G, PBuf<R> in, PBuf<R
                     B[0] += W * p1.y; B[1] += W * p2.x; B[2] += W * p2.y;
                 }
             }
-        boris<R>(v, E, B, h);
+        boris<R>(v, E, B, h, ic2);
 
-        // move in cell units (no CFL assumption)
+        // move in cell units (no CFL assumption) with the velocity (u / gamma
+        // in relativistic mode)
+        R vel[3];
+        lab_velocity<R>(v, ic2, vel);
         int nc[3] = {cx, cy, cz};
 #pragma unroll
         for (int d = 0; d < D; ++d) {
-            R xi = o[d] + v[d] * dtdx;
+            R xi = o[d] + vel[d] * dtdx;
             R fl = floor(xi);
             nc[d] += (int)fl;
             o[d] = xi - fl;
@@ -457,7 +465,7 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(Geo G, PBuf<R> in, PBuf<R
 
         if constexpr (DEP) {
             if (kind == 0)
-                status |= deposit_particle<R, D, S>(sd, dx0, dy0, dz0, mom, G, nc[0], nc[1], nc[2], o, v, oor);
+                status |= deposit_particle<R, D, S, REL>(sd, dx0, dy0, dz0, mom, G, nc[0], nc[1], nc[2], o, v, oor);
         }
 
         // write to the destination tile's bin: stayers bottom-up through one
@@ -531,7 +539,7 @@ __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int3
         double vout[3], back = 0.0;
         int refl;
         if (policy == 1) {
-            refl = faux_shock_event(G.seed, step, pid, G.u2, xl.delta[i], v, vout, back);
+            refl = faux_shock_event(G.seed, step, pid, G.u2, G.c_light, xl.delta[i], v, vout, back);
         } else {
             vout[0] = -v[0]; vout[1] = v[1]; vout[2] = v[2];
             back = xl.delta[i];
@@ -613,6 +621,12 @@ __global__ __launch_bounds__(256) void k_inject(Geo G, PBuf<R> out0, int32_t* cn
         vv[1] = G.sigma * n2;
         vv[2] = G.sigma * n3;
         xi = vv[0] * U[0] * G.dt / G.dx;
+        if (G.c_light > 0.0) {   // relativistic mode: store the four-velocity
+            const double cc = G.c_light * G.c_light;
+            const double g = 1.0 / sqrt(1.0 - (vv[0] * vv[0] + vv[1] * vv[1] + vv[2] * vv[2]) / cc);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vv[c] *= g;
+        }
     } else {
         draw4(G.seed, kStreamInjectCr, step, id, 0, U);
         draw4(G.seed, kStreamInjectCr, step, id, 1, V);
@@ -623,7 +637,20 @@ __global__ __launch_bounds__(256) void k_inject(Geo G, PBuf<R> out0, int32_t* cn
         vv[0] = G.u2 - G.cr_w * mu;
         vv[1] = G.cr_w * st * cos(phi);
         vv[2] = G.cr_w * st * sin(phi);
-        xi = (double)G.nx - fabs(vv[0]) * U[0] * G.dt / G.dx;
+        double vx = vv[0];
+        if (G.c_light > 0.0) {
+            // relativistic mode: four-velocity of speed cr_w in the downstream
+            // frame, boosted to the lab along x
+            const double cc = G.c_light * G.c_light;
+            const double g2 = 1.0 / sqrt(1.0 - (G.u2 * G.u2) / cc);
+            const double Gw = 1.0 / sqrt(1.0 - (G.cr_w * G.cr_w) / cc);
+            const double Wabs = Gw * G.cr_w, Wx = -Wabs * mu;
+            vv[0] = g2 * (Wx + G.u2 * Gw);
+            vv[1] = Wabs * st * cos(phi);
+            vv[2] = Wabs * st * sin(phi);
+            vx = vv[0] / (g2 * (Gw + G.u2 * Wx / cc));
+        }
+        xi = (double)G.nx - fabs(vx) * U[0] * G.dt / G.dx;
     }
     double fl = floor(xi);
     int cx = (int)fl;
@@ -673,7 +700,12 @@ __device__ __forceinline__ void deposit_particle_c(double* lds, int bx0, int by0
     weights_real<double, S>((double)o[0], rx, wx);
     if constexpr (D >= 2) weights_real<double, S>((double)o[1], ry, wy);
     if constexpr (D >= 3) weights_real<double, S>((double)o[2], rz, wz);
-    const double vd[3] = {(double)v[0], (double)v[1], (double)v[2]};
+    double vd[3] = {(double)v[0], (double)v[1], (double)v[2]};
+    if (G.ic2 != 0.0) {   // relativistic mode: v holds u, the flux needs u / gamma
+        const double g = sqrt(1.0 + (vd[0] * vd[0] + vd[1] * vd[1] + vd[2] * vd[2]) * G.ic2);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) vd[d] /= g;
+    }
     int lx = cx + rx - bx0, ly = D >= 2 ? cy + ry - by0 : 0, lz = D >= 3 ? cz + rz - bz0 : 0;
     bool in_lds = lds != nullptr && lx >= 0 && lx + N <= X::DX;
     if constexpr (D >= 2) in_lds = in_lds && ly >= 0 && ly + N <= X::DY;

@@ -42,7 +42,7 @@ class FsConfig(C.Structure):
         ("gamma_e", C.c_double), ("theta_deg", C.c_double), ("r", C.c_double),
         ("n_cr", C.c_double), ("cr_w", C.c_double), ("alpha_cr", C.c_double), ("j_ext", C.c_double),
         ("n_floor", C.c_double), ("eta", C.c_double), ("mode_amp", C.c_double), ("v_max", C.c_double),
-        ("cap_factor_th", C.c_double), ("cap_factor_cr", C.c_double),
+        ("cap_factor_th", C.c_double), ("cap_factor_cr", C.c_double), ("c_light", C.c_double),
         ("seed", C.c_uint64),
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("ppc", C.c_int32), ("ppc_cr", C.c_int32), ("shape", C.c_int32), ("precision", C.c_int32),
@@ -156,6 +156,7 @@ def make_config(p: dict) -> FsConfig:
         setattr(c, k, float(p[k]))
     c.cap_factor_th = float(p.get("cap_factor_th", 0.0))
     c.cap_factor_cr = float(p.get("cap_factor_cr", 0.0))
+    c.c_light = float(p.get("c_light", 0.0))
     c.seed = int(p["seed"])
     for k in ("dim", "nx", "ny", "nz", "ppc", "ppc_cr", "n_sub", "n_modes"):
         setattr(c, k, int(p[k]))

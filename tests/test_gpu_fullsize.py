@@ -83,11 +83,14 @@ def live_mask(sec, L):
     return ((j < cnt[:nt, None]) | (j >= cap - cnt[nt:, None])).reshape(-1)
 
 
-@pytest.mark.parametrize("name", ["cfg4", "cfg3", "cfg2"])
-def test_full_size_step_sampled_parity(name):
-    p = W.preset(name)
+@pytest.mark.parametrize("name,c_light", [("cfg4", 0.0), ("cfg3", 0.0), ("cfg2", 0.0),
+                                          ("cfg4", 1000.0), ("cfg3", 1000.0)])
+def test_full_size_step_sampled_parity(name, c_light):
+    # c_light > 0: the relativistic push at the paper's c / v_A = 1000 (Run A)
+    p = W.preset(name, c_light=c_light)
     dim = int(p["dim"])
-    print(f"full-size {name}: dim {dim}, {p['nx']}x{p['ny']}x{p['nz']}, ppc {p['ppc']}", flush=True)
+    print(f"full-size {name}: dim {dim}, {p['nx']}x{p['ny']}x{p['nz']}, ppc {p['ppc']}, c/v_A {c_light:g}",
+          flush=True)
     sim = F.Simulation(p, "cuda:0")
     sim.init_plasma()
     for s in range(2):
@@ -135,7 +138,8 @@ def test_full_size_step_sampled_parity(name):
 
     # --- exact deposit identities over the whole box --------------------------
     # every ion's integer weights sum to 2^sw over its stencil (sw = D b for
-    # CIC, D (2b + 1) for TSC), so sum R = N 2^sw and sum G = 2^sw sum v_q
+    # CIC, D (2b + 1) for TSC), so sum R = N 2^sw and sum G = 2^sw sum v_q;
+    # relativistic mode codes u / gamma, formed in FP64 in the kernel's order
     sw = int(L.sw_bits)
     sv = int(L.sv_bits)
     vmax = (1 << 23) - 1
@@ -146,8 +150,15 @@ def test_full_size_step_sampled_parity(name):
         assert n_live == sim.count(spc)
         M = sim.mom[spc]
         assert int(M[:, 0].sum().item()) == n_live << sw, spc
+        g = None
+        if c_light > 0:
+            a, b, cc = (sec["v"][k].double() for k in range(3))
+            g = torch.sqrt(1.0 + (((a * a) + (b * b)) + (cc * cc)) * (1.0 / (c_light * c_light)))
+            del a, b, cc
         for c in range(3):
-            vq = torch.round(sec["v"][c].float() * float(1 << sv)).clamp(-vmax, vmax).to(torch.int64)
+            vel = sec["v"][c].float() if g is None else sec["v"][c].double() / g
+            vq = torch.round(vel * float(1 << sv)).clamp(-vmax, vmax).to(torch.int64)
+            del vel
             qsum = int(vq[mask].sum().item())
             msum = int(M[:, 1 + c].sum().item()) % (1 << 64)
             assert msum == (qsum << sw) % (1 << 64), (spc, c)

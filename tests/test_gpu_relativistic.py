@@ -1,0 +1,157 @@
+"""Parity of the relativistic mode (c_light > 0, the dHybridR push of the
+paper's 2D runs, Sec. 2) of the HIP path with the FP64 CPU oracle.
+
+Same bars as the non-relativistic parity: ids, cells, wall counts and
+fixed-point moments exact (a cell may differ only at a certified
+straddle); floating-point state within 1e-12 in FP64 mode and 1e-5 per
+step in FP32 mode.  The velocity arrays hold the four-velocity u.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2507_14282_amd import workloads as W
+from tests import inputs
+from tests.test_gpu_parity import by_id, compare_particles, rel, setup_pair, small
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def lib():
+    from paper_2507_14282_amd import fshybrid
+    return fshybrid
+
+
+COUNTS = ("incident", "reflected", "transmitted", "open_removed", "escaped", "injected_th", "injected_cr")
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_relativistic_init_fp64_matches_oracle(dim):
+    p = small(dim, precision=64, n_modes=3, mode_amp=0.01, c_light=60.0)
+    sim = lib().Simulation(p, "cuda:0")
+    sim.init_plasma()
+    o = O.Oracle(p)
+    o.init()
+    g, r = sim.particles(0), o.particles(0)
+    compare_particles(g, r, p, 1e-13)
+    assert np.array_equal(sim.moments(0), o.moments(0))
+    assert rel(sim.get_E(), o.E()) < 1e-11
+    # the stored variable is u: |u| exceeds the speed by gamma
+    u = by_id(g)["v"]
+    gam = np.sqrt(1 + np.sum(u**2, axis=1) / 60.0**2)
+    assert gam.min() > 1.0 and gam.max() < 1.5
+
+
+@pytest.mark.parametrize("case", ["1d_fs_thermal", "1d_cr_tsc", "2d_cr", "3d_fs"])
+def test_relativistic_fp64_free_run(case):
+    if case == "1d_fs_thermal":
+        p, n = W.preset("cfg1", precision=64, c_light=40.0), 40
+    elif case == "1d_cr_tsc":
+        p, n = W.preset("cfg5", nx=128, ppc=32, ppc_cr=32, precision=64, n_modes=8, mode_amp=0.01,
+                        shape="tsc", c_light=150.0), 30
+    elif case == "2d_cr":
+        p, n = small(2, precision=64, n_cr=0.01, ppc_cr=4, wall_th="open", wall_cr="faux_shock",
+                     n_modes=3, mode_amp=0.02, c_light=150.0), 20
+    else:
+        p, n = small(3, precision=64, n_modes=3, mode_amp=0.02, c_light=50.0), 15
+    sim = lib().Simulation(p, "cuda:0")
+    sim.init_plasma()
+    o = O.Oracle(p)
+    o.init()
+    tot = {"incident": 0, "injected_cr": 0}
+    for s in range(n):
+        st, so = sim.step(s), o.step()
+        for k in COUNTS:
+            assert st[k] == so[k], (s, k, st[k], so[k])
+        for k in tot:
+            tot[k] += st[k]
+    for sp in range(2 if p["n_cr"] > 0 else 1):
+        assert sim.count(sp) == o.count(sp)
+        nstr = compare_particles(sim.particles(sp), o.particles(sp), p, 1e-12, straddle=1e-9)
+        if nstr == 0:
+            assert np.array_equal(sim.moments(sp), o.moments(sp)), sp
+    assert rel(sim.get_B(), o.B()) < 1e-12
+    assert rel(sim.get_E(), o.E()) < 1e-10
+    # the wall (thermal cases) or the CR injection at the wall (CR cases) ran
+    assert tot["injected_cr" if p["n_cr"] > 0 else "incident"] > 0
+    dg, do = sim.diagnostics(), o.diag()
+    for k in ("kinetic_th", "kinetic_cr", "field_energy"):
+        assert abs(dg[k] - do[k]) <= 1e-11 * max(abs(do[k]), 1e-300), k
+
+
+def test_relativistic_wall_list_matches_oracle():
+    c = 50.0
+    p = W.params(dim=1, nx=64, u_sh=20.0, r=4.0, wall_th="faux_shock", seed=31, precision=32, c_light=c)
+    ids, delta, v = inputs.crosser_list(20000, seed=4, u2=5.0, wmin=0.5, wmax=40.0)
+    u = v / np.sqrt(1.0 - np.sum(v**2, axis=1) / c**2)[:, None]
+    sim = lib().Simulation(p, "cuda:0")
+    out_g, u_g, xi_g = sim.apply_faux_shock(0, 123, ids, delta, u)
+    out_o, u_o, xi_o = O.wall_list(p, 123, 0, ids, delta, u)
+    assert np.array_equal(out_g, out_o)
+    assert 0 < out_g.sum() < len(out_g)
+    assert rel(u_g, u_o) < 1e-14
+    assert rel(xi_g[out_g == 1], xi_o[out_o == 1]) < 1e-14
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+@pytest.mark.parametrize("shape", ["cic", "tsc"])
+def test_relativistic_push_fp32_one_step(dim, shape):
+    p = small(dim, precision=32, shape=shape, dt=0.01, c_light=40.0)
+    st = inputs.particle_state(p, 8, seed=50 + dim, drift=20.0, sigma=1.0)
+    B = inputs.magnetic_field(p, 0.3, seed=6)
+    sim, o = setup_pair(p, st, B, step0=7)
+    # the deposit from the loaded four-velocities is exact
+    assert np.array_equal(sim.moments(0), o.moments(0))
+    g = sim.step(7, lib().PUSH)
+    r = o.step(O.PUSH | O.BOUNDARY)
+    assert (g["incident"], g["reflected"], g["transmitted"], g["escaped"]) == \
+           (r["incident"], r["reflected"], r["transmitted"], r["escaped"])
+    compare_particles(sim.particles(0), o.particles(0), p, 1e-5)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_relativistic_full_step_fp32_one_step(dim):
+    p = small(dim, precision=32, dt=0.01, n_cr=0.01, ppc_cr=4, wall_th="open", wall_cr="faux_shock",
+              c_light=150.0)
+    st = inputs.particle_state(p, 8, seed=70 + dim, drift=20.0, sigma=0.7)
+    B = inputs.magnetic_field(p, 0.2, seed=16)
+    sim, o = setup_pair(p, st, B, step0=3)
+    g = sim.step(3, lib().ALL)
+    r = o.step(O.ALL)
+    for k in COUNTS:
+        assert g[k] == r[k], k
+    compare_particles(sim.particles(0), o.particles(0), p, 1e-5)
+    if g["injected_cr"]:
+        compare_particles(sim.particles(1), o.particles(1), p, 1e-5)
+    for sp in (0, 1):
+        mg, mo = sim.moments(sp).astype(np.float64), o.moments(sp).astype(np.float64)
+        assert rel(mg, mo) < 1e-5
+    assert rel(sim.get_B(), o.B()) < 1e-5
+    assert rel(sim.get_E(), o.E()) < 1e-5
+
+
+def test_relativistic_injection_matches_oracle():
+    p = W.preset("cfg2", nx=64, ppc=64, ppc_cr=64, precision=64, c_light=150.0)
+    sim = lib().Simulation(p, "cuda:0")
+    sim.set_clock(1000)
+    o = O.Oracle(p)
+    o.set_clock(11, 1000)
+    g = sim.step(11, lib().INJECT)
+    r = o.step(O.INJECT)
+    assert g["injected_th"] == r["injected_th"] > 0
+    assert g["injected_cr"] == r["injected_cr"] > 0
+    compare_particles(sim.particles(0), o.particles(0), p, 1e-13)
+    compare_particles(sim.particles(1), o.particles(1), p, 1e-13)
+
+
+def test_adjoint_refuses_relativistic_mode():
+    from paper_2507_14282_amd import adjoint as A
+    F = lib()
+    p = W.preset("cfg5", nx=64, ppc=16, ppc_cr=16, n_modes=4, c_light=1000.0)
+    run = A.AdjointRun(p, nsteps=2, K=1)
+    run.forward(20.0, 1.0, np.full(4, 1e-3))
+    with pytest.raises(F.FsError) as e:
+        run.backward()
+    assert e.value.code == F.FS_EINVAL
