@@ -341,7 +341,7 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
                 }
             }
         R v1[3] = {v[0], v[1], v[2]};
-        boris<R>(v1, E, B, hR, (R)0);   // the adjoint covers the non-relativistic push
+        boris<R, false>(v1, E, B, hR, (R)0);   // the adjoint covers the non-relativistic push
         if (refl) {
             // overshoot as the forward move computed it
             R xi = o[0] + v1[0] * dtdxR;

@@ -148,33 +148,37 @@ template <typename R> __device__ __forceinline__ int vcode(R v, int sv, int& sta
     return (int)t;
 }
 
-// Velocity of an ion from its stored velocity variable: u / gamma in
-// relativistic mode (ic2 = 1/c^2 > 0), the stored velocity when ic2 = 0.
-template <typename R> __device__ __forceinline__ void lab_velocity(const R u[3], R ic2, R v[3]) {
-    if (ic2 != (R)0) {
-        const R ig = (R)1 / sqrt((R)1 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * ic2);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) v[d] = u[d] * ig;
-    } else {
-#pragma unroll
-        for (int d = 0; d < 3; ++d) v[d] = u[d];
-    }
+// 1 / gamma = 1 / sqrt(1 + x) with x = |u|^2 / c^2, IEEE square root and
+// division (the hardware reciprocal square root, about 1 ulp, moved enough
+// FP32 deposit codes to matter against the FP64 oracle).
+template <typename R> __device__ __forceinline__ R inv_gamma(R x) { return (R)1 / sqrt((R)1 + x); }
+
+// 1 / gamma of a stored four-velocity u, in FP64 whatever the particle
+// precision and in a fixed order without contraction:
+// 1 / sqrt(1 + ((u_x u_x + u_y u_y) + u_z u_z) / c^2).  The relativistic push
+// moves with u * (1/gamma) and codes the deposit velocity from the same
+// FP64 product, so that each code is that of the stored u (an FP32 quotient
+// would move codes by one).
+template <typename R> __device__ __forceinline__ double inv_gamma_u(const R u[3], double ic2) {
+#pragma clang fp contract(off)
+    const double a = (double)u[0], b = (double)u[1], c = (double)u[2];
+    return 1.0 / sqrt(1.0 + (a * a + b * b + c * c) * ic2);
 }
 
-// Velocity codes of the deposit from the stored velocity variable.  In
-// relativistic mode the velocity u / gamma is formed in FP64 whatever the
-// particle precision, so that the code is that of the exact velocity of the
-// stored u (an FP32 quotient would move codes by one), in a fixed order
-// without contraction: g = sqrt(1 + ((a a + b b) + c c) / c^2), code of a / g.
-template <typename R> __device__ __forceinline__ void velocity_codes(const R u[3], double ic2, int sv, int& status,
-                                                                     int vq[3]) {
-    if (ic2 != 0.0) {
+// Deposit velocity codes of a relativistic ion from u and its 1 / gamma.
+template <typename R>
+__device__ __forceinline__ void velocity_codes_ig(const R u[3], double ig, int sv, int& status, int vq[3]) {
 #pragma clang fp contract(off)
-        const double a = (double)u[0], b = (double)u[1], c = (double)u[2];
-        const double g = sqrt(1.0 + (a * a + b * b + c * c) * ic2);
-        vq[0] = vcode<double>(a / g, sv, status);
-        vq[1] = vcode<double>(b / g, sv, status);
-        vq[2] = vcode<double>(c / g, sv, status);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) vq[d] = vcode<double>((double)u[d] * ig, sv, status);
+}
+
+// Velocity codes of the deposit from the stored velocity variable: of
+// u / gamma in relativistic mode (REL), of the velocity itself otherwise.
+template <typename R, bool REL>
+__device__ __forceinline__ void velocity_codes(const R u[3], double ic2, int sv, int& status, int vq[3]) {
+    if constexpr (REL) {
+        velocity_codes_ig<R>(u, inv_gamma_u<R>(u, ic2), sv, status, vq);
     } else {
 #pragma unroll
         for (int d = 0; d < 3; ++d) vq[d] = vcode<R>(u[d], sv, status);
@@ -189,15 +193,16 @@ __device__ __forceinline__ long long mul24(int w, int q) {
 }
 
 // Boris rotation with half electric kicks (q/m = 1): v^{n-1/2} -> v^{n+1/2}.
-// Relativistic mode (ic2 = 1/c^2 > 0): v is the four-velocity u and the
+// Relativistic mode (REL, ic2 = 1/c^2): v is the four-velocity u and the
 // rotation vector is divided by the Lorentz factor sqrt(1 + |u^-|^2 / c^2)
-// after the first half kick; ic2 = 0 is the non-relativistic rotation.
-template <typename R> __device__ __forceinline__ void boris(R v[3], const R E[3], const R B[3], R h, R ic2) {
+// after the first half kick.  REL is a compile-time choice: the hot kernel
+// is instantiated per mode, so neither pays for the other's registers.
+template <typename R, bool REL> __device__ __forceinline__ void boris(R v[3], const R E[3], const R B[3], R h, R ic2) {
     R vm[3], t[3], s[3], vp[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) vm[d] = v[d] + h * E[d];
     R hb = h;
-    if (ic2 != (R)0) hb = h / sqrt((R)1 + (vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2]) * ic2);
+    if constexpr (REL) hb = h * inv_gamma((vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2]) * ic2);
 #pragma unroll
     for (int d = 0; d < 3; ++d) t[d] = hb * B[d];
     R tt = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];

@@ -224,20 +224,33 @@ __device__ __forceinline__ void deposit_one(unsigned long long* lds, int bx0, in
     }
 }
 
-// Integer weights + velocity codes of a particle and its deposit.
-// REL false: the caller knows the run is non-relativistic (v is the
-// velocity); true: the run's 1/c^2 decides at run time.
-template <typename R, int D, int S, bool REL = true>
-__device__ __forceinline__ int deposit_particle(unsigned long long* lds, int bx0, int by0, int bz0,
-                                                unsigned long long* mom, const Geo& G, int cx, int cy,
-                                                int cz, const R* o, const R* v, int& oor) {
+// Deposit of a particle whose velocity codes are already formed.
+template <typename R, int D, int S>
+__device__ __forceinline__ void deposit_coded(unsigned long long* lds, int bx0, int by0, int bz0,
+                                              unsigned long long* mom, const Geo& G, int cx, int cy, int cz,
+                                              const R* o, const int vq[3], int& oor) {
     int wx[3], wy[3] = {1, 0, 0}, wz[3] = {1, 0, 0}, rx, ry = 0, rz = 0;
     weights_int<R, S>(o[0], G.b, rx, wx);
     if constexpr (D >= 2) weights_int<R, S>(o[1], G.b, ry, wy);
     if constexpr (D >= 3) weights_int<R, S>(o[2], G.b, rz, wz);
-    int status = 0, vq[3];
-    velocity_codes<R>(v, REL ? G.ic2 : 0.0, G.sv, status, vq);
     deposit_one<D, S>(lds, bx0, by0, bz0, mom, G, cx, cy, cz, wx, wy, wz, rx, ry, rz, vq, oor);
+}
+
+// Integer weights + velocity codes of a particle and its deposit.  MODE 0:
+// non-relativistic (v is the velocity), 1: relativistic (v is u), 2: the
+// run's 1/c^2 decides at run time (the kernels off the hot path).
+template <typename R, int D, int S, int MODE = 2>
+__device__ __forceinline__ int deposit_particle(unsigned long long* lds, int bx0, int by0, int bz0,
+                                                unsigned long long* mom, const Geo& G, int cx, int cy,
+                                                int cz, const R* o, const R* v, int& oor) {
+    int status = 0, vq[3];
+    if constexpr (MODE == 2) {
+        if (G.ic2 != 0.0) velocity_codes<R, true>(v, G.ic2, G.sv, status, vq);
+        else velocity_codes<R, false>(v, 0.0, G.sv, status, vq);
+    } else {
+        velocity_codes<R, MODE == 1>(v, G.ic2, G.sv, status, vq);
+    }
+    deposit_coded<R, D, S>(lds, bx0, by0, bz0, mom, G, cx, cy, cz, o, vq, oor);
     return status;
 }
 
@@ -418,12 +431,17 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(Geo G, PBuf<R> in, PBuf<R
                     B[0] += W * p1.y; B[1] += W * p2.x; B[2] += W * p2.y;
                 }
             }
-        boris<R>(v, E, B, h, ic2);
+        boris<R, REL>(v, E, B, h, ic2);
 
         // move in cell units (no CFL assumption) with the velocity (u / gamma
-        // in relativistic mode)
-        R vel[3];
-        lab_velocity<R>(v, ic2, vel);
+        // in relativistic mode, 1 / gamma kept for the deposit codes)
+        R vel[3] = {v[0], v[1], v[2]};
+        double ig = 1.0;
+        if constexpr (REL) {
+            ig = inv_gamma_u<R>(v, G.ic2);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) vel[d] = v[d] * (R)ig;
+        }
         int nc[3] = {cx, cy, cz};
 #pragma unroll
         for (int d = 0; d < D; ++d) {
@@ -464,8 +482,15 @@ __global__ __launch_bounds__(PUSH_THREADS) void k_push(Geo G, PBuf<R> in, PBuf<R
         nopen += kind == 3;
 
         if constexpr (DEP) {
-            if (kind == 0)
-                status |= deposit_particle<R, D, S, REL>(sd, dx0, dy0, dz0, mom, G, nc[0], nc[1], nc[2], o, v, oor);
+            if (kind == 0) {
+                if constexpr (REL) {
+                    int vq[3];
+                    velocity_codes_ig<R>(v, ig, G.sv, status, vq);
+                    deposit_coded<R, D, S>(sd, dx0, dy0, dz0, mom, G, nc[0], nc[1], nc[2], o, vq, oor);
+                } else {
+                    status |= deposit_particle<R, D, S, 0>(sd, dx0, dy0, dz0, mom, G, nc[0], nc[1], nc[2], o, v, oor);
+                }
+            }
         }
 
         // write to the destination tile's bin: stayers bottom-up through one

@@ -153,10 +153,10 @@ def test_full_size_step_sampled_parity(name, c_light):
         g = None
         if c_light > 0:
             a, b, cc = (sec["v"][k].double() for k in range(3))
-            g = torch.sqrt(1.0 + (((a * a) + (b * b)) + (cc * cc)) * (1.0 / (c_light * c_light)))
+            g = 1.0 / torch.sqrt(1.0 + (((a * a) + (b * b)) + (cc * cc)) * (1.0 / (c_light * c_light)))
             del a, b, cc
         for c in range(3):
-            vel = sec["v"][c].float() if g is None else sec["v"][c].double() / g
+            vel = sec["v"][c].float() if g is None else sec["v"][c].double() * g
             vq = torch.round(vel * float(1 << sv)).clamp(-vmax, vmax).to(torch.int64)
             del vel
             qsum = int(vq[mask].sum().item())
