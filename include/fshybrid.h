@@ -218,6 +218,36 @@ int64_t fs_next_id(const fs_handle* h);
 int fs_diagnostics(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out8,
                    double* prof, hipStream_t s);
 
+/* Momentum phase space of one species: the paper's phase-space and
+ * spectrum figures (Sec. 3, Figs. 2 and 4: x-|p|, x-p_x, x-p_y, x-p_z, and
+ * the spectra n(p) summed over x).  p is the stored velocity variable per
+ * unit mass: the four-velocity in relativistic mode, the velocity otherwise.
+ * sp: both species' particles as for fs_step; species 0 or 1 (1 needs CRs).
+ * counts (device, int64, nxb x nb, x-bin major, nxb = ceil(nx /
+ * x_cells_per_bin)) is overwritten with the number of ions whose cell x
+ * index / x_cells_per_bin is the x bin and whose momentum falls in bin j:
+ *   component -1: edges[j]^2 <= |p|^2 < edges[j+1]^2  (edges >= 0);
+ *   component 0, 1, 2: edges[j] <= p_c < edges[j+1].
+ * |p|^2 = (p_x p_x + p_y p_y) + p_z p_z and the squared edges are FP64 in
+ * that order without contraction, so the counts are an exact function of the
+ * stored state.  Ions outside the edges are not counted.  edges: device, nb
+ * + 1 ascending FP64 values (not checked; counts are undefined otherwise).
+ * FS_EINVAL: NULL pointer, bad species, component or bin count. */
+int fs_phase_space(fs_handle* h, const fs_particles* sp, int32_t species, int32_t component,
+                   int32_t x_cells_per_bin, int32_t nb, const double* edges, int64_t* counts,
+                   hipStream_t s);
+
+/* Perpendicular magnetic power spectrum along x (the paper's Sec. 3 power
+ * spectra of B_perp, Fig. 3): out (device, nx/2 + 1 FP64) = the mean over
+ * the (y, z) lines of |B^_y(k)|^2 + |B^_z(k)|^2 with
+ * B^(k) = (1/nx) sum_x B(x) exp(-2 pi i k x / nx), k = 0 .. nx/2, for B at the
+ * centres as stored (B0 included at k = 0).  A mode A cos(2 pi m x / nx + phi)
+ * of B_y and A sin(...) of B_z gives A^2 / 2 at k = m.  Direct transform with
+ * a twiddle table, summed over line groups in a fixed order (deterministic).
+ * The handle keeps a scratch of 2 nx + min(lines, 256) (nx/2 + 1) doubles from
+ * the first call.  FS_EINVAL: NULL pointer; FS_EDEVICE: scratch allocation. */
+int fs_bperp_spectrum(fs_handle* h, const fs_fields* f, double* out, hipStream_t s);
+
 /* ---------------------------------------------------------------------
  * Reverse mode.  The derivative is that of the continuous-deposit step
  * (deposit_mode 1) with every discrete decision of the forward run held

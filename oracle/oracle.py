@@ -372,6 +372,41 @@ def adj_rk3(p: dict, B, fn, fg, lam_out):
     return Bo, lB, lfn, lfg
 
 
+# --- diagnostics of the paper's Sec. 3 figures ----------------------------------
+def phase_space(cell3, v3, nx: int, component: int, edges, x_cells_per_bin: int = 1) -> np.ndarray:
+    """Counts of ions per (x bin, momentum bin), by definition: x bin = cell x
+    index // x_cells_per_bin; component -1 bins |p|^2 = (p_x p_x + p_y p_y) +
+    p_z p_z against the squared edges, component 0..2 bins p_c against the
+    edges; bin j holds edge_j <= q < edge_{j+1}; ions outside are dropped.
+    p is the stored velocity variable (four-velocity in relativistic mode)."""
+    cell3 = np.asarray(cell3, dtype=np.int64).reshape(-1, 3)
+    v = np.asarray(v3, dtype=np.float64).reshape(-1, 3)
+    e = np.asarray(edges, dtype=np.float64)
+    if component < 0:
+        q = (v[:, 0] * v[:, 0] + v[:, 1] * v[:, 1]) + v[:, 2] * v[:, 2]
+        E = e * e
+    else:
+        q = v[:, component].copy()
+        E = e
+    nb = len(e) - 1
+    nxb = -(-int(nx) // int(x_cells_per_bin))
+    j = np.searchsorted(E, q, side="right") - 1
+    ok = (q >= E[0]) & (q < E[-1])
+    counts = np.zeros((nxb, nb), dtype=np.int64)
+    np.add.at(counts, (cell3[ok, 0] // int(x_cells_per_bin), j[ok]), 1)
+    return counts
+
+
+def bperp_spectrum(B3, nx: int, nyc: int, nzc: int) -> np.ndarray:
+    """Mean over the (y, z) lines of |B^_y(k)|^2 + |B^_z(k)|^2, k = 0..nx/2,
+    with B^(k) = (1/nx) sum_x B(x) exp(-2 pi i k x / nx) (numpy's FFT); B3 is
+    (ncent, 3) with centre index i + nx (j + nyc k)."""
+    B = np.asarray(B3, dtype=np.float64).reshape(nzc, nyc, nx, 3)
+    Fy = np.fft.rfft(B[..., 1], axis=-1) / nx
+    Fz = np.fft.rfft(B[..., 2], axis=-1) / nx
+    return np.mean(np.abs(Fy) ** 2 + np.abs(Fz) ** 2, axis=(0, 1))
+
+
 # --- sampled evaluation -------------------------------------------------------
 def push_sample(p: dict, E3, Bb3, cell3, off3, v3):
     """Gather + Boris + move of given particles (no boundaries) in given

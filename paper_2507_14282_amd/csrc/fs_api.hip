@@ -35,6 +35,8 @@ struct fs_handle {
     double* phase = nullptr;
     double* part = nullptr;
     int64_t npart = 0;
+    double* spec = nullptr;   // B_perp spectrum: twiddles + partial sums (first use)
+    int64_t nspec = 0;
     // reverse-mode scratch (deposit_mode 1 only)
     double* amom[2] = {nullptr, nullptr};   // moments recomputed for the reverse step
     double* alM[2] = {nullptr, nullptr};    // their adjoints
@@ -791,7 +793,7 @@ void fs_destroy(fs_handle* h) {
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     hipFree(h->ctr);
     if (h->ctr_host) hipHostFree(h->ctr_host);
-    hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->phase); hipFree(h->part);
+    hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->phase); hipFree(h->part); hipFree(h->spec);
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
     for (int k = 0; k < 2; ++k) { hipFree(h->amom[k]); hipFree(h->alM[k]); }
     hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->alE);
@@ -1214,6 +1216,51 @@ int fs_read_particles(fs_handle* h, const fs_particles* sp, int64_t* n, int64_t*
     if (!h || !sp || !n) return fail(h, FS_EINVAL, "bad argument");
     if (cell3 && (!off3 || !v3 || !id)) return fail(h, FS_EINVAL, "NULL array");
     FS_DISPATCH_RD(h, (read_impl<R, D>(h, sp, n, cell3, off3, v3, id, s)));
+}
+
+int fs_phase_space(fs_handle* h, const fs_particles* sp, int32_t species, int32_t component,
+                   int32_t x_cells_per_bin, int32_t nb, const double* edges, int64_t* counts, hipStream_t s) {
+    if (!h || !sp || !edges || !counts) return fail(h, FS_EINVAL, "NULL argument");
+    if (species < 0 || species > (h->has_cr ? 1 : 0)) return fail(h, FS_EINVAL, "no such species");
+    if (component < -1 || component > 2) return fail(h, FS_EINVAL, "component must be -1, 0, 1 or 2");
+    if (x_cells_per_bin < 1 || nb < 1 || nb > (1 << 24)) return fail(h, FS_EINVAL, "bad bin counts");
+    if (int rc = check_particles(h, sp)) return rc;
+    const fs_particles& P = sp[species];
+    const int64_t nxb = (h->cfg.nx + x_cells_per_bin - 1) / x_cells_per_bin;
+    zero_u64(counts, nxb * nb, s);
+    auto run = [&](auto tag) {
+        using R = decltype(tag);
+        PBuf<R> b = sections<R>(P.buf[P.cur], P.capacity, h->cfg.dim);
+        k_phase_space<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, b, P.tile_count[P.cur], (int)h->L.ntiles,
+                                                              P.tile_cap, component, x_cells_per_bin, nb, edges,
+                                                              reinterpret_cast<unsigned long long*>(counts));
+    };
+    if (h->cfg.precision == 32) run(float());
+    else run(double());
+    return hip_check(h, hipGetLastError(), "phase space launch");
+}
+
+int fs_bperp_spectrum(fs_handle* h, const fs_fields* f, double* out, hipStream_t s) {
+    if (!h || !f || !f->B || !out) return fail(h, FS_EINVAL, "NULL argument");
+    const int nx = h->cfg.nx, nk = nx / 2 + 1;
+    const int64_t nlines = h->L.nyc * h->L.nzc;
+    const int ngroups = (int)std::min<int64_t>(nlines, 256);
+    const int64_t need = 2 * (int64_t)nx + (int64_t)ngroups * nk;
+    if (h->nspec < need) {
+        hipFree(h->spec);
+        h->spec = nullptr;
+        h->nspec = 0;
+        if (hipMalloc((void**)&h->spec, need * sizeof(double)) != hipSuccess) return fail(h, FS_EDEVICE, "spectrum scratch");
+        h->nspec = need;
+    }
+    double* tw = h->spec;
+    double* part = h->spec + 2 * (int64_t)nx;
+    k_twiddles<<<grid_for(nx), 256, 0, s>>>(nx, tw);
+    k_bperp_dft<<<dim3((unsigned)((nk + 255) / 256), (unsigned)ngroups), 256, 0, s>>>(h->F, f->B, h->L.ncent, tw, nk,
+                                                                                      ngroups, part);
+    k_bperp_reduce<<<grid_for(nk), 256, 0, s>>>(nk, ngroups, 1.0 / ((double)nlines * (double)nx * (double)nx), part,
+                                                out);
+    return hip_check(h, hipGetLastError(), "spectrum launch");
 }
 
 int fs_diagnostics(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out8, double* prof, hipStream_t s) {

@@ -923,6 +923,96 @@ __global__ __launch_bounds__(256) void k_diag_kin(PBuf<R> in, const int32_t* cnt
     if (threadIdx.x == 0) part[tile] = t;
 }
 
+// Momentum phase space (the paper's phase-space and spectrum figures): one
+// count per ion into (x bin, momentum bin).  The binned quantity is |p|^2 =
+// (p_x p_x + p_y p_y) + p_z p_z against the squared edges (comp < 0) or the
+// component p_comp against the edges, all FP64 without contraction, so the
+// counts are an exact function of the stored state; p is the stored velocity
+// variable (the four-velocity in relativistic mode).  Ions outside the edges
+// are not counted.
+template <typename R>
+__global__ __launch_bounds__(256) void k_phase_space(Geo G, PBuf<R> in, const int32_t* cnt, int ntiles, int64_t cap,
+                                                     int comp, int xpb, int nb, const double* __restrict__ edges,
+                                                     unsigned long long* __restrict__ counts) {
+#pragma clang fp contract(off)
+    const int tile = blockIdx.x;
+    const int lo = cnt[tile];
+    const int n = min(lo + cnt[ntiles + tile], (int)cap);
+    auto edge = [&](int j) {
+        const double e = edges[j];
+        return comp < 0 ? e * e : e;
+    };
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const long src = bin_slot(tile, cap, lo, i);
+        double q;
+        if (comp < 0) {
+            const double a = in.v[0][src], b = in.v[1][src], c = in.v[2][src];
+            q = a * a + b * b + c * c;
+        } else {
+            q = (double)in.v[comp][src];
+        }
+        if (!(edge(0) <= q) || !(q < edge(nb))) continue;
+        int a = 0, b = nb;   // edge(a) <= q < edge(b)
+        while (b - a > 1) {
+            const int mid = (a + b) >> 1;
+            if (edge(mid) <= q) a = mid;
+            else b = mid;
+        }
+        atomicAdd(counts + (long)(cell_x(in.cell[src], G) / xpb) * nb + a, 1ull);
+    }
+}
+
+// Twiddles of the x transform: (cos, sin)(2 pi m / nx), m = 0 .. nx-1.
+__global__ void k_twiddles(int nx, double* tw) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= nx) return;
+    double s, c;
+    sincospi(2.0 * (double)m / (double)nx, &s, &c);
+    tw[2 * m] = c;
+    tw[2 * m + 1] = s;
+}
+
+// Perpendicular power spectrum along x, partial sum over one group of (y, z)
+// lines: thread k accumulates |sum_x By(x) e^{-2 pi i k x / nx}|^2 plus the
+// same for Bz over the group's lines.  The phase index k x mod nx advances by
+// k per cell, so the twiddle table replaces every transcendental; the groups
+// are summed in a fixed order afterwards (deterministic result).
+__global__ __launch_bounds__(256) void k_bperp_dft(FieldGeo F, const double* __restrict__ B, long ncent,
+                                                   const double* __restrict__ tw, int nk, int ngroups,
+                                                   double* __restrict__ part) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (k >= nk) return;
+    const long nlines = (long)F.nyc * F.nzc;
+    const long l0 = nlines * g / ngroups, l1 = nlines * (g + 1) / ngroups;
+    double acc = 0.0;
+    for (long l = l0; l < l1; ++l) {
+        const double* by = B + ncent + (long)F.nx * l;
+        const double* bz = B + 2 * ncent + (long)F.nx * l;
+        double yr = 0.0, yi = 0.0, zr = 0.0, zi = 0.0;
+        int m = 0;
+        for (int x = 0; x < F.nx; ++x) {
+            const double c = tw[2 * m], s = tw[2 * m + 1], a = by[x], b = bz[x];
+            yr += a * c; yi -= a * s;
+            zr += b * c; zi -= b * s;
+            m += k;
+            if (m >= F.nx) m -= F.nx;
+        }
+        acc += yr * yr + yi * yi + zr * zr + zi * zi;
+    }
+    part[(long)g * nk + k] = acc;
+}
+
+// Sum of the groups in order, normalised to the mean over lines of
+// |B^_y(k)|^2 + |B^_z(k)|^2 with B^(k) = (1/nx) sum_x B(x) e^{-2 pi i k x / nx}.
+__global__ void k_bperp_reduce(int nk, int ngroups, double norm, const double* __restrict__ part, double* out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nk) return;
+    double s = 0.0;
+    for (int g = 0; g < ngroups; ++g) s += part[(long)g * nk + k];
+    out[k] = s * norm;
+}
+
 __global__ void k_profile(FieldGeo F, const double* __restrict__ B, long ncent, double* prof) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= F.nx) return;

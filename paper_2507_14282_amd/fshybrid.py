@@ -131,6 +131,8 @@ def library():
         L.fs_next_id.argtypes = [vp]
         L.fs_next_id.restype = i64
         L.fs_diagnostics.argtypes = [vp, P, F, vp, vp, vp]
+        L.fs_phase_space.argtypes = [vp, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
+        L.fs_bperp_spectrum.argtypes = [vp, F, vp, vp]
         L.fs_timing_enable.argtypes = [vp, i32]
         L.fs_timing_read.argtypes = [vp, vp, vp, vp]
         R, A = C.POINTER(FsRecord), C.POINTER(FsAdjoint)
@@ -146,6 +148,7 @@ def exported_symbols():
     return ["fs_layout", "fs_create", "fs_destroy", "fs_last_error", "fs_init_plasma", "fs_step",
             "fs_deposit_moments", "fs_apply_faux_shock", "fs_field_update", "fs_refresh_fields",
             "fs_load_particles", "fs_read_particles", "fs_set_clock", "fs_next_id", "fs_diagnostics",
+            "fs_phase_space", "fs_bperp_spectrum",
             "fs_timing_enable", "fs_timing_read", "fs_step_record", "fs_adjoint_step", "fs_adjoint_init"]
 
 
@@ -393,6 +396,25 @@ class Simulation:
         n = np.zeros(5, dtype=np.int64)
         self._check(self.lib.fs_timing_read(self.h, ms.ctypes.data, n.ctypes.data, self.stream))
         return ms, n
+
+    def phase_space(self, species: int, component: int, edges, x_cells_per_bin: int = 1) -> np.ndarray:
+        """Counts of ions per (x bin, momentum bin); component -1 bins |p|,
+        0..2 bin p_x, p_y, p_z (see fs_phase_space)."""
+        e = torch.as_tensor(np.ascontiguousarray(edges, dtype=np.float64), device=self.device)
+        nb = int(e.numel()) - 1
+        nxb = -(-int(self.p["nx"]) // int(x_cells_per_bin))
+        counts = torch.zeros((nxb, max(nb, 1)), dtype=torch.int64, device=self.device)
+        self._check(self.lib.fs_phase_space(self.h, self.sp, int(species), int(component), int(x_cells_per_bin),
+                                            nb, _ptr(e), _ptr(counts), self.stream))
+        torch.cuda.synchronize(self.device)
+        return counts.cpu().numpy()
+
+    def bperp_spectrum(self) -> np.ndarray:
+        """Mean over (y, z) lines of |B^_y(k)|^2 + |B^_z(k)|^2, k = 0 .. nx/2."""
+        out = torch.zeros(int(self.p["nx"]) // 2 + 1, dtype=torch.float64, device=self.device)
+        self._check(self.lib.fs_bperp_spectrum(self.h, C.byref(self.f), _ptr(out), self.stream))
+        torch.cuda.synchronize(self.device)
+        return out.cpu().numpy()
 
     def diagnostics(self) -> dict:
         out = np.zeros(8)
