@@ -27,12 +27,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def push_bytes_dim(n_ions, L, dim, nsp):
-    """Algorithmic HBM bytes of one step's push launches in FP32: every ion's
-    state read and written once (int32 cell, D fp32 offsets, 3 fp32
-    velocities, uint32 id), and per species launch the gather grid read once
-    (24 B per node) and the int64 moments written once (32 B per node)."""
-    return n_ions * 2 * (20 + 4 * dim) + nsp * (int(L.nnode) * 24 + int(L.ndep) * 32)
+def push_bytes_dim(n_ions, L, dim, nsp, rb=4):
+    """Algorithmic HBM bytes of one step's push launches with rb-byte reals
+    (4: FP32, 8: FP64): every ion's state read and written once (int32 cell,
+    D offsets, 3 velocities, uint32 id), and per species launch the gather
+    grid read once (6 reals per node) and the int64 moments written once
+    (32 B per node)."""
+    return n_ions * 2 * (8 + rb * (dim + 3)) + nsp * (int(L.nnode) * 6 * rb + int(L.ndep) * 32)
 
 
 def workload_throughput(name, steps, warmup, **overrides):
@@ -396,12 +397,18 @@ def main():
     value = np_avg * args.steps / elapsed
     push_ms = ms[0] / max(nrec[0], 1)
     region_ms = (ms[0] + ms[1] + ms[2]) / max(nrec[0], 1)
-    alg = push_bytes(np_avg, sim.L)
+    dim = int(p["dim"])
+    nsp = 2 if sim.has_cr else 1
+    alg = push_bytes(np_avg, sim.L) if (dim == 3 and nsp == 1) else push_bytes_dim(np_avg, sim.L, dim, nsp, int(sim.L.real_bytes))
     achieved = alg / (push_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles(kernel_source_hash())
-    pmc = atomics_from_profiles(kernel_source_hash())
-    # LDS atomics of the deposit: 8 CIC corners x 4 moments per ion
-    lds_ops = 32.0 * np_avg
+    # the committed counters are of the 3D benchmark box's push kernel
+    profiled = args.workload == "cfg4"
+    traffic = traffic_from_profiles(kernel_source_hash()) if profiled else None
+    pmc = atomics_from_profiles(kernel_source_hash()) if profiled else None
+    # LDS atomics of the deposit: 4 moments at each of the 2^D (CIC) or 3^D
+    # (TSC) corners per ion (8 x 4 for the 3D CIC box)
+    corners = (3 if p["shape"] == "tsc" else 2) ** dim
+    lds_ops = 4.0 * corners * np_avg
     atomics = {
         "lds_u64_lane_ops_per_launch": lds_ops,
         "lds_rate": lds_ops / (push_ms * 1e-3), "lds_peak": LDS_U64_ATOMIC_PEAK, "unit": "lane-ops/s",
@@ -430,10 +437,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f64" if int(p["precision"]) == 64 else "f32",
         "data": "synthetic (Philox-seeded drifting Maxwellian load, no external data)",
         "config": {
-            "workload": f"3D3V FP32 faux-shock box {p['nx']}x{p['ny']}x{p['nz']} cells dx={p['dx']} d_i, "
+            "workload": f"{dim}D3V FP{int(p['precision'])} faux-shock box {p['nx']}x{p['ny']}x{p['nz']} cells dx={p['dx']} d_i, "
                         f"{p['ppc']} ppc, M_A={p['u_sh']:g}, beta={p['beta_i']:g}, theta_Bn={p['theta_deg']:g} deg",
             "ions": int(np_avg),
             "step": "push+wall+inject+deposit (FP32 particles, int64 moments) + FP64 SSP-RK3 field update",
@@ -446,7 +453,8 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_push<float,3,CIC,deposit>", "alg_bytes_per_launch": alg,
+            "kernel": f"k_push<{'double' if int(p['precision']) == 64 else 'float'},{dim},{p['shape'].upper()},deposit>",
+            "alg_bytes_per_launch": alg,
             "avg_launch_ms": push_ms,
             "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
         },
