@@ -218,6 +218,31 @@ int64_t fs_next_id(const fs_handle* h);
 int fs_diagnostics(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out8,
                    double* prof, hipStream_t s);
 
+/* Checkpoint and restore (the restart of long runs).  A checkpoint holds
+ * the live ions of both species (packed tile by tile in the particle
+ * buffers' own section layout and precision), B at the centres and the id
+ * counter, behind a header recording the layout (precision, dim, grid,
+ * shape, tile plan), c_light and the seed.
+ * fs_checkpoint_bytes: the size of a checkpoint of the current state
+ *   (synchronises the stream to read the live counts).
+ * fs_checkpoint: writes it to dst, device memory or host memory (pinned or
+ *   pageable), cap >= that size else FS_ECAPACITY; the library stages it in
+ *   device memory it allocates and frees within the call, and returns after
+ *   the copy has completed.
+ * fs_restore: loads a checkpoint (device or host src of `bytes` bytes) into a
+ *   handle of the same layout, c_light and seed (else FS_EINVAL), into the
+ *   current buffers' bins; sets the id counter, deposits the moments and
+ *   recomputes E and the gather grid, so that fs_step continues bit for bit
+ *   as the checkpointed run would have (ions are matched by id; their order
+ *   within a bin is not part of the state).  Every offset and per-tile count
+ *   is checked on the host before a kernel reads the blob: a truncated or
+ *   corrupt checkpoint gives FS_EINVAL and leaves the state unchanged.  The
+ *   step index is the caller's (the argument of fs_step). */
+int fs_checkpoint_bytes(fs_handle* h, const fs_particles* sp, int64_t* bytes, hipStream_t s);
+int fs_checkpoint(fs_handle* h, const fs_particles* sp, const fs_fields* f, void* dst, int64_t cap,
+                  hipStream_t s);
+int fs_restore(fs_handle* h, fs_particles* sp, fs_fields* f, const void* src, int64_t bytes, hipStream_t s);
+
 /* Momentum phase space of one species: the paper's phase-space and
  * spectrum figures (Sec. 3, Figs. 2 and 4: x-|p|, x-p_x, x-p_y, x-p_z, and
  * the spectra n(p) summed over x).  p is the stored velocity variable per

@@ -1148,6 +1148,147 @@ int read_impl(fs_handle* h, const fs_particles* sp, int64_t* n_out, int64_t* cel
         return fail(h, FS_EINVAL, "unsupported configuration");                  \
     } while (0)
 
+// ---------------------------------------------------------------------------
+// checkpoints: header, then per species the per-tile offsets and the live
+// ions packed tile after tile (particle-buffer section layout), then B
+// ---------------------------------------------------------------------------
+struct CkptHeader {
+    char magic[8];
+    int32_t version, precision, dim, nx, ny, nz, shape, nsp;
+    int64_t ntiles, tile_cap[2], ncent;
+    double c_light;
+    uint64_t seed;
+    int64_t next_id;
+    int64_t n[2];
+    int64_t off_toff[2], off_part[2], off_B, total;
+};
+constexpr char kCkptMagic[8] = {'F', 'S', 'C', 'K', 'P', 'T', '0', '1'};
+constexpr int64_t kCkptHead = 256;
+static_assert(sizeof(CkptHeader) <= kCkptHead, "checkpoint header must fit its slot");
+
+int64_t part_block_bytes(int64_t n, int dim, int rb) {
+    return round_up(n * 4, 256) + (int64_t)(dim + 3) * round_up(n * rb, 256) + round_up(n * 4, 256);
+}
+
+// Header and per-tile offsets of a checkpoint of the current state.
+int ckpt_plan(fs_handle* h, const fs_particles* sp, CkptHeader& H, std::vector<int64_t> toff[2], hipStream_t s) {
+    std::memset(&H, 0, sizeof(H));
+    std::memcpy(H.magic, kCkptMagic, 8);
+    const fs_config& c = h->cfg;
+    H.version = 1; H.precision = c.precision; H.dim = c.dim; H.nx = c.nx;
+    H.ny = (int32_t)h->L.nyc; H.nz = (int32_t)h->L.nzc; H.shape = c.shape;
+    H.nsp = h->has_cr ? 2 : 1;
+    H.ntiles = h->L.ntiles; H.tile_cap[0] = h->L.tile_cap[0]; H.tile_cap[1] = h->L.tile_cap[1];
+    H.ncent = h->L.ncent; H.c_light = c.c_light; H.seed = c.seed; H.next_id = h->next_id;
+    const int64_t nt = h->L.ntiles;
+    const int rb = c.precision == 64 ? 8 : 4;
+    int64_t off = kCkptHead;
+    for (int k = 0; k < H.nsp; ++k) {
+        std::vector<int32_t> cnt(2 * nt);
+        hipError_t e = hipMemcpyAsync(cnt.data(), sp[k].tile_count[sp[k].cur], 2 * nt * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_check(h, e, "checkpoint counts");
+        toff[k].assign(nt + 1, 0);
+        for (int64_t t = 0; t < nt; ++t)
+            toff[k][t + 1] = toff[k][t] + std::min<int64_t>((int64_t)cnt[t] + cnt[nt + t], sp[k].tile_cap);
+        H.n[k] = toff[k][nt];
+        H.off_toff[k] = off;
+        off += round_up((nt + 1) * 8, 256);
+        H.off_part[k] = off;
+        off += part_block_bytes(H.n[k], c.dim, rb);
+    }
+    H.off_B = off;
+    off += round_up(3 * h->L.ncent * 8, 256);
+    H.total = off;
+    return FS_OK;
+}
+
+template <typename R, int D>
+int checkpoint_impl(fs_handle* h, const fs_particles* sp, const fs_fields* f, void* dst, int64_t cap_bytes,
+                    hipStream_t s) {
+    CkptHeader H;
+    std::vector<int64_t> toff[2];
+    if (int rc = ckpt_plan(h, sp, H, toff, s)) return rc;
+    if (cap_bytes < H.total) return fail(h, FS_ECAPACITY, "checkpoint buffer smaller than fs_checkpoint_bytes");
+    char* st = nullptr;
+    if (hipMalloc((void**)&st, H.total) != hipSuccess) return fail(h, FS_EDEVICE, "checkpoint staging");
+    hipError_t e = hipMemcpyAsync(st, &H, sizeof(H), hipMemcpyHostToDevice, s);
+    for (int k = 0; k < H.nsp && e == hipSuccess; ++k) {
+        const fs_particles& P = sp[k];
+        int64_t* dtoff = reinterpret_cast<int64_t*>(st + H.off_toff[k]);
+        e = hipMemcpyAsync(dtoff, toff[k].data(), toff[k].size() * 8, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess || H.n[k] == 0) continue;
+        PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
+        PBuf<R> out = sections<R>(st + H.off_part[k], H.n[k], D);
+        k_ckpt_pack<R, D><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], dtoff, P.tile_cap, out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(st + H.off_B, f->B, 3 * h->L.ncent * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dst, st, H.total, hipMemcpyDefault, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    hipFree(st);
+    if (e == hipSuccess) e = e2;
+    return hip_check(h, e, "checkpoint");
+}
+
+template <typename R, int D>
+int restore_impl(fs_handle* h, fs_particles* sp, fs_fields* f, const void* src, int64_t bytes, hipStream_t s) {
+    CkptHeader H;
+    if (bytes < kCkptHead) return fail(h, FS_EINVAL, "checkpoint too short");
+    hipError_t e = hipMemcpy(&H, src, sizeof(H), hipMemcpyDefault);
+    if (e != hipSuccess) return hip_check(h, e, "checkpoint header");
+    const fs_config& c = h->cfg;
+    const int nsp = h->has_cr ? 2 : 1;
+    if (std::memcmp(H.magic, kCkptMagic, 8) != 0 || H.version != 1) return fail(h, FS_EINVAL, "not a checkpoint");
+    if (H.precision != c.precision || H.dim != c.dim || H.nx != c.nx || H.ny != (int32_t)h->L.nyc ||
+        H.nz != (int32_t)h->L.nzc || H.shape != c.shape || H.nsp != nsp || H.ntiles != h->L.ntiles ||
+        H.tile_cap[0] != h->L.tile_cap[0] || H.tile_cap[1] != h->L.tile_cap[1] || H.ncent != h->L.ncent ||
+        H.c_light != c.c_light || H.seed != c.seed)
+        return fail(h, FS_EINVAL, "checkpoint of a different configuration");
+    if (H.total > bytes || H.next_id < 0 || H.next_id > (int64_t)UINT32_MAX + 1)
+        return fail(h, FS_EINVAL, "checkpoint truncated or corrupt");
+    // every offset and count is checked here, before a kernel reads the blob
+    const int64_t nt = h->L.ntiles;
+    const int rb = c.precision == 64 ? 8 : 4;
+    std::vector<int64_t> toff[2];
+    int64_t end = kCkptHead;
+    for (int k = 0; k < nsp; ++k) {
+        if (H.n[k] < 0 || H.off_toff[k] != end) return fail(h, FS_EINVAL, "checkpoint corrupt");
+        end += round_up((nt + 1) * 8, 256);
+        if (H.off_part[k] != end) return fail(h, FS_EINVAL, "checkpoint corrupt");
+        end += part_block_bytes(H.n[k], c.dim, rb);
+        if (end > H.total) return fail(h, FS_EINVAL, "checkpoint corrupt");
+        toff[k].resize(nt + 1);
+        e = hipMemcpy(toff[k].data(), static_cast<const char*>(src) + H.off_toff[k], (nt + 1) * 8, hipMemcpyDefault);
+        if (e != hipSuccess) return hip_check(h, e, "checkpoint offsets");
+        if (toff[k][0] != 0 || toff[k][nt] != H.n[k]) return fail(h, FS_EINVAL, "checkpoint corrupt");
+        for (int64_t t = 0; t < nt; ++t)
+            if (toff[k][t + 1] < toff[k][t] || toff[k][t + 1] - toff[k][t] > sp[k].tile_cap)
+                return fail(h, FS_EINVAL, "checkpoint corrupt");
+    }
+    if (H.off_B != end || end + round_up(3 * h->L.ncent * 8, 256) != H.total)
+        return fail(h, FS_EINVAL, "checkpoint corrupt");
+    char* st = nullptr;
+    if (hipMalloc((void**)&st, H.total) != hipSuccess) return fail(h, FS_EDEVICE, "restore staging");
+    e = hipMemcpyAsync(st, src, H.total, hipMemcpyDefault, s);
+    for (int k = 0; k < nsp && e == hipSuccess; ++k) {
+        fs_particles& P = sp[k];
+        PBuf<R> in = sections<R>(st + H.off_part[k], H.n[k], D);
+        PBuf<R> out = sections<R>(P.buf[P.cur], P.capacity, D);
+        k_ckpt_unpack<R, D><<<(unsigned)nt, 256, 0, s>>>(h->G, in, reinterpret_cast<const int64_t*>(st + H.off_toff[k]),
+                                                         P.tile_cap, out, P.tile_count[P.cur]);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(P.count, &H.n[k], 8, hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(f->B, st + H.off_B, 3 * h->L.ncent * 8, hipMemcpyDeviceToDevice, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    hipFree(st);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_check(h, e, "restore");
+    h->next_id = H.next_id;
+    return FS_OK;
+}
+
 template <typename R> int diag_impl(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out, double* prof,
                                     hipStream_t s) {
     const long nc = h->L.ncent;
@@ -1216,6 +1357,34 @@ int fs_read_particles(fs_handle* h, const fs_particles* sp, int64_t* n, int64_t*
     if (!h || !sp || !n) return fail(h, FS_EINVAL, "bad argument");
     if (cell3 && (!off3 || !v3 || !id)) return fail(h, FS_EINVAL, "NULL array");
     FS_DISPATCH_RD(h, (read_impl<R, D>(h, sp, n, cell3, off3, v3, id, s)));
+}
+
+int fs_checkpoint_bytes(fs_handle* h, const fs_particles* sp, int64_t* bytes, hipStream_t s) {
+    if (!h || !sp || !bytes) return fail(h, FS_EINVAL, "NULL argument");
+    if (int rc = check_particles(h, sp)) return rc;
+    CkptHeader H;
+    std::vector<int64_t> toff[2];
+    if (int rc = ckpt_plan(h, sp, H, toff, s)) return rc;
+    *bytes = H.total;
+    return FS_OK;
+}
+
+int fs_checkpoint(fs_handle* h, const fs_particles* sp, const fs_fields* f, void* dst, int64_t cap_bytes,
+                  hipStream_t s) {
+    if (!h || !sp || !f || !dst) return fail(h, FS_EINVAL, "NULL argument");
+    if (int rc = check_particles(h, sp)) return rc;
+    if (int rc = check_fields(h, f)) return rc;
+    FS_DISPATCH_RD(h, (checkpoint_impl<R, D>(h, sp, f, dst, cap_bytes, s)));
+}
+
+int fs_restore(fs_handle* h, fs_particles* sp, fs_fields* f, const void* src, int64_t bytes, hipStream_t s) {
+    if (!h || !sp || !f || !src) return fail(h, FS_EINVAL, "NULL argument");
+    if (int rc = check_particles(h, sp)) return rc;
+    if (int rc = check_fields(h, f)) return rc;
+    auto load = [&]() -> int { FS_DISPATCH_RD(h, (restore_impl<R, D>(h, sp, f, src, bytes, s))); };
+    if (int rc = load()) return rc;
+    if (int rc = fs_deposit_moments(h, sp, f, s)) return rc;
+    return fs_refresh_fields(h, f, s);
 }
 
 int fs_phase_space(fs_handle* h, const fs_particles* sp, int32_t species, int32_t component,

@@ -815,6 +815,48 @@ __global__ void k_set_i64(int64_t* p, int64_t v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
 
+// Checkpoint: the live ions of each tile, packed tile after tile at the
+// offsets toff, in the particle buffers' own section layout.
+template <typename R, int D>
+__global__ void k_ckpt_pack(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, const int64_t* __restrict__ toff,
+                            int64_t cap, PBuf<R> out) {
+    const int tile = blockIdx.x;
+    const int lo = cnt[tile];
+    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const long src = bin_slot(tile, cap, lo, i), dst = toff[tile] + i;
+        out.cell[dst] = in.cell[src];
+#pragma unroll
+        for (int d = 0; d < D; ++d) out.off[d][dst] = in.off[d][src];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out.v[c][dst] = in.v[c][src];
+        out.id[dst] = in.id[src];
+    }
+}
+
+// Restore: tile t's packed ions back into the bottom of its bin (counts lo =
+// n_t, hi = 0).  toff has been checked on the host: ascending, n_t <= cap.
+template <typename R, int D>
+__global__ void k_ckpt_unpack(Geo G, PBuf<R> in, const int64_t* __restrict__ toff, int64_t cap, PBuf<R> out,
+                              int32_t* cnt) {
+    const int tile = blockIdx.x;
+    const long b = toff[tile];
+    const int n = (int)(toff[tile + 1] - b);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const long src = b + i, dst = (long)tile * cap + i;
+        out.cell[dst] = in.cell[src];
+#pragma unroll
+        for (int d = 0; d < D; ++d) out.off[d][dst] = in.off[d][src];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out.v[c][dst] = in.v[c][src];
+        out.id[dst] = in.id[src];
+    }
+    if (threadIdx.x == 0) {
+        cnt[tile] = n;
+        cnt[G.ntiles + tile] = 0;
+    }
+}
+
 // Copy the live particles of every tile to flat arrays (host offsets).
 template <typename R, int D>
 __global__ void k_compact(Geo G, PBuf<R> in, const int32_t* cnt, const int64_t* offs, int64_t cap,

@@ -133,6 +133,9 @@ def library():
         L.fs_diagnostics.argtypes = [vp, P, F, vp, vp, vp]
         L.fs_phase_space.argtypes = [vp, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
         L.fs_bperp_spectrum.argtypes = [vp, F, vp, vp]
+        L.fs_checkpoint_bytes.argtypes = [vp, P, vp, vp]
+        L.fs_checkpoint.argtypes = [vp, P, F, vp, i64, vp]
+        L.fs_restore.argtypes = [vp, P, F, vp, i64, vp]
         L.fs_timing_enable.argtypes = [vp, i32]
         L.fs_timing_read.argtypes = [vp, vp, vp, vp]
         R, A = C.POINTER(FsRecord), C.POINTER(FsAdjoint)
@@ -148,7 +151,7 @@ def exported_symbols():
     return ["fs_layout", "fs_create", "fs_destroy", "fs_last_error", "fs_init_plasma", "fs_step",
             "fs_deposit_moments", "fs_apply_faux_shock", "fs_field_update", "fs_refresh_fields",
             "fs_load_particles", "fs_read_particles", "fs_set_clock", "fs_next_id", "fs_diagnostics",
-            "fs_phase_space", "fs_bperp_spectrum",
+            "fs_phase_space", "fs_bperp_spectrum", "fs_checkpoint_bytes", "fs_checkpoint", "fs_restore",
             "fs_timing_enable", "fs_timing_read", "fs_step_record", "fs_adjoint_step", "fs_adjoint_init"]
 
 
@@ -408,6 +411,31 @@ class Simulation:
                                             nb, _ptr(e), _ptr(counts), self.stream))
         torch.cuda.synchronize(self.device)
         return counts.cpu().numpy()
+
+    def checkpoint(self, device: bool = False):
+        """The current state (ions, B, id counter) as a byte blob: a numpy
+        array on the host, or a uint8 tensor on the device."""
+        nb = C.c_int64(0)
+        self._check(self.lib.fs_checkpoint_bytes(self.h, self.sp, C.byref(nb), self.stream))
+        if device:
+            buf = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+            ptr = _ptr(buf)
+        else:
+            buf = np.empty(nb.value, dtype=np.uint8)
+            ptr = buf.ctypes.data
+        self._check(self.lib.fs_checkpoint(self.h, self.sp, C.byref(self.f), ptr, nb.value, self.stream))
+        return buf
+
+    def restore(self, blob):
+        """Load a checkpoint (numpy array or device tensor) written by a run
+        of the same layout; E and the moments are recomputed."""
+        if isinstance(blob, torch.Tensor):
+            ptr, n = _ptr(blob), blob.numel() * blob.element_size()
+        else:
+            blob = np.ascontiguousarray(blob, dtype=np.uint8)
+            ptr, n = blob.ctypes.data, blob.nbytes
+        self._check(self.lib.fs_restore(self.h, self.sp, C.byref(self.f), ptr, int(n), self.stream))
+        torch.cuda.synchronize(self.device)
 
     def bperp_spectrum(self) -> np.ndarray:
         """Mean over (y, z) lines of |B^_y(k)|^2 + |B^_z(k)|^2, k = 0 .. nx/2."""

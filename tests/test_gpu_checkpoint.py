@@ -1,0 +1,102 @@
+"""Checkpoint and restore through the C ABI: a run restored from a
+checkpoint continues bit for bit as the original (ions compared by id,
+every field and moment array compared exactly), from host and device
+blobs; a checkpoint of another configuration, a truncated one and a
+corrupt one are refused with FS_EINVAL and leave the state unchanged.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2507_14282_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+COUNTS = ("incident", "reflected", "transmitted", "open_removed", "escaped", "injected_th", "injected_cr")
+
+
+def lib():
+    from paper_2507_14282_amd import fshybrid
+    return fshybrid
+
+
+def by_id(d):
+    o = np.argsort(d["id"], kind="stable")
+    return {k: v[o] for k, v in d.items()}
+
+
+def params(case):
+    if case == "1d_fp64_fs":
+        return W.preset("cfg1", nx=128, ppc=32)
+    if case == "2d_fp32_cr":
+        return W.params(dim=2, nx=64, ny=16, dx=0.5, ppc=8, n_cr=0.01, ppc_cr=8, wall_th="open",
+                        wall_cr="faux_shock", n_modes=3, mode_amp=0.02, seed=8)
+    if case == "3d_fp32":
+        return W.params(dim=3, nx=32, ny=16, nz=8, dx=1.0, ppc=8, theta_deg=45.0, seed=9)
+    return W.params(dim=2, nx=64, ny=16, dx=0.5, ppc=8, n_cr=0.01, ppc_cr=8, wall_th="open",
+                    wall_cr="faux_shock", c_light=150.0, seed=10)
+
+
+@pytest.mark.parametrize("case", ["1d_fp64_fs", "2d_fp32_cr", "3d_fp32", "2d_rel_cr"])
+def test_restore_continues_bit_for_bit(case):
+    F = lib()
+    p = params(case)
+    a = F.Simulation(p, "cuda:0")
+    a.init_plasma()
+    for s in range(12):
+        a.step(s)
+    blob = a.checkpoint(device=case == "3d_fp32")
+    b = F.Simulation(p, "cuda:0")
+    b.restore(blob)
+    assert b.next_id == a.next_id
+    for s in range(12, 24):
+        sa, sb = a.step(s), b.step(s)
+        for k in COUNTS:
+            assert sa[k] == sb[k], (s, k)
+    for sp in range(2 if p["n_cr"] > 0 else 1):
+        ga, gb = by_id(a.particles(sp)), by_id(b.particles(sp))
+        assert len(ga["id"]) > 0
+        for k in ("id", "cell", "off", "v"):
+            assert np.array_equal(ga[k], gb[k]), (sp, k)
+        assert np.array_equal(a.moments(sp), b.moments(sp))
+    assert np.array_equal(a.get_B(), b.get_B())
+    assert np.array_equal(a.get_E(), b.get_E())
+
+
+def test_restore_refuses_other_configurations_and_damage():
+    F = lib()
+    p = params("2d_fp32_cr")
+    a = F.Simulation(p, "cuda:0")
+    a.init_plasma()
+    for s in range(5):
+        a.step(s)
+    blob = a.checkpoint()
+    b = F.Simulation(p, "cuda:0")
+    b.init_plasma()
+    before = by_id(b.particles(0))
+    B0 = b.get_B()
+
+    def refused(bl, sim=b):
+        with pytest.raises(F.FsError) as e:
+            sim.restore(bl)
+        assert e.value.code == F.FS_EINVAL
+
+    other = F.Simulation(dict(p, nx=96), "cuda:0")
+    refused(blob, other)
+    refused(blob[:-256])                     # truncated
+    bad = blob.copy()
+    bad[0] ^= 0xFF                           # not a checkpoint
+    refused(bad)
+    bad = blob.copy()
+    bad[256 + 8:256 + 16] = np.frombuffer(np.int64(1 << 40).tobytes(), np.uint8)   # tile offset past the end
+    refused(bad)
+    bad = blob.copy()
+    bad[256 + 16:256 + 24] = np.frombuffer(np.int64(-3).tobytes(), np.uint8)       # offsets not ascending
+    refused(bad)
+    after = by_id(b.particles(0))
+    for k in ("id", "cell", "off", "v"):
+        assert np.array_equal(before[k], after[k])
+    assert np.array_equal(B0, b.get_B())
+    b.restore(blob)                          # the intact one is accepted
+    assert b.count(0) == a.count(0) and b.count(1) == a.count(1)
