@@ -58,8 +58,14 @@ extern "C" {
 #define FS_XBC_BOX       0      /* inflow at x = 0, wall at x = L */
 #define FS_XBC_PERIODIC  1      /* periodic x (test boxes) */
 
-/* fs_step flags */
-#define FS_PUSH    1u   /* gather + Boris + move + boundaries + FS wall */
+/* fs_step flags.  The wall events and the re-binning of the ions are part
+ * of FS_PUSH: the wall runs on the crosser list the push builds, within the
+ * same call, and every pushed ion is written straight into its destination
+ * tile's bin (so there is no separate wall or binning flag, and a push
+ * without its wall, which would lose the crossers, cannot be asked for).
+ * Diagnostics are their own calls (fs_diagnostics, fs_phase_space,
+ * fs_bperp_spectrum). */
+#define FS_PUSH    1u   /* gather + Boris + move + boundaries + FS wall + binning */
 #define FS_INJECT  4u   /* thermal injection at x = 0, CR injection at x = L */
 #define FS_DEPOSIT 8u   /* fixed-point moments at the new positions */
 #define FS_FIELD  16u   /* SSP-RK3 Faraday update with frozen moments, then Ohm */
