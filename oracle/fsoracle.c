@@ -731,7 +731,8 @@ static void deposit_species(ora_sim* s, int k, ora_stats* st)
 
 static double species_weight(const ora_sim* s, int k)
 {
-    if (k == 0) return 1.0 / (double)s->c.ppc;
+    /* a species with no ions per cell contributes no moments: weight 0 */
+    if (k == 0) return s->c.ppc > 0 ? 1.0 / (double)s->c.ppc : 0.0;
     return s->c.alpha_cr * s->c.n_cr / (double)s->c.ppc_cr;
 }
 

@@ -684,7 +684,8 @@ static void snap_free(snap* S)
 
 static double species_w(const geo* G, int k)
 {
-    return k == 0 ? 1.0 / (double)G->c.ppc : G->c.alpha_cr * G->c.n_cr / (double)G->c.ppc_cr;
+    /* a species with no ions per cell contributes no moments: weight 0 */
+    return k == 0 ? (G->c.ppc > 0 ? 1.0 / (double)G->c.ppc : 0.0) : G->c.alpha_cr * G->c.n_cr / (double)G->c.ppc_cr;
 }
 
 /* Transpose of fluid_from_moments: lam_fn, lam_fg -> lam_Mc per species;

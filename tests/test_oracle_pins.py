@@ -528,3 +528,27 @@ def test_div_b_round_off_3d():
     for _ in range(10):
         o.step()
     assert o.diag()["max_divB"] < 1e-12
+
+
+# --------------------------------------------------------------------------
+# degenerate case: an empty box stays exactly uniform
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_empty_box_stays_exactly_uniform(dim):
+    """No ions at all: n = n_floor everywhere, J = 0 and grad p_e = 0 for a
+    uniform B, so E = 0 exactly and B stays uniform (identical in every
+    cell) and equal to B0 up to the rounding of the RK3 weights 1/3, 2/3."""
+    p = W.params(dim=dim, nx=16, ny=8, nz=4, dx=0.5, ppc=0, xbc="periodic", inject=False, theta_deg=30.0,
+                 beta_e=1.0)
+    o = O.Oracle(p)
+    o.init()
+    B0 = o.B().copy()
+    for _ in range(5):
+        st = o.step()
+        assert st["injected_th"] == 0 and o.count(0) == 0
+    B = o.B()
+    assert np.all(B == B[0])
+    assert np.max(np.abs(B - B0)) < 1e-15
+    assert np.all(o.E() == 0.0)
+    d = o.diag()
+    assert d["kinetic_th"] == 0.0 and np.isfinite(d["field_energy"])
