@@ -4,7 +4,8 @@ compared on binned statistics after many steps rather than state by state.
 
 Two boxes shaped like the paper's runs, reduced so that the oracle finishes
 in seconds: the 1D box with TSC shapes and a 1% CR population released from
-the wall (1500 steps), and the 2D box with M_A = 30 and CRs (500 steps).
+the wall (1500 steps), and the 2D box with M_A = 30 and CRs (500 steps);
+each also with the relativistic push.
 Compared within 2%:
   * the transverse magnetic energy profile dB^2(x) = (B_y - B0_y)^2 +
     (B_z - B0_z)^2 averaged over 8 slabs in x;
@@ -26,6 +27,12 @@ pytestmark = pytest.mark.gpu
 CASES = {
     "1d_tsc_cr": (W.preset("cfg2", nx=512, ppc=64, ppc_cr=64, seed=31, n_modes=4, mode_amp=0.05), 1500),
     "2d_cr": (W.preset("cfg3", nx=128, ny=32, ppc=16, ppc_cr=16, seed=33, n_modes=4, mode_amp=0.05), 500),
+    # the same boxes with the relativistic push (CR Lorentz factors ~1.25 and
+    # ~1.1); the spectra are then of |u|, the momentum per unit mass
+    "1d_tsc_cr_rel": (W.preset("cfg2", nx=512, ppc=64, ppc_cr=64, seed=35, n_modes=4, mode_amp=0.05,
+                               c_light=150.0), 1500),
+    "2d_cr_rel": (W.preset("cfg3", nx=128, ny=32, ppc=16, ppc_cr=16, seed=37, n_modes=4, mode_amp=0.05,
+                           c_light=300.0), 500),
 }
 
 
