@@ -1401,7 +1401,8 @@ int fs_phase_space(fs_handle* h, const fs_particles* sp, int32_t species, int32_
         using R = decltype(tag);
         PBuf<R> b = sections<R>(P.buf[P.cur], P.capacity, h->cfg.dim);
         k_phase_space<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, b, P.tile_count[P.cur], (int)h->L.ntiles,
-                                                              P.tile_cap, component, x_cells_per_bin, nb, edges,
+                                                              P.tile_cap, component, x_cells_per_bin, (int)nxb, nb,
+                                                              edges,
                                                               reinterpret_cast<unsigned long long*>(counts));
     };
     if (h->cfg.precision == 32) run(float());

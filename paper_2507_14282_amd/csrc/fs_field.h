@@ -974,7 +974,8 @@ __global__ __launch_bounds__(256) void k_diag_kin(PBuf<R> in, const int32_t* cnt
 // are not counted.
 template <typename R>
 __global__ __launch_bounds__(256) void k_phase_space(Geo G, PBuf<R> in, const int32_t* cnt, int ntiles, int64_t cap,
-                                                     int comp, int xpb, int nb, const double* __restrict__ edges,
+                                                     int comp, int xpb, int nxb, int nb,
+                                                     const double* __restrict__ edges,
                                                      unsigned long long* __restrict__ counts) {
 #pragma clang fp contract(off)
     const int tile = blockIdx.x;
@@ -1000,7 +1001,10 @@ __global__ __launch_bounds__(256) void k_phase_space(Geo G, PBuf<R> in, const in
             if (edge(mid) <= q) a = mid;
             else b = mid;
         }
-        atomicAdd(counts + (long)(cell_x(in.cell[src], G) / xpb) * nb + a, 1ull);
+        // a cell outside the box (only a corrupt state has one) is not counted
+        const int xb = cell_x(in.cell[src], G) / xpb;
+        if ((unsigned)xb >= (unsigned)nxb) continue;
+        atomicAdd(counts + (long)xb * nb + a, 1ull);
     }
 }
 
