@@ -180,3 +180,81 @@ def test_full_size_step_sampled_parity(name, c_light):
     d = sim.diagnostics()
     assert d["max_divB"] < 1e-12
     print(f"  sampled Ohm: {len(k)} nodes of {nn}, max |dE| = {np.max(np.abs(Eg - Ee)):.2e}", flush=True)
+
+
+def wall_threshold2(p, step, pid):
+    """T^2 of the faux-shock decision for ion pid at `step` (Philox draw keyed
+    (seed, WALL), counter (step, id, 0, 0); m = max(U1, U2))."""
+    r = O.philox([int(step), int(pid), 0, 0], [int(p["seed"]), 4])
+    U = [((int(x) >> 11) + 0.5) * 2.0**-53 for x in r]
+    m = max(U[0], U[1])
+    u2 = float(p["u_sh"]) / float(p["r"])
+    T = u2 * (1.0 + m) / (1.0 - m)
+    return T * T
+
+
+@pytest.mark.parametrize("name", ["cfg4", "cfg2"])
+def test_full_size_wall_events(name):
+    """Every ion of the tile column at the wall, pushed by the oracle in the
+    GPU's own gather grid; the crossers go through the oracle's wall.  After
+    the GPU step, transmitted (and open-wall) crossers are gone and reflected
+    ones are back in the box with the oracle's velocity and re-entry point.
+    A decision may differ only at a certified straddle: the oracle's position
+    within 1e-5 cells of the wall, or |w|^2 within 1e-5 of the threshold T^2."""
+    p = W.preset(name)
+    print(f"full-size wall {name}", flush=True)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    for s in range(2):
+        sim.step(s, stats=False)
+    torch.cuda.synchronize()
+    L = sim.L
+    ntx = int(L.ntile[0])
+    wall_tiles = [t for t in range(int(L.ntiles)) if tile_coords(L, t)[0] == ntx - 1]
+    g = sim.gather.double().cpu().numpy()
+    E3, Bb3 = np.ascontiguousarray(g[:, 0:3]), np.ascontiguousarray(g[:, 4:7])
+    del g
+    nsp = 2 if sim.has_cr else 1
+    before = {}
+    for sp in range(nsp):
+        sec = sim.sections(sp)
+        before[sp] = read_ions(sim, sec, live_slots(sec, wall_tiles))
+    st = sim.step(2)
+    assert st["flags"] == 0 and st["saturated"] == 0, st
+    nx = int(p["nx"])
+    u2 = float(p["u_sh"]) / float(p["r"])
+    total = {"cross": 0, "refl": 0, "straddle": 0}
+    for sp in range(nsp):
+        c0, o0, v0, id0 = before[sp]
+        ce, oe, ve = O.push_sample(p, E3, Bb3, c0, o0, v0)
+        cross = ce[:, 0] >= nx
+        ids, vc = id0[cross], ve[cross]
+        delta = (ce[cross, 0] - nx) + oe[cross, 0]
+        out, vnew, xinew = O.wall_list(p, 2, sp, ids.astype(np.uint64), delta, vc)
+        sec = sim.sections(sp)
+        c1, o1, v1, id1 = read_ions(sim, sec, live_slots(sec, wall_tiles))
+        where = {int(i): k for k, i in enumerate(id1)}
+        vt = max(float(np.max(np.abs(vc))) if len(vc) else 1.0, 1.0)
+        # ions the GPU may have seen crossing while the oracle did not
+        near = (~cross) & (np.abs(ce[:, 0] + oe[:, 0] - nx) < 1e-5)
+        total["straddle"] += int(near.sum())
+        for j in range(len(ids)):
+            pid = int(ids[j])
+            present, expect = pid in where, out[j] == 1
+            if present != expect:
+                w = vc[j] - np.array([u2, 0.0, 0.0])
+                w2 = float(w @ w)
+                ok = delta[j] < 1e-5 or abs(w2 / wall_threshold2(p, 2, pid) - 1.0) < 1e-5
+                assert ok, (sp, pid, present, expect, delta[j])
+                total["straddle"] += 1
+                continue
+            if present:
+                k = where[pid]
+                assert np.max(np.abs(v1[k] - vnew[j])) <= 1e-5 * vt, (sp, pid, v1[k], vnew[j])
+                assert abs((c1[k, 0] + o1[k, 0]) - xinew[j]) <= 1e-5, (sp, pid)
+                total["refl"] += 1
+        total["cross"] += len(ids)
+    print(f"  {total['cross']} crossers, {total['refl']} reflected, {total['straddle']} certified straddles",
+          flush=True)
+    assert total["cross"] > 0
+    assert total["straddle"] <= max(2, total["cross"] // 1000)
