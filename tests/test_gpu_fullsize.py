@@ -258,3 +258,51 @@ def test_full_size_wall_events(name):
           flush=True)
     assert total["cross"] > 0
     assert total["straddle"] <= max(2, total["cross"] // 1000)
+
+
+@pytest.mark.parametrize("name", ["cfg4", "cfg3"])
+def test_full_size_injection(name):
+    """The ions one GPU step injects at the full benchmark sizes (thermal
+    ions through every transverse cell of x = 0, CRs from the wall) against
+    the oracle injecting into an empty box of the same size with the same
+    step and id counter: equal counts and ids, equal cells (a difference
+    only where the position lies within rounding of a cell boundary), FP32
+    offsets and velocities within their rounding."""
+    p = W.preset(name)
+    print(f"full-size injection {name}", flush=True)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    for s in range(2):
+        sim.step(s, stats=False)
+    nid0 = sim.next_id
+    st = sim.step(2)
+    assert st["flags"] == 0, st
+    L = sim.L
+    ntx = int(L.ntile[0])
+    edge_tiles = [t for t in range(int(L.ntiles)) if tile_coords(L, t)[0] in (0, ntx - 1)]
+    o = O.Oracle(p)
+    o.set_clock(2, nid0)
+    so = o.step(O.INJECT)
+    assert so["injected_th"] == st["injected_th"] > 0
+    assert so["injected_cr"] == st["injected_cr"]
+    dim = int(p["dim"])
+    for sp in range(2 if sim.has_cr else 1):
+        sec = sim.sections(sp)
+        c1, o1, v1, id1 = read_ions(sim, sec, live_slots(sec, edge_tiles))
+        new = id1 >= nid0
+        g = np.argsort(id1[new])
+        cg, og, vg, ig = c1[new][g], o1[new][g], v1[new][g], id1[new][g]
+        r = o.particles(sp)
+        ro = np.argsort(r["id"])
+        assert np.array_equal(ig, r["id"][ro].astype(np.int64)), sp
+        xo = r["cell"][ro][:, :dim] + r["off"][ro][:, :dim]
+        xg = cg[:, :dim] + og[:, :dim]
+        assert np.max(np.abs(xg - xo)) <= 1e-5, sp
+        mism = np.any(cg[:, :dim] != r["cell"][ro][:, :dim], axis=1)
+        if mism.any():
+            fr = xo[mism] - np.floor(xo[mism])
+            assert np.all(np.minimum(fr, 1 - fr) < 1e-5), sp
+        vt = float(np.max(np.abs(r["v"])))
+        assert np.max(np.abs(vg - r["v"][ro])) <= 1e-6 * vt, sp
+        print(f"  species {sp}: {len(ig)} injected ions match, {int(mism.sum())} certified cell straddles", flush=True)
+    assert sim.next_id == o.next_id
