@@ -342,8 +342,10 @@ __device__ __forceinline__ void load_ion(const PBuf<R>& in, long src, Ion<R, D>&
 // that moved further go straight to the global grid) and write each ion to
 // the bin of its destination tile.
 // ---------------------------------------------------------------------------
+// The relativistic CIC FP32 kernel is held to 6 waves per SIMD (<= 80 VGPRs,
+// which it fits without scratch); left to itself it takes 82 and 5 waves.
 template <typename R, int D, int S, bool DEP, bool REL>
-__global__ __launch_bounds__(PUSH_THREADS) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
+__global__ __launch_bounds__(PUSH_THREADS, (REL && S == 1 && sizeof(R) == 4) ? 6 : 1) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
                                               int32_t* __restrict__ cnt_out, int64_t cap,
                                               const R* __restrict__ gather, unsigned long long* __restrict__ mom,
                                               XList xl, unsigned long long* __restrict__ ctr, int policy,
