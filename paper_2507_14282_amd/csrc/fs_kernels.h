@@ -342,10 +342,18 @@ __device__ __forceinline__ void load_ion(const PBuf<R>& in, long src, Ion<R, D>&
 // that moved further go straight to the global grid) and write each ion to
 // the bin of its destination tile.
 // ---------------------------------------------------------------------------
-// The relativistic CIC FP32 kernel is held to 6 waves per SIMD (<= 80 VGPRs,
-// which it fits without scratch); left to itself it takes 82 and 5 waves.
+// Minimum waves per SIMD the push is compiled for, where the kernel fits
+// without scratch (measured): 8 for the FP32 1D kernels (their SGPRs would
+// otherwise cap them at 7, i.e. 6 with 8-wave workgroups) and the FP32 2D CIC
+// ones (71 VGPRs otherwise); 6 for the relativistic 3D CIC FP32 one (82 VGPRs
+// and 5 waves otherwise).  The others take what their registers give.
+template <typename R, int D, int S, bool REL> struct PushWaves {
+    static constexpr int value =
+        sizeof(R) != 4 ? 1 : ((D == 1 || (D == 2 && S == 1)) ? 8 : ((REL && S == 1) ? 6 : 1));
+};
+
 template <typename R, int D, int S, bool DEP, bool REL>
-__global__ __launch_bounds__(PUSH_THREADS, (REL && S == 1 && sizeof(R) == 4) ? 6 : 1) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
+__global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
                                               int32_t* __restrict__ cnt_out, int64_t cap,
                                               const R* __restrict__ gather, unsigned long long* __restrict__ mom,
                                               XList xl, unsigned long long* __restrict__ ctr, int policy,
