@@ -256,7 +256,7 @@ def adjoint_timing(steps=400, K=20):
     t2 = time.perf_counter()
     return {
         "workload": f"1D3V adjoint box {p['nx']} cells dx={p['dx']} d_i, {p['ppc']} ppc + CRs "
-                    f"(n_cr={p['n_cr']}), {p['n_modes']} Fourier modes, {steps} steps, checkpoint every {K}",
+                    f"(n_cr={p['n_cr']}), {p['n_modes']} Fourier modes, {steps} steps, checkpoint every {run.K_run}",
         "loss": "precursor sum(By^2+Bz^2) over x in [L/2, L]",
         "params": "u_sh, alpha_cr, 64 amplitudes",
         "dtype": "f32 particles / f64 fields",

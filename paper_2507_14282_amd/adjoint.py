@@ -89,6 +89,32 @@ def _recorded_step(sim: F.Simulation, n: int, a: _State, b: _State, rec: F.FsRec
     b.next_id = sim.next_id
 
 
+def checkpoint_interval(nsteps: int, K: int, state_bytes: int, free_bytes: int, share: float = 0.8) -> int:
+    """Checkpoint interval for a reverse pass that must fit in memory.
+
+    The forward keeps ceil(nsteps / k) checkpoints and the reverse a tape of
+    k states, each state_bytes large.  Returns the largest k <= K for which
+    (ceil(nsteps / k) + k) states fit in `share` of free_bytes.  Raises
+    MemoryError if no interval fits.  The gradient does not depend on k."""
+    nsteps, K = max(1, int(nsteps)), max(1, int(K))
+    budget = share * float(free_bytes)
+    for k in range(min(K, nsteps), 0, -1):
+        if (-(-nsteps // k) + k) * float(state_bytes) <= budget:
+            return k
+    raise MemoryError(f"a reverse pass over {nsteps} steps needs at least "
+                      f"{2 * (nsteps ** 0.5) * state_bytes / 1e9:.1f} GB of checkpoints and tape "
+                      f"({state_bytes / 1e9:.2f} GB per state), {free_bytes / 1e9:.1f} GB are free")
+
+
+def _state_bytes(sim: F.Simulation, nsp: int) -> int:
+    """Bytes of one checkpoint / tape state of this simulation."""
+    t = [sim.B, sim.E, sim.gather] + list(sim.mom[:nsp])
+    for k in range(nsp):
+        cur = int(sim.sp[k].cur)
+        t += [sim.bufs[k][cur], sim.cnts[k][cur]]
+    return int(sum(x.numel() * x.element_size() for x in t))
+
+
 class AdjointRun:
     """Forward and reverse passes of N steps of one configuration.
 
@@ -115,9 +141,13 @@ class AdjointRun:
         if int(p["n_modes"]) > 0:
             a = torch.as_tensor(np.asarray(amps, dtype=np.float64), device=self.device)
         sim.init_plasma(a)
+        # the interval actually used: the requested one, or less if the
+        # checkpoints and the tape would not fit in the device's free memory
+        free, _ = torch.cuda.mem_get_info(self.device)
+        self.K_run = checkpoint_interval(self.nsteps, self.K, _state_bytes(sim, self.nsp), free)
         self.checkpoints = {}
         for n in range(self.nsteps):
-            if n % self.K == 0:
+            if n % self.K_run == 0:
                 self.checkpoints[n] = _State(sim, self.nsp)
             sim.step(n, stats=False)
         self.nid = sim.next_id
@@ -164,10 +194,11 @@ class AdjointRun:
         lBv[2, :, nx // 2:] = 2.0 * B[2, :, nx // 2:]
         grads = torch.zeros(2 + int(self.p["n_modes"]), dtype=torch.float64, device=self.device)
         gptr = C.c_void_p(grads.data_ptr())
-        refl = [torch.zeros(self.lam.nid, dtype=torch.uint8, device=self.device) for _ in range(self.K)]
-        slots = [_State(sim, self.nsp, copy=False) for _ in range(self.K)]
+        K = self.K_run
+        refl = [torch.zeros(self.lam.nid, dtype=torch.uint8, device=self.device) for _ in range(K)]
+        slots = [_State(sim, self.nsp, copy=False) for _ in range(K)]
         for s0 in sorted(self.checkpoints, reverse=True):
-            s1 = min(s0 + self.K, self.nsteps)
+            s1 = min(s0 + K, self.nsteps)
             ck = self.checkpoints[s0]
             sim.set_clock(ck.next_id)
             tape, recs = [ck], []
