@@ -29,6 +29,9 @@ CASES = {
     "1d_tsc": dict(dim=1, nx=40, dx=0.5, shape="tsc"),
     "2d_cic": dict(dim=2, nx=24, ny=16, dx=0.5, shape="cic"),
     "3d_cic": dict(dim=3, nx=16, ny=16, nz=12, dx=1.0, shape="cic"),
+    # the relativistic push (c/v_A = 150: CR Lorentz factors up to ~1.3)
+    "2d_cic_rel": dict(dim=2, nx=24, ny=16, dx=0.5, shape="cic", c_light=150.0),
+    "3d_cic_rel": dict(dim=3, nx=16, ny=16, nz=12, dx=1.0, shape="cic", c_light=150.0),
 }
 
 
