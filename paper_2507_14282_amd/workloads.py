@@ -62,6 +62,21 @@ PRESETS = {
                  u_sh=20.0, beta_i=1.0, theta_deg=0.0, n_cr=0.01,
                  cr_w=89.44271909999159, wall_th="open", wall_cr="faux_shock",
                  n_modes=64, mode_amp=1e-3, seed=1005, precision=32, steps=400),
+    # Reflecting-wall (RW) boxes, the paper's benchmark setup (Sec. 3, Table 1
+    # Runs C and 3D): the frame is the downstream one, the flow enters at
+    # u_sh = 20 v_A and the thermal ions bounce off a mirror at x = L, so a
+    # real shock forms there and runs upstream at about u_sh / (r - 1).  No
+    # CRs are injected.  The downstream holds r ~ 3-4 times the inflow
+    # density (overshoots reach ~5 over a tile), hence six-fold bins.
+    # rw1: 1D, theta_Bn = 80 deg as in Run 3D (a quasi-perpendicular shock
+    # forms within ~2 / Omega_ci), sized for the oracle.
+    "rw1": dict(dim=1, nx=512, dx=0.5, dt=0.005, ppc=32, u_sh=20.0, beta_i=1.0,
+                theta_deg=80.0, n_cr=0.0, wall_th="specular", seed=1011,
+                precision=32, steps=2400, cap_factor_th=6.0),
+    # rw2: 2D, theta_Bn = 0 as in Run C, on the 2D box's grid.
+    "rw2": dict(dim=2, nx=8192, ny=512, dx=0.5, dt=0.005, ppc=16, u_sh=20.0,
+                beta_i=1.0, theta_deg=0.0, n_cr=0.0, wall_th="specular",
+                seed=1012, precision=32, steps=5000, cap_factor_th=6.0),
 }
 
 
