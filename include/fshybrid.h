@@ -100,7 +100,30 @@ typedef struct fs_config {
     int32_t deposit_mode;   /* 0: int64 fixed point (bit-reproducible); 1: real
                                weights, FP64 sums (the differentiable variant the
                                adjoint needs; moments then hold doubles) */
-    int32_t pad1;
+    int32_t wall_model;     /* 0: the faux-shock event of eq. (1) with the
+                               isotropic-flux kick; the five fields below are
+                               then ignored.  1: the prescribed wall, the
+                               calibration the paper leaves open (Sec. 1: return
+                               rate, anisotropy and energy gain prescribed from
+                               RW runs; Sec. 4: a boundary that may change in
+                               time), for a crosser of downstream-frame speed
+                               |w| at step s, u2(s) = u_sh / max(1, r + r_dot s dt):
+                                 returns with probability
+                                   min(1, ret_f0 (|w| / cr_w)^ret_alpha) rho^2,
+                                   rho = (|w| - u2) / (|w| + u2), 0 if |w| <= u2;
+                                 leaves with downstream-frame speed gain |w|
+                                   (four-velocity gain |W| in the relativistic
+                                   mode; no return if that is <= u2);
+                                 with direction cosine mu' into the box of pdf
+                                   ~ (mu' - a)^(1 + kappa) on (a, 1],
+                                   a = u2 / (new speed), azimuth uniform.
+                               CR injection keeps u_sh / r.  The adjoint entry
+                               points refuse it (FS_EINVAL). */
+    double ret_f0, ret_alpha;   /* return-probability factor and its power of |w| / cr_w
+                                   (ret_f0 > 0; ret_alpha != 0 needs cr_w > 0) */
+    double gain;                /* speed gain of a return, > 0 */
+    double kappa;               /* anisotropy exponent of the return direction, > -2 */
+    double r_dot;               /* d r / d t of the wall's compression ratio */
 } fs_config;
 
 /* Sizes the caller must allocate, reported by fs_layout(). */

@@ -68,6 +68,17 @@
  *     to u; CRs get the R8 downstream-frame speed cr_w, boosted to the lab.
  *     Kinetic energy is (gamma - 1) c^2 = |u|^2 / (gamma + 1) per mass.  The
  *     field update is unchanged.  c_light = 0 is the non-relativistic R4.
+ *  R12 prescribed wall (wall_model = 1): the paper leaves the return rate,
+ *     the anisotropy and the energy gain of the FS open to calibration
+ *     against RW runs (Sec. 1) and allows a boundary that changes in time
+ *     (Sec. 4).  Read as: at step s the wall uses u2 = u_sh / max(1, r +
+ *     r_dot s dt); a crosser of downstream-frame speed |w| > u2 returns with
+ *     probability min(1, f rho^2), rho = (|w| - u2) / (|w| + u2) (eq. 1 is
+ *     rho^2), f = ret_f0 (|w| / cr_w)^ret_alpha; it leaves with speed (or,
+ *     relativistic, four-velocity magnitude) multiplied by gain, in the
+ *     direction cosine mu' of pdf ~ (mu' - a)^(1 + kappa) on (a, 1], a = u2 /
+ *     new speed (kappa = 0 is R7's isotropic flux), azimuth uniform.  A
+ *     return slower than u2 cannot leave and counts as transmitted.
  */
 #include "fsoracle.h"
 #include <stdlib.h>
@@ -469,11 +480,73 @@ static int wall_event_rel(const ora_cfg* c, int64_t step, uint64_t id, double de
     return 1;
 }
 
+/* Reading R12: the wall's u2 at a step. */
+static double wall_u2(const ora_cfg* c, int64_t step)
+{
+    double r = c->r + c->r_dot * ((double)step * c->dt);
+    return c->u_sh / (r > 1.0 ? r : 1.0);
+}
+
+/* Reading R12's event, in both modes.  W is the crosser's velocity in the
+ * downstream frame (its four-velocity there in the relativistic mode, with
+ * Lorentz factor Gam), |w| = |W| / Gam its speed.  Uniform U[0] decides;
+ * U[2] and U[3] direct the return as in R7. */
+static int wall_event_prescribed(const ora_cfg* c, int64_t step, uint64_t id, double delta,
+                                 const double v[3], double vout[3], double* back)
+{
+    int rel = relativistic(c);
+    double u2 = wall_u2(c, step);
+    double cc = rel ? c->c_light * c->c_light : 1.0;
+    double gam = 1.0, g2 = 1.0, Gam = 1.0, Wx;
+    if (rel) {
+        gam = sqrt(1.0 + (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / cc);
+        g2 = 1.0 / sqrt(1.0 - (u2 * u2) / cc);
+        Gam = g2 * (gam - u2 * v[0] / cc);
+        Wx = g2 * (v[0] - u2 * gam);
+    } else {
+        Wx = v[0] - u2;
+    }
+    double Wabs = sqrt(Wx * Wx + v[1] * v[1] + v[2] * v[2]);
+    double w = Wabs / Gam;
+    if (!(w > u2)) return 0;
+    double rho = (w - u2) / (w + u2);
+    double f = c->ret_f0;
+    if (c->ret_alpha != 0.0) f = f * pow(w / c->cr_w, c->ret_alpha);
+    double P = f * (rho * rho);
+    if (P > 1.0) P = 1.0;
+    double U[4];
+    draw(c, ORA_STREAM_WALL, step, id, 0, U);
+    if (!(U[0] < P)) return 0;
+    double Wn = c->gain * Wabs;
+    double Gn = rel ? sqrt(1.0 + (Wn * Wn) / cc) : 1.0;
+    double wn = Wn / Gn;
+    if (!(wn > u2)) return 0;
+    double a = u2 / wn;
+    double q = c->kappa == 0.0 ? sqrt(U[2]) : pow(U[2], 1.0 / (2.0 + c->kappa));
+    double mu = a + (1.0 - a) * q;
+    double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    double phi = ORA_TWO_PI * U[3];
+    double Wxn = -Wn * mu;
+    vout[1] = Wn * st * cos(phi);
+    vout[2] = Wn * st * sin(phi);
+    if (rel) {
+        vout[0] = g2 * (Wxn + u2 * Gn);
+        double gl = g2 * (Gn + u2 * Wxn / cc);
+        double vx = v[0] / gam, vxn = vout[0] / gl;
+        *back = vx > 0.0 ? delta * (-vxn) / vx : 0.0;
+    } else {
+        vout[0] = u2 + Wxn;
+        *back = v[0] > 0.0 ? delta * (-vout[0]) / v[0] : 0.0;
+    }
+    return 1;
+}
+
 /* Returns 1 (reflect) or 0 (transmit).  On reflection writes the new
  * velocity and how far (in cells) the particle travels back from x = L. */
 static int wall_event(const ora_cfg* c, int64_t step, uint64_t id, double delta,
                       const double v[3], double vout[3], double* back)
 {
+    if (c->wall_model == 1) return wall_event_prescribed(c, step, id, delta, v, vout, back);
     if (relativistic(c)) return wall_event_rel(c, step, id, delta, v, vout, back);
     double u2 = c->u_sh / c->r;
     double wx = v[0] - u2, wy = v[1], wz = v[2];

@@ -38,7 +38,9 @@ typedef struct ora_cfg {
     int32_t dim, nx, ny, nz;
     int32_t ppc, ppc_cr, shape, deposit_mode; /* shape 1 CIC 2 TSC; deposit 0 fixed point, 1 continuous */
     int32_t wall_th, wall_cr, xbc, n_sub;
-    int32_t n_modes, inject, replay, pad0;
+    int32_t n_modes, inject, replay;
+    int32_t wall_model;   /* 0: eq. (1) with the R7 kick; 1: the prescribed wall (reading R12) */
+    double ret_f0, ret_alpha, gain, kappa, r_dot;
 } ora_cfg;
 
 typedef struct ora_stats {

@@ -55,7 +55,9 @@ class OraCfg(C.Structure):
         ("wall_th", C.c_int32), ("wall_cr", C.c_int32), ("xbc", C.c_int32),
         ("n_sub", C.c_int32),
         ("n_modes", C.c_int32), ("inject", C.c_int32), ("replay", C.c_int32),
-        ("pad0", C.c_int32),
+        ("wall_model", C.c_int32),
+        ("ret_f0", C.c_double), ("ret_alpha", C.c_double), ("gain", C.c_double),
+        ("kappa", C.c_double), ("r_dot", C.c_double),
     ]
 
 
@@ -83,6 +85,9 @@ def make_cfg(p: dict, deposit_mode: str = "fixed") -> OraCfg:
     c.wall_cr = WALL[p["wall_cr"]]
     c.xbc = XBC[p["xbc"]]
     c.inject = 1 if p.get("inject", True) else 0
+    c.wall_model = int(p.get("wall_model", 0))
+    for k, d in (("ret_f0", 1.0), ("ret_alpha", 0.0), ("gain", 1.0), ("kappa", 0.0), ("r_dot", 0.0)):
+        setattr(c, k, float(p.get(k, d)))
     return c
 
 

@@ -133,6 +133,15 @@ int compute_layout(const fs_config* c, fs_layout_info* L, std::string& err) {
             return FS_EINVAL;
         }
     }
+    if (c->wall_model != 0 && c->wall_model != 1) { err = "wall_model must be 0 or 1"; return FS_EINVAL; }
+    if (c->wall_model == 1) {
+        if (!(c->ret_f0 > 0.0) || !std::isfinite(c->ret_f0) || !std::isfinite(c->ret_alpha) || !(c->gain > 0.0) ||
+            !std::isfinite(c->gain) || !(c->kappa > -2.0) || !std::isfinite(c->kappa) || !std::isfinite(c->r_dot)) {
+            err = "prescribed wall needs ret_f0 > 0, gain > 0, kappa > -2, all finite";
+            return FS_EINVAL;
+        }
+        if (c->ret_alpha != 0.0 && !(c->cr_w > 0.0)) { err = "ret_alpha != 0 needs cr_w > 0"; return FS_EINVAL; }
+    }
     int t[3];
     tile_shape(c->dim, t);
     L->tile[0] = t[0]; L->tile[1] = t[1]; L->tile[2] = t[2];
@@ -235,6 +244,19 @@ void timing_end(fs_handle* h, int k, hipStream_t s) {
 unsigned grid_for(int64_t n, int block = 256) { return (unsigned)std::max<int64_t>(1, (n + block - 1) / block); }
 
 int policy_of(const fs_handle* h, int s) { return s == 0 ? h->cfg.wall_th : h->cfg.wall_cr; }
+
+// The wall's parameters at a step: with the prescribed wall, u2 follows the
+// drifting compression ratio u_sh / max(1, r + r_dot t), t = step dt.
+WallModel wall_model_at(const fs_handle* h, int64_t step) {
+#pragma clang fp contract(off)
+    const fs_config& c = h->cfg;
+    WallModel m{};
+    m.on = c.wall_model == 1;
+    const double r = c.r + c.r_dot * ((double)step * c.dt);
+    m.u2 = m.on ? c.u_sh / (r > 1.0 ? r : 1.0) : h->G.u2;
+    m.f0 = c.ret_f0; m.alpha = c.ret_alpha; m.wref = c.cr_w; m.gain = c.gain; m.kappa = c.kappa;
+    return m;
+}
 
 void zero_u64(void* p, int64_t n, hipStream_t s) {
     if (n <= 0) return;
@@ -368,12 +390,13 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
                 unsigned gw = std::min<unsigned>(grid_for(h->xl[k].cap), 1024u);
                 auto* mom = reinterpret_cast<unsigned long long*>(f->mom[k]);
                 uint8_t* rd = rec ? rec->refl : nullptr;
+                const WallModel wm = wall_model_at(h, step);
                 if (dep)
                     k_wall<R, D, S, true><<<gw, 256, 0, s>>>(G, h->xl[k], out, P.tile_count[P.cur ^ 1], P.tile_cap, mom,
-                                                            h->ctr, policy_of(h, k), k, (uint64_t)step, rd);
+                                                            h->ctr, policy_of(h, k), k, (uint64_t)step, rd, wm);
                 else
                     k_wall<R, D, S, false><<<gw, 256, 0, s>>>(G, h->xl[k], out, P.tile_count[P.cur ^ 1], P.tile_cap, mom,
-                                                             h->ctr, policy_of(h, k), k, (uint64_t)step, rd);
+                                                             h->ctr, policy_of(h, k), k, (uint64_t)step, rd, wm);
             }
         }
         timing_end(h, t_wall, s);
@@ -889,6 +912,7 @@ int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n
         return fail(h, FS_EINVAL, "NULL argument");
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
     if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
+    if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
     if (!f_n->B || !f_n->gather || !f_n1->B) return fail(h, FS_EINVAL, "NULL field array");
     if (step < 0) return fail(h, FS_EINVAL, "negative step");
     int64_t cth = 0, ccr = 0;
@@ -910,6 +934,7 @@ int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, 
     if (!h || !sp0 || !f0 || !lam || !grads) return fail(h, FS_EINVAL, "NULL argument");
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
     if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
+    if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
     if (!f0->B) return fail(h, FS_EINVAL, "NULL field array");
     int rc = check_adjoint(h, lam);
     if (!rc) rc = check_particles(h, sp0);
@@ -948,13 +973,15 @@ int fs_refresh_fields(fs_handle* h, fs_fields* f, hipStream_t s) {
 }  // extern "C"
 
 namespace {
-__global__ void k_wall_list(Geo G, int policy, uint64_t step, int64_t n, const uint32_t* id, const double* delta,
-                            double* v, int32_t* outcome, double* xi_new) {
+__global__ void k_wall_list(Geo G, WallModel wm, int policy, uint64_t step, int64_t n, const uint32_t* id,
+                            const double* delta, double* v, int32_t* outcome, double* xi_new) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double vin[3] = {v[i], v[n + i], v[2 * n + i]}, vout[3], back = 0.0;
     int r = 0;
-    if (policy == FS_WALL_FAUX_SHOCK) r = faux_shock_event(G.seed, step, id[i], G.u2, G.c_light, delta[i], vin, vout, back);
+    if (policy == FS_WALL_FAUX_SHOCK)
+        r = wm.on ? faux_shock_event_prescribed(wm, G.seed, step, id[i], G.c_light, delta[i], vin, vout, back)
+                  : faux_shock_event(G.seed, step, id[i], G.u2, G.c_light, delta[i], vin, vout, back);
     else if (policy == FS_WALL_SPECULAR) {
         vout[0] = -vin[0]; vout[1] = vin[1]; vout[2] = vin[2];
         back = delta[i];
@@ -978,7 +1005,8 @@ int fs_apply_faux_shock(fs_handle* h, int32_t species, int64_t step, int64_t n, 
     if (species < 0 || species > 1 || n < 0) return fail(h, FS_EINVAL, "bad species or count");
     if (n == 0) return FS_OK;
     if (!id || !delta || !v || !outcome || !xi_new) return fail(h, FS_EINVAL, "NULL array");
-    k_wall_list<<<grid_for(n), 256, 0, s>>>(h->G, policy_of(h, species), (uint64_t)step, n, id, delta, v, outcome, xi_new);
+    k_wall_list<<<grid_for(n), 256, 0, s>>>(h->G, wall_model_at(h, step), policy_of(h, species), (uint64_t)step, n, id,
+                                            delta, v, outcome, xi_new);
     return hip_check(h, hipGetLastError(), "wall launch");
 }
 

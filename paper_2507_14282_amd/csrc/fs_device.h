@@ -285,6 +285,75 @@ __device__ __noinline__ int faux_shock_event(uint64_t seed, uint64_t step, uint3
     return 1;
 }
 
+// Prescribed faux-shock wall: the calibration the paper leaves open (Sec. 1:
+// return rate, anisotropy and energy gain fitted to RW runs; Sec. 4: a wall
+// that changes in time).  u2 is that of the step, u_sh / max(1, r + r_dot t),
+// set on the host.  A crosser of downstream-frame speed |w| > u2 returns
+// with probability min(1, f rho^2), rho = (|w| - u2) / (|w| + u2) (eq. 1 is
+// rho^2) and f = f0 (|w| / w_ref)^alpha, decided by U1; it leaves with speed
+// (relativistic: four-velocity magnitude) times gain, direction cosine mu'
+// of pdf ~ (mu' - a)^(1 + kappa) on (a, 1], a = u2 / new speed, drawn by
+// inversion from U3, and azimuth 2 pi U4.  A return that cannot outrun u2 is
+// a transmission.  With kappa = 0 the direction is drawn with the IEEE square
+// root, so a return the eq. (1) event also makes gets its kick bit for bit
+// (non-relativistic mode).  pow() may differ from another implementation's
+// in the last bit: a decision within one ulp of f rho^2 could then differ.
+struct WallModel {
+    int on;
+    double u2, f0, alpha, wref, gain, kappa;
+};
+
+__device__ __noinline__ int faux_shock_event_prescribed(const WallModel& M, uint64_t seed, uint64_t step, uint32_t id,
+                                                        double c_light, double delta, const double v[3],
+                                                        double vout[3], double& back) {
+#pragma clang fp contract(off)
+    const bool rel = c_light > 0.0;
+    const double u2 = M.u2;
+    const double cc = rel ? c_light * c_light : 1.0;
+    double gam = 1.0, g2 = 1.0, Gam = 1.0, Wx;
+    if (rel) {
+        gam = sqrt(1.0 + (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]) / cc);
+        g2 = 1.0 / sqrt(1.0 - (u2 * u2) / cc);
+        Gam = g2 * (gam - u2 * v[0] / cc);
+        Wx = g2 * (v[0] - u2 * gam);
+    } else {
+        Wx = v[0] - u2;
+    }
+    const double Wabs = sqrt(Wx * Wx + v[1] * v[1] + v[2] * v[2]);
+    const double w = Wabs / Gam;
+    if (!(w > u2)) return 0;
+    const double rho = (w - u2) / (w + u2);
+    double f = M.f0;
+    if (M.alpha != 0.0) f = f * pow(w / M.wref, M.alpha);
+    double P = f * (rho * rho);
+    if (P > 1.0) P = 1.0;
+    double U[4];
+    draw4(seed, kStreamWall, step, (uint64_t)id, 0, U);
+    if (!(U[0] < P)) return 0;
+    const double Wn = M.gain * Wabs;
+    const double Gn = rel ? sqrt(1.0 + (Wn * Wn) / cc) : 1.0;
+    const double wn = Wn / Gn;
+    if (!(wn > u2)) return 0;
+    const double a = u2 / wn;
+    const double q = M.kappa == 0.0 ? sqrt(U[2]) : pow(U[2], 1.0 / (2.0 + M.kappa));
+    const double mu = a + (1.0 - a) * q;
+    const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    const double phi = kTwoPi * U[3];
+    const double Wxn = -Wn * mu;
+    vout[1] = Wn * st * cos(phi);
+    vout[2] = Wn * st * sin(phi);
+    if (rel) {
+        vout[0] = g2 * (Wxn + u2 * Gn);
+        const double gl = g2 * (Gn + u2 * Wxn / cc);
+        const double vx = v[0] / gam, vxn = vout[0] / gl;
+        back = vx > 0.0 ? delta * (-vxn) / vx : 0.0;
+    } else {
+        vout[0] = u2 + Wxn;
+        back = v[0] > 0.0 ? delta * (-vout[0]) / v[0] : 0.0;
+    }
+    return 1;
+}
+
 // Workgroup index -> tile, so that the workgroups the hardware hands to one
 // XCD (round robin over 8) get a contiguous run of tiles and share its L2.
 __device__ __forceinline__ int xcd_tile(int bid, int n) {

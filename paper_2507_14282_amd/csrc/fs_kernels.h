@@ -557,13 +557,15 @@ __global__ void k_check_bins(const int32_t* counts, int ntiles, int64_t cap, uns
 }
 
 // ---------------------------------------------------------------------------
-// Faux-shock wall on the crosser list of one species (or SPECULAR mirror).
+// Faux-shock wall on the crosser list of one species (or SPECULAR mirror),
+// with eq. (1) or, when wm.on, the prescribed wall.
 // Reflected ions are binned into their new tile and deposited directly.
 // ---------------------------------------------------------------------------
 template <typename R, int D, int S, bool DEP>
 __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int32_t* cnt_out, int64_t cap,
                                               unsigned long long* mom, unsigned long long* ctr,
-                                              int policy, int species, uint64_t step, uint8_t* refl_rec) {
+                                              int policy, int species, uint64_t step, uint8_t* refl_rec,
+                                              WallModel wm) {
     int ncross = *xl.count;
     if (ncross > xl.cap) ncross = (int)xl.cap;
     int status = 0, oor = 0;
@@ -574,7 +576,8 @@ __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int3
         double vout[3], back = 0.0;
         int refl;
         if (policy == 1) {
-            refl = faux_shock_event(G.seed, step, pid, G.u2, G.c_light, xl.delta[i], v, vout, back);
+            refl = wm.on ? faux_shock_event_prescribed(wm, G.seed, step, pid, G.c_light, xl.delta[i], v, vout, back)
+                         : faux_shock_event(G.seed, step, pid, G.u2, G.c_light, xl.delta[i], v, vout, back);
         } else {
             vout[0] = -v[0]; vout[1] = v[1]; vout[2] = v[2];
             back = xl.delta[i];

@@ -47,7 +47,9 @@ class FsConfig(C.Structure):
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
         ("ppc", C.c_int32), ("ppc_cr", C.c_int32), ("shape", C.c_int32), ("precision", C.c_int32),
         ("wall_th", C.c_int32), ("wall_cr", C.c_int32), ("xbc", C.c_int32), ("n_sub", C.c_int32),
-        ("n_modes", C.c_int32), ("inject", C.c_int32), ("deposit_mode", C.c_int32), ("pad1", C.c_int32),
+        ("n_modes", C.c_int32), ("inject", C.c_int32), ("deposit_mode", C.c_int32), ("wall_model", C.c_int32),
+        ("ret_f0", C.c_double), ("ret_alpha", C.c_double), ("gain", C.c_double), ("kappa", C.c_double),
+        ("r_dot", C.c_double),
     ]
 
 
@@ -173,6 +175,9 @@ def make_config(p: dict) -> FsConfig:
     c.xbc = XBC[p["xbc"]]
     c.inject = 1 if p.get("inject", True) else 0
     c.deposit_mode = DEPOSIT_MODE[p.get("deposit_mode", "fixed")]
+    c.wall_model = int(p.get("wall_model", 0))
+    for k, d in (("ret_f0", 1.0), ("ret_alpha", 0.0), ("gain", 1.0), ("kappa", 0.0), ("r_dot", 0.0)):
+        setattr(c, k, float(p.get(k, d)))
     return c
 
 

@@ -27,6 +27,9 @@ DEFAULTS = dict(
     n_floor=0.05, eta=0.0, n_sub=1, v_max=1024.0,
     c_light=0.0,   # c / v_A; 0 is the non-relativistic push, > 0 the relativistic one
     seed=1000, n_modes=0, mode_amp=1e-3, inject=True,
+    # wall_model 1 is the prescribed faux shock (return factor and its power
+    # of |w| / cr_w, speed gain, direction anisotropy, d r / d t); 0 is eq. (1)
+    wall_model=0, ret_f0=1.0, ret_alpha=0.0, gain=1.0, kappa=0.0, r_dot=0.0,
     precision=32, steps=10,
 )
 

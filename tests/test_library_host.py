@@ -51,7 +51,7 @@ def test_binding_argument_counts_match_header():
 
 def test_struct_sizes_match_header():
     # sizes of the C structs as laid out by the compiler for the ABI
-    assert C.sizeof(F.FsConfig) == 19 * 8 + 8 + 16 * 4
+    assert C.sizeof(F.FsConfig) == 19 * 8 + 8 + 16 * 4 + 5 * 8
     assert C.sizeof(F.FsParticles) == 5 * 8 + 2 * 8 + 2 * 4
     assert C.sizeof(F.FsFields) == 5 * 8
     assert C.sizeof(F.FsRecord) == 3 * 8
@@ -81,7 +81,12 @@ def test_layout_rejects_bad_configs():
     bad = [dict(dim=4), dict(shape="cic", nx=2), dict(precision=16), dict(dt=0.0), dict(v_max=-1.0),
            dict(dim=2, ny=1), dict(n_sub=0),
            # relativistic mode: c must exceed every sampled speed
-           dict(c_light=-1.0), dict(c_light=25.0), dict(c_light=60.0, n_cr=0.01)]
+           dict(c_light=-1.0), dict(c_light=25.0), dict(c_light=60.0, n_cr=0.01),
+           # prescribed wall: model 0 or 1, positive factor and gain, kappa > -2,
+           # a power of |w| / cr_w only with cr_w > 0
+           dict(wall_model=2), dict(wall_model=1, ret_f0=0.0), dict(wall_model=1, gain=0.0),
+           dict(wall_model=1, kappa=-2.0), dict(wall_model=1, ret_alpha=1.0, cr_w=0.0),
+           dict(wall_model=1, r_dot=float("nan"))]
     for b in bad:
         p = W.params(**{k: v for k, v in b.items()})
         if "precision" in b:
