@@ -76,10 +76,16 @@ PRESETS = {
     "rw1": dict(dim=1, nx=512, dx=0.5, dt=0.005, ppc=32, u_sh=20.0, beta_i=1.0,
                 theta_deg=80.0, n_cr=0.0, wall_th="specular", seed=1011,
                 precision=32, steps=2400, cap_factor_th=6.0),
-    # rw2: 2D, theta_Bn = 0 as in Run C, on the 2D box's grid.
-    "rw2": dict(dim=2, nx=8192, ny=512, dx=0.5, dt=0.005, ppc=16, u_sh=20.0,
+    # rw2: 2D, theta_Bn = 0 and dx = 1.5 d_i as in Run C (Table 1), 8192 x
+    # 512 cells = 12288 x 768 d_i (Run C: 20000 x 300).  The beams the mirror
+    # sends upstream drive fields of tens of B0 at the grid scale; with no
+    # filter in the scheme the box needs eight field substeps and a density
+    # floor of 0.2 to stay finite, and does so to t = 12 (at dx = 1 and 1.5
+    # alike it flags a saturated velocity code between t = 12.5 and 15).
+    "rw2": dict(dim=2, nx=8192, ny=512, dx=1.5, dt=0.005, ppc=16, u_sh=20.0,
                 beta_i=1.0, theta_deg=0.0, n_cr=0.0, wall_th="specular",
-                seed=1012, precision=32, steps=5000, cap_factor_th=6.0),
+                n_sub=8, n_floor=0.2, seed=1012, precision=32, steps=2400,
+                cap_factor_th=6.0),
 }
 
 

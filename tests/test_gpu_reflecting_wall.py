@@ -90,3 +90,30 @@ def test_reflecting_wall_2d_shock_obeys_the_jump_conditions():
     # the two- (3) and three-degree-of-freedom (4) strong-shock values, with
     # room for the overshoot of a shock that is not yet steady
     _jump_checks(p, m, (3.0, 5.0))
+
+
+def test_rw2_box_runs_its_length():
+    """The 2D RW workload (8192 x 512 cells at dx = 1.5 d_i, 16 ppc, 6.7e7
+    ions, theta_Bn = 0) over its 2400 steps: no bin, crosser-list or
+    velocity-code flag and a finite field; on every 500th step every
+    crosser is reflected and the ion count changes only by injection and
+    escape at the inflow."""
+    p = W.preset("rw2")
+    nsteps = int(p["steps"])
+    print(f"rw2 2D {p['nx']} x {p['ny']}, {nsteps} steps", flush=True)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    n0 = sim.count(0)
+    for s in range(nsteps):
+        check = s % 500 == 499 or s == nsteps - 1
+        if not check:
+            sim.step(s, stats=False)
+            continue
+        before = sim.count(0)
+        st = sim.step(s, stats=True)
+        assert st["flags"] == 0, (s, st)
+        assert st["transmitted"] == 0 and st["open_removed"] == 0 and st["incident"] == st["reflected"] > 0
+        assert sim.count(0) == before + st["injected_th"] - st["escaped"]
+        print(f"  step {s + 1}: {sim.count(0)} ions, {st['reflected']} reflected", flush=True)
+    assert np.isfinite(sim.get_B()).all()
+    assert sim.count(0) > n0
