@@ -124,6 +124,22 @@ typedef struct fs_config {
     double gain;                /* speed gain of a return, > 0 */
     double kappa;               /* anisotropy exponent of the return direction, > -2 */
     double r_dot;               /* d r / d t of the wall's compression ratio */
+    int32_t smooth;         /* passes of the 1-2-1 binomial filter on the ion
+                               density (floored) and flux before Ohm's law, each
+                               pass along x, then y, then z; 0 (the default) for
+                               none.  The paper runs dHybrid(R), which smooths,
+                               but does not describe the filter; the 2D
+                               reflecting-wall runs need it past t ~ 12.  In the
+                               box x boundaries the end nodes keep their values and
+                               the nodes within `shape` of them copy the nearest
+                               filtered node.  The adjoint entry points refuse it. */
+    int32_t wall_field;     /* field boundary at x = L in the box.  0: the last
+                               cell's B is copied into the ghost and Ohm's law
+                               holds at the wall node (open to the outflowing
+                               plasma of the faux-shock runs).  1: a conducting
+                               wall at rest, E_y = E_z = 0 at the wall node (the
+                               reflecting-wall runs, whose plasma piles up there).
+                               The adjoint entry points refuse 1. */
 } fs_config;
 
 /* Sizes the caller must allocate, reported by fs_layout(). */

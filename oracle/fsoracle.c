@@ -79,6 +79,19 @@
  *     direction cosine mu' of pdf ~ (mu' - a)^(1 + kappa) on (a, 1], a = u2 /
  *     new speed (kappa = 0 is R7's isotropic flux), azimuth uniform.  A
  *     return slower than u2 cannot leave and counts as transmitted.
+ *  R13 smoothing (smooth = N > 0): the paper's codes smooth their fields
+ *     but the paper does not say how.  Read as N passes of the 1-2-1
+ *     binomial filter, f_i <- (f_{i-1} + 2 f_i + f_{i+1}) / 4, along x, then
+ *     y, then z, on the boundary-filled ion density n_e = max(n, n_floor)
+ *     and flux Gamma (without J_ext) at the nodes, before Ohm's law.  In the
+ *     box the end nodes x = 0 and x = L keep their values; y, z (and x when
+ *     periodic) wrap.  The boundary fill and the floor then apply again.
+ *  R14 conducting wall (wall_field = 1): the paper does not give the field
+ *     boundary of its reflecting wall.  Read as a perfect conductor at rest
+ *     in the simulation frame: the tangential E vanishes at the wall node
+ *     x = L, E_y = E_z = 0, and E_x keeps Ohm's law.  With 0 the wall node
+ *     keeps Ohm's law against the copied ghost (R10), the open boundary the
+ *     faux-shock runs need.
  */
 #include "fsoracle.h"
 #include <stdlib.h>
@@ -809,6 +822,8 @@ static double species_weight(const ora_sim* s, int k)
     return s->c.alpha_cr * s->c.n_cr / (double)s->c.ppc_cr;
 }
 
+static void smooth_fluid(ora_sim* s);
+
 /* Ion density and flux at the field nodes from both species' moments. */
 static void fluid_from_moments(ora_sim* s)
 {
@@ -831,6 +846,57 @@ static void fluid_from_moments(ora_sim* s)
         s->fn[n] = dens;
         for (int d = 0; d < 3; ++d) s->fg[3 * n + d] = G[d];
     }
+    if (s->c.smooth > 0) smooth_fluid(s);
+}
+
+/* Reading R13: N passes of the 1-2-1 filter over n_e and Gamma. */
+static void smooth_fluid(ora_sim* s)
+{
+    int64_t N = s->nnode, nxn = s->nxn, nyc = s->nyc, nzc = s->nzc;
+    double* a = (double*)malloc((size_t)(4 * N) * sizeof(double));
+    double* b = (double*)malloc((size_t)(4 * N) * sizeof(double));
+    for (int64_t n = 0; n < N; ++n) {
+        int64_t i = n % nxn, j = (n / nxn) % nyc, k = n / (nxn * nyc);
+        int64_t f = fluid_node(s, i, j, k);
+        a[n] = fmax(s->fn[f], s->c.n_floor);
+        for (int d = 0; d < 3; ++d) a[(1 + d) * N + n] = s->fg[3 * f + d];
+    }
+    for (int pass = 0; pass < s->c.smooth; ++pass) {
+        for (int axis = 0; axis < s->c.dim; ++axis) {
+            for (int64_t n = 0; n < N; ++n) {
+                int64_t i = n % nxn, j = (n / nxn) % nyc, k = n / (nxn * nyc);
+                int64_t m, p;
+                int keep = 0;
+                if (axis == 0) {
+                    if (s->c.xbc == ORA_XBC_PERIODIC) {
+                        m = node_idx(s, wrapi(i - 1, s->c.nx), j, k);
+                        p = node_idx(s, wrapi(i + 1, s->c.nx), j, k);
+                    } else {
+                        keep = i == 0 || i == s->c.nx;
+                        m = keep ? n : node_idx(s, i - 1, j, k);
+                        p = keep ? n : node_idx(s, i + 1, j, k);
+                    }
+                } else if (axis == 1) {
+                    m = node_idx(s, i, wrapi(j - 1, nyc), k);
+                    p = node_idx(s, i, wrapi(j + 1, nyc), k);
+                } else {
+                    m = node_idx(s, i, j, wrapi(k - 1, nzc));
+                    p = node_idx(s, i, j, wrapi(k + 1, nzc));
+                }
+                for (int q = 0; q < 4; ++q) {
+                    const double* x = a + q * N;
+                    b[q * N + n] = keep ? x[n] : 0.25 * ((x[m] + 2.0 * x[n]) + x[p]);
+                }
+            }
+            double* t = a; a = b; b = t;
+        }
+    }
+    for (int64_t n = 0; n < N; ++n) {
+        s->fn[n] = a[n];
+        for (int d = 0; d < 3; ++d) s->fg[3 * n + d] = a[(1 + d) * N + n];
+    }
+    free(a);
+    free(b);
 }
 
 /* ------------------------------------------------------------------ */
@@ -900,6 +966,11 @@ static void ohm_node(const ora_sim* s, const double* B, int64_t i, int64_t j, in
         E[0] = 0.0;
         E[1] = s->c.u_sh * s->B0[2];
         E[2] = -s->c.u_sh * s->B0[1];
+    }
+    /* Reading R14: a conducting wall at x = L. */
+    if (s->c.xbc != ORA_XBC_PERIODIC && s->c.wall_field == 1 && i == s->c.nx) {
+        E[1] = 0.0;
+        E[2] = 0.0;
     }
 }
 

@@ -41,6 +41,8 @@ typedef struct ora_cfg {
     int32_t n_modes, inject, replay;
     int32_t wall_model;   /* 0: eq. (1) with the R7 kick; 1: the prescribed wall (reading R12) */
     double ret_f0, ret_alpha, gain, kappa, r_dot;
+    int32_t smooth;         /* binomial passes on the fluid moments (reading R13) */
+    int32_t wall_field;     /* 1: conducting wall at x = L (reading R14) */
 } ora_cfg;
 
 typedef struct ora_stats {

@@ -57,7 +57,7 @@ class OraCfg(C.Structure):
         ("n_modes", C.c_int32), ("inject", C.c_int32), ("replay", C.c_int32),
         ("wall_model", C.c_int32),
         ("ret_f0", C.c_double), ("ret_alpha", C.c_double), ("gain", C.c_double),
-        ("kappa", C.c_double), ("r_dot", C.c_double),
+        ("kappa", C.c_double), ("r_dot", C.c_double), ("smooth", C.c_int32), ("wall_field", C.c_int32),
     ]
 
 
@@ -88,6 +88,8 @@ def make_cfg(p: dict, deposit_mode: str = "fixed") -> OraCfg:
     c.wall_model = int(p.get("wall_model", 0))
     for k, d in (("ret_f0", 1.0), ("ret_alpha", 0.0), ("gain", 1.0), ("kappa", 0.0), ("r_dot", 0.0)):
         setattr(c, k, float(p.get(k, d)))
+    c.smooth = int(p.get("smooth", 0))
+    c.wall_field = int(p.get("wall_field", 0))
     return c
 
 

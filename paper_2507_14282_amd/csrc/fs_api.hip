@@ -32,6 +32,7 @@ struct fs_handle {
     double* B2 = nullptr;
     double* Etmp = nullptr;
     double* fluid = nullptr;
+    double* fluid2 = nullptr;     // second fluid buffer of the binomial filter
     double* phase = nullptr;
     double* part = nullptr;
     int64_t npart = 0;
@@ -142,6 +143,8 @@ int compute_layout(const fs_config* c, fs_layout_info* L, std::string& err) {
         }
         if (c->ret_alpha != 0.0 && !(c->cr_w > 0.0)) { err = "ret_alpha != 0 needs cr_w > 0"; return FS_EINVAL; }
     }
+    if (c->smooth < 0 || c->smooth > 64) { err = "smooth must be in [0, 64]"; return FS_EINVAL; }
+    if (c->wall_field != 0 && c->wall_field != 1) { err = "wall_field must be 0 or 1"; return FS_EINVAL; }
     int t[3];
     tile_shape(c->dim, t);
     L->tile[0] = t[0]; L->tile[1] = t[1]; L->tile[2] = t[2];
@@ -276,6 +279,19 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
     k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(f->mom[0]),
                                reinterpret_cast<const long long*>(h->has_cr ? f->mom[1] : f->mom[0]), h->fluid, nn);
+    if (h->cfg.smooth > 0) {
+        // passes ping-pong between the two buffers; the finish writes the
+        // other one, which then becomes h->fluid
+        double* a = h->fluid;
+        double* b = h->fluid2;
+        for (int pass = 0; pass < h->cfg.smooth; ++pass)
+            for (int axis = 0; axis < D; ++axis) {
+                k_smooth_axis<<<gn, blk, 0, s>>>(h->F, a, b, axis, nn);
+                std::swap(a, b);
+            }
+        k_smooth_finish<<<gn, blk, 0, s>>>(h->F, a, b, nn);
+        if (b != h->fluid) std::swap(h->fluid, h->fluid2);
+    }
     const double hs = h->cfg.dt / (double)h->cfg.n_sub;
     if constexpr (D == 3) {
         // z-marching kernels: 32 x 8 columns over runs of at most 32 z planes
@@ -750,6 +766,8 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     const double th = c.theta_deg * (kTwoPi / 360.0);
     F.B0[0] = std::cos(th); F.B0[1] = std::sin(th); F.B0[2] = 0.0;
     F.n_floor = c.n_floor; F.beta_e = c.beta_e; F.gamma_e = c.gamma_e; F.eta = c.eta; F.j_ext = c.j_ext;
+    F.smooth = c.smooth;
+    F.conduct = c.xbc == FS_XBC_BOX && c.wall_field == 1;
     F.u_sh = c.u_sh;
     F.wth = c.ppc > 0 ? 1.0 / (double)c.ppc : 0.0;
     F.wcr = h->has_cr ? c.alpha_cr * c.n_cr / (double)c.ppc_cr : 0.0;
@@ -769,6 +787,7 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     ok = ok && dmalloc((void**)&h->B2, 3 * nc * sizeof(double));
     ok = ok && dmalloc((void**)&h->Etmp, 3 * nn * sizeof(double));
     ok = ok && dmalloc((void**)&h->fluid, 5 * nn * sizeof(double));
+    if (c.smooth > 0) ok = ok && dmalloc((void**)&h->fluid2, 5 * nn * sizeof(double));
     ok = ok && dmalloc((void**)&h->phase, (c.n_modes + 1) * sizeof(double));
     h->npart = std::max<int64_t>(grid_for(nc), h->L.ntiles) * 4;
     ok = ok && dmalloc((void**)&h->part, h->npart * sizeof(double));
@@ -816,7 +835,7 @@ void fs_destroy(fs_handle* h) {
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     hipFree(h->ctr);
     if (h->ctr_host) hipHostFree(h->ctr_host);
-    hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->phase); hipFree(h->part); hipFree(h->spec);
+    hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->fluid2); hipFree(h->phase); hipFree(h->part); hipFree(h->spec);
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
     for (int k = 0; k < 2; ++k) { hipFree(h->amom[k]); hipFree(h->alM[k]); }
     hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->alE);
@@ -913,6 +932,8 @@ int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
     if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
     if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
+    if (h->cfg.smooth != 0) return fail(h, FS_EINVAL, "the adjoint covers the unfiltered moments only");
+    if (h->cfg.wall_field != 0) return fail(h, FS_EINVAL, "the adjoint covers the open wall field only");
     if (!f_n->B || !f_n->gather || !f_n1->B) return fail(h, FS_EINVAL, "NULL field array");
     if (step < 0) return fail(h, FS_EINVAL, "negative step");
     int64_t cth = 0, ccr = 0;
@@ -935,6 +956,8 @@ int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, 
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
     if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
     if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
+    if (h->cfg.smooth != 0) return fail(h, FS_EINVAL, "the adjoint covers the unfiltered moments only");
+    if (h->cfg.wall_field != 0) return fail(h, FS_EINVAL, "the adjoint covers the open wall field only");
     if (!f0->B) return fail(h, FS_EINVAL, "NULL field array");
     int rc = check_adjoint(h, lam);
     if (!rc) rc = check_particles(h, sp0);

@@ -21,6 +21,8 @@ struct FieldGeo {
     double wth, wcr, scR, scG;    // species weights and fixed-point scales
     int has_cr;
     int cont;                     // moments hold FP64 sums (continuous deposit)
+    int smooth;                   // binomial passes on the fluid moments (0: none)
+    int conduct;                  // conducting wall at x = L: E_y = E_z = 0 there
 };
 
 // The inflow node x = 0 of the box carries the motional field of the
@@ -28,6 +30,10 @@ struct FieldGeo {
 // evaluated against the fixed ghost centre (which lets 2D perturbations grow
 // at the boundary).
 __device__ __forceinline__ bool inflow_node(const FieldGeo& F, int i) { return F.xbc == 0 && i == 0; }
+// A conducting wall at x = L (box only): the tangential E vanishes at its node.
+__device__ __forceinline__ void wall_E(const FieldGeo& F, int i, double e[3]) {
+    if (F.conduct && i == F.nx) { e[1] = 0.0; e[2] = 0.0; }
+}
 __device__ __forceinline__ void inflow_E(const FieldGeo& F, double e[3]) {
     e[0] = 0.0;
     e[1] = F.u_sh * F.B0[2];
@@ -100,9 +106,71 @@ __global__ __launch_bounds__(256) void k_fluid(FieldGeo F, const long long* __re
     double ne = fmax(dens, F.n_floor);
     fl[n] = ne;
     fl[nnode + n] = 0.5 * F.beta_e * pow(ne, F.gamma_e);
-    fl[2 * nnode + n] = G[0] + F.j_ext;
+    fl[2 * nnode + n] = F.smooth ? G[0] : G[0] + F.j_ext;   // smoothing adds J_ext after the filter
     fl[3 * nnode + n] = G[1];
     fl[4 * nnode + n] = G[2];
+}
+
+// One pass of the 1-2-1 binomial filter along one axis over the fluid
+// planes 0 (n_e, floored) and 2-4 (Gamma without J_ext):
+// f_i <- (f_{i-1} + 2 f_i + f_{i+1}) / 4 in this operation order.  In the box
+// the x end nodes keep their values; y, z and periodic x wrap.  Plane 1 is
+// left alone (p_e follows from the filtered n_e at the end).
+__global__ __launch_bounds__(256) void k_smooth_axis(FieldGeo F, const double* __restrict__ in,
+                                                     double* __restrict__ out, int axis, long nnode) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * kFX + threadIdx.x;
+    const int j = blockIdx.y * kFY + threadIdx.y, k = blockIdx.z;
+    if (i >= F.nxn || j >= F.nyc) return;
+    const long n = lin(i, j, k, F.nxn, F.nyc);
+    long m = n, p = n;
+    bool keep = false;
+    if (axis == 0) {
+        if (F.xbc == 1) {
+            m = lin(wrapi(i - 1, F.nx), j, k, F.nxn, F.nyc);
+            p = lin(wrapi(i + 1, F.nx), j, k, F.nxn, F.nyc);
+        } else if (i == 0 || i == F.nx) {
+            keep = true;
+        } else {
+            m = n - 1;
+            p = n + 1;
+        }
+    } else if (axis == 1) {
+        m = lin(i, wrapi(j - 1, F.nyc), k, F.nxn, F.nyc);
+        p = lin(i, wrapi(j + 1, F.nyc), k, F.nxn, F.nyc);
+    } else {
+        m = lin(i, j, wrapi(k - 1, F.nzc), F.nxn, F.nyc);
+        p = lin(i, j, wrapi(k + 1, F.nzc), F.nxn, F.nyc);
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        if (q == 1) continue;
+        const double* x = in + q * nnode;
+        out[q * nnode + n] = keep ? x[n] : 0.25 * ((x[m] + 2.0 * x[n]) + x[p]);
+    }
+}
+
+// After the passes: the boundary fill again (box nodes within `shape` of an
+// x end copy the nearest covered node), the floor, p_e and J_ext.  Reads
+// `src`, writes `fl` (distinct buffers).
+__global__ __launch_bounds__(256) void k_smooth_finish(FieldGeo F, const double* __restrict__ src,
+                                                       double* __restrict__ fl, long nnode) {
+    const int i = blockIdx.x * kFX + threadIdx.x;
+    const int j = blockIdx.y * kFY + threadIdx.y, k = blockIdx.z;
+    if (i >= F.nxn || j >= F.nyc) return;
+    const long n = lin(i, j, k, F.nxn, F.nyc);
+    int ic = i;
+    if (F.xbc == 0) {
+        if (ic < F.mclamp) ic = F.mclamp;
+        if (ic > F.nx - F.mclamp) ic = F.nx - F.mclamp;
+    }
+    const long c = lin(ic, j, k, F.nxn, F.nyc);
+    const double ne = fmax(src[c], F.n_floor);
+    fl[n] = ne;
+    fl[nnode + n] = 0.5 * F.beta_e * pow(ne, F.gamma_e);
+    fl[2 * nnode + n] = src[2 * nnode + c] + F.j_ext;
+    fl[3 * nnode + n] = src[3 * nnode + c];
+    fl[4 * nnode + n] = src[4 * nnode + c];
 }
 
 __device__ __forceinline__ long fnode(const FieldGeo& F, int i, int j, int k) {
@@ -322,6 +390,7 @@ __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restric
     double e[3], bb[3];
     ohm_tile<D>(F, sB, sP, fl, nnode, n, tx, ty, tz, e, bb);
     if (inflow_node(F, i)) inflow_E(F, e);
+    wall_E(F, i, e);
 #pragma unroll
     for (int d = 0; d < 3; ++d) E[(long)d * nnode + n] = e[d];
     store_gather(gather + 8 * n, e, bb);
@@ -356,6 +425,7 @@ __global__ __launch_bounds__(256) void k_stage(FieldGeo F, const double* __restr
             const long n = lin(i, j, k, F.nxn, F.nyc);
             ohm_tile<D>(F, sB, sP, fl, nnode, n, lx, ly, lz, e, bb);
             if (inflow_node(F, i)) inflow_E(F, e);
+            wall_E(F, i, e);
         }
         sE[0][l] = e[0]; sE[1][l] = e[1]; sE[2][l] = e[2];
     }
@@ -566,6 +636,7 @@ __global__ __launch_bounds__(256) void k_stage3(FieldGeo F, const double* __rest
                 double e[3], bb[3];
                 inflow_E(F, e);
                 if (fn[it].ok) zm_ohm(F, sB[b0], sB[b1], sP[p0], sP[p1], sP[p2], fn[it], l % Z::NX, l / Z::NX, e, bb);
+                wall_E(F, x0 + l % Z::NX, e);
                 sE[slot][0][l] = e[0]; sE[slot][1][l] = e[1]; sE[slot][2][l] = e[2];
             }
         }
@@ -690,6 +761,7 @@ __global__ __launch_bounds__(256) void k_ohm3(FieldGeo F, const double* __restri
             double e[3], bb[3];
             zm_ohm(F, sB[r & 1], sB[(r + 1) & 1], sP[r % 3], sP[(r + 1) % 3], sP[(r + 2) % 3], f, tx, ty, e, bb);
             if (inflow_node(F, x0 + tx)) inflow_E(F, e);
+            wall_E(F, x0 + tx, e);
 #pragma unroll
             for (int d = 0; d < 3; ++d) E[(long)d * nnode + f.n] = e[d];
             store_gather(gather + 8 * f.n, e, bb);

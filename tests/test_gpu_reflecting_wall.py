@@ -17,7 +17,8 @@ from oracle import oracle as O
 from paper_2507_14282_amd import fshybrid as F
 from paper_2507_14282_amd import workloads as W
 from tests.shock import by_of, ion_x, shock_state
-from tests.test_gpu_parity import _free_run
+from tests import inputs
+from tests.test_gpu_parity import _free_run, rel, setup_pair, small
 
 pytestmark = pytest.mark.gpu
 
@@ -94,7 +95,8 @@ def test_reflecting_wall_2d_shock_obeys_the_jump_conditions():
 
 def test_rw2_box_runs_its_length():
     """The 2D RW workload (8192 x 512 cells at dx = 1.5 d_i, 16 ppc, 6.7e7
-    ions, theta_Bn = 0) over its 2400 steps: no bin, crosser-list or
+    ions, theta_Bn = 0, conducting wall) over its 4000 steps, past the
+    t = 12.5-15 at which the open field boundary breaks down: no bin, crosser-list or
     velocity-code flag and a finite field; on every 500th step every
     crosser is reflected and the ion count changes only by injection and
     escape at the inflow."""
@@ -117,3 +119,28 @@ def test_rw2_box_runs_its_length():
         print(f"  step {s + 1}: {sim.count(0)} ions, {st['reflected']} reflected", flush=True)
     assert np.isfinite(sim.get_B()).all()
     assert sim.count(0) > n0
+
+
+# --------------------------------------------------------------------------
+# conducting wall at x = L (E_y = E_z = 0 at the wall node)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_field_update_fp64_with_a_conducting_wall(dim):
+    p = small(dim, precision=64, beta_e=1.0, eta=0.01, n_sub=2, wall_field=1, wall_th="specular")
+    st = inputs.particle_state(p, 6, seed=23, drift=4.0, sigma=1.0)
+    B = inputs.magnetic_field(p, 0.05, seed=10)
+    sim, o = setup_pair(p, st, B)
+    assert rel(sim.get_E(), o.E()) < 1e-12
+    for _ in range(2):
+        sim.field_update()
+        o.step(O.FIELD)
+        assert rel(sim.get_B(), o.B()) < 1e-12
+        assert rel(sim.get_E(), o.E()) < 1e-12
+    nx = p["nx"]
+    E = sim.get_E().reshape(-1, nx + 1, 3)
+    assert np.all(E[:, nx, 1:] == 0.0)
+
+
+def test_fp64_reflecting_wall_free_run_with_a_conducting_wall():
+    p = W.preset("rw1", precision=64, nx=128, seed=1017, wall_field=1)
+    assert _free_run(p, 60) > 0

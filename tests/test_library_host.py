@@ -51,7 +51,7 @@ def test_binding_argument_counts_match_header():
 
 def test_struct_sizes_match_header():
     # sizes of the C structs as laid out by the compiler for the ABI
-    assert C.sizeof(F.FsConfig) == 19 * 8 + 8 + 16 * 4 + 5 * 8
+    assert C.sizeof(F.FsConfig) == 19 * 8 + 8 + 16 * 4 + 5 * 8 + 2 * 4
     assert C.sizeof(F.FsParticles) == 5 * 8 + 2 * 8 + 2 * 4
     assert C.sizeof(F.FsFields) == 5 * 8
     assert C.sizeof(F.FsRecord) == 3 * 8
@@ -86,7 +86,8 @@ def test_layout_rejects_bad_configs():
            # a power of |w| / cr_w only with cr_w > 0
            dict(wall_model=2), dict(wall_model=1, ret_f0=0.0), dict(wall_model=1, gain=0.0),
            dict(wall_model=1, kappa=-2.0), dict(wall_model=1, ret_alpha=1.0, cr_w=0.0),
-           dict(wall_model=1, r_dot=float("nan"))]
+           dict(wall_model=1, r_dot=float("nan")), dict(smooth=-1), dict(smooth=65),
+           dict(wall_field=2)]
     for b in bad:
         p = W.params(**{k: v for k, v in b.items()})
         if "precision" in b:
