@@ -69,11 +69,16 @@ def workload_throughput(name, steps, warmup, **overrides):
     out = {
         "workload": f"{dim}D3V FP32 {p['nx']}x{p['ny']}x{p['nz']} cells dx={p['dx']} d_i, {p['ppc']} ppc"
                     + (f" + CRs n_cr={p['n_cr']:g}" if sim.has_cr else "") + f", {p['shape']}, M_A={p['u_sh']:g}"
-                    + (f", relativistic c/v_A={p['c_light']:g}" if p.get("c_light", 0) > 0 else ""),
+                    + (f", relativistic c/v_A={p['c_light']:g}" if p.get("c_light", 0) > 0 else "")
+                    + (", reflecting wall" + (" (conducting)" if p.get("wall_field", 0) else "")
+                       if p["wall_th"] == "specular" else "")
+                    + (f", prescribed wall (f0={p['ret_f0']:g}, gain={p['gain']:g}, kappa={p['kappa']:g}, "
+                       f"r_dot={p['r_dot']:g})" if p.get("wall_model", 0) else ""),
         "ions": int(nav), "steps": steps, "warmup": warmup,
         "ms_per_step": (t1 - t0) / steps * 1e3,
         "pu_per_s": nav * steps / (t1 - t0),
         "push_deposit_ms": push_ms,
+        "wall_ms": ms[1] / max(nrec[1], 1),
         "field_ms": ms[3] / max(nrec[3], 1),
         "push_alg_bytes_per_step": alg, "push_GBs": ach, "push_frac_of_hbm_peak": ach / HBM_PEAK_GBS,
         "final_step_flags": st["flags"],
@@ -348,7 +353,8 @@ def main():
     ap.add_argument("--write-atomics", metavar="PMC_DIR",
                     help="write profiles/push3d_atomics.json from a rocprofv3 run of the atomic counters")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward measurement")
-    ap.add_argument("--no-other", action="store_true", help="skip the 1D, 2D and relativistic workload lines")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the 1D, 2D, relativistic, reflecting-wall and prescribed-wall workload lines")
     ap.add_argument("--adjoint-only", action="store_true", help="only the adjoint/forward measurement")
     args = ap.parse_args()
     if args.copy_calibration:
@@ -468,6 +474,12 @@ def main():
             # the relativistic push at the paper's c / v_A = 1000 (Run A)
             "2D cfg3 relativistic": workload_throughput("cfg3", 50, 10, c_light=1000.0),
             "3D cfg4 relativistic": workload_throughput("cfg4", 30, 10, c_light=1000.0),
+            # the reflecting-wall box of Run C's shape, timed after 2000 steps
+            # (t = 10) so that the reflected beams and the shock are in it
+            "2D rw2 reflecting wall": workload_throughput("rw2", 50, 2000),
+            # the prescribed faux shock on the 3D box
+            "3D cfg4 prescribed wall": workload_throughput("cfg4", 30, 10, wall_model=1, ret_f0=0.8, ret_alpha=0.0,
+                                                            gain=1.2, kappa=1.5, r_dot=0.1),
         }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
