@@ -193,16 +193,39 @@ def wall_threshold2(p, step, pid):
     return T * T
 
 
-@pytest.mark.parametrize("name", ["cfg4", "cfg2"])
-def test_full_size_wall_events(name):
+def wall_margin(p, step, pid, v):
+    """Relative distance of ion pid's wall decision from its threshold: for
+    eq. (1), |w|^2 against T^2; for the prescribed wall, the uniform against
+    min(1, f rho^2) at the step's u2, and |w| and gain |w| against u2."""
+    if not p.get("wall_model", 0):
+        u2 = float(p["u_sh"]) / float(p["r"])
+        w = np.asarray(v, dtype=np.float64) - np.array([u2, 0.0, 0.0])
+        return abs(float(w @ w) / wall_threshold2(p, step, pid) - 1.0)
+    r = O.philox([int(step), int(pid), 0, 0], [int(p["seed"]), 4])
+    U0 = ((int(r[0]) >> 11) + 0.5) * 2.0**-53
+    u2 = float(p["u_sh"]) / max(1.0, float(p["r"]) + float(p["r_dot"]) * (step * float(p["dt"])))
+    w = float(np.linalg.norm(np.asarray(v, dtype=np.float64) - np.array([u2, 0.0, 0.0])))
+    if w <= u2:
+        return abs(w / u2 - 1.0)
+    rho = (w - u2) / (w + u2)
+    P = min(1.0, float(p["ret_f0"]) * (w / float(p["cr_w"])) ** float(p["ret_alpha"]) * rho * rho)
+    return min(abs(U0 / P - 1.0), abs(w / u2 - 1.0), abs(float(p["gain"]) * w / u2 - 1.0))
+
+
+PRESCRIBED = dict(wall_model=1, ret_f0=0.8, ret_alpha=0.5, gain=1.2, kappa=1.5, r_dot=0.4)
+
+
+@pytest.mark.parametrize("name,model", [("cfg4", {}), ("cfg2", {}), ("cfg4", PRESCRIBED)],
+                         ids=["cfg4", "cfg2", "cfg4-prescribed"])
+def test_full_size_wall_events(name, model):
     """Every ion of the tile column at the wall, pushed by the oracle in the
     GPU's own gather grid; the crossers go through the oracle's wall.  After
     the GPU step, transmitted (and open-wall) crossers are gone and reflected
     ones are back in the box with the oracle's velocity and re-entry point.
     A decision may differ only at a certified straddle: the oracle's position
     within 1e-5 cells of the wall, or |w|^2 within 1e-5 of the threshold T^2."""
-    p = W.preset(name)
-    print(f"full-size wall {name}", flush=True)
+    p = W.preset(name, **model)
+    print(f"full-size wall {name}{' prescribed' if model else ''}", flush=True)
     sim = F.Simulation(p, "cuda:0")
     sim.init_plasma()
     for s in range(2):
@@ -222,7 +245,6 @@ def test_full_size_wall_events(name):
     st = sim.step(2)
     assert st["flags"] == 0 and st["saturated"] == 0, st
     nx = int(p["nx"])
-    u2 = float(p["u_sh"]) / float(p["r"])
     total = {"cross": 0, "refl": 0, "straddle": 0}
     for sp in range(nsp):
         c0, o0, v0, id0 = before[sp]
@@ -242,9 +264,7 @@ def test_full_size_wall_events(name):
             pid = int(ids[j])
             present, expect = pid in where, out[j] == 1
             if present != expect:
-                w = vc[j] - np.array([u2, 0.0, 0.0])
-                w2 = float(w @ w)
-                ok = delta[j] < 1e-5 or abs(w2 / wall_threshold2(p, 2, pid) - 1.0) < 1e-5
+                ok = delta[j] < 1e-5 or wall_margin(p, 2, pid, vc[j]) < 1e-5
                 assert ok, (sp, pid, present, expect, delta[j])
                 total["straddle"] += 1
                 continue
