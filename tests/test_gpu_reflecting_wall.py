@@ -93,6 +93,15 @@ def test_reflecting_wall_2d_shock_obeys_the_jump_conditions():
     _jump_checks(p, m, (3.0, 5.0))
 
 
+def test_reflecting_wall_3d_shock_obeys_the_jump_conditions():
+    # the 3D counterpart (the paper's Run 3D is a 3D RW box at theta_Bn = 80
+    # deg), with the 2D box's settings
+    p = W.preset("rw1", dim=3, nx=256, ny=16, nz=16, dx=1.0, ppc=16, n_floor=0.2, n_sub=8, seed=1018)
+    print("rw 3D 256 x 16 x 16 at dx = 1, 16 ppc, 8 field substeps, FP32, 2400 steps", flush=True)
+    _, m = _gpu_run(p, (800, 2400), slab=4)
+    _jump_checks(p, m, (3.0, 5.0))
+
+
 def test_rw2_box_runs_its_length():
     """The 2D RW workload (8192 x 512 cells at dx = 1.5 d_i, 16 ppc, 6.7e7
     ions, theta_Bn = 0, conducting wall) over its 4000 steps, past the
