@@ -79,17 +79,16 @@ PRESETS = {
                 theta_deg=80.0, n_cr=0.0, wall_th="specular", seed=1011,
                 precision=32, steps=2400, cap_factor_th=6.0),
     # rw2: 2D, theta_Bn = 0 and dx = 1.5 d_i as in Run C (Table 1), 8192 x
-    # 512 cells = 12288 x 768 d_i (Run C: 20000 x 300).  The beams the mirror
-    # sends upstream drive fields of tens of B0 at the grid scale, so the box
-    # runs with eight field substeps and a density floor of 0.2, and with a
-    # conducting wall: with the open field boundary the last cell's field
-    # grows without bound between t = 12.5 and 15.  It runs to t = 20.
-    # (rw1 keeps the open boundary: in 1D the conducting wall empties the
-    # cells next to it after t ~ 8.)
+    # 512 cells = 12288 x 768 d_i (Run C: 20000 x 300), with a conducting
+    # wall: with the open field boundary the last cell's field grows without
+    # bound between t = 12.5 and 15 (eight field substeps and a density floor
+    # of 0.2 do not prevent it).  It runs to t = 20.  (rw1 keeps the open
+    # boundary: in 1D the conducting wall empties the cells next to it after
+    # t ~ 8.)
     "rw2": dict(dim=2, nx=8192, ny=512, dx=1.5, dt=0.005, ppc=16, u_sh=20.0,
                 beta_i=1.0, theta_deg=0.0, n_cr=0.0, wall_th="specular",
-                wall_field=1, n_sub=8, n_floor=0.2, seed=1012, precision=32,
-                steps=4000, cap_factor_th=6.0),
+                wall_field=1, seed=1012, precision=32, steps=4000,
+                cap_factor_th=6.0),
 }
 
 
