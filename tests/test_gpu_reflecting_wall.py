@@ -80,12 +80,11 @@ def test_reflecting_wall_shock_fp32_against_oracle():
 
 
 def test_reflecting_wall_2d_shock_obeys_the_jump_conditions():
-    # 2D quasi-perpendicular RW shocks grow B_z spikes of tens of B0 along y
-    # in the ramp; with no filter in the scheme their whistler frequency
-    # k^2 B / n outruns one SSP-RK3 field step per ion step, so the box runs
-    # at dx = 1 d_i with 8 field substeps and a density floor of 0.2
-    p = W.preset("rw1", dim=2, nx=256, ny=32, dx=1.0, ppc=16, n_floor=0.2, n_sub=8, seed=1014)
-    print("rw 2D 256 x 32 at dx = 1, 16 ppc, 8 field substeps, FP32, 2400 steps", flush=True)
+    # 2D quasi-perpendicular RW shocks grow B_z spikes of tens of B0 along y;
+    # with the open field boundary the box next to the mirror breaks down,
+    # so it runs with the conducting wall, at dx = 1 d_i
+    p = W.preset("rw1", dim=2, nx=256, ny=32, dx=1.0, ppc=16, wall_field=1, seed=1014)
+    print("rw 2D 256 x 32 at dx = 1, 16 ppc, conducting wall, FP32, 2400 steps", flush=True)
     _, m = _gpu_run(p, (800, 2400), slab=4)
     # in 2D the rippled shock also heats the ions along B, so r lies between
     # the two- (3) and three-degree-of-freedom (4) strong-shock values, with
@@ -96,8 +95,8 @@ def test_reflecting_wall_2d_shock_obeys_the_jump_conditions():
 def test_reflecting_wall_3d_shock_obeys_the_jump_conditions():
     # the 3D counterpart (the paper's Run 3D is a 3D RW box at theta_Bn = 80
     # deg), with the 2D box's settings
-    p = W.preset("rw1", dim=3, nx=256, ny=16, nz=16, dx=1.0, ppc=16, n_floor=0.2, n_sub=8, seed=1018)
-    print("rw 3D 256 x 16 x 16 at dx = 1, 16 ppc, 8 field substeps, FP32, 2400 steps", flush=True)
+    p = W.preset("rw1", dim=3, nx=256, ny=16, nz=16, dx=1.0, ppc=16, wall_field=1, seed=1018)
+    print("rw 3D 256 x 16 x 16 at dx = 1, 16 ppc, conducting wall, FP32, 2400 steps", flush=True)
     _, m = _gpu_run(p, (800, 2400), slab=4)
     _jump_checks(p, m, (3.0, 5.0))
 
