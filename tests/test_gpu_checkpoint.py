@@ -1,7 +1,9 @@
 """Checkpoint and restore through the C ABI: a run restored from a
 checkpoint continues bit for bit as the original (ions compared by id,
 every field and moment array compared exactly), from host and device
-blobs; a checkpoint of another configuration, a truncated one and a
+blobs, also with the reflecting wall, the conducting field boundary, the
+binomial filter and the prescribed wall; a checkpoint of another
+configuration, a truncated one and a
 corrupt one are refused with FS_EINVAL and leave the state unchanged.
 """
 
@@ -34,11 +36,19 @@ def params(case):
                         wall_cr="faux_shock", n_modes=3, mode_amp=0.02, seed=8)
     if case == "3d_fp32":
         return W.params(dim=3, nx=32, ny=16, nz=8, dx=1.0, ppc=8, theta_deg=45.0, seed=9)
-    return W.params(dim=2, nx=64, ny=16, dx=0.5, ppc=8, n_cr=0.01, ppc_cr=8, wall_th="open",
-                    wall_cr="faux_shock", c_light=150.0, seed=10)
+    if case == "2d_rel_cr":
+        return W.params(dim=2, nx=64, ny=16, dx=0.5, ppc=8, n_cr=0.01, ppc_cr=8, wall_th="open",
+                        wall_cr="faux_shock", c_light=150.0, seed=10)
+    if case == "2d_rw_conducting_smoothed":
+        # reflecting wall with the conducting field boundary and two binomial passes
+        return W.preset("rw1", dim=2, nx=64, ny=16, dx=1.0, ppc=8, wall_field=1, smooth=2, seed=11)
+    # the prescribed faux shock (u2 drifting with the step) on the 1D FP64 box
+    return W.preset("cfg1", nx=128, ppc=32, wall_model=1, ret_f0=0.8, ret_alpha=0.5, gain=1.2, kappa=1.5,
+                    r_dot=0.4, seed=12)
 
 
-@pytest.mark.parametrize("case", ["1d_fp64_fs", "2d_fp32_cr", "3d_fp32", "2d_rel_cr"])
+@pytest.mark.parametrize("case", ["1d_fp64_fs", "2d_fp32_cr", "3d_fp32", "2d_rel_cr", "2d_rw_conducting_smoothed",
+                                  "1d_fp64_prescribed"])
 def test_restore_continues_bit_for_bit(case):
     F = lib()
     p = params(case)
