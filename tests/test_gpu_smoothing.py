@@ -2,8 +2,8 @@
 oracle) on the GPU against the oracle:
 
   * the FP64 field update (Ohm, SSP-RK3 Faraday, final Ohm) with 1 and 3
-    passes, box and periodic x, 1D/2D/3D, with J_ext and a density floor
-    that some nodes hit: B and E within 1e-12;
+    passes (CIC) and 2 (TSC), box and periodic x, 1D/2D/3D, with J_ext and a
+    density floor that some nodes hit: B and E within 1e-12;
   * an FP64 free run with the filter and the faux-shock wall: ids, cells and
     wall counts bit-exact;
   * the adjoint refuses the filter.
@@ -23,9 +23,11 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("dim", [1, 2, 3])
 @pytest.mark.parametrize("xbc", ["box", "periodic"])
-@pytest.mark.parametrize("passes", [1, 3])
-def test_field_update_fp64_with_smoothing(dim, xbc, passes):
-    p = small(dim, precision=64, xbc=xbc, beta_e=1.0, eta=0.01, j_ext=0.1, n_sub=2, smooth=passes, n_floor=0.6)
+@pytest.mark.parametrize("passes,shape", [(1, "cic"), (3, "cic"), (2, "tsc")])
+def test_field_update_fp64_with_smoothing(dim, xbc, passes, shape):
+    # TSC fills two boundary nodes on each x side, CIC one
+    p = small(dim, precision=64, xbc=xbc, beta_e=1.0, eta=0.01, j_ext=0.1, n_sub=2, smooth=passes, n_floor=0.6,
+              shape=shape)
     st = inputs.particle_state(p, 6, seed=22, drift=4.0, sigma=1.0)
     B = inputs.magnetic_field(p, 0.05, seed=9)
     sim, o = setup_pair(p, st, B)
