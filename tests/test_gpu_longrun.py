@@ -5,7 +5,8 @@ compared on binned statistics after many steps rather than state by state.
 Two boxes shaped like the paper's runs, reduced so that the oracle finishes
 in seconds: the 1D box with TSC shapes and a 1% CR population released from
 the wall (1500 steps), and the 2D box with M_A = 30 and CRs (500 steps);
-each also with the relativistic push.
+each also with the relativistic push, and the 1D box with the prescribed
+wall on the CRs.
 Compared within 2%:
   * the transverse magnetic energy profile dB^2(x) = (B_y - B0_y)^2 +
     (B_z - B0_z)^2 averaged over 8 slabs in x;
@@ -33,6 +34,11 @@ CASES = {
                                c_light=150.0), 1500),
     "2d_cr_rel": (W.preset("cfg3", nx=128, ny=32, ppc=16, ppc_cr=16, seed=37, n_modes=4, mode_amp=0.05,
                            c_light=300.0), 500),
+    # the 1D box with the prescribed wall on the CRs (a gain of 2% per return:
+    # CRs return many times, and a larger gain compounds past v_max)
+    "1d_tsc_cr_prescribed": (W.preset("cfg2", nx=512, ppc=64, ppc_cr=64, seed=39, n_modes=4, mode_amp=0.05,
+                                      wall_model=1, ret_f0=0.9, ret_alpha=-0.2, gain=1.02, kappa=1.0,
+                                      r_dot=0.05), 1500),
 }
 
 
