@@ -4,7 +4,9 @@
 // FP64 moments) with every discrete decision of the forward run held fixed:
 // the cell of each ion, FS reflections (the eq. 1 decision), removals,
 // injection counts and the density floor.  The FS kick that follows a
-// reflection is differentiated, including its dependence on u2 = u_sh / r.
+// reflection is differentiated, including its dependence on u2 = u_sh / r;
+// the reflecting wall's mirror (x' = 2L - x, v_x' = -v_x) is its own
+// transpose on the x components.
 //
 // One reverse step n+1 -> n, given the adjoints lam(B^{n+1}), lam(E^{n+1}),
 // lam(Bbar^{n+1}) and the particle adjoints lam(x^{n+1}), lam(v^{n+1/2}):
@@ -281,7 +283,7 @@ template <typename R, int D, int S>
 __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
                                                   const R* __restrict__ gather, const uint8_t* __restrict__ refl_of,
                                                   PLam<R> lam, double* __restrict__ lEB, long nnode, uint64_t step,
-                                                  double* grads, int split) {
+                                                  double* grads, int split, int mirror) {
     using X = Extent<D, S>;
     using T = TileShape<D>;
     constexpr int LO = Stencil<S>::LO, N = Stencil<S>::N;
@@ -342,7 +344,11 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
             }
         R v1[3] = {v[0], v[1], v[2]};
         boris<R, false>(v1, E, B, hR, (R)0);   // the adjoint covers the non-relativistic push
-        if (refl) {
+        if (refl && mirror) {
+            // the reflecting wall: x' = 2 L - x and v_x' = -v_x
+            lx[0] = -lx[0];
+            lv[0] = -lv[0];
+        } else if (refl) {
             // overshoot as the forward move computed it
             R xi = o[0] + v1[0] * dtdxR;
             R fl = floor(xi);

@@ -656,7 +656,7 @@ int adjoint_step_impl(fs_handle* h, const fs_particles* sp_n, const fs_fields* f
         const int sp_ = split_of(P.tile_cap);
         k_push_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
             h->G, in, P.tile_count[P.cur], P.tile_cap, static_cast<const R*>(f_n->gather), rec->refl, plam<R>(lam, D),
-            lam->lE, nn, (uint64_t)step, grads, sp_);
+            lam->lE, nn, (uint64_t)step, grads, sp_, policy_of(h, k) == FS_WALL_SPECULAR ? 1 : 0);
     }
     return hip_check(h, hipGetLastError(), "adjoint step launch");
 }

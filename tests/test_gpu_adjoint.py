@@ -27,6 +27,9 @@ CASES = {
                         n_sub=2), 8),
     "3d_box": (dict(dim=3, nx=8, ny=4, nz=4, dx=0.5, dt=0.0047, ppc=2, ppc_cr=2, n_cr=0.05, theta_deg=20.0,
                     wall_th="faux_shock", wall_cr="faux_shock", n_modes=2, mode_amp=0.05, seed=17), 6),
+    # the reflecting wall (SPECULAR) on the thermal ions: the mirror's transpose
+    "specular_th": (dict(dim=1, nx=16, dx=0.5, dt=0.0047, ppc=8, ppc_cr=8, n_cr=0.05, wall_th="specular",
+                         wall_cr="faux_shock", n_modes=2, mode_amp=0.05, seed=19, u_sh=19.3), 12),
 }
 
 
