@@ -138,8 +138,7 @@ typedef struct fs_config {
                                holds at the wall node (open to the outflowing
                                plasma of the faux-shock runs).  1: a conducting
                                wall at rest, E_y = E_z = 0 at the wall node (the
-                               reflecting-wall runs, whose plasma piles up there).
-                               The adjoint entry points refuse 1. */
+                               reflecting-wall runs, whose plasma piles up there). */
 } fs_config;
 
 /* Sizes the caller must allocate, reported by fs_layout(). */

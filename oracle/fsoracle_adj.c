@@ -89,6 +89,11 @@ static void geo_init(geo* G, const ora_cfg* c)
 
 /* The inflow node x = 0 of the box (reading R10). */
 static int inflow_node(const geo* G, int64_t i) { return G->c.xbc != ORA_XBC_PERIODIC && i == 0; }
+/* The conducting wall node x = L (reading R14): E_y = E_z = 0 there. */
+static int conduct_node(const geo* G, int64_t i)
+{
+    return G->c.xbc != ORA_XBC_PERIODIC && G->c.wall_field == 1 && i == G->c.nx;
+}
 
 /* ---------------------------------------------------------------------- */
 /* index rules (readings R3, R9)                                          */
@@ -402,6 +407,7 @@ static void ohm_fw(const geo* G, const double* B, const double* fn, const double
         E[1] = G->c.u_sh * G->B0[2];
         E[2] = -G->c.u_sh * G->B0[1];
     }
+    if (conduct_node(G, i)) { E[1] = 0.0; E[2] = 0.0; }
 }
 
 /* Transpose of Ohm at one node: (lam_E, lam_Bbar) -> lam_B (centres),
@@ -420,6 +426,12 @@ static void ohm_vjp_node(const geo* G, const double* B, const double* fn, const 
     if (inflow_node(G, i)) {
         if (G->lu_inflow) *G->lu_inflow += lE[1] * G->B0[2] - lE[2] * G->B0[1];
         lE = lE0;
+    }
+    /* at the conducting wall node E_y, E_z are constants: only lam_E_x passes */
+    double lEc[3];
+    if (conduct_node(G, i)) {
+        lEc[0] = lE[0]; lEc[1] = 0.0; lEc[2] = 0.0;
+        lE = lEc;
     }
     /* E = num / ne + eta J */
     double lnum[3], lJ[3], lbb[3], lG[3], lgp[3], tmp[3];

@@ -525,6 +525,7 @@ __global__ __launch_bounds__(256) void k_ohm_adj(FieldGeo F, const double* __res
     // E = num / ne + eta J; at the inflow node E = -u_sh x_hat x B0, so its
     // adjoint goes to u_sh alone (lam_Bbar still reaches the centres)
     const bool inflow = inflow_node(F, i);
+    const bool conduct = F.conduct && i == F.nx;   // E_y = E_z = 0 there: constants
     if (inflow) {
         const double le_y = lE[nnode + n], le_z = lE[2 * nnode + n];
         unsafeAtomicAdd(grads, le_y * F.B0[2] - le_z * F.B0[1]);
@@ -533,7 +534,7 @@ __global__ __launch_bounds__(256) void k_ohm_adj(FieldGeo F, const double* __res
     double lne = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double le = inflow ? 0.0 : lE[(long)d * nnode + n];
+        const double le = (inflow || (conduct && d > 0)) ? 0.0 : lE[(long)d * nnode + n];
         lnum[d] = le / ne;
         lne -= num[d] * le / (ne * ne);
         lJ[d] = F.eta * le;

@@ -933,7 +933,6 @@ int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n
     if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
     if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
     if (h->cfg.smooth != 0) return fail(h, FS_EINVAL, "the adjoint covers the unfiltered moments only");
-    if (h->cfg.wall_field != 0) return fail(h, FS_EINVAL, "the adjoint covers the open wall field only");
     if (!f_n->B || !f_n->gather || !f_n1->B) return fail(h, FS_EINVAL, "NULL field array");
     if (step < 0) return fail(h, FS_EINVAL, "negative step");
     int64_t cth = 0, ccr = 0;
@@ -957,7 +956,6 @@ int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, 
     if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
     if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
     if (h->cfg.smooth != 0) return fail(h, FS_EINVAL, "the adjoint covers the unfiltered moments only");
-    if (h->cfg.wall_field != 0) return fail(h, FS_EINVAL, "the adjoint covers the open wall field only");
     if (!f0->B) return fail(h, FS_EINVAL, "NULL field array");
     int rc = check_adjoint(h, lam);
     if (!rc) rc = check_particles(h, sp0);

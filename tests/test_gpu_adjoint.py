@@ -30,6 +30,12 @@ CASES = {
     # the reflecting wall (SPECULAR) on the thermal ions: the mirror's transpose
     "specular_th": (dict(dim=1, nx=16, dx=0.5, dt=0.0047, ppc=8, ppc_cr=8, n_cr=0.05, wall_th="specular",
                          wall_cr="faux_shock", n_modes=2, mode_amp=0.05, seed=19, u_sh=19.3), 12),
+    "specular_conducting": (dict(dim=1, nx=16, dx=0.5, dt=0.0047, ppc=8, ppc_cr=8, n_cr=0.05, wall_th="specular",
+                                 wall_cr="faux_shock", wall_field=1, n_modes=2, mode_amp=0.05, seed=19,
+                                 u_sh=19.3), 12),
+    "2d_conducting": (dict(dim=2, nx=8, ny=4, dx=0.5, dt=0.0047, ppc=4, ppc_cr=4, n_cr=0.05, theta_deg=30.0,
+                           wall_th="specular", wall_cr="faux_shock", wall_field=1, n_modes=2, mode_amp=0.05,
+                           seed=21, n_sub=2), 8),
 }
 
 

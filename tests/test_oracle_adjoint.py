@@ -155,6 +155,10 @@ CASES = {
     # the reflecting wall (SPECULAR) on the thermal ions, FS on the CRs
     "specular_th": (dict(dim=1, nx=16, dx=0.5, dt=0.0047, ppc=8, ppc_cr=8, n_cr=0.05, wall_th="specular",
                          wall_cr="faux_shock", n_modes=2, mode_amp=0.05, seed=19, u_sh=19.3), 12, 1),
+    # the same with the conducting field boundary at the wall
+    "specular_conducting": (dict(dim=1, nx=16, dx=0.5, dt=0.0047, ppc=8, ppc_cr=8, n_cr=0.05, wall_th="specular",
+                                 wall_cr="faux_shock", wall_field=1, n_modes=2, mode_amp=0.05, seed=19,
+                                 u_sh=19.3), 12, 1),
 }
 
 
