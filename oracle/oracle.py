@@ -8,9 +8,12 @@ and returns numpy arrays.  It imports nothing from the GPU package.
 
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
+import shutil
 import subprocess
+import tempfile
 
 import numpy as np
 
@@ -96,50 +99,94 @@ def make_cfg(p: dict, deposit_mode: str = "fixed") -> OraCfg:
 _lib = None
 
 
+def _load(path: str):
+    L = C.CDLL(path)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.ora_new.restype = vp
+    L.ora_new.argtypes = [C.POINTER(OraCfg)]
+    L.ora_free.argtypes = [vp]
+    L.ora_init.argtypes = [vp, vp]
+    L.ora_step.argtypes = [vp, i32, C.POINTER(OraStats)]
+    for f in ("ora_count",):
+        getattr(L, f).restype = i64
+        getattr(L, f).argtypes = [vp, i32]
+    for f in ("ora_next_id", "ora_get_step"):
+        getattr(L, f).restype = i64
+        getattr(L, f).argtypes = [vp]
+    L.ora_set_clock.argtypes = [vp, i64, i64]
+    L.ora_set_particles.argtypes = [vp, i32, i64, vp, vp, vp, vp]
+    L.ora_get_particles.argtypes = [vp, i32, vp, vp, vp, vp]
+    for f in ("ora_set_B", "ora_get_B", "ora_set_E", "ora_get_E", "ora_get_Bbar",
+              "ora_profile", "ora_diag", "ora_sizes", "ora_fixed_point"):
+        getattr(L, f).argtypes = [vp, vp]
+    L.ora_compute_E.argtypes = [vp]
+    for f in ("ora_get_moments", "ora_get_cmoments", "ora_set_moments"):
+        getattr(L, f).argtypes = [vp, i32, vp]
+    L.ora_get_fluid.argtypes = [vp, vp, vp]
+    L.ora_loss.restype = dp
+    L.ora_loss.argtypes = [vp]
+    L.ora_wall_list.argtypes = [C.POINTER(OraCfg), i64, i32, i64, vp, vp, vp, vp, vp]
+    L.ora_philox.argtypes = [vp, C.c_uint64, C.c_uint64, vp]
+    L.ora_inject_counts.argtypes = [C.POINTER(OraCfg), i64, vp]
+    L.ora_record.argtypes = [vp, i32]
+    pc = C.POINTER(OraCfg)
+    L.ora_push_sample.argtypes = [pc, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+    L.ora_ohm_sample.argtypes = [pc, vp, vp, vp, i64, vp, vp, vp]
+    L.ora_adjoint.restype = C.c_int
+    L.ora_adjoint.argtypes = [pc, vp, i64, vp, vp]
+    L.ora_adj_boris.argtypes = [vp, vp, vp, dp, vp, vp, vp, vp, vp]
+    L.ora_adj_kick.argtypes = [pc, i64, C.c_uint64, vp, dp, dp, dp, vp, vp, vp]
+    L.ora_adj_ohm.argtypes = [pc, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.ora_adj_rk3.argtypes = [pc, vp, vp, vp, vp, vp, vp, vp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         build_oracle()
-        L = C.CDLL(LIB_PATH)
-        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
-        L.ora_new.restype = vp
-        L.ora_new.argtypes = [C.POINTER(OraCfg)]
-        L.ora_free.argtypes = [vp]
-        L.ora_init.argtypes = [vp, vp]
-        L.ora_step.argtypes = [vp, i32, C.POINTER(OraStats)]
-        for f in ("ora_count",):
-            getattr(L, f).restype = i64
-            getattr(L, f).argtypes = [vp, i32]
-        for f in ("ora_next_id", "ora_get_step"):
-            getattr(L, f).restype = i64
-            getattr(L, f).argtypes = [vp]
-        L.ora_set_clock.argtypes = [vp, i64, i64]
-        L.ora_set_particles.argtypes = [vp, i32, i64, vp, vp, vp, vp]
-        L.ora_get_particles.argtypes = [vp, i32, vp, vp, vp, vp]
-        for f in ("ora_set_B", "ora_get_B", "ora_set_E", "ora_get_E", "ora_get_Bbar",
-                  "ora_profile", "ora_diag", "ora_sizes", "ora_fixed_point"):
-            getattr(L, f).argtypes = [vp, vp]
-        L.ora_compute_E.argtypes = [vp]
-        for f in ("ora_get_moments", "ora_get_cmoments", "ora_set_moments"):
-            getattr(L, f).argtypes = [vp, i32, vp]
-        L.ora_get_fluid.argtypes = [vp, vp, vp]
-        L.ora_loss.restype = dp
-        L.ora_loss.argtypes = [vp]
-        L.ora_wall_list.argtypes = [C.POINTER(OraCfg), i64, i32, i64, vp, vp, vp, vp, vp]
-        L.ora_philox.argtypes = [vp, C.c_uint64, C.c_uint64, vp]
-        L.ora_inject_counts.argtypes = [C.POINTER(OraCfg), i64, vp]
-        L.ora_record.argtypes = [vp, i32]
-        pc = C.POINTER(OraCfg)
-        L.ora_push_sample.argtypes = [pc, vp, vp, i64, vp, vp, vp, vp, vp, vp]
-        L.ora_ohm_sample.argtypes = [pc, vp, vp, vp, i64, vp, vp, vp]
-        L.ora_adjoint.restype = C.c_int
-        L.ora_adjoint.argtypes = [pc, vp, i64, vp, vp]
-        L.ora_adj_boris.argtypes = [vp, vp, vp, dp, vp, vp, vp, vp, vp]
-        L.ora_adj_kick.argtypes = [pc, i64, C.c_uint64, vp, dp, dp, dp, vp, vp, vp]
-        L.ora_adj_ohm.argtypes = [pc, vp, vp, vp, vp, vp, vp, vp, vp]
-        L.ora_adj_rk3.argtypes = [pc, vp, vp, vp, vp, vp, vp, vp]
-        _lib = L
+        _lib = _load(LIB_PATH)
     return _lib
+
+
+@contextlib.contextmanager
+def variant(replacements):
+    """Planted-mistake oracle, for the tests that show a pin has teeth.
+
+    Builds a copy of the oracle sources in a temporary directory with each
+    (old, new) or (file, old, new) text replacement applied (each `old` must
+    occur exactly once in the sources, or in that file), and makes it the library that everything created inside
+    the `with` block uses.  The oracle's own sources and library are not
+    touched."""
+    global _lib
+    tmp = tempfile.mkdtemp(prefix="fsoracle_variant_")
+    saved = lib()
+    try:
+        texts = {}
+        for s in SOURCES + ["fsoracle.h"]:
+            with open(os.path.join(HERE, s)) as f:
+                texts[s] = f.read()
+        for rep in replacements:
+            # (old, new) anywhere in the sources, or (file, old, new)
+            files = [rep[0]] if len(rep) == 3 else list(texts)
+            old, new = rep[-2], rep[-1]
+            total = sum(texts[s].count(old) for s in files)
+            if total != 1:
+                raise ValueError(f"replacement target occurs {total} times: {old!r}")
+            hit = next(s for s in files if old in texts[s])
+            texts[hit] = texts[hit].replace(old, new)
+        for s, t in texts.items():
+            with open(os.path.join(tmp, s), "w") as f:
+                f.write(t)
+        out = os.path.join(tmp, "libfsoracle_variant.so")
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-o", out] + \
+              [os.path.join(tmp, s) for s in SOURCES] + ["-lm"]
+        subprocess.run(cmd, check=True, capture_output=True)
+        _lib = _load(out)
+        yield _lib
+    finally:
+        _lib = saved
+        shutil.rmtree(tmp, ignore_errors=True)
 
 
 def _p(a: np.ndarray):
@@ -179,21 +226,22 @@ class Oracle:
     def __init__(self, p: dict, deposit_mode: str = "fixed"):
         self.p = dict(p)
         self.cfg = make_cfg(p, deposit_mode)
-        self.h = lib().ora_new(C.byref(self.cfg))
+        self.L = lib()
+        self.h = self.L.ora_new(C.byref(self.cfg))
         if not self.h:
             raise ValueError("oracle rejected the configuration")
         s = np.zeros(6, dtype=np.int64)
-        lib().ora_sizes(self.h, _p(s))
+        self.L.ora_sizes(self.h, _p(s))
         self.nxn, self.ndx, self.nyc, self.nzc, self.ncent, self.nnode = (int(x) for x in s)
         fp = np.zeros(3, dtype=np.int32)
-        lib().ora_fixed_point(self.h, _p(fp))
+        self.L.ora_fixed_point(self.h, _p(fp))
         self.b, self.sv, self.SW = (int(x) for x in fp)
         self.ndep = self.ndx * self.nyc * self.nzc
 
     def __del__(self):
         h = getattr(self, "h", None)
         if h:
-            lib().ora_free(h)
+            self.L.ora_free(h)
             self.h = None
 
     # --- evolution -------------------------------------------------------
@@ -201,30 +249,30 @@ class Oracle:
         a = None
         if amps is not None:
             a = np.ascontiguousarray(amps, dtype=np.float64)
-        return lib().ora_init(self.h, _p(a) if a is not None else None)
+        return self.L.ora_init(self.h, _p(a) if a is not None else None)
 
     def step(self, flags: int = ALL) -> dict:
         st = OraStats()
-        lib().ora_step(self.h, int(flags), C.byref(st))
+        self.L.ora_step(self.h, int(flags), C.byref(st))
         return st.as_dict()
 
     def compute_E(self):
-        lib().ora_compute_E(self.h)
+        self.L.ora_compute_E(self.h)
 
     # --- state -----------------------------------------------------------
     @property
     def step_index(self) -> int:
-        return int(lib().ora_get_step(self.h))
+        return int(self.L.ora_get_step(self.h))
 
     @property
     def next_id(self) -> int:
-        return int(lib().ora_next_id(self.h))
+        return int(self.L.ora_next_id(self.h))
 
     def set_clock(self, step: int, next_id: int):
-        lib().ora_set_clock(self.h, int(step), int(next_id))
+        self.L.ora_set_clock(self.h, int(step), int(next_id))
 
     def count(self, species: int = 0) -> int:
-        return int(lib().ora_count(self.h, species))
+        return int(self.L.ora_count(self.h, species))
 
     def particles(self, species: int = 0) -> dict:
         n = self.count(species)
@@ -233,7 +281,7 @@ class Oracle:
         v = np.zeros((n, 3))
         ids = np.zeros(n, dtype=np.uint64)
         if n:
-            lib().ora_get_particles(self.h, species, _p(cell), _p(off), _p(v), _p(ids))
+            self.L.ora_get_particles(self.h, species, _p(cell), _p(off), _p(v), _p(ids))
         return dict(cell=cell, off=off, v=v, id=ids)
 
     def set_particles(self, species: int, cell, off, v, ids):
@@ -241,68 +289,68 @@ class Oracle:
         off = np.ascontiguousarray(np.asarray(off, dtype=np.float64).reshape(-1, 3))
         v = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1, 3))
         ids = np.ascontiguousarray(ids, dtype=np.uint64)
-        lib().ora_set_particles(self.h, species, len(ids), _p(cell), _p(off), _p(v), _p(ids))
+        self.L.ora_set_particles(self.h, species, len(ids), _p(cell), _p(off), _p(v), _p(ids))
 
     def B(self):
         out = np.zeros((self.ncent, 3))
-        lib().ora_get_B(self.h, _p(out))
+        self.L.ora_get_B(self.h, _p(out))
         return out
 
     def set_B(self, B):
         B = np.ascontiguousarray(np.asarray(B, dtype=np.float64).reshape(self.ncent, 3))
-        lib().ora_set_B(self.h, _p(B))
+        self.L.ora_set_B(self.h, _p(B))
 
     def E(self):
         out = np.zeros((self.nnode, 3))
-        lib().ora_get_E(self.h, _p(out))
+        self.L.ora_get_E(self.h, _p(out))
         return out
 
     def set_E(self, E):
         E = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(self.nnode, 3))
-        lib().ora_set_E(self.h, _p(E))
+        self.L.ora_set_E(self.h, _p(E))
 
     def Bbar(self):
         out = np.zeros((self.nnode, 3))
-        lib().ora_get_Bbar(self.h, _p(out))
+        self.L.ora_get_Bbar(self.h, _p(out))
         return out
 
     def moments(self, species: int = 0):
         out = np.zeros((self.ndep, 4), dtype=np.int64)
-        lib().ora_get_moments(self.h, species, _p(out))
+        self.L.ora_get_moments(self.h, species, _p(out))
         return out
 
     def set_moments(self, species: int, m):
         m = np.ascontiguousarray(np.asarray(m, dtype=np.int64).reshape(self.ndep, 4))
-        lib().ora_set_moments(self.h, species, _p(m))
+        self.L.ora_set_moments(self.h, species, _p(m))
 
     def cmoments(self, species: int = 0):
         out = np.zeros((self.ndep, 4))
-        lib().ora_get_cmoments(self.h, species, _p(out))
+        self.L.ora_get_cmoments(self.h, species, _p(out))
         return out
 
     def fluid(self):
         n = np.zeros(self.nnode)
         g = np.zeros((self.nnode, 3))
-        lib().ora_get_fluid(self.h, _p(n), _p(g))
+        self.L.ora_get_fluid(self.h, _p(n), _p(g))
         return n, g
 
     def profile(self):
         out = np.zeros(int(self.p["nx"]))
-        lib().ora_profile(self.h, _p(out))
+        self.L.ora_profile(self.h, _p(out))
         return out
 
     def loss(self) -> float:
-        return float(lib().ora_loss(self.h))
+        return float(self.L.ora_loss(self.h))
 
     def diag(self) -> dict:
         out = np.zeros(8)
-        lib().ora_diag(self.h, _p(out))
+        self.L.ora_diag(self.h, _p(out))
         keys = ("field_energy", "kinetic_th", "kinetic_cr", "n_th", "n_cr", "loss",
                 "max_divB", "bperp2")
         return dict(zip(keys, (float(x) for x in out)))
 
     def record(self, on: bool = True):
-        lib().ora_record(self.h, 1 if on else 0)
+        self.L.ora_record(self.h, 1 if on else 0)
 
 
 # --- reverse mode (fsoracle_adj.c) ------------------------------------------
