@@ -27,13 +27,16 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def push_bytes_dim(n_ions, L, dim, nsp, rb=4):
+def push_bytes_dim(n_ions, L, dim, nsp, rb=4, with_id=False):
     """Algorithmic HBM bytes of one step's push launches with rb-byte reals
-    (4: FP32, 8: FP64): every ion's state read and written once (int32 cell,
-    D offsets, 3 velocities, uint32 id), and per species launch the gather
-    grid read once (6 reals per node) and the int64 moments written once
-    (32 B per node)."""
-    return n_ions * 2 * (8 + rb * (dim + 3)) + nsp * (int(L.nnode) * 6 * rb + int(L.ndep) * 32)
+    (4: FP32, 8: FP64), counted as the method needs them: every ion's state
+    read and written once (int32 cell, D offsets, 3 velocities: 28 B each
+    way in 3D FP32), and per species launch the gather grid read once (6
+    reals per node) and the int64 moments written once (32 B per node).
+    with_id adds the uint32 particle id the bins carry along with each ion
+    (4 B each way), which the method itself does not move."""
+    ion = 2 * (4 + rb * (dim + 3)) + (8 if with_id else 0)
+    return n_ions * ion + nsp * (int(L.nnode) * 6 * rb + int(L.ndep) * 32)
 
 
 def workload_throughput(name, steps, warmup, **overrides):
@@ -66,6 +69,7 @@ def workload_throughput(name, steps, warmup, **overrides):
     dim = int(p["dim"])
     alg = push_bytes_dim(nav, sim.L, dim, nsp)
     ach = alg / (push_ms * 1e-3) / 1e9
+    ach_id = push_bytes_dim(nav, sim.L, dim, nsp, with_id=True) / (push_ms * 1e-3) / 1e9
     out = {
         "workload": f"{dim}D3V FP32 {p['nx']}x{p['ny']}x{p['nz']} cells dx={p['dx']} d_i, {p['ppc']} ppc"
                     + (f" + CRs n_cr={p['n_cr']:g}" if sim.has_cr else "") + f", {p['shape']}, M_A={p['u_sh']:g}"
@@ -81,6 +85,7 @@ def workload_throughput(name, steps, warmup, **overrides):
         "wall_ms": ms[1] / max(nrec[1], 1),
         "field_ms": ms[3] / max(nrec[3], 1),
         "push_alg_bytes_per_step": alg, "push_GBs": ach, "push_frac_of_hbm_peak": ach / HBM_PEAK_GBS,
+        "push_frac_with_id": ach_id / HBM_PEAK_GBS,
         "final_step_flags": st["flags"],
     }
     del sim
@@ -88,12 +93,12 @@ def workload_throughput(name, steps, warmup, **overrides):
     return out
 
 
-def push_bytes(np_live, L):
-    """Algorithmic HBM bytes of one launch of the fused push kernel: the ion
-    state read and written once (int32 cell, 3 fp32 offsets, 3 fp32
-    velocities, uint32 id = 32 B each way), the FP32 E/Bbar of every node read
-    once (24 B) and the four int64 moments of every node written once (32 B)."""
-    return np_live * 64 + int(L.nnode) * 24 + int(L.ndep) * 32
+def push_bytes(np_live, L, with_id=False):
+    """Algorithmic HBM bytes of one launch of the fused 3D FP32 push kernel:
+    56 B per ion (28 B of state in and out), 24 B of E/Bbar read and 32 B of
+    int64 moments written per node, i.e. 63 B per particle-update at 8 ions
+    per cell; with_id adds the 8 B of the id."""
+    return push_bytes_dim(np_live, L, 3, 1, 4, with_id)
 
 
 def traffic_from_profiles(kernel_hash):
@@ -405,7 +410,9 @@ def main():
     region_ms = (ms[0] + ms[1] + ms[2]) / max(nrec[0], 1)
     dim = int(p["dim"])
     nsp = 2 if sim.has_cr else 1
-    alg = push_bytes(np_avg, sim.L) if (dim == 3 and nsp == 1) else push_bytes_dim(np_avg, sim.L, dim, nsp, int(sim.L.real_bytes))
+    rb = int(sim.L.real_bytes)
+    alg = push_bytes_dim(np_avg, sim.L, dim, nsp, rb)
+    alg_id = push_bytes_dim(np_avg, sim.L, dim, nsp, rb, with_id=True)
     achieved = alg / (push_ms * 1e-3) / 1e9
     # the committed counters are of the 3D benchmark box's push kernel
     profiled = args.workload == "cfg4"
@@ -461,7 +468,11 @@ def main():
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": f"k_push<{'double' if int(p['precision']) == 64 else 'float'},{dim},{p['shape'].upper()},deposit>",
             "alg_bytes_per_launch": alg,
+            "alg_bytes_per_particle_update": alg / np_avg,
             "avg_launch_ms": push_ms,
+            # the same launch counting the uint32 id each ion carries
+            "alg_bytes_per_launch_with_id": alg_id,
+            "frac_with_id": alg_id / (push_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "copy_GBs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
         },
         "atomics": atomics,

@@ -376,6 +376,26 @@ int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n
 int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, fs_adjoint* lam, double* grads,
                     hipStream_t s);
 
+/* The loss of the reverse-mode workload: the magnetic energy of the
+ * transverse field in the precursor, the region ahead of the shock where
+ * the CR current drives the Bell instability (Sec. 3), taken as the
+ * downstream half of the box next to the wall,
+ *   L = sum over cell centres with x index i >= nx/2 of B_y^2 + B_z^2.
+ * f->B: FP64 planar B (3 x ncent, device).  loss: device pointer to one
+ * double, written asynchronously on s (valid after a stream sync).  The sum
+ * is taken in a fixed order (partials per workgroup of a fixed grid in the
+ * handle's scratch, then one workgroup), so repeated calls agree bit for
+ * bit.  FS_EINVAL on a NULL argument. */
+int fs_precursor_loss(fs_handle* h, const fs_fields* f, double* loss, hipStream_t s);
+
+/* Start of a reverse sweep for that loss.  Zeroes every particle adjoint
+ * of *lam (x[d] for d < dim and v[3], nid entries each, in the particle
+ * precision), lE and grads (2 + n_modes doubles, device), and sets
+ * lB = dL/dB at the final state f->B: (0, 2 B_y, 2 B_z) at the centres with
+ * i >= nx/2, 0 elsewhere.  FS_EINVAL on a NULL array, FS_ECAPACITY if
+ * lam->nid is below the ids the run has handed out. */
+int fs_adjoint_seed(fs_handle* h, const fs_fields* f, fs_adjoint* lam, double* grads, hipStream_t s);
+
 /* Phase timing with HIP events recorded on the caller's stream (benchmark
  * support).  While enabled, every fs_step records an event pair around each
  * phase: 0 = push kernels (gather, Boris, move, boundaries, fused deposit),

@@ -10,8 +10,9 @@ fills the precursor).  The derivative is that of the continuous-deposit step
 with every discrete decision of the forward run held fixed (pathwise, common
 random numbers).
 
-Everything numeric runs in the library (``fs_step_record``,
-``fs_adjoint_step``, ``fs_adjoint_init``); this module owns the buffers and
+Everything numeric runs in the library (``fs_precursor_loss``,
+``fs_adjoint_seed``, ``fs_step_record``, ``fs_adjoint_step``,
+``fs_adjoint_init``); this module owns the buffers and
 the schedule: a forward pass that keeps a checkpoint every K steps, and a
 reverse pass that re-runs each K-step segment from its checkpoint with
 recording and walks it backwards.  Particle adjoints are indexed by particle
@@ -151,12 +152,15 @@ class AdjointRun:
                 self.checkpoints[n] = _State(sim, self.nsp)
             sim.step(n, stats=False)
         self.nid = sim.next_id
-        return float(self.loss_value())
+        return self.loss_value()
 
-    def loss_value(self) -> torch.Tensor:
-        nx = int(self.p["nx"])
-        B = self.sim.B.view(3, -1, nx)
-        return (B[1, :, nx // 2:] ** 2 + B[2, :, nx // 2:] ** 2).sum()
+    def loss_value(self) -> float:
+        """The precursor loss of the current state (fs_precursor_loss)."""
+        sim = self.sim
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        sim._check(sim.lib.fs_precursor_loss(sim.h, C.byref(sim.f), C.c_void_p(out.data_ptr()), sim.stream))
+        torch.cuda.synchronize(self.device)
+        return float(out.item())
 
     # --- reverse ----------------------------------------------------------
     def _alloc_lambda(self):
@@ -165,19 +169,20 @@ class AdjointRun:
         nid = max(self.nid, 1)
         lam = F.FsAdjoint()
         self._lam_keep = []
+        # buffers only: fs_adjoint_seed fills them
         for d in range(3):
-            vv = torch.zeros(nid, dtype=sim.real, device=self.device)
+            vv = torch.empty(nid, dtype=sim.real, device=self.device)
             lam.v[d] = vv.data_ptr()
             self._lam_keep.append(vv)
             if d < dim:
-                xv = torch.zeros(nid, dtype=sim.real, device=self.device)
+                xv = torch.empty(nid, dtype=sim.real, device=self.device)
                 lam.x[d] = xv.data_ptr()
                 self._lam_keep.append(xv)
             else:
                 lam.x[d] = None
         lam.nid = nid
-        self.lB = torch.zeros(3, int(sim.L.ncent), dtype=torch.float64, device=self.device)
-        self.lE = torch.zeros(6, int(sim.L.nnode), dtype=torch.float64, device=self.device)
+        self.lB = torch.empty(3, int(sim.L.ncent), dtype=torch.float64, device=self.device)
+        self.lE = torch.empty(6, int(sim.L.nnode), dtype=torch.float64, device=self.device)
         lam.lB, lam.lE = self.lB.data_ptr(), self.lE.data_ptr()
         self.lam = lam
 
@@ -186,16 +191,13 @@ class AdjointRun:
         forward pass."""
         sim = self.sim
         lib, stream = sim.lib, sim.stream
-        nx = int(self.p["nx"])
         self._alloc_lambda()
-        B = sim.B.view(3, -1, nx)
-        lBv = self.lB.view(3, -1, nx)
-        lBv[1, :, nx // 2:] = 2.0 * B[1, :, nx // 2:]
-        lBv[2, :, nx // 2:] = 2.0 * B[2, :, nx // 2:]
-        grads = torch.zeros(2 + int(self.p["n_modes"]), dtype=torch.float64, device=self.device)
+        grads = torch.empty(2 + int(self.p["n_modes"]), dtype=torch.float64, device=self.device)
         gptr = C.c_void_p(grads.data_ptr())
+        # zero every adjoint and seed lB = dL/dB at the final state
+        sim._check(lib.fs_adjoint_seed(sim.h, C.byref(sim.f), C.byref(self.lam), gptr, stream))
         K = self.K_run
-        refl = [torch.zeros(self.lam.nid, dtype=torch.uint8, device=self.device) for _ in range(K)]
+        refl = [torch.empty(self.lam.nid, dtype=torch.uint8, device=self.device) for _ in range(K)]   # cleared by each recorded step
         slots = [_State(sim, self.nsp, copy=False) for _ in range(K)]
         for s0 in sorted(self.checkpoints, reverse=True):
             s1 = min(s0 + K, self.nsteps)

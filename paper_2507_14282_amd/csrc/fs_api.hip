@@ -910,7 +910,8 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
     inject_counts(h->cfg, step, cth, ccr);
     const int64_t ninj = (cth + ccr) * h->L.nyc * h->L.nzc;
     if (h->next_id + ninj > rec->nid) return fail(h, FS_ECAPACITY, "record smaller than the ids the step hands out");
-    int rc = hip_check(h, hipMemsetAsync(rec->refl, 0, (size_t)rec->nid, s), "record clear");
+    if (rec->nid > 0) k_fill_u8<<<std::min<unsigned>(grid_for(rec->nid), 4096u), 256, 0, s>>>(rec->refl, 0, rec->nid);
+    int rc = hip_check(h, hipGetLastError(), "record clear");
     if (rc) return rc;
     rec->id0 = h->next_id;
     return step_common(h, sp, f, step, FS_ALL, st, s, rec);
@@ -1480,6 +1481,35 @@ int fs_bperp_spectrum(fs_handle* h, const fs_fields* f, double* out, hipStream_t
     k_bperp_reduce<<<grid_for(nk), 256, 0, s>>>(nk, ngroups, 1.0 / ((double)nlines * (double)nx * (double)nx), part,
                                                 out);
     return hip_check(h, hipGetLastError(), "spectrum launch");
+}
+
+int fs_precursor_loss(fs_handle* h, const fs_fields* f, double* loss, hipStream_t s) {
+    if (!h || !f || !f->B || !loss) return fail(h, FS_EINVAL, "NULL argument");
+    const long nc = h->L.ncent;
+    const int64_t total = (int64_t)(h->cfg.nx - h->cfg.nx / 2) * (nc / h->cfg.nx);
+    const unsigned g = std::min<unsigned>(grid_for(total), (unsigned)std::min<int64_t>(kLossParts, h->npart));
+    k_loss_part<<<g, 256, 0, s>>>(h->F, f->B, nc, h->part);
+    k_loss_final<<<1, 256, 0, s>>>(h->part, (int)g, loss);
+    return hip_check(h, hipGetLastError(), "loss launch");
+}
+
+int fs_adjoint_seed(fs_handle* h, const fs_fields* f, fs_adjoint* lam, double* grads, hipStream_t s) {
+    if (!h || !f || !f->B || !grads) return fail(h, FS_EINVAL, "NULL argument");
+    int rc = check_adjoint(h, lam);
+    if (rc) return rc;
+    const int rb = h->cfg.precision == 64 ? 8 : 4;
+    for (int d = 0; d < 3; ++d) {
+        void* arr[2] = {d < h->cfg.dim ? lam->x[d] : nullptr, lam->v[d]};
+        for (void* a : arr) {
+            if (!a) continue;
+            if (rb == 8) zero_u64(a, lam->nid, s);
+            else zero_i32(static_cast<int32_t*>(a), lam->nid, s);
+        }
+    }
+    zero_u64(lam->lE, 6 * h->L.nnode, s);
+    zero_u64(grads, 2 + (int64_t)h->cfg.n_modes, s);
+    k_loss_seed<<<grid_for(h->L.ncent), 256, 0, s>>>(h->F, f->B, h->L.ncent, lam->lB);
+    return hip_check(h, hipGetLastError(), "adjoint seed launch");
 }
 
 int fs_diagnostics(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out8, double* prof, hipStream_t s) {

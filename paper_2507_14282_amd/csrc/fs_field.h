@@ -874,6 +874,9 @@ __global__ void k_fill_i32(int32_t* p, int32_t v, long n) {
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, long n) {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
 }
+__global__ void k_fill_u8(uint8_t* p, uint8_t v, long n) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
 
 // Live-particle totals after a step: count += injected - removed.
 __global__ void k_count_update(int64_t* c0, int64_t* c1, const unsigned long long* ctr) {
@@ -963,6 +966,49 @@ __device__ __forceinline__ double block_sum(double x, double* sh) {
     double r = sh[0];
     __syncthreads();
     return r;
+}
+
+// Precursor loss of the reverse-mode workload, L = sum over the cell
+// centres with x index i >= nx/2 of B_y^2 + B_z^2.  k_loss_part: workgroup b
+// of a fixed grid sums a fixed strided share of the precursor half-rows into
+// part[b]; k_loss_final adds the partials in a fixed order, so the value
+// does not depend on scheduling.
+constexpr int kLossParts = 1024;   // largest grid of k_loss_part (partials)
+
+__global__ __launch_bounds__(256) void k_loss_part(FieldGeo F, const double* __restrict__ B, long ncent,
+                                                   double* __restrict__ part) {
+    __shared__ double sh[256];
+    const long h0 = F.nx / 2, nh = F.nx - h0;
+    const long total = nh * (ncent / F.nx);
+    double acc = 0.0;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+        const long n = (h0 + t % nh) + (long)F.nx * (t / nh);
+        const double by = B[ncent + n], bz = B[2 * ncent + n];
+        acc += by * by + bz * bz;
+    }
+    const double sum = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = sum;
+}
+
+__global__ __launch_bounds__(256) void k_loss_final(const double* __restrict__ part, int nparts,
+                                                    double* __restrict__ out) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += part[i];
+    const double sum = block_sum(acc, sh);
+    if (threadIdx.x == 0) *out = sum;
+}
+
+// Seed of the reverse sweep: lB = dL/dB of the precursor loss,
+// (0, 2 B_y, 2 B_z) at centres with i >= nx/2 and 0 elsewhere.
+__global__ __launch_bounds__(256) void k_loss_seed(FieldGeo F, const double* __restrict__ B, long ncent,
+                                                   double* __restrict__ lB) {
+    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= ncent) return;
+    const bool pre = (int)(n % F.nx) >= F.nx / 2;
+    lB[n] = 0.0;
+    lB[ncent + n] = pre ? 2.0 * B[ncent + n] : 0.0;
+    lB[2 * ncent + n] = pre ? 2.0 * B[2 * ncent + n] : 0.0;
 }
 
 // Field sums per block: |B|^2, By^2 + Bz^2, loss region, max |div B|.

@@ -144,6 +144,8 @@ def library():
         L.fs_step_record.argtypes = [vp, P, F, i64, R, C.POINTER(FsStats), vp]
         L.fs_adjoint_step.argtypes = [vp, P, F, P, F, R, i64, A, vp, vp]
         L.fs_adjoint_init.argtypes = [vp, P, F, A, vp, vp]
+        L.fs_precursor_loss.argtypes = [vp, F, vp, vp]
+        L.fs_adjoint_seed.argtypes = [vp, F, A, vp, vp]
         _lib = L
     return _lib
 
@@ -154,7 +156,8 @@ def exported_symbols():
             "fs_deposit_moments", "fs_apply_faux_shock", "fs_field_update", "fs_refresh_fields",
             "fs_load_particles", "fs_read_particles", "fs_set_clock", "fs_next_id", "fs_diagnostics",
             "fs_phase_space", "fs_bperp_spectrum", "fs_checkpoint_bytes", "fs_checkpoint", "fs_restore",
-            "fs_timing_enable", "fs_timing_read", "fs_step_record", "fs_adjoint_step", "fs_adjoint_init"]
+            "fs_timing_enable", "fs_timing_read", "fs_step_record", "fs_adjoint_step", "fs_adjoint_init",
+            "fs_precursor_loss", "fs_adjoint_seed"]
 
 
 def make_config(p: dict) -> FsConfig:

@@ -5,7 +5,7 @@ The GPU runs the continuous-deposit step (deposit_mode 1) and its adjoint
 through the C ABI (fs_step_record, fs_adjoint_step, fs_adjoint_init) with
 checkpoints every K steps.  FP64 mode must match the oracle's gradient to
 round-off; FP32 mode (FP32 particles and particle adjoints, FP64 fields)
-to the accuracy an FP32 trajectory allows.
+component by component within 1e-4.
 """
 
 import numpy as np
@@ -56,9 +56,10 @@ def test_fp64_gradient_matches_oracle_adjoint(case):
     # K = 7 splits the run into uneven checkpoint segments
     lg, gg = gpu_grad(p, nsteps, K=7)
     print(f"case {case}: gpu    loss {lg:.12e} grad {gg}", flush=True)
-    assert abs(lg - lo) <= 1e-11 * abs(lo)
+    assert abs(lg - lo) <= 1e-12 * abs(lo)
     scale = np.max(np.abs(go))
-    assert np.max(np.abs(gg - go)) <= 1e-8 * scale, (gg, go)
+    print(f"case {case}: max |grad difference| / max |grad| = {np.max(np.abs(gg - go)) / scale:.2e}", flush=True)
+    assert np.max(np.abs(gg - go)) <= 1e-12 * scale, (gg, go)
 
 
 def test_checkpoint_interval_does_not_change_the_gradient():
@@ -66,18 +67,28 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     p = W.params(**kw)
     _, g1 = gpu_grad(p, nsteps, K=nsteps)
     _, g2 = gpu_grad(p, nsteps, K=5)
-    assert np.max(np.abs(g1 - g2)) <= 1e-10 * np.max(np.abs(g1))
+    assert np.max(np.abs(g1 - g2)) <= 1e-12 * np.max(np.abs(g1))
 
 
-@pytest.mark.parametrize("case", ["cic_cr_inject", "tsc_th_fs"])
-def test_fp32_gradient_near_fp64_oracle(case):
+# Floor of the per-component FP32 bar, relative to the largest component:
+# a component below it is held to FLOOR * max|grad| absolute.
+FP32_FLOOR = 1e-6
+
+
+@pytest.mark.parametrize("case", ["cic_cr_inject", "tsc_th_fs", "2d_oblique"])
+def test_fp32_gradient_per_component(case):
+    # FP32 particle state and particle adjoints, FP64 fields: each component
+    # (u_sh, alpha_cr, every Fourier amplitude) against the FP64 oracle
+    # adjoint within 1e-4 of itself, or of FP32_FLOOR * max|grad| for the
+    # tiny ones
     kw, nsteps = CASES[case]
     p = W.params(**kw)
     _, go = O.adjoint(p, nsteps)
     _, gg = gpu_grad(p, nsteps, K=10, precision=32)
-    print(f"case {case}: fp32 grad {gg}\n oracle {go}", flush=True)
-    # FP32 particle state: the trajectory itself differs at the 1e-6 level
-    assert np.max(np.abs(gg - go)) <= 2e-3 * np.max(np.abs(go)), (gg, go)
+    tol = 1e-4 * np.maximum(np.abs(go), FP32_FLOOR * np.max(np.abs(go)))
+    relc = np.abs(gg - go) / np.maximum(np.abs(go), FP32_FLOOR * np.max(np.abs(go)))
+    print(f"case {case}: fp32 grad {gg}\n oracle {go}\n per-component error {relc}", flush=True)
+    assert np.all(np.abs(gg - go) <= tol), relc
 
 
 def test_autograd_function_matches_direct_backward():
@@ -93,8 +104,8 @@ def test_autograd_function_matches_direct_backward():
     L.backward()
     lo, go = O.adjoint(p, nsteps)
     got = np.concatenate([[u.grad.item(), a.grad.item()], amps.grad.numpy()])
-    assert abs(L.item() - lo) <= 1e-11 * abs(lo)
-    assert np.max(np.abs(got - go)) <= 1e-8 * np.max(np.abs(go))
+    assert abs(L.item() - lo) <= 1e-12 * abs(lo)
+    assert np.max(np.abs(got - go)) <= 1e-12 * np.max(np.abs(go))
 
 
 def test_adjoint_entry_points_reject_fixed_point_mode():
@@ -106,3 +117,65 @@ def test_adjoint_entry_points_reject_fixed_point_mode():
     with pytest.raises(F.FsError) as e:
         sim.step_record(0, rec)
     assert e.value.code == F.FS_EINVAL
+
+
+def test_precursor_loss_and_seed_through_the_c_abi():
+    """fs_precursor_loss against the oracle's loss of the same B (and bit for
+    bit on a second call); fs_adjoint_seed zeroes every adjoint it is given,
+    whatever they held, and sets lB = dL/dB."""
+    import ctypes as C
+    import torch
+    from paper_2507_14282_amd import fshybrid as F
+    p = W.params(dim=2, nx=24, ny=8, dx=0.5, ppc=4, ppc_cr=4, n_cr=0.05, n_modes=3, mode_amp=0.05, theta_deg=30.0,
+                 wall_cr="faux_shock", precision=32, deposit_mode="continuous", seed=5)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    for s in range(3):
+        sim.step(s)
+    B = sim.get_B()
+    o = O.Oracle(p)
+    o.set_B(B)
+    want = o.loss()
+    out = torch.empty(2, dtype=torch.float64, device="cuda:0")
+    for k in range(2):
+        sim._check(sim.lib.fs_precursor_loss(sim.h, C.byref(sim.f), C.c_void_p(out[k:].data_ptr()), sim.stream))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert got[0] == got[1]
+    assert abs(got[0] - want) <= 1e-13 * abs(want), (got[0], want)
+
+    nid = sim.next_id + 8
+    dev = "cuda:0"
+    lam = F.FsAdjoint()
+    keep = []
+    for d in range(3):
+        vv = torch.full((nid,), float("nan"), dtype=torch.float32, device=dev)
+        lam.v[d] = vv.data_ptr()
+        keep.append(vv)
+        if d < 2:
+            xv = torch.full((nid,), float("nan"), dtype=torch.float32, device=dev)
+            lam.x[d] = xv.data_ptr()
+            keep.append(xv)
+        else:
+            lam.x[d] = None
+    lam.nid = nid
+    lB = torch.full((3, int(sim.L.ncent)), float("nan"), dtype=torch.float64, device=dev)
+    lE = torch.full((6, int(sim.L.nnode)), float("nan"), dtype=torch.float64, device=dev)
+    lam.lB, lam.lE = lB.data_ptr(), lE.data_ptr()
+    grads = torch.full((2 + p["n_modes"],), float("nan"), dtype=torch.float64, device=dev)
+    sim._check(sim.lib.fs_adjoint_seed(sim.h, C.byref(sim.f), C.byref(lam), C.c_void_p(grads.data_ptr()),
+                                       sim.stream))
+    torch.cuda.synchronize()
+    for t in keep + [lE, grads]:
+        assert torch.all(t == 0).item()
+    nx = p["nx"]
+    i = np.arange(int(sim.L.ncent)) % nx
+    want_lB = np.zeros((3, int(sim.L.ncent)))
+    want_lB[1:, i >= nx // 2] = 2.0 * B[i >= nx // 2, 1:].T
+    np.testing.assert_array_equal(lB.cpu().numpy(), want_lB)
+    # an adjoint state too small for the ids handed out is refused
+    lam.nid = sim.next_id - 1
+    with pytest.raises(F.FsError) as e:
+        sim._check(sim.lib.fs_adjoint_seed(sim.h, C.byref(sim.f), C.byref(lam), C.c_void_p(grads.data_ptr()),
+                                           sim.stream))
+    assert e.value.code == F.FS_ECAPACITY

@@ -165,6 +165,9 @@ def test_full_size_step_sampled_parity(name, c_light):
             del vq
         del mask
 
+    # --- the deposit node by node in a block of tiles -------------------------
+    block_deposit_matches(sim, p, L, rng)
+
     # --- sampled Ohm's law and div B --------------------------------------------
     nn = int(L.nnode)
     k = np.stack([rng.integers(0, int(L.nxn), 400), rng.integers(0, int(L.nyc), 400),
@@ -180,6 +183,59 @@ def test_full_size_step_sampled_parity(name, c_light):
     d = sim.diagnostics()
     assert d["max_divB"] < 1e-12
     print(f"  sampled Ohm: {len(k)} nodes of {nn}, max |dE| = {np.max(np.abs(Eg - Ee)):.2e}", flush=True)
+
+
+def block_deposit_matches(sim, p, L, rng):
+    """Every live ion of a block of 5 tiles per active axis (3 interior
+    tiles and a ring) is deposited by the oracle in a box of the block's
+    size, the ions translated into it; the GPU's moments must equal the
+    oracle's bit for bit at every node whose stencil cells all lie in the
+    block (2 nodes in from its faces), i.e. the central 3 x 3 x 3 tiles and
+    most of the ring."""
+    dim = int(p["dim"])
+    T = [int(L.tile[d]) for d in range(3)]
+    nt = [int(L.ntile[d]) for d in range(3)]
+    full = [int(p["nx"]), int(p["ny"]) if dim >= 2 else 1, int(p["nz"]) if dim >= 3 else 1]
+    ext = [5 if d < dim else 1 for d in range(3)]
+    c = [int(rng.integers(2, nt[0] - 2)), int(rng.integers(nt[1])) if dim >= 2 else 0,
+         int(rng.integers(nt[2])) if dim >= 3 else 0]
+    org = [(c[d] - 2) * T[d] if d < dim else 0 for d in range(3)]
+    tiles = []
+    for dz in range(ext[2]):
+        for dy in range(ext[1]):
+            for dx in range(ext[0]):
+                tx = c[0] - 2 + dx
+                ty = (c[1] - 2 + dy) % nt[1] if dim >= 2 else 0
+                tz = (c[2] - 2 + dz) % nt[2] if dim >= 3 else 0
+                tiles.append(tx + nt[0] * (ty + nt[1] * tz))
+    size = [ext[d] * T[d] for d in range(3)]
+    ps = dict(p, nx=size[0], ny=size[1] if dim >= 2 else 1, nz=size[2] if dim >= 3 else 1)
+    ndx = int(L.ndx)
+    g = (ndx - int(L.nxn)) // 2
+    compared = 0
+    for sp in range(2 if sim.has_cr else 1):
+        sec = sim.sections(sp)
+        c3, off, v, ids = read_ions(sim, sec, live_slots(sec, tiles))
+        cs = c3.copy()
+        for d in range(dim):
+            cs[:, d] = (c3[:, d] - org[d]) % full[d] if d > 0 else c3[:, d] - org[d]
+            assert np.all((cs[:, d] >= 0) & (cs[:, d] < size[d])), d
+        o = O.Oracle(ps)
+        o.set_particles(sp, cs, off, v, ids.astype(np.uint64))
+        o.step(O.DEPOSIT)
+        Mo = o.moments(sp)
+        gs = (o.ndx - (size[0] + 1)) // 2
+        rngs = [np.arange(2, size[d] - 1) if d < dim else np.zeros(1, dtype=np.int64) for d in range(3)]
+        K, J, I = np.meshgrid(rngs[2], rngs[1], rngs[0], indexing="ij")
+        I, J, K = I.ravel(), J.ravel(), K.ravel()
+        loc = (I + gs) + o.ndx * (J + o.nyc * K)
+        gi = (I + org[0] + g) + ndx * (((J + org[1]) % full[1]) + full[1] * ((K + org[2]) % full[2]))
+        Mg = sim.mom[sp][torch.as_tensor(gi, device=sim.device)].cpu().numpy()
+        np.testing.assert_array_equal(Mg, Mo[loc])
+        if sp == 0:   # the thermal ions fill the block; CRs may not reach it
+            assert np.count_nonzero(Mo[loc][:, 0]) > 0.9 * len(loc)
+        compared += len(loc)
+    print(f"  block deposit: {compared} nodes bit-exact in a block of {len(tiles)} tiles", flush=True)
 
 
 def wall_threshold2(p, step, pid):
