@@ -317,6 +317,21 @@ int fs_phase_space(fs_handle* h, const fs_particles* sp, int32_t species, int32_
  * the first call.  FS_EINVAL: NULL pointer; FS_EDEVICE: scratch allocation. */
 int fs_bperp_spectrum(fs_handle* h, const fs_fields* f, double* out, hipStream_t s);
 
+/* The same spectrum for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * same arguments and result as fs_bperp_spectrum, bit for bit, but the call
+ * allocates nothing.  Its 2 nx + min(lines, 256) (nx/2 + 1) doubles of
+ * scratch live in a static device array of the library, 2^21 doubles
+ * (16 MiB), one per GPU for the life of the process; its address on the
+ * handle's device is resolved by fs_create.  Every partial is written before
+ * it is read, so nothing carries over from the previous call.  All calls on
+ * one GPU share that array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and give undefined results.
+ * FS_EINVAL: NULL pointer, a box whose scratch exceeds 2^21 doubles (e.g.
+ * nx = 16384 with 256 or more (y, z) lines), or a current device other than
+ * the handle's. */
+int fs_bperp_spectrum_noalloc(fs_handle* h, const fs_fields* f, double* out, hipStream_t s);
+
 /* ---------------------------------------------------------------------
  * Reverse mode.  The derivative is that of the continuous-deposit step
  * (deposit_mode 1) with every discrete decision of the forward run held

@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -38,6 +39,8 @@ struct fs_handle {
     int64_t npart = 0;
     double* spec = nullptr;   // B_perp spectrum: twiddles + partial sums (first use)
     int64_t nspec = 0;
+    int device = -1;                  // device current at fs_create
+    double* static_scratch = nullptr; // device address of `scratch` on that device
     // reverse-mode scratch (deposit_mode 1 only)
     double* amom[2] = {nullptr, nullptr};   // moments recomputed for the reverse step
     double* alM[2] = {nullptr, nullptr};    // their adjoints
@@ -70,6 +73,44 @@ int hip_check(fs_handle* h, hipError_t e, const char* what) {
 }
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+}  // namespace
+
+// Scratch of the allocation-free B_perp spectrum (fs_bperp_spectrum_noalloc):
+// its twiddles and per-group partial sums live in this file-scope device
+// array, one copy per GPU for the life of the process.  Host code never
+// uses the name itself (on the host it is only a stand-in for the symbol):
+// fs_create resolves the device address once per device and the kernels
+// receive that address.
+constexpr int64_t kStaticScratchDoubles = int64_t(1) << 21;   // 16 MiB
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+namespace {
+
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+double* g_scratch_dev[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Records the current device in the handle and the address of `scratch` on
+// it, resolving that address with hipGetSymbolAddress on the device's first
+// handle.
+int resolve_static_scratch(fs_handle* h) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(h, e, "current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(h, FS_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_check(h, e, "address of the static scratch");
+        if (!p) return fail(h, FS_EDEVICE, "address of the static scratch is NULL");
+        g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    h->device = dev;
+    h->static_scratch = g_scratch_dev[dev];
+    return FS_OK;
+}
 
 // Workgroups per tile for the per-particle passes that may split a bin: about
 // 2048 slots each, at most 16.
@@ -826,6 +867,11 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
         fs_destroy(h);
         return fail(nullptr, FS_EDEVICE, "device allocation of library scratch failed");
     }
+    if (int rc = resolve_static_scratch(h)) {
+        const std::string msg = h->err;
+        fs_destroy(h);
+        return fail(nullptr, rc, msg);
+    }
     *out = h;
     return FS_OK;
 }
@@ -1339,6 +1385,30 @@ int restore_impl(fs_handle* h, fs_particles* sp, fs_fields* f, const void* src, 
     return FS_OK;
 }
 
+// Scratch of the B_perp spectrum: 2 nx twiddles, then one partial sum per
+// (line group, wavenumber) with up to 256 groups of (y, z) lines.
+int spectrum_groups(const fs_handle* h) { return (int)std::min<int64_t>(h->L.nyc * h->L.nzc, 256); }
+int64_t spectrum_scratch_doubles(const fs_handle* h) {
+    const int nx = h->cfg.nx, nk = nx / 2 + 1;
+    return 2 * (int64_t)nx + (int64_t)spectrum_groups(h) * nk;
+}
+
+// The spectrum's three kernels with their scratch at `scr`: every partial
+// is written before it is read, so the scratch needs no clearing.
+int spectrum_launch(fs_handle* h, const fs_fields* f, double* out, double* scr, hipStream_t s) {
+    const int nx = h->cfg.nx, nk = nx / 2 + 1;
+    const int64_t nlines = h->L.nyc * h->L.nzc;
+    const int ngroups = spectrum_groups(h);
+    double* tw = scr;
+    double* part = scr + 2 * (int64_t)nx;
+    k_twiddles<<<grid_for(nx), 256, 0, s>>>(nx, tw);
+    k_bperp_dft<<<dim3((unsigned)((nk + 255) / 256), (unsigned)ngroups), 256, 0, s>>>(h->F, f->B, h->L.ncent, tw, nk,
+                                                                                      ngroups, part);
+    k_bperp_reduce<<<grid_for(nk), 256, 0, s>>>(nk, ngroups, 1.0 / ((double)nlines * (double)nx * (double)nx), part,
+                                                out);
+    return hip_check(h, hipGetLastError(), "spectrum launch");
+}
+
 template <typename R> int diag_impl(fs_handle* h, const fs_particles* sp, const fs_fields* f, double* out, double* prof,
                                     hipStream_t s) {
     const long nc = h->L.ncent;
@@ -1462,10 +1532,7 @@ int fs_phase_space(fs_handle* h, const fs_particles* sp, int32_t species, int32_
 
 int fs_bperp_spectrum(fs_handle* h, const fs_fields* f, double* out, hipStream_t s) {
     if (!h || !f || !f->B || !out) return fail(h, FS_EINVAL, "NULL argument");
-    const int nx = h->cfg.nx, nk = nx / 2 + 1;
-    const int64_t nlines = h->L.nyc * h->L.nzc;
-    const int ngroups = (int)std::min<int64_t>(nlines, 256);
-    const int64_t need = 2 * (int64_t)nx + (int64_t)ngroups * nk;
+    const int64_t need = spectrum_scratch_doubles(h);
     if (h->nspec < need) {
         hipFree(h->spec);
         h->spec = nullptr;
@@ -1473,14 +1540,23 @@ int fs_bperp_spectrum(fs_handle* h, const fs_fields* f, double* out, hipStream_t
         if (hipMalloc((void**)&h->spec, need * sizeof(double)) != hipSuccess) return fail(h, FS_EDEVICE, "spectrum scratch");
         h->nspec = need;
     }
-    double* tw = h->spec;
-    double* part = h->spec + 2 * (int64_t)nx;
-    k_twiddles<<<grid_for(nx), 256, 0, s>>>(nx, tw);
-    k_bperp_dft<<<dim3((unsigned)((nk + 255) / 256), (unsigned)ngroups), 256, 0, s>>>(h->F, f->B, h->L.ncent, tw, nk,
-                                                                                      ngroups, part);
-    k_bperp_reduce<<<grid_for(nk), 256, 0, s>>>(nk, ngroups, 1.0 / ((double)nlines * (double)nx * (double)nx), part,
-                                                out);
-    return hip_check(h, hipGetLastError(), "spectrum launch");
+    return spectrum_launch(h, f, out, h->spec, s);
+}
+
+int fs_bperp_spectrum_noalloc(fs_handle* h, const fs_fields* f, double* out, hipStream_t s) {
+    if (!h || !f || !f->B || !out) return fail(h, FS_EINVAL, "NULL argument");
+    const int64_t need = spectrum_scratch_doubles(h);
+    if (need > kStaticScratchDoubles)
+        return fail(h, FS_EINVAL, "box too large for the allocation-free spectrum: it needs " + std::to_string(need) +
+                                      " doubles of scratch, the static array holds " +
+                                      std::to_string(kStaticScratchDoubles));
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(h, e, "current device");
+    if (dev != h->device || !h->static_scratch)
+        return fail(h, FS_EINVAL, "the handle was created on device " + std::to_string(h->device) +
+                                      ", the current device is " + std::to_string(dev));
+    return spectrum_launch(h, f, out, h->static_scratch, s);
 }
 
 int fs_precursor_loss(fs_handle* h, const fs_fields* f, double* loss, hipStream_t s) {

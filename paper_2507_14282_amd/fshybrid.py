@@ -135,6 +135,7 @@ def library():
         L.fs_diagnostics.argtypes = [vp, P, F, vp, vp, vp]
         L.fs_phase_space.argtypes = [vp, P, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp, vp, vp]
         L.fs_bperp_spectrum.argtypes = [vp, F, vp, vp]
+        L.fs_bperp_spectrum_noalloc.argtypes = [vp, F, vp, vp]
         L.fs_checkpoint_bytes.argtypes = [vp, P, vp, vp]
         L.fs_checkpoint.argtypes = [vp, P, F, vp, i64, vp]
         L.fs_restore.argtypes = [vp, P, F, vp, i64, vp]
@@ -157,7 +158,7 @@ def exported_symbols():
             "fs_load_particles", "fs_read_particles", "fs_set_clock", "fs_next_id", "fs_diagnostics",
             "fs_phase_space", "fs_bperp_spectrum", "fs_checkpoint_bytes", "fs_checkpoint", "fs_restore",
             "fs_timing_enable", "fs_timing_read", "fs_step_record", "fs_adjoint_step", "fs_adjoint_init",
-            "fs_precursor_loss", "fs_adjoint_seed"]
+            "fs_precursor_loss", "fs_adjoint_seed", "fs_bperp_spectrum_noalloc"]
 
 
 def make_config(p: dict) -> FsConfig:
