@@ -77,7 +77,8 @@ def workload_throughput(name, steps, warmup, **overrides):
                     + (", reflecting wall" + (" (conducting)" if p.get("wall_field", 0) else "")
                        if p["wall_th"] == "specular" else "")
                     + (f", prescribed wall (f0={p['ret_f0']:g}, gain={p['gain']:g}, kappa={p['kappa']:g}, "
-                       f"r_dot={p['r_dot']:g})" if p.get("wall_model", 0) else ""),
+                       f"r_dot={p['r_dot']:g}, loss-cone depletion={p.get('lc_depletion', 0.0):g})"
+                       if p.get("wall_model", 0) else ""),
         "ions": int(nav), "steps": steps, "warmup": warmup,
         "ms_per_step": (t1 - t0) / steps * 1e3,
         "pu_per_s": nav * steps / (t1 - t0),
@@ -489,8 +490,9 @@ def main():
             # (t = 10) so that the reflected beams and the shock are in it
             "2D rw2 reflecting wall": workload_throughput("rw2", 50, 2000),
             # the prescribed faux shock on the 3D box
+            # with the loss cone of the oblique (45 deg) shock depleted
             "3D cfg4 prescribed wall": workload_throughput("cfg4", 30, 10, wall_model=1, ret_f0=0.8, ret_alpha=0.0,
-                                                            gain=1.2, kappa=1.5, r_dot=0.1),
+                                                            gain=1.2, kappa=1.5, r_dot=0.1, lc_depletion=0.5),
         }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()

@@ -139,6 +139,21 @@ typedef struct fs_config {
                                plasma of the faux-shock runs).  1: a conducting
                                wall at rest, E_y = E_z = 0 at the wall node (the
                                reflecting-wall runs, whose plasma piles up there). */
+    double lc_depletion;    /* prescribed wall only (wall_model 1), in [0, 1]:
+                               the loss cone of an oblique shock, which the paper
+                               expects the downstream CRs not to fill
+                               isotropically (Sec. 3.2).  Downstream CRs gyrate
+                               about b2 ~ (cos th_Bn, r(t) sin th_Bn, 0) (normal
+                               B continuous, tangential B compressed by the
+                               wall's ratio); a return direction n whose motion
+                               along b2 alone outruns the receding shock,
+                               (n . s) |b2_x| > u2 / (return speed) with s the
+                               field direction pointing upstream, is in the loss
+                               cone and returns as above; any other return is
+                               turned into a transmission with probability
+                               lc_depletion.  0 (the default) leaves the wall
+                               as above, bit for bit; a parallel shock's cone
+                               holds every return direction. */
 } fs_config;
 
 /* Sizes the caller must allocate, reported by fs_layout(). */

@@ -86,6 +86,20 @@
  *     and flux Gamma (without J_ext) at the nodes, before Ohm's law.  In the
  *     box the end nodes x = 0 and x = L keep their values; y, z (and x when
  *     periodic) wrap.  The boundary fill and the floor then apply again.
+ *  R15 loss cone of the prescribed wall (lc_depletion > 0): the paper
+ *     expects highly oblique shocks not to fill the CR loss cone isotropically,
+ *     which changes the return probability and the energy gain (Sec. 3.2),
+ *     and leaves the anisotropy to calibration (Sec. 1).  Read as: downstream
+ *     CRs gyrate about the downstream field b2, whose normal component is
+ *     B0's and whose tangential one is compressed by the wall's ratio r(t),
+ *     b2 ~ (cos th_Bn, r sin th_Bn, 0).  A return direction n (drawn as in
+ *     R12) lies in the loss cone when its motion along b2 alone outruns the
+ *     receding shock, (n . s) |b2_x| > a = u2 / (return speed), s the field
+ *     direction pointing upstream; such returns keep R12's weight, the rest
+ *     (which reach the shock only through their gyration) are removed with
+ *     probability lc_depletion, decided by U[1].  A parallel shock's cone
+ *     holds every return direction, so the knob acts only at oblique ones;
+ *     lc_depletion = 0 is R12 itself.
  *  R14 conducting wall (wall_field = 1): the paper does not give the field
  *     boundary of its reflecting wall.  Read as a perfect conductor at rest
  *     in the simulation frame: the tangential E vanishes at the wall node
@@ -500,6 +514,19 @@ static double wall_u2(const ora_cfg* c, int64_t step)
     return c->u_sh / (r > 1.0 ? r : 1.0);
 }
 
+/* Reading R15: the downstream field direction at a step (normal component
+ * continuous, tangential one compressed by r(t)), as its x and y parts. */
+static void downstream_b(const ora_cfg* c, int64_t step, double* bx, double* by)
+{
+    double r = c->r + c->r_dot * ((double)step * c->dt);
+    if (r < 1.0) r = 1.0;
+    double th = c->theta_deg * (ORA_TWO_PI / 360.0);
+    double bn = cos(th), bt = r * sin(th);
+    double nb = sqrt(bn * bn + bt * bt);
+    *bx = bn / nb;
+    *by = bt / nb;
+}
+
 /* Reading R12's event, in both modes.  W is the crosser's velocity in the
  * downstream frame (its four-velocity there in the relativistic mode, with
  * Lorentz factor Gam), |w| = |W| / Gam its speed.  Uniform U[0] decides;
@@ -539,6 +566,14 @@ static int wall_event_prescribed(const ora_cfg* c, int64_t step, uint64_t id, do
     double mu = a + (1.0 - a) * q;
     double st = sqrt(fmax(0.0, 1.0 - mu * mu));
     double phi = ORA_TWO_PI * U[3];
+    if (c->lc_depletion > 0.0) {
+        /* reading R15: n = (-mu, st cos phi, st sin phi), s = (-cx, -sy, 0) */
+        double bx, by;
+        downstream_b(c, step, &bx, &by);
+        double cx = fabs(bx), sy = bx < 0.0 ? -by : by;
+        double ns = mu * cx - (st * cos(phi)) * sy;
+        if (!(ns * cx > a) && U[1] < c->lc_depletion) return 0;
+    }
     double Wxn = -Wn * mu;
     vout[1] = Wn * st * cos(phi);
     vout[2] = Wn * st * sin(phi);

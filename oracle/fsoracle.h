@@ -43,6 +43,7 @@ typedef struct ora_cfg {
     double ret_f0, ret_alpha, gain, kappa, r_dot;
     int32_t smooth;         /* binomial passes on the fluid moments (reading R13) */
     int32_t wall_field;     /* 1: conducting wall at x = L (reading R14) */
+    double lc_depletion;    /* prescribed wall: depletion of the return flux outside the loss cone (reading R15) */
 } ora_cfg;
 
 typedef struct ora_stats {

@@ -61,6 +61,7 @@ class OraCfg(C.Structure):
         ("wall_model", C.c_int32),
         ("ret_f0", C.c_double), ("ret_alpha", C.c_double), ("gain", C.c_double),
         ("kappa", C.c_double), ("r_dot", C.c_double), ("smooth", C.c_int32), ("wall_field", C.c_int32),
+        ("lc_depletion", C.c_double),
     ]
 
 
@@ -93,6 +94,7 @@ def make_cfg(p: dict, deposit_mode: str = "fixed") -> OraCfg:
         setattr(c, k, float(p.get(k, d)))
     c.smooth = int(p.get("smooth", 0))
     c.wall_field = int(p.get("wall_field", 0))
+    c.lc_depletion = float(p.get("lc_depletion", 0.0))
     return c
 
 

@@ -184,6 +184,8 @@ int compute_layout(const fs_config* c, fs_layout_info* L, std::string& err) {
         }
         if (c->ret_alpha != 0.0 && !(c->cr_w > 0.0)) { err = "ret_alpha != 0 needs cr_w > 0"; return FS_EINVAL; }
     }
+    if (!(c->lc_depletion >= 0.0 && c->lc_depletion <= 1.0)) { err = "lc_depletion must be in [0, 1]"; return FS_EINVAL; }
+    if (c->lc_depletion > 0.0 && c->wall_model != 1) { err = "lc_depletion needs the prescribed wall"; return FS_EINVAL; }
     if (c->smooth < 0 || c->smooth > 64) { err = "smooth must be in [0, 64]"; return FS_EINVAL; }
     if (c->wall_field != 0 && c->wall_field != 1) { err = "wall_field must be 0 or 1"; return FS_EINVAL; }
     int t[3];
@@ -299,6 +301,15 @@ WallModel wall_model_at(const fs_handle* h, int64_t step) {
     const double r = c.r + c.r_dot * ((double)step * c.dt);
     m.u2 = m.on ? c.u_sh / (r > 1.0 ? r : 1.0) : h->G.u2;
     m.f0 = c.ret_f0; m.alpha = c.ret_alpha; m.wref = c.cr_w; m.gain = c.gain; m.kappa = c.kappa;
+    // loss cone: downstream field b2 ~ (cos th, r sin th, 0) at this step's r,
+    // its upstream-pointing direction (-lc_cx, -lc_sy, 0)
+    m.lc_dep = c.lc_depletion;
+    const double th = c.theta_deg * (kTwoPi / 360.0);
+    const double bn = std::cos(th), bt = (r > 1.0 ? r : 1.0) * std::sin(th);
+    const double nb = std::sqrt(bn * bn + bt * bt);
+    const double bx = bn / nb, by = bt / nb;
+    m.lc_cx = std::fabs(bx);
+    m.lc_sy = bx < 0.0 ? -by : by;
     return m;
 }
 

@@ -298,9 +298,17 @@ __device__ __noinline__ int faux_shock_event(uint64_t seed, uint64_t step, uint3
 // root, so a return the eq. (1) event also makes gets its kick bit for bit
 // (non-relativistic mode).  pow() may differ from another implementation's
 // in the last bit: a decision within one ulp of f rho^2 could then differ.
+// Loss cone (lc_dep > 0): downstream CRs gyrate about the compressed field
+// b2; a return direction whose motion along b2 alone outruns the receding
+// shock is in the loss cone and returns as above, any other return becomes
+// a transmission with probability lc_dep (uniform U2), which the paper
+// expects at oblique shocks (Sec. 3.2).  cos(phi) of another libm may differ
+// in the last bit: a direction within one ulp of the cone's edge could then
+// be placed differently.
 struct WallModel {
     int on;
     double u2, f0, alpha, wref, gain, kappa;
+    double lc_dep, lc_cx, lc_sy;   // loss-cone depletion, |b2_x| and the y part of the upstream field direction
 };
 
 __device__ __noinline__ int faux_shock_event_prescribed(const WallModel& M, uint64_t seed, uint64_t step, uint32_t id,
@@ -339,6 +347,13 @@ __device__ __noinline__ int faux_shock_event_prescribed(const WallModel& M, uint
     const double mu = a + (1.0 - a) * q;
     const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
     const double phi = kTwoPi * U[3];
+    if (M.lc_dep > 0.0) {
+        // loss cone: the direction n = (-mu, st cos phi, st sin phi) against
+        // the upstream field direction s = (-lc_cx, -lc_sy, 0); outside the
+        // cone a return is removed with probability lc_dep, decided by U2
+        const double ns = mu * M.lc_cx - (st * cos(phi)) * M.lc_sy;
+        if (!(ns * M.lc_cx > a) && U[1] < M.lc_dep) return 0;
+    }
     const double Wxn = -Wn * mu;
     vout[1] = Wn * st * cos(phi);
     vout[2] = Wn * st * sin(phi);

@@ -50,6 +50,7 @@ class FsConfig(C.Structure):
         ("n_modes", C.c_int32), ("inject", C.c_int32), ("deposit_mode", C.c_int32), ("wall_model", C.c_int32),
         ("ret_f0", C.c_double), ("ret_alpha", C.c_double), ("gain", C.c_double), ("kappa", C.c_double),
         ("r_dot", C.c_double), ("smooth", C.c_int32), ("wall_field", C.c_int32),
+        ("lc_depletion", C.c_double),
     ]
 
 
@@ -184,6 +185,7 @@ def make_config(p: dict) -> FsConfig:
         setattr(c, k, float(p.get(k, d)))
     c.smooth = int(p.get("smooth", 0))
     c.wall_field = int(p.get("wall_field", 0))
+    c.lc_depletion = float(p.get("lc_depletion", 0.0))
     return c
 
 

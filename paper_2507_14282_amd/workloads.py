@@ -30,6 +30,9 @@ DEFAULTS = dict(
     # wall_model 1 is the prescribed faux shock (return factor and its power
     # of |w| / cr_w, speed gain, direction anisotropy, d r / d t); 0 is eq. (1)
     wall_model=0, ret_f0=1.0, ret_alpha=0.0, gain=1.0, kappa=0.0, r_dot=0.0,
+    # prescribed wall: share of the return flux outside the field-aligned loss
+    # cone that is removed (0: the isotropic downstream population)
+    lc_depletion=0.0,
     smooth=0,      # passes of the 1-2-1 filter on the fluid moments (0: none)
     wall_field=0,  # 1: conducting wall at x = L (E_y = E_z = 0 there)
     precision=32, steps=10,

@@ -13,6 +13,8 @@ At these sizes the oracle cannot run the whole box, so the checks are
     with 2^sw the fixed-point weight of one ion) and div B at round-off.
 """
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -265,14 +267,34 @@ def wall_margin(p, step, pid, v):
         return abs(w / u2 - 1.0)
     rho = (w - u2) / (w + u2)
     P = min(1.0, float(p["ret_f0"]) * (w / float(p["cr_w"])) ** float(p["ret_alpha"]) * rho * rho)
-    return min(abs(U0 / P - 1.0), abs(w / u2 - 1.0), abs(float(p["gain"]) * w / u2 - 1.0))
+    m = min(abs(U0 / P - 1.0), abs(w / u2 - 1.0), abs(float(p["gain"]) * w / u2 - 1.0))
+    dep = float(p.get("lc_depletion", 0.0))
+    if dep > 0.0:
+        # loss cone: the return direction against the cone's edge, U1 against
+        # the depletion
+        U1 = ((int(r[1]) >> 11) + 0.5) * 2.0**-53
+        U2d = ((int(r[2]) >> 11) + 0.5) * 2.0**-53
+        U3 = ((int(r[3]) >> 11) + 0.5) * 2.0**-53
+        a = u2 / (float(p["gain"]) * w)
+        kap = float(p["kappa"])
+        q = math.sqrt(U2d) if kap == 0.0 else U2d ** (1.0 / (2.0 + kap))
+        mu = a + (1.0 - a) * q
+        st = math.sqrt(max(0.0, 1.0 - mu * mu))
+        th = math.radians(float(p["theta_deg"]))
+        rr = max(1.0, float(p["r"]) + float(p["r_dot"]) * (step * float(p["dt"])))
+        bn, bt = math.cos(th), rr * math.sin(th)
+        cx, sy = bn / math.hypot(bn, bt), bt / math.hypot(bn, bt)
+        ns = mu * cx - st * math.cos(2 * math.pi * U3) * sy
+        m = min(m, abs(ns * cx / a - 1.0), abs(U1 / dep - 1.0))
+    return m
 
 
 PRESCRIBED = dict(wall_model=1, ret_f0=0.8, ret_alpha=0.5, gain=1.2, kappa=1.5, r_dot=0.4)
+LOSS_CONE = dict(PRESCRIBED, lc_depletion=0.6)
 
 
-@pytest.mark.parametrize("name,model", [("cfg4", {}), ("cfg2", {}), ("cfg4", PRESCRIBED)],
-                         ids=["cfg4", "cfg2", "cfg4-prescribed"])
+@pytest.mark.parametrize("name,model", [("cfg4", {}), ("cfg2", {}), ("cfg4", PRESCRIBED), ("cfg4", LOSS_CONE)],
+                         ids=["cfg4", "cfg2", "cfg4-prescribed", "cfg4-loss-cone"])
 def test_full_size_wall_events(name, model):
     """Every ion of the tile column at the wall, pushed by the oracle in the
     GPU's own gather grid; the crossers go through the oracle's wall.  After
