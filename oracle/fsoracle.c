@@ -100,6 +100,18 @@
  *     probability lc_depletion, decided by U[1].  A parallel shock's cone
  *     holds every return direction, so the knob acts only at oblique ones;
  *     lc_depletion = 0 is R12 itself.
+ *  R16 time-centred ion-field coupling (coupling = 2): the paper's 2D runs
+ *     use dHybridR (Sec. 2), whose coupling is second order in time; the
+ *     paper gives no scheme.  Read as: the push as in R4; the density is
+ *     deposited at x^{n+1} and the flux at the midpoint of the move,
+ *     x^{n+1/2} = x^n + v^{n+1/2} dt / 2, with v^{n+1/2} (ions reflected or
+ *     injected during the step deposit both at their new position); the
+ *     Faraday update from B^n to B^{n+1} holds the moments frozen at
+ *     t_{n+1/2}: n^{n+1/2} = (n^n + n^{n+1}) / 2 and the midpoint flux; E^{n+1}
+ *     takes n^{n+1} and the flux extrapolated to t_{n+1},
+ *     (3 Gamma^{n+1/2} - Gamma^{n-1/2}) / 2.  The initial load's flux stands in
+ *     for Gamma^{-1/2} and its density for n^0.  Smoothing is not combined
+ *     with it.
  *  R14 conducting wall (wall_field = 1): the paper does not give the field
  *     boundary of its reflecting wall.  Read as a perfect conductor at rest
  *     in the simulation frame: the tangential E vanishes at the wall node
@@ -121,6 +133,8 @@ typedef struct ora_sp {
     double  *o;    /* 3 per particle: offset in [0,1) per dimension */
     double  *v;    /* 3 per particle */
     uint64_t *id;
+    int64_t *ch;   /* R16: cell and offset of the midpoint of the last move */
+    double  *oh;
 } ora_sp;
 
 typedef struct ora_event { int64_t step; uint64_t id; int32_t kind; } ora_event;
@@ -136,6 +150,7 @@ struct ora_sim {
     int64_t *M[2];             /* fixed-point moments per species: R, Gx, Gy, Gz */
     double *Mc[2];             /* continuous moments */
     double *fn, *fg;           /* fluid density and ion flux at nodes */
+    double *fn_prev, *fg_prev; /* R16: density n^n and flux Gamma^{n-1/2} of the previous step */
     ora_sp sp[2];
     int64_t step, next_id;
     int32_t recording;
@@ -237,6 +252,8 @@ ora_sim* ora_new(const ora_cfg* cfg)
 {
     if (cfg->dim < 1 || cfg->dim > 3 || cfg->nx < 4 || cfg->shape < 1 || cfg->shape > 2) return NULL;
     if (!(cfg->v_max > 0.0)) return NULL;
+    if (cfg->coupling != 1 && cfg->coupling != 2) return NULL;
+    if (cfg->coupling == 2 && cfg->smooth > 0) return NULL;
     if (cfg->c_light < 0.0 || cfg->c_light != cfg->c_light) return NULL;
     if (relativistic(cfg)) {
         /* every sampled velocity below c: a Box-Muller normal is at most
@@ -268,6 +285,8 @@ ora_sim* ora_new(const ora_cfg* cfg)
     s->Bb = (double*)calloc((size_t)(3 * s->nnode), sizeof(double));
     s->fn = (double*)calloc((size_t)s->nnode, sizeof(double));
     s->fg = (double*)calloc((size_t)(3 * s->nnode), sizeof(double));
+    s->fn_prev = (double*)calloc((size_t)s->nnode, sizeof(double));
+    s->fg_prev = (double*)calloc((size_t)(3 * s->nnode), sizeof(double));
     for (int k = 0; k < 2; ++k) {
         s->M[k] = (int64_t*)calloc((size_t)(4 * s->ndep), sizeof(int64_t));
         s->Mc[k] = (double*)calloc((size_t)(4 * s->ndep), sizeof(double));
@@ -280,10 +299,11 @@ ora_sim* ora_new(const ora_cfg* cfg)
 void ora_free(ora_sim* s)
 {
     if (!s) return;
-    free(s->B); free(s->E); free(s->Bb); free(s->fn); free(s->fg);
+    free(s->B); free(s->E); free(s->Bb); free(s->fn); free(s->fg); free(s->fn_prev); free(s->fg_prev);
     for (int k = 0; k < 2; ++k) {
         free(s->M[k]); free(s->Mc[k]);
         free(s->sp[k].c); free(s->sp[k].o); free(s->sp[k].v); free(s->sp[k].id);
+        free(s->sp[k].ch); free(s->sp[k].oh);
     }
     free(s->ev);
     free(s);
@@ -298,6 +318,8 @@ static void sp_reserve(ora_sp* p, int64_t n)
     p->o = (double*)realloc(p->o, (size_t)(3 * cap) * sizeof(double));
     p->v = (double*)realloc(p->v, (size_t)(3 * cap) * sizeof(double));
     p->id = (uint64_t*)realloc(p->id, (size_t)cap * sizeof(uint64_t));
+    p->ch = (int64_t*)realloc(p->ch, (size_t)(3 * cap) * sizeof(int64_t));
+    p->oh = (double*)realloc(p->oh, (size_t)(3 * cap) * sizeof(double));
     p->cap = cap;
 }
 
@@ -305,7 +327,10 @@ static void sp_append(ora_sp* p, const int64_t c[3], const double o[3], const do
 {
     sp_reserve(p, p->n + 1);
     int64_t k = p->n++;
-    for (int d = 0; d < 3; ++d) { p->c[3 * k + d] = c[d]; p->o[3 * k + d] = o[d]; p->v[3 * k + d] = v[d]; }
+    for (int d = 0; d < 3; ++d) {
+        p->c[3 * k + d] = c[d]; p->o[3 * k + d] = o[d]; p->v[3 * k + d] = v[d];
+        p->ch[3 * k + d] = c[d]; p->oh[3 * k + d] = o[d];   /* born here: no move this step */
+    }
     p->id[k] = id;
 }
 
@@ -457,6 +482,18 @@ static void push_species(ora_sim* s, int k)
         boris(&s->c, v, E, B, s->c.dt);
         double vel[3];
         velocity_of(&s->c, v, vel);
+        if (s->c.coupling == 2) {
+            /* reading R16: midpoint of the move, where the flux is deposited */
+            double hdtdx = 0.5 * dtdx;
+            for (int d = 0; d < 3; ++d) { p->ch[3 * i + d] = c[d]; p->oh[3 * i + d] = o[d]; }
+            for (int d = 0; d < s->c.dim; ++d) {
+                double xh = o[d] + vel[d] * hdtdx;
+                double fh = floor(xh);
+                p->ch[3 * i + d] = c[d] + (int64_t)fh;
+                p->oh[3 * i + d] = xh - fh;
+                if (p->oh[3 * i + d] >= 1.0) { p->oh[3 * i + d] = 0.0; p->ch[3 * i + d] += 1; }
+            }
+        }
         for (int d = 0; d < s->c.dim; ++d) {
             double xi = o[d] + vel[d] * dtdx;
             double fl = floor(xi);
@@ -686,6 +723,8 @@ static void boundaries(ora_sim* s, int k, ora_stats* st)
                     c[0] = (int64_t)fl; o[0] = xi - fl;
                     if (c[0] >= nx) { c[0] = nx - 1; o[0] = nextafter(1.0, 0.0); }
                     if (c[0] < 0) { keep = 0; st->escaped++; }
+                    /* reading R16: a reflected ion deposits its flux where it ends */
+                    for (int d = 0; d < 3; ++d) { p->ch[3 * i + d] = c[d]; p->oh[3 * i + d] = o[d]; }
                 } else { keep = 0; st->transmitted++; }
             }
         } else if (c[0] < 0) { keep = 0; st->escaped++; record(s, p->id[i], 3); }
@@ -693,6 +732,7 @@ static void boundaries(ora_sim* s, int k, ora_stats* st)
             if (out != i) {
                 for (int d = 0; d < 3; ++d) {
                     p->c[3 * out + d] = c[d]; p->o[3 * out + d] = o[d]; p->v[3 * out + d] = v[d];
+                    p->ch[3 * out + d] = p->ch[3 * i + d]; p->oh[3 * out + d] = p->oh[3 * i + d];
                 }
                 p->id[out] = p->id[i];
             }
@@ -809,44 +849,57 @@ static int64_t dep_index(const ora_sim* s, int64_t i, int64_t j, int64_t k)
     return i + s->ndx * (j + s->nyc * k);
 }
 
+/* One particle's moments at (c, o): the density when which & 1, the flux
+ * when which & 2. */
+static void deposit_at(ora_sim* s, int k, const int64_t c[3], const double o[3], const double v[3],
+                       const int64_t vq[3], int which, ora_stats* st)
+{
+    int64_t* M = s->M[k];
+    double* Mc = s->Mc[k];
+    int64_t first[3] = {0, 0, 0}, wi[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
+    double wr[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
+    int np[3] = {1, 1, 1};
+    for (int d = 0; d < s->c.dim; ++d) {
+        if (s->c.deposit_mode == 0) np[d] = shape_int(s->c.shape, s->b, c[d], o[d], &first[d], wi[d]);
+        else np[d] = shape_real(s->c.shape, c[d], o[d], &first[d], wr[d]);
+    }
+    for (int a = 0; a < np[0]; ++a)
+        for (int bb = 0; bb < np[1]; ++bb)
+            for (int cc = 0; cc < np[2]; ++cc) {
+                int64_t n = dep_index(s, first[0] + a, first[1] + bb, first[2] + cc);
+                if (n < 0) { st->out_of_range++; continue; }
+                if (s->c.deposit_mode == 0) {
+                    int64_t W = wi[0][a] * wi[1][bb] * wi[2][cc];
+                    if (which & 1) M[4 * n + 0] += W;
+                    if (which & 2)
+                        for (int d = 0; d < 3; ++d) M[4 * n + 1 + d] += W * vq[d];
+                } else {
+                    double W = wr[0][a] * wr[1][bb] * wr[2][cc];
+                    if (which & 1) Mc[4 * n + 0] += W;
+                    if (which & 2)
+                        for (int d = 0; d < 3; ++d) Mc[4 * n + 1 + d] += W * v[d];
+                }
+            }
+}
+
+/* Moments of one species: density and flux at the particles' positions, or
+ * (reading R16) the flux at the midpoints of their last move. */
 static void deposit_species(ora_sim* s, int k, ora_stats* st)
 {
     ora_sp* p = &s->sp[k];
-    int64_t* M = s->M[k];
-    double* Mc = s->Mc[k];
-    memset(M, 0, (size_t)(4 * s->ndep) * sizeof(int64_t));
-    memset(Mc, 0, (size_t)(4 * s->ndep) * sizeof(double));
+    memset(s->M[k], 0, (size_t)(4 * s->ndep) * sizeof(int64_t));
+    memset(s->Mc[k], 0, (size_t)(4 * s->ndep) * sizeof(double));
     for (int64_t i = 0; i < p->n; ++i) {
-        const int64_t* c = &p->c[3 * i];
-        const double* o = &p->o[3 * i];
         double v[3];
         velocity_of(&s->c, &p->v[3 * i], v);
-        int64_t first[3] = {0, 0, 0}, wi[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
-        double wr[3][3] = {{1, 0, 0}, {1, 0, 0}, {1, 0, 0}};
-        int np[3] = {1, 1, 1};
-        for (int d = 0; d < s->c.dim; ++d) {
-            if (s->c.deposit_mode == 0) np[d] = shape_int(s->c.shape, s->b, c[d], o[d], &first[d], wi[d]);
-            else np[d] = shape_real(s->c.shape, c[d], o[d], &first[d], wr[d]);
-        }
         int64_t vq[3];
         for (int d = 0; d < 3; ++d) vq[d] = quant_v(v[d], s->sv, &st->saturated);
-        for (int a = 0; a < np[0]; ++a)
-            for (int bb = 0; bb < np[1]; ++bb)
-                for (int cc = 0; cc < np[2]; ++cc) {
-                    if (s->c.deposit_mode == 0) {
-                        int64_t n = dep_index(s, first[0] + a, first[1] + bb, first[2] + cc);
-                        if (n < 0) { st->out_of_range++; continue; }
-                        int64_t W = wi[0][a] * wi[1][bb] * wi[2][cc];
-                        M[4 * n + 0] += W;
-                        for (int d = 0; d < 3; ++d) M[4 * n + 1 + d] += W * vq[d];
-                    } else {
-                        int64_t n = dep_index(s, first[0] + a, first[1] + bb, first[2] + cc);
-                        if (n < 0) { st->out_of_range++; continue; }
-                        double W = wr[0][a] * wr[1][bb] * wr[2][cc];
-                        Mc[4 * n + 0] += W;
-                        for (int d = 0; d < 3; ++d) Mc[4 * n + 1 + d] += W * v[d];
-                    }
-                }
+        if (s->c.coupling == 2) {
+            deposit_at(s, k, &p->c[3 * i], &p->o[3 * i], v, vq, 1, st);
+            deposit_at(s, k, &p->ch[3 * i], &p->oh[3 * i], v, vq, 2, st);
+        } else {
+            deposit_at(s, k, &p->c[3 * i], &p->o[3 * i], v, vq, 3, st);
+        }
     }
 }
 
@@ -1067,8 +1120,16 @@ static void field_update(ora_sim* s)
     double *B0 = (double*)malloc(nb), *B1 = (double*)malloc(nb), *B2 = (double*)malloc(nb);
     double *F = (double*)malloc(nb);
     double* E = (double*)malloc((size_t)(3 * s->nnode) * sizeof(double));
-    int64_t N = 3 * s->ncent;
+    int64_t N = 3 * s->ncent, nn = s->nnode;
     fluid_from_moments(s);
+    double* fn1 = NULL;
+    if (s->c.coupling == 2) {
+        /* reading R16: moments frozen at t_{n+1/2} during the update: the
+         * mean of the two densities, the midpoint flux as deposited */
+        fn1 = (double*)malloc((size_t)nn * sizeof(double));
+        memcpy(fn1, s->fn, (size_t)nn * sizeof(double));
+        for (int64_t q = 0; q < nn; ++q) s->fn[q] = 0.5 * (s->fn_prev[q] + fn1[q]);
+    }
     double h = s->c.dt / (double)s->c.n_sub;
     for (int sub = 0; sub < s->c.n_sub; ++sub) {
         memcpy(B0, s->B, nb);
@@ -1079,14 +1140,47 @@ static void field_update(ora_sim* s)
         ohm_all(s, B2, E, NULL); faraday_rhs(s, E, F);
         for (int64_t q = 0; q < N; ++q) s->B[q] = (1.0 / 3.0) * B0[q] + (2.0 / 3.0) * (B2[q] + h * F[q]);
     }
+    if (s->c.coupling == 2) {
+        /* E^{n+1}: n^{n+1} and the flux extrapolated from t_{n-1/2} and
+         * t_{n+1/2} to t_{n+1}; both become the previous step's values */
+        for (int64_t q = 0; q < nn; ++q) {
+            s->fn[q] = fn1[q];
+            s->fn_prev[q] = fn1[q];
+        }
+        for (int64_t q = 0; q < 3 * nn; ++q) {
+            double gh = s->fg[q];
+            s->fg[q] = 1.5 * gh - 0.5 * s->fg_prev[q];
+            s->fg_prev[q] = gh;
+        }
+        free(fn1);
+    }
     ohm_all(s, s->B, s->E, s->Bb);
     free(B0); free(B1); free(B2); free(F); free(E);
 }
 
+/* E from the current B and moments.  With reading R16 the moments' density
+ * and flux also become the previous step's (a loaded or initial state has
+ * no earlier flux: its own stands in for it). */
 void ora_compute_E(ora_sim* s)
 {
     fluid_from_moments(s);
+    if (s->c.coupling == 2) {
+        memcpy(s->fn_prev, s->fn, (size_t)s->nnode * sizeof(double));
+        memcpy(s->fg_prev, s->fg, (size_t)(3 * s->nnode) * sizeof(double));
+    }
     ohm_all(s, s->B, s->E, s->Bb);
+}
+
+void ora_leapfrog_start(ora_sim* s)
+{
+    for (int k = 0; k < 2; ++k) {
+        ora_sp* p = &s->sp[k];
+        for (int64_t i = 0; i < p->n; ++i) {
+            double E[3], B[3];
+            gather(s, &p->c[3 * i], &p->o[3 * i], E, B);
+            boris(&s->c, &p->v[3 * i], E, B, -0.5 * s->c.dt);
+        }
+    }
 }
 
 /* ------------------------------------------------------------------ */
@@ -1182,6 +1276,8 @@ int ora_set_particles(ora_sim* s, int32_t k, int64_t n, const int64_t* cell3, co
     memcpy(p->o, off3, (size_t)(3 * n) * sizeof(double));
     memcpy(p->v, v3, (size_t)(3 * n) * sizeof(double));
     memcpy(p->id, id, (size_t)n * sizeof(uint64_t));
+    memcpy(p->ch, cell3, (size_t)(3 * n) * sizeof(int64_t));   /* no move yet: midpoint = position */
+    memcpy(p->oh, off3, (size_t)(3 * n) * sizeof(double));
     p->n = n;
     return 0;
 }

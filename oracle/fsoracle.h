@@ -44,6 +44,7 @@ typedef struct ora_cfg {
     int32_t smooth;         /* binomial passes on the fluid moments (reading R13) */
     int32_t wall_field;     /* 1: conducting wall at x = L (reading R14) */
     double lc_depletion;    /* prescribed wall: depletion of the return flux outside the loss cone (reading R15) */
+    int32_t coupling;       /* ion-field time coupling: 1 first order (R4), 2 time-centred (reading R16) */
 } ora_cfg;
 
 typedef struct ora_stats {
@@ -86,6 +87,10 @@ int      ora_wall_list(const ora_cfg* cfg, int64_t step, int32_t species, int64_
 void     ora_philox(const uint64_t ctr[4], uint64_t k0, uint64_t k1, uint64_t out[4]);
 int      ora_inject_counts(const ora_cfg* cfg, int64_t step, int64_t* out2);
 int      ora_record(ora_sim* s, int32_t on);
+/* Start of the leapfrog from velocities given at t = 0: one Boris step of
+ * -dt/2 in the current E and Bbar (positions unchanged), so that the stored
+ * velocities are v^{-1/2} to second order. */
+void     ora_leapfrog_start(ora_sim* s);
 
 /* Sampled evaluation for large runs: the push (gather, Boris, move; no
  * boundaries) of given particles in given node fields (E3, Bb3: nnode x 3),

@@ -61,7 +61,7 @@ class OraCfg(C.Structure):
         ("wall_model", C.c_int32),
         ("ret_f0", C.c_double), ("ret_alpha", C.c_double), ("gain", C.c_double),
         ("kappa", C.c_double), ("r_dot", C.c_double), ("smooth", C.c_int32), ("wall_field", C.c_int32),
-        ("lc_depletion", C.c_double),
+        ("lc_depletion", C.c_double), ("coupling", C.c_int32),
     ]
 
 
@@ -95,6 +95,7 @@ def make_cfg(p: dict, deposit_mode: str = "fixed") -> OraCfg:
     c.smooth = int(p.get("smooth", 0))
     c.wall_field = int(p.get("wall_field", 0))
     c.lc_depletion = float(p.get("lc_depletion", 0.0))
+    c.coupling = int(p.get("coupling", 1))
     return c
 
 
@@ -131,6 +132,7 @@ def _load(path: str):
     L.ora_philox.argtypes = [vp, C.c_uint64, C.c_uint64, vp]
     L.ora_inject_counts.argtypes = [C.POINTER(OraCfg), i64, vp]
     L.ora_record.argtypes = [vp, i32]
+    L.ora_leapfrog_start.argtypes = [vp]
     pc = C.POINTER(OraCfg)
     L.ora_push_sample.argtypes = [pc, vp, vp, i64, vp, vp, vp, vp, vp, vp]
     L.ora_ohm_sample.argtypes = [pc, vp, vp, vp, i64, vp, vp, vp]
@@ -260,6 +262,9 @@ class Oracle:
 
     def compute_E(self):
         self.L.ora_compute_E(self.h)
+
+    def leapfrog_start(self):
+        self.L.ora_leapfrog_start(self.h)
 
     # --- state -----------------------------------------------------------
     @property

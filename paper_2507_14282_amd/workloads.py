@@ -33,6 +33,10 @@ DEFAULTS = dict(
     # prescribed wall: share of the return flux outside the field-aligned loss
     # cone that is removed (0: the isotropic downstream population)
     lc_depletion=0.0,
+    # ion-field time coupling: 1 first order (moments of the new positions,
+    # frozen over the field update), 2 time-centred (moments at t_{n+1/2},
+    # flux extrapolated to t_{n+1} for E^{n+1})
+    coupling=1,
     smooth=0,      # passes of the 1-2-1 filter on the fluid moments (0: none)
     wall_field=0,  # 1: conducting wall at x = L (E_y = E_z = 0 there)
     precision=32, steps=10,
