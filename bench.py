@@ -74,6 +74,7 @@ def workload_throughput(name, steps, warmup, **overrides):
         "workload": f"{dim}D3V FP32 {p['nx']}x{p['ny']}x{p['nz']} cells dx={p['dx']} d_i, {p['ppc']} ppc"
                     + (f" + CRs n_cr={p['n_cr']:g}" if sim.has_cr else "") + f", {p['shape']}, M_A={p['u_sh']:g}"
                     + (f", relativistic c/v_A={p['c_light']:g}" if p.get("c_light", 0) > 0 else "")
+                    + (", time-centred coupling" if p.get("coupling", 1) == 2 else "")
                     + (", reflecting wall" + (" (conducting)" if p.get("wall_field", 0) else "")
                        if p["wall_th"] == "specular" else "")
                     + (f", prescribed wall (f0={p['ret_f0']:g}, gain={p['gain']:g}, kappa={p['kappa']:g}, "
@@ -490,6 +491,11 @@ def main():
             # (t = 10) so that the reflected beams and the shock are in it
             "2D rw2 reflecting wall": workload_throughput("rw2", 50, 2000),
             # the prescribed faux shock on the 3D box
+            # the time-centred (second-order) ion-field coupling, on the 3D box
+            # and on the 2D box with the paper's relativistic dHybridR push
+            "3D cfg4 time-centred coupling": workload_throughput("cfg4", 30, 10, coupling=2),
+            "2D cfg3 relativistic, time-centred coupling": workload_throughput("cfg3", 50, 10, c_light=1000.0,
+                                                                               coupling=2),
             # with the loss cone of the oblique (45 deg) shock depleted
             "3D cfg4 prescribed wall": workload_throughput("cfg4", 30, 10, wall_model=1, ret_f0=0.8, ret_alpha=0.0,
                                                             gain=1.2, kappa=1.5, r_dot=0.1, lc_depletion=0.5),

@@ -154,6 +154,23 @@ typedef struct fs_config {
                                lc_depletion.  0 (the default) leaves the wall
                                as above, bit for bit; a parallel shock's cone
                                holds every return direction. */
+    int32_t coupling;       /* ion-field time coupling.  1 (the default): the
+                               moments of the new positions, frozen over the
+                               field update, first order in dt.  2: time-centred,
+                               second order (the coupling of the dHybridR code
+                               the paper runs, Sec. 2; the paper gives no
+                               scheme): the density is deposited at x^{n+1} and
+                               the flux at the midpoint of the move,
+                               x^n + v^{n+1/2} dt / 2 (ions reflected or injected
+                               in the step at their new position); B advances
+                               with the moments frozen at t_{n+1/2} (the mean of
+                               the last two densities, the midpoint flux); E^{n+1}
+                               takes n^{n+1} and the flux extrapolated to t_{n+1},
+                               (3 Gamma^{n+1/2} - Gamma^{n-1/2}) / 2.  A load or a
+                               refresh takes its own flux as Gamma^{-1/2}.  Needs
+                               deposit_mode 0 and no smoothing; checkpoints and
+                               the adjoint entry points refuse it (FS_EINVAL). */
+    int32_t pad_coupling;
 } fs_config;
 
 /* Sizes the caller must allocate, reported by fs_layout(). */

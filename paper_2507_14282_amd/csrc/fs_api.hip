@@ -33,7 +33,9 @@ struct fs_handle {
     double* B2 = nullptr;
     double* Etmp = nullptr;
     double* fluid = nullptr;
-    double* fluid2 = nullptr;     // second fluid buffer of the binomial filter
+    double* fluid2 = nullptr;     // second fluid buffer: binomial filter, or the final Ohm of the time-centred coupling
+    double* nprev = nullptr;      // time-centred coupling: density of the previous step (nnode)
+    double* gprev = nullptr;      // and its midpoint flux (3 x nnode)
     double* phase = nullptr;
     double* part = nullptr;
     int64_t npart = 0;
@@ -185,6 +187,11 @@ int compute_layout(const fs_config* c, fs_layout_info* L, std::string& err) {
         if (c->ret_alpha != 0.0 && !(c->cr_w > 0.0)) { err = "ret_alpha != 0 needs cr_w > 0"; return FS_EINVAL; }
     }
     if (!(c->lc_depletion >= 0.0 && c->lc_depletion <= 1.0)) { err = "lc_depletion must be in [0, 1]"; return FS_EINVAL; }
+    if (c->coupling != 1 && c->coupling != 2) { err = "coupling must be 1 or 2"; return FS_EINVAL; }
+    if (c->coupling == 2 && (c->deposit_mode != 0 || c->smooth != 0)) {
+        err = "the time-centred coupling needs deposit_mode 0 and no smoothing";
+        return FS_EINVAL;
+    }
     if (c->lc_depletion > 0.0 && c->wall_model != 1) { err = "lc_depletion needs the prescribed wall"; return FS_EINVAL; }
     if (c->smooth < 0 || c->smooth > 64) { err = "smooth must be in [0, 64]"; return FS_EINVAL; }
     if (c->wall_field != 0 && c->wall_field != 1) { err = "wall_field must be 0 or 1"; return FS_EINVAL; }
@@ -329,8 +336,14 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
     const long nn = h->L.nnode, nc = h->L.ncent;
     const dim3 blk(kFX, kFY, 1);
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
+    // the time-centred coupling: the step's field update takes the moments at
+    // t_{n+1/2} (h->fluid) and its final Ohm those at t_{n+1} (h->fluid2); a
+    // refresh (Ohm only) makes the current moments the previous step's
+    const int tc = h->cfg.coupling == 2 ? (rk ? 2 : 1) : 0;
     k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(f->mom[0]),
-                               reinterpret_cast<const long long*>(h->has_cr ? f->mom[1] : f->mom[0]), h->fluid, nn);
+                               reinterpret_cast<const long long*>(h->has_cr ? f->mom[1] : f->mom[0]), h->fluid, nn,
+                               h->fluid2, h->nprev, h->gprev, tc);
+    const double* fl_ohm = tc == 2 ? h->fluid2 : h->fluid;
     if (h->cfg.smooth > 0) {
         // passes ping-pong between the two buffers; the finish writes the
         // other one, which then becomes h->fluid
@@ -359,7 +372,7 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
                                             zc);
             }
         }
-        k_ohm3<R><<<(unsigned)(gxo * gy * gz), 256, 0, s>>>(h->F, f->B, h->fluid, f->E, static_cast<R*>(f->gather), nn,
+        k_ohm3<R><<<(unsigned)(gxo * gy * gz), 256, 0, s>>>(h->F, f->B, fl_ohm, f->E, static_cast<R*>(f->gather), nn,
                                                            nc, gxo, gy, zc);
         return;
     }
@@ -377,7 +390,7 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
         }
     }
     const int gxo = (int)((h->L.nxn + FB::X - 1) / FB::X);
-    k_ohm<R, D><<<(unsigned)(gxo * gy * gz), 256, 0, s>>>(h->F, f->B, h->fluid, f->E, static_cast<R*>(f->gather), nn, nc,
+    k_ohm<R, D><<<(unsigned)(gxo * gy * gz), 256, 0, s>>>(h->F, f->B, fl_ohm, f->E, static_cast<R*>(f->gather), nn, nc,
                                                         gxo, gy);
 }
 
@@ -445,7 +458,9 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
                     mom, h->xl[k], h->ctr, policy_of(h, k), k);
             };
             const bool rel = h->cfg.c_light > 0.0;
-            if (dep) rel ? launch(k_push<R, D, S, true, true>) : launch(k_push<R, D, S, true, false>);
+            if (dep && h->cfg.coupling == 2)
+                rel ? launch(k_push<R, D, S, true, true, true>) : launch(k_push<R, D, S, true, false, true>);
+            else if (dep) rel ? launch(k_push<R, D, S, true, true>) : launch(k_push<R, D, S, true, false>);
             else rel ? launch(k_push<R, D, S, false, true>) : launch(k_push<R, D, S, false, false>);
         }
         timing_end(h, t_push, s);
@@ -616,7 +631,7 @@ void fluid_of(fs_handle* h, const fs_particles* sp, int64_t* const* mom, hipStre
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
     k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(h->amom[0]),
                                reinterpret_cast<const long long*>(h->has_cr ? h->amom[1] : h->amom[0]), h->afl,
-                               h->L.nnode);
+                               h->L.nnode, nullptr, nullptr, nullptr, 0);
 }
 
 // lam_B += (dF/dB)^T lF and lam_fl += (dF/dfl)^T lF for F(B) = -curl Ohm(B, fl).
@@ -839,7 +854,11 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     ok = ok && dmalloc((void**)&h->B2, 3 * nc * sizeof(double));
     ok = ok && dmalloc((void**)&h->Etmp, 3 * nn * sizeof(double));
     ok = ok && dmalloc((void**)&h->fluid, 5 * nn * sizeof(double));
-    if (c.smooth > 0) ok = ok && dmalloc((void**)&h->fluid2, 5 * nn * sizeof(double));
+    if (c.smooth > 0 || c.coupling == 2) ok = ok && dmalloc((void**)&h->fluid2, 5 * nn * sizeof(double));
+    if (c.coupling == 2) {
+        ok = ok && dmalloc((void**)&h->nprev, nn * sizeof(double));
+        ok = ok && dmalloc((void**)&h->gprev, 3 * nn * sizeof(double));
+    }
     ok = ok && dmalloc((void**)&h->phase, (c.n_modes + 1) * sizeof(double));
     h->npart = std::max<int64_t>(grid_for(nc), h->L.ntiles) * 4;
     ok = ok && dmalloc((void**)&h->part, h->npart * sizeof(double));
@@ -892,7 +911,7 @@ void fs_destroy(fs_handle* h) {
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     hipFree(h->ctr);
     if (h->ctr_host) hipHostFree(h->ctr_host);
-    hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->fluid2); hipFree(h->phase); hipFree(h->part); hipFree(h->spec);
+    hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->fluid2); hipFree(h->nprev); hipFree(h->gprev); hipFree(h->phase); hipFree(h->part); hipFree(h->spec);
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
     for (int k = 0; k < 2; ++k) { hipFree(h->amom[k]); hipFree(h->alM[k]); }
     hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->alE);
@@ -990,6 +1009,7 @@ int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
     if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
     if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
+    if (h->cfg.coupling != 1) return fail(h, FS_EINVAL, "the adjoint covers the first-order coupling only");
     if (h->cfg.smooth != 0) return fail(h, FS_EINVAL, "the adjoint covers the unfiltered moments only");
     if (!f_n->B || !f_n->gather || !f_n1->B) return fail(h, FS_EINVAL, "NULL field array");
     if (step < 0) return fail(h, FS_EINVAL, "negative step");
@@ -1013,6 +1033,7 @@ int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, 
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
     if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
     if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
+    if (h->cfg.coupling != 1) return fail(h, FS_EINVAL, "the adjoint covers the first-order coupling only");
     if (h->cfg.smooth != 0) return fail(h, FS_EINVAL, "the adjoint covers the unfiltered moments only");
     if (!f0->B) return fail(h, FS_EINVAL, "NULL field array");
     int rc = check_adjoint(h, lam);
@@ -1492,6 +1513,7 @@ int fs_read_particles(fs_handle* h, const fs_particles* sp, int64_t* n, int64_t*
 
 int fs_checkpoint_bytes(fs_handle* h, const fs_particles* sp, int64_t* bytes, hipStream_t s) {
     if (!h || !sp || !bytes) return fail(h, FS_EINVAL, "NULL argument");
+    if (h->cfg.coupling == 2) return fail(h, FS_EINVAL, "checkpoints do not carry the time-centred coupling's previous moments");
     if (int rc = check_particles(h, sp)) return rc;
     CkptHeader H;
     std::vector<int64_t> toff[2];
@@ -1503,6 +1525,7 @@ int fs_checkpoint_bytes(fs_handle* h, const fs_particles* sp, int64_t* bytes, hi
 int fs_checkpoint(fs_handle* h, const fs_particles* sp, const fs_fields* f, void* dst, int64_t cap_bytes,
                   hipStream_t s) {
     if (!h || !sp || !f || !dst) return fail(h, FS_EINVAL, "NULL argument");
+    if (h->cfg.coupling == 2) return fail(h, FS_EINVAL, "checkpoints do not carry the time-centred coupling's previous moments");
     if (int rc = check_particles(h, sp)) return rc;
     if (int rc = check_fields(h, f)) return rc;
     FS_DISPATCH_RD(h, (checkpoint_impl<R, D>(h, sp, f, dst, cap_bytes, s)));
@@ -1510,6 +1533,7 @@ int fs_checkpoint(fs_handle* h, const fs_particles* sp, const fs_fields* f, void
 
 int fs_restore(fs_handle* h, fs_particles* sp, fs_fields* f, const void* src, int64_t bytes, hipStream_t s) {
     if (!h || !sp || !f || !src) return fail(h, FS_EINVAL, "NULL argument");
+    if (h->cfg.coupling == 2) return fail(h, FS_EINVAL, "checkpoints do not carry the time-centred coupling's previous moments");
     if (int rc = check_particles(h, sp)) return rc;
     if (int rc = check_fields(h, f)) return rc;
     auto load = [&]() -> int { FS_DISPATCH_RD(h, (restore_impl<R, D>(h, sp, f, src, bytes, s))); };

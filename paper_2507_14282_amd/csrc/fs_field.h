@@ -62,12 +62,32 @@ __device__ __forceinline__ double centre_B(const double* __restrict__ B, const F
 // block layer, so every thread knows its (i, j, k) without any division.
 constexpr int kFX = 64, kFY = 4;
 
+// One node's fluid record: n_e = max(n, n_floor), p_e = (beta_e / 2)
+// n_e^gamma_e and the flux plus the rigid external current (added after the
+// filter when smoothing).
+__device__ __forceinline__ void store_fluid(const FieldGeo& F, double* __restrict__ fl, long nnode, long n,
+                                            double dens, const double G[3]) {
+    const double ne = fmax(dens, F.n_floor);
+    fl[n] = ne;
+    fl[nnode + n] = 0.5 * F.beta_e * pow(ne, F.gamma_e);
+    fl[2 * nnode + n] = F.smooth ? G[0] : G[0] + F.j_ext;
+    fl[3 * nnode + n] = G[1];
+    fl[4 * nnode + n] = G[2];
+}
+
 // Ion density / flux at the field nodes from both species' integer moments,
 // boundary-filled, floored, plus the rigid external current, and the
-// electron pressure p_e = (beta_e / 2) n_e^gamma_e.
+// electron pressure p_e = (beta_e / 2) n_e^gamma_e.  tc selects the
+// time-centred coupling: 0 off; 1 also keep the density and flux as the
+// previous step's (nprev, gprev: a load or a refresh); 2 a step's field
+// update: fl gets the moments at t_{n+1/2} (the mean of the previous and new
+// densities, the flux as deposited at the moves' midpoints), fl2 those of the
+// final Ohm's law at t_{n+1} (the new density, the flux extrapolated,
+// (3 Gamma^{n+1/2} - Gamma^{n-1/2}) / 2), and nprev / gprev move on.
 __global__ __launch_bounds__(256) void k_fluid(FieldGeo F, const long long* __restrict__ m0,
                                                const long long* __restrict__ m1, double* __restrict__ fl,
-                                               long nnode) {
+                                               long nnode, double* __restrict__ fl2, double* __restrict__ nprev,
+                                               double* __restrict__ gprev, int tc) {
     int i = blockIdx.x * kFX + threadIdx.x;
     const int j = blockIdx.y * kFY + threadIdx.y, k = blockIdx.z;
     if (i >= F.nxn || j >= F.nyc) return;
@@ -103,12 +123,22 @@ __global__ __launch_bounds__(256) void k_fluid(FieldGeo F, const long long* __re
             G[2] += F.wcr * ((double)d.y * F.scG);
         }
     }
-    double ne = fmax(dens, F.n_floor);
-    fl[n] = ne;
-    fl[nnode + n] = 0.5 * F.beta_e * pow(ne, F.gamma_e);
-    fl[2 * nnode + n] = F.smooth ? G[0] : G[0] + F.j_ext;   // smoothing adds J_ext after the filter
-    fl[3 * nnode + n] = G[1];
-    fl[4 * nnode + n] = G[2];
+    if (tc == 2) {
+#pragma clang fp contract(off)
+        const double dh = 0.5 * (nprev[n] + dens);
+        store_fluid(F, fl, nnode, n, dh, G);
+        double Ge[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Ge[c] = 1.5 * G[c] - 0.5 * gprev[c * nnode + n];
+        store_fluid(F, fl2, nnode, n, dens, Ge);
+    } else {
+        store_fluid(F, fl, nnode, n, dens, G);
+    }
+    if (tc) {
+        nprev[n] = dens;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gprev[c * nnode + n] = G[c];
+    }
 }
 
 // One pass of the 1-2-1 binomial filter along one axis over the fluid

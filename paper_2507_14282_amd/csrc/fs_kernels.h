@@ -104,7 +104,8 @@ __device__ __forceinline__ long gather_index(int i, int j, int k, const Geo& G) 
 // with integer weights wx/wy/wz starting at the stencil offsets rx/ry/rz.
 // Into LDS when the whole stencil lies in the tile's deposit box, otherwise
 // straight into the global grid.
-template <int D, int S>
+// WHICH selects the moments: 1 the density R, 2 the flux G, 3 both.
+template <int D, int S, int WHICH = 3>
 __device__ __forceinline__ void deposit_one(unsigned long long* lds, int bx0, int by0, int bz0,
                                             unsigned long long* mom, const Geo& G, int cx, int cy,
                                             int cz, const int* wx, const int* wy, const int* wz,
@@ -138,10 +139,12 @@ __device__ __forceinline__ void deposit_one(unsigned long long* lds, int bx0, in
                     for (int a = 0; a < 2; ++a) {
                         const int W = D >= 2 ? __umul24(ux[a], wyz) : ux[a];
                         unsigned long long* p = lds + (base + a * sx + b * sy + c * sz);
-                        atomicAdd(p, (unsigned long long)W);
-                        atomicAdd(p + X::DN, (unsigned long long)mul24(W, vq[0]));
-                        atomicAdd(p + 2 * X::DN, (unsigned long long)mul24(W, vq[1]));
-                        atomicAdd(p + 3 * X::DN, (unsigned long long)mul24(W, vq[2]));
+                        if constexpr (WHICH & 1) atomicAdd(p, (unsigned long long)W);
+                        if constexpr (WHICH & 2) {
+                            atomicAdd(p + X::DN, (unsigned long long)mul24(W, vq[0]));
+                            atomicAdd(p + 2 * X::DN, (unsigned long long)mul24(W, vq[1]));
+                            atomicAdd(p + 3 * X::DN, (unsigned long long)mul24(W, vq[2]));
+                        }
                     }
                 }
             }
@@ -181,10 +184,12 @@ __device__ __forceinline__ void deposit_one(unsigned long long* lds, int bx0, in
                     for (int a = 0; a < 3; ++a) {
                         const int W = D >= 2 ? __umul24(ux[a], wyz) : ux[a];
                         unsigned long long* p = lds + (base + ox[a] + oy[b] + oz[c]);
-                        atomicAdd(p, (unsigned long long)W);
-                        atomicAdd(p + X::DN, (unsigned long long)mul24(W, vq[0]));
-                        atomicAdd(p + 2 * X::DN, (unsigned long long)mul24(W, vq[1]));
-                        atomicAdd(p + 3 * X::DN, (unsigned long long)mul24(W, vq[2]));
+                        if constexpr (WHICH & 1) atomicAdd(p, (unsigned long long)W);
+                        if constexpr (WHICH & 2) {
+                            atomicAdd(p + X::DN, (unsigned long long)mul24(W, vq[0]));
+                            atomicAdd(p + 2 * X::DN, (unsigned long long)mul24(W, vq[1]));
+                            atomicAdd(p + 3 * X::DN, (unsigned long long)mul24(W, vq[2]));
+                        }
                     }
                 }
             }
@@ -206,18 +211,22 @@ __device__ __forceinline__ void deposit_one(unsigned long long* lds, int bx0, in
                 if (in_lds) {
                     // planar [moment][node]: lanes at different nodes hit different banks
                     unsigned long long* p = lds + ((lz + c) * X::DY * X::DX + (ly + b) * X::DX + (lx + a));
-                    atomicAdd(p, r);
-                    atomicAdd(p + X::DN, gx);
-                    atomicAdd(p + 2 * X::DN, gy);
-                    atomicAdd(p + 3 * X::DN, gz);
+                    if constexpr (WHICH & 1) atomicAdd(p, r);
+                    if constexpr (WHICH & 2) {
+                        atomicAdd(p + X::DN, gx);
+                        atomicAdd(p + 2 * X::DN, gy);
+                        atomicAdd(p + 3 * X::DN, gz);
+                    }
                 } else {
                     long gi = dep_index(cx + rx + a, D >= 2 ? cy + ry + b : 0, D >= 3 ? cz + rz + c : 0, G);
                     if (gi < 0) { oor = 1; continue; }
                     unsigned long long* p = mom + 4 * gi;
-                    atomicAdd(p + 0, r);
-                    atomicAdd(p + 1, gx);
-                    atomicAdd(p + 2, gy);
-                    atomicAdd(p + 3, gz);
+                    if constexpr (WHICH & 1) atomicAdd(p + 0, r);
+                    if constexpr (WHICH & 2) {
+                        atomicAdd(p + 1, gx);
+                        atomicAdd(p + 2, gy);
+                        atomicAdd(p + 3, gz);
+                    }
                 }
             }
         }
@@ -225,7 +234,7 @@ __device__ __forceinline__ void deposit_one(unsigned long long* lds, int bx0, in
 }
 
 // Deposit of a particle whose velocity codes are already formed.
-template <typename R, int D, int S>
+template <typename R, int D, int S, int WHICH = 3>
 __device__ __forceinline__ void deposit_coded(unsigned long long* lds, int bx0, int by0, int bz0,
                                               unsigned long long* mom, const Geo& G, int cx, int cy, int cz,
                                               const R* o, const int vq[3], int& oor) {
@@ -233,7 +242,7 @@ __device__ __forceinline__ void deposit_coded(unsigned long long* lds, int bx0, 
     weights_int<R, S>(o[0], G.b, rx, wx);
     if constexpr (D >= 2) weights_int<R, S>(o[1], G.b, ry, wy);
     if constexpr (D >= 3) weights_int<R, S>(o[2], G.b, rz, wz);
-    deposit_one<D, S>(lds, bx0, by0, bz0, mom, G, cx, cy, cz, wx, wy, wz, rx, ry, rz, vq, oor);
+    deposit_one<D, S, WHICH>(lds, bx0, by0, bz0, mom, G, cx, cy, cz, wx, wy, wz, rx, ry, rz, vq, oor);
 }
 
 // Integer weights + velocity codes of a particle and its deposit.  MODE 0:
@@ -352,7 +361,9 @@ template <typename R, int D, int S, bool REL> struct PushWaves {
         sizeof(R) != 4 ? 1 : ((D == 1 || (D == 2 && S == 1)) ? 8 : ((REL && S == 1) ? 6 : 1));
 };
 
-template <typename R, int D, int S, bool DEP, bool REL>
+// TC: the time-centred coupling, density deposited at the new position and
+// flux at the midpoint of the move.
+template <typename R, int D, int S, bool DEP, bool REL, bool TC = false>
 __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
                                               int32_t* __restrict__ cnt_out, int64_t cap,
                                               const R* __restrict__ gather, unsigned long long* __restrict__ mom,
@@ -453,6 +464,20 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
             for (int d = 0; d < 3; ++d) vel[d] = v[d] * (R)ig;
         }
         int nc[3] = {cx, cy, cz};
+        // time-centred coupling: the midpoint of the move, where the flux goes
+        int hc[3] = {cx, cy, cz};
+        R ho[3] = {o[0], o[1], o[2]};
+        if constexpr (TC) {
+            const R hdtdx = (R)(0.5 * G.dtdx);
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                R xh = o[d] + vel[d] * hdtdx;
+                R fh = floor(xh);
+                hc[d] += (int)fh;
+                ho[d] = xh - fh;
+                if (ho[d] >= (R)1) { ho[d] = (R)0; hc[d] += 1; }
+            }
+        }
 #pragma unroll
         for (int d = 0; d < D; ++d) {
             R xi = o[d] + vel[d] * dtdx;
@@ -493,7 +518,13 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
 
         if constexpr (DEP) {
             if (kind == 0) {
-                if constexpr (REL) {
+                if constexpr (TC) {
+                    int vq[3];
+                    if constexpr (REL) velocity_codes_ig<R>(v, ig, G.sv, status, vq);
+                    else velocity_codes<R, false>(v, 0.0, G.sv, status, vq);
+                    deposit_coded<R, D, S, 1>(sd, dx0, dy0, dz0, mom, G, nc[0], nc[1], nc[2], o, vq, oor);
+                    deposit_coded<R, D, S, 2>(sd, dx0, dy0, dz0, mom, G, hc[0], hc[1], hc[2], ho, vq, oor);
+                } else if constexpr (REL) {
                     int vq[3];
                     velocity_codes_ig<R>(v, ig, G.sv, status, vq);
                     deposit_coded<R, D, S>(sd, dx0, dy0, dz0, mom, G, nc[0], nc[1], nc[2], o, vq, oor);

@@ -50,7 +50,7 @@ class FsConfig(C.Structure):
         ("n_modes", C.c_int32), ("inject", C.c_int32), ("deposit_mode", C.c_int32), ("wall_model", C.c_int32),
         ("ret_f0", C.c_double), ("ret_alpha", C.c_double), ("gain", C.c_double), ("kappa", C.c_double),
         ("r_dot", C.c_double), ("smooth", C.c_int32), ("wall_field", C.c_int32),
-        ("lc_depletion", C.c_double),
+        ("lc_depletion", C.c_double), ("coupling", C.c_int32), ("pad_coupling", C.c_int32),
     ]
 
 
@@ -186,6 +186,7 @@ def make_config(p: dict) -> FsConfig:
     c.smooth = int(p.get("smooth", 0))
     c.wall_field = int(p.get("wall_field", 0))
     c.lc_depletion = float(p.get("lc_depletion", 0.0))
+    c.coupling = int(p.get("coupling", 1))
     return c
 
 

@@ -51,7 +51,7 @@ def test_binding_argument_counts_match_header():
 
 def test_struct_sizes_match_header():
     # sizes of the C structs as laid out by the compiler for the ABI
-    assert C.sizeof(F.FsConfig) == 19 * 8 + 8 + 16 * 4 + 5 * 8 + 2 * 4 + 8
+    assert C.sizeof(F.FsConfig) == 19 * 8 + 8 + 16 * 4 + 5 * 8 + 2 * 4 + 8 + 2 * 4
     assert C.sizeof(F.FsParticles) == 5 * 8 + 2 * 8 + 2 * 4
     assert C.sizeof(F.FsFields) == 5 * 8
     assert C.sizeof(F.FsRecord) == 3 * 8
