@@ -39,6 +39,11 @@ def push_bytes_dim(n_ions, L, dim, nsp, rb=4, with_id=False):
     return n_ions * ion + nsp * (int(L.nnode) * 6 * rb + int(L.ndep) * 32)
 
 
+def progress(msg):
+    """A progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def workload_throughput(name, steps, warmup, **overrides):
     """Whole-step and push+deposit throughput of one preset, with the push
     roofline as for the 3D box (used for the 1D and 2D boxes, and for the
@@ -46,6 +51,7 @@ def workload_throughput(name, steps, warmup, **overrides):
     import torch
     from paper_2507_14282_amd import fshybrid as F
     from paper_2507_14282_amd import workloads as W
+    progress(f"workload {name} {overrides} ({warmup} + {steps} steps)")
     p = W.preset(name, **overrides)
     sim = F.Simulation(p, "cuda:0")
     sim.init_plasma()
@@ -173,7 +179,7 @@ def write_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, command)
     (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the same
     counter reads for the 1 GiB copy; written with the hash of the kernel
     source it was measured on."""
-    kern = "k_push<float, 3, 1, true, false>"
+    kern = "k_push<float, 3, 1, true, false, false>"
     f = _counter(fetch_dir, "FETCH_SIZE", kern)
     w = _counter(write_dir, "WRITE_SIZE", kern)
     cf = _counter(copy_fetch_dir, "FETCH_SIZE", "copy")
@@ -213,7 +219,7 @@ def write_atomics(pmc_dir, command):
     into the tile box), LDS bank / address conflict cycles, and L2 atomic
     requests (the flush of the box into the global moment grid and the
     deposits of ions outside the box)."""
-    kern = "k_push<float, 3, 1, true, false>"
+    kern = "k_push<float, 3, 1, true, false, false>"
     d = {"kernel": kern, "workload": "cfg4 3D box 1024x192x192, 8 ppc", "counters": {}}
     for c in ATOMIC_COUNTERS:
         v = _counter(pmc_dir, c.replace("_sum", "") if c.endswith("_sum") else c, kern)
@@ -389,6 +395,7 @@ def main():
         return 0
 
     p = W.preset(args.workload)
+    progress(f"{args.workload}: load, {args.warmup} warm-up + {args.steps} timed steps")
     sim = F.Simulation(p, "cuda:0")
     sim.init_plasma()
     for s in range(args.warmup):
@@ -501,8 +508,10 @@ def main():
                                                             gain=1.2, kappa=1.5, r_dot=0.1, lc_depletion=0.5),
         }
     if not args.no_adjoint:
+        progress("adjoint workload")
         out["adjoint"] = adjoint_timing()
     if not args.no_cpu_baseline:
+        progress("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out))
     return 0
