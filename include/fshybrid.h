@@ -374,33 +374,45 @@ int fs_bperp_spectrum_noalloc(fs_handle* h, const fs_fields* f, double* out, hip
  * macro-weight multiplier) and the initial Fourier amplitudes.
  * --------------------------------------------------------------------- */
 
-/* What a recorded step writes.  refl (device, nid bytes, indexed by
- * particle id) is cleared by the call and set to 1 for every ion the FS wall
- * reflects during the step; id0 receives the first id the step can inject
- * (the injected ions are id0, id0 + 1, ..., thermal first).  nid must exceed
- * every id the run will hand out. */
+/* What a recorded step writes, per species k (k = 1 only with CRs): dst[k]
+ * (device, int32, one entry per bin slot of the species' particle buffers,
+ * capacity[k] entries, at least the species' capacity) receives, at the bin
+ * slot each ion occupied in the step's input buffer, where the step put it:
+ * its bin slot in the output buffer (>= 0), -1 if the step removed it (it
+ * left through x = 0, or the wall transmitted or dropped it), or -2 - slot
+ * if the FS wall reflected it into that slot.  Entries of slots that held
+ * no ion keep whatever they held.  id0 receives the first id the step can
+ * inject (the injected ions are id0, id0 + 1, ..., thermal first). */
 typedef struct fs_record {
-    uint8_t* refl;
-    int64_t  nid;
+    int32_t* dst[2];
+    int64_t  capacity[2];
     int64_t  id0;
 } fs_record;
 
 /* Adjoint state (device arrays owned by the caller).  Particle adjoints are
- * in the particle precision and indexed by particle id: x[d] (d < dim; dL
- * per cell of position) and v[3], nid entries each, both species sharing the
- * id space; an id not alive at the step holds zero.  Grid adjoints are FP64
- * planar: lB (3 x ncent) = dL/dB at the centres, lE (6 x nnode) = dL/d(Ex,
- * Ey, Ez, Bbarx, Bbary, Bbarz) of the gather grid. */
+ * in the particle precision and laid out like the particle buffers, one
+ * entry per bin slot: for species k and buffer b, x[k][b][d] (d < dim; dL
+ * per cell of position) and v[k][b][c], capacity[k] entries each (at least
+ * the species' capacity).  Buffer cur holds the adjoints of the state a
+ * reverse step starts from, in the bin slots of that state's particle
+ * buffer; the step writes buffer cur ^ 1 in the slots of the state before
+ * it and flips cur.  Grid adjoints are FP64 planar: lB (3 x ncent) = dL/dB
+ * at the centres, lE (6 x nnode) = dL/d(Ex, Ey, Ez, Bbarx, Bbary, Bbarz) of
+ * the gather grid. */
 typedef struct fs_adjoint {
-    void*   x[3];
-    void*   v[3];
-    int64_t nid;
+    void*   x[2][2][3];
+    void*   v[2][2][3];
+    int64_t capacity[2];
+    int32_t cur;
+    int32_t pad;
     double* lB;
     double* lE;
 } fs_adjoint;
 
 /* One full step (deposit_mode 1 only) that also fills *rec.  Same contract
- * as fs_step with flags = FS_ALL. */
+ * as fs_step with flags = FS_ALL.  FS_EINVAL on a NULL dst of a species,
+ * FS_ECAPACITY if a dst holds fewer entries than the species' capacity or
+ * the capacity does not fit the int32 encoding (above 2^31 - 3 slots). */
 int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec,
                    fs_step_stats* st, hipStream_t s);
 
@@ -409,12 +421,29 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
  * gather grid) before the step; sp_n1 / f_n1: particles, B and the moment
  * grids after it (f_n1->mom as the recorded step left them, or NULL to
  * deposit them again).
- * *lam holds on entry the adjoints after the step (particles, lB, lE of
- * B^{n+1} and E^{n+1}) and on exit those before it (B^n, E^n).  grads
- * (device, 2 + n_modes doubles) accumulates dL/du_sh and dL/dalpha_cr. */
+ * *lam holds on entry the adjoints after the step (particles in buffer cur,
+ * in the slots of sp_n1; lB, lE of B^{n+1} and E^{n+1}) and on exit those
+ * before it (particles in the other buffer, in the slots of sp_n, which
+ * becomes cur; B^n, E^n).  Every live slot of sp_n is written, zero for an
+ * ion the step removed.  grads (device, 2 + n_modes doubles) accumulates
+ * dL/du_sh and dL/dalpha_cr.  FS_ECAPACITY if an adjoint buffer or dst
+ * holds fewer entries than the species' capacity. */
 int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n, const fs_particles* sp_n1,
                     const fs_fields* f_n1, const fs_record* rec, int64_t step, fs_adjoint* lam, double* grads,
                     hipStream_t s);
+
+/* Carries the particle adjoints of buffer lam->cur from the bin slots of
+ * `from` to those of `to`: two bin layouts of one state, such as the
+ * checkpoint at the end of a segment of steps and the same state re-run from
+ * the segment's start (the push places ions in an order that depends on the
+ * timing of its atomics, so a re-run puts them in other slots).  Ions are
+ * matched by id through scratch (device, (dim + 3) * nid reals of the
+ * particle precision, nid above every id in both states; an id `from` does
+ * not hold reads zero, ids >= nid are skipped).  Writes buffer cur ^ 1 at
+ * every live slot of `to` and flips lam->cur.  FS_EINVAL on a NULL argument
+ * or a negative nid, FS_ECAPACITY as fs_adjoint_step. */
+int fs_adjoint_relayout(fs_handle* h, const fs_particles* from, const fs_particles* to, fs_adjoint* lam,
+                        void* scratch, int64_t nid, hipStream_t s);
 
 /* Reverse of fs_init_plasma: E^0 = Ohm(B^0, moments of the initial load),
  * the initial velocities (v_x = u_sh + sigma n) and the Fourier modes of
@@ -435,12 +464,13 @@ int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, 
  * bit.  FS_EINVAL on a NULL argument. */
 int fs_precursor_loss(fs_handle* h, const fs_fields* f, double* loss, hipStream_t s);
 
-/* Start of a reverse sweep for that loss.  Zeroes every particle adjoint
- * of *lam (x[d] for d < dim and v[3], nid entries each, in the particle
- * precision), lE and grads (2 + n_modes doubles, device), and sets
- * lB = dL/dB at the final state f->B: (0, 2 B_y, 2 B_z) at the centres with
- * i >= nx/2, 0 elsewhere.  FS_EINVAL on a NULL array, FS_ECAPACITY if
- * lam->nid is below the ids the run has handed out. */
+/* Start of a reverse sweep for that loss.  Zeroes buffer lam->cur of every
+ * species' particle adjoints (x[k][cur][d] for d < dim and v[k][cur][c],
+ * capacity[k] entries each, in the particle precision), lE and grads
+ * (2 + n_modes doubles, device), and sets lB = dL/dB at the final state f->B:
+ * (0, 2 B_y, 2 B_z) at the centres with i >= nx/2, 0 elsewhere.  FS_EINVAL
+ * on a NULL array or cur outside {0, 1}, FS_ECAPACITY if capacity[k] is
+ * below the species' capacity. */
 int fs_adjoint_seed(fs_handle* h, const fs_fields* f, fs_adjoint* lam, double* grads, hipStream_t s);
 
 /* Phase timing with HIP events recorded on the caller's stream (benchmark

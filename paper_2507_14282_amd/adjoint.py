@@ -15,9 +15,12 @@ Everything numeric runs in the library (``fs_precursor_loss``,
 ``fs_adjoint_init``); this module owns the buffers and
 the schedule: a forward pass that keeps a checkpoint every K steps, and a
 reverse pass that re-runs each K-step segment from its checkpoint with
-recording and walks it backwards.  Particle adjoints are indexed by particle
-id, so a re-run segment may place ions in other bin slots than the first
-run did.
+recording and walks it backwards.  Particle adjoints are laid out like the
+particle buffers (one entry per bin slot, two buffers that the reverse steps
+ping-pong); each recorded step keeps where it put every ion, which is all
+the reverse step needs to carry an ion's adjoint from its slot after the
+step to its slot before it.  The tape, the records and the adjoint buffers
+are allocated once and reused by every later reverse pass of the run.
 """
 
 from __future__ import annotations
@@ -108,12 +111,21 @@ def checkpoint_interval(nsteps: int, K: int, state_bytes: int, free_bytes: int, 
 
 
 def _state_bytes(sim: F.Simulation, nsp: int) -> int:
-    """Bytes of one checkpoint / tape state of this simulation."""
+    """Bytes of one checkpoint / tape state of this simulation, with the
+    step record a tape state carries (4 bytes per bin slot)."""
     t = [sim.B, sim.E, sim.gather] + list(sim.mom[:nsp])
     for k in range(nsp):
         cur = int(sim.sp[k].cur)
         t += [sim.bufs[k][cur], sim.cnts[k][cur]]
-    return int(sum(x.numel() * x.element_size() for x in t))
+    rec = sum(4 * int(sim.L.capacity[k]) for k in range(nsp))
+    return int(sum(x.numel() * x.element_size() for x in t)) + rec
+
+
+def _lambda_bytes(sim: F.Simulation, nsp: int, dim: int) -> int:
+    """Bytes of the two particle adjoint buffers and the grid adjoints."""
+    rb = torch.finfo(sim.real).bits // 8
+    part = sum(2 * (dim + 3) * rb * int(sim.L.capacity[k]) for k in range(nsp))
+    return part + 8 * (3 * int(sim.L.ncent) + 6 * int(sim.L.nnode))
 
 
 class AdjointRun:
@@ -130,11 +142,14 @@ class AdjointRun:
         self.device = torch.device(device)
         self.sim = None
         self.checkpoints = {}
+        self._bufs = None      # tape, records and adjoints, kept for later reverse passes
 
     # --- forward ----------------------------------------------------------
     def forward(self, u_sh: float, alpha_cr: float, amps) -> float:
         p = dict(self.p, u_sh=float(u_sh), alpha_cr=float(alpha_cr))
         self.p_run = p
+        self.checkpoints = {}
+        self.sim = None
         sim = F.Simulation(p, self.device)
         self.sim = sim
         self.nsp = 2 if sim.has_cr else 1
@@ -143,10 +158,16 @@ class AdjointRun:
             a = torch.as_tensor(np.asarray(amps, dtype=np.float64), device=self.device)
         sim.init_plasma(a)
         # the interval actually used: the requested one, or less if the
-        # checkpoints and the tape would not fit in the device's free memory
+        # checkpoints and the tape would not fit in the memory free on the
+        # device plus what the allocator holds unused
         free, _ = torch.cuda.mem_get_info(self.device)
+        free += torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
+        if self._bufs is not None and self._bufs["key"] == self._key(sim):
+            free += self._bufs["bytes"]          # reused, already counted out of free
+        else:
+            self._bufs = None
+            free -= _lambda_bytes(sim, self.nsp, int(p["dim"]))
         self.K_run = checkpoint_interval(self.nsteps, self.K, _state_bytes(sim, self.nsp), free)
-        self.checkpoints = {}
         for n in range(self.nsteps):
             if n % self.K_run == 0:
                 self.checkpoints[n] = _State(sim, self.nsp)
@@ -163,65 +184,103 @@ class AdjointRun:
         return float(out.item())
 
     # --- reverse ----------------------------------------------------------
-    def _alloc_lambda(self):
+    def _key(self, sim):
+        return (tuple(int(sim.L.capacity[k]) for k in range(2)), int(sim.L.ncent), int(sim.L.nnode),
+                sim.real, self.nsp)
+
+    def _buffers(self):
+        """The tape states, step records and adjoint buffers of this run,
+        allocated by the first reverse pass and reused afterwards."""
         sim = self.sim
+        K = self.K_run
+        b = self._bufs
+        if b is not None and b["key"] == self._key(sim) and len(b["slots"]) >= K:
+            return b
         dim = int(self.p["dim"])
-        nid = max(self.nid, 1)
+        keep = []
         lam = F.FsAdjoint()
-        self._lam_keep = []
-        # buffers only: fs_adjoint_seed fills them
-        for d in range(3):
-            vv = torch.empty(nid, dtype=sim.real, device=self.device)
-            lam.v[d] = vv.data_ptr()
-            self._lam_keep.append(vv)
-            if d < dim:
-                xv = torch.empty(nid, dtype=sim.real, device=self.device)
-                lam.x[d] = xv.data_ptr()
-                self._lam_keep.append(xv)
-            else:
-                lam.x[d] = None
-        lam.nid = nid
-        self.lB = torch.empty(3, int(sim.L.ncent), dtype=torch.float64, device=self.device)
-        self.lE = torch.empty(6, int(sim.L.nnode), dtype=torch.float64, device=self.device)
-        lam.lB, lam.lE = self.lB.data_ptr(), self.lE.data_ptr()
-        self.lam = lam
+        for k in range(self.nsp):
+            cap = int(sim.L.capacity[k])
+            lam.capacity[k] = cap
+            for buf in range(2):
+                for d in range(3):
+                    vv = torch.empty(cap, dtype=sim.real, device=self.device)
+                    lam.v[k][buf][d] = vv.data_ptr()
+                    keep.append(vv)
+                    if d < dim:
+                        xv = torch.empty(cap, dtype=sim.real, device=self.device)
+                        lam.x[k][buf][d] = xv.data_ptr()
+                        keep.append(xv)
+        lB = torch.empty(3, int(sim.L.ncent), dtype=torch.float64, device=self.device)
+        lE = torch.empty(6, int(sim.L.nnode), dtype=torch.float64, device=self.device)
+        lam.lB, lam.lE = lB.data_ptr(), lE.data_ptr()
+        recs, dsts = [], []
+        for _ in range(K):
+            rec = F.FsRecord()
+            for k in range(self.nsp):
+                cap = int(sim.L.capacity[k])
+                t = torch.empty(cap, dtype=torch.int32, device=self.device)
+                rec.dst[k], rec.capacity[k] = t.data_ptr(), cap
+                dsts.append(t)
+            recs.append(rec)
+        slots = [_State(sim, self.nsp, copy=False) for _ in range(K)]
+        nbytes = _lambda_bytes(sim, self.nsp, dim) + K * _state_bytes(sim, self.nsp)
+        self._bufs = dict(key=self._key(sim), lam=lam, keep=keep, lB=lB, lE=lE, recs=recs, dsts=dsts, slots=slots,
+                          bytes=nbytes, scratch=None)
+        return self._bufs
+
+    def _scratch(self, bufs):
+        """Id-indexed scratch of the relayout between a checkpoint and its
+        re-run ((dim + 3) reals per id), grown when a run hands out more ids."""
+        need = (int(self.p["dim"]) + 3) * self.nid
+        if bufs["scratch"] is None or bufs["scratch"].numel() < need:
+            bufs["scratch"] = torch.empty(need + need // 8, dtype=self.sim.real, device=self.device)
+        return bufs["scratch"]
 
     def backward(self) -> np.ndarray:
         """Gradient [dL/du_sh, dL/dalpha_cr, dL/dA_1 .. dL/dA_M] of the last
         forward pass."""
         sim = self.sim
         lib, stream = sim.lib, sim.stream
-        self._alloc_lambda()
+        bufs = self._buffers()
+        lam = bufs["lam"]
+        lam.cur = 0
+        self.lB, self.lE = bufs["lB"], bufs["lE"]
         grads = torch.empty(2 + int(self.p["n_modes"]), dtype=torch.float64, device=self.device)
         gptr = C.c_void_p(grads.data_ptr())
-        # zero every adjoint and seed lB = dL/dB at the final state
-        sim._check(lib.fs_adjoint_seed(sim.h, C.byref(sim.f), C.byref(self.lam), gptr, stream))
+        # zero the particle adjoints, lE and grads; seed lB = dL/dB at the final state
+        sim._check(lib.fs_adjoint_seed(sim.h, C.byref(sim.f), C.byref(lam), gptr, stream))
         K = self.K_run
-        refl = [torch.empty(self.lam.nid, dtype=torch.uint8, device=self.device) for _ in range(K)]   # cleared by each recorded step
-        slots = [_State(sim, self.nsp, copy=False) for _ in range(K)]
+        slots, recs = bufs["slots"], bufs["recs"]
+        scratch = self._scratch(bufs)
+        later = None     # checkpoint that started the segment walked back last
         for s0 in sorted(self.checkpoints, reverse=True):
             s1 = min(s0 + K, self.nsteps)
             ck = self.checkpoints[s0]
             sim.set_clock(ck.next_id)
-            tape, recs = [ck], []
+            tape = [ck]
             for j, n in enumerate(range(s0, s1)):
-                rec = F.FsRecord()
-                rec.refl, rec.nid = refl[j].data_ptr(), self.lam.nid
-                _recorded_step(sim, n, tape[j], slots[j], rec)
+                _recorded_step(sim, n, tape[j], slots[j], recs[j])
                 tape.append(slots[j])
-                recs.append(rec)
+            if later is not None:
+                # the adjoints of state s1 sit in the slots of its checkpoint;
+                # the re-run placed the same ions elsewhere
+                rc = lib.fs_adjoint_relayout(sim.h, later.particles(sim), tape[-1].particles(sim), C.byref(lam),
+                                             C.c_void_p(scratch.data_ptr()), int(self.nid), stream)
+                sim._check(rc)
+            later = ck
             for j in range(s1 - s0 - 1, -1, -1):
                 a, b = tape[j], tape[j + 1]
                 f_n, f_n1 = a.fields(sim), b.fields(sim)
                 rc = lib.fs_adjoint_step(sim.h, a.particles(sim), C.byref(f_n), b.particles(sim), C.byref(f_n1),
-                                         C.byref(recs[j]), s0 + j, C.byref(self.lam), gptr, stream)
+                                         C.byref(recs[j]), s0 + j, C.byref(lam), gptr, stream)
                 sim._check(rc)
             if s0 == 0:
                 a = tape[0]
                 f0 = a.fields(sim)
-                rc = lib.fs_adjoint_init(sim.h, a.particles(sim), C.byref(f0), C.byref(self.lam), gptr, stream)
+                rc = lib.fs_adjoint_init(sim.h, a.particles(sim), C.byref(f0), C.byref(lam), gptr, stream)
                 sim._check(rc)
-            del tape, recs
+            del tape
         torch.cuda.synchronize(self.device)
         return grads.cpu().numpy()
 

@@ -12,23 +12,25 @@
 // lam(Bbar^{n+1}) and the particle adjoints lam(x^{n+1}), lam(v^{n+1/2}):
 //   final Ohm^T -> SSP-RK3^T (stages recomputed) -> fluid^T -> deposit^T ->
 //   injection^T -> (FS kick^T) -> move^T -> Boris^T -> gather^T.
-// Particle adjoints are stored in the particle precision and indexed by
-// particle id (ids are unique and never reused, so the adjoint of an ion
-// keeps its place whatever bin slot the ion occupies; an ion removed by a
-// step simply has zero adjoint from then on).  Grid adjoints are FP64.  The
-// push pass accumulates per tile in LDS (FP64 atomics) and flushes once per
-// node.
+// Particle adjoints are stored in the particle precision and laid out like
+// the particle buffers, one entry per bin slot, in two buffers: a reverse
+// step reads the adjoints after the step at the slots the recorded step put
+// each ion in and writes those before it at the ion's slot in the state
+// before, so every particle pass streams its arrays in the same order as
+// the particle state (an ion removed by the step gets zero).  Grid adjoints
+// are FP64.  The push pass accumulates per tile in LDS (FP64 atomics) and
+// flushes once per node.
 #pragma once
 #include "fs_field.h"
 
 namespace fsk {
 
-// Planar particle adjoints indexed by particle id: x[d] (d < D, per cell
-// of position) and v[3], nid entries each.
+// Planar particle adjoints of one species in one buffer, one entry per bin
+// slot of that species' particle buffers: x[d] (d < D, per cell of
+// position) and v[3].
 template <typename R> struct PLam {
     R* x[3];
     R* v[3];
-    int64_t nid;
 };
 
 // Real shape weights in FP64 and their derivatives d/d(offset).
@@ -160,17 +162,55 @@ __device__ __forceinline__ TileShare tile_share(const int32_t* cnt, int ntiles, 
     return t;
 }
 
+// u_sh adjoint of one ion injected during the step (reading of the
+// injection: thermal v_x = |u_sh + sigma n1| entering at x = v_x U0 dt/dx;
+// CRs with |w| = cr_w, mu = a + (1 - a) sqrt(U2), a = u2 / |w|, entering at
+// x = nx - |v_x| U0 dt/dx), from its adjoints lx (x) and lv after the step.
+__device__ __forceinline__ double inject_vjp(const Geo& G, uint64_t step, uint64_t id, bool cr, double lx,
+                                             const double lv[3]) {
+    const double dtdx = G.dt / G.dx;
+    double U[4];
+    if (!cr) {
+        double V[4], n1, n2;
+        draw4(G.seed, kStreamInjectTh, step, id, 0, U);
+        draw4(G.seed, kStreamInjectTh, step, id, 1, V);
+        box_muller(V[0], V[1], n1, n2);
+        const double vx = G.u_sh + G.sigma * n1;
+        const double sg = vx >= 0.0 ? 1.0 : -1.0;
+        const double xi = fabs(vx) * U[0] * dtdx;
+        return lv[0] * sg + (xi < (double)G.nx ? lx * sg * U[0] * dtdx : 0.0);
+    }
+    draw4(G.seed, kStreamInjectCr, step, id, 0, U);
+    const double a = G.u2 / G.cr_w, su = sqrt(U[2]);
+    const double mu = a + (1.0 - a) * su;
+    const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    const double phi = kTwoPi * U[3];
+    const double vx = G.u2 - G.cr_w * mu;
+    const double dmu = (1.0 - su) / G.cr_w;
+    const double dvx = 1.0 - G.cr_w * dmu;
+    const double dst = st > 0.0 ? -mu / st * dmu : 0.0;
+    const double sg = vx >= 0.0 ? 1.0 : -1.0;
+    const double xi = (double)G.nx - fabs(vx) * U[0] * dtdx;
+    const double dxi = xi < (double)G.nx ? -sg * dvx * U[0] * dtdx : 0.0;
+    return (lv[0] * dvx + lv[1] * G.cr_w * cos(phi) * dst + lv[2] * G.cr_w * sin(phi) * dst + lx * dxi) * G.rinv;
+}
+
 // Deposit transpose over the live particles of one buffer (the state at
 // n+1): lam(x) += sum_nodes dW/dx (lam_R + lam_G . v), lam(v) += sum W lam_G,
-// added to the adjoints of the ions' ids.
+// added to the adjoints at the ions' bin slots.  The ions the step injected
+// (ids id0 .. id0 + ninj - 1, thermal first, nth of them) then have their
+// final adjoint, which goes into dL/du_sh through their injection.
 template <typename R, int D, int S>
 __global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
-                                                     const double* __restrict__ lM, PLam<R> lam, int split) {
+                                                     const double* __restrict__ lM, PLam<R> lam, int split,
+                                                     uint64_t step, int64_t id0, int64_t nth, int64_t ninj,
+                                                     double* grads) {
     constexpr int N = Stencil<S>::N;
     constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
     const TileShare ts = tile_share(cnt, G.ntiles, cap, split);
     const int tile = ts.tile;
     const int lo = cnt[tile];
+    double acc = 0.0;
     for (int i = ts.begin + threadIdx.x; i < ts.end; i += blockDim.x) {
         const long src = bin_slot(tile, cap, lo, i);
         const int32_t pc = in.cell[src];
@@ -204,57 +244,61 @@ __global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const in
 #pragma unroll
                     for (int d = 0; d < 3; ++d) gv[d] += W * m[1 + d];
                 }
-        const int64_t id = in.id[src];
-        if (id >= lam.nid) continue;
+        R nx0 = 0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) lam.x[d][id] = (R)((double)lam.x[d][id] + gx[d]);
+        for (int d = 0; d < D; ++d) {
+            const R t = (R)((double)lam.x[d][src] + gx[d]);
+            lam.x[d][src] = t;
+            if (d == 0) nx0 = t;
+        }
+        double lv[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) lam.v[d][id] = (R)((double)lam.v[d][id] + gv[d]);
+        for (int d = 0; d < 3; ++d) {
+            const R t = (R)((double)lam.v[d][src] + gv[d]);
+            lam.v[d][src] = t;
+            lv[d] = (double)t;
+        }
+        const int64_t g = (int64_t)in.id[src] - id0;
+        if (g >= 0 && g < ninj) acc += inject_vjp(G, step, (uint64_t)(id0 + g), g >= nth, (double)nx0, lv);
+    }
+    block_add(acc, grads);
+}
+
+// Relayout of particle adjoints between two bin layouts of the same ions,
+// matched by id through an id-indexed scratch (ncomp planar arrays of nid):
+// k_lam_scatter writes the adjoints of every live ion of `from` at its id,
+// k_lam_gather reads them back at the live slots of `to`.  The scratch is
+// zeroed first, so an id `from` lacks reads zero; ids >= nid are skipped.
+template <typename R>
+__global__ __launch_bounds__(256) void k_lam_scatter(Geo G, const uint32_t* __restrict__ id, const int32_t* __restrict__ cnt,
+                                                     int64_t cap, PLam<R> lam, int D, R* __restrict__ scratch,
+                                                     int64_t nid) {
+    const int tile = blockIdx.x;
+    const int lo = cnt[tile];
+    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const long src = bin_slot(tile, cap, lo, i);
+        const int64_t q = id[src];
+        if (q >= nid) continue;
+        for (int d = 0; d < D; ++d) scratch[d * nid + q] = lam.x[d][src];
+        for (int c = 0; c < 3; ++c) scratch[(D + c) * nid + q] = lam.v[c][src];
     }
 }
 
-// u_sh adjoint of the ions injected during the step (reading of the
-// injection: thermal v_x = |u_sh + sigma n1| entering at x = v_x U0 dt/dx;
-// CRs with |w| = cr_w, mu = a + (1 - a) sqrt(U2), a = u2 / |w|, entering at
-// x = nx - |v_x| U0 dt/dx).  The step's ids are id0 + g, thermal first.
 template <typename R>
-__global__ __launch_bounds__(256) void k_inject_adj(Geo G, PLam<R> lam, uint64_t step, int64_t id0, int64_t nth,
-                                                    int64_t ncr, double* grads) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double acc = 0.0;
-    const int64_t id = id0 + g;
-    if (g < nth + ncr && id < lam.nid) {
-        const bool cr = g >= nth;
-        const double dtdx = G.dt / G.dx;
-        const double lx = (double)lam.x[0][id];
-        const double lv[3] = {(double)lam.v[0][id], (double)lam.v[1][id], (double)lam.v[2][id]};
-        double U[4];
-        if (!cr) {
-            double V[4], n1, n2;
-            draw4(G.seed, kStreamInjectTh, step, (uint64_t)id, 0, U);
-            draw4(G.seed, kStreamInjectTh, step, (uint64_t)id, 1, V);
-            box_muller(V[0], V[1], n1, n2);
-            const double vx = G.u_sh + G.sigma * n1;
-            const double sg = vx >= 0.0 ? 1.0 : -1.0;
-            const double xi = fabs(vx) * U[0] * dtdx;
-            acc = lv[0] * sg + (xi < (double)G.nx ? lx * sg * U[0] * dtdx : 0.0);
-        } else {
-            draw4(G.seed, kStreamInjectCr, step, (uint64_t)id, 0, U);
-            const double a = G.u2 / G.cr_w, su = sqrt(U[2]);
-            const double mu = a + (1.0 - a) * su;
-            const double st = sqrt(fmax(0.0, 1.0 - mu * mu));
-            const double phi = kTwoPi * U[3];
-            const double vx = G.u2 - G.cr_w * mu;
-            const double dmu = (1.0 - su) / G.cr_w;
-            const double dvx = 1.0 - G.cr_w * dmu;
-            const double dst = st > 0.0 ? -mu / st * dmu : 0.0;
-            const double sg = vx >= 0.0 ? 1.0 : -1.0;
-            const double xi = (double)G.nx - fabs(vx) * U[0] * dtdx;
-            const double dxi = xi < (double)G.nx ? -sg * dvx * U[0] * dtdx : 0.0;
-            acc = (lv[0] * dvx + lv[1] * G.cr_w * cos(phi) * dst + lv[2] * G.cr_w * sin(phi) * dst + lx * dxi) * G.rinv;
-        }
+__global__ __launch_bounds__(256) void k_lam_gather(Geo G, const uint32_t* __restrict__ id, const int32_t* __restrict__ cnt,
+                                                    int64_t cap, PLam<R> lam, int D, const R* __restrict__ scratch,
+                                                    int64_t nid) {
+    const int tile = blockIdx.x;
+    const int lo = cnt[tile];
+    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const long dst = bin_slot(tile, cap, lo, i);
+        const int64_t q = id[dst];
+        const bool ok = q < nid;
+        for (int d = 0; d < D; ++d) lam.x[d][dst] = ok ? scratch[d * nid + q] : (R)0;
+        for (int c = 0; c < 3; ++c) lam.v[c][dst] = ok ? scratch[(D + c) * nid + q] : (R)0;
     }
-    block_add(acc, grads);
 }
 
 // u_sh adjoint of the initial load (v_x = u_sh + sigma n1 for every thermal ion).
@@ -265,25 +309,23 @@ __global__ __launch_bounds__(256) void k_init_adj(Geo G, PBuf<R> in, const int32
     const int lo = cnt[tile];
     const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int64_t id = in.id[bin_slot(tile, cap, lo, i)];
-        if (id < lam.nid) acc += (double)lam.v[0][id];
-    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)lam.v[0][bin_slot(tile, cap, lo, i)];
     block_add(acc, grads);
 }
 
 // Push transpose over the live particles of the state at n: recompute the
 // gather, Boris and move as the forward step did, undo the FS kick for the
 // ions the step recorded as reflected, then the move, Boris and the gather.
-// The adjoint of each ion is read and written in place (it holds the value
-// after the step on entry and before it on exit); an ion the step removed
-// has a zero adjoint and contributes nothing.  lam(E^n), lam(Bbar^n) (6
-// planar FP64 arrays of nnode) accumulate per tile in LDS.
+// Each ion reads its adjoint after the step from post, at the bin slot the
+// step's record gives (dst >= 0 kept, -2 - slot reflected, -1 removed), and
+// writes its adjoint before the step into pre at its own slot, zero for an
+// ion the step removed.  lam(E^n), lam(Bbar^n) (6 planar FP64 arrays of
+// nnode) accumulate per tile in LDS.
 template <typename R, int D, int S>
 __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
-                                                  const R* __restrict__ gather, const uint8_t* __restrict__ refl_of,
-                                                  PLam<R> lam, double* __restrict__ lEB, long nnode, uint64_t step,
-                                                  double* grads, int split, int mirror) {
+                                                  const R* __restrict__ gather, const int32_t* __restrict__ dst_of,
+                                                  PLam<R> post, PLam<R> pre, double* __restrict__ lEB, long nnode,
+                                                  uint64_t step, double* grads, int split, int mirror) {
     using X = Extent<D, S>;
     using T = TileShape<D>;
     constexpr int LO = Stencil<S>::LO, N = Stencil<S>::N;
@@ -304,17 +346,26 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
     double acc = 0.0;
     for (int i = ts.begin + threadIdx.x; i < ts.end; i += blockDim.x) {
         const long src = bin_slot(tile, cap, lo, i);
-        const int64_t id = in.id[src];
-        if (id >= lam.nid) continue;
-        // adjoint of the ion after the step
-        double lx[3] = {0, 0, 0}, lv[3];
+        // adjoint of the ion after the step, where the step put it
+        const int32_t dr = dst_of[src];
+        const bool refl = dr <= -2;
+        const long slot = refl ? (long)(-2 - dr) : (long)dr;
+        double lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
         bool any = false;
+        if (dr != -1) {
 #pragma unroll
-        for (int d = 0; d < D; ++d) { lx[d] = (double)lam.x[d][id]; any |= lx[d] != 0.0; }
+            for (int d = 0; d < D; ++d) { lx[d] = (double)post.x[d][slot]; any |= lx[d] != 0.0; }
 #pragma unroll
-        for (int d = 0; d < 3; ++d) { lv[d] = (double)lam.v[d][id]; any |= lv[d] != 0.0; }
-        if (!any) continue;   // removed by the step (or no influence): stays zero
-        const bool refl = refl_of[id] != 0;
+            for (int d = 0; d < 3; ++d) { lv[d] = (double)post.v[d][slot]; any |= lv[d] != 0.0; }
+        }
+        if (!any) {   // removed by the step (or no influence): zero before it too
+#pragma unroll
+            for (int d = 0; d < D; ++d) pre.x[d][src] = (R)0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) pre.v[d][src] = (R)0;
+            continue;
+        }
+        const uint32_t id = in.id[src];
         const int32_t pc = in.cell[src];
         const int cx = cell_x(pc, G), cy = D >= 2 ? cell_y(pc, G) : 0, cz = D >= 3 ? cell_z(pc, G) : 0;
         R o[3] = {0, 0, 0}, v[3];
@@ -358,7 +409,7 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
             const double delta = (double)(ncx - G.nx) + (double)ox;
             const double vp[3] = {(double)v1[0], (double)v1[1], (double)v1[2]};
             double lxpre, lvpre[3], lu2;
-            kick_vjp(G.seed, step, (uint32_t)id, G.u2, (double)G.nx, vp, delta, lx[0], lv, lxpre, lvpre, lu2);
+            kick_vjp(G.seed, step, id, G.u2, (double)G.nx, vp, delta, lx[0], lv, lxpre, lvpre, lu2);
             acc += lu2 * G.rinv;
             lx[0] = lxpre;
 #pragma unroll
@@ -407,9 +458,9 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
                     atomicAdd(&sl[5 * X::GN + l], W * lB[2]);
                 }
 #pragma unroll
-        for (int d = 0; d < D; ++d) lam.x[d][id] = (R)lx[d];
+        for (int d = 0; d < D; ++d) pre.x[d][src] = (R)lx[d];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) lam.v[d][id] = (R)lv0[d];
+        for (int d = 0; d < 3; ++d) pre.v[d][src] = (R)lv0[d];
     }
     __syncthreads();
     for (int l = threadIdx.x; l < X::GN; l += blockDim.x) {
@@ -439,19 +490,22 @@ __device__ __forceinline__ long centre_index(const FieldGeo& F, int i, int j, in
     return i + (long)F.nx * (j + (long)F.nyc * k);
 }
 
-// Transpose of Ohm's law at every node: (lam_E, lam_Bbar) -> lam_B (centres,
-// added atomically) and lam of the fluid arrays (n_e, p_e, Gx, Gy, Gz at the
-// nodes, added).  fl is the forward fluid state the E was computed from.
+// Transpose of Ohm's law, first pass, one thread per node: (lam_E,
+// lam_Bbar) at the node -> the adjoints of its fluid state (n_e and Gamma of
+// the node, added; p_e of its neighbours, added atomically, several nodes
+// share one near a box end), of u_sh through the inflow node, and
+// ob = (lam_Bbar, lam_J) of the node (6 planar arrays of nnode) for the
+// centre pass.  fl is the forward fluid state the E was computed from.
 template <int D>
-__global__ __launch_bounds__(256) void k_ohm_adj(FieldGeo F, const double* __restrict__ B, const double* __restrict__ fl,
-                                                 const double* __restrict__ lE, const double* __restrict__ lBb,
-                                                 double* __restrict__ lB, double* __restrict__ lfl, double* grads,
-                                                 long nnode, long ncent) {
-    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_ohm_adj_node(FieldGeo F, const double* __restrict__ B,
+                                                      const double* __restrict__ fl, const double* __restrict__ lE,
+                                                      const double* __restrict__ lBb, double* __restrict__ ob,
+                                                      double* __restrict__ lfl, double* grads, long nnode, long ncent) {
+    const int n = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (n >= nnode) return;
-    const int i = (int)(n % F.nxn);
-    const long rest = n / F.nxn;
-    const int j = (int)(rest % F.nyc), k = (int)(rest / F.nyc);
+    const int i = n % F.nxn;
+    const int rest = n / F.nxn;
+    const int j = rest % F.nyc, k = rest / F.nyc;
     constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
     double C[2][NB][NC][3];
 #pragma unroll
@@ -564,28 +618,66 @@ __global__ __launch_bounds__(256) void k_ohm_adj(FieldGeo F, const double* __res
         unsafeAtomicAdd(lpe + nzp, -lnum[2] * h2);
         unsafeAtomicAdd(lpe + nzm, lnum[2] * h2);
     }
-    // J and Bbar back to the centres
-    double ldBx[3] = {0, 0, 0}, ldBy[3] = {0, 0, 0}, ldBz[3] = {0, 0, 0};
-    ldBy[2] += lJ[0]; ldBz[1] -= lJ[0];
-    ldBz[0] += lJ[1]; ldBx[2] -= lJ[1];
-    ldBx[1] += lJ[2]; ldBy[0] -= lJ[2];
+    // lam(Bbar) and lam(J) for the centres around the node
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ob[(long)d * nnode + n] = lbb[d];
+        ob[(long)(3 + d) * nnode + n] = lJ[d];
+    }
+}
+
+// Transpose of Ohm's law, second pass, one thread per centre: lam_B += the
+// Bbar average and J differences of the 2^D nodes around the centre,
+// transposed, from their (lam_Bbar, lam_J) in ob.  In the box the centre
+// next to the wall also takes the wall ghost's share of node nx (the ghost
+// holds a copy of it); the inflow ghost (a constant B0) takes none.
+template <int D>
+__global__ __launch_bounds__(256) void k_ohm_adj_centre(FieldGeo F, const double* __restrict__ ob,
+                                                        double* __restrict__ lB, long nnode, long ncent) {
+    const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (q >= ncent) return;
+    constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
+    const int I = q % F.nx, rest = q / F.nx;
+    const int J = rest % F.nyc, K = rest / F.nyc;
+    const double wbb = 1.0 / (double)(2 * NB * NC);
+    const double wx = (1.0 / (double)(NB * NC)) * F.rdx, wy = (1.0 / (double)(2 * NC)) * F.rdx, wz = 0.25 * F.rdx;
+    double acc[3] = {0.0, 0.0, 0.0};
+    // the node whose centre (i-1+a, j-1+b, k-1+c) this is: (I+1-a, J+1-b, K+1-c)
+    auto add = [&](int ni, int a, int b, int c) {
+        const int nj = D >= 2 ? wrapi(J + 1 - b, F.nyc) : 0, nk = D >= 3 ? wrapi(K + 1 - c, F.nzc) : 0;
+        if (F.xbc == 1) ni = wrapi(ni, F.nx);
+        const long n = lin(ni, nj, nk, F.nxn, F.nyc);
+        double lbb[3], lJ[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            lbb[d] = ob[(long)d * nnode + n];
+            lJ[d] = ob[(long)(3 + d) * nnode + n];
+        }
+        // J = (dBy_z - dBz_y, dBz_x - dBx_z, dBx_y - dBy_x)
+        const double ldBx[3] = {0.0, lJ[2], -lJ[1]};
+        const double ldBy[3] = {-lJ[2], 0.0, lJ[0]};
+        const double ldBz[3] = {lJ[1], -lJ[0], 0.0};
+        const double sa = a == 1 ? 1.0 : -1.0, sb = b == 1 ? 1.0 : -1.0, sc = c == 1 ? 1.0 : -1.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            double v = lbb[d] * wbb;
+            v += sa * ldBx[d] * wx;
+            if (D >= 2) v += sb * ldBy[d] * wy;
+            if (D >= 3) v += sc * ldBz[d] * wz;
+            acc[d] += v;
+        }
+    };
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                const long q = centre_index(F, i - 1 + a, D >= 2 ? j - 1 + b : 0, D >= 3 ? k - 1 + c : 0);
-                if (q < 0) continue;
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    double s = lbb[d] * (1.0 / (double)(2 * NB * NC));
-                    s += (a == 1 ? 1.0 : -1.0) * ldBx[d] * (1.0 / (double)(NB * NC)) * F.rdx;
-                    if (D >= 2) s += (b == 1 ? 1.0 : -1.0) * ldBy[d] * (1.0 / (double)(2 * NC)) * F.rdx;
-                    if (D >= 3) s += (c == 1 ? 1.0 : -1.0) * ldBz[d] * 0.25 * F.rdx;
-                    unsafeAtomicAdd(lB + (long)d * ncent + q, s);
-                }
+                add(I + 1 - a, a, b, c);
+                if (F.xbc == 0 && I == F.nx - 1 && a == 0) add(F.nx, 1, b, c);   // the wall ghost at nx
             }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lB[(long)d * ncent + q] += acc[d];
 }
 
 // Transpose of F(B) = -curl E (nodes -> centres): lam_E at every node
@@ -633,12 +725,16 @@ __global__ __launch_bounds__(256) void k_faraday_adj(FieldGeo F, const double* _
 __global__ __launch_bounds__(256) void k_fluid_adj(FieldGeo F, const double* __restrict__ m0, const double* __restrict__ m1,
                                                    const double* __restrict__ lfl, double* __restrict__ lM0,
                                                    double* __restrict__ lM1, long nnode, double dwcr, double* grads) {
-    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     double acc = 0.0;
     if (n < nnode) {
-        int i = (int)(n % F.nxn);
-        const long rest = n / F.nxn;
+        const int i0 = n % F.nxn, rest = n / F.nxn;
+        int i = i0;
+        // nodes near a box end share the deposit entry of the nearest fully
+        // covered node; only those entries take more than one contribution
+        bool shared = false;
         if (F.xbc == 0) {
+            shared = i0 <= F.mclamp || i0 >= F.nx - F.mclamp;
             if (i < F.mclamp) i = F.mclamp;
             if (i > F.nx - F.mclamp) i = F.nx - F.mclamp;
         }
@@ -649,13 +745,17 @@ __global__ __launch_bounds__(256) void k_fluid_adj(FieldGeo F, const double* __r
         if (dens > F.n_floor)
             ld = lfl[n] + lfl[nnode + n] * 0.5 * F.beta_e * F.gamma_e * pow(dens, F.gamma_e - 1.0);
         const double lg[3] = {lfl[2 * nnode + n], lfl[3 * nnode + n], lfl[4 * nnode + n]};
-        unsafeAtomicAdd(lM0 + 4 * dn, F.wth * ld);
+        auto put = [&](double* a, double v) {
+            if (shared) unsafeAtomicAdd(a, v);
+            else *a = v;
+        };
+        put(lM0 + 4 * dn, F.wth * ld);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) unsafeAtomicAdd(lM0 + 4 * dn + 1 + d, F.wth * lg[d]);
+        for (int d = 0; d < 3; ++d) put(lM0 + 4 * dn + 1 + d, F.wth * lg[d]);
         if (F.has_cr) {
-            unsafeAtomicAdd(lM1 + 4 * dn, F.wcr * ld);
+            put(lM1 + 4 * dn, F.wcr * ld);
 #pragma unroll
-            for (int d = 0; d < 3; ++d) unsafeAtomicAdd(lM1 + 4 * dn + 1 + d, F.wcr * lg[d]);
+            for (int d = 0; d < 3; ++d) put(lM1 + 4 * dn + 1 + d, F.wcr * lg[d]);
             acc = dwcr * (m1[4 * dn] * ld + m1[4 * dn + 1] * lg[0] + m1[4 * dn + 2] * lg[1] + m1[4 * dn + 3] * lg[2]);
         }
     }
@@ -696,12 +796,13 @@ __global__ void k_rk_adj1(double* __restrict__ l0, double* __restrict__ lF, cons
 }
 
 // Amplitude adjoints of the initial modes: dB_y = A cos(k_m x + phi_m),
-// dB_z = A sin(k_m x + phi_m) at every centre, one block per mode.
+// dB_z = A sin(k_m x + phi_m) at every centre; blockIdx.y is the mode, the
+// blocks along x share its centres.
 __global__ __launch_bounds__(256) void k_amps_adj(FieldGeo F, const double* __restrict__ lB, const double* __restrict__ phase,
                                                   double Lx, long ncent, double* grads) {
-    const int m = blockIdx.x + 1;
+    const int m = blockIdx.y + 1;
     double acc = 0.0;
-    for (long q = threadIdx.x; q < ncent; q += blockDim.x) {
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < ncent; q += (long)gridDim.x * blockDim.x) {
         const int i = (int)(q % F.nx);
         const double x = ((double)i + 0.5) * F.dx;
         const double ph = kTwoPi * (double)m * x / Lx + phase[m];

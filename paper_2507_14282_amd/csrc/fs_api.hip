@@ -51,6 +51,7 @@ struct fs_handle {
     double* al[4] = {nullptr, nullptr, nullptr, nullptr};  // RK3 stage adjoints l0, l1, l2, lF
     double* aBs = nullptr;                  // B at the start of each RK substep
     double* alE = nullptr;                  // curl transpose output at the nodes
+    double* aob = nullptr;                  // Ohm transpose: lam(Bbar), lam(J) per node
     std::string err;
     // phase timing: pool of event pairs recorded on the caller's stream
     bool timing = false;
@@ -455,7 +456,7 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
                 allow_lds(kern, lds_push);
                 kern<<<(unsigned)h->L.ntiles, PUSH_THREADS, lds_push, s>>>(
                     G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, static_cast<const R*>(f->gather),
-                    mom, h->xl[k], h->ctr, policy_of(h, k), k);
+                    mom, h->xl[k], h->ctr, policy_of(h, k), k, rec ? rec->dst[k] : nullptr);
             };
             const bool rel = h->cfg.c_light > 0.0;
             if (dep && h->cfg.coupling == 2)
@@ -472,7 +473,7 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
                 PBuf<R> out = sections<R>(P.buf[P.cur ^ 1], P.capacity, D);
                 unsigned gw = std::min<unsigned>(grid_for(h->xl[k].cap), 1024u);
                 auto* mom = reinterpret_cast<unsigned long long*>(f->mom[k]);
-                uint8_t* rd = rec ? rec->refl : nullptr;
+                int32_t* rd = rec ? rec->dst[k] : nullptr;
                 const WallModel wm = wall_model_at(h, step);
                 if (dep)
                     k_wall<R, D, S, true><<<gw, 256, 0, s>>>(G, h->xl[k], out, P.tile_count[P.cur ^ 1], P.tile_cap, mom,
@@ -606,13 +607,13 @@ void stage_launch(fs_handle* h, const double* Bin, const double* Bn, double* Bou
     }
 }
 
-template <typename R> PLam<R> plam(const fs_adjoint* a, int D) {
+// Particle adjoints of species k in buffer b.
+template <typename R> PLam<R> plam(const fs_adjoint* a, int k, int b, int D) {
     PLam<R> L;
     for (int d = 0; d < 3; ++d) {
-        L.x[d] = d < D ? static_cast<R*>(a->x[d]) : nullptr;
-        L.v[d] = static_cast<R*>(a->v[d]);
+        L.x[d] = d < D ? static_cast<R*>(a->x[k][b][d]) : nullptr;
+        L.v[d] = static_cast<R*>(a->v[k][b][d]);
     }
-    L.nid = a->nid;
     return L;
 }
 
@@ -634,12 +635,22 @@ void fluid_of(fs_handle* h, const fs_particles* sp, int64_t* const* mom, hipStre
                                h->L.nnode, nullptr, nullptr, nullptr, 0);
 }
 
+// Transpose of Ohm's law at every node (see k_ohm_adj_node): per node pass,
+// then the gather of lam(Bbar) and lam(J) into lam_B at the centres.
+template <int D>
+void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb, double* lB, double* grads,
+             hipStream_t s) {
+    const long nn = h->L.nnode, nc = h->L.ncent;
+    k_ohm_adj_node<D><<<grid_for(nn), 256, 0, s>>>(h->F, B, h->afl, lE, lBb, h->aob, h->alfl, grads, nn, nc);
+    k_ohm_adj_centre<D><<<grid_for(nc), 256, 0, s>>>(h->F, h->aob, lB, nn, nc);
+}
+
 // lam_B += (dF/dB)^T lF and lam_fl += (dF/dfl)^T lF for F(B) = -curl Ohm(B, fl).
 template <int D>
 void rhs_adj(fs_handle* h, const double* B, const double* lF, double* lB, double* grads, hipStream_t s) {
     const long nn = h->L.nnode, nc = h->L.ncent;
     k_faraday_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, lF, h->alE, nn, nc);
-    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, B, h->afl, h->alE, nullptr, lB, h->alfl, grads, nn, nc);
+    ohm_adj<D>(h, B, h->alE, nullptr, lB, grads, s);
 }
 
 // Transpose of the SSP-RK3 field update from B^n with the fluid state in
@@ -677,9 +688,12 @@ template <int D> void rk3_adj(fs_handle* h, const double* Bn, double* lB, double
 }
 
 // Fluid and deposit transposes: lam of the fluid state in h->alfl -> the
-// particle adjoints of the state whose moments are in h->amom.
+// particle adjoints (buffer lam->cur) of the state whose moments are in
+// h->amom; then the injection transpose of the ions a step injected (ids
+// id0 .. id0 + nth + ncr - 1, none when ncr + nth = 0).
 template <typename R, int D, int S>
-void moments_adj(fs_handle* h, const fs_particles* sp, const fs_adjoint* lam, double* grads, hipStream_t s) {
+void moments_adj(fs_handle* h, const fs_particles* sp, const fs_adjoint* lam, double* grads, hipStream_t s,
+                 uint64_t step = 0, int64_t id0 = 0, int64_t nth = 0, int64_t ncr = 0) {
     const long nn = h->L.nnode;
     for (int k = 0; k < 2; ++k) zero_u64(reinterpret_cast<unsigned long long*>(h->alM[k]), 4 * h->L.ndep, s);
     const double dwcr = h->has_cr ? h->cfg.n_cr / (double)h->cfg.ppc_cr : 0.0;
@@ -689,8 +703,9 @@ void moments_adj(fs_handle* h, const fs_particles* sp, const fs_adjoint* lam, do
         const fs_particles& P = sp[k];
         PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
         const int sp_ = split_of(P.tile_cap);
-        k_deposit_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
-                                                                             h->alM[k], plam<R>(lam, D), sp_);
+        k_deposit_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
+            h->G, in, P.tile_count[P.cur], P.tile_cap, h->alM[k], plam<R>(lam, k, lam->cur, D), sp_, step, id0, nth,
+            nth + ncr, grads);
     }
 }
 
@@ -703,28 +718,28 @@ int adjoint_step_impl(fs_handle* h, const fs_particles* sp_n, const fs_fields* f
     fluid_of<R, D, S>(h, sp_n1, f_n1->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
     // final Ohm, then the RK3 update
-    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, f_n1->B, h->afl, lam->lE, lam->lE + 3 * nn, lam->lB, h->alfl, grads,
-                                              nn, nc);
+    ohm_adj<D>(h, f_n1->B, lam->lE, lam->lE + 3 * nn, lam->lB, grads, s);
     rk3_adj<D>(h, f_n->B, lam->lB, grads, s);
-    // fluid and deposit at n+1, into the particle adjoints after the step
-    moments_adj<R, D, S>(h, sp_n1, lam, grads, s);
-    // ions injected by the step
+    // fluid and deposit at n+1, into the particle adjoints after the step,
+    // then the ions injected by the step
     int64_t cth = 0, ccr = 0;
     inject_counts(h->cfg, step, cth, ccr);
     const int64_t ntr = h->L.nyc * h->L.nzc, nth = cth * ntr, ncr = ccr * ntr;
-    if (nth + ncr > 0)
-        k_inject_adj<R><<<grid_for(nth + ncr), 256, 0, s>>>(h->G, plam<R>(lam, D), (uint64_t)step, rec->id0, nth, ncr,
-                                                           grads);
-    // push, wall and gather of the ions that lived before the step
+    moments_adj<R, D, S>(h, sp_n1, lam, grads, s, (uint64_t)step, rec->id0, nth, ncr);
+    // push, wall and gather of the ions that lived before the step: buffer
+    // cur (slots after the step) -> cur ^ 1 (slots before it)
     zero_u64(reinterpret_cast<unsigned long long*>(lam->lE), 6 * nn, s);
+    const int post = lam->cur, pre = lam->cur ^ 1;
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         const fs_particles& P = sp_n[k];
         PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
         const int sp_ = split_of(P.tile_cap);
         k_push_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
-            h->G, in, P.tile_count[P.cur], P.tile_cap, static_cast<const R*>(f_n->gather), rec->refl, plam<R>(lam, D),
-            lam->lE, nn, (uint64_t)step, grads, sp_, policy_of(h, k) == FS_WALL_SPECULAR ? 1 : 0);
+            h->G, in, P.tile_count[P.cur], P.tile_cap, static_cast<const R*>(f_n->gather), rec->dst[k],
+            plam<R>(lam, k, post, D), plam<R>(lam, k, pre, D), lam->lE, nn, (uint64_t)step, grads, sp_,
+            policy_of(h, k) == FS_WALL_SPECULAR ? 1 : 0);
     }
+    lam->cur = pre;
     return hip_check(h, hipGetLastError(), "adjoint step launch");
 }
 
@@ -734,17 +749,18 @@ int adjoint_init_impl(fs_handle* h, const fs_particles* sp0, const fs_fields* f0
     const long nn = h->L.nnode, nc = h->L.ncent;
     fluid_of<R, D, S>(h, sp0, f0->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
-    k_ohm_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, f0->B, h->afl, lam->lE, lam->lE + 3 * nn, lam->lB, h->alfl, grads,
-                                              nn, nc);
+    ohm_adj<D>(h, f0->B, lam->lE, lam->lE + 3 * nn, lam->lB, grads, s);
     moments_adj<R, D, S>(h, sp0, lam, grads, s);
     const fs_particles& P = sp0[0];
     PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
-    k_init_adj<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap, plam<R>(lam, D),
-                                                        grads);
+    k_init_adj<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
+                                                        plam<R>(lam, 0, lam->cur, D), grads);
     const fs_config& c = h->cfg;
     if (c.n_modes > 0) {
         k_phases<<<grid_for(c.n_modes), 256, 0, s>>>(c.seed, c.n_modes, h->phase);
-        k_amps_adj<<<(unsigned)c.n_modes, 256, 0, s>>>(h->F, lam->lB, h->phase, (double)c.nx * c.dx, nc, grads);
+        const int parts = (int)std::min<int64_t>(64, std::max<int64_t>(1, nc / 4096));
+        k_amps_adj<<<dim3((unsigned)parts, (unsigned)c.n_modes), 256, 0, s>>>(h->F, lam->lB, h->phase,
+                                                                           (double)c.nx * c.dx, nc, grads);
     }
     return hip_check(h, hipGetLastError(), "adjoint init launch");
 }
@@ -873,12 +889,13 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
         for (int k = 0; k < 4 && ok; ++k) ok = ok && dmalloc((void**)&h->al[k], 3 * nc * sizeof(double));
         ok = ok && dmalloc((void**)&h->aBs, (size_t)c.n_sub * 3 * nc * sizeof(double));
         ok = ok && dmalloc((void**)&h->alE, 3 * nn * sizeof(double));
+        ok = ok && dmalloc((void**)&h->aob, 6 * nn * sizeof(double));
     }
     // crosser lists: a generous bound on the ions that can reach the wall in one step
     for (int k = 0; k < 2 && ok; ++k) {
         int64_t ppc = k == 0 ? c.ppc : c.ppc_cr;
         int64_t cap = (k == 1 && !h->has_cr) ? 64 : h->L.nyc * h->L.nzc * std::max<int64_t>(ppc, 1) * 8 + 4096;
-        size_t bytes = 256 + 3 * round_up(cap * 8, 256) + round_up(3 * cap * 8, 256) + 3 * round_up(cap * 4, 256);
+        size_t bytes = 256 + 3 * round_up(cap * 8, 256) + round_up(3 * cap * 8, 256) + 4 * round_up(cap * 4, 256);
         ok = dmalloc(&h->xl_mem[k], bytes);
         if (!ok) break;
         char* p = static_cast<char*>(h->xl_mem[k]);
@@ -891,7 +908,8 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
         x.v = reinterpret_cast<double*>(p); p += round_up(3 * cap * 8, 256);
         x.id = reinterpret_cast<uint32_t*>(p); p += round_up(cap * 4, 256);
         x.cy = reinterpret_cast<int32_t*>(p); p += round_up(cap * 4, 256);
-        x.cz = reinterpret_cast<int32_t*>(p);
+        x.cz = reinterpret_cast<int32_t*>(p); p += round_up(cap * 4, 256);
+        x.src = reinterpret_cast<int32_t*>(p);
     }
     if (!ok) {
         fs_destroy(h);
@@ -914,7 +932,7 @@ void fs_destroy(fs_handle* h) {
     hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->fluid2); hipFree(h->nprev); hipFree(h->gprev); hipFree(h->phase); hipFree(h->part); hipFree(h->spec);
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
     for (int k = 0; k < 2; ++k) { hipFree(h->amom[k]); hipFree(h->alM[k]); }
-    hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->alE);
+    hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->alE); hipFree(h->aob);
     for (int k = 0; k < 4; ++k) hipFree(h->al[k]);
     delete h;
 }
@@ -978,33 +996,43 @@ int fs_step(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t
     return step_common(h, sp, f, step, flags, st, s, nullptr);
 }
 
-int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec, fs_step_stats* st,
-                   hipStream_t s) {
-    if (!h || !rec || !rec->refl) return fail(h, FS_EINVAL, "NULL argument");
-    if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "a recorded step needs deposit_mode 1");
-    int64_t cth = 0, ccr = 0;
-    inject_counts(h->cfg, step, cth, ccr);
-    const int64_t ninj = (cth + ccr) * h->L.nyc * h->L.nzc;
-    if (h->next_id + ninj > rec->nid) return fail(h, FS_ECAPACITY, "record smaller than the ids the step hands out");
-    if (rec->nid > 0) k_fill_u8<<<std::min<unsigned>(grid_for(rec->nid), 4096u), 256, 0, s>>>(rec->refl, 0, rec->nid);
-    int rc = hip_check(h, hipGetLastError(), "record clear");
-    if (rc) return rc;
-    rec->id0 = h->next_id;
-    return step_common(h, sp, f, step, FS_ALL, st, s, rec);
-}
-
 static int check_adjoint(fs_handle* h, const fs_adjoint* lam) {
     if (!lam || !lam->lB || !lam->lE) return fail(h, FS_EINVAL, "NULL adjoint array");
-    for (int d = 0; d < 3; ++d)
-        if ((d < h->cfg.dim && !lam->x[d]) || !lam->v[d]) return fail(h, FS_EINVAL, "NULL particle adjoint array");
-    if (lam->nid < h->next_id) return fail(h, FS_ECAPACITY, "particle adjoint arrays smaller than the id range");
+    if (lam->cur != 0 && lam->cur != 1) return fail(h, FS_EINVAL, "adjoint buffer index outside {0, 1}");
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        for (int b = 0; b < 2; ++b)
+            for (int d = 0; d < 3; ++d)
+                if ((d < h->cfg.dim && !lam->x[k][b][d]) || !lam->v[k][b][d])
+                    return fail(h, FS_EINVAL, "NULL particle adjoint array");
+        if (lam->capacity[k] < h->L.capacity[k])
+            return fail(h, FS_ECAPACITY, "particle adjoint arrays smaller than the particle buffers");
+    }
     return FS_OK;
+}
+
+static int check_record(fs_handle* h, const fs_record* rec) {
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        if (!rec->dst[k]) return fail(h, FS_EINVAL, "NULL record array");
+        if (rec->capacity[k] < h->L.capacity[k]) return fail(h, FS_ECAPACITY, "record smaller than the particle buffers");
+        if (h->L.capacity[k] > (int64_t)INT32_MAX - 2)
+            return fail(h, FS_ECAPACITY, "particle buffers too large for the int32 step record");
+    }
+    return FS_OK;
+}
+
+int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec, fs_step_stats* st,
+                   hipStream_t s) {
+    if (!h || !rec) return fail(h, FS_EINVAL, "NULL argument");
+    if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "a recorded step needs deposit_mode 1");
+    if (int rc = check_record(h, rec)) return rc;
+    rec->id0 = h->next_id;
+    return step_common(h, sp, f, step, FS_ALL, st, s, rec);
 }
 
 int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n, const fs_particles* sp_n1,
                     const fs_fields* f_n1, const fs_record* rec, int64_t step, fs_adjoint* lam, double* grads,
                     hipStream_t s) {
-    if (!h || !sp_n || !f_n || !sp_n1 || !f_n1 || !rec || !rec->refl || !lam || !grads)
+    if (!h || !sp_n || !f_n || !sp_n1 || !f_n1 || !rec || !lam || !grads)
         return fail(h, FS_EINVAL, "NULL argument");
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
     if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
@@ -1013,11 +1041,8 @@ int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n
     if (h->cfg.smooth != 0) return fail(h, FS_EINVAL, "the adjoint covers the unfiltered moments only");
     if (!f_n->B || !f_n->gather || !f_n1->B) return fail(h, FS_EINVAL, "NULL field array");
     if (step < 0) return fail(h, FS_EINVAL, "negative step");
-    int64_t cth = 0, ccr = 0;
-    inject_counts(h->cfg, step, cth, ccr);
-    if (rec->id0 + (cth + ccr) * h->L.nyc * h->L.nzc > lam->nid || rec->nid > lam->nid)
-        return fail(h, FS_ECAPACITY, "particle adjoint arrays smaller than the id range");
-    int rc = check_adjoint(h, lam);
+    int rc = check_record(h, rec);
+    if (!rc) rc = check_adjoint(h, lam);
     if (!rc) rc = check_particles(h, sp_n);
     if (!rc) rc = check_particles(h, sp_n1);
     if (rc) return rc;
@@ -1025,6 +1050,42 @@ int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n
         FS_DISPATCH(h, (adjoint_step_impl<R, D, S>(h, sp_n, f_n, sp_n1, f_n1, rec, step, lam, grads, s)));
     };
     return run();
+}
+
+int fs_adjoint_relayout(fs_handle* h, const fs_particles* from, const fs_particles* to, fs_adjoint* lam, void* scratch,
+                        int64_t nid, hipStream_t s) {
+    if (!h || !from || !to || !lam || !scratch) return fail(h, FS_EINVAL, "NULL argument");
+    if (nid < 0) return fail(h, FS_EINVAL, "negative id range");
+    int rc = check_adjoint(h, lam);
+    if (!rc) rc = check_particles(h, from);
+    if (!rc) rc = check_particles(h, to);
+    if (rc) return rc;
+    const int D = h->cfg.dim, rb = h->cfg.precision == 64 ? 8 : 4;
+    const int a = lam->cur, b = lam->cur ^ 1;
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        if (rb == 8) zero_u64(scratch, (int64_t)(D + 3) * nid, s);
+        else zero_i32(static_cast<int32_t*>(scratch), (int64_t)(D + 3) * nid, s);
+        const fs_particles& F = from[k];
+        const fs_particles& T = to[k];
+        const unsigned nt = (unsigned)h->L.ntiles;
+        if (rb == 8) {
+            PBuf<double> pf = sections<double>(F.buf[F.cur], F.capacity, D);
+            PBuf<double> pt = sections<double>(T.buf[T.cur], T.capacity, D);
+            k_lam_scatter<double><<<nt, 256, 0, s>>>(h->G, pf.id, F.tile_count[F.cur], F.tile_cap,
+                                                     plam<double>(lam, k, a, D), D, static_cast<double*>(scratch), nid);
+            k_lam_gather<double><<<nt, 256, 0, s>>>(h->G, pt.id, T.tile_count[T.cur], T.tile_cap,
+                                                    plam<double>(lam, k, b, D), D, static_cast<double*>(scratch), nid);
+        } else {
+            PBuf<float> pf = sections<float>(F.buf[F.cur], F.capacity, D);
+            PBuf<float> pt = sections<float>(T.buf[T.cur], T.capacity, D);
+            k_lam_scatter<float><<<nt, 256, 0, s>>>(h->G, pf.id, F.tile_count[F.cur], F.tile_cap,
+                                                    plam<float>(lam, k, a, D), D, static_cast<float*>(scratch), nid);
+            k_lam_gather<float><<<nt, 256, 0, s>>>(h->G, pt.id, T.tile_count[T.cur], T.tile_cap,
+                                                   plam<float>(lam, k, b, D), D, static_cast<float*>(scratch), nid);
+        }
+    }
+    lam->cur = b;
+    return hip_check(h, hipGetLastError(), "adjoint relayout launch");
 }
 
 int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, fs_adjoint* lam, double* grads,
@@ -1609,14 +1670,15 @@ int fs_adjoint_seed(fs_handle* h, const fs_fields* f, fs_adjoint* lam, double* g
     int rc = check_adjoint(h, lam);
     if (rc) return rc;
     const int rb = h->cfg.precision == 64 ? 8 : 4;
-    for (int d = 0; d < 3; ++d) {
-        void* arr[2] = {d < h->cfg.dim ? lam->x[d] : nullptr, lam->v[d]};
-        for (void* a : arr) {
-            if (!a) continue;
-            if (rb == 8) zero_u64(a, lam->nid, s);
-            else zero_i32(static_cast<int32_t*>(a), lam->nid, s);
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k)
+        for (int d = 0; d < 3; ++d) {
+            void* arr[2] = {d < h->cfg.dim ? lam->x[k][lam->cur][d] : nullptr, lam->v[k][lam->cur][d]};
+            for (void* a : arr) {
+                if (!a) continue;
+                if (rb == 8) zero_u64(a, h->L.capacity[k], s);
+                else zero_i32(static_cast<int32_t*>(a), h->L.capacity[k], s);
+            }
         }
-    }
     zero_u64(lam->lE, 6 * h->L.nnode, s);
     zero_u64(grads, 2 + (int64_t)h->cfg.n_modes, s);
     k_loss_seed<<<grid_for(h->L.ncent), 256, 0, s>>>(h->F, f->B, h->L.ncent, lam->lB);

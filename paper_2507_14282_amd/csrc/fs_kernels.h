@@ -48,6 +48,7 @@ struct XList {
     double* oy;
     double* oz;
     double* v;                    // 3 planar arrays of cap
+    int32_t* src;                 // bin slot the crosser came from (for a step's record)
     int32_t* count;
     int64_t cap;
 };
@@ -368,7 +369,7 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
                                               int32_t* __restrict__ cnt_out, int64_t cap,
                                               const R* __restrict__ gather, unsigned long long* __restrict__ mom,
                                               XList xl, unsigned long long* __restrict__ ctr, int policy,
-                                              int species) {
+                                              int species, int32_t* __restrict__ rec_dst) {
     using X = Extent<D, S>;
     using T = TileShape<D>;
     using L = PushLds<R, D, S>;
@@ -497,10 +498,12 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
         const int wzc = D >= 3 ? wrapi(nc[2], G.nzc) : 0;
         if (!valid) kind = 4;
 
+        const long src = valid ? bin_slot(tile, cap, lo_in, i) : 0;
         if (kind == 1) {
             int slot = atomicAdd(xl.count, 1);
             if (slot < xl.cap) {
                 xl.id[slot] = cur.id;
+                xl.src[slot] = (int32_t)src;
                 xl.delta[slot] = (double)(nc[0] - G.nx) + (double)o[0];
                 xl.cy[slot] = wyc;
                 xl.cz[slot] = wzc;
@@ -551,6 +554,8 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
             }
         }
         if (kind == 0 && !stay) dst = bin_push_top(cnt_out, G.ntiles, dest, cap);
+        // step record: where each ion went (the wall fills in its reflections)
+        if (rec_dst != nullptr && valid) rec_dst[src] = (kind == 0 && dst >= 0) ? (int32_t)dst : -1;
         if (kind == 0) {
             if (dst >= 0) {
                 out.cell[dst] = pack_cell(wxc, wyc, wzc, G);
@@ -595,7 +600,7 @@ __global__ void k_check_bins(const int32_t* counts, int ntiles, int64_t cap, uns
 template <typename R, int D, int S, bool DEP>
 __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int32_t* cnt_out, int64_t cap,
                                               unsigned long long* mom, unsigned long long* ctr,
-                                              int policy, int species, uint64_t step, uint8_t* refl_rec,
+                                              int policy, int species, uint64_t step, int32_t* rec_dst,
                                               WallModel wm) {
     int ncross = *xl.count;
     if (ncross > xl.cap) ncross = (int)xl.cap;
@@ -641,7 +646,7 @@ __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int3
 #pragma unroll
         for (int c = 0; c < 3; ++c) out.v[c][dst] = vr[c];
         out.id[dst] = pid;
-        if (refl_rec != nullptr) refl_rec[pid] = 1;   // step record: this ion was reflected
+        if (rec_dst != nullptr) rec_dst[xl.src[i]] = (int32_t)(-2 - dst);   // step record: reflected into dst
         if constexpr (DEP) status |= deposit_particle<R, D, S>(nullptr, 0, 0, 0, mom, G, cx, cy, cz, o, vr, oor);
     }
     wave_add(ctr + C_INC, n_inc);

@@ -94,12 +94,12 @@ class FsStats(C.Structure):
 
 
 class FsRecord(C.Structure):
-    _fields_ = [("refl", C.c_void_p), ("nid", C.c_int64), ("id0", C.c_int64)]
+    _fields_ = [("dst", C.c_void_p * 2), ("capacity", C.c_int64 * 2), ("id0", C.c_int64)]
 
 
 class FsAdjoint(C.Structure):
-    _fields_ = [("x", C.c_void_p * 3), ("v", C.c_void_p * 3), ("nid", C.c_int64), ("lB", C.c_void_p),
-                ("lE", C.c_void_p)]
+    _fields_ = [("x", (C.c_void_p * 3) * 2 * 2), ("v", (C.c_void_p * 3) * 2 * 2), ("capacity", C.c_int64 * 2),
+                ("cur", C.c_int32), ("pad", C.c_int32), ("lB", C.c_void_p), ("lE", C.c_void_p)]
 
 
 DEPOSIT_MODE = {"fixed": 0, "continuous": 1, 0: 0, 1: 1}
@@ -146,6 +146,7 @@ def library():
         L.fs_step_record.argtypes = [vp, P, F, i64, R, C.POINTER(FsStats), vp]
         L.fs_adjoint_step.argtypes = [vp, P, F, P, F, R, i64, A, vp, vp]
         L.fs_adjoint_init.argtypes = [vp, P, F, A, vp, vp]
+        L.fs_adjoint_relayout.argtypes = [vp, P, P, A, vp, i64, vp]
         L.fs_precursor_loss.argtypes = [vp, F, vp, vp]
         L.fs_adjoint_seed.argtypes = [vp, F, A, vp, vp]
         _lib = L
@@ -159,7 +160,7 @@ def exported_symbols():
             "fs_load_particles", "fs_read_particles", "fs_set_clock", "fs_next_id", "fs_diagnostics",
             "fs_phase_space", "fs_bperp_spectrum", "fs_checkpoint_bytes", "fs_checkpoint", "fs_restore",
             "fs_timing_enable", "fs_timing_read", "fs_step_record", "fs_adjoint_step", "fs_adjoint_init",
-            "fs_precursor_loss", "fs_adjoint_seed", "fs_bperp_spectrum_noalloc"]
+            "fs_precursor_loss", "fs_adjoint_seed", "fs_bperp_spectrum_noalloc", "fs_adjoint_relayout"]
 
 
 def make_config(p: dict) -> FsConfig:

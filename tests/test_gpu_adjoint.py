@@ -121,8 +121,9 @@ def test_adjoint_entry_points_reject_fixed_point_mode():
 
 def test_precursor_loss_and_seed_through_the_c_abi():
     """fs_precursor_loss against the oracle's loss of the same B (and bit for
-    bit on a second call); fs_adjoint_seed zeroes every adjoint it is given,
-    whatever they held, and sets lB = dL/dB."""
+    bit on a second call); fs_adjoint_seed zeroes buffer cur of every particle
+    adjoint of both species, whatever it held, leaves the other buffer alone,
+    and sets lB = dL/dB."""
     import ctypes as C
     import torch
     from paper_2507_14282_amd import fshybrid as F
@@ -144,21 +145,22 @@ def test_precursor_loss_and_seed_through_the_c_abi():
     assert got[0] == got[1]
     assert abs(got[0] - want) <= 1e-13 * abs(want), (got[0], want)
 
-    nid = sim.next_id + 8
     dev = "cuda:0"
     lam = F.FsAdjoint()
-    keep = []
-    for d in range(3):
-        vv = torch.full((nid,), float("nan"), dtype=torch.float32, device=dev)
-        lam.v[d] = vv.data_ptr()
-        keep.append(vv)
-        if d < 2:
-            xv = torch.full((nid,), float("nan"), dtype=torch.float32, device=dev)
-            lam.x[d] = xv.data_ptr()
-            keep.append(xv)
-        else:
-            lam.x[d] = None
-    lam.nid = nid
+    lam.cur = 1
+    seeded, other = [], []
+    for k in range(2):
+        cap = int(sim.L.capacity[k])
+        lam.capacity[k] = cap
+        for b in range(2):
+            for d in range(3):
+                for arr, n in ((lam.v, 3), (lam.x, 2)):
+                    if d >= n:
+                        arr[k][b][d] = None
+                        continue
+                    t = torch.full((cap,), float("nan"), dtype=torch.float32, device=dev)
+                    arr[k][b][d] = t.data_ptr()
+                    (seeded if b == 1 else other).append(t)
     lB = torch.full((3, int(sim.L.ncent)), float("nan"), dtype=torch.float64, device=dev)
     lE = torch.full((6, int(sim.L.nnode)), float("nan"), dtype=torch.float64, device=dev)
     lam.lB, lam.lE = lB.data_ptr(), lE.data_ptr()
@@ -166,16 +168,96 @@ def test_precursor_loss_and_seed_through_the_c_abi():
     sim._check(sim.lib.fs_adjoint_seed(sim.h, C.byref(sim.f), C.byref(lam), C.c_void_p(grads.data_ptr()),
                                        sim.stream))
     torch.cuda.synchronize()
-    for t in keep + [lE, grads]:
+    for t in seeded + [lE, grads]:
         assert torch.all(t == 0).item()
+    for t in other:
+        assert torch.all(torch.isnan(t)).item()
     nx = p["nx"]
     i = np.arange(int(sim.L.ncent)) % nx
     want_lB = np.zeros((3, int(sim.L.ncent)))
     want_lB[1:, i >= nx // 2] = 2.0 * B[i >= nx // 2, 1:].T
     np.testing.assert_array_equal(lB.cpu().numpy(), want_lB)
-    # an adjoint state too small for the ids handed out is refused
-    lam.nid = sim.next_id - 1
+    # an adjoint state smaller than a species' particle buffers is refused,
+    # and so is a buffer index outside {0, 1}
+    lam.capacity[1] = int(sim.L.capacity[1]) - 1
     with pytest.raises(F.FsError) as e:
         sim._check(sim.lib.fs_adjoint_seed(sim.h, C.byref(sim.f), C.byref(lam), C.c_void_p(grads.data_ptr()),
                                            sim.stream))
     assert e.value.code == F.FS_ECAPACITY
+    lam.capacity[1] = int(sim.L.capacity[1])
+    lam.cur = 2
+    with pytest.raises(F.FsError) as e:
+        sim._check(sim.lib.fs_adjoint_seed(sim.h, C.byref(sim.f), C.byref(lam), C.c_void_p(grads.data_ptr()),
+                                           sim.stream))
+    assert e.value.code == F.FS_EINVAL
+
+
+def _live_slots(counts, ntiles, cap):
+    """Bin slots holding an ion: [t cap, t cap + lo) and the top hi slots of each tile."""
+    lo, hi = counts[:ntiles], counts[ntiles:]
+    out = []
+    for t in range(ntiles):
+        base = t * cap
+        out.append(np.arange(base, base + lo[t]))
+        out.append(np.arange(base + cap - hi[t], base + cap))
+    return np.concatenate(out).astype(np.int64)
+
+
+@pytest.mark.parametrize("dim,wall", [(1, "faux_shock"), (2, "faux_shock"), (2, "specular")])
+def test_step_record_maps_every_ion_to_where_the_step_put_it(dim, wall):
+    """fs_step_record writes, at every live input slot, the output slot of
+    that ion (its id is found there), -2 - slot for the ions the wall
+    reflected and -1 for the removed ones; the mapped slots are distinct and,
+    with the injected ions, cover every live output slot.  The counts match
+    the step's reflected / removed counters (four recorded steps in a row)."""
+    import torch
+    from paper_2507_14282_amd import fshybrid as F
+    kw = dict(nx=48, dx=0.5, ppc=8) if dim == 1 else dict(nx=24, ny=8, dx=0.5, ppc=8)
+    p = W.params(dim=dim, ppc_cr=4, n_cr=0.05, wall_th=wall, wall_cr="faux_shock", u_sh=19.3, dt=0.0047,
+                 precision=64, deposit_mode="continuous", seed=23, **kw)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    for s in range(30):
+        sim.step(s)
+    nsp = 2
+    total_refl = 0
+    for step in range(30, 34):
+        pre = []
+        for k in range(nsp):
+            sec = sim.sections(k)
+            cap, ntiles = sec["tile_cap"], int(sim.L.ntiles)
+            live = _live_slots(sec["counts"].cpu().numpy(), ntiles, cap)
+            pre.append((live, sec["id"].cpu().numpy()[live]))
+        rec = F.FsRecord()
+        dst = []
+        for k in range(nsp):
+            t = torch.full((int(sim.L.capacity[k]),), -7, dtype=torch.int32, device="cuda:0")
+            rec.dst[k], rec.capacity[k] = t.data_ptr(), int(sim.L.capacity[k])
+            dst.append(t)
+        id0 = sim.next_id
+        st = sim.step_record(step, rec, stats=True)
+        assert rec.id0 == id0
+        nrefl = nrem = 0
+        for k in range(nsp):
+            sec = sim.sections(k)
+            cap, ntiles = sec["tile_cap"], int(sim.L.ntiles)
+            live_post = _live_slots(sec["counts"].cpu().numpy(), ntiles, cap)
+            post_id = sec["id"].cpu().numpy()
+            live_pre, ids_pre = pre[k]
+            d = dst[k].cpu().numpy()[live_pre].astype(np.int64)
+            assert np.all(d != -7)
+            kept = d >= 0
+            refl = d <= -2
+            slot = np.where(refl, -2 - d, d)
+            moved = kept | refl
+            assert np.all(slot[moved] < len(post_id))
+            assert np.array_equal(post_id[slot[moved]], ids_pre[moved])
+            assert len(np.unique(slot[moved])) == moved.sum()
+            assert np.all(np.isin(slot[moved], live_post))
+            rest = np.setdiff1d(live_post, slot[moved])
+            assert np.all(post_id[rest].astype(np.int64) >= id0)       # only the injected ions are new
+            nrefl += refl.sum()
+            nrem += (d == -1).sum()
+        assert nrefl == st["reflected"] and nrem == st["transmitted"] + st["escaped"] + st["open_removed"], st
+        total_refl += nrefl
+    assert total_refl > 0
