@@ -344,7 +344,6 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
     k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(f->mom[0]),
                                reinterpret_cast<const long long*>(h->has_cr ? f->mom[1] : f->mom[0]), h->fluid, nn,
                                h->fluid2, h->nprev, h->gprev, tc);
-    const double* fl_ohm = tc == 2 ? h->fluid2 : h->fluid;
     if (h->cfg.smooth > 0) {
         // passes ping-pong between the two buffers; the finish writes the
         // other one, which then becomes h->fluid
@@ -358,6 +357,9 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
         k_smooth_finish<<<gn, blk, 0, s>>>(h->F, a, b, nn);
         if (b != h->fluid) std::swap(h->fluid, h->fluid2);
     }
+    // taken after the filter, which may have swapped the buffers (the
+    // time-centred coupling, which uses fluid2, runs without it)
+    const double* fl_ohm = tc == 2 ? h->fluid2 : h->fluid;
     const double hs = h->cfg.dt / (double)h->cfg.n_sub;
     if constexpr (D == 3) {
         // z-marching kernels: 32 x 8 columns over runs of at most 32 z planes
