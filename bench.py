@@ -248,22 +248,21 @@ def atomics_from_profiles(kernel_hash):
     return {k: v["per_dispatch"] for k, v in d["counters"].items()}
 
 
-def adjoint_timing(steps=400, K=20):
-    """Forward and checkpointed reverse pass of the 1D adjoint workload
-    (2048 cells, dx = 0.5, 256 ppc plus CRs, 64 seeded Fourier modes, FP32
-    particles): wall time of each pass, and their ratio (the reverse pass
-    includes re-running every K-step segment from its checkpoint)."""
+def adjoint_timing(preset="cfg5", steps=400, K=20, **overrides):
+    """Forward and checkpointed reverse pass of an adjoint workload: wall
+    time of each pass and their ratio (the reverse pass includes re-running
+    every K-step segment from its checkpoint), in steady state: the run's
+    first forward and reverse pass allocate its checkpoints, tape, records
+    and adjoint buffers, the second one is timed."""
     import numpy as np
     import torch
     from paper_2507_14282_amd import adjoint as A
     from paper_2507_14282_amd import workloads as W
-    p = W.preset("cfg5")
+    p = W.preset(preset, **overrides)
     amps = np.full(p["n_modes"], p["mode_amp"])
-    warm = A.AdjointRun(p, K, K=K)
-    warm.forward(p["u_sh"], p["alpha_cr"], amps)
-    warm.backward()
-    del warm
     run = A.AdjointRun(p, steps, K=K)
+    run.forward(p["u_sh"], p["alpha_cr"], amps)
+    run.backward()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     loss = run.forward(p["u_sh"], p["alpha_cr"], amps)
@@ -272,11 +271,12 @@ def adjoint_timing(steps=400, K=20):
     g = run.backward()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    return {
-        "workload": f"1D3V adjoint box {p['nx']} cells dx={p['dx']} d_i, {p['ppc']} ppc + CRs "
+    ny = f"x{p['ny']}" if p["dim"] >= 2 else ""
+    out = {
+        "workload": f"{p['dim']}D3V adjoint box {p['nx']}{ny} cells dx={p['dx']} d_i, {p['ppc']} ppc + CRs "
                     f"(n_cr={p['n_cr']}), {p['n_modes']} Fourier modes, {steps} steps, checkpoint every {run.K_run}",
         "loss": "precursor sum(By^2+Bz^2) over x in [L/2, L]",
-        "params": "u_sh, alpha_cr, 64 amplitudes",
+        "params": f"u_sh, alpha_cr, {p['n_modes']} amplitudes",
         "dtype": "f32 particles / f64 fields",
         "fwd_ms_per_step": (t1 - t0) / steps * 1e3,
         "adj_ms_per_step": (t2 - t1) / steps * 1e3,
@@ -284,6 +284,15 @@ def adjoint_timing(steps=400, K=20):
         "loss_value": loss,
         "grad_u_sh": float(g[0]), "grad_alpha_cr": float(g[1]), "grad_amps_norm": float(np.linalg.norm(g[2:])),
     }
+    if "cap_factor_cr" in overrides:
+        out["cr_bins"] = (f"CR bins sized at {overrides['cap_factor_cr']} x ppc_cr per cell (the CRs {steps} steps "
+                          f"inject), since the tape holds K full-capacity particle buffers")
+    return out
+
+
+# The 2D adjoint workload: the 2D faux-shock box (8192 x 512 cells, 16 ppc,
+# CRs) with 16 seeded Fourier modes, 40 steps at K = 20.
+ADJOINT_2D = dict(preset="cfg3", steps=40, K=20, n_modes=16, mode_amp=1e-3, cap_factor_cr=0.5)
 
 
 def kernel_source_hash():
@@ -391,7 +400,7 @@ def main():
     from paper_2507_14282_amd import workloads as W
 
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_timing()}))
+        print(json.dumps({"adjoint": adjoint_timing(), "adjoint_2d": adjoint_timing(**ADJOINT_2D)}))
         return 0
 
     p = W.preset(args.workload)
@@ -510,6 +519,8 @@ def main():
     if not args.no_adjoint:
         progress("adjoint workload")
         out["adjoint"] = adjoint_timing()
+        progress("2D adjoint workload")
+        out["adjoint_2d"] = adjoint_timing(**ADJOINT_2D)
     if not args.no_cpu_baseline:
         progress("oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
