@@ -409,8 +409,10 @@ typedef struct fs_adjoint {
     double* lE;
 } fs_adjoint;
 
-/* One full step (deposit_mode 1 only) that also fills *rec.  Same contract
- * as fs_step with flags = FS_ALL.  FS_EINVAL on a NULL dst of a species,
+/* One full step (deposit_mode 1, non-relativistic, first-order coupling:
+ * the step the reverse mode covers) that also fills *rec.  Same contract as
+ * fs_step with flags = FS_ALL.  FS_EINVAL on another configuration or on a
+ * NULL dst of a species,
  * FS_ECAPACITY if a dst holds fewer entries than the species' capacity or
  * the capacity does not fit the int32 encoding (above 2^31 - 3 slots). */
 int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec,

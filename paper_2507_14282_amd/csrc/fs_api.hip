@@ -461,7 +461,8 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
                     mom, h->xl[k], h->ctr, policy_of(h, k), k, rec ? rec->dst[k] : nullptr);
             };
             const bool rel = h->cfg.c_light > 0.0;
-            if (dep && h->cfg.coupling == 2)
+            if (rec) launch(k_push<R, D, S, false, false, false, true>);   // continuous deposit, non-relativistic
+            else if (dep && h->cfg.coupling == 2)
                 rel ? launch(k_push<R, D, S, true, true, true>) : launch(k_push<R, D, S, true, false, true>);
             else if (dep) rel ? launch(k_push<R, D, S, true, true>) : launch(k_push<R, D, S, true, false>);
             else rel ? launch(k_push<R, D, S, false, true>) : launch(k_push<R, D, S, false, false>);
@@ -1026,6 +1027,8 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
                    hipStream_t s) {
     if (!h || !rec) return fail(h, FS_EINVAL, "NULL argument");
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "a recorded step needs deposit_mode 1");
+    if (h->cfg.c_light != 0.0 || h->cfg.coupling != 1)
+        return fail(h, FS_EINVAL, "a recorded step covers the non-relativistic first-order step only");
     if (int rc = check_record(h, rec)) return rc;
     rec->id0 = h->next_id;
     return step_common(h, sp, f, step, FS_ALL, st, s, rec);

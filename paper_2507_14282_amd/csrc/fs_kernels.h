@@ -356,15 +356,19 @@ __device__ __forceinline__ void load_ion(const PBuf<R>& in, long src, Ion<R, D>&
 // without scratch (measured): 8 for the FP32 1D kernels (their SGPRs would
 // otherwise cap them at 7, i.e. 6 with 8-wave workgroups) and the FP32 2D CIC
 // ones (71 VGPRs otherwise); 6 for the relativistic 3D CIC FP32 one (82 VGPRs
-// and 5 waves otherwise).  The others take what their registers give.
+// and 5 waves otherwise).  The others take what their registers give (the
+// non-relativistic 3D CIC ones sit at 79-80 VGPRs, where one more register
+// costs a wave per SIMD and 15% of the time).
 template <typename R, int D, int S, bool REL> struct PushWaves {
     static constexpr int value =
         sizeof(R) != 4 ? 1 : ((D == 1 || (D == 2 && S == 1)) ? 8 : ((REL && S == 1) ? 6 : 1));
 };
 
 // TC: the time-centred coupling, density deposited at the new position and
-// flux at the midpoint of the move.
-template <typename R, int D, int S, bool DEP, bool REL, bool TC = false>
+// flux at the midpoint of the move.  REC: a recorded step (reverse mode),
+// which writes where each ion went into rec_dst and keeps each crosser's
+// source slot in the crosser list for the wall.
+template <typename R, int D, int S, bool DEP, bool REL, bool TC = false, bool REC = false>
 __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
                                               int32_t* __restrict__ cnt_out, int64_t cap,
                                               const R* __restrict__ gather, unsigned long long* __restrict__ mom,
@@ -498,12 +502,11 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
         const int wzc = D >= 3 ? wrapi(nc[2], G.nzc) : 0;
         if (!valid) kind = 4;
 
-        const long src = valid ? bin_slot(tile, cap, lo_in, i) : 0;
         if (kind == 1) {
             int slot = atomicAdd(xl.count, 1);
             if (slot < xl.cap) {
                 xl.id[slot] = cur.id;
-                xl.src[slot] = (int32_t)src;
+                if constexpr (REC) xl.src[slot] = (int32_t)bin_slot(tile, cap, lo_in, i);
                 xl.delta[slot] = (double)(nc[0] - G.nx) + (double)o[0];
                 xl.cy[slot] = wyc;
                 xl.cz[slot] = wzc;
@@ -555,7 +558,8 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
         }
         if (kind == 0 && !stay) dst = bin_push_top(cnt_out, G.ntiles, dest, cap);
         // step record: where each ion went (the wall fills in its reflections)
-        if (rec_dst != nullptr && valid) rec_dst[src] = (kind == 0 && dst >= 0) ? (int32_t)dst : -1;
+        if constexpr (REC)
+            if (valid) rec_dst[bin_slot(tile, cap, lo_in, i)] = (kind == 0 && dst >= 0) ? (int32_t)dst : -1;
         if (kind == 0) {
             if (dst >= 0) {
                 out.cell[dst] = pack_cell(wxc, wyc, wzc, G);
