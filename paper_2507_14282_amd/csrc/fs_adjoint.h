@@ -205,10 +205,26 @@ __global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const in
                                                      const double* __restrict__ lM, PLam<R> lam, int split,
                                                      uint64_t step, int64_t id0, int64_t nth, int64_t ninj,
                                                      double* grads) {
-    constexpr int N = Stencil<S>::N;
+    using X = Extent<D, S>;
+    using T = TileShape<D>;
+    constexpr int LO = Stencil<S>::LO, N = Stencil<S>::N;
     constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
+    // the moment adjoints of the tile's stencil nodes, [node][R, Gx, Gy, Gz];
+    // nodes outside the deposit grid hold zero
+    __shared__ double sm[4 * X::GN];
     const TileShare ts = tile_share(cnt, G.ntiles, cap, split);
     const int tile = ts.tile;
+    const int tx = tile % G.ntx;
+    const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
+    const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
+    const int gx0 = tx * T::X - LO, gy0 = D >= 2 ? ty * T::Y - LO : 0, gz0 = D >= 3 ? tz * T::Z - LO : 0;
+    for (int l = threadIdx.x; l < X::GN; l += blockDim.x) {
+        const int lx = l % X::GX, ly = (l / X::GX) % X::GY, lz = l / (X::GX * X::GY);
+        const long gi = dep_index(gx0 + lx, gy0 + ly, gz0 + lz, G);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sm[4 * l + q] = gi < 0 ? 0.0 : lM[4 * gi + q];
+    }
+    __syncthreads();
     const int lo = cnt[tile];
     double acc = 0.0;
     for (int i = ts.begin + threadIdx.x; i < ts.end; i += blockDim.x) {
@@ -226,16 +242,17 @@ __global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const in
         for (int d = 0; d < D; ++d) weights_dw<S>((double)in.off[d][src], rel[d], w[d], dw[d]);
         const double v[3] = {(double)in.v[0][src], (double)in.v[1][src], (double)in.v[2][src]};
         double gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
+        // a binned ion lies in its tile; the clamp only guards a corrupt state
+        const int lx0 = min(max(cx - gx0 + rel[0], 0), X::GX - N);
+        const int ly0 = D >= 2 ? min(max(cy - gy0 + rel[1], 0), X::GY - N) : 0;
+        const int lz0 = D >= 3 ? min(max(cz - gz0 + rel[2], 0), X::GZ - N) : 0;
 #pragma unroll
         for (int c = 0; c < NZ; ++c)
 #pragma unroll
             for (int b = 0; b < NY; ++b)
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
-                    const long gi = dep_index(cx + rel[0] + a, D >= 2 ? cy + rel[1] + b : 0,
-                                              D >= 3 ? cz + rel[2] + c : 0, G);
-                    if (gi < 0) continue;
-                    const double* m = lM + 4 * gi;
+                    const double* m = sm + 4 * (((lz0 + c) * X::GY + (ly0 + b)) * X::GX + (lx0 + a));
                     const double lm = m[0] + m[1] * v[0] + m[2] * v[1] + m[3] * v[2];
                     const double W = w[0][a] * w[1][b] * w[2][c];
                     gx[0] += dw[0][a] * w[1][b] * w[2][c] * lm;
@@ -331,6 +348,8 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
     constexpr int LO = Stencil<S>::LO, N = Stencil<S>::N;
     constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
     __shared__ double sl[6 * X::GN];
+    // the gather grid of the tile's stencil, as the forward push stages it
+    __shared__ Pair<R> sg[3 * X::GN];
     const TileShare ts = tile_share(cnt, G.ntiles, cap, split);
     const int tile = ts.tile;
     const int tx = tile % G.ntx;
@@ -338,6 +357,13 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
     const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
     const int gx0 = tx * T::X - LO, gy0 = D >= 2 ? ty * T::Y - LO : 0, gz0 = D >= 3 ? tz * T::Z - LO : 0;
     for (int l = threadIdx.x; l < 6 * X::GN; l += blockDim.x) sl[l] = 0.0;
+    for (int l = threadIdx.x; l < X::GN; l += blockDim.x) {
+        const int lx = l % X::GX, ly = (l / X::GX) % X::GY, lz = l / (X::GX * X::GY);
+        const R* g8 = gather + 8 * gather_index(gx0 + lx, gy0 + ly, gz0 + lz, G);
+        sg[l] = Pair<R>{g8[0], g8[1]};
+        sg[X::GN + l] = Pair<R>{g8[2], g8[4]};
+        sg[2 * X::GN + l] = Pair<R>{g8[5], g8[6]};
+    }
     __syncthreads();
     const int lo = cnt[tile];
     const R hR = (R)(0.5 * G.dt);
@@ -380,6 +406,10 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
         if constexpr (D >= 2) weights_real<R, S>(o[1], ry, wy);
         if constexpr (D >= 3) weights_real<R, S>(o[2], rz, wz);
         R E[3] = {0, 0, 0}, B[3] = {0, 0, 0};
+        // a binned ion lies in its tile; the clamps only guard a corrupt state
+        const int lx0 = min(max(cx - gx0 + rx, 0), X::GX - N);
+        const int ly0 = D >= 2 ? min(max(cy - gy0 + ry, 0), X::GY - N) : 0;
+        const int lz0 = D >= 3 ? min(max(cz - gz0 + rz, 0), X::GZ - N) : 0;
 #pragma unroll
         for (int c = 0; c < NZ; ++c)
 #pragma unroll
@@ -388,9 +418,10 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
                     const R W = wx[a] * wyz;
-                    const R* g8 = gather + 8 * gather_index(cx + rx + a, cy + ry + b, cz + rz + c, G);
-                    E[0] += W * g8[0]; E[1] += W * g8[1]; E[2] += W * g8[2];
-                    B[0] += W * g8[4]; B[1] += W * g8[5]; B[2] += W * g8[6];
+                    const int l = ((lz0 + c) * X::GY + (ly0 + b)) * X::GX + (lx0 + a);
+                    const Pair<R> p0 = sg[l], p1 = sg[X::GN + l], p2 = sg[2 * X::GN + l];
+                    E[0] += W * p0.x; E[1] += W * p0.y; E[2] += W * p1.x;
+                    B[0] += W * p1.y; B[1] += W * p2.x; B[2] += W * p2.y;
                 }
             }
         R v1[3] = {v[0], v[1], v[2]};
@@ -433,23 +464,20 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) weights_dw<S>((double)o[d], rel[d], w[d], dw[d]);
-        const int lx0 = min(max(cx - gx0 + rel[0], 0), X::GX - N);
-        const int ly0 = D >= 2 ? min(max(cy - gy0 + rel[1], 0), X::GY - N) : 0;
-        const int lz0 = D >= 3 ? min(max(cz - gz0 + rel[2], 0), X::GZ - N) : 0;
 #pragma unroll
         for (int c = 0; c < NZ; ++c)
 #pragma unroll
             for (int b = 0; b < NY; ++b)
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
-                    const R* g8 = gather + 8 * gather_index(cx + rel[0] + a, cy + rel[1] + b, cz + rel[2] + c, G);
-                    const double dot = (double)g8[0] * lE[0] + (double)g8[1] * lE[1] + (double)g8[2] * lE[2] +
-                                       (double)g8[4] * lB[0] + (double)g8[5] * lB[1] + (double)g8[6] * lB[2];
+                    const int l = ((lz0 + c) * X::GY + (ly0 + b)) * X::GX + (lx0 + a);
+                    const Pair<R> p0 = sg[l], p1 = sg[X::GN + l], p2 = sg[2 * X::GN + l];
+                    const double dot = (double)p0.x * lE[0] + (double)p0.y * lE[1] + (double)p1.x * lE[2] +
+                                       (double)p1.y * lB[0] + (double)p2.x * lB[1] + (double)p2.y * lB[2];
                     const double W = w[0][a] * w[1][b] * w[2][c];
                     lx[0] += dw[0][a] * w[1][b] * w[2][c] * dot;
                     if (D >= 2) lx[1] += w[0][a] * dw[1][b] * w[2][c] * dot;
                     if (D >= 3) lx[2] += w[0][a] * w[1][b] * dw[2][c] * dot;
-                    const int l = ((lz0 + c) * X::GY + (ly0 + b)) * X::GX + (lx0 + a);
                     atomicAdd(&sl[l], W * lE[0]);
                     atomicAdd(&sl[X::GN + l], W * lE[1]);
                     atomicAdd(&sl[2 * X::GN + l], W * lE[2]);
