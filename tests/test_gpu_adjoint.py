@@ -119,6 +119,25 @@ def test_adjoint_entry_points_reject_fixed_point_mode():
     assert e.value.code == F.FS_EINVAL
 
 
+def test_step_record_refuses_the_relativistic_push():
+    # the reverse mode covers the non-relativistic push; the time-centred
+    # coupling needs the fixed-point deposit, which fs_step_record refuses
+    import torch
+    from paper_2507_14282_amd import fshybrid as F
+    p = W.params(dim=1, nx=16, ppc=4, deposit_mode="continuous", c_light=300.0)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    rec = F.FsRecord()
+    keep = []
+    for k in range(2):
+        t = torch.zeros(max(int(sim.L.capacity[k]), 1), dtype=torch.int32, device="cuda:0")
+        rec.dst[k], rec.capacity[k] = t.data_ptr(), int(sim.L.capacity[k])
+        keep.append(t)
+    with pytest.raises(F.FsError) as e:
+        sim.step_record(0, rec)
+    assert e.value.code == F.FS_EINVAL
+
+
 def test_precursor_loss_and_seed_through_the_c_abi():
     """fs_precursor_loss against the oracle's loss of the same B (and bit for
     bit on a second call); fs_adjoint_seed zeroes buffer cur of every particle
