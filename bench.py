@@ -284,15 +284,12 @@ def adjoint_timing(preset="cfg5", steps=400, K=20, **overrides):
         "loss_value": loss,
         "grad_u_sh": float(g[0]), "grad_alpha_cr": float(g[1]), "grad_amps_norm": float(np.linalg.norm(g[2:])),
     }
-    if "cap_factor_cr" in overrides:
-        out["cr_bins"] = (f"CR bins sized at {overrides['cap_factor_cr']} x ppc_cr per cell (the CRs {steps} steps "
-                          f"inject), since the tape holds K full-capacity particle buffers")
     return out
 
 
 # The 2D adjoint workload: the 2D faux-shock box (8192 x 512 cells, 16 ppc,
 # CRs) with 16 seeded Fourier modes, 40 steps at K = 20.
-ADJOINT_2D = dict(preset="cfg3", steps=40, K=20, n_modes=16, mode_amp=1e-3, cap_factor_cr=0.5)
+ADJOINT_2D = dict(preset="cfg3", steps=40, K=20, n_modes=16, mode_amp=1e-3)
 
 
 def kernel_source_hash():

@@ -389,16 +389,34 @@ typedef struct fs_record {
     int64_t  id0;
 } fs_record;
 
+/* A particle state packed to its live ions: the reverse mode's tape, sized
+ * to the ions rather than to the bins.  Per species k (k = 1 only with CRs),
+ * buf[k] holds the sections of a particle buffer (the layout above) with
+ * n[k] entries in place of capacity, tile t's ions at [toff[k][t],
+ * toff[k][t + 1]) in the order of its bin (the bottom run, then the top run
+ * from the top down); toff[k] has ntiles + 1 entries.  dst[k] (n[k] int32)
+ * holds the record of the step that leaves this state, in packed indices of
+ * the state after it: >= 0 kept there, -2 - i reflected into i, -1 removed.
+ * *status (device int32) is set nonzero by fs_tape_pack when a species had
+ * more live ions than n[k] (those beyond are dropped).  All arrays are
+ * device memory owned by the caller. */
+typedef struct fs_packed {
+    void*    buf[2];
+    int32_t* toff[2];
+    int32_t* dst[2];
+    int64_t  n[2];
+    int32_t* status;
+} fs_packed;
+
 /* Adjoint state (device arrays owned by the caller).  Particle adjoints are
- * in the particle precision and laid out like the particle buffers, one
- * entry per bin slot: for species k and buffer b, x[k][b][d] (d < dim; dL
+ * in the particle precision and laid out like the packed states, one entry
+ * per packed index: for species k and buffer b, x[k][b][d] (d < dim; dL
  * per cell of position) and v[k][b][c], capacity[k] entries each (at least
- * the species' capacity).  Buffer cur holds the adjoints of the state a
- * reverse step starts from, in the bin slots of that state's particle
- * buffer; the step writes buffer cur ^ 1 in the slots of the state before
- * it and flips cur.  Grid adjoints are FP64 planar: lB (3 x ncent) = dL/dB
- * at the centres, lE (6 x nnode) = dL/d(Ex, Ey, Ez, Bbarx, Bbary, Bbarz) of
- * the gather grid. */
+ * the n[k] of the packed states they serve).  Buffer cur holds the adjoints
+ * of the state a reverse step starts from; the step writes buffer cur ^ 1
+ * in the packed indices of the state before it and flips cur.  Grid
+ * adjoints are FP64 planar: lB (3 x ncent) = dL/dB at the centres, lE
+ * (6 x nnode) = dL/d(Ex, Ey, Ez, Bbarx, Bbary, Bbarz) of the gather grid. */
 typedef struct fs_adjoint {
     void*   x[2][2][3];
     void*   v[2][2][3];
@@ -410,48 +428,63 @@ typedef struct fs_adjoint {
 } fs_adjoint;
 
 /* One full step (deposit_mode 1, non-relativistic, first-order coupling:
- * the step the reverse mode covers) that also fills *rec.  Same contract as
- * fs_step with flags = FS_ALL.  FS_EINVAL on another configuration or on a
- * NULL dst of a species,
- * FS_ECAPACITY if a dst holds fewer entries than the species' capacity or
- * the capacity does not fit the int32 encoding (above 2^31 - 3 slots). */
+ * the step the reverse mode covers) that also fills *rec (in bin slots, see
+ * fs_record).  Same contract as fs_step with flags = FS_ALL.  FS_EINVAL on
+ * another configuration or on a NULL dst of a species, FS_ECAPACITY if a
+ * dst holds fewer entries than the species' capacity or the capacity does
+ * not fit the int32 encoding (above 2^31 - 3 slots). */
 int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec,
                    fs_step_stats* st, hipStream_t s);
 
-/* Reverse of step `step` (n -> n+1, run by fs_step_record with record
- * *rec).  sp_n / f_n: particles (buf[cur], tile_count[cur]) and fields (B,
- * gather grid) before the step; sp_n1 / f_n1: particles, B and the moment
- * grids after it (f_n1->mom as the recorded step left them, or NULL to
- * deposit them again).
+/* Packs the live ions of sp (buf[cur], tile_count[cur]) into *out: the tile
+ * offsets, then the ions.  With prev_sp, rec and prev given, sp is the
+ * output of the recorded step *rec whose input prev_sp (as the step read it,
+ * packed earlier into *prev) left the record in bin slots; it goes into
+ * prev->dst in packed indices of *out.  Asynchronous on s; an overflow of
+ * n[k] sets *out->status (*prev->status for a record entry that points past
+ * out's n).  FS_EINVAL on a NULL argument (prev_sp, rec and prev are all
+ * given or all NULL). */
+int fs_tape_pack(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_particles* prev_sp,
+                 const fs_record* rec, fs_packed* prev, hipStream_t s);
+
+/* Reverse of step `step` (n -> n+1, recorded with fs_step_record and packed
+ * with fs_tape_pack).  pn / f_n: the packed state before the step (with the
+ * step's record in pn->dst) and its fields (B, gather grid); pn1 / f_n1: the
+ * packed state after it and its B and moment grids (f_n1->mom as the step
+ * left them).  id0: the first id the step handed out (fs_record.id0).
  * *lam holds on entry the adjoints after the step (particles in buffer cur,
- * in the slots of sp_n1; lB, lE of B^{n+1} and E^{n+1}) and on exit those
- * before it (particles in the other buffer, in the slots of sp_n, which
- * becomes cur; B^n, E^n).  Every live slot of sp_n is written, zero for an
- * ion the step removed.  grads (device, 2 + n_modes doubles) accumulates
- * dL/du_sh and dL/dalpha_cr.  FS_ECAPACITY if an adjoint buffer or dst
- * holds fewer entries than the species' capacity. */
-int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n, const fs_particles* sp_n1,
-                    const fs_fields* f_n1, const fs_record* rec, int64_t step, fs_adjoint* lam, double* grads,
+ * in the packed indices of pn1; lB, lE of B^{n+1} and E^{n+1}) and on exit
+ * those before it (particles in the other buffer, in the packed indices of
+ * pn, which becomes cur; B^n, E^n).  Every ion of pn is written, zero for
+ * one the step removed.  grads (device, 2 + n_modes doubles) accumulates
+ * dL/du_sh and dL/dalpha_cr.  FS_EINVAL on a NULL argument (f_n1->mom
+ * included), FS_ECAPACITY if an adjoint buffer is shorter than pn or pn1. */
+int fs_adjoint_step(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, const fs_packed* pn1,
+                    const fs_fields* f_n1, int64_t id0, int64_t step, fs_adjoint* lam, double* grads,
                     hipStream_t s);
 
-/* Carries the particle adjoints of buffer lam->cur from the bin slots of
- * `from` to those of `to`: two bin layouts of one state, such as the
- * checkpoint at the end of a segment of steps and the same state re-run from
- * the segment's start (the push places ions in an order that depends on the
- * timing of its atomics, so a re-run puts them in other slots).  Ions are
- * matched by id through scratch (device, (dim + 3) * nid reals of the
- * particle precision, nid above every id in both states; an id `from` does
- * not hold reads zero, ids >= nid are skipped).  Writes buffer cur ^ 1 at
- * every live slot of `to` and flips lam->cur.  FS_EINVAL on a NULL argument
- * or a negative nid, FS_ECAPACITY as fs_adjoint_step. */
-int fs_adjoint_relayout(fs_handle* h, const fs_particles* from, const fs_particles* to, fs_adjoint* lam,
-                        void* scratch, int64_t nid, hipStream_t s);
+/* Moving the particle adjoints between two packings of one state: a segment
+ * of steps re-run from its checkpoint packs its last state in another order
+ * than the checkpoint that began the later segment (the push places ions in
+ * an order set by the timing of its atomics).  fs_adjoint_park writes the
+ * adjoints of buffer lam->cur, at the packed indices of `from`, into scratch
+ * by particle id (after zeroing it); fs_adjoint_unpark reads them back into
+ * buffer lam->cur at the packed indices of `to` (zero for an id scratch does
+ * not hold).  scratch: device, (dim + 3) * nid reals of the particle
+ * precision per call, nid above every id; ids >= nid are skipped.  FS_EINVAL
+ * on a NULL argument or a negative nid, FS_ECAPACITY if an adjoint buffer
+ * is shorter than the packed state. */
+int fs_adjoint_park(fs_handle* h, const fs_packed* from, fs_adjoint* lam, void* scratch, int64_t nid,
+                    hipStream_t s);
+int fs_adjoint_unpark(fs_handle* h, const fs_packed* to, fs_adjoint* lam, const void* scratch, int64_t nid,
+                      hipStream_t s);
 
 /* Reverse of fs_init_plasma: E^0 = Ohm(B^0, moments of the initial load),
  * the initial velocities (v_x = u_sh + sigma n) and the Fourier modes of
- * B^0 (f0->mom: moments of the initial load, or NULL to deposit them).
- * Adds to dL/du_sh, dL/dalpha_cr and grads[1 + m] = dL/dA_m. */
-int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, fs_adjoint* lam, double* grads,
+ * B^0.  p0: the initial state packed, f0: its fields (f0->mom: the moments
+ * of the initial load).  Adds to dL/du_sh, dL/dalpha_cr and
+ * grads[1 + m] = dL/dA_m. */
+int fs_adjoint_init(fs_handle* h, const fs_packed* p0, const fs_fields* f0, fs_adjoint* lam, double* grads,
                     hipStream_t s);
 
 /* The loss of the reverse-mode workload: the magnetic energy of the
@@ -471,8 +504,7 @@ int fs_precursor_loss(fs_handle* h, const fs_fields* f, double* loss, hipStream_
  * capacity[k] entries each, in the particle precision), lE and grads
  * (2 + n_modes doubles, device), and sets lB = dL/dB at the final state f->B:
  * (0, 2 B_y, 2 B_z) at the centres with i >= nx/2, 0 elsewhere.  FS_EINVAL
- * on a NULL array or cur outside {0, 1}, FS_ECAPACITY if capacity[k] is
- * below the species' capacity. */
+ * on a NULL array, a negative capacity or cur outside {0, 1}. */
 int fs_adjoint_seed(fs_handle* h, const fs_fields* f, fs_adjoint* lam, double* grads, hipStream_t s);
 
 /* Phase timing with HIP events recorded on the caller's stream (benchmark

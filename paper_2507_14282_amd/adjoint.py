@@ -11,16 +11,18 @@ with every discrete decision of the forward run held fixed (pathwise, common
 random numbers).
 
 Everything numeric runs in the library (``fs_precursor_loss``,
-``fs_adjoint_seed``, ``fs_step_record``, ``fs_adjoint_step``,
-``fs_adjoint_init``); this module owns the buffers and
-the schedule: a forward pass that keeps a checkpoint every K steps, and a
-reverse pass that re-runs each K-step segment from its checkpoint with
-recording and walks it backwards.  Particle adjoints are laid out like the
-particle buffers (one entry per bin slot, two buffers that the reverse steps
-ping-pong); each recorded step keeps where it put every ion, which is all
-the reverse step needs to carry an ion's adjoint from its slot after the
-step to its slot before it.  The tape, the records and the adjoint buffers
-are allocated once and reused by every later reverse pass of the run.
+``fs_adjoint_seed``, ``fs_step_record``, ``fs_tape_pack``,
+``fs_adjoint_step``, ``fs_adjoint_park`` / ``fs_adjoint_unpark``,
+``fs_adjoint_init``); this module owns the buffers and the schedule: a
+forward pass that keeps a checkpoint every K steps, and a reverse pass that
+re-runs each K-step segment from its checkpoint with recording and walks it
+backwards.  The re-run steps between two working bin buffers; after each
+step the state is packed to its live ions into the tape (``fs_packed``),
+together with where the step put every ion.  Particle adjoints are indexed
+like the packed states, in two buffers the reverse steps ping-pong, so the
+reverse passes stream them in the order of the particles.  The tape, the
+records and the adjoint buffers are allocated once and reused by every
+later reverse pass of the run.
 """
 
 from __future__ import annotations
@@ -76,7 +78,91 @@ class _State:
         return f
 
 
-def _recorded_step(sim: F.Simulation, n: int, a: _State, b: _State, rec: F.FsRecord):
+class _Fields:
+    """The grid part of a tape state: B, E, the gather grid and the moment
+    grids (filled by the recorded step that produces the state)."""
+
+    def __init__(self, sim: F.Simulation, nsp: int):
+        self.B = torch.empty_like(sim.B)
+        self.E = torch.empty_like(sim.E)
+        self.gather = torch.empty_like(sim.gather)
+        self.mom = [torch.empty_like(m) for m in sim.mom[:nsp]]
+
+    fields = _State.fields
+
+    def bytes(self) -> int:
+        return int(sum(t.numel() * t.element_size() for t in [self.B, self.E, self.gather] + self.mom))
+
+
+class _Step:
+    """The bins of one state with the fields of another: a recorded step
+    reads the particles of one working buffer and writes the other, while
+    its fields go to the tape entry of the state it produces."""
+
+    def __init__(self, bins: _State, fields):
+        self.buf, self.cnt = bins.buf, bins.cnt
+        self.B, self.E, self.gather, self.mom = fields.B, fields.E, fields.gather, fields.mom
+
+    particles = _State.particles
+    fields = _State.fields
+
+
+def _section_bytes(n: int, dim: int, rb: int) -> int:
+    """Bytes of particle sections of n entries (cell, off[dim], v[3], id,
+    each on a 256-byte boundary, the layout of the library's buffers)."""
+    r = lambda x: (x + 255) // 256 * 256
+    return r(4 * n) + (dim + 3) * r(rb * n) + r(4 * n)
+
+
+class _Packed:
+    """One packed tape state (fs_packed): the live ions of each species, the
+    tile offsets and the record of the step that leaves the state."""
+
+    def __init__(self, sim: F.Simulation, nsp: int, n, status: torch.Tensor):
+        dim = int(sim.p["dim"])
+        rb = torch.finfo(sim.real).bits // 8
+        nt = int(sim.L.ntiles)
+        dev = sim.device
+        self.s = F.FsPacked()
+        self.keep = []
+        self.n, self.dim, self.real = [int(x) for x in n], dim, sim.real
+        for k in range(nsp):
+            buf = torch.empty(_section_bytes(int(n[k]), dim, rb), dtype=torch.uint8, device=dev)
+            toff = torch.empty(nt + 1, dtype=torch.int32, device=dev)
+            dst = torch.empty(max(int(n[k]), 1), dtype=torch.int32, device=dev)
+            self.s.buf[k], self.s.toff[k], self.s.dst[k] = buf.data_ptr(), toff.data_ptr(), dst.data_ptr()
+            self.s.n[k] = int(n[k])
+            self.keep += [buf, toff, dst]
+        self.s.status = status.data_ptr()
+
+    def sections(self, k: int) -> dict:
+        """Views of species k's packed ions (cell, off[dim], v[3], id), its
+        tile offsets and its record."""
+        buf, toff, dst = self.keep[3 * k:3 * k + 3]
+        n, rb = self.n[k], torch.finfo(self.real).bits // 8
+        out, pos = {}, 0
+
+        def take(nbytes, dtype):
+            nonlocal pos
+            t = buf[pos:pos + nbytes].view(dtype)
+            pos += (nbytes + 255) // 256 * 256
+            return t
+
+        out["cell"] = take(4 * n, torch.int32)
+        out["off"] = [take(rb * n, self.real) for _ in range(self.dim)]
+        out["v"] = [take(rb * n, self.real) for _ in range(3)]
+        out["id"] = take(4 * n, torch.int32)
+        out["toff"], out["dst"] = toff, dst[:n]
+        return out
+
+    @staticmethod
+    def bytes(sim: F.Simulation, nsp: int, n) -> int:
+        dim = int(sim.p["dim"])
+        rb = torch.finfo(sim.real).bits // 8
+        return sum(_section_bytes(int(n[k]), dim, rb) + 4 * (int(n[k]) + int(sim.L.ntiles) + 2) for k in range(nsp))
+
+
+def _recorded_step(sim: F.Simulation, n: int, a, b, rec: F.FsRecord):
     """Step n from state a into state b without copying particles: the
     step reads a's buffers and writes b's (the field update works in place,
     so B and the gather grid of a are first copied into b)."""
@@ -90,42 +176,52 @@ def _recorded_step(sim: F.Simulation, n: int, a: _State, b: _State, rec: F.FsRec
     f = b.fields(sim)
     rc = sim.lib.fs_step_record(sim.h, sp, C.byref(f), int(n), C.byref(rec), None, sim.stream)
     sim._check(rc)
-    b.next_id = sim.next_id
 
 
-def checkpoint_interval(nsteps: int, K: int, state_bytes: int, free_bytes: int, share: float = 0.8) -> int:
+def checkpoint_interval(nsteps: int, K: int, state_bytes: int, free_bytes: int, share: float = 0.8,
+                        tape_bytes: int | None = None) -> int:
     """Checkpoint interval for a reverse pass that must fit in memory.
 
-    The forward keeps ceil(nsteps / k) checkpoints and the reverse a tape of
-    k states, each state_bytes large.  Returns the largest k <= K for which
-    (ceil(nsteps / k) + k) states fit in `share` of free_bytes.  Raises
-    MemoryError if no interval fits.  The gradient does not depend on k."""
+    The forward keeps ceil(nsteps / k) checkpoints of state_bytes each and
+    the reverse a tape of k states of tape_bytes each (state_bytes when not
+    given).  Returns the largest k <= K for which both fit in `share` of
+    free_bytes.  Raises MemoryError if no interval fits.  The gradient does
+    not depend on k."""
     nsteps, K = max(1, int(nsteps)), max(1, int(K))
+    tape = float(state_bytes if tape_bytes is None else tape_bytes)
     budget = share * float(free_bytes)
     for k in range(min(K, nsteps), 0, -1):
-        if (-(-nsteps // k) + k) * float(state_bytes) <= budget:
+        if (-(-nsteps // k)) * float(state_bytes) + k * tape <= budget:
             return k
     raise MemoryError(f"a reverse pass over {nsteps} steps needs at least "
-                      f"{2 * (nsteps ** 0.5) * state_bytes / 1e9:.1f} GB of checkpoints and tape "
-                      f"({state_bytes / 1e9:.2f} GB per state), {free_bytes / 1e9:.1f} GB are free")
+                      f"{2 * (nsteps ** 0.5) * (state_bytes * tape) ** 0.5 / 1e9:.1f} GB of checkpoints and tape "
+                      f"({state_bytes / 1e9:.2f} GB per checkpoint, {tape / 1e9:.2f} GB per tape state), "
+                      f"{free_bytes / 1e9:.1f} GB are free")
 
 
 def _state_bytes(sim: F.Simulation, nsp: int) -> int:
-    """Bytes of one checkpoint / tape state of this simulation, with the
-    step record a tape state carries (4 bytes per bin slot)."""
+    """Bytes of one checkpoint (the full particle bins and the fields)."""
     t = [sim.B, sim.E, sim.gather] + list(sim.mom[:nsp])
     for k in range(nsp):
         cur = int(sim.sp[k].cur)
         t += [sim.bufs[k][cur], sim.cnts[k][cur]]
-    rec = sum(4 * int(sim.L.capacity[k]) for k in range(nsp))
-    return int(sum(x.numel() * x.element_size() for x in t)) + rec
+    return int(sum(x.numel() * x.element_size() for x in t))
 
 
-def _lambda_bytes(sim: F.Simulation, nsp: int, dim: int) -> int:
-    """Bytes of the two particle adjoint buffers and the grid adjoints."""
+def _fields_bytes(sim: F.Simulation, nsp: int) -> int:
+    return int(sum(x.numel() * x.element_size() for x in [sim.B, sim.E, sim.gather] + list(sim.mom[:nsp])))
+
+
+def _fixed_bytes(sim: F.Simulation, nsp: int, n) -> int:
+    """Bytes the reverse pass holds besides checkpoints and tape: two working
+    bin states, the bin record, the adjoints (two buffers of n per species
+    and the grid adjoints) and the id-indexed parking scratch."""
+    dim = int(sim.p["dim"])
     rb = torch.finfo(sim.real).bits // 8
-    part = sum(2 * (dim + 3) * rb * int(sim.L.capacity[k]) for k in range(nsp))
-    return part + 8 * (3 * int(sim.L.ncent) + 6 * int(sim.L.nnode))
+    work = 2 * _state_bytes(sim, nsp) + sum(4 * int(sim.L.capacity[k]) for k in range(nsp))
+    lam = sum(2 * (dim + 3) * rb * int(n[k]) for k in range(nsp)) + 8 * (3 * int(sim.L.ncent) + 6 * int(sim.L.nnode))
+    park = nsp * (dim + 3) * rb * int(sim.next_id + sim.next_id // 8 + 4096)
+    return work + lam + park
 
 
 class AdjointRun:
@@ -159,18 +255,25 @@ class AdjointRun:
         sim.init_plasma(a)
         # the interval actually used: the requested one, or less if the
         # checkpoints and the tape would not fit in the memory free on the
-        # device plus what the allocator holds unused
+        # device plus what the allocator holds unused; the tape's packed
+        # states are sized here from the initial load (the reverse pass sizes
+        # them exactly from the counts the forward pass saw)
         free, _ = torch.cuda.mem_get_info(self.device)
         free += torch.cuda.memory_reserved(self.device) - torch.cuda.memory_allocated(self.device)
         if self._bufs is not None and self._bufs["key"] == self._key(sim):
             free += self._bufs["bytes"]          # reused, already counted out of free
         else:
             self._bufs = None
-            free -= _lambda_bytes(sim, self.nsp, int(p["dim"]))
-        self.K_run = checkpoint_interval(self.nsteps, self.K, _state_bytes(sim, self.nsp), free)
+        n0 = [sim.count(k) for k in range(self.nsp)]
+        n_est = [c + c // 4 + 4096 for c in n0]
+        free -= _fixed_bytes(sim, self.nsp, n_est)
+        tape = _fields_bytes(sim, self.nsp) + _Packed.bytes(sim, self.nsp, n_est)
+        self.K_run = checkpoint_interval(self.nsteps, self.K, _state_bytes(sim, self.nsp), free, tape_bytes=tape)
         for n in range(self.nsteps):
             if n % self.K_run == 0:
-                self.checkpoints[n] = _State(sim, self.nsp)
+                ck = _State(sim, self.nsp)
+                ck.counts = [sim.count(k) for k in range(self.nsp)]
+                self.checkpoints[n] = ck
             sim.step(n, stats=False)
         self.nid = sim.next_id
         return self.loss_value()
@@ -188,54 +291,64 @@ class AdjointRun:
         return (tuple(int(sim.L.capacity[k]) for k in range(2)), int(sim.L.ncent), int(sim.L.nnode),
                 sim.real, self.nsp)
 
+    def _packed_size(self):
+        """Ions a packed state of each species can hold: at most the ions of
+        its segment's checkpoint plus every id the segment handed out."""
+        starts = sorted(self.checkpoints)
+        n = [0] * self.nsp
+        for i, s0 in enumerate(starts):
+            ck = self.checkpoints[s0]
+            nid1 = self.checkpoints[starts[i + 1]].next_id if i + 1 < len(starts) else self.nid
+            for k in range(self.nsp):
+                n[k] = max(n[k], ck.counts[k] + (nid1 - ck.next_id))
+        return n
+
     def _buffers(self):
-        """The tape states, step records and adjoint buffers of this run,
-        allocated by the first reverse pass and reused afterwards."""
+        """The tape (packed states and their fields), the working bins, the
+        bin record, the adjoint buffers and the parking scratch of this run,
+        allocated by the first reverse pass and reused while they fit."""
         sim = self.sim
         K = self.K_run
+        n = self._packed_size()
         b = self._bufs
-        if b is not None and b["key"] == self._key(sim) and len(b["slots"]) >= K:
+        if (b is not None and b["key"] == self._key(sim) and len(b["fields"]) >= K
+                and all(b["n"][k] >= n[k] for k in range(self.nsp)) and b["nid"] >= self.nid):
             return b
+        self._bufs = b = None
         dim = int(self.p["dim"])
+        dev = self.device
         keep = []
         lam = F.FsAdjoint()
         for k in range(self.nsp):
-            cap = int(sim.L.capacity[k])
-            lam.capacity[k] = cap
+            lam.capacity[k] = n[k]
             for buf in range(2):
                 for d in range(3):
-                    vv = torch.empty(cap, dtype=sim.real, device=self.device)
+                    vv = torch.empty(max(n[k], 1), dtype=sim.real, device=dev)
                     lam.v[k][buf][d] = vv.data_ptr()
                     keep.append(vv)
                     if d < dim:
-                        xv = torch.empty(cap, dtype=sim.real, device=self.device)
+                        xv = torch.empty(max(n[k], 1), dtype=sim.real, device=dev)
                         lam.x[k][buf][d] = xv.data_ptr()
                         keep.append(xv)
-        lB = torch.empty(3, int(sim.L.ncent), dtype=torch.float64, device=self.device)
-        lE = torch.empty(6, int(sim.L.nnode), dtype=torch.float64, device=self.device)
+        lB = torch.empty(3, int(sim.L.ncent), dtype=torch.float64, device=dev)
+        lE = torch.empty(6, int(sim.L.nnode), dtype=torch.float64, device=dev)
         lam.lB, lam.lE = lB.data_ptr(), lE.data_ptr()
-        recs, dsts = [], []
-        for _ in range(K):
-            rec = F.FsRecord()
-            for k in range(self.nsp):
-                cap = int(sim.L.capacity[k])
-                t = torch.empty(cap, dtype=torch.int32, device=self.device)
-                rec.dst[k], rec.capacity[k] = t.data_ptr(), cap
-                dsts.append(t)
-            recs.append(rec)
-        slots = [_State(sim, self.nsp, copy=False) for _ in range(K)]
-        nbytes = _lambda_bytes(sim, self.nsp, dim) + K * _state_bytes(sim, self.nsp)
-        self._bufs = dict(key=self._key(sim), lam=lam, keep=keep, lB=lB, lE=lE, recs=recs, dsts=dsts, slots=slots,
-                          bytes=nbytes, scratch=None)
+        rec = F.FsRecord()
+        for k in range(self.nsp):
+            cap = int(sim.L.capacity[k])
+            t = torch.empty(cap, dtype=torch.int32, device=dev)
+            rec.dst[k], rec.capacity[k] = t.data_ptr(), cap
+            keep.append(t)
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
+        nid = self.nid + self.nid // 8 + 4096
+        scratch = torch.empty(self.nsp * (dim + 3) * nid, dtype=sim.real, device=dev)
+        work = [_State(sim, self.nsp, copy=False) for _ in range(2)]
+        fields = [_Fields(sim, self.nsp) for _ in range(K)]
+        packed = [_Packed(sim, self.nsp, n, status) for _ in range(K + 1)]
+        nbytes = _fixed_bytes(sim, self.nsp, n) + K * (_fields_bytes(sim, self.nsp) + _Packed.bytes(sim, self.nsp, n))
+        self._bufs = dict(key=self._key(sim), n=n, nid=nid, lam=lam, keep=keep, lB=lB, lE=lE, rec=rec,
+                          status=status, scratch=scratch, work=work, fields=fields, packed=packed, bytes=nbytes)
         return self._bufs
-
-    def _scratch(self, bufs):
-        """Id-indexed scratch of the relayout between a checkpoint and its
-        re-run ((dim + 3) reals per id), grown when a run hands out more ids."""
-        need = (int(self.p["dim"]) + 3) * self.nid
-        if bufs["scratch"] is None or bufs["scratch"].numel() < need:
-            bufs["scratch"] = torch.empty(need + need // 8, dtype=self.sim.real, device=self.device)
-        return bufs["scratch"]
 
     def backward(self) -> np.ndarray:
         """Gradient [dL/du_sh, dL/dalpha_cr, dL/dA_1 .. dL/dA_M] of the last
@@ -243,45 +356,53 @@ class AdjointRun:
         sim = self.sim
         lib, stream = sim.lib, sim.stream
         bufs = self._buffers()
-        lam = bufs["lam"]
+        lam, rec, P = bufs["lam"], bufs["rec"], bufs["packed"]
         lam.cur = 0
+        bufs["status"].zero_()
         self.lB, self.lE = bufs["lB"], bufs["lE"]
         grads = torch.empty(2 + int(self.p["n_modes"]), dtype=torch.float64, device=self.device)
         gptr = C.c_void_p(grads.data_ptr())
+        scratch = C.c_void_p(bufs["scratch"].data_ptr())
+        nid = bufs["nid"]
         # zero the particle adjoints, lE and grads; seed lB = dL/dB at the final state
         sim._check(lib.fs_adjoint_seed(sim.h, C.byref(sim.f), C.byref(lam), gptr, stream))
         K = self.K_run
-        slots, recs = bufs["slots"], bufs["recs"]
-        scratch = self._scratch(bufs)
-        later = None     # checkpoint that started the segment walked back last
+        parked = False
         for s0 in sorted(self.checkpoints, reverse=True):
             s1 = min(s0 + K, self.nsteps)
             ck = self.checkpoints[s0]
             sim.set_clock(ck.next_id)
-            tape = [ck]
+            flds = [ck] + bufs["fields"]
+            sim._check(lib.fs_tape_pack(sim.h, ck.particles(sim), C.byref(P[0].s), None, None, None, stream))
+            pre, id0 = ck, []
             for j, n in enumerate(range(s0, s1)):
-                _recorded_step(sim, n, tape[j], slots[j], recs[j])
-                tape.append(slots[j])
-            if later is not None:
-                # the adjoints of state s1 sit in the slots of its checkpoint;
-                # the re-run placed the same ions elsewhere
-                rc = lib.fs_adjoint_relayout(sim.h, later.particles(sim), tape[-1].particles(sim), C.byref(lam),
-                                             C.c_void_p(scratch.data_ptr()), int(self.nid), stream)
-                sim._check(rc)
-            later = ck
-            for j in range(s1 - s0 - 1, -1, -1):
-                a, b = tape[j], tape[j + 1]
-                f_n, f_n1 = a.fields(sim), b.fields(sim)
-                rc = lib.fs_adjoint_step(sim.h, a.particles(sim), C.byref(f_n), b.particles(sim), C.byref(f_n1),
-                                         C.byref(recs[j]), s0 + j, C.byref(lam), gptr, stream)
+                post = bufs["work"][j % 2]
+                a, b = _Step(pre, flds[j]), _Step(post, flds[j + 1])
+                _recorded_step(sim, n, a, b, rec)
+                id0.append(int(rec.id0))
+                sim._check(lib.fs_tape_pack(sim.h, b.particles(sim), C.byref(P[j + 1].s), a.particles(sim),
+                                            C.byref(rec), C.byref(P[j].s), stream))
+                pre = post
+            m = s1 - s0
+            if parked:
+                # the adjoints of state s1 were parked by id from its
+                # checkpoint's packing; the re-run packed the same ions in
+                # another order
+                sim._check(lib.fs_adjoint_unpark(sim.h, C.byref(P[m].s), C.byref(lam), scratch, nid, stream))
+            for j in range(m - 1, -1, -1):
+                f_n, f_n1 = flds[j].fields(sim), flds[j + 1].fields(sim)
+                rc = lib.fs_adjoint_step(sim.h, C.byref(P[j].s), C.byref(f_n), C.byref(P[j + 1].s), C.byref(f_n1),
+                                         id0[j], s0 + j, C.byref(lam), gptr, stream)
                 sim._check(rc)
             if s0 == 0:
-                a = tape[0]
-                f0 = a.fields(sim)
-                rc = lib.fs_adjoint_init(sim.h, a.particles(sim), C.byref(f0), C.byref(lam), gptr, stream)
-                sim._check(rc)
-            del tape
+                f0 = ck.fields(sim)
+                sim._check(lib.fs_adjoint_init(sim.h, C.byref(P[0].s), C.byref(f0), C.byref(lam), gptr, stream))
+            else:
+                sim._check(lib.fs_adjoint_park(sim.h, C.byref(P[0].s), C.byref(lam), scratch, nid, stream))
+                parked = True
         torch.cuda.synchronize(self.device)
+        if int(bufs["status"].item()) != 0:
+            raise RuntimeError("a packed tape state overflowed its size: the gradient is invalid")
         return grads.cpu().numpy()
 
 

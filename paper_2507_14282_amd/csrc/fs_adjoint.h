@@ -12,21 +12,23 @@
 // lam(Bbar^{n+1}) and the particle adjoints lam(x^{n+1}), lam(v^{n+1/2}):
 //   final Ohm^T -> SSP-RK3^T (stages recomputed) -> fluid^T -> deposit^T ->
 //   injection^T -> (FS kick^T) -> move^T -> Boris^T -> gather^T.
-// Particle adjoints are stored in the particle precision and laid out like
-// the particle buffers, one entry per bin slot, in two buffers: a reverse
-// step reads the adjoints after the step at the slots the recorded step put
-// each ion in and writes those before it at the ion's slot in the state
-// before, so every particle pass streams its arrays in the same order as
-// the particle state (an ion removed by the step gets zero).  Grid adjoints
-// are FP64.  The push pass accumulates per tile in LDS (FP64 atomics) and
-// flushes once per node.
+// The reverse pass reads its particle states from a tape packed to the live
+// ions (tile t's ions at [toff[t], toff[t + 1]) in bin order), each with the
+// record of the step that leaves it in packed indices of the next state.
+// Particle adjoints are stored in the particle precision and indexed like
+// the packed states, in two buffers: a reverse step reads the adjoints after
+// the step at the packed index the record gives for each ion and writes
+// those before it at the ion's own packed index, so every particle pass
+// streams its arrays in the same order as the packed state (an ion removed
+// by the step gets zero).  Grid adjoints are FP64.  The push pass
+// accumulates per tile in LDS (FP64 atomics) and flushes once per node.
 #pragma once
 #include "fs_field.h"
 
 namespace fsk {
 
-// Planar particle adjoints of one species in one buffer, one entry per bin
-// slot of that species' particle buffers: x[d] (d < D, per cell of
+// Planar particle adjoints of one species in one buffer, one entry per
+// packed index of that species' tape states: x[d] (d < D, per cell of
 // position) and v[3].
 template <typename R> struct PLam {
     R* x[3];
@@ -148,18 +150,112 @@ __device__ __forceinline__ void block_add(double v, double* out) {
 // (consecutive blocks), each taking a contiguous share of the bin, so that
 // few large tiles still fill the chip.
 // ---------------------------------------------------------------------------
-struct TileShare {
-    int tile, begin, end;
+// The share of a packed tile's ions one workgroup takes: tiles with many
+// ions are split over `split` workgroups (blockIdx.x = tile * split + part).
+struct PackShare {
+    int tile;
+    long begin, end;
 };
-__device__ __forceinline__ TileShare tile_share(const int32_t* cnt, int ntiles, int64_t cap, int split) {
-    TileShare t;
-    t.tile = blockIdx.x / split;
+__device__ __forceinline__ PackShare pack_share(const int32_t* toff, int64_t n, int split) {
+    PackShare r;
+    r.tile = blockIdx.x / split;
     const int part = blockIdx.x % split;
-    const int n = min(cnt[t.tile] + cnt[ntiles + t.tile], (int)cap);
-    const int chunk = (n + split - 1) / split;
-    t.begin = min(n, part * chunk);
-    t.end = min(n, t.begin + chunk);
-    return t;
+    const long b = min((long)toff[r.tile], (long)n), e = min((long)toff[r.tile + 1], (long)n);
+    const long len = e > b ? e - b : 0;
+    const long chunk = (len + split - 1) / split;
+    r.begin = b + min(len, part * chunk);
+    r.end = min(e, r.begin + chunk);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// The tape: particle states packed to their live ions
+// ---------------------------------------------------------------------------
+
+// Tile offsets of a packed state: toff[t] = ions of the tiles before t (one
+// workgroup of 1024 threads; each thread sums a run of tiles, a block scan
+// of the run totals places them).  Sets *status when the total exceeds n.
+__global__ __launch_bounds__(1024) void k_tape_offsets(const int32_t* __restrict__ cnt, int ntiles, int64_t cap,
+                                                       int32_t* __restrict__ toff, int64_t n,
+                                                       int32_t* __restrict__ status) {
+    __shared__ long part[1024];
+    const int t = threadIdx.x;
+    const int per = (ntiles + 1023) / 1024;
+    const int b = min(ntiles, t * per), e = min(ntiles, b + per);
+    auto live = [&](int i) { return min((long)cnt[i] + cnt[ntiles + i], (long)cap); };
+    long sum = 0;
+    for (int i = b; i < e; ++i) sum += live(i);
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const long v = t >= off ? part[t - off] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    long run = t > 0 ? part[t - 1] : 0;
+    for (int i = b; i < e; ++i) {
+        toff[i] = (int32_t)run;
+        run += live(i);
+    }
+    if (t == 1023) {
+        toff[ntiles] = (int32_t)part[1023];
+        if (part[1023] > n) *status = 1;
+    }
+}
+
+// Copy of every tile's live ions, in bin order, to its packed range (ions
+// past n are dropped; k_tape_offsets flagged them).
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_tape_pack(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
+                                                   const int32_t* __restrict__ toff, int64_t n, PBuf<R> out) {
+    const int tile = blockIdx.x;
+    const int lo = cnt[tile];
+    const int m = min(lo + cnt[G.ntiles + tile], (int)cap);
+    const long base = toff[tile];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const long dst = base + i;
+        if (dst >= n) break;
+        const long src = bin_slot(tile, cap, lo, i);
+        out.cell[dst] = in.cell[src];
+#pragma unroll
+        for (int d = 0; d < D; ++d) out.off[d][dst] = in.off[d][src];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out.v[c][dst] = in.v[c][src];
+        out.id[dst] = in.id[src];
+    }
+}
+
+// A step's record from bin slots to packed indices: for each ion of the
+// input state (tile t, rank i in its bin, packed at toff_in[t] + i), the
+// output bin slot it went to, turned into the packed index of the output
+// state (the slot's tile, its rank in that bin).
+__global__ __launch_bounds__(256) void k_tape_record(Geo G, const int32_t* __restrict__ cnt_in, int64_t cap,
+                                                     const int32_t* __restrict__ toff_in, int64_t n_in,
+                                                     const int32_t* __restrict__ dst_bin,
+                                                     const int32_t* __restrict__ cnt_out,
+                                                     const int32_t* __restrict__ toff_out, int64_t n_out,
+                                                     int32_t* __restrict__ dst, int32_t* __restrict__ status) {
+    const int tile = blockIdx.x;
+    const int lo = cnt_in[tile];
+    const int m = min(lo + cnt_in[G.ntiles + tile], (int)cap);
+    const long base = toff_in[tile];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const long p = base + i;
+        if (p >= n_in) break;
+        const int32_t d = dst_bin[bin_slot(tile, cap, lo, i)];
+        int32_t r = -1;
+        if (d != -1) {
+            const long slot = d >= 0 ? (long)d : (long)(-2 - d);
+            const int t2 = (int)(slot / cap);
+            const int j = (int)(slot - (long)t2 * cap);
+            const int lo2 = cnt_out[t2];
+            const long q = toff_out[t2] + (j < lo2 ? j : lo2 + (int)(cap - 1 - j));
+            if (q < n_out) r = d >= 0 ? (int32_t)q : (int32_t)(-2 - q);
+            else *status = 1;
+        }
+        dst[p] = r;
+    }
 }
 
 // u_sh adjoint of one ion injected during the step (reading of the
@@ -195,13 +291,13 @@ __device__ __forceinline__ double inject_vjp(const Geo& G, uint64_t step, uint64
     return (lv[0] * dvx + lv[1] * G.cr_w * cos(phi) * dst + lv[2] * G.cr_w * sin(phi) * dst + lx * dxi) * G.rinv;
 }
 
-// Deposit transpose over the live particles of one buffer (the state at
-// n+1): lam(x) += sum_nodes dW/dx (lam_R + lam_G . v), lam(v) += sum W lam_G,
-// added to the adjoints at the ions' bin slots.  The ions the step injected
+// Deposit transpose over the ions of a packed state (the state at n+1):
+// lam(x) += sum_nodes dW/dx (lam_R + lam_G . v), lam(v) += sum W lam_G,
+// added to the adjoints at the ions' packed indices.  The ions the step injected
 // (ids id0 .. id0 + ninj - 1, thermal first, nth of them) then have their
 // final adjoint, which goes into dL/du_sh through their injection.
 template <typename R, int D, int S>
-__global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
+__global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ toff, int64_t n,
                                                      const double* __restrict__ lM, PLam<R> lam, int split,
                                                      uint64_t step, int64_t id0, int64_t nth, int64_t ninj,
                                                      double* grads) {
@@ -212,7 +308,7 @@ __global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const in
     // the moment adjoints of the tile's stencil nodes, [node][R, Gx, Gy, Gz];
     // nodes outside the deposit grid hold zero
     __shared__ double sm[4 * X::GN];
-    const TileShare ts = tile_share(cnt, G.ntiles, cap, split);
+    const PackShare ts = pack_share(toff, n, split);
     const int tile = ts.tile;
     const int tx = tile % G.ntx;
     const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
@@ -225,10 +321,8 @@ __global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const in
         for (int q = 0; q < 4; ++q) sm[4 * l + q] = gi < 0 ? 0.0 : lM[4 * gi + q];
     }
     __syncthreads();
-    const int lo = cnt[tile];
     double acc = 0.0;
-    for (int i = ts.begin + threadIdx.x; i < ts.end; i += blockDim.x) {
-        const long src = bin_slot(tile, cap, lo, i);
+    for (long src = ts.begin + threadIdx.x; src < ts.end; src += blockDim.x) {
         const int32_t pc = in.cell[src];
         const int cx = cell_x(pc, G), cy = D >= 2 ? cell_y(pc, G) : 0, cz = D >= 3 ? cell_z(pc, G) : 0;
         double w[3][3], dw[3][3];
@@ -281,65 +375,59 @@ __global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const in
     block_add(acc, grads);
 }
 
-// Relayout of particle adjoints between two bin layouts of the same ions,
-// matched by id through an id-indexed scratch (ncomp planar arrays of nid):
-// k_lam_scatter writes the adjoints of every live ion of `from` at its id,
-// k_lam_gather reads them back at the live slots of `to`.  The scratch is
-// zeroed first, so an id `from` lacks reads zero; ids >= nid are skipped.
+// Particle adjoints between two packings of the same ions, matched by id
+// through an id-indexed scratch (ncomp planar arrays of nid): k_lam_park
+// writes the adjoints of every ion of `from` at its id, k_lam_unpark reads
+// them back at the ions of `to`.  The scratch is zeroed first, so an id
+// `from` lacks reads zero; ids >= nid are skipped.
 template <typename R>
-__global__ __launch_bounds__(256) void k_lam_scatter(Geo G, const uint32_t* __restrict__ id, const int32_t* __restrict__ cnt,
-                                                     int64_t cap, PLam<R> lam, int D, R* __restrict__ scratch,
-                                                     int64_t nid) {
-    const int tile = blockIdx.x;
-    const int lo = cnt[tile];
-    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const long src = bin_slot(tile, cap, lo, i);
-        const int64_t q = id[src];
+__global__ __launch_bounds__(256) void k_lam_park(const uint32_t* __restrict__ id, const int32_t* __restrict__ toff,
+                                                  int ntiles, int64_t n, PLam<R> lam, int D, R* __restrict__ scratch,
+                                                  int64_t nid) {
+    const long m = min((long)toff[ntiles], (long)n);
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (long)gridDim.x * blockDim.x) {
+        const int64_t q = id[p];
         if (q >= nid) continue;
-        for (int d = 0; d < D; ++d) scratch[d * nid + q] = lam.x[d][src];
-        for (int c = 0; c < 3; ++c) scratch[(D + c) * nid + q] = lam.v[c][src];
+        for (int d = 0; d < D; ++d) scratch[d * nid + q] = lam.x[d][p];
+        for (int c = 0; c < 3; ++c) scratch[(D + c) * nid + q] = lam.v[c][p];
     }
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_lam_gather(Geo G, const uint32_t* __restrict__ id, const int32_t* __restrict__ cnt,
-                                                    int64_t cap, PLam<R> lam, int D, const R* __restrict__ scratch,
-                                                    int64_t nid) {
-    const int tile = blockIdx.x;
-    const int lo = cnt[tile];
-    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const long dst = bin_slot(tile, cap, lo, i);
-        const int64_t q = id[dst];
+__global__ __launch_bounds__(256) void k_lam_unpark(const uint32_t* __restrict__ id, const int32_t* __restrict__ toff,
+                                                    int ntiles, int64_t n, PLam<R> lam, int D,
+                                                    const R* __restrict__ scratch, int64_t nid) {
+    const long m = min((long)toff[ntiles], (long)n);
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (long)gridDim.x * blockDim.x) {
+        const int64_t q = id[p];
         const bool ok = q < nid;
-        for (int d = 0; d < D; ++d) lam.x[d][dst] = ok ? scratch[d * nid + q] : (R)0;
-        for (int c = 0; c < 3; ++c) lam.v[c][dst] = ok ? scratch[(D + c) * nid + q] : (R)0;
+        for (int d = 0; d < D; ++d) lam.x[d][p] = ok ? scratch[d * nid + q] : (R)0;
+        for (int c = 0; c < 3; ++c) lam.v[c][p] = ok ? scratch[(D + c) * nid + q] : (R)0;
     }
 }
 
-// u_sh adjoint of the initial load (v_x = u_sh + sigma n1 for every thermal ion).
+// u_sh adjoint of the initial load (v_x = u_sh + sigma n1 for every thermal
+// ion), over the packed initial state.
 template <typename R>
-__global__ __launch_bounds__(256) void k_init_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
-                                                  PLam<R> lam, double* grads) {
-    const int tile = blockIdx.x;
-    const int lo = cnt[tile];
-    const int n = min(lo + cnt[G.ntiles + tile], (int)cap);
+__global__ __launch_bounds__(256) void k_init_adj(const int32_t* __restrict__ toff, int ntiles, int64_t n, PLam<R> lam,
+                                                  double* grads) {
+    const long m = min((long)toff[ntiles], (long)n);
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) acc += (double)lam.v[0][bin_slot(tile, cap, lo, i)];
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (long)gridDim.x * blockDim.x)
+        acc += (double)lam.v[0][p];
     block_add(acc, grads);
 }
 
-// Push transpose over the live particles of the state at n: recompute the
+// Push transpose over the ions of the packed state at n: recompute the
 // gather, Boris and move as the forward step did, undo the FS kick for the
 // ions the step recorded as reflected, then the move, Boris and the gather.
-// Each ion reads its adjoint after the step from post, at the bin slot the
-// step's record gives (dst >= 0 kept, -2 - slot reflected, -1 removed), and
-// writes its adjoint before the step into pre at its own slot, zero for an
+// Each ion reads its adjoint after the step from post, at the packed index
+// the step's record gives (dst >= 0 kept, -2 - i reflected, -1 removed), and
+// writes its adjoint before the step into pre at its own index, zero for an
 // ion the step removed.  lam(E^n), lam(Bbar^n) (6 planar FP64 arrays of
 // nnode) accumulate per tile in LDS.
 template <typename R, int D, int S>
-__global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
+__global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ toff, int64_t n,
                                                   const R* __restrict__ gather, const int32_t* __restrict__ dst_of,
                                                   PLam<R> post, PLam<R> pre, double* __restrict__ lEB, long nnode,
                                                   uint64_t step, double* grads, int split, int mirror) {
@@ -350,7 +438,7 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
     __shared__ double sl[6 * X::GN];
     // the gather grid of the tile's stencil, as the forward push stages it
     __shared__ Pair<R> sg[3 * X::GN];
-    const TileShare ts = tile_share(cnt, G.ntiles, cap, split);
+    const PackShare ts = pack_share(toff, n, split);
     const int tile = ts.tile;
     const int tx = tile % G.ntx;
     const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
@@ -365,13 +453,11 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
         sg[2 * X::GN + l] = Pair<R>{g8[5], g8[6]};
     }
     __syncthreads();
-    const int lo = cnt[tile];
     const R hR = (R)(0.5 * G.dt);
     const R dtdxR = (R)G.dtdx;
     const double hD = 0.5 * G.dt, dtdx = G.dtdx;
     double acc = 0.0;
-    for (int i = ts.begin + threadIdx.x; i < ts.end; i += blockDim.x) {
-        const long src = bin_slot(tile, cap, lo, i);
+    for (long src = ts.begin + threadIdx.x; src < ts.end; src += blockDim.x) {
         // adjoint of the ion after the step, where the step put it
         const int32_t dr = dst_of[src];
         const bool refl = dr <= -2;

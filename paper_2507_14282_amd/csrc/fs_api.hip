@@ -620,17 +620,11 @@ template <typename R> PLam<R> plam(const fs_adjoint* a, int k, int b, int D) {
     return L;
 }
 
-// Moments and fluid state of a particle state, into the reverse scratch:
-// the moments are copied from `mom` (the caller's grids of that state) when
-// given, otherwise deposited again.
-template <typename R, int D, int S>
-void fluid_of(fs_handle* h, const fs_particles* sp, int64_t* const* mom, hipStream_t s) {
-    if (mom && mom[0] && (!h->has_cr || mom[1])) {
-        for (int k = 0; k < (h->has_cr ? 2 : 1); ++k)
-            (void)hipMemcpyAsync(h->amom[k], mom[k], 4 * h->L.ndep * sizeof(double), hipMemcpyDeviceToDevice, s);
-    } else {
-        deposit_continuous<R, D, S>(h, sp, h->amom, s);
-    }
+// Moments and fluid state of a tape state, into the reverse scratch: the
+// moments are copied from `mom` (the tape's grids of that state).
+void fluid_of(fs_handle* h, int64_t* const* mom, hipStream_t s) {
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k)
+        (void)hipMemcpyAsync(h->amom[k], mom[k], 4 * h->L.ndep * sizeof(double), hipMemcpyDeviceToDevice, s);
     const dim3 blk(kFX, kFY, 1);
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
     k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(h->amom[0]),
@@ -691,11 +685,11 @@ template <int D> void rk3_adj(fs_handle* h, const double* Bn, double* lB, double
 }
 
 // Fluid and deposit transposes: lam of the fluid state in h->alfl -> the
-// particle adjoints (buffer lam->cur) of the state whose moments are in
-// h->amom; then the injection transpose of the ions a step injected (ids
+// particle adjoints (buffer lam->cur) of the packed state whose moments are
+// in h->amom; then the injection transpose of the ions a step injected (ids
 // id0 .. id0 + nth + ncr - 1, none when ncr + nth = 0).
 template <typename R, int D, int S>
-void moments_adj(fs_handle* h, const fs_particles* sp, const fs_adjoint* lam, double* grads, hipStream_t s,
+void moments_adj(fs_handle* h, const fs_packed* pk, const fs_adjoint* lam, double* grads, hipStream_t s,
                  uint64_t step = 0, int64_t id0 = 0, int64_t nth = 0, int64_t ncr = 0) {
     const long nn = h->L.nnode;
     for (int k = 0; k < 2; ++k) zero_u64(reinterpret_cast<unsigned long long*>(h->alM[k]), 4 * h->L.ndep, s);
@@ -703,22 +697,21 @@ void moments_adj(fs_handle* h, const fs_particles* sp, const fs_adjoint* lam, do
     k_fluid_adj<<<grid_for(nn), 256, 0, s>>>(h->F, h->amom[0], h->has_cr ? h->amom[1] : h->amom[0], h->alfl, h->alM[0],
                                              h->alM[1], nn, dwcr, grads + 1);
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
-        const fs_particles& P = sp[k];
-        PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
-        const int sp_ = split_of(P.tile_cap);
+        PBuf<R> in = sections<R>(pk->buf[k], pk->n[k], D);
+        const int sp_ = split_of(h->L.tile_cap[k]);
         k_deposit_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
-            h->G, in, P.tile_count[P.cur], P.tile_cap, h->alM[k], plam<R>(lam, k, lam->cur, D), sp_, step, id0, nth,
-            nth + ncr, grads);
+            h->G, in, pk->toff[k], pk->n[k], h->alM[k], plam<R>(lam, k, lam->cur, D), sp_, step, id0, nth, nth + ncr,
+            grads);
     }
 }
 
 template <typename R, int D, int S>
-int adjoint_step_impl(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n, const fs_particles* sp_n1,
-                      const fs_fields* f_n1, const fs_record* rec, int64_t step, fs_adjoint* lam, double* grads,
+int adjoint_step_impl(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, const fs_packed* pn1,
+                      const fs_fields* f_n1, int64_t id0, int64_t step, fs_adjoint* lam, double* grads,
                       hipStream_t s) {
-    const long nn = h->L.nnode, nc = h->L.ncent;
+    const long nn = h->L.nnode;
     // fluid state the step's field update used: moments of the particles after it
-    fluid_of<R, D, S>(h, sp_n1, f_n1->mom, s);
+    fluid_of(h, f_n1->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
     // final Ohm, then the RK3 update
     ohm_adj<D>(h, f_n1->B, lam->lE, lam->lE + 3 * nn, lam->lB, grads, s);
@@ -728,17 +721,16 @@ int adjoint_step_impl(fs_handle* h, const fs_particles* sp_n, const fs_fields* f
     int64_t cth = 0, ccr = 0;
     inject_counts(h->cfg, step, cth, ccr);
     const int64_t ntr = h->L.nyc * h->L.nzc, nth = cth * ntr, ncr = ccr * ntr;
-    moments_adj<R, D, S>(h, sp_n1, lam, grads, s, (uint64_t)step, rec->id0, nth, ncr);
+    moments_adj<R, D, S>(h, pn1, lam, grads, s, (uint64_t)step, id0, nth, ncr);
     // push, wall and gather of the ions that lived before the step: buffer
-    // cur (slots after the step) -> cur ^ 1 (slots before it)
+    // cur (indices after the step) -> cur ^ 1 (indices before it)
     zero_u64(reinterpret_cast<unsigned long long*>(lam->lE), 6 * nn, s);
     const int post = lam->cur, pre = lam->cur ^ 1;
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
-        const fs_particles& P = sp_n[k];
-        PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
-        const int sp_ = split_of(P.tile_cap);
+        PBuf<R> in = sections<R>(pn->buf[k], pn->n[k], D);
+        const int sp_ = split_of(h->L.tile_cap[k]);
         k_push_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
-            h->G, in, P.tile_count[P.cur], P.tile_cap, static_cast<const R*>(f_n->gather), rec->dst[k],
+            h->G, in, pn->toff[k], pn->n[k], static_cast<const R*>(f_n->gather), pn->dst[k],
             plam<R>(lam, k, post, D), plam<R>(lam, k, pre, D), lam->lE, nn, (uint64_t)step, grads, sp_,
             policy_of(h, k) == FS_WALL_SPECULAR ? 1 : 0);
     }
@@ -747,17 +739,15 @@ int adjoint_step_impl(fs_handle* h, const fs_particles* sp_n, const fs_fields* f
 }
 
 template <typename R, int D, int S>
-int adjoint_init_impl(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, fs_adjoint* lam, double* grads,
+int adjoint_init_impl(fs_handle* h, const fs_packed* p0, const fs_fields* f0, fs_adjoint* lam, double* grads,
                       hipStream_t s) {
     const long nn = h->L.nnode, nc = h->L.ncent;
-    fluid_of<R, D, S>(h, sp0, f0->mom, s);
+    fluid_of(h, f0->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
     ohm_adj<D>(h, f0->B, lam->lE, lam->lE + 3 * nn, lam->lB, grads, s);
-    moments_adj<R, D, S>(h, sp0, lam, grads, s);
-    const fs_particles& P = sp0[0];
-    PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
-    k_init_adj<R><<<(unsigned)h->L.ntiles, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
-                                                        plam<R>(lam, 0, lam->cur, D), grads);
+    moments_adj<R, D, S>(h, p0, lam, grads, s);
+    k_init_adj<R><<<std::min<unsigned>(grid_for(p0->n[0]), 2048u), 256, 0, s>>>(
+        p0->toff[0], (int)h->L.ntiles, p0->n[0], plam<R>(lam, 0, lam->cur, D), grads);
     const fs_config& c = h->cfg;
     if (c.n_modes > 0) {
         k_phases<<<grid_for(c.n_modes), 256, 0, s>>>(c.seed, c.n_modes, h->phase);
@@ -767,6 +757,46 @@ int adjoint_init_impl(fs_handle* h, const fs_particles* sp0, const fs_fields* f0
     }
     return hip_check(h, hipGetLastError(), "adjoint init launch");
 }
+
+// Packs the live ions of sp into out (and, with a record, converts it).
+template <typename R, int D>
+int tape_pack_impl(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_particles* prev_sp,
+                   const fs_record* rec, fs_packed* prev, hipStream_t s) {
+    const int nt = (int)h->L.ntiles;
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        const fs_particles& P = sp[k];
+        k_tape_offsets<<<1, 1024, 0, s>>>(P.tile_count[P.cur], nt, P.tile_cap, out->toff[k], out->n[k], out->status);
+        PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
+        PBuf<R> o = sections<R>(out->buf[k], out->n[k], D);
+        k_tape_pack<R, D><<<(unsigned)nt, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap, out->toff[k],
+                                                       out->n[k], o);
+        if (rec) {
+            const fs_particles& Q = prev_sp[k];
+            k_tape_record<<<(unsigned)nt, 256, 0, s>>>(h->G, Q.tile_count[Q.cur], Q.tile_cap, prev->toff[k],
+                                                       prev->n[k], rec->dst[k], P.tile_count[P.cur], out->toff[k],
+                                                       out->n[k], prev->dst[k], prev->status);
+        }
+    }
+    return hip_check(h, hipGetLastError(), "tape pack launch");
+}
+
+// Dispatch a templated implementation on (precision, dim).
+#define FS_DISPATCH_RD(h, CALL)                                                  \
+    do {                                                                         \
+        const int _d = (h)->cfg.dim;                                             \
+        if ((h)->cfg.precision == 32) {                                          \
+            using R = float;                                                     \
+            if (_d == 1) { constexpr int D = 1; return CALL; }                   \
+            if (_d == 2) { constexpr int D = 2; return CALL; }                   \
+            if (_d == 3) { constexpr int D = 3; return CALL; }                   \
+        } else {                                                                 \
+            using R = double;                                                    \
+            if (_d == 1) { constexpr int D = 1; return CALL; }                   \
+            if (_d == 2) { constexpr int D = 2; return CALL; }                   \
+            if (_d == 3) { constexpr int D = 3; return CALL; }                   \
+        }                                                                        \
+        return fail(h, FS_EINVAL, "unsupported configuration");                  \
+    } while (0)
 
 // Dispatch a templated implementation on (precision, dim, shape).
 #define FS_DISPATCH(h, CALL)                                                           \
@@ -816,6 +846,29 @@ int check_fields(fs_handle* h, const fs_fields* f) {
 // ==========================================================================
 // C ABI
 // ==========================================================================
+// Id-indexed parking of the adjoints of buffer lam->cur (see the header).
+template <typename R>
+int park_impl(fs_handle* h, const fs_packed* pk, fs_adjoint* lam, void* scratch, const void* cscratch, int64_t nid,
+              bool park, hipStream_t s) {
+    const int D = h->cfg.dim;
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        PBuf<R> p = sections<R>(pk->buf[k], pk->n[k], D);
+        const unsigned g = std::min<unsigned>(grid_for(std::max<int64_t>(pk->n[k], 1)), 4096u);
+        if (park) {
+            R* sc = static_cast<R*>(scratch) + (int64_t)k * (D + 3) * nid;
+            if (sizeof(R) == 8) zero_u64(sc, (int64_t)(D + 3) * nid, s);
+            else zero_i32(reinterpret_cast<int32_t*>(sc), (int64_t)(D + 3) * nid, s);
+            k_lam_park<R><<<g, 256, 0, s>>>(p.id, pk->toff[k], (int)h->L.ntiles, pk->n[k],
+                                            plam<R>(lam, k, lam->cur, D), D, sc, nid);
+        } else {
+            const R* sc = static_cast<const R*>(cscratch) + (int64_t)k * (D + 3) * nid;
+            k_lam_unpark<R><<<g, 256, 0, s>>>(p.id, pk->toff[k], (int)h->L.ntiles, pk->n[k],
+                                              plam<R>(lam, k, lam->cur, D), D, sc, nid);
+        }
+    }
+    return hip_check(h, hipGetLastError(), "adjoint park launch");
+}
+
 extern "C" {
 
 int fs_layout(const fs_config* cfg, fs_layout_info* out) {
@@ -1007,8 +1060,20 @@ static int check_adjoint(fs_handle* h, const fs_adjoint* lam) {
             for (int d = 0; d < 3; ++d)
                 if ((d < h->cfg.dim && !lam->x[k][b][d]) || !lam->v[k][b][d])
                     return fail(h, FS_EINVAL, "NULL particle adjoint array");
-        if (lam->capacity[k] < h->L.capacity[k])
-            return fail(h, FS_ECAPACITY, "particle adjoint arrays smaller than the particle buffers");
+        if (lam->capacity[k] < 0) return fail(h, FS_EINVAL, "negative adjoint capacity");
+    }
+    return FS_OK;
+}
+
+// A packed state: arrays given, sizes within the int32 indices, and (with
+// lam) adjoint buffers at least as long.
+static int check_packed(fs_handle* h, const fs_packed* pk, const fs_adjoint* lam, bool need_dst) {
+    if (!pk || !pk->status) return fail(h, FS_EINVAL, "NULL packed state");
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        if (!pk->buf[k] || !pk->toff[k] || (need_dst && !pk->dst[k])) return fail(h, FS_EINVAL, "NULL packed array");
+        if (pk->n[k] < 0 || pk->n[k] > (int64_t)INT32_MAX - 2) return fail(h, FS_EINVAL, "packed size out of range");
+        if (lam && lam->capacity[k] < pk->n[k])
+            return fail(h, FS_ECAPACITY, "particle adjoint arrays shorter than the packed state");
     }
     return FS_OK;
 }
@@ -1023,6 +1088,15 @@ static int check_record(fs_handle* h, const fs_record* rec) {
     return FS_OK;
 }
 
+static int check_reverse_cfg(fs_handle* h) {
+    if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
+    if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
+    if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
+    if (h->cfg.coupling != 1) return fail(h, FS_EINVAL, "the adjoint covers the first-order coupling only");
+    if (h->cfg.smooth != 0) return fail(h, FS_EINVAL, "the adjoint covers the unfiltered moments only");
+    return FS_OK;
+}
+
 int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec, fs_step_stats* st,
                    hipStream_t s) {
     if (!h || !rec) return fail(h, FS_EINVAL, "NULL argument");
@@ -1034,78 +1108,69 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
     return step_common(h, sp, f, step, FS_ALL, st, s, rec);
 }
 
-int fs_adjoint_step(fs_handle* h, const fs_particles* sp_n, const fs_fields* f_n, const fs_particles* sp_n1,
-                    const fs_fields* f_n1, const fs_record* rec, int64_t step, fs_adjoint* lam, double* grads,
+int fs_tape_pack(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_particles* prev_sp,
+                 const fs_record* rec, fs_packed* prev, hipStream_t s) {
+    if (!h || !sp || !out) return fail(h, FS_EINVAL, "NULL argument");
+    const bool with = prev_sp || rec || prev;
+    if (with && !(prev_sp && rec && prev)) return fail(h, FS_EINVAL, "prev_sp, rec and prev go together");
+    int rc = check_particles(h, sp);
+    if (!rc) rc = check_packed(h, out, nullptr, false);
+    if (!rc && with) rc = check_particles(h, prev_sp);
+    if (!rc && with) rc = check_packed(h, prev, nullptr, true);
+    if (!rc && with) rc = check_record(h, rec);
+    if (rc) return rc;
+    auto run = [&]() -> int { FS_DISPATCH_RD(h, (tape_pack_impl<R, D>(h, sp, out, prev_sp, rec, prev, s))); };
+    return run();
+}
+
+int fs_adjoint_step(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, const fs_packed* pn1,
+                    const fs_fields* f_n1, int64_t id0, int64_t step, fs_adjoint* lam, double* grads,
                     hipStream_t s) {
-    if (!h || !sp_n || !f_n || !sp_n1 || !f_n1 || !rec || !lam || !grads)
-        return fail(h, FS_EINVAL, "NULL argument");
-    if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
-    if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
-    if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
-    if (h->cfg.coupling != 1) return fail(h, FS_EINVAL, "the adjoint covers the first-order coupling only");
-    if (h->cfg.smooth != 0) return fail(h, FS_EINVAL, "the adjoint covers the unfiltered moments only");
-    if (!f_n->B || !f_n->gather || !f_n1->B) return fail(h, FS_EINVAL, "NULL field array");
-    if (step < 0) return fail(h, FS_EINVAL, "negative step");
-    int rc = check_record(h, rec);
-    if (!rc) rc = check_adjoint(h, lam);
-    if (!rc) rc = check_particles(h, sp_n);
-    if (!rc) rc = check_particles(h, sp_n1);
+    if (!h || !pn || !f_n || !pn1 || !f_n1 || !lam || !grads) return fail(h, FS_EINVAL, "NULL argument");
+    if (int rc = check_reverse_cfg(h)) return rc;
+    if (!f_n->B || !f_n->gather || !f_n1->B || !f_n1->mom[0] || (h->has_cr && !f_n1->mom[1]))
+        return fail(h, FS_EINVAL, "NULL field array");
+    if (step < 0 || id0 < 0) return fail(h, FS_EINVAL, "negative step or id");
+    int rc = check_adjoint(h, lam);
+    if (!rc) rc = check_packed(h, pn, lam, true);
+    if (!rc) rc = check_packed(h, pn1, lam, false);
     if (rc) return rc;
     auto run = [&]() -> int {
-        FS_DISPATCH(h, (adjoint_step_impl<R, D, S>(h, sp_n, f_n, sp_n1, f_n1, rec, step, lam, grads, s)));
+        FS_DISPATCH(h, (adjoint_step_impl<R, D, S>(h, pn, f_n, pn1, f_n1, id0, step, lam, grads, s)));
     };
     return run();
 }
 
-int fs_adjoint_relayout(fs_handle* h, const fs_particles* from, const fs_particles* to, fs_adjoint* lam, void* scratch,
-                        int64_t nid, hipStream_t s) {
-    if (!h || !from || !to || !lam || !scratch) return fail(h, FS_EINVAL, "NULL argument");
+int fs_adjoint_park(fs_handle* h, const fs_packed* from, fs_adjoint* lam, void* scratch, int64_t nid, hipStream_t s) {
+    if (!h || !from || !lam || !scratch) return fail(h, FS_EINVAL, "NULL argument");
     if (nid < 0) return fail(h, FS_EINVAL, "negative id range");
     int rc = check_adjoint(h, lam);
-    if (!rc) rc = check_particles(h, from);
-    if (!rc) rc = check_particles(h, to);
+    if (!rc) rc = check_packed(h, from, lam, false);
     if (rc) return rc;
-    const int D = h->cfg.dim, rb = h->cfg.precision == 64 ? 8 : 4;
-    const int a = lam->cur, b = lam->cur ^ 1;
-    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
-        if (rb == 8) zero_u64(scratch, (int64_t)(D + 3) * nid, s);
-        else zero_i32(static_cast<int32_t*>(scratch), (int64_t)(D + 3) * nid, s);
-        const fs_particles& F = from[k];
-        const fs_particles& T = to[k];
-        const unsigned nt = (unsigned)h->L.ntiles;
-        if (rb == 8) {
-            PBuf<double> pf = sections<double>(F.buf[F.cur], F.capacity, D);
-            PBuf<double> pt = sections<double>(T.buf[T.cur], T.capacity, D);
-            k_lam_scatter<double><<<nt, 256, 0, s>>>(h->G, pf.id, F.tile_count[F.cur], F.tile_cap,
-                                                     plam<double>(lam, k, a, D), D, static_cast<double*>(scratch), nid);
-            k_lam_gather<double><<<nt, 256, 0, s>>>(h->G, pt.id, T.tile_count[T.cur], T.tile_cap,
-                                                    plam<double>(lam, k, b, D), D, static_cast<double*>(scratch), nid);
-        } else {
-            PBuf<float> pf = sections<float>(F.buf[F.cur], F.capacity, D);
-            PBuf<float> pt = sections<float>(T.buf[T.cur], T.capacity, D);
-            k_lam_scatter<float><<<nt, 256, 0, s>>>(h->G, pf.id, F.tile_count[F.cur], F.tile_cap,
-                                                    plam<float>(lam, k, a, D), D, static_cast<float*>(scratch), nid);
-            k_lam_gather<float><<<nt, 256, 0, s>>>(h->G, pt.id, T.tile_count[T.cur], T.tile_cap,
-                                                   plam<float>(lam, k, b, D), D, static_cast<float*>(scratch), nid);
-        }
-    }
-    lam->cur = b;
-    return hip_check(h, hipGetLastError(), "adjoint relayout launch");
+    if (h->cfg.precision == 64) return park_impl<double>(h, from, lam, scratch, nullptr, nid, true, s);
+    return park_impl<float>(h, from, lam, scratch, nullptr, nid, true, s);
 }
 
-int fs_adjoint_init(fs_handle* h, const fs_particles* sp0, const fs_fields* f0, fs_adjoint* lam, double* grads,
-                    hipStream_t s) {
-    if (!h || !sp0 || !f0 || !lam || !grads) return fail(h, FS_EINVAL, "NULL argument");
-    if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "the adjoint needs deposit_mode 1");
-    if (h->cfg.c_light != 0.0) return fail(h, FS_EINVAL, "the adjoint covers the non-relativistic push only");
-    if (h->cfg.wall_model != 0) return fail(h, FS_EINVAL, "the adjoint covers the eq. (1) wall only");
-    if (h->cfg.coupling != 1) return fail(h, FS_EINVAL, "the adjoint covers the first-order coupling only");
-    if (h->cfg.smooth != 0) return fail(h, FS_EINVAL, "the adjoint covers the unfiltered moments only");
-    if (!f0->B) return fail(h, FS_EINVAL, "NULL field array");
+int fs_adjoint_unpark(fs_handle* h, const fs_packed* to, fs_adjoint* lam, const void* scratch, int64_t nid,
+                      hipStream_t s) {
+    if (!h || !to || !lam || !scratch) return fail(h, FS_EINVAL, "NULL argument");
+    if (nid < 0) return fail(h, FS_EINVAL, "negative id range");
     int rc = check_adjoint(h, lam);
-    if (!rc) rc = check_particles(h, sp0);
+    if (!rc) rc = check_packed(h, to, lam, false);
     if (rc) return rc;
-    auto run = [&]() -> int { FS_DISPATCH(h, (adjoint_init_impl<R, D, S>(h, sp0, f0, lam, grads, s))); };
+    if (h->cfg.precision == 64) return park_impl<double>(h, to, lam, nullptr, scratch, nid, false, s);
+    return park_impl<float>(h, to, lam, nullptr, scratch, nid, false, s);
+}
+
+int fs_adjoint_init(fs_handle* h, const fs_packed* p0, const fs_fields* f0, fs_adjoint* lam, double* grads,
+                    hipStream_t s) {
+    if (!h || !p0 || !f0 || !lam || !grads) return fail(h, FS_EINVAL, "NULL argument");
+    if (int rc = check_reverse_cfg(h)) return rc;
+    if (!f0->B || !f0->mom[0] || (h->has_cr && !f0->mom[1])) return fail(h, FS_EINVAL, "NULL field array");
+    int rc = check_adjoint(h, lam);
+    if (!rc) rc = check_packed(h, p0, lam, false);
+    if (rc) return rc;
+    auto run = [&]() -> int { FS_DISPATCH(h, (adjoint_init_impl<R, D, S>(h, p0, f0, lam, grads, s))); };
     return run();
 }
 
@@ -1325,22 +1390,6 @@ int read_impl(fs_handle* h, const fs_particles* sp, int64_t* n_out, int64_t* cel
     return hip_check(h, e, "particle readback");
 }
 
-#define FS_DISPATCH_RD(h, CALL)                                                  \
-    do {                                                                         \
-        const int _d = (h)->cfg.dim;                                             \
-        if ((h)->cfg.precision == 32) {                                          \
-            using R = float;                                                     \
-            if (_d == 1) { constexpr int D = 1; return CALL; }                   \
-            if (_d == 2) { constexpr int D = 2; return CALL; }                   \
-            if (_d == 3) { constexpr int D = 3; return CALL; }                   \
-        } else {                                                                 \
-            using R = double;                                                    \
-            if (_d == 1) { constexpr int D = 1; return CALL; }                   \
-            if (_d == 2) { constexpr int D = 2; return CALL; }                   \
-            if (_d == 3) { constexpr int D = 3; return CALL; }                   \
-        }                                                                        \
-        return fail(h, FS_EINVAL, "unsupported configuration");                  \
-    } while (0)
 
 // ---------------------------------------------------------------------------
 // checkpoints: header, then per species the per-tile offsets and the live
@@ -1680,8 +1729,8 @@ int fs_adjoint_seed(fs_handle* h, const fs_fields* f, fs_adjoint* lam, double* g
             void* arr[2] = {d < h->cfg.dim ? lam->x[k][lam->cur][d] : nullptr, lam->v[k][lam->cur][d]};
             for (void* a : arr) {
                 if (!a) continue;
-                if (rb == 8) zero_u64(a, h->L.capacity[k], s);
-                else zero_i32(static_cast<int32_t*>(a), h->L.capacity[k], s);
+                if (rb == 8) zero_u64(a, lam->capacity[k], s);
+                else zero_i32(static_cast<int32_t*>(a), lam->capacity[k], s);
             }
         }
     zero_u64(lam->lE, 6 * h->L.nnode, s);

@@ -102,6 +102,11 @@ class FsAdjoint(C.Structure):
                 ("cur", C.c_int32), ("pad", C.c_int32), ("lB", C.c_void_p), ("lE", C.c_void_p)]
 
 
+class FsPacked(C.Structure):
+    _fields_ = [("buf", C.c_void_p * 2), ("toff", C.c_void_p * 2), ("dst", C.c_void_p * 2), ("n", C.c_int64 * 2),
+                ("status", C.c_void_p)]
+
+
 DEPOSIT_MODE = {"fixed": 0, "continuous": 1, 0: 0, 1: 1}
 
 _lib = None
@@ -144,9 +149,12 @@ def library():
         L.fs_timing_read.argtypes = [vp, vp, vp, vp]
         R, A = C.POINTER(FsRecord), C.POINTER(FsAdjoint)
         L.fs_step_record.argtypes = [vp, P, F, i64, R, C.POINTER(FsStats), vp]
-        L.fs_adjoint_step.argtypes = [vp, P, F, P, F, R, i64, A, vp, vp]
-        L.fs_adjoint_init.argtypes = [vp, P, F, A, vp, vp]
-        L.fs_adjoint_relayout.argtypes = [vp, P, P, A, vp, i64, vp]
+        K = C.POINTER(FsPacked)
+        L.fs_tape_pack.argtypes = [vp, P, K, P, R, K, vp]
+        L.fs_adjoint_step.argtypes = [vp, K, F, K, F, i64, i64, A, vp, vp]
+        L.fs_adjoint_park.argtypes = [vp, K, A, vp, i64, vp]
+        L.fs_adjoint_unpark.argtypes = [vp, K, A, vp, i64, vp]
+        L.fs_adjoint_init.argtypes = [vp, K, F, A, vp, vp]
         L.fs_precursor_loss.argtypes = [vp, F, vp, vp]
         L.fs_adjoint_seed.argtypes = [vp, F, A, vp, vp]
         _lib = L
@@ -160,7 +168,8 @@ def exported_symbols():
             "fs_load_particles", "fs_read_particles", "fs_set_clock", "fs_next_id", "fs_diagnostics",
             "fs_phase_space", "fs_bperp_spectrum", "fs_checkpoint_bytes", "fs_checkpoint", "fs_restore",
             "fs_timing_enable", "fs_timing_read", "fs_step_record", "fs_adjoint_step", "fs_adjoint_init",
-            "fs_precursor_loss", "fs_adjoint_seed", "fs_bperp_spectrum_noalloc", "fs_adjoint_relayout"]
+            "fs_precursor_loss", "fs_adjoint_seed", "fs_bperp_spectrum_noalloc", "fs_tape_pack",
+            "fs_adjoint_park", "fs_adjoint_unpark"]
 
 
 def make_config(p: dict) -> FsConfig:

@@ -196,13 +196,12 @@ def test_precursor_loss_and_seed_through_the_c_abi():
     want_lB = np.zeros((3, int(sim.L.ncent)))
     want_lB[1:, i >= nx // 2] = 2.0 * B[i >= nx // 2, 1:].T
     np.testing.assert_array_equal(lB.cpu().numpy(), want_lB)
-    # an adjoint state smaller than a species' particle buffers is refused,
-    # and so is a buffer index outside {0, 1}
-    lam.capacity[1] = int(sim.L.capacity[1]) - 1
+    # a negative capacity is refused, and so is a buffer index outside {0, 1}
+    lam.capacity[1] = -1
     with pytest.raises(F.FsError) as e:
         sim._check(sim.lib.fs_adjoint_seed(sim.h, C.byref(sim.f), C.byref(lam), C.c_void_p(grads.data_ptr()),
                                            sim.stream))
-    assert e.value.code == F.FS_ECAPACITY
+    assert e.value.code == F.FS_EINVAL
     lam.capacity[1] = int(sim.L.capacity[1])
     lam.cur = 2
     with pytest.raises(F.FsError) as e:
@@ -280,3 +279,89 @@ def test_step_record_maps_every_ion_to_where_the_step_put_it(dim, wall):
         assert nrefl == st["reflected"] and nrem == st["transmitted"] + st["escaped"] + st["open_removed"], st
         total_refl += nrefl
     assert total_refl > 0
+
+
+@pytest.mark.parametrize("dim,wall", [(1, "faux_shock"), (2, "specular")])
+def test_tape_pack_keeps_the_live_ions_and_the_record_in_packed_indices(dim, wall):
+    """fs_tape_pack of the states before and after a recorded step: the tile
+    offsets are the running sums of the live counts, each tile's ions appear
+    in bin order (bottom run, then the top run from the top down) with every
+    section copied, and the packed record of the state before maps each ion
+    to the packed index of the same ion after the step (the bin record,
+    translated).  A packed state one ion too small sets the status flag."""
+    import ctypes as C
+    import torch
+    from paper_2507_14282_amd import adjoint as A
+    from paper_2507_14282_amd import fshybrid as F
+    kw = dict(nx=48, dx=0.5, ppc=8) if dim == 1 else dict(nx=24, ny=8, dx=0.5, ppc=8)
+    p = W.params(dim=dim, ppc_cr=4, n_cr=0.05, wall_th=wall, wall_cr="faux_shock", u_sh=19.3, dt=0.0047,
+                 precision=32, deposit_mode="continuous", seed=29, **kw)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    for s in range(20):
+        sim.step(s)
+    nsp, ntiles = 2, int(sim.L.ntiles)
+    status = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    pre_sec = [{k2: (v.clone() if torch.is_tensor(v) else [x.clone() for x in v] if isinstance(v, list) else v)
+                for k2, v in sim.sections(k).items()} for k in range(nsp)]
+    n_pre = [sim.count(k) for k in range(nsp)]
+    P0 = A._Packed(sim, nsp, [n + 5 for n in n_pre], status)
+    sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(P0.s), None, None, None, sim.stream))
+    pre_sp = (F.FsParticles * 2)()
+    C.memmove(pre_sp, sim.sp, C.sizeof(pre_sp))
+    rec = F.FsRecord()
+    keep = []
+    for k in range(nsp):
+        t = torch.full((int(sim.L.capacity[k]),), -7, dtype=torch.int32, device="cuda:0")
+        rec.dst[k], rec.capacity[k] = t.data_ptr(), int(sim.L.capacity[k])
+        keep.append(t)
+    sim.step_record(20, rec)
+    n_post = [sim.count(k) for k in range(nsp)]
+    P1 = A._Packed(sim, nsp, n_post, status)
+    sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(P1.s), pre_sp, C.byref(rec), C.byref(P0.s),
+                                    sim.stream))
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    for k in range(nsp):
+        for P, sec, n in ((P0, pre_sec[k], n_pre[k]), (P1, sim.sections(k), n_post[k])):
+            cap = sec["tile_cap"]
+            cnt = sec["counts"].cpu().numpy()
+            live = _live_slots(cnt, ntiles, cap)
+            pk = P.sections(k)
+            toff = pk["toff"].cpu().numpy().astype(np.int64)
+            per = np.minimum(cnt[:ntiles] + cnt[ntiles:], cap)
+            assert toff[0] == 0 and np.array_equal(np.diff(toff), per) and toff[-1] == n
+            order = []
+            for t in range(ntiles):
+                lo, hi = int(cnt[t]), int(cnt[ntiles + t])
+                order += list(range(t * cap, t * cap + lo)) + list(range(t * cap + cap - 1, t * cap + cap - 1 - hi, -1))
+            order = np.array(order, dtype=np.int64)
+            assert np.array_equal(np.sort(order), np.sort(live))
+            for name in ("cell", "id"):
+                assert np.array_equal(pk[name][:n].cpu().numpy(), sec[name].cpu().numpy()[order])
+            for name in ("off", "v"):
+                for a, b in zip(pk[name], sec[name]):
+                    assert np.array_equal(a[:n].cpu().numpy(), b.cpu().numpy()[order])
+        ids0 = P0.sections(k)["id"][:n_pre[k]].cpu().numpy()
+        ids1 = P1.sections(k)["id"][:n_post[k]].cpu().numpy()
+        d = P0.sections(k)["dst"][:n_pre[k]].cpu().numpy().astype(np.int64)
+        moved = d != -1
+        q = np.where(d >= 0, d, -2 - d)
+        assert np.all(q[moved] < n_post[k])
+        assert np.array_equal(ids1[q[moved]], ids0[moved])
+        assert len(np.unique(q[moved])) == moved.sum()
+        # the same decisions as the bin record
+        bin_d = keep[k].cpu().numpy()
+        cap = pre_sec[k]["tile_cap"]
+        cnt = pre_sec[k]["counts"].cpu().numpy()
+        order = []
+        for t in range(ntiles):
+            lo, hi = int(cnt[t]), int(cnt[ntiles + t])
+            order += list(range(t * cap, t * cap + lo)) + list(range(t * cap + cap - 1, t * cap + cap - 1 - hi, -1))
+        bd = bin_d[np.array(order, dtype=np.int64)]
+        assert np.array_equal(bd == -1, d == -1) and np.array_equal(bd <= -2, d <= -2)
+    # one ion short
+    small = A._Packed(sim, nsp, [n - 1 for n in n_post], status)
+    sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(small.s), None, None, None, sim.stream))
+    torch.cuda.synchronize()
+    assert int(status.item()) != 0
