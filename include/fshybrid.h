@@ -443,7 +443,8 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
  * prev->dst in packed indices of *out.  Asynchronous on s; an overflow of
  * n[k] sets *out->status (*prev->status for a record entry that points past
  * out's n).  FS_EINVAL on a NULL argument (prev_sp, rec and prev are all
- * given or all NULL). */
+ * given or all NULL), FS_ECAPACITY if a species' capacity does not fit the
+ * int32 tile offsets (above 2^31 - 3 slots). */
 int fs_tape_pack(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_particles* prev_sp,
                  const fs_record* rec, fs_packed* prev, hipStream_t s);
 
@@ -471,9 +472,10 @@ int fs_adjoint_step(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, con
  * by particle id (after zeroing it); fs_adjoint_unpark reads them back into
  * buffer lam->cur at the packed indices of `to` (zero for an id scratch does
  * not hold).  scratch: device, (dim + 3) * nid reals of the particle
- * precision per call, nid above every id; ids >= nid are skipped.  FS_EINVAL
- * on a NULL argument or a negative nid, FS_ECAPACITY if an adjoint buffer
- * is shorter than the packed state. */
+ * precision per species (species 1 after species 0), nid above every id;
+ * ids >= nid are skipped; its layout between a park and an unpark is the
+ * library's own.  FS_EINVAL on a NULL argument or a negative nid,
+ * FS_ECAPACITY if an adjoint buffer is shorter than the packed state. */
 int fs_adjoint_park(fs_handle* h, const fs_packed* from, fs_adjoint* lam, void* scratch, int64_t nid,
                     hipStream_t s);
 int fs_adjoint_unpark(fs_handle* h, const fs_packed* to, fs_adjoint* lam, const void* scratch, int64_t nid,

@@ -77,34 +77,48 @@ class _State:
         f.mom[1] = self.mom[1].data_ptr() if len(self.mom) > 1 else None
         return f
 
+    # The structs of a state only hold the addresses of its own tensors, so
+    # each is built once and kept on the state (the reverse pass would
+    # otherwise spend more host time building them than the GPU spends on
+    # the small boxes' steps).
+    def sp(self, sim: F.Simulation):
+        if "_sp" not in self.__dict__:
+            self._sp = self.particles(sim)
+        return self._sp
+
+    def f(self, sim: F.Simulation) -> F.FsFields:
+        if "_f" not in self.__dict__:
+            self._f = self.fields(sim)
+        return self._f
+
+    def step_to(self, sim: F.Simulation, post: "_State"):
+        """fs_particles of a step that reads this state's bins and writes
+        post's (cur 0)."""
+        key = post.buf[0].data_ptr()
+        cache = self.__dict__.setdefault("_to", {})
+        if key not in cache:
+            sp = self.particles(sim)
+            for k in range(len(self.buf)):
+                sp[k].buf[1] = post.buf[k].data_ptr()
+                sp[k].tile_count[1] = post.cnt[k].data_ptr()
+            cache[key] = sp
+        return cache[key]
+
 
 class _Fields:
-    """The grid part of a tape state: B, E, the gather grid and the moment
-    grids (filled by the recorded step that produces the state)."""
+    """The grid part of a tape state: B, the gather grid and the moment grids
+    (filled by the recorded step that produces the state).  The reverse step
+    does not read E, so every tape state's step writes E into one shared
+    array."""
 
-    def __init__(self, sim: F.Simulation, nsp: int):
+    def __init__(self, sim: F.Simulation, nsp: int, E: torch.Tensor):
         self.B = torch.empty_like(sim.B)
-        self.E = torch.empty_like(sim.E)
+        self.E = E
         self.gather = torch.empty_like(sim.gather)
         self.mom = [torch.empty_like(m) for m in sim.mom[:nsp]]
 
     fields = _State.fields
-
-    def bytes(self) -> int:
-        return int(sum(t.numel() * t.element_size() for t in [self.B, self.E, self.gather] + self.mom))
-
-
-class _Step:
-    """The bins of one state with the fields of another: a recorded step
-    reads the particles of one working buffer and writes the other, while
-    its fields go to the tape entry of the state it produces."""
-
-    def __init__(self, bins: _State, fields):
-        self.buf, self.cnt = bins.buf, bins.cnt
-        self.B, self.E, self.gather, self.mom = fields.B, fields.E, fields.gather, fields.mom
-
-    particles = _State.particles
-    fields = _State.fields
+    f = _State.f
 
 
 def _section_bytes(n: int, dim: int, rb: int) -> int:
@@ -162,19 +176,17 @@ class _Packed:
         return sum(_section_bytes(int(n[k]), dim, rb) + 4 * (int(n[k]) + int(sim.L.ntiles) + 2) for k in range(nsp))
 
 
-def _recorded_step(sim: F.Simulation, n: int, a, b, rec: F.FsRecord):
-    """Step n from state a into state b without copying particles: the
-    step reads a's buffers and writes b's (the field update works in place,
-    so B and the gather grid of a are first copied into b)."""
-    b.B.copy_(a.B)
-    b.gather.copy_(a.gather)
-    b.E.copy_(a.E)
-    sp = a.particles(sim)
-    for k in range(len(a.buf)):
-        sp[k].buf[1] = b.buf[k].data_ptr()
-        sp[k].tile_count[1] = b.cnt[k].data_ptr()
-    f = b.fields(sim)
-    rc = sim.lib.fs_step_record(sim.h, sp, C.byref(f), int(n), C.byref(rec), None, sim.stream)
+def _recorded_step(sim: F.Simulation, n: int, pre: _State, f_pre, post: _State, f_post, rec: F.FsRecord):
+    """Step n from the bins of `pre` (fields f_pre) into the bins of `post`
+    (fields f_post) without copying particles.  The field update works in
+    place, so B and the gather grid are first copied across; E is only
+    written."""
+    f_post.B.copy_(f_pre.B)
+    f_post.gather.copy_(f_pre.gather)
+    sp = pre.step_to(sim, post)
+    rc = sim.lib.fs_step_record(sim.h, sp, C.byref(f_post.f(sim)), int(n), C.byref(rec), None, sim.stream)
+    for k in range(2):
+        sp[k].cur = 0          # the step flips it
     sim._check(rc)
 
 
@@ -209,16 +221,19 @@ def _state_bytes(sim: F.Simulation, nsp: int) -> int:
 
 
 def _fields_bytes(sim: F.Simulation, nsp: int) -> int:
-    return int(sum(x.numel() * x.element_size() for x in [sim.B, sim.E, sim.gather] + list(sim.mom[:nsp])))
+    """Bytes of the grids of one tape state (E is shared)."""
+    return int(sum(x.numel() * x.element_size() for x in [sim.B, sim.gather] + list(sim.mom[:nsp])))
 
 
 def _fixed_bytes(sim: F.Simulation, nsp: int, n) -> int:
     """Bytes the reverse pass holds besides checkpoints and tape: two working
-    bin states, the bin record, the adjoints (two buffers of n per species
-    and the grid adjoints) and the id-indexed parking scratch."""
+    bin states, the bin record, the tape's shared E, the adjoints (two
+    buffers of n per species and the grid adjoints) and the id-indexed
+    parking scratch."""
     dim = int(sim.p["dim"])
     rb = torch.finfo(sim.real).bits // 8
     work = 2 * _state_bytes(sim, nsp) + sum(4 * int(sim.L.capacity[k]) for k in range(nsp))
+    work += sim.E.numel() * sim.E.element_size()
     lam = sum(2 * (dim + 3) * rb * int(n[k]) for k in range(nsp)) + 8 * (3 * int(sim.L.ncent) + 6 * int(sim.L.nnode))
     park = nsp * (dim + 3) * rb * int(sim.next_id + sim.next_id // 8 + 4096)
     return work + lam + park
@@ -343,7 +358,8 @@ class AdjointRun:
         nid = self.nid + self.nid // 8 + 4096
         scratch = torch.empty(self.nsp * (dim + 3) * nid, dtype=sim.real, device=dev)
         work = [_State(sim, self.nsp, copy=False) for _ in range(2)]
-        fields = [_Fields(sim, self.nsp) for _ in range(K)]
+        E = torch.empty_like(sim.E)
+        fields = [_Fields(sim, self.nsp, E) for _ in range(K)]
         packed = [_Packed(sim, self.nsp, n, status) for _ in range(K + 1)]
         nbytes = _fixed_bytes(sim, self.nsp, n) + K * (_fields_bytes(sim, self.nsp) + _Packed.bytes(sim, self.nsp, n))
         self._bufs = dict(key=self._key(sim), n=n, nid=nid, lam=lam, keep=keep, lB=lB, lE=lE, rec=rec,
@@ -373,15 +389,14 @@ class AdjointRun:
             ck = self.checkpoints[s0]
             sim.set_clock(ck.next_id)
             flds = [ck] + bufs["fields"]
-            sim._check(lib.fs_tape_pack(sim.h, ck.particles(sim), C.byref(P[0].s), None, None, None, stream))
+            sim._check(lib.fs_tape_pack(sim.h, ck.sp(sim), C.byref(P[0].s), None, None, None, stream))
             pre, id0 = ck, []
             for j, n in enumerate(range(s0, s1)):
                 post = bufs["work"][j % 2]
-                a, b = _Step(pre, flds[j]), _Step(post, flds[j + 1])
-                _recorded_step(sim, n, a, b, rec)
+                _recorded_step(sim, n, pre, flds[j], post, flds[j + 1], rec)
                 id0.append(int(rec.id0))
-                sim._check(lib.fs_tape_pack(sim.h, b.particles(sim), C.byref(P[j + 1].s), a.particles(sim),
-                                            C.byref(rec), C.byref(P[j].s), stream))
+                sim._check(lib.fs_tape_pack(sim.h, post.sp(sim), C.byref(P[j + 1].s), pre.sp(sim), C.byref(rec),
+                                            C.byref(P[j].s), stream))
                 pre = post
             m = s1 - s0
             if parked:
@@ -390,13 +405,12 @@ class AdjointRun:
                 # another order
                 sim._check(lib.fs_adjoint_unpark(sim.h, C.byref(P[m].s), C.byref(lam), scratch, nid, stream))
             for j in range(m - 1, -1, -1):
-                f_n, f_n1 = flds[j].fields(sim), flds[j + 1].fields(sim)
-                rc = lib.fs_adjoint_step(sim.h, C.byref(P[j].s), C.byref(f_n), C.byref(P[j + 1].s), C.byref(f_n1),
-                                         id0[j], s0 + j, C.byref(lam), gptr, stream)
+                rc = lib.fs_adjoint_step(sim.h, C.byref(P[j].s), C.byref(flds[j].f(sim)), C.byref(P[j + 1].s),
+                                         C.byref(flds[j + 1].f(sim)), id0[j], s0 + j, C.byref(lam), gptr, stream)
                 sim._check(rc)
             if s0 == 0:
-                f0 = ck.fields(sim)
-                sim._check(lib.fs_adjoint_init(sim.h, C.byref(P[0].s), C.byref(f0), C.byref(lam), gptr, stream))
+                sim._check(lib.fs_adjoint_init(sim.h, C.byref(P[0].s), C.byref(ck.f(sim)), C.byref(lam), gptr,
+                                               stream))
             else:
                 sim._check(lib.fs_adjoint_park(sim.h, C.byref(P[0].s), C.byref(lam), scratch, nid, stream))
                 parked = True

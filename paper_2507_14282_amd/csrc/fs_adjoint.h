@@ -172,48 +172,85 @@ __device__ __forceinline__ PackShare pack_share(const int32_t* toff, int64_t n, 
 // The tape: particle states packed to their live ions
 // ---------------------------------------------------------------------------
 
-// Tile offsets of a packed state: toff[t] = ions of the tiles before t (one
-// workgroup of 1024 threads; each thread sums a run of tiles, a block scan
-// of the run totals places them).  Sets *status when the total exceeds n.
+// Tile offsets of a packed state: toff[t] = ions of the tiles before t.  One
+// workgroup of 1024 threads walks the tiles in chunks of 4096, four adjacent
+// tiles a thread (neighbouring threads read neighbouring counts), with a
+// wave scan and a scan of the 16 wave totals per chunk.  Sets *status when
+// the total exceeds n.
 __global__ __launch_bounds__(1024) void k_tape_offsets(const int32_t* __restrict__ cnt, int ntiles, int64_t cap,
                                                        int32_t* __restrict__ toff, int64_t n,
                                                        int32_t* __restrict__ status) {
-    __shared__ long part[1024];
-    const int t = threadIdx.x;
-    const int per = (ntiles + 1023) / 1024;
-    const int b = min(ntiles, t * per), e = min(ntiles, b + per);
-    auto live = [&](int i) { return min((long)cnt[i] + cnt[ntiles + i], (long)cap); };
-    long sum = 0;
-    for (int i = b; i < e; ++i) sum += live(i);
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const long v = t >= off ? part[t - off] : 0;
+    __shared__ long long wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    long long carry = 0;
+    for (int base = 0; base < ntiles; base += 4096) {
+        long long c[4], loc = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + 4 * t + u;
+            c[u] = i < ntiles ? min((long long)cnt[i] + cnt[ntiles + i], (long long)cap) : 0;
+            loc += c[u];
+        }
+        long long x = loc;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const long long y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
         __syncthreads();
-        part[t] += v;
+        long long before = 0, total = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const long long v = wsum[q];
+            before += q < w ? v : 0;
+            total += v;
+        }
+        long long run = carry + before + x - loc;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + 4 * t + u;
+            if (i < ntiles) toff[i] = (int32_t)run;
+            run += c[u];
+        }
+        carry += total;
         __syncthreads();
     }
-    long run = t > 0 ? part[t - 1] : 0;
-    for (int i = b; i < e; ++i) {
-        toff[i] = (int32_t)run;
-        run += live(i);
-    }
-    if (t == 1023) {
-        toff[ntiles] = (int32_t)part[1023];
-        if (part[1023] > n) *status = 1;
+    if (t == 0) {
+        toff[ntiles] = (int32_t)carry;
+        if (carry > n) *status = 1;
     }
 }
 
+// The ranks [begin, end) of a tile's m live ions that workgroup `part` of
+// the tile's `split` takes.
+struct RankShare {
+    int tile, begin, end;
+};
+__device__ __forceinline__ RankShare rank_share(const int32_t* cnt, int ntiles, int64_t cap, int split, int& lo) {
+    RankShare r;
+    r.tile = blockIdx.x / split;
+    const int part = blockIdx.x % split;
+    lo = cnt[r.tile];
+    const int m = min(lo + cnt[ntiles + r.tile], (int)cap);
+    const int chunk = (m + split - 1) / split;
+    r.begin = min(m, part * chunk);
+    r.end = min(m, r.begin + chunk);
+    return r;
+}
+
 // Copy of every tile's live ions, in bin order, to its packed range (ions
-// past n are dropped; k_tape_offsets flagged them).
+// past n are dropped; k_tape_offsets flagged them); `split` workgroups a
+// tile.
 template <typename R, int D>
 __global__ __launch_bounds__(256) void k_tape_pack(Geo G, PBuf<R> in, const int32_t* __restrict__ cnt, int64_t cap,
-                                                   const int32_t* __restrict__ toff, int64_t n, PBuf<R> out) {
-    const int tile = blockIdx.x;
-    const int lo = cnt[tile];
-    const int m = min(lo + cnt[G.ntiles + tile], (int)cap);
+                                                   const int32_t* __restrict__ toff, int64_t n, PBuf<R> out,
+                                                   int split) {
+    int lo;
+    const RankShare rs = rank_share(cnt, G.ntiles, cap, split, lo);
+    const int tile = rs.tile;
     const long base = toff[tile];
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    for (int i = rs.begin + threadIdx.x; i < rs.end; i += blockDim.x) {
         const long dst = base + i;
         if (dst >= n) break;
         const long src = bin_slot(tile, cap, lo, i);
@@ -229,18 +266,18 @@ __global__ __launch_bounds__(256) void k_tape_pack(Geo G, PBuf<R> in, const int3
 // A step's record from bin slots to packed indices: for each ion of the
 // input state (tile t, rank i in its bin, packed at toff_in[t] + i), the
 // output bin slot it went to, turned into the packed index of the output
-// state (the slot's tile, its rank in that bin).
+// state (the slot's tile, its rank in that bin); `split` workgroups a tile.
 __global__ __launch_bounds__(256) void k_tape_record(Geo G, const int32_t* __restrict__ cnt_in, int64_t cap,
                                                      const int32_t* __restrict__ toff_in, int64_t n_in,
                                                      const int32_t* __restrict__ dst_bin,
                                                      const int32_t* __restrict__ cnt_out,
                                                      const int32_t* __restrict__ toff_out, int64_t n_out,
-                                                     int32_t* __restrict__ dst, int32_t* __restrict__ status) {
-    const int tile = blockIdx.x;
-    const int lo = cnt_in[tile];
-    const int m = min(lo + cnt_in[G.ntiles + tile], (int)cap);
+                                                     int32_t* __restrict__ dst, int32_t* __restrict__ status, int split) {
+    int lo;
+    const RankShare rs = rank_share(cnt_in, G.ntiles, cap, split, lo);
+    const int tile = rs.tile;
     const long base = toff_in[tile];
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    for (int i = rs.begin + threadIdx.x; i < rs.end; i += blockDim.x) {
         const long p = base + i;
         if (p >= n_in) break;
         const int32_t d = dst_bin[bin_slot(tile, cap, lo, i)];
@@ -291,118 +328,185 @@ __device__ __forceinline__ double inject_vjp(const Geo& G, uint64_t step, uint64
     return (lv[0] * dvx + lv[1] * G.cr_w * cos(phi) * dst + lv[2] * G.cr_w * sin(phi) * dst + lx * dxi) * G.rinv;
 }
 
-// Deposit transpose over the ions of a packed state (the state at n+1):
-// lam(x) += sum_nodes dW/dx (lam_R + lam_G . v), lam(v) += sum W lam_G,
-// added to the adjoints at the ions' packed indices.  The ions the step injected
-// (ids id0 .. id0 + ninj - 1, thermal first, nth of them) then have their
-// final adjoint, which goes into dL/du_sh through their injection.
-template <typename R, int D, int S>
-__global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ toff, int64_t n,
-                                                     const double* __restrict__ lM, PLam<R> lam, int split,
-                                                     uint64_t step, int64_t id0, int64_t nth, int64_t ninj,
-                                                     double* grads) {
+// Staging of the moment adjoints of a tile's stencil nodes into LDS,
+// [node][R, Gx, Gy, Gz] (nodes outside the deposit grid hold zero).
+template <int D, int S>
+__device__ __forceinline__ void stage_moment_adj(const Geo& G, const double* __restrict__ lM, int gx0, int gy0, int gz0,
+                                                 double* sm) {
     using X = Extent<D, S>;
-    using T = TileShape<D>;
-    constexpr int LO = Stencil<S>::LO, N = Stencil<S>::N;
-    constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
-    // the moment adjoints of the tile's stencil nodes, [node][R, Gx, Gy, Gz];
-    // nodes outside the deposit grid hold zero
-    __shared__ double sm[4 * X::GN];
-    const PackShare ts = pack_share(toff, n, split);
-    const int tile = ts.tile;
-    const int tx = tile % G.ntx;
-    const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
-    const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
-    const int gx0 = tx * T::X - LO, gy0 = D >= 2 ? ty * T::Y - LO : 0, gz0 = D >= 3 ? tz * T::Z - LO : 0;
     for (int l = threadIdx.x; l < X::GN; l += blockDim.x) {
         const int lx = l % X::GX, ly = (l / X::GX) % X::GY, lz = l / (X::GX * X::GY);
         const long gi = dep_index(gx0 + lx, gy0 + ly, gz0 + lz, G);
 #pragma unroll
         for (int q = 0; q < 4; ++q) sm[4 * l + q] = gi < 0 ? 0.0 : lM[4 * gi + q];
     }
-    __syncthreads();
-    double acc = 0.0;
-    for (long src = ts.begin + threadIdx.x; src < ts.end; src += blockDim.x) {
-        const int32_t pc = in.cell[src];
-        const int cx = cell_x(pc, G), cy = D >= 2 ? cell_y(pc, G) : 0, cz = D >= 3 ? cell_z(pc, G) : 0;
-        double w[3][3], dw[3][3];
-        int rel[3] = {0, 0, 0};
+}
+
+// Deposit transpose of one ion (cell pc, offsets o, velocity v):
+// gx[d] = sum_nodes dW/dx_d (lam_R + lam_G . v) (per cell of position),
+// gv = sum_nodes W lam_G.  The moment adjoints come from sm, staged for the
+// nodes [gx0, gx0 + GX) x [gy0, ..) x [gz0, ..), when the ion's stencil lies
+// there, else from lM in global memory.
+template <typename R, int D, int S>
+__device__ __forceinline__ void deposit_vjp(const Geo& G, const double* sm, const double* __restrict__ lM, int gx0,
+                                            int gy0, int gz0, int32_t pc, const R* o, const R* vr, double gx[3],
+                                            double gv[3]) {
+    using X = Extent<D, S>;
+    constexpr int N = Stencil<S>::N;
+    constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
+    const int cx = cell_x(pc, G), cy = D >= 2 ? cell_y(pc, G) : 0, cz = D >= 3 ? cell_z(pc, G) : 0;
+    double w[3][3], dw[3][3];
+    int rel[3] = {0, 0, 0};
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            w[d][0] = 1.0; w[d][1] = w[d][2] = 0.0;
-            dw[d][0] = dw[d][1] = dw[d][2] = 0.0;
-        }
+    for (int d = 0; d < 3; ++d) {
+        w[d][0] = 1.0; w[d][1] = w[d][2] = 0.0;
+        dw[d][0] = dw[d][1] = dw[d][2] = 0.0;
+    }
 #pragma unroll
-        for (int d = 0; d < D; ++d) weights_dw<S>((double)in.off[d][src], rel[d], w[d], dw[d]);
-        const double v[3] = {(double)in.v[0][src], (double)in.v[1][src], (double)in.v[2][src]};
-        double gx[3] = {0, 0, 0}, gv[3] = {0, 0, 0};
-        // a binned ion lies in its tile; the clamp only guards a corrupt state
-        const int lx0 = min(max(cx - gx0 + rel[0], 0), X::GX - N);
-        const int ly0 = D >= 2 ? min(max(cy - gy0 + rel[1], 0), X::GY - N) : 0;
-        const int lz0 = D >= 3 ? min(max(cz - gz0 + rel[2], 0), X::GZ - N) : 0;
+    for (int d = 0; d < D; ++d) weights_dw<S>((double)o[d], rel[d], w[d], dw[d]);
+    const double v[3] = {(double)vr[0], (double)vr[1], (double)vr[2]};
+    const int ax = cx + rel[0], ay = cy + rel[1], az = cz + rel[2];
+    const int lx0 = ax - gx0, ly0 = D >= 2 ? ay - gy0 : 0, lz0 = D >= 3 ? az - gz0 : 0;
+    const bool inside = lx0 >= 0 && lx0 <= X::GX - N && ly0 >= 0 && ly0 <= X::GY - NY && lz0 >= 0 &&
+                        lz0 <= X::GZ - NZ;
 #pragma unroll
-        for (int c = 0; c < NZ; ++c)
+    for (int d = 0; d < 3; ++d) gx[d] = gv[d] = 0.0;
 #pragma unroll
-            for (int b = 0; b < NY; ++b)
+    for (int c = 0; c < NZ; ++c)
 #pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    const double* m = sm + 4 * (((lz0 + c) * X::GY + (ly0 + b)) * X::GX + (lx0 + a));
-                    const double lm = m[0] + m[1] * v[0] + m[2] * v[1] + m[3] * v[2];
-                    const double W = w[0][a] * w[1][b] * w[2][c];
-                    gx[0] += dw[0][a] * w[1][b] * w[2][c] * lm;
-                    if (D >= 2) gx[1] += w[0][a] * dw[1][b] * w[2][c] * lm;
-                    if (D >= 3) gx[2] += w[0][a] * w[1][b] * dw[2][c] * lm;
+        for (int b = 0; b < NY; ++b)
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) gv[d] += W * m[1 + d];
+            for (int a = 0; a < N; ++a) {
+                double m[4];
+                if (inside) {
+                    const double* ms = sm + 4 * (((lz0 + c) * X::GY + (ly0 + b)) * X::GX + (lx0 + a));
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) m[q] = ms[q];
+                } else {
+                    const long gi = dep_index(ax + a, D >= 2 ? ay + b : 0, D >= 3 ? az + c : 0, G);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) m[q] = gi < 0 ? 0.0 : lM[4 * gi + q];
                 }
-        R nx0 = 0;
+                const double lm = m[0] + m[1] * v[0] + m[2] * v[1] + m[3] * v[2];
+                const double W = w[0][a] * w[1][b] * w[2][c];
+                gx[0] += dw[0][a] * w[1][b] * w[2][c] * lm;
+                if (D >= 2) gx[1] += w[0][a] * dw[1][b] * w[2][c] * lm;
+                if (D >= 3) gx[2] += w[0][a] * w[1][b] * dw[2][c] * lm;
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            const R t = (R)((double)lam.x[d][src] + gx[d]);
-            lam.x[d][src] = t;
-            if (d == 0) nx0 = t;
-        }
-        double lv[3];
+                for (int d = 0; d < 3; ++d) gv[d] += W * m[1 + d];
+            }
+}
+
+// An origin no stencil lies beyond: deposit_vjp then reads every node from
+// global memory.
+constexpr int kNoRegion = -(1 << 29);
+
+// Tile origin of the staged stencil region of `tile`.
+template <int D, int S>
+__device__ __forceinline__ void tile_origin(const Geo& G, int tile, int& gx0, int& gy0, int& gz0) {
+    using T = TileShape<D>;
+    constexpr int LO = Stencil<S>::LO;
+    const int tx = tile % G.ntx;
+    const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
+    const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
+    gx0 = tx * T::X - LO;
+    gy0 = D >= 2 ? ty * T::Y - LO : 0;
+    gz0 = D >= 3 ? tz * T::Z - LO : 0;
+}
+
+// Deposit transpose over the ions of a packed state (the initial load):
+// lam(x) += sum_nodes dW/dx (lam_R + lam_G . v), lam(v) += sum W lam_G, added
+// to the adjoints at the ions' packed indices.
+template <typename R, int D, int S>
+__global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ toff, int64_t n,
+                                                     const double* __restrict__ lM, PLam<R> lam, int split) {
+    using X = Extent<D, S>;
+    __shared__ double sm[4 * X::GN];
+    const PackShare ts = pack_share(toff, n, split);
+    int gx0, gy0, gz0;
+    tile_origin<D, S>(G, ts.tile, gx0, gy0, gz0);
+    stage_moment_adj<D, S>(G, lM, gx0, gy0, gz0, sm);
+    __syncthreads();
+    for (long src = ts.begin + threadIdx.x; src < ts.end; src += blockDim.x) {
+        R o[3] = {0, 0, 0}, v[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const R t = (R)((double)lam.v[d][src] + gv[d]);
-            lam.v[d][src] = t;
-            lv[d] = (double)t;
-        }
-        const int64_t g = (int64_t)in.id[src] - id0;
-        if (g >= 0 && g < ninj) acc += inject_vjp(G, step, (uint64_t)(id0 + g), g >= nth, (double)nx0, lv);
+        for (int d = 0; d < D; ++d) o[d] = in.off[d][src];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = in.v[c][src];
+        double gx[3], gv[3];
+        deposit_vjp<R, D, S>(G, sm, lM, gx0, gy0, gz0, in.cell[src], o, v, gx, gv);
+#pragma unroll
+        for (int d = 0; d < D; ++d) lam.x[d][src] = (R)((double)lam.x[d][src] + gx[d]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lam.v[d][src] = (R)((double)lam.v[d][src] + gv[d]);
+    }
+}
+
+// The ions a step injected (ids id0 .. id0 + ninj - 1, thermal first, nth
+// of them), found in the packed state after the step: their adjoint there
+// (post plus the deposit transpose at that state) goes into dL/du_sh
+// through their injection.  Few ions: the moment adjoints are read from
+// global memory.
+template <typename R, int D, int S>
+__global__ __launch_bounds__(256) void k_inject_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ toff, int64_t n,
+                                                    const double* __restrict__ lM, PLam<R> post, uint64_t step,
+                                                    int64_t id0, int64_t nth, int64_t ninj, double* grads) {
+    const long m = min((long)toff[G.ntiles], (long)n);
+    double acc = 0.0;
+    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += (long)gridDim.x * blockDim.x) {
+        const int64_t g = (int64_t)in.id[q] - id0;
+        if (g < 0 || g >= ninj) continue;
+        R o[3] = {0, 0, 0}, v[3];
+#pragma unroll
+        for (int d = 0; d < D; ++d) o[d] = in.off[d][q];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = in.v[c][q];
+        double gx[3], gv[3];
+        // no staged region: every stencil node is read from lM
+        deposit_vjp<R, D, S>(G, nullptr, lM, kNoRegion, kNoRegion, kNoRegion, in.cell[q], o, v, gx, gv);
+        const double lx0 = (double)post.x[0][q] + gx[0];
+        const double lv[3] = {(double)post.v[0][q] + gv[0], (double)post.v[1][q] + gv[1],
+                              (double)post.v[2][q] + gv[2]};
+        acc += inject_vjp(G, step, (uint64_t)(id0 + g), g >= nth, lx0, lv);
     }
     block_add(acc, grads);
 }
 
 // Particle adjoints between two packings of the same ions, matched by id
-// through an id-indexed scratch (ncomp planar arrays of nid): k_lam_park
-// writes the adjoints of every ion of `from` at its id, k_lam_unpark reads
-// them back at the ions of `to`.  The scratch is zeroed first, so an id
-// `from` lacks reads zero; ids >= nid are skipped.
-template <typename R>
+// through an id-indexed scratch (the D + 3 components of id q at
+// [q (D + 3), (q + 1)(D + 3)), so a scattered ion touches one run of
+// memory): k_lam_park writes the adjoints of every ion of `from` at its id,
+// k_lam_unpark reads them back at the ions of `to`.  The scratch is zeroed
+// first, so an id `from` lacks reads zero; ids >= nid are skipped.
+template <typename R, int D>
 __global__ __launch_bounds__(256) void k_lam_park(const uint32_t* __restrict__ id, const int32_t* __restrict__ toff,
-                                                  int ntiles, int64_t n, PLam<R> lam, int D, R* __restrict__ scratch,
+                                                  int ntiles, int64_t n, PLam<R> lam, R* __restrict__ scratch,
                                                   int64_t nid) {
     const long m = min((long)toff[ntiles], (long)n);
     for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (long)gridDim.x * blockDim.x) {
         const int64_t q = id[p];
         if (q >= nid) continue;
-        for (int d = 0; d < D; ++d) scratch[d * nid + q] = lam.x[d][p];
-        for (int c = 0; c < 3; ++c) scratch[(D + c) * nid + q] = lam.v[c][p];
+        R* o = scratch + q * (D + 3);
+#pragma unroll
+        for (int d = 0; d < D; ++d) o[d] = lam.x[d][p];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o[D + c] = lam.v[c][p];
     }
 }
 
-template <typename R>
+template <typename R, int D>
 __global__ __launch_bounds__(256) void k_lam_unpark(const uint32_t* __restrict__ id, const int32_t* __restrict__ toff,
-                                                    int ntiles, int64_t n, PLam<R> lam, int D,
-                                                    const R* __restrict__ scratch, int64_t nid) {
+                                                    int ntiles, int64_t n, PLam<R> lam, const R* __restrict__ scratch,
+                                                    int64_t nid) {
     const long m = min((long)toff[ntiles], (long)n);
     for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < m; p += (long)gridDim.x * blockDim.x) {
         const int64_t q = id[p];
         const bool ok = q < nid;
-        for (int d = 0; d < D; ++d) lam.x[d][p] = ok ? scratch[d * nid + q] : (R)0;
-        for (int c = 0; c < 3; ++c) lam.v[c][p] = ok ? scratch[(D + c) * nid + q] : (R)0;
+        const R* o = scratch + (ok ? q : 0) * (D + 3);
+#pragma unroll
+        for (int d = 0; d < D; ++d) lam.x[d][p] = ok ? o[d] : (R)0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lam.v[c][p] = ok ? o[D + c] : (R)0;
     }
 }
 
@@ -418,32 +522,39 @@ __global__ __launch_bounds__(256) void k_init_adj(const int32_t* __restrict__ to
     block_add(acc, grads);
 }
 
-// Push transpose over the ions of the packed state at n: recompute the
-// gather, Boris and move as the forward step did, undo the FS kick for the
-// ions the step recorded as reflected, then the move, Boris and the gather.
-// Each ion reads its adjoint after the step from post, at the packed index
-// the step's record gives (dst >= 0 kept, -2 - i reflected, -1 removed), and
-// writes its adjoint before the step into pre at its own index, zero for an
-// ion the step removed.  lam(E^n), lam(Bbar^n) (6 planar FP64 arrays of
-// nnode) accumulate per tile in LDS.
+// Push transpose over the ions of the packed state at n, with the deposit
+// transpose of the state after the step fused in: each ion finds itself
+// after the step at the packed index the step's record gives (dst >= 0
+// kept, -2 - i reflected, -1 removed), takes its adjoint there from post
+// plus the deposit transpose at its position and velocity there (moment
+// adjoints lM; the ions the step injected are k_inject_adj's), then
+// recomputes the gather, Boris and move as the forward step did, undoes
+// the FS kick for the ions the step reflected, the move, Boris and the
+// gather, and writes its adjoint before the step into pre at its own index,
+// zero for an ion the step removed.  in1 / n1: the packed state after the
+// step.  lam(E^n), lam(Bbar^n) (6 planar FP64 arrays of nnode) accumulate
+// per tile in LDS.
 template <typename R, int D, int S>
 __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ toff, int64_t n,
+                                                  PBuf<R> in1, const double* __restrict__ lM,
                                                   const R* __restrict__ gather, const int32_t* __restrict__ dst_of,
                                                   PLam<R> post, PLam<R> pre, double* __restrict__ lEB, long nnode,
                                                   uint64_t step, double* grads, int split, int mirror) {
     using X = Extent<D, S>;
-    using T = TileShape<D>;
-    constexpr int LO = Stencil<S>::LO, N = Stencil<S>::N;
+    constexpr int N = Stencil<S>::N;
     constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
     __shared__ double sl[6 * X::GN];
     // the gather grid of the tile's stencil, as the forward push stages it
     __shared__ Pair<R> sg[3 * X::GN];
+    // the moment adjoints of the same nodes (most ions stay in their tile),
+    // where LDS holds them beside the rest (not the FP64 3D TSC stencil)
+    constexpr bool SM = (6 * sizeof(double) + 3 * sizeof(Pair<R>) + 4 * sizeof(double)) * X::GN <= 163840;
+    __shared__ double sm[SM ? 4 * X::GN : 1];
     const PackShare ts = pack_share(toff, n, split);
-    const int tile = ts.tile;
-    const int tx = tile % G.ntx;
-    const int ty = D >= 2 ? (tile / G.ntx) % G.nty : 0;
-    const int tz = D >= 3 ? tile / (G.ntx * G.nty) : 0;
-    const int gx0 = tx * T::X - LO, gy0 = D >= 2 ? ty * T::Y - LO : 0, gz0 = D >= 3 ? tz * T::Z - LO : 0;
+    int gx0, gy0, gz0;
+    tile_origin<D, S>(G, ts.tile, gx0, gy0, gz0);
+    if constexpr (SM) stage_moment_adj<D, S>(G, lM, gx0, gy0, gz0, sm);
+    const int mx0 = SM ? gx0 : kNoRegion, my0 = SM ? gy0 : kNoRegion, mz0 = SM ? gz0 : kNoRegion;
     for (int l = threadIdx.x; l < 6 * X::GN; l += blockDim.x) sl[l] = 0.0;
     for (int l = threadIdx.x; l < X::GN; l += blockDim.x) {
         const int lx = l % X::GX, ly = (l / X::GX) % X::GY, lz = l / (X::GX * X::GY);
@@ -465,10 +576,17 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
         double lx[3] = {0, 0, 0}, lv[3] = {0, 0, 0};
         bool any = false;
         if (dr != -1) {
+            R o1[3] = {0, 0, 0}, v1[3];
 #pragma unroll
-            for (int d = 0; d < D; ++d) { lx[d] = (double)post.x[d][slot]; any |= lx[d] != 0.0; }
+            for (int d = 0; d < D; ++d) o1[d] = in1.off[d][slot];
 #pragma unroll
-            for (int d = 0; d < 3; ++d) { lv[d] = (double)post.v[d][slot]; any |= lv[d] != 0.0; }
+            for (int c = 0; c < 3; ++c) v1[c] = in1.v[c][slot];
+            double gx[3], gv[3];
+            deposit_vjp<R, D, S>(G, sm, lM, mx0, my0, mz0, in1.cell[slot], o1, v1, gx, gv);
+#pragma unroll
+            for (int d = 0; d < D; ++d) { lx[d] = (double)post.x[d][slot] + gx[d]; any |= lx[d] != 0.0; }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) { lv[d] = (double)post.v[d][slot] + gv[d]; any |= lv[d] != 0.0; }
         }
         if (!any) {   // removed by the step (or no influence): zero before it too
 #pragma unroll
@@ -604,13 +722,47 @@ __device__ __forceinline__ long centre_index(const FieldGeo& F, int i, int j, in
     return i + (long)F.nx * (j + (long)F.nyc * k);
 }
 
+// Transpose of F(B) = -curl E (nodes -> centres) at node (i, j, k): lam_E
+// there, gathered from lam_F of the centres that use the node.
+template <int D>
+__device__ __forceinline__ void faraday_adj_at(const FieldGeo& F, const double* __restrict__ lF, int i, int j, int k,
+                                               long ncent, double out[3]) {
+    constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
+    out[0] = out[1] = out[2] = 0.0;
+    // node (i, j, k) = centre (ci + a, cj + b, ck + c) for a, b, c in {0, 1}
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                int ci = i - a;
+                const int cj = D >= 2 ? wrapi(j - b, F.nyc) : 0, ck = D >= 3 ? wrapi(k - c, F.nzc) : 0;
+                if (F.xbc == 1) ci = wrapi(ci, F.nx);
+                else if (ci < 0 || ci >= F.nx) continue;
+                const long q = ci + (long)F.nx * (cj + (long)F.nyc * ck);
+                const double l0 = lF[q], l1 = lF[ncent + q], l2 = lF[2 * ncent + q];
+                const double ldEx[3] = {0.0, -l2, l1}, ldEy[3] = {l2, 0.0, -l0}, ldEz[3] = {-l1, l0, 0.0};
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    double s = (a == 1 ? 1.0 : -1.0) * ldEx[d] * (1.0 / (double)(NB * NC)) * F.rdx;
+                    if (D >= 2) s += (b == 1 ? 1.0 : -1.0) * ldEy[d] * (1.0 / (double)(2 * NC)) * F.rdx;
+                    if (D >= 3) s += (c == 1 ? 1.0 : -1.0) * ldEz[d] * 0.25 * F.rdx;
+                    out[d] += s;
+                }
+            }
+}
+
 // Transpose of Ohm's law, first pass, one thread per node: (lam_E,
 // lam_Bbar) at the node -> the adjoints of its fluid state (n_e and Gamma of
 // the node, added; p_e of its neighbours, added atomically, several nodes
 // share one near a box end), of u_sh through the inflow node, and
 // ob = (lam_Bbar, lam_J) of the node (6 planar arrays of nnode) for the
 // centre pass.  fl is the forward fluid state the E was computed from.
-template <int D>
+// With CURL, lam_E is not read from lE but gathered from lam_F of an RK
+// stage (lE then points at lam_F, 3 planar arrays of ncent): the Faraday
+// transpose fused into the node pass.
+template <int D, bool CURL>
 __global__ __launch_bounds__(256) void k_ohm_adj_node(FieldGeo F, const double* __restrict__ B,
                                                       const double* __restrict__ fl, const double* __restrict__ lE,
                                                       const double* __restrict__ lBb, double* __restrict__ ob,
@@ -621,6 +773,13 @@ __global__ __launch_bounds__(256) void k_ohm_adj_node(FieldGeo F, const double* 
     const int rest = n / F.nxn;
     const int j = rest % F.nyc, k = rest / F.nyc;
     constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
+    double lEn[3];
+    if constexpr (CURL) {
+        faraday_adj_at<D>(F, lE, i, j, k, ncent, lEn);
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lEn[d] = lE[(long)d * nnode + n];
+    }
     double C[2][NB][NC][3];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -694,15 +853,12 @@ __global__ __launch_bounds__(256) void k_ohm_adj_node(FieldGeo F, const double* 
     // adjoint goes to u_sh alone (lam_Bbar still reaches the centres)
     const bool inflow = inflow_node(F, i);
     const bool conduct = F.conduct && i == F.nx;   // E_y = E_z = 0 there: constants
-    if (inflow) {
-        const double le_y = lE[nnode + n], le_z = lE[2 * nnode + n];
-        unsafeAtomicAdd(grads, le_y * F.B0[2] - le_z * F.B0[1]);
-    }
+    if (inflow) unsafeAtomicAdd(grads, lEn[1] * F.B0[2] - lEn[2] * F.B0[1]);
     double lnum[3], lJ[3], lbb[3], tmp[3];
     double lne = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double le = (inflow || (conduct && d > 0)) ? 0.0 : lE[(long)d * nnode + n];
+        const double le = (inflow || (conduct && d > 0)) ? 0.0 : lEn[d];
         lnum[d] = le / ne;
         lne -= num[d] * le / (ne * ne);
         lJ[d] = F.eta * le;
@@ -740,14 +896,33 @@ __global__ __launch_bounds__(256) void k_ohm_adj_node(FieldGeo F, const double* 
     }
 }
 
-// Transpose of Ohm's law, second pass, one thread per centre: lam_B += the
-// Bbar average and J differences of the 2^D nodes around the centre,
-// transposed, from their (lam_Bbar, lam_J) in ob.  In the box the centre
-// next to the wall also takes the wall ghost's share of node nx (the ghost
-// holds a copy of it); the inflow ghost (a constant B0) takes none.
-template <int D>
-__global__ __launch_bounds__(256) void k_ohm_adj_centre(FieldGeo F, const double* __restrict__ ob,
-                                                        double* __restrict__ lB, long nnode, long ncent) {
+// Where the centre pass puts v = base + (its gather), per centre and
+// component: the vector updates of the SSP-RK3 transpose (Shu-Osher form
+// B1 = B0 + h F(B0), B2 = 3/4 B0 + 1/4 (B1 + h F(B1)),
+// B3 = 1/3 B0 + 2/3 (B2 + h F(B2))) fused into the pass that completes
+// the adjoint they start from.
+enum RkEmit {
+    kEmitOut = 0,     // out = v (out may be base)
+    kEmitStage1 = 1,  // l0 += v, lF = h v                    (v: lam of B1)
+    kEmitStage2 = 2,  // l0 += 3/4 v, l1 = v/4, lF = h v/4    (v: lam of B2)
+    kEmitStage3 = 3   // l0 = v/3, l2 = 2 v/3, lF = 2 h v/3   (v: lam of B3)
+};
+struct RkOut {
+    const double* base;
+    double *l0, *l1, *l2, *lF, *out;
+    double h;
+};
+
+// Transpose of Ohm's law, second pass, one thread per centre: v = base +
+// the Bbar average and J differences of the 2^D nodes around the centre,
+// transposed, from their (lam_Bbar, lam_J) in ob, stored as EMIT says.  In
+// the box the centre next to the wall also takes the wall ghost's share of
+// node nx (the ghost holds a copy of it); the inflow ghost (a constant B0)
+// takes none.  base may alias l0 (each thread reads its centre before
+// writing it).
+template <int D, int EMIT>
+__global__ __launch_bounds__(256) void k_ohm_adj_centre(FieldGeo F, const double* __restrict__ ob, RkOut o, long nnode,
+                                                        long ncent) {
     const int q = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (q >= ncent) return;
     constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
@@ -791,45 +966,24 @@ __global__ __launch_bounds__(256) void k_ohm_adj_centre(FieldGeo F, const double
                 if (F.xbc == 0 && I == F.nx - 1 && a == 0) add(F.nx, 1, b, c);   // the wall ghost at nx
             }
 #pragma unroll
-    for (int d = 0; d < 3; ++d) lB[(long)d * ncent + q] += acc[d];
-}
-
-// Transpose of F(B) = -curl E (nodes -> centres): lam_E at every node
-// gathered from the centres that use it.
-template <int D>
-__global__ __launch_bounds__(256) void k_faraday_adj(FieldGeo F, const double* __restrict__ lF, double* __restrict__ lE,
-                                                     long nnode, long ncent) {
-    const long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nnode) return;
-    const int i = (int)(n % F.nxn);
-    const long rest = n / F.nxn;
-    const int j = (int)(rest % F.nyc), k = (int)(rest / F.nyc);
-    constexpr int NB = D >= 2 ? 2 : 1, NC = D >= 3 ? 2 : 1;
-    double acc[3] = {0, 0, 0};
-    // node (i, j, k) = centre (ci + a, cj + b, ck + c) for a, b, c in {0, 1}
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < NB; ++b)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                int ci = i - a;
-                const int cj = D >= 2 ? wrapi(j - b, F.nyc) : 0, ck = D >= 3 ? wrapi(k - c, F.nzc) : 0;
-                if (F.xbc == 1) ci = wrapi(ci, F.nx);
-                else if (ci < 0 || ci >= F.nx) continue;
-                const long q = ci + (long)F.nx * (cj + (long)F.nyc * ck);
-                const double l0 = lF[q], l1 = lF[ncent + q], l2 = lF[2 * ncent + q];
-                const double ldEx[3] = {0.0, -l2, l1}, ldEy[3] = {l2, 0.0, -l0}, ldEz[3] = {-l1, l0, 0.0};
-#pragma unroll
-                for (int d = 0; d < 3; ++d) {
-                    double s = (a == 1 ? 1.0 : -1.0) * ldEx[d] * (1.0 / (double)(NB * NC)) * F.rdx;
-                    if (D >= 2) s += (b == 1 ? 1.0 : -1.0) * ldEy[d] * (1.0 / (double)(2 * NC)) * F.rdx;
-                    if (D >= 3) s += (c == 1 ? 1.0 : -1.0) * ldEz[d] * 0.25 * F.rdx;
-                    acc[d] += s;
-                }
-            }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) lE[(long)d * nnode + n] = acc[d];
+    for (int d = 0; d < 3; ++d) {
+        const long e = (long)d * ncent + q;
+        const double v = o.base[e] + acc[d];
+        if constexpr (EMIT == kEmitStage1) {
+            o.l0[e] += v;
+            o.lF[e] = o.h * v;
+        } else if constexpr (EMIT == kEmitStage2) {
+            o.l0[e] += 0.75 * v;
+            o.l1[e] = 0.25 * v;
+            o.lF[e] = 0.25 * o.h * v;
+        } else if constexpr (EMIT == kEmitStage3) {
+            o.l0[e] = v * (1.0 / 3.0);
+            o.l2[e] = v * (2.0 / 3.0);
+            o.lF[e] = v * (2.0 / 3.0) * o.h;
+        } else {
+            o.out[e] = v;
+        }
+    }
 }
 
 // Transpose of the fluid moments (continuous deposit): lam of (n_e, p_e,
@@ -874,39 +1028,6 @@ __global__ __launch_bounds__(256) void k_fluid_adj(FieldGeo F, const double* __r
         }
     }
     block_add(acc, grads);
-}
-
-// The vector updates of the SSP-RK3 transpose (Shu-Osher form
-// B1 = B0 + h F(B0), B2 = 3/4 B0 + 1/4 (B1 + h F(B1)),
-// B3 = 1/3 B0 + 2/3 (B2 + h F(B2))), one pass each.
-// stage 3: l0 = lam/3, l2 = 2 lam/3, lF = 2 h lam/3
-__global__ void k_rk_adj3(double* __restrict__ l0, double* __restrict__ l2, double* __restrict__ lF,
-                          const double* __restrict__ lam, double h, long n) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double v = lam[i];
-        l0[i] = v * (1.0 / 3.0);
-        l2[i] = v * (2.0 / 3.0);
-        lF[i] = v * (2.0 / 3.0) * h;
-    }
-}
-// stage 2: l0 += 3/4 l2, l1 = l2/4, lF = h l2/4
-__global__ void k_rk_adj2(double* __restrict__ l0, double* __restrict__ l1, double* __restrict__ lF,
-                          const double* __restrict__ l2, double h, long n) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double v = l2[i];
-        l0[i] += 0.75 * v;
-        l1[i] = 0.25 * v;
-        lF[i] = 0.25 * h * v;
-    }
-}
-// stage 1: l0 += l1, lF = h l1
-__global__ void k_rk_adj1(double* __restrict__ l0, double* __restrict__ lF, const double* __restrict__ l1, double h,
-                          long n) {
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double v = l1[i];
-        l0[i] += v;
-        lF[i] = h * v;
-    }
 }
 
 // Amplitude adjoints of the initial modes: dB_y = A cos(k_m x + phi_m),

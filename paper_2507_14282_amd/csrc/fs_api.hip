@@ -50,7 +50,6 @@ struct fs_handle {
     double* alfl = nullptr;                 // its adjoint
     double* al[4] = {nullptr, nullptr, nullptr, nullptr};  // RK3 stage adjoints l0, l1, l2, lF
     double* aBs = nullptr;                  // B at the start of each RK substep
-    double* alE = nullptr;                  // curl transpose output at the nodes
     double* aob = nullptr;                  // Ohm transpose: lam(Bbar), lam(J) per node
     std::string err;
     // phase timing: pool of event pairs recorded on the caller's stream
@@ -632,28 +631,27 @@ void fluid_of(fs_handle* h, int64_t* const* mom, hipStream_t s) {
                                h->L.nnode, nullptr, nullptr, nullptr, 0);
 }
 
-// Transpose of Ohm's law at every node (see k_ohm_adj_node): per node pass,
-// then the gather of lam(Bbar) and lam(J) into lam_B at the centres.
-template <int D>
-void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb, double* lB, double* grads,
+// Transpose of Ohm's law at every node (see k_ohm_adj_node) evaluated at B:
+// the node pass from lam_E (lE, or with curl the Faraday transpose of lam_F
+// in lE), then the centre pass into o as EMIT says.
+template <int D, bool CURL, int EMIT>
+void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb, const RkOut& o, double* grads,
              hipStream_t s) {
     const long nn = h->L.nnode, nc = h->L.ncent;
-    k_ohm_adj_node<D><<<grid_for(nn), 256, 0, s>>>(h->F, B, h->afl, lE, lBb, h->aob, h->alfl, grads, nn, nc);
-    k_ohm_adj_centre<D><<<grid_for(nc), 256, 0, s>>>(h->F, h->aob, lB, nn, nc);
+    k_ohm_adj_node<D, CURL><<<grid_for(nn), 256, 0, s>>>(h->F, B, h->afl, lE, lBb, h->aob, h->alfl, grads, nn, nc);
+    k_ohm_adj_centre<D, EMIT><<<grid_for(nc), 256, 0, s>>>(h->F, h->aob, o, nn, nc);
 }
 
-// lam_B += (dF/dB)^T lF and lam_fl += (dF/dfl)^T lF for F(B) = -curl Ohm(B, fl).
+// Transpose of the field update of one step (the SSP-RK3 sub-steps from
+// B^n, then Ohm's law at B^{n+1}) with the fluid state in h->afl: lam_B
+// (in: lam(B^{n+1}), out: lam(B^n)), lam(E^{n+1}) in lE, lam(Bbar^{n+1})
+// in lBb; fluid adjoints added to h->alfl.  The stages are recomputed.
+// Each stage's F(B) = -curl Ohm(B, fl) is transposed by one node pass (the
+// Faraday transpose gathered in it) and one centre pass that also does the
+// RK vector update that follows it.
 template <int D>
-void rhs_adj(fs_handle* h, const double* B, const double* lF, double* lB, double* grads, hipStream_t s) {
-    const long nn = h->L.nnode, nc = h->L.ncent;
-    k_faraday_adj<D><<<grid_for(nn), 256, 0, s>>>(h->F, lF, h->alE, nn, nc);
-    ohm_adj<D>(h, B, h->alE, nullptr, lB, grads, s);
-}
-
-// Transpose of the SSP-RK3 field update from B^n with the fluid state in
-// h->afl: lam_B (in: lam(B^{n+1}), out: lam(B^n)); fluid adjoints added to
-// h->alfl.  The stages are recomputed.
-template <int D> void rk3_adj(fs_handle* h, const double* Bn, double* lB, double* grads, hipStream_t s) {
+void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* lBb, const double* Bn, double* lB,
+               double* grads, hipStream_t s) {
     const long N = 3 * h->L.ncent;
     const int ns = h->cfg.n_sub;
     const double hs = h->cfg.dt / (double)ns;
@@ -665,44 +663,38 @@ template <int D> void rk3_adj(fs_handle* h, const double* Bn, double* lB, double
         stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
         stage_launch<D>(h, h->B2, B0, B0 + N, h->afl, 1.0 / 3.0, 2.0 / 3.0, hs, s);
     }
-    double *l0 = h->al[0], *l1 = h->al[1], *l2 = h->al[2], *lF = h->al[3];
+    RkOut o;
+    o.l0 = h->al[0]; o.l1 = h->al[1]; o.l2 = h->al[2]; o.lF = h->al[3]; o.out = lB; o.h = hs;
+    // Ohm at B^{n+1}; its centre pass starts the last sub-step's transpose
+    // B3 = 1/3 B0 + 2/3 (B2 + h F(B2))
+    o.base = lB;
+    ohm_adj<D, false, kEmitStage3>(h, Bn1, lE, lBb, o, grads, s);
     for (int sub = ns - 1; sub >= 0; --sub) {
-        double* B0 = Bs + (size_t)sub * N;
+        const double* B0 = Bs + (size_t)sub * N;
         stage_launch<D>(h, B0, B0, h->B1, h->afl, 0.0, 1.0, hs, s);
         stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
-        const unsigned g = grid_for(N);
-        // B3 = 1/3 B0 + 2/3 (B2 + h F(B2))
-        k_rk_adj3<<<g, 256, 0, s>>>(l0, l2, lF, lB, hs, N);
-        rhs_adj<D>(h, h->B2, lF, l2, grads, s);
-        // B2 = 3/4 B0 + 1/4 (B1 + h F(B1))
-        k_rk_adj2<<<g, 256, 0, s>>>(l0, l1, lF, l2, hs, N);
-        rhs_adj<D>(h, h->B1, lF, l1, grads, s);
-        // B1 = B0 + h F(B0)
-        k_rk_adj1<<<g, 256, 0, s>>>(l0, lF, l1, hs, N);
-        rhs_adj<D>(h, B0, lF, l0, grads, s);
-        (void)hipMemcpyAsync(lB, l0, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+        // lam(B2) = l2 + (dF/dB2)^T lF, then B2 = 3/4 B0 + 1/4 (B1 + h F(B1))
+        o.base = o.l2;
+        ohm_adj<D, true, kEmitStage2>(h, h->B2, o.lF, nullptr, o, grads, s);
+        // lam(B1) = l1 + (dF/dB1)^T lF, then B1 = B0 + h F(B0)
+        o.base = o.l1;
+        ohm_adj<D, true, kEmitStage1>(h, h->B1, o.lF, nullptr, o, grads, s);
+        // lam(B0) = l0 + (dF/dB0)^T lF: the start of this sub-step, which
+        // ends the previous one (or is lam(B^n))
+        o.base = o.l0;
+        if (sub > 0) ohm_adj<D, true, kEmitStage3>(h, B0, o.lF, nullptr, o, grads, s);
+        else ohm_adj<D, true, kEmitOut>(h, B0, o.lF, nullptr, o, grads, s);
     }
 }
 
-// Fluid and deposit transposes: lam of the fluid state in h->alfl -> the
-// particle adjoints (buffer lam->cur) of the packed state whose moments are
-// in h->amom; then the injection transpose of the ions a step injected (ids
-// id0 .. id0 + nth + ncr - 1, none when ncr + nth = 0).
-template <typename R, int D, int S>
-void moments_adj(fs_handle* h, const fs_packed* pk, const fs_adjoint* lam, double* grads, hipStream_t s,
-                 uint64_t step = 0, int64_t id0 = 0, int64_t nth = 0, int64_t ncr = 0) {
+// Fluid transpose: lam of the fluid state in h->alfl -> the moment adjoints
+// h->alM[k] at the deposit nodes (and the alpha_cr adjoint).
+void fluid_adj(fs_handle* h, double* grads, hipStream_t s) {
     const long nn = h->L.nnode;
     for (int k = 0; k < 2; ++k) zero_u64(reinterpret_cast<unsigned long long*>(h->alM[k]), 4 * h->L.ndep, s);
     const double dwcr = h->has_cr ? h->cfg.n_cr / (double)h->cfg.ppc_cr : 0.0;
     k_fluid_adj<<<grid_for(nn), 256, 0, s>>>(h->F, h->amom[0], h->has_cr ? h->amom[1] : h->amom[0], h->alfl, h->alM[0],
                                              h->alM[1], nn, dwcr, grads + 1);
-    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
-        PBuf<R> in = sections<R>(pk->buf[k], pk->n[k], D);
-        const int sp_ = split_of(h->L.tile_cap[k]);
-        k_deposit_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
-            h->G, in, pk->toff[k], pk->n[k], h->alM[k], plam<R>(lam, k, lam->cur, D), sp_, step, id0, nth, nth + ncr,
-            grads);
-    }
 }
 
 template <typename R, int D, int S>
@@ -713,24 +705,31 @@ int adjoint_step_impl(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, c
     // fluid state the step's field update used: moments of the particles after it
     fluid_of(h, f_n1->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
-    // final Ohm, then the RK3 update
-    ohm_adj<D>(h, f_n1->B, lam->lE, lam->lE + 3 * nn, lam->lB, grads, s);
-    rk3_adj<D>(h, f_n->B, lam->lB, grads, s);
-    // fluid and deposit at n+1, into the particle adjoints after the step,
-    // then the ions injected by the step
+    // final Ohm, then the RK3 sub-steps
+    field_adj<D>(h, f_n1->B, lam->lE, lam->lE + 3 * nn, f_n->B, lam->lB, grads, s);
+    // fluid at n+1: the moment adjoints the deposit transpose reads
+    fluid_adj(h, grads, s);
+    const int post = lam->cur, pre = lam->cur ^ 1;
+    // the ions the step injected: their adjoint after it into dL/du_sh
     int64_t cth = 0, ccr = 0;
     inject_counts(h->cfg, step, cth, ccr);
     const int64_t ntr = h->L.nyc * h->L.nzc, nth = cth * ntr, ncr = ccr * ntr;
-    moments_adj<R, D, S>(h, pn1, lam, grads, s, (uint64_t)step, id0, nth, ncr);
-    // push, wall and gather of the ions that lived before the step: buffer
-    // cur (indices after the step) -> cur ^ 1 (indices before it)
+    for (int k = 0; k < (h->has_cr ? 2 : 1) && nth + ncr > 0; ++k) {
+        PBuf<R> in1 = sections<R>(pn1->buf[k], pn1->n[k], D);
+        const unsigned g = std::min<unsigned>(grid_for(std::max<int64_t>(pn1->n[k], 1)), 4096u);
+        k_inject_adj<R, D, S><<<g, 256, 0, s>>>(h->G, in1, pn1->toff[k], pn1->n[k], h->alM[k],
+                                                plam<R>(lam, k, post, D), (uint64_t)step, id0, nth, nth + ncr, grads);
+    }
+    // deposit at n+1, then push, wall and gather of the ions that lived
+    // before the step: buffer cur (indices after the step) -> cur ^ 1
+    // (indices before it)
     zero_u64(reinterpret_cast<unsigned long long*>(lam->lE), 6 * nn, s);
-    const int post = lam->cur, pre = lam->cur ^ 1;
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         PBuf<R> in = sections<R>(pn->buf[k], pn->n[k], D);
+        PBuf<R> in1 = sections<R>(pn1->buf[k], pn1->n[k], D);
         const int sp_ = split_of(h->L.tile_cap[k]);
         k_push_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
-            h->G, in, pn->toff[k], pn->n[k], static_cast<const R*>(f_n->gather), pn->dst[k],
+            h->G, in, pn->toff[k], pn->n[k], in1, h->alM[k], static_cast<const R*>(f_n->gather), pn->dst[k],
             plam<R>(lam, k, post, D), plam<R>(lam, k, pre, D), lam->lE, nn, (uint64_t)step, grads, sp_,
             policy_of(h, k) == FS_WALL_SPECULAR ? 1 : 0);
     }
@@ -744,8 +743,16 @@ int adjoint_init_impl(fs_handle* h, const fs_packed* p0, const fs_fields* f0, fs
     const long nn = h->L.nnode, nc = h->L.ncent;
     fluid_of(h, f0->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
-    ohm_adj<D>(h, f0->B, lam->lE, lam->lE + 3 * nn, lam->lB, grads, s);
-    moments_adj<R, D, S>(h, p0, lam, grads, s);
+    RkOut o{};
+    o.base = o.out = lam->lB;
+    ohm_adj<D, false, kEmitOut>(h, f0->B, lam->lE, lam->lE + 3 * nn, o, grads, s);
+    fluid_adj(h, grads, s);
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        PBuf<R> in = sections<R>(p0->buf[k], p0->n[k], D);
+        const int sp_ = split_of(h->L.tile_cap[k]);
+        k_deposit_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
+            h->G, in, p0->toff[k], p0->n[k], h->alM[k], plam<R>(lam, k, lam->cur, D), sp_);
+    }
     k_init_adj<R><<<std::min<unsigned>(grid_for(p0->n[0]), 2048u), 256, 0, s>>>(
         p0->toff[0], (int)h->L.ntiles, p0->n[0], plam<R>(lam, 0, lam->cur, D), grads);
     const fs_config& c = h->cfg;
@@ -768,13 +775,17 @@ int tape_pack_impl(fs_handle* h, const fs_particles* sp, fs_packed* out, const f
         k_tape_offsets<<<1, 1024, 0, s>>>(P.tile_count[P.cur], nt, P.tile_cap, out->toff[k], out->n[k], out->status);
         PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
         PBuf<R> o = sections<R>(out->buf[k], out->n[k], D);
-        k_tape_pack<R, D><<<(unsigned)nt, 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap, out->toff[k],
-                                                       out->n[k], o);
+        // boxes with few tiles (large ones) split each over workgroups of
+        // about 1024 ions, up to some 4096 workgroups in all
+        const int sp_ = (int)std::max<int64_t>(1, std::min<int64_t>(P.tile_cap / 1024, 4096 / nt));
+        k_tape_pack<R, D><<<(unsigned)(nt * sp_), 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
+                                                               out->toff[k], out->n[k], o, sp_);
         if (rec) {
             const fs_particles& Q = prev_sp[k];
-            k_tape_record<<<(unsigned)nt, 256, 0, s>>>(h->G, Q.tile_count[Q.cur], Q.tile_cap, prev->toff[k],
-                                                       prev->n[k], rec->dst[k], P.tile_count[P.cur], out->toff[k],
-                                                       out->n[k], prev->dst[k], prev->status);
+            k_tape_record<<<(unsigned)(nt * sp_), 256, 0, s>>>(h->G, Q.tile_count[Q.cur], Q.tile_cap, prev->toff[k],
+                                                               prev->n[k], rec->dst[k], P.tile_count[P.cur],
+                                                               out->toff[k], out->n[k], prev->dst[k], prev->status,
+                                                               sp_);
         }
     }
     return hip_check(h, hipGetLastError(), "tape pack launch");
@@ -847,10 +858,9 @@ int check_fields(fs_handle* h, const fs_fields* f) {
 // C ABI
 // ==========================================================================
 // Id-indexed parking of the adjoints of buffer lam->cur (see the header).
-template <typename R>
+template <typename R, int D>
 int park_impl(fs_handle* h, const fs_packed* pk, fs_adjoint* lam, void* scratch, const void* cscratch, int64_t nid,
               bool park, hipStream_t s) {
-    const int D = h->cfg.dim;
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         PBuf<R> p = sections<R>(pk->buf[k], pk->n[k], D);
         const unsigned g = std::min<unsigned>(grid_for(std::max<int64_t>(pk->n[k], 1)), 4096u);
@@ -858,12 +868,12 @@ int park_impl(fs_handle* h, const fs_packed* pk, fs_adjoint* lam, void* scratch,
             R* sc = static_cast<R*>(scratch) + (int64_t)k * (D + 3) * nid;
             if (sizeof(R) == 8) zero_u64(sc, (int64_t)(D + 3) * nid, s);
             else zero_i32(reinterpret_cast<int32_t*>(sc), (int64_t)(D + 3) * nid, s);
-            k_lam_park<R><<<g, 256, 0, s>>>(p.id, pk->toff[k], (int)h->L.ntiles, pk->n[k],
-                                            plam<R>(lam, k, lam->cur, D), D, sc, nid);
+            k_lam_park<R, D><<<g, 256, 0, s>>>(p.id, pk->toff[k], (int)h->L.ntiles, pk->n[k],
+                                               plam<R>(lam, k, lam->cur, D), sc, nid);
         } else {
             const R* sc = static_cast<const R*>(cscratch) + (int64_t)k * (D + 3) * nid;
-            k_lam_unpark<R><<<g, 256, 0, s>>>(p.id, pk->toff[k], (int)h->L.ntiles, pk->n[k],
-                                              plam<R>(lam, k, lam->cur, D), D, sc, nid);
+            k_lam_unpark<R, D><<<g, 256, 0, s>>>(p.id, pk->toff[k], (int)h->L.ntiles, pk->n[k],
+                                                 plam<R>(lam, k, lam->cur, D), sc, nid);
         }
     }
     return hip_check(h, hipGetLastError(), "adjoint park launch");
@@ -944,7 +954,6 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
         ok = ok && dmalloc((void**)&h->alfl, 5 * nn * sizeof(double));
         for (int k = 0; k < 4 && ok; ++k) ok = ok && dmalloc((void**)&h->al[k], 3 * nc * sizeof(double));
         ok = ok && dmalloc((void**)&h->aBs, (size_t)c.n_sub * 3 * nc * sizeof(double));
-        ok = ok && dmalloc((void**)&h->alE, 3 * nn * sizeof(double));
         ok = ok && dmalloc((void**)&h->aob, 6 * nn * sizeof(double));
     }
     // crosser lists: a generous bound on the ions that can reach the wall in one step
@@ -988,7 +997,7 @@ void fs_destroy(fs_handle* h) {
     hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->fluid2); hipFree(h->nprev); hipFree(h->gprev); hipFree(h->phase); hipFree(h->part); hipFree(h->spec);
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
     for (int k = 0; k < 2; ++k) { hipFree(h->amom[k]); hipFree(h->alM[k]); }
-    hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->alE); hipFree(h->aob);
+    hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->aob);
     for (int k = 0; k < 4; ++k) hipFree(h->al[k]);
     delete h;
 }
@@ -1114,6 +1123,9 @@ int fs_tape_pack(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_
     const bool with = prev_sp || rec || prev;
     if (with && !(prev_sp && rec && prev)) return fail(h, FS_EINVAL, "prev_sp, rec and prev go together");
     int rc = check_particles(h, sp);
+    for (int k = 0; !rc && k < (h->has_cr ? 2 : 1); ++k)
+        if (h->L.capacity[k] > (int64_t)INT32_MAX - 2)
+            rc = fail(h, FS_ECAPACITY, "particle buffers too large for the int32 tile offsets");
     if (!rc) rc = check_packed(h, out, nullptr, false);
     if (!rc && with) rc = check_particles(h, prev_sp);
     if (!rc && with) rc = check_packed(h, prev, nullptr, true);
@@ -1147,8 +1159,8 @@ int fs_adjoint_park(fs_handle* h, const fs_packed* from, fs_adjoint* lam, void* 
     int rc = check_adjoint(h, lam);
     if (!rc) rc = check_packed(h, from, lam, false);
     if (rc) return rc;
-    if (h->cfg.precision == 64) return park_impl<double>(h, from, lam, scratch, nullptr, nid, true, s);
-    return park_impl<float>(h, from, lam, scratch, nullptr, nid, true, s);
+    auto run = [&]() -> int { FS_DISPATCH_RD(h, (park_impl<R, D>(h, from, lam, scratch, nullptr, nid, true, s))); };
+    return run();
 }
 
 int fs_adjoint_unpark(fs_handle* h, const fs_packed* to, fs_adjoint* lam, const void* scratch, int64_t nid,
@@ -1158,8 +1170,8 @@ int fs_adjoint_unpark(fs_handle* h, const fs_packed* to, fs_adjoint* lam, const 
     int rc = check_adjoint(h, lam);
     if (!rc) rc = check_packed(h, to, lam, false);
     if (rc) return rc;
-    if (h->cfg.precision == 64) return park_impl<double>(h, to, lam, nullptr, scratch, nid, false, s);
-    return park_impl<float>(h, to, lam, nullptr, scratch, nid, false, s);
+    auto run = [&]() -> int { FS_DISPATCH_RD(h, (park_impl<R, D>(h, to, lam, nullptr, scratch, nid, false, s))); };
+    return run();
 }
 
 int fs_adjoint_init(fs_handle* h, const fs_packed* p0, const fs_fields* f0, fs_adjoint* lam, double* grads,
