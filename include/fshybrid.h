@@ -429,24 +429,30 @@ typedef struct fs_adjoint {
 
 /* One full step (deposit_mode 1, non-relativistic, first-order coupling:
  * the step the reverse mode covers) that also fills *rec (in bin slots, see
- * fs_record).  Same contract as fs_step with flags = FS_ALL.  FS_EINVAL on
- * another configuration or on a NULL dst of a species, FS_ECAPACITY if a
- * dst holds fewer entries than the species' capacity or the capacity does
- * not fit the int32 encoding (above 2^31 - 3 slots). */
+ * fs_record).  Same contract as fs_step with flags = FS_ALL.  With pack_in
+ * (NULL for none), whose toff fs_tape_pack has already set for the input
+ * state (sp's buf[cur]), the push also copies each input ion as it reads it
+ * to its packed index in pack_in->buf: the ions of fs_tape_pack with
+ * FS_PACK_IONS, without a pass of their own.  FS_EINVAL on another
+ * configuration or on a NULL dst of a species, FS_ECAPACITY if a dst holds
+ * fewer entries than the species' capacity or the capacity does not fit
+ * the int32 encoding (above 2^31 - 3 slots). */
 int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec,
-                   fs_step_stats* st, hipStream_t s);
+                   const fs_packed* pack_in, fs_step_stats* st, hipStream_t s);
 
 /* Packs the live ions of sp (buf[cur], tile_count[cur]) into *out: the tile
- * offsets, then the ions.  With prev_sp, rec and prev given, sp is the
- * output of the recorded step *rec whose input prev_sp (as the step read it,
- * packed earlier into *prev) left the record in bin slots; it goes into
- * prev->dst in packed indices of *out.  Asynchronous on s; an overflow of
- * n[k] sets *out->status (*prev->status for a record entry that points past
- * out's n).  FS_EINVAL on a NULL argument (prev_sp, rec and prev are all
- * given or all NULL), FS_ECAPACITY if a species' capacity does not fit the
- * int32 tile offsets (above 2^31 - 3 slots). */
+ * offsets, and with FS_PACK_IONS in flags the ions (else a recorded step
+ * from this state copies them, see fs_step_record).  With prev_sp, rec and
+ * prev given, sp is the output of the recorded step *rec whose input
+ * prev_sp (as the step read it, packed into *prev) left the record in bin
+ * slots; it goes into prev->dst in packed indices of *out.  Asynchronous on
+ * s; an overflow of n[k] sets *out->status (*prev->status for a record
+ * entry that points past out's n).  FS_EINVAL on a NULL argument (prev_sp, rec and prev are all
+ * given or all NULL) or an unknown flag, FS_ECAPACITY if a species'
+ * capacity does not fit the int32 tile offsets (above 2^31 - 3 slots). */
+#define FS_PACK_IONS 1u
 int fs_tape_pack(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_particles* prev_sp,
-                 const fs_record* rec, fs_packed* prev, hipStream_t s);
+                 const fs_record* rec, fs_packed* prev, uint32_t flags, hipStream_t s);
 
 /* Reverse of step `step` (n -> n+1, recorded with fs_step_record and packed
  * with fs_tape_pack).  pn / f_n: the packed state before the step (with the

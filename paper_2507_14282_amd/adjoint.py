@@ -176,15 +176,18 @@ class _Packed:
         return sum(_section_bytes(int(n[k]), dim, rb) + 4 * (int(n[k]) + int(sim.L.ntiles) + 2) for k in range(nsp))
 
 
-def _recorded_step(sim: F.Simulation, n: int, pre: _State, f_pre, post: _State, f_post, rec: F.FsRecord):
+def _recorded_step(sim: F.Simulation, n: int, pre: _State, f_pre, post: _State, f_post, rec: F.FsRecord,
+                   pack_in: "_Packed"):
     """Step n from the bins of `pre` (fields f_pre) into the bins of `post`
-    (fields f_post) without copying particles.  The field update works in
-    place, so B and the gather grid are first copied across; E is only
-    written."""
+    (fields f_post) without copying particles, packing pre's ions into
+    pack_in (whose offsets are set) as the push reads them.  The field
+    update works in place, so B and the gather grid are first copied
+    across; E is only written."""
     f_post.B.copy_(f_pre.B)
     f_post.gather.copy_(f_pre.gather)
     sp = pre.step_to(sim, post)
-    rc = sim.lib.fs_step_record(sim.h, sp, C.byref(f_post.f(sim)), int(n), C.byref(rec), None, sim.stream)
+    rc = sim.lib.fs_step_record(sim.h, sp, C.byref(f_post.f(sim)), int(n), C.byref(rec), C.byref(pack_in.s), None,
+                                sim.stream)
     for k in range(2):
         sp[k].cur = 0          # the step flips it
     sim._check(rc)
@@ -389,14 +392,17 @@ class AdjointRun:
             ck = self.checkpoints[s0]
             sim.set_clock(ck.next_id)
             flds = [ck] + bufs["fields"]
-            sim._check(lib.fs_tape_pack(sim.h, ck.sp(sim), C.byref(P[0].s), None, None, None, stream))
+            # each state's tile offsets, then its ions as the recorded step
+            # from it reads them (the segment's last state has no such step)
+            sim._check(lib.fs_tape_pack(sim.h, ck.sp(sim), C.byref(P[0].s), None, None, None, 0, stream))
             pre, id0 = ck, []
             for j, n in enumerate(range(s0, s1)):
                 post = bufs["work"][j % 2]
-                _recorded_step(sim, n, pre, flds[j], post, flds[j + 1], rec)
+                _recorded_step(sim, n, pre, flds[j], post, flds[j + 1], rec, P[j])
                 id0.append(int(rec.id0))
+                last = F.FS_PACK_IONS if n + 1 == s1 else 0
                 sim._check(lib.fs_tape_pack(sim.h, post.sp(sim), C.byref(P[j + 1].s), pre.sp(sim), C.byref(rec),
-                                            C.byref(P[j].s), stream))
+                                            C.byref(P[j].s), last, stream))
                 pre = post
             m = s1 - s0
             if parked:

@@ -422,7 +422,7 @@ void deposit_continuous(fs_handle* h, const fs_particles* sp, double* const mom[
 
 template <typename R, int D, int S>
 int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t flags, hipStream_t s,
-              const fs_record* rec = nullptr) {
+              const fs_record* rec = nullptr, const fs_packed* pk = nullptr) {
     const bool push = flags & FS_PUSH, inj = flags & FS_INJECT, fld = flags & FS_FIELD;
     const bool cont = h->cfg.deposit_mode == 1;
     // the continuous deposit runs as its own pass after the particles have moved
@@ -453,11 +453,20 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
             PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
             PBuf<R> out = sections<R>(P.buf[P.cur ^ 1], P.capacity, D);
             auto* mom = reinterpret_cast<unsigned long long*>(f->mom[k]);
+            // a recorded step with a packed state: the push copies its input there
+            PBuf<R> pko{};
+            const int32_t* pk_toff = nullptr;
+            int64_t pk_n = 0;
+            if (pk) {
+                pko = sections<R>(pk->buf[k], pk->n[k], D);
+                pk_toff = pk->toff[k];
+                pk_n = pk->n[k];
+            }
             auto launch = [&](auto kern) {
                 allow_lds(kern, lds_push);
                 kern<<<(unsigned)h->L.ntiles, PUSH_THREADS, lds_push, s>>>(
                     G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, static_cast<const R*>(f->gather),
-                    mom, h->xl[k], h->ctr, policy_of(h, k), k, rec ? rec->dst[k] : nullptr);
+                    mom, h->xl[k], h->ctr, policy_of(h, k), k, rec ? rec->dst[k] : nullptr, pko, pk_toff, pk_n);
             };
             const bool rel = h->cfg.c_light > 0.0;
             if (rec) launch(k_push<R, D, S, false, false, false, true>);   // continuous deposit, non-relativistic
@@ -765,10 +774,11 @@ int adjoint_init_impl(fs_handle* h, const fs_packed* p0, const fs_fields* f0, fs
     return hip_check(h, hipGetLastError(), "adjoint init launch");
 }
 
-// Packs the live ions of sp into out (and, with a record, converts it).
+// The tile offsets of sp's live ions into out, with `ions` the ions
+// themselves, and with a record its conversion into prev->dst.
 template <typename R, int D>
 int tape_pack_impl(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_particles* prev_sp,
-                   const fs_record* rec, fs_packed* prev, hipStream_t s) {
+                   const fs_record* rec, fs_packed* prev, bool ions, hipStream_t s) {
     const int nt = (int)h->L.ntiles;
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         const fs_particles& P = sp[k];
@@ -778,8 +788,9 @@ int tape_pack_impl(fs_handle* h, const fs_particles* sp, fs_packed* out, const f
         // boxes with few tiles (large ones) split each over workgroups of
         // about 1024 ions, up to some 4096 workgroups in all
         const int sp_ = (int)std::max<int64_t>(1, std::min<int64_t>(P.tile_cap / 1024, 4096 / nt));
-        k_tape_pack<R, D><<<(unsigned)(nt * sp_), 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
-                                                               out->toff[k], out->n[k], o, sp_);
+        if (ions)
+            k_tape_pack<R, D><<<(unsigned)(nt * sp_), 256, 0, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
+                                                                   out->toff[k], out->n[k], o, sp_);
         if (rec) {
             const fs_particles& Q = prev_sp[k];
             k_tape_record<<<(unsigned)(nt * sp_), 256, 0, s>>>(h->G, Q.tile_count[Q.cur], Q.tile_cap, prev->toff[k],
@@ -1022,14 +1033,14 @@ int fs_init_plasma(fs_handle* h, fs_particles* sp, fs_fields* f, const double* a
 }
 
 static int step_common(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32_t flags, fs_step_stats* st,
-                       hipStream_t s, const fs_record* rec) {
+                       hipStream_t s, const fs_record* rec, const fs_packed* pk = nullptr) {
     if (!h || !sp || !f) return fail(h, FS_EINVAL, "NULL argument");
     if (flags & ~FS_ALL) return fail(h, FS_EINVAL, "unknown step flags");
     if (step < 0) return fail(h, FS_EINVAL, "negative step");
     int rc = check_particles(h, sp);
     if (!rc) rc = check_fields(h, f);
     if (rc) return rc;
-    auto run = [&]() -> int { FS_DISPATCH(h, (step_impl<R, D, S>(h, sp, f, step, flags, s, rec))); };
+    auto run = [&]() -> int { FS_DISPATCH(h, (step_impl<R, D, S>(h, sp, f, step, flags, s, rec, pk))); };
     rc = run();
     if (rc) return rc;
     if (!st) return FS_OK;
@@ -1106,20 +1117,23 @@ static int check_reverse_cfg(fs_handle* h) {
     return FS_OK;
 }
 
-int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec, fs_step_stats* st,
-                   hipStream_t s) {
+int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec,
+                   const fs_packed* pack_in, fs_step_stats* st, hipStream_t s) {
     if (!h || !rec) return fail(h, FS_EINVAL, "NULL argument");
     if (h->cfg.deposit_mode != 1) return fail(h, FS_EINVAL, "a recorded step needs deposit_mode 1");
     if (h->cfg.c_light != 0.0 || h->cfg.coupling != 1)
         return fail(h, FS_EINVAL, "a recorded step covers the non-relativistic first-order step only");
     if (int rc = check_record(h, rec)) return rc;
+    if (pack_in)
+        if (int rc = check_packed(h, pack_in, nullptr, false)) return rc;
     rec->id0 = h->next_id;
-    return step_common(h, sp, f, step, FS_ALL, st, s, rec);
+    return step_common(h, sp, f, step, FS_ALL, st, s, rec, pack_in);
 }
 
 int fs_tape_pack(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_particles* prev_sp,
-                 const fs_record* rec, fs_packed* prev, hipStream_t s) {
+                 const fs_record* rec, fs_packed* prev, uint32_t flags, hipStream_t s) {
     if (!h || !sp || !out) return fail(h, FS_EINVAL, "NULL argument");
+    if (flags & ~(uint32_t)FS_PACK_IONS) return fail(h, FS_EINVAL, "unknown pack flags");
     const bool with = prev_sp || rec || prev;
     if (with && !(prev_sp && rec && prev)) return fail(h, FS_EINVAL, "prev_sp, rec and prev go together");
     int rc = check_particles(h, sp);
@@ -1131,7 +1145,9 @@ int fs_tape_pack(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_
     if (!rc && with) rc = check_packed(h, prev, nullptr, true);
     if (!rc && with) rc = check_record(h, rec);
     if (rc) return rc;
-    auto run = [&]() -> int { FS_DISPATCH_RD(h, (tape_pack_impl<R, D>(h, sp, out, prev_sp, rec, prev, s))); };
+    auto run = [&]() -> int {
+        FS_DISPATCH_RD(h, (tape_pack_impl<R, D>(h, sp, out, prev_sp, rec, prev, (flags & FS_PACK_IONS) != 0, s)));
+    };
     return run();
 }
 

@@ -343,6 +343,16 @@ __device__ __forceinline__ void load_ion(const PBuf<R>& in, long src, Ion<R, D>&
     p.id = in.id[src];
 }
 
+template <typename R, int D>
+__device__ __forceinline__ void store_ion(const PBuf<R>& out, long dst, const Ion<R, D>& p) {
+    out.cell[dst] = p.cell;
+#pragma unroll
+    for (int d = 0; d < D; ++d) out.off[d][dst] = p.o[d];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out.v[c][dst] = p.v[c];
+    out.id[dst] = p.id;
+}
+
 // ---------------------------------------------------------------------------
 // REL selects the relativistic push at compile time: a run-time switch would
 // cost the non-relativistic kernel registers (and occupancy) it never uses.
@@ -366,14 +376,17 @@ template <typename R, int D, int S, bool REL> struct PushWaves {
 
 // TC: the time-centred coupling, density deposited at the new position and
 // flux at the midpoint of the move.  REC: a recorded step (reverse mode),
-// which writes where each ion went into rec_dst and keeps each crosser's
-// source slot in the crosser list for the wall.
+// which writes where each ion went into rec_dst, keeps each crosser's
+// source slot in the crosser list for the wall and, with pk_n > 0, copies
+// each input ion as it is read to its packed index pk_toff[tile] + rank
+// (the tape's packing of the input state, ions past pk_n dropped).
 template <typename R, int D, int S, bool DEP, bool REL, bool TC = false, bool REC = false>
 __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
                                               int32_t* __restrict__ cnt_out, int64_t cap,
                                               const R* __restrict__ gather, unsigned long long* __restrict__ mom,
                                               XList xl, unsigned long long* __restrict__ ctr, int policy,
-                                              int species, int32_t* __restrict__ rec_dst) {
+                                              int species, int32_t* __restrict__ rec_dst, PBuf<R> pk,
+                                              const int32_t* __restrict__ pk_toff, int64_t pk_n) {
     using X = Extent<D, S>;
     using T = TileShape<D>;
     using L = PushLds<R, D, S>;
@@ -414,11 +427,16 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
     int oor = 0, nesc = 0, nopen = 0;
     const int lane = __lane_id();
 
+    long pk_base = 0;
+    if constexpr (REC) pk_base = pk_n > 0 ? (long)pk_toff[tile] : 0;
+
     Ion<R, D> cur;
     if (n > 0) load_ion<R, D>(in, bin_slot(tile, cap, lo_in, min((int)threadIdx.x, n - 1)), cur);
     for (int i0 = 0; i0 < n; i0 += blockDim.x) {
         const int i = i0 + threadIdx.x;
         const bool valid = i < n;
+        if constexpr (REC)
+            if (valid && pk_base + i < pk_n) store_ion<R, D>(pk, pk_base + i, cur);
         // prefetch the next ion of this lane while the current one is pushed
         Ion<R, D> nxt;
         const int inext = i + blockDim.x;

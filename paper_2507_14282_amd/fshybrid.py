@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfshybrid.so")
 
 FS_OK, FS_EINVAL, FS_ECAPACITY, FS_EIDOVERFLOW, FS_ENUMERIC, FS_EDEVICE, FS_ETILE = 0, -1, -2, -3, -4, -5, -6
+FS_PACK_IONS = 1
 PUSH, INJECT, DEPOSIT, FIELD = 1, 4, 8, 16
 ALL = PUSH | INJECT | DEPOSIT | FIELD
 WALL = {"open": 0, "faux_shock": 1, "specular": 2}
@@ -148,9 +149,9 @@ def library():
         L.fs_timing_enable.argtypes = [vp, i32]
         L.fs_timing_read.argtypes = [vp, vp, vp, vp]
         R, A = C.POINTER(FsRecord), C.POINTER(FsAdjoint)
-        L.fs_step_record.argtypes = [vp, P, F, i64, R, C.POINTER(FsStats), vp]
+        L.fs_step_record.argtypes = [vp, P, F, i64, R, C.POINTER(FsPacked), C.POINTER(FsStats), vp]
         K = C.POINTER(FsPacked)
-        L.fs_tape_pack.argtypes = [vp, P, K, P, R, K, vp]
+        L.fs_tape_pack.argtypes = [vp, P, K, P, R, K, u32, vp]
         L.fs_adjoint_step.argtypes = [vp, K, F, K, F, i64, i64, A, vp, vp]
         L.fs_adjoint_park.argtypes = [vp, K, A, vp, i64, vp]
         L.fs_adjoint_unpark.argtypes = [vp, K, A, vp, i64, vp]
@@ -293,11 +294,13 @@ class Simulation:
         self._check(rc)
         return st.as_dict() if st is not None else None
 
-    def step_record(self, step: int, rec: "FsRecord", stats: bool = False):
+    def step_record(self, step: int, rec: "FsRecord", stats: bool = False, pack_in: "FsPacked | None" = None):
         """Full step that writes the record the reverse sweep needs
-        (continuous deposit mode only)."""
+        (continuous deposit mode only), and with pack_in packs its input
+        state's ions there."""
         st = FsStats() if stats else None
         rc = self.lib.fs_step_record(self.h, self.sp, C.byref(self.f), int(step), C.byref(rec),
+                                     C.byref(pack_in) if pack_in is not None else None,
                                      C.byref(st) if st is not None else None, self.stream)
         self._check(rc)
         return st.as_dict() if st is not None else None

@@ -288,7 +288,9 @@ def test_tape_pack_keeps_the_live_ions_and_the_record_in_packed_indices(dim, wal
     in bin order (bottom run, then the top run from the top down) with every
     section copied, and the packed record of the state before maps each ion
     to the packed index of the same ion after the step (the bin record,
-    translated).  A packed state one ion too small sets the status flag."""
+    translated).  The recorded step's own packing of its input (pack_in)
+    equals the pack pass bit for bit.  A packed state one ion too small sets
+    the status flag."""
     import ctypes as C
     import torch
     from paper_2507_14282_amd import adjoint as A
@@ -306,7 +308,10 @@ def test_tape_pack_keeps_the_live_ions_and_the_record_in_packed_indices(dim, wal
                 for k2, v in sim.sections(k).items()} for k in range(nsp)]
     n_pre = [sim.count(k) for k in range(nsp)]
     P0 = A._Packed(sim, nsp, [n + 5 for n in n_pre], status)
-    sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(P0.s), None, None, None, sim.stream))
+    sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(P0.s), None, None, None, F.FS_PACK_IONS, sim.stream))
+    # the same state's offsets alone; the recorded step packs its ions
+    P0s = A._Packed(sim, nsp, [n + 5 for n in n_pre], status)
+    sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(P0s.s), None, None, None, 0, sim.stream))
     pre_sp = (F.FsParticles * 2)()
     C.memmove(pre_sp, sim.sp, C.sizeof(pre_sp))
     rec = F.FsRecord()
@@ -315,13 +320,22 @@ def test_tape_pack_keeps_the_live_ions_and_the_record_in_packed_indices(dim, wal
         t = torch.full((int(sim.L.capacity[k]),), -7, dtype=torch.int32, device="cuda:0")
         rec.dst[k], rec.capacity[k] = t.data_ptr(), int(sim.L.capacity[k])
         keep.append(t)
-    sim.step_record(20, rec)
+    sim.step_record(20, rec, pack_in=P0s.s)
     n_post = [sim.count(k) for k in range(nsp)]
     P1 = A._Packed(sim, nsp, n_post, status)
     sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(P1.s), pre_sp, C.byref(rec), C.byref(P0.s),
-                                    sim.stream))
+                                    F.FS_PACK_IONS, sim.stream))
     torch.cuda.synchronize()
     assert int(status.item()) == 0
+    for k in range(nsp):
+        a, b = P0.sections(k), P0s.sections(k)
+        n = n_pre[k]
+        assert torch.equal(a["toff"], b["toff"])
+        for name in ("cell", "id"):
+            assert torch.equal(a[name][:n], b[name][:n]), name
+        for name in ("off", "v"):
+            for x, y in zip(a[name], b[name]):
+                assert torch.equal(x[:n], y[:n]), name
     for k in range(nsp):
         for P, sec, n in ((P0, pre_sec[k], n_pre[k]), (P1, sim.sections(k), n_post[k])):
             cap = sec["tile_cap"]
@@ -362,6 +376,7 @@ def test_tape_pack_keeps_the_live_ions_and_the_record_in_packed_indices(dim, wal
         assert np.array_equal(bd == -1, d == -1) and np.array_equal(bd <= -2, d <= -2)
     # one ion short
     small = A._Packed(sim, nsp, [n - 1 for n in n_post], status)
-    sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(small.s), None, None, None, sim.stream))
+    sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(small.s), None, None, None, F.FS_PACK_IONS,
+                                    sim.stream))
     torch.cuda.synchronize()
     assert int(status.item()) != 0
