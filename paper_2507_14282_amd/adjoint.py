@@ -292,7 +292,10 @@ class AdjointRun:
                 ck = _State(sim, self.nsp)
                 ck.counts = [sim.count(k) for k in range(self.nsp)]
                 self.checkpoints[n] = ck
-            sim.step(n, stats=False)
+            # the last step of each segment reports its counters, so a tile
+            # bin or crosser list that overflowed raises (FS_ETILE) rather
+            # than dropping ions from the differentiated run
+            sim.step(n, stats=(n + 1) % self.K_run == 0 or n + 1 == self.nsteps)
         self.nid = sim.next_id
         return self.loss_value()
 
