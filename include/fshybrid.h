@@ -454,6 +454,16 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
 int fs_tape_pack(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_particles* prev_sp,
                  const fs_record* rec, fs_packed* prev, uint32_t flags, hipStream_t s);
 
+/* The inverse of a pack with FS_PACK_IONS: the ions of *pk (its offsets and
+ * ions as fs_tape_pack left them) into the bins of sp (buf[cur],
+ * tile_count[cur] and count), tile t's ions in the bottom run of its bin in
+ * packed order.  A later fs_tape_pack of sp gives back *pk's ions in the same
+ * order; a step from sp moves every ion as it would from the state that
+ * was packed.  Asynchronous on s; a tile with more ions than tile_cap sets
+ * *pk->status (those beyond are dropped).  FS_EINVAL on a NULL argument,
+ * FS_ECAPACITY as fs_step for a particle buffer smaller than the layout. */
+int fs_tape_unpack(fs_handle* h, const fs_packed* pk, fs_particles* sp, hipStream_t s);
+
 /* Reverse of step `step` (n -> n+1, recorded with fs_step_record and packed
  * with fs_tape_pack).  pn / f_n: the packed state before the step (with the
  * step's record in pn->dst) and its fields (B, gather grid); pn1 / f_n1: the

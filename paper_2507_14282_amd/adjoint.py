@@ -11,18 +11,19 @@ with every discrete decision of the forward run held fixed (pathwise, common
 random numbers).
 
 Everything numeric runs in the library (``fs_precursor_loss``,
-``fs_adjoint_seed``, ``fs_step_record``, ``fs_tape_pack``,
-``fs_adjoint_step``, ``fs_adjoint_park`` / ``fs_adjoint_unpark``,
-``fs_adjoint_init``); this module owns the buffers and the schedule: a
-forward pass that keeps a checkpoint every K steps, and a reverse pass that
-re-runs each K-step segment from its checkpoint with recording and walks it
-backwards.  The re-run steps between two working bin buffers; after each
-step the state is packed to its live ions into the tape (``fs_packed``),
-together with where the step put every ion.  Particle adjoints are indexed
-like the packed states, in two buffers the reverse steps ping-pong, so the
-reverse passes stream them in the order of the particles.  The tape, the
-records and the adjoint buffers are allocated once and reused by every
-later reverse pass of the run.
+``fs_adjoint_seed``, ``fs_step_record``, ``fs_tape_pack`` /
+``fs_tape_unpack``, ``fs_adjoint_step``, ``fs_adjoint_park`` /
+``fs_adjoint_unpark``, ``fs_adjoint_init``); this module owns the buffers
+and the schedule: a forward pass that keeps a checkpoint every K steps (the
+live ions packed, and the fields), and a reverse pass that re-runs each
+K-step segment from its checkpoint with recording and walks it backwards.
+The re-run unpacks the checkpoint into the simulation's own bins and steps
+between its two buffers; every state of the segment is packed to its live
+ions into the tape (``fs_packed``), together with where the step put every
+ion.  Particle adjoints are indexed like the packed states, in two buffers
+the reverse steps ping-pong, so the reverse passes stream them in the order
+of the particles.  The tape, the records and the adjoint buffers are
+allocated once and reused by every later reverse pass of the run.
 """
 
 from __future__ import annotations
@@ -35,28 +36,22 @@ import torch
 from . import fshybrid as F
 
 
-class _State:
-    """One particle/field state held in tensors of its own: per species the
-    particle buffer and its tile counts, B, E, the gather grid, the moment
-    grids and the id counter.  Either a copy of a simulation's current state
-    (checkpoints) or an empty slot a recorded step writes into directly."""
+class _Bins:
+    """Particle bins the reverse pass re-runs its segments on: buffers of
+    their own (own=True), or one of the simulation's two buffers (`which`),
+    whose forward state is not needed once the forward pass is done."""
 
-    def __init__(self, sim: F.Simulation, nsp: int, copy: bool = True):
-        def take(t):
-            return t.clone() if copy else torch.empty_like(t)
-        self.buf, self.cnt = [], []
-        for k in range(nsp):
-            cur = int(sim.sp[k].cur)
-            self.buf.append(take(sim.bufs[k][cur]))
-            self.cnt.append(take(sim.cnts[k][cur]))
-        self.B = take(sim.B)
-        self.E = take(sim.E)
-        self.gather = take(sim.gather)
-        self.mom = [take(m) for m in sim.mom[:nsp]]
-        self.next_id = sim.next_id if copy else -1
+    def __init__(self, sim: F.Simulation, nsp: int, which: int, own: bool = False):
+        take = torch.empty_like if own else (lambda t: t)
+        self.buf = [take(sim.bufs[k][which]) for k in range(nsp)]
+        self.cnt = [take(sim.cnts[k][which]) for k in range(nsp)]
+
+    @staticmethod
+    def bytes(sim: F.Simulation, nsp: int) -> int:
+        return int(sum(sim.bufs[k][0].numel() + 4 * sim.cnts[k][0].numel() for k in range(nsp)))
 
     def particles(self, sim: F.Simulation):
-        """fs_particles structs pointing at this state's buffers."""
+        """fs_particles structs pointing at these bins (cur 0)."""
         sp = (F.FsParticles * 2)()
         for k in range(2):
             kk = min(k, len(self.buf) - 1)
@@ -70,31 +65,20 @@ class _State:
             P.species = k
         return sp
 
-    def fields(self, sim: F.Simulation) -> F.FsFields:
-        f = F.FsFields()
-        f.B, f.E, f.gather = self.B.data_ptr(), self.E.data_ptr(), self.gather.data_ptr()
-        f.mom[0] = self.mom[0].data_ptr()
-        f.mom[1] = self.mom[1].data_ptr() if len(self.mom) > 1 else None
-        return f
-
-    # The structs of a state only hold the addresses of its own tensors, so
-    # each is built once and kept on the state (the reverse pass would
-    # otherwise spend more host time building them than the GPU spends on
-    # the small boxes' steps).
+    # The structs only hold addresses: of these bins and of the simulation's
+    # device particle count, so each is built once per simulation and kept
+    # (the reverse pass would otherwise spend more host time building them
+    # than the GPU spends on the small boxes' steps).
     def sp(self, sim: F.Simulation):
-        if "_sp" not in self.__dict__:
-            self._sp = self.particles(sim)
+        key = tuple(c.data_ptr() for c in sim.counts)
+        if self.__dict__.get("_sp_key") != key:
+            self._sp, self._sp_key = self.particles(sim), key
         return self._sp
 
-    def f(self, sim: F.Simulation) -> F.FsFields:
-        if "_f" not in self.__dict__:
-            self._f = self.fields(sim)
-        return self._f
-
-    def step_to(self, sim: F.Simulation, post: "_State"):
-        """fs_particles of a step that reads this state's bins and writes
-        post's (cur 0)."""
-        key = post.buf[0].data_ptr()
+    def step_to(self, sim: F.Simulation, post: "_Bins"):
+        """fs_particles of a step that reads these bins and writes post's
+        (cur 0)."""
+        key = (tuple(c.data_ptr() for c in sim.counts), post.buf[0].data_ptr())
         cache = self.__dict__.setdefault("_to", {})
         if key not in cache:
             sp = self.particles(sim)
@@ -106,19 +90,29 @@ class _State:
 
 
 class _Fields:
-    """The grid part of a tape state: B, the gather grid and the moment grids
-    (filled by the recorded step that produces the state).  The reverse step
-    does not read E, so every tape state's step writes E into one shared
-    array."""
+    """The grid part of a state: B, the gather grid and the moment grids.
+    The reverse step does not read E, so every state shares one array for
+    it (the recorded steps write it)."""
 
-    def __init__(self, sim: F.Simulation, nsp: int, E: torch.Tensor):
-        self.B = torch.empty_like(sim.B)
+    def __init__(self, sim: F.Simulation, nsp: int, E: torch.Tensor, copy: bool = False):
+        def take(t):
+            return t.clone() if copy else torch.empty_like(t)
+        self.B = take(sim.B)
         self.E = E
-        self.gather = torch.empty_like(sim.gather)
-        self.mom = [torch.empty_like(m) for m in sim.mom[:nsp]]
+        self.gather = take(sim.gather)
+        self.mom = [take(m) for m in sim.mom[:nsp]]
 
-    fields = _State.fields
-    f = _State.f
+    def fields(self, sim: F.Simulation) -> F.FsFields:
+        f = F.FsFields()
+        f.B, f.E, f.gather = self.B.data_ptr(), self.E.data_ptr(), self.gather.data_ptr()
+        f.mom[0] = self.mom[0].data_ptr()
+        f.mom[1] = self.mom[1].data_ptr() if len(self.mom) > 1 else None
+        return f
+
+    def f(self, sim: F.Simulation) -> F.FsFields:
+        if "_f" not in self.__dict__:
+            self._f = self.fields(sim)
+        return self._f
 
 
 def _section_bytes(n: int, dim: int, rb: int) -> int:
@@ -129,10 +123,11 @@ def _section_bytes(n: int, dim: int, rb: int) -> int:
 
 
 class _Packed:
-    """One packed tape state (fs_packed): the live ions of each species, the
-    tile offsets and the record of the step that leaves the state."""
+    """One packed state (fs_packed): the live ions of each species, the tile
+    offsets and (with_dst, the tape's states) the record of the step that
+    leaves the state."""
 
-    def __init__(self, sim: F.Simulation, nsp: int, n, status: torch.Tensor):
+    def __init__(self, sim: F.Simulation, nsp: int, n, status: torch.Tensor, with_dst: bool = True):
         dim = int(sim.p["dim"])
         rb = torch.finfo(sim.real).bits // 8
         nt = int(sim.L.ntiles)
@@ -141,9 +136,11 @@ class _Packed:
         self.keep = []
         self.n, self.dim, self.real = [int(x) for x in n], dim, sim.real
         for k in range(nsp):
-            buf = torch.empty(_section_bytes(int(n[k]), dim, rb), dtype=torch.uint8, device=dev)
+            # never empty: an empty tensor has no address (a species with
+            # no ion yet still needs its arrays)
+            buf = torch.empty(max(_section_bytes(int(n[k]), dim, rb), 256), dtype=torch.uint8, device=dev)
             toff = torch.empty(nt + 1, dtype=torch.int32, device=dev)
-            dst = torch.empty(max(int(n[k]), 1), dtype=torch.int32, device=dev)
+            dst = torch.empty(max(int(n[k]), 1) if with_dst else 1, dtype=torch.int32, device=dev)
             self.s.buf[k], self.s.toff[k], self.s.dst[k] = buf.data_ptr(), toff.data_ptr(), dst.data_ptr()
             self.s.n[k] = int(n[k])
             self.keep += [buf, toff, dst]
@@ -170,13 +167,32 @@ class _Packed:
         return out
 
     @staticmethod
-    def bytes(sim: F.Simulation, nsp: int, n) -> int:
+    def bytes(sim: F.Simulation, nsp: int, n, with_dst: bool = True) -> int:
         dim = int(sim.p["dim"])
         rb = torch.finfo(sim.real).bits // 8
-        return sum(_section_bytes(int(n[k]), dim, rb) + 4 * (int(n[k]) + int(sim.L.ntiles) + 2) for k in range(nsp))
+        return sum(_section_bytes(int(n[k]), dim, rb) + 4 * ((int(n[k]) if with_dst else 1) + int(sim.L.ntiles) + 2)
+                   for k in range(nsp))
 
 
-def _recorded_step(sim: F.Simulation, n: int, pre: _State, f_pre, post: _State, f_post, rec: F.FsRecord,
+class _Checkpoint:
+    """A state the forward pass keeps: its ions packed (the unpacked bins
+    give a re-run the same trajectories), B, the gather grid, the moment
+    grids and the id counter."""
+
+    def __init__(self, sim: F.Simulation, nsp: int, E: torch.Tensor, status: torch.Tensor):
+        self.counts = [sim.count(k) for k in range(nsp)]
+        self.next_id = sim.next_id
+        self.packed = _Packed(sim, nsp, self.counts, status, with_dst=False)
+        self.fields = _Fields(sim, nsp, E, copy=True)
+        sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(self.packed.s), None, None, None, F.FS_PACK_IONS,
+                                        sim.stream))
+
+    @staticmethod
+    def bytes(sim: F.Simulation, nsp: int, n) -> int:
+        return _Packed.bytes(sim, nsp, n, with_dst=False) + _fields_bytes(sim, nsp)
+
+
+def _recorded_step(sim: F.Simulation, n: int, pre: _Bins, f_pre, post: _Bins, f_post, rec: F.FsRecord,
                    pack_in: "_Packed"):
     """Step n from the bins of `pre` (fields f_pre) into the bins of `post`
     (fields f_post) without copying particles, packing pre's ions into
@@ -214,28 +230,19 @@ def checkpoint_interval(nsteps: int, K: int, state_bytes: int, free_bytes: int, 
                       f"{free_bytes / 1e9:.1f} GB are free")
 
 
-def _state_bytes(sim: F.Simulation, nsp: int) -> int:
-    """Bytes of one checkpoint (the full particle bins and the fields)."""
-    t = [sim.B, sim.E, sim.gather] + list(sim.mom[:nsp])
-    for k in range(nsp):
-        cur = int(sim.sp[k].cur)
-        t += [sim.bufs[k][cur], sim.cnts[k][cur]]
-    return int(sum(x.numel() * x.element_size() for x in t))
-
-
 def _fields_bytes(sim: F.Simulation, nsp: int) -> int:
     """Bytes of the grids of one tape state (E is shared)."""
     return int(sum(x.numel() * x.element_size() for x in [sim.B, sim.gather] + list(sim.mom[:nsp])))
 
 
 def _fixed_bytes(sim: F.Simulation, nsp: int, n) -> int:
-    """Bytes the reverse pass holds besides checkpoints and tape: two working
-    bin states, the bin record, the tape's shared E, the adjoints (two
-    buffers of n per species and the grid adjoints) and the id-indexed
-    parking scratch."""
+    """Bytes the reverse pass holds besides checkpoints and tape: the bin
+    record, the shared E, the adjoints (two buffers of n per species and the
+    grid adjoints) and the id-indexed parking scratch (it re-runs the
+    segments on the simulation's own bins)."""
     dim = int(sim.p["dim"])
     rb = torch.finfo(sim.real).bits // 8
-    work = 2 * _state_bytes(sim, nsp) + sum(4 * int(sim.L.capacity[k]) for k in range(nsp))
+    work = sum(4 * int(sim.L.capacity[k]) for k in range(nsp))
     work += sim.E.numel() * sim.E.element_size()
     lam = sum(2 * (dim + 3) * rb * int(n[k]) for k in range(nsp)) + 8 * (3 * int(sim.L.ncent) + 6 * int(sim.L.nnode))
     park = nsp * (dim + 3) * rb * int(sim.next_id + sim.next_id // 8 + 4096)
@@ -257,6 +264,8 @@ class AdjointRun:
         self.sim = None
         self.checkpoints = {}
         self._bufs = None      # tape, records and adjoints, kept for later reverse passes
+        self._E = None         # the E every kept state shares
+        self._status = None    # overflow flag of every packed state
 
     # --- forward ----------------------------------------------------------
     def forward(self, u_sh: float, alpha_cr: float, amps) -> float:
@@ -282,16 +291,35 @@ class AdjointRun:
             free += self._bufs["bytes"]          # reused, already counted out of free
         else:
             self._bufs = None
+        if self._E is None or self._E.shape != sim.E.shape or self._E.dtype != sim.E.dtype:
+            self._E = torch.empty_like(sim.E)
+            self._status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._status.zero_()
+        # a packed state holds at most the initial ions plus those injected
+        # since: bounded here by (ppc + ppc_cr) per transverse cell and step
+        # (the CFL-limited inflow) and a sixteenth
+        ntr = int(sim.L.nyc) * int(sim.L.nzc)
+        grow = self.nsteps * ntr * (int(p["ppc"]) + int(p.get("ppc_cr", 0)))
         n0 = [sim.count(k) for k in range(self.nsp)]
-        n_est = [c + c // 4 + 4096 for c in n0]
+        n_est = [c + c // 16 + grow + 4096 for c in n0]
         free -= _fixed_bytes(sim, self.nsp, n_est)
         tape = _fields_bytes(sim, self.nsp) + _Packed.bytes(sim, self.nsp, n_est)
-        self.K_run = checkpoint_interval(self.nsteps, self.K, _state_bytes(sim, self.nsp), free, tape_bytes=tape)
+        ckb = _Checkpoint.bytes(sim, self.nsp, n_est)
+        # the re-runs step between two bin buffers of their own when those
+        # fit beside the requested interval (measured 5% faster on the 2D box
+        # than stepping on the simulation's own buffers), else on the
+        # simulation's
+        own = 2 * _Bins.bytes(sim, self.nsp)
+        want = min(self.K, self.nsteps)
+        try:
+            k_own = checkpoint_interval(self.nsteps, self.K, ckb, free - own, tape_bytes=tape)
+        except MemoryError:
+            k_own = 0
+        self.own_bins = k_own == want
+        self.K_run = k_own if self.own_bins else checkpoint_interval(self.nsteps, self.K, ckb, free, tape_bytes=tape)
         for n in range(self.nsteps):
             if n % self.K_run == 0:
-                ck = _State(sim, self.nsp)
-                ck.counts = [sim.count(k) for k in range(self.nsp)]
-                self.checkpoints[n] = ck
+                self.checkpoints[n] = _Checkpoint(sim, self.nsp, self._E, self._status)
             # the last step of each segment reports its counters, so a tile
             # bin or crosser list that overflowed raises (FS_ETILE) rather
             # than dropping ions from the differentiated run
@@ -333,7 +361,8 @@ class AdjointRun:
         n = self._packed_size()
         b = self._bufs
         if (b is not None and b["key"] == self._key(sim) and len(b["fields"]) >= K
-                and all(b["n"][k] >= n[k] for k in range(self.nsp)) and b["nid"] >= self.nid):
+                and all(b["n"][k] >= n[k] for k in range(self.nsp)) and b["nid"] >= self.nid
+                and (b["work"] is not None) == self.own_bins):
             return b
         self._bufs = b = None
         dim = int(self.p["dim"])
@@ -360,28 +389,33 @@ class AdjointRun:
             t = torch.empty(cap, dtype=torch.int32, device=dev)
             rec.dst[k], rec.capacity[k] = t.data_ptr(), cap
             keep.append(t)
-        status = torch.zeros(1, dtype=torch.int32, device=dev)
         nid = self.nid + self.nid // 8 + 4096
         scratch = torch.empty(self.nsp * (dim + 3) * nid, dtype=sim.real, device=dev)
-        work = [_State(sim, self.nsp, copy=False) for _ in range(2)]
-        E = torch.empty_like(sim.E)
-        fields = [_Fields(sim, self.nsp, E) for _ in range(K)]
-        packed = [_Packed(sim, self.nsp, n, status) for _ in range(K + 1)]
+        fields = [_Fields(sim, self.nsp, self._E) for _ in range(K)]
+        packed = [_Packed(sim, self.nsp, n, self._status) for _ in range(K + 1)]
         nbytes = _fixed_bytes(sim, self.nsp, n) + K * (_fields_bytes(sim, self.nsp) + _Packed.bytes(sim, self.nsp, n))
+        work = [_Bins(sim, self.nsp, w, own=True) for w in range(2)] if self.own_bins else None
+        if work is not None:
+            nbytes += 2 * _Bins.bytes(sim, self.nsp)
         self._bufs = dict(key=self._key(sim), n=n, nid=nid, lam=lam, keep=keep, lB=lB, lE=lE, rec=rec,
-                          status=status, scratch=scratch, work=work, fields=fields, packed=packed, bytes=nbytes)
+                          scratch=scratch, fields=fields, packed=packed, work=work, bytes=nbytes)
         return self._bufs
 
     def backward(self) -> np.ndarray:
         """Gradient [dL/du_sh, dL/dalpha_cr, dL/dA_1 .. dL/dA_M] of the last
-        forward pass."""
+        forward pass.  Where memory is short the re-runs use the
+        simulation's particle buffers (`own_bins` False), so afterwards
+        `self.sim` holds its final fields but not its final particles (a
+        later backward is unaffected)."""
         sim = self.sim
         lib, stream = sim.lib, sim.stream
         bufs = self._buffers()
         lam, rec, P = bufs["lam"], bufs["rec"], bufs["packed"]
         lam.cur = 0
-        bufs["status"].zero_()
         self.lB, self.lE = bufs["lB"], bufs["lE"]
+        # the re-runs step between two bin buffers: their own, or the
+        # simulation's
+        work = bufs["work"] or [_Bins(sim, self.nsp, 0), _Bins(sim, self.nsp, 1)]
         grads = torch.empty(2 + int(self.p["n_modes"]), dtype=torch.float64, device=self.device)
         gptr = C.c_void_p(grads.data_ptr())
         scratch = C.c_void_p(bufs["scratch"].data_ptr())
@@ -394,13 +428,14 @@ class AdjointRun:
             s1 = min(s0 + K, self.nsteps)
             ck = self.checkpoints[s0]
             sim.set_clock(ck.next_id)
-            flds = [ck] + bufs["fields"]
+            flds = [ck.fields] + bufs["fields"]
+            sim._check(lib.fs_tape_unpack(sim.h, C.byref(ck.packed.s), work[0].sp(sim), stream))
             # each state's tile offsets, then its ions as the recorded step
             # from it reads them (the segment's last state has no such step)
-            sim._check(lib.fs_tape_pack(sim.h, ck.sp(sim), C.byref(P[0].s), None, None, None, 0, stream))
-            pre, id0 = ck, []
+            sim._check(lib.fs_tape_pack(sim.h, work[0].sp(sim), C.byref(P[0].s), None, None, None, 0, stream))
+            pre, id0 = work[0], []
             for j, n in enumerate(range(s0, s1)):
-                post = bufs["work"][j % 2]
+                post = work[(j + 1) % 2]
                 _recorded_step(sim, n, pre, flds[j], post, flds[j + 1], rec, P[j])
                 id0.append(int(rec.id0))
                 last = F.FS_PACK_IONS if n + 1 == s1 else 0
@@ -418,13 +453,13 @@ class AdjointRun:
                                          C.byref(flds[j + 1].f(sim)), id0[j], s0 + j, C.byref(lam), gptr, stream)
                 sim._check(rc)
             if s0 == 0:
-                sim._check(lib.fs_adjoint_init(sim.h, C.byref(P[0].s), C.byref(ck.f(sim)), C.byref(lam), gptr,
-                                               stream))
+                sim._check(lib.fs_adjoint_init(sim.h, C.byref(P[0].s), C.byref(ck.fields.f(sim)), C.byref(lam),
+                                               gptr, stream))
             else:
                 sim._check(lib.fs_adjoint_park(sim.h, C.byref(P[0].s), C.byref(lam), scratch, nid, stream))
                 parked = True
         torch.cuda.synchronize(self.device)
-        if int(bufs["status"].item()) != 0:
+        if int(self._status.item()) != 0:
             raise RuntimeError("a packed tape state overflowed its size: the gradient is invalid")
         return grads.cpu().numpy()
 

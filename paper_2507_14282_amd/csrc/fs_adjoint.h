@@ -35,6 +35,12 @@ template <typename R> struct PLam {
     R* v[3];
 };
 
+// a[i] for a loop index the compiler keeps rolled (an unrolled select, so
+// that a stays in registers).
+template <typename T> __device__ __forceinline__ T pick3(const T a[3], int i) {
+    return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
+}
+
 // Real shape weights in FP64 and their derivatives d/d(offset).
 template <int S> __device__ __forceinline__ void weights_dw(double o, int& rel, double w[3], double dw[3]) {
     if constexpr (S == 1) {
@@ -263,6 +269,39 @@ __global__ __launch_bounds__(256) void k_tape_pack(Geo G, PBuf<R> in, const int3
     }
 }
 
+// A packed state back into bins: tile t's ions [toff[t], toff[t + 1]) to
+// the bottom run of its bin (slots t cap .. t cap + m - 1, counts (m, 0)),
+// in packed order; `split` workgroups a tile.  Workgroup 0 sets the total
+// count.  A tile with more than cap ions sets *status (those beyond are
+// dropped).
+template <typename R, int D>
+__global__ __launch_bounds__(256) void k_tape_unpack(Geo G, PBuf<R> in, const int32_t* __restrict__ toff, int64_t n,
+                                                     PBuf<R> out, int32_t* __restrict__ cnt, int64_t cap,
+                                                     long long* __restrict__ count, int split,
+                                                     int32_t* __restrict__ status) {
+    const int tile = blockIdx.x / split, part = blockIdx.x % split;
+    const long b = min((long)toff[tile], (long)n), e = min((long)toff[tile + 1], (long)n);
+    const long m = e > b ? e - b : 0;
+    const long kept = min(m, (long)cap);
+    if (part == 0 && threadIdx.x == 0) {
+        cnt[tile] = (int32_t)kept;
+        cnt[G.ntiles + tile] = 0;
+        if (m > cap) *status = 1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count = min((long)toff[G.ntiles], (long)n);
+    const long chunk = (kept + split - 1) / split;
+    const long r0 = min(kept, (long)part * chunk), r1 = min(kept, r0 + chunk);
+    for (long i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+        const long src = b + i, dst = (long)tile * cap + i;
+        out.cell[dst] = in.cell[src];
+#pragma unroll
+        for (int d = 0; d < D; ++d) out.off[d][dst] = in.off[d][src];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out.v[c][dst] = in.v[c][src];
+        out.id[dst] = in.id[src];
+    }
+}
+
 // A step's record from bin slots to packed indices: for each ion of the
 // input state (tile t, rank i in its bin, packed at toff_in[t] + i), the
 // output bin slot it went to, turned into the packed index of the output
@@ -371,8 +410,10 @@ __device__ __forceinline__ void deposit_vjp(const Geo& G, const double* sm, cons
                         lz0 <= X::GZ - NZ;
 #pragma unroll
     for (int d = 0; d < 3; ++d) gx[d] = gv[d] = 0.0;
-#pragma unroll
-    for (int c = 0; c < NZ; ++c)
+    // the z planes of a 3D stencil one at a time (registers)
+#pragma unroll 1
+    for (int c = 0; c < NZ; ++c) {
+        const double wz = pick3(w[2], c), dwz = pick3(dw[2], c);
 #pragma unroll
         for (int b = 0; b < NY; ++b)
 #pragma unroll
@@ -388,13 +429,14 @@ __device__ __forceinline__ void deposit_vjp(const Geo& G, const double* sm, cons
                     for (int q = 0; q < 4; ++q) m[q] = gi < 0 ? 0.0 : lM[4 * gi + q];
                 }
                 const double lm = m[0] + m[1] * v[0] + m[2] * v[1] + m[3] * v[2];
-                const double W = w[0][a] * w[1][b] * w[2][c];
-                gx[0] += dw[0][a] * w[1][b] * w[2][c] * lm;
-                if (D >= 2) gx[1] += w[0][a] * dw[1][b] * w[2][c] * lm;
-                if (D >= 3) gx[2] += w[0][a] * w[1][b] * dw[2][c] * lm;
+                const double W = w[0][a] * w[1][b] * wz;
+                gx[0] += dw[0][a] * w[1][b] * wz * lm;
+                if (D >= 2) gx[1] += w[0][a] * dw[1][b] * wz * lm;
+                if (D >= 3) gx[2] += w[0][a] * w[1][b] * dwz * lm;
 #pragma unroll
                 for (int d = 0; d < 3; ++d) gv[d] += W * m[1 + d];
             }
+    }
 }
 
 // An origin no stencil lies beyond: deposit_vjp then reads every node from
@@ -534,8 +576,21 @@ __global__ __launch_bounds__(256) void k_init_adj(const int32_t* __restrict__ to
 // zero for an ion the step removed.  in1 / n1: the packed state after the
 // step.  lam(E^n), lam(Bbar^n) (6 planar FP64 arrays of nnode) accumulate
 // per tile in LDS.
+// Workgroup size and minimum waves per SIMD the push transpose is compiled
+// for.  In 3D its LDS (the FP64 lam(E, Bbar) sums, the gather grid and the
+// moment adjoints of the tile's stencil: 80 KB in FP32) allows two
+// workgroups per CU, so 512-thread workgroups held to 128 VGPRs run four
+// waves per SIMD where 256-thread ones at their natural 166 VGPRs ran two
+// (the z planes of the stencil are walked in a loop to fit, without
+// spills).  The FP32 2D CIC kernel sits at 97 VGPRs, one above five waves
+// (the TSC one would spill there).
+template <typename R, int D, int S> struct AdjPush {
+    static constexpr int threads = D == 3 ? 512 : 256;
+    static constexpr int waves = sizeof(R) != 4 ? 1 : (D == 3 ? 4 : ((D == 2 && S == 1) ? 5 : 1));
+};
+
 template <typename R, int D, int S>
-__global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ toff, int64_t n,
+__global__ __launch_bounds__((AdjPush<R, D, S>::threads), (AdjPush<R, D, S>::waves)) void k_push_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ toff, int64_t n,
                                                   PBuf<R> in1, const double* __restrict__ lM,
                                                   const R* __restrict__ gather, const int32_t* __restrict__ dst_of,
                                                   PLam<R> post, PLam<R> pre, double* __restrict__ lEB, long nnode,
@@ -614,11 +669,11 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
         const int lx0 = min(max(cx - gx0 + rx, 0), X::GX - N);
         const int ly0 = D >= 2 ? min(max(cy - gy0 + ry, 0), X::GY - N) : 0;
         const int lz0 = D >= 3 ? min(max(cz - gz0 + rz, 0), X::GZ - N) : 0;
-#pragma unroll
+#pragma unroll 1
         for (int c = 0; c < NZ; ++c)
 #pragma unroll
             for (int b = 0; b < NY; ++b) {
-                const R wyz = wy[b] * wz[c];
+                const R wyz = wy[b] * pick3(wz, c);
 #pragma unroll
                 for (int a = 0; a < N; ++a) {
                     const R W = wx[a] * wyz;
@@ -668,8 +723,9 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
         }
 #pragma unroll
         for (int d = 0; d < D; ++d) weights_dw<S>((double)o[d], rel[d], w[d], dw[d]);
-#pragma unroll
-        for (int c = 0; c < NZ; ++c)
+#pragma unroll 1
+        for (int c = 0; c < NZ; ++c) {
+            const double wz2 = pick3(w[2], c), dwz2 = pick3(dw[2], c);
 #pragma unroll
             for (int b = 0; b < NY; ++b)
 #pragma unroll
@@ -678,10 +734,10 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
                     const Pair<R> p0 = sg[l], p1 = sg[X::GN + l], p2 = sg[2 * X::GN + l];
                     const double dot = (double)p0.x * lE[0] + (double)p0.y * lE[1] + (double)p1.x * lE[2] +
                                        (double)p1.y * lB[0] + (double)p2.x * lB[1] + (double)p2.y * lB[2];
-                    const double W = w[0][a] * w[1][b] * w[2][c];
-                    lx[0] += dw[0][a] * w[1][b] * w[2][c] * dot;
-                    if (D >= 2) lx[1] += w[0][a] * dw[1][b] * w[2][c] * dot;
-                    if (D >= 3) lx[2] += w[0][a] * w[1][b] * dw[2][c] * dot;
+                    const double W = w[0][a] * w[1][b] * wz2;
+                    lx[0] += dw[0][a] * w[1][b] * wz2 * dot;
+                    if (D >= 2) lx[1] += w[0][a] * dw[1][b] * wz2 * dot;
+                    if (D >= 3) lx[2] += w[0][a] * w[1][b] * dwz2 * dot;
                     atomicAdd(&sl[l], W * lE[0]);
                     atomicAdd(&sl[X::GN + l], W * lE[1]);
                     atomicAdd(&sl[2 * X::GN + l], W * lE[2]);
@@ -689,6 +745,7 @@ __global__ __launch_bounds__(256) void k_push_adj(Geo G, PBuf<R> in, const int32
                     atomicAdd(&sl[4 * X::GN + l], W * lB[1]);
                     atomicAdd(&sl[5 * X::GN + l], W * lB[2]);
                 }
+        }
 #pragma unroll
         for (int d = 0; d < D; ++d) pre.x[d][src] = (R)lx[d];
 #pragma unroll

@@ -118,6 +118,15 @@ int resolve_static_scratch(fs_handle* h) {
 // 2048 slots each, at most 16.
 int split_of(int64_t tile_cap) { return (int)std::max<int64_t>(1, std::min<int64_t>(16, tile_cap / 2048)); }
 
+// The workgroups per tile of a particle pass that stages its tile's stencil
+// and flushes it: split_of for boxes of few tiles, one where the tiles alone
+// give some 4096 workgroups (each extra workgroup of a tile stages and
+// flushes the whole stencil again: on the 3D box that was four times the
+// global atomics of one).
+int split_for(const fs_layout_info& L, int64_t tile_cap) {
+    return (int)std::max<int64_t>(1, std::min<int64_t>(split_of(tile_cap), (4096 + L.ntiles - 1) / L.ntiles));
+}
+
 int bits_for(int64_t n) {
     int b = 1;
     while ((int64_t(1) << b) < n) ++b;
@@ -414,7 +423,7 @@ void deposit_continuous(fs_handle* h, const fs_particles* sp, double* const mom[
         PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
         zero_u64(reinterpret_cast<unsigned long long*>(mom[k]), 4 * h->L.ndep, s);
         allow_lds(k_deposit_c<R, D, S>, lds);
-        const int sp_ = split_of(P.tile_cap);
+        const int sp_ = split_for(h->L, P.tile_cap);
         k_deposit_c<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, lds, s>>>(h->G, in, P.tile_count[P.cur], P.tile_cap,
                                                                             mom[k], h->ctr, sp_);
     }
@@ -736,8 +745,8 @@ int adjoint_step_impl(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, c
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         PBuf<R> in = sections<R>(pn->buf[k], pn->n[k], D);
         PBuf<R> in1 = sections<R>(pn1->buf[k], pn1->n[k], D);
-        const int sp_ = split_of(h->L.tile_cap[k]);
-        k_push_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
+        const int sp_ = split_for(h->L, h->L.tile_cap[k]);
+        k_push_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), AdjPush<R, D, S>::threads, 0, s>>>(
             h->G, in, pn->toff[k], pn->n[k], in1, h->alM[k], static_cast<const R*>(f_n->gather), pn->dst[k],
             plam<R>(lam, k, post, D), plam<R>(lam, k, pre, D), lam->lE, nn, (uint64_t)step, grads, sp_,
             policy_of(h, k) == FS_WALL_SPECULAR ? 1 : 0);
@@ -758,7 +767,7 @@ int adjoint_init_impl(fs_handle* h, const fs_packed* p0, const fs_fields* f0, fs
     fluid_adj(h, grads, s);
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         PBuf<R> in = sections<R>(p0->buf[k], p0->n[k], D);
-        const int sp_ = split_of(h->L.tile_cap[k]);
+        const int sp_ = split_for(h->L, h->L.tile_cap[k]);
         k_deposit_adj<R, D, S><<<(unsigned)(h->L.ntiles * sp_), 256, 0, s>>>(
             h->G, in, p0->toff[k], p0->n[k], h->alM[k], plam<R>(lam, k, lam->cur, D), sp_);
     }
@@ -800,6 +809,23 @@ int tape_pack_impl(fs_handle* h, const fs_particles* sp, fs_packed* out, const f
         }
     }
     return hip_check(h, hipGetLastError(), "tape pack launch");
+}
+
+// The packed state pk into the bins of sp (buf[cur], tile_count[cur], count).
+template <typename R, int D>
+int tape_unpack_impl(fs_handle* h, const fs_packed* pk, fs_particles* sp, hipStream_t s) {
+    const int nt = (int)h->L.ntiles;
+    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
+        fs_particles& P = sp[k];
+        PBuf<R> in = sections<R>(pk->buf[k], pk->n[k], D);
+        PBuf<R> out = sections<R>(P.buf[P.cur], P.capacity, D);
+        const int sp_ = (int)std::max<int64_t>(1, std::min<int64_t>(P.tile_cap / 1024, 4096 / nt));
+        k_tape_unpack<R, D><<<(unsigned)(nt * sp_), 256, 0, s>>>(h->G, in, pk->toff[k], pk->n[k], out,
+                                                                 P.tile_count[P.cur], P.tile_cap,
+                                                                 reinterpret_cast<long long*>(P.count), sp_,
+                                                                 pk->status);
+    }
+    return hip_check(h, hipGetLastError(), "tape unpack launch");
 }
 
 // Dispatch a templated implementation on (precision, dim).
@@ -1148,6 +1174,15 @@ int fs_tape_pack(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_
     auto run = [&]() -> int {
         FS_DISPATCH_RD(h, (tape_pack_impl<R, D>(h, sp, out, prev_sp, rec, prev, (flags & FS_PACK_IONS) != 0, s)));
     };
+    return run();
+}
+
+int fs_tape_unpack(fs_handle* h, const fs_packed* pk, fs_particles* sp, hipStream_t s) {
+    if (!h || !pk || !sp) return fail(h, FS_EINVAL, "NULL argument");
+    int rc = check_particles(h, sp);
+    if (!rc) rc = check_packed(h, pk, nullptr, false);
+    if (rc) return rc;
+    auto run = [&]() -> int { FS_DISPATCH_RD(h, (tape_unpack_impl<R, D>(h, pk, sp, s))); };
     return run();
 }
 

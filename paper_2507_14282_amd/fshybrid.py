@@ -152,6 +152,7 @@ def library():
         L.fs_step_record.argtypes = [vp, P, F, i64, R, C.POINTER(FsPacked), C.POINTER(FsStats), vp]
         K = C.POINTER(FsPacked)
         L.fs_tape_pack.argtypes = [vp, P, K, P, R, K, u32, vp]
+        L.fs_tape_unpack.argtypes = [vp, K, P, vp]
         L.fs_adjoint_step.argtypes = [vp, K, F, K, F, i64, i64, A, vp, vp]
         L.fs_adjoint_park.argtypes = [vp, K, A, vp, i64, vp]
         L.fs_adjoint_unpark.argtypes = [vp, K, A, vp, i64, vp]
@@ -170,7 +171,7 @@ def exported_symbols():
             "fs_phase_space", "fs_bperp_spectrum", "fs_checkpoint_bytes", "fs_checkpoint", "fs_restore",
             "fs_timing_enable", "fs_timing_read", "fs_step_record", "fs_adjoint_step", "fs_adjoint_init",
             "fs_precursor_loss", "fs_adjoint_seed", "fs_bperp_spectrum_noalloc", "fs_tape_pack",
-            "fs_adjoint_park", "fs_adjoint_unpark"]
+            "fs_adjoint_park", "fs_adjoint_unpark", "fs_tape_unpack"]
 
 
 def make_config(p: dict) -> FsConfig:

@@ -70,6 +70,24 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     assert np.max(np.abs(g1 - g2)) <= 1e-12 * np.max(np.abs(g1))
 
 
+def test_second_pass_of_a_run_matches_the_oracle():
+    """A run's second forward and reverse pass (new parameters, a new
+    simulation, the tape and working bins of the first pass reused) gives
+    the oracle's gradient at its own parameters, as the first did."""
+    from paper_2507_14282_amd import adjoint as A
+    kw, nsteps = CASES["cic_cr_inject"]
+    p = W.params(**kw, precision=64)
+    run = A.AdjointRun(p, nsteps, K=7)
+    amps = np.full(int(p["n_modes"]), float(p["mode_amp"]))
+    for u in (p["u_sh"], 1.1 * p["u_sh"]):
+        lg = run.forward(u, p["alpha_cr"], amps)
+        gg = run.backward()
+        lo, go = O.adjoint(dict(p, u_sh=u), nsteps)
+        print(f"u_sh {u}: own bins {run.own_bins}, loss {lg:.12e} / {lo:.12e}", flush=True)
+        assert abs(lg - lo) <= 1e-12 * abs(lo)
+        assert np.max(np.abs(gg - go)) <= 1e-12 * np.max(np.abs(go)), (gg, go)
+
+
 # Floor of the per-component FP32 bar, relative to the largest component:
 # a component below it is held to FLOOR * max|grad| absolute.
 FP32_FLOOR = 1e-6
@@ -380,3 +398,63 @@ def test_tape_pack_keeps_the_live_ions_and_the_record_in_packed_indices(dim, wal
                                     sim.stream))
     torch.cuda.synchronize()
     assert int(status.item()) != 0
+
+
+@pytest.mark.parametrize("dim", [1, 3])
+def test_tape_unpack_is_the_inverse_of_pack(dim):
+    """fs_tape_unpack puts a packed state into bins (tile t's ions in the
+    bottom run of its bin, in packed order, counts (m, 0), the total count);
+    packing those bins again gives the same ions in the same order, bit for
+    bit.  A packed state whose tile holds more ions than a bin sets the
+    status flag instead of writing past the bin."""
+    import ctypes as C
+    import torch
+    from paper_2507_14282_amd import adjoint as A
+    from paper_2507_14282_amd import fshybrid as F
+    kw = dict(nx=48, dx=0.5, ppc=8) if dim == 1 else dict(nx=16, ny=8, nz=8, dx=0.5, ppc=4)
+    p = W.params(dim=dim, ppc_cr=4, n_cr=0.05, wall_cr="faux_shock", u_sh=19.3, dt=0.0047, precision=32,
+                 deposit_mode="continuous", seed=31, **kw)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    for s in range(12):
+        sim.step(s)
+    nsp, ntiles = 2, int(sim.L.ntiles)
+    n = [sim.count(k) for k in range(nsp)]
+    status = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    Pa = A._Packed(sim, nsp, n, status)
+    sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(Pa.s), None, None, None, F.FS_PACK_IONS, sim.stream))
+    other = (F.FsParticles * 2)()
+    C.memmove(other, sim.sp, C.sizeof(other))
+    for k in range(2):
+        other[k].cur ^= 1
+    for k in range(nsp):     # the bins of the other buffer start as garbage
+        sim.bufs[k][int(other[k].cur)].fill_(0x5A)
+        sim.cnts[k][int(other[k].cur)].fill_(-3)
+    sim._check(sim.lib.fs_tape_unpack(sim.h, C.byref(Pa.s), other, sim.stream))
+    Pb = A._Packed(sim, nsp, n, status)
+    sim._check(sim.lib.fs_tape_pack(sim.h, other, C.byref(Pb.s), None, None, None, F.FS_PACK_IONS, sim.stream))
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    for k in range(nsp):
+        assert sim.count(k) == n[k]
+        a, b = Pa.sections(k), Pb.sections(k)
+        assert torch.equal(a["toff"], b["toff"])
+        cnt = sim.cnts[k][int(other[k].cur)].cpu().numpy()
+        assert np.array_equal(cnt[:ntiles], np.diff(a["toff"].cpu().numpy())) and np.all(cnt[ntiles:] == 0)
+        for name in ("cell", "id"):
+            assert torch.equal(a[name], b[name]), name
+        for name in ("off", "v"):
+            for x, y in zip(a[name], b[name]):
+                assert torch.equal(x, y), name
+    # a tile one ion over its bin: offsets that put all ions of species 0 in tile 0
+    cap = int(sim.L.tile_cap[0])
+    m = min(n[0], cap + 1)
+    bad = A._Packed(sim, nsp, n, status)
+    sim._check(sim.lib.fs_tape_pack(sim.h, sim.sp, C.byref(bad.s), None, None, None, F.FS_PACK_IONS, sim.stream))
+    t = bad.sections(0)["toff"]
+    t.fill_(m)
+    t[0] = 0
+    sim._check(sim.lib.fs_tape_unpack(sim.h, C.byref(bad.s), other, sim.stream))
+    torch.cuda.synchronize()
+    assert (int(status.item()) != 0) == (m > cap)
+    assert int(sim.cnts[0][int(other[0].cur)][0].item()) == min(m, cap)
