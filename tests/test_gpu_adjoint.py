@@ -93,7 +93,7 @@ def test_second_pass_of_a_run_matches_the_oracle():
 FP32_FLOOR = 1e-6
 
 
-@pytest.mark.parametrize("case", ["cic_cr_inject", "tsc_th_fs", "2d_oblique"])
+@pytest.mark.parametrize("case", ["cic_cr_inject", "tsc_th_fs", "2d_oblique", "3d_box"])
 def test_fp32_gradient_per_component(case):
     # FP32 particle state and particle adjoints, FP64 fields: each component
     # (u_sh, alpha_cr, every Fourier amplitude) against the FP64 oracle
