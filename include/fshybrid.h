@@ -382,11 +382,15 @@ int fs_bperp_spectrum_noalloc(fs_handle* h, const fs_fields* f, double* out, hip
  * left through x = 0, or the wall transmitted or dropped it), or -2 - slot
  * if the FS wall reflected it into that slot.  Entries of slots that held
  * no ion keep whatever they held.  id0 receives the first id the step can
- * inject (the injected ions are id0, id0 + 1, ..., thermal first). */
+ * inject (the injected ions are id0, id0 + 1, ..., thermal first).  stages
+ * (NULL for none; n_sub = 1 only) is device memory of 6 x ncent doubles
+ * where the step leaves its SSP-RK3 stages B1 and B2 (each planar like B),
+ * for fs_adjoint_step to read instead of recomputing them. */
 typedef struct fs_record {
     int32_t* dst[2];
     int64_t  capacity[2];
     int64_t  id0;
+    double*  stages;
 } fs_record;
 
 /* A particle state packed to its live ions: the reverse mode's tape, sized
@@ -434,9 +438,9 @@ typedef struct fs_adjoint {
  * state (sp's buf[cur]), the push also copies each input ion as it reads it
  * to its packed index in pack_in->buf: the ions of fs_tape_pack with
  * FS_PACK_IONS, without a pass of their own.  FS_EINVAL on another
- * configuration or on a NULL dst of a species, FS_ECAPACITY if a dst holds
- * fewer entries than the species' capacity or the capacity does not fit
- * the int32 encoding (above 2^31 - 3 slots). */
+ * configuration, a NULL dst of a species or rec->stages with n_sub > 1,
+ * FS_ECAPACITY if a dst holds fewer entries than the species' capacity or
+ * the capacity does not fit the int32 encoding (above 2^31 - 3 slots). */
 int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec,
                    const fs_packed* pack_in, fs_step_stats* st, hipStream_t s);
 
@@ -447,9 +451,10 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
  * prev_sp (as the step read it, packed into *prev) left the record in bin
  * slots; it goes into prev->dst in packed indices of *out.  Asynchronous on
  * s; an overflow of n[k] sets *out->status (*prev->status for a record
- * entry that points past out's n).  FS_EINVAL on a NULL argument (prev_sp, rec and prev are all
- * given or all NULL) or an unknown flag, FS_ECAPACITY if a species'
- * capacity does not fit the int32 tile offsets (above 2^31 - 3 slots). */
+ * entry that points past out's n).  FS_EINVAL on a NULL argument (prev_sp,
+ * rec and prev are all given or all NULL) or an unknown flag, FS_ECAPACITY
+ * if a species' capacity does not fit the int32 tile offsets (above
+ * 2^31 - 3 slots). */
 #define FS_PACK_IONS 1u
 int fs_tape_pack(fs_handle* h, const fs_particles* sp, fs_packed* out, const fs_particles* prev_sp,
                  const fs_record* rec, fs_packed* prev, uint32_t flags, hipStream_t s);
@@ -468,17 +473,20 @@ int fs_tape_unpack(fs_handle* h, const fs_packed* pk, fs_particles* sp, hipStrea
  * with fs_tape_pack).  pn / f_n: the packed state before the step (with the
  * step's record in pn->dst) and its fields (B, gather grid); pn1 / f_n1: the
  * packed state after it and its B and moment grids (f_n1->mom as the step
- * left them).  id0: the first id the step handed out (fs_record.id0).
+ * left them).  stages: the step's RK stages as fs_record.stages kept them
+ * (n_sub = 1), or NULL to recompute them from f_n->B.  id0: the first id
+ * the step handed out (fs_record.id0).
  * *lam holds on entry the adjoints after the step (particles in buffer cur,
  * in the packed indices of pn1; lB, lE of B^{n+1} and E^{n+1}) and on exit
  * those before it (particles in the other buffer, in the packed indices of
  * pn, which becomes cur; B^n, E^n).  Every ion of pn is written, zero for
  * one the step removed.  grads (device, 2 + n_modes doubles) accumulates
  * dL/du_sh and dL/dalpha_cr.  FS_EINVAL on a NULL argument (f_n1->mom
- * included), FS_ECAPACITY if an adjoint buffer is shorter than pn or pn1. */
+ * included) or stages with n_sub > 1, FS_ECAPACITY if an adjoint buffer is
+ * shorter than pn or pn1. */
 int fs_adjoint_step(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, const fs_packed* pn1,
-                    const fs_fields* f_n1, int64_t id0, int64_t step, fs_adjoint* lam, double* grads,
-                    hipStream_t s);
+                    const fs_fields* f_n1, const double* stages, int64_t id0, int64_t step, fs_adjoint* lam,
+                    double* grads, hipStream_t s);
 
 /* Moving the particle adjoints between two packings of one state: a segment
  * of steps re-run from its checkpoint packs its last state in another order

@@ -90,17 +90,23 @@ class _Bins:
 
 
 class _Fields:
-    """The grid part of a state: B, the gather grid and the moment grids.
-    The reverse step does not read E, so every state shares one array for
-    it (the recorded steps write it)."""
+    """The grid part of a state: B, the gather grid and the moment grids,
+    and (stages, for a tape state with one RK sub-step) the RK stages of the
+    step that produced it.  The reverse step does not read E, so every state
+    shares one array for it (the recorded steps write it)."""
 
-    def __init__(self, sim: F.Simulation, nsp: int, E: torch.Tensor, copy: bool = False):
+    def __init__(self, sim: F.Simulation, nsp: int, E: torch.Tensor, copy: bool = False, stages: bool = False):
         def take(t):
             return t.clone() if copy else torch.empty_like(t)
         self.B = take(sim.B)
         self.E = E
         self.gather = take(sim.gather)
         self.mom = [take(m) for m in sim.mom[:nsp]]
+        self.stages = torch.empty((2,) + tuple(sim.B.shape), dtype=torch.float64, device=sim.B.device) \
+            if stages else None
+
+    def stages_ptr(self):
+        return self.stages.data_ptr() if self.stages is not None else None
 
     def fields(self, sim: F.Simulation) -> F.FsFields:
         f = F.FsFields()
@@ -201,6 +207,7 @@ def _recorded_step(sim: F.Simulation, n: int, pre: _Bins, f_pre, post: _Bins, f_
     across; E is only written."""
     f_post.B.copy_(f_pre.B)
     f_post.gather.copy_(f_pre.gather)
+    rec.stages = f_post.stages_ptr()
     sp = pre.step_to(sim, post)
     rc = sim.lib.fs_step_record(sim.h, sp, C.byref(f_post.f(sim)), int(n), C.byref(rec), C.byref(pack_in.s), None,
                                 sim.stream)
@@ -230,9 +237,11 @@ def checkpoint_interval(nsteps: int, K: int, state_bytes: int, free_bytes: int, 
                       f"{free_bytes / 1e9:.1f} GB are free")
 
 
-def _fields_bytes(sim: F.Simulation, nsp: int) -> int:
-    """Bytes of the grids of one tape state (E is shared)."""
-    return int(sum(x.numel() * x.element_size() for x in [sim.B, sim.gather] + list(sim.mom[:nsp])))
+def _fields_bytes(sim: F.Simulation, nsp: int, stages: bool = False) -> int:
+    """Bytes of the grids of one state (E is shared), with the two RK stages
+    of a tape state."""
+    t = [sim.B, sim.gather] + list(sim.mom[:nsp])
+    return int(sum(x.numel() * x.element_size() for x in t) + (2 * 8 * sim.B.numel() if stages else 0))
 
 
 def _fixed_bytes(sim: F.Simulation, nsp: int, n) -> int:
@@ -303,7 +312,10 @@ class AdjointRun:
         n0 = [sim.count(k) for k in range(self.nsp)]
         n_est = [c + c // 16 + grow + 4096 for c in n0]
         free -= _fixed_bytes(sim, self.nsp, n_est)
-        tape = _fields_bytes(sim, self.nsp) + _Packed.bytes(sim, self.nsp, n_est)
+        # a tape state keeps the RK stages of its step (one sub-step only),
+        # which the reverse step would otherwise recompute
+        self.keep_stages = int(p["n_sub"]) == 1
+        tape = _fields_bytes(sim, self.nsp, self.keep_stages) + _Packed.bytes(sim, self.nsp, n_est)
         ckb = _Checkpoint.bytes(sim, self.nsp, n_est)
         # the re-runs step between two bin buffers of their own when those
         # fit beside the requested interval (measured 5% faster on the 2D box
@@ -362,7 +374,8 @@ class AdjointRun:
         b = self._bufs
         if (b is not None and b["key"] == self._key(sim) and len(b["fields"]) >= K
                 and all(b["n"][k] >= n[k] for k in range(self.nsp)) and b["nid"] >= self.nid
-                and (b["work"] is not None) == self.own_bins):
+                and (b["work"] is not None) == self.own_bins
+                and (b["fields"][0].stages is not None) == self.keep_stages):
             return b
         self._bufs = b = None
         dim = int(self.p["dim"])
@@ -391,9 +404,10 @@ class AdjointRun:
             keep.append(t)
         nid = self.nid + self.nid // 8 + 4096
         scratch = torch.empty(self.nsp * (dim + 3) * nid, dtype=sim.real, device=dev)
-        fields = [_Fields(sim, self.nsp, self._E) for _ in range(K)]
+        fields = [_Fields(sim, self.nsp, self._E, stages=self.keep_stages) for _ in range(K)]
         packed = [_Packed(sim, self.nsp, n, self._status) for _ in range(K + 1)]
-        nbytes = _fixed_bytes(sim, self.nsp, n) + K * (_fields_bytes(sim, self.nsp) + _Packed.bytes(sim, self.nsp, n))
+        nbytes = _fixed_bytes(sim, self.nsp, n) + K * (_fields_bytes(sim, self.nsp, self.keep_stages)
+                                                       + _Packed.bytes(sim, self.nsp, n))
         work = [_Bins(sim, self.nsp, w, own=True) for w in range(2)] if self.own_bins else None
         if work is not None:
             nbytes += 2 * _Bins.bytes(sim, self.nsp)
@@ -450,7 +464,8 @@ class AdjointRun:
                 sim._check(lib.fs_adjoint_unpark(sim.h, C.byref(P[m].s), C.byref(lam), scratch, nid, stream))
             for j in range(m - 1, -1, -1):
                 rc = lib.fs_adjoint_step(sim.h, C.byref(P[j].s), C.byref(flds[j].f(sim)), C.byref(P[j + 1].s),
-                                         C.byref(flds[j + 1].f(sim)), id0[j], s0 + j, C.byref(lam), gptr, stream)
+                                         C.byref(flds[j + 1].f(sim)), flds[j + 1].stages_ptr(), id0[j], s0 + j,
+                                         C.byref(lam), gptr, stream)
                 sim._check(rc)
             if s0 == 0:
                 sim._check(lib.fs_adjoint_init(sim.h, C.byref(P[0].s), C.byref(ck.fields.f(sim)), C.byref(lam),

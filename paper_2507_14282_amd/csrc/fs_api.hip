@@ -341,7 +341,10 @@ void zero_i32(int32_t* p, int64_t n, hipStream_t s) {
 // ------------------------------------------------------------------------
 // field update (FP64)
 // ------------------------------------------------------------------------
-template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hipStream_t s, bool rk) {
+// stages: NULL, or (one sub-step) where the RK stages B1 and B2 go instead
+// of the handle's scratch (3 x ncent doubles each, B1 first).
+template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hipStream_t s, bool rk,
+                                                 double* stages = nullptr) {
     const long nn = h->L.nnode, nc = h->L.ncent;
     const dim3 blk(kFX, kFY, 1);
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
@@ -376,10 +379,12 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
         const int zc = (int)std::min<int64_t>(h->L.nzc, 32), gz = (int)((h->L.nzc + zc - 1) / zc);
         if (rk) {
             const unsigned nb = (unsigned)(gx * gy * gz);
+            double* B1 = stages ? stages : h->B1;
+            double* B2 = stages ? stages + 3 * nc : h->B2;
             for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
-                k_stage3<<<nb, 256, 0, s>>>(h->F, f->B, f->B, h->B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy, zc);
-                k_stage3<<<nb, 256, 0, s>>>(h->F, h->B1, f->B, h->B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy, zc);
-                k_stage3<<<nb, 256, 0, s>>>(h->F, h->B2, f->B, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy,
+                k_stage3<<<nb, 256, 0, s>>>(h->F, f->B, f->B, B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy, zc);
+                k_stage3<<<nb, 256, 0, s>>>(h->F, B1, f->B, B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy, zc);
+                k_stage3<<<nb, 256, 0, s>>>(h->F, B2, f->B, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy,
                                             zc);
             }
         }
@@ -392,12 +397,14 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
     if (rk) {
         const int gx = (h->cfg.nx + FB::X - 1) / FB::X;
         const unsigned nb = (unsigned)(gx * gy * gz);
+        double* B1 = stages ? stages : h->B1;
+        double* B2 = stages ? stages + 3 * nc : h->B2;
         for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
             // SSP-RK3 (Shu-Osher): B1 = B + h F(B); B2 = 3/4 B + 1/4 (B1 + h F(B1));
             // B <- 1/3 B + 2/3 (B2 + h F(B2)); the last stage writes in place
-            k_stage<D><<<nb, 256, 0, s>>>(h->F, f->B, f->B, h->B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy);
-            k_stage<D><<<nb, 256, 0, s>>>(h->F, h->B1, f->B, h->B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy);
-            k_stage<D><<<nb, 256, 0, s>>>(h->F, h->B2, f->B, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy);
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, f->B, f->B, B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy);
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, B1, f->B, B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy);
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, B2, f->B, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy);
         }
     }
     const int gxo = (int)((h->L.nxn + FB::X - 1) / FB::X);
@@ -405,10 +412,10 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
                                                         gxo, gy);
 }
 
-template <typename R> void field_update(fs_handle* h, fs_fields* f, hipStream_t s, bool rk) {
-    if (h->cfg.dim == 1) field_update_d<R, 1>(h, f, s, rk);
-    else if (h->cfg.dim == 2) field_update_d<R, 2>(h, f, s, rk);
-    else field_update_d<R, 3>(h, f, s, rk);
+template <typename R> void field_update(fs_handle* h, fs_fields* f, hipStream_t s, bool rk, double* stages = nullptr) {
+    if (h->cfg.dim == 1) field_update_d<R, 1>(h, f, s, rk, stages);
+    else if (h->cfg.dim == 2) field_update_d<R, 2>(h, f, s, rk, stages);
+    else field_update_d<R, 3>(h, f, s, rk, stages);
 }
 
 // ------------------------------------------------------------------------
@@ -549,7 +556,7 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
     }
     if (fld) {
         const int t_fld = timing_begin(h, 3, s);
-        field_update<R>(h, f, s, true);
+        field_update<R>(h, f, s, true, rec ? rec->stages : nullptr);
         timing_end(h, t_fld, s);
     }
     if (push || inj)
@@ -669,17 +676,17 @@ void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb,
 // RK vector update that follows it.
 template <int D>
 void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* lBb, const double* Bn, double* lB,
-               double* grads, hipStream_t s) {
+               const double* stages, double* grads, hipStream_t s) {
     const long N = 3 * h->L.ncent;
     const int ns = h->cfg.n_sub;
     const double hs = h->cfg.dt / (double)ns;
+    // the start of each sub-step (B^n for the first)
     double* Bs = h->aBs;
-    (void)hipMemcpyAsync(Bs, Bn, N * sizeof(double), hipMemcpyDeviceToDevice, s);
     for (int sub = 0; sub + 1 < ns; ++sub) {
-        double* B0 = Bs + (size_t)sub * N;
+        const double* B0 = sub == 0 ? Bn : Bs + (size_t)sub * N;
         stage_launch<D>(h, B0, B0, h->B1, h->afl, 0.0, 1.0, hs, s);
         stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
-        stage_launch<D>(h, h->B2, B0, B0 + N, h->afl, 1.0 / 3.0, 2.0 / 3.0, hs, s);
+        stage_launch<D>(h, h->B2, B0, Bs + (size_t)(sub + 1) * N, h->afl, 1.0 / 3.0, 2.0 / 3.0, hs, s);
     }
     RkOut o;
     o.l0 = h->al[0]; o.l1 = h->al[1]; o.l2 = h->al[2]; o.lF = h->al[3]; o.out = lB; o.h = hs;
@@ -688,15 +695,22 @@ void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* 
     o.base = lB;
     ohm_adj<D, false, kEmitStage3>(h, Bn1, lE, lBb, o, grads, s);
     for (int sub = ns - 1; sub >= 0; --sub) {
-        const double* B0 = Bs + (size_t)sub * N;
-        stage_launch<D>(h, B0, B0, h->B1, h->afl, 0.0, 1.0, hs, s);
-        stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
+        const double* B0 = sub == 0 ? Bn : Bs + (size_t)sub * N;
+        // the stages, as the recorded step kept them or recomputed
+        const double *B1 = h->B1, *B2 = h->B2;
+        if (stages) {
+            B1 = stages;
+            B2 = stages + N;
+        } else {
+            stage_launch<D>(h, B0, B0, h->B1, h->afl, 0.0, 1.0, hs, s);
+            stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
+        }
         // lam(B2) = l2 + (dF/dB2)^T lF, then B2 = 3/4 B0 + 1/4 (B1 + h F(B1))
         o.base = o.l2;
-        ohm_adj<D, true, kEmitStage2>(h, h->B2, o.lF, nullptr, o, grads, s);
+        ohm_adj<D, true, kEmitStage2>(h, B2, o.lF, nullptr, o, grads, s);
         // lam(B1) = l1 + (dF/dB1)^T lF, then B1 = B0 + h F(B0)
         o.base = o.l1;
-        ohm_adj<D, true, kEmitStage1>(h, h->B1, o.lF, nullptr, o, grads, s);
+        ohm_adj<D, true, kEmitStage1>(h, B1, o.lF, nullptr, o, grads, s);
         // lam(B0) = l0 + (dF/dB0)^T lF: the start of this sub-step, which
         // ends the previous one (or is lam(B^n))
         o.base = o.l0;
@@ -717,14 +731,14 @@ void fluid_adj(fs_handle* h, double* grads, hipStream_t s) {
 
 template <typename R, int D, int S>
 int adjoint_step_impl(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, const fs_packed* pn1,
-                      const fs_fields* f_n1, int64_t id0, int64_t step, fs_adjoint* lam, double* grads,
-                      hipStream_t s) {
+                      const fs_fields* f_n1, const double* stages, int64_t id0, int64_t step, fs_adjoint* lam,
+                      double* grads, hipStream_t s) {
     const long nn = h->L.nnode;
     // fluid state the step's field update used: moments of the particles after it
     fluid_of(h, f_n1->mom, s);
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
     // final Ohm, then the RK3 sub-steps
-    field_adj<D>(h, f_n1->B, lam->lE, lam->lE + 3 * nn, f_n->B, lam->lB, grads, s);
+    field_adj<D>(h, f_n1->B, lam->lE, lam->lE + 3 * nn, f_n->B, lam->lB, stages, grads, s);
     // fluid at n+1: the moment adjoints the deposit transpose reads
     fluid_adj(h, grads, s);
     const int post = lam->cur, pre = lam->cur ^ 1;
@@ -1150,6 +1164,7 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
     if (h->cfg.c_light != 0.0 || h->cfg.coupling != 1)
         return fail(h, FS_EINVAL, "a recorded step covers the non-relativistic first-order step only");
     if (int rc = check_record(h, rec)) return rc;
+    if (rec->stages && h->cfg.n_sub != 1) return fail(h, FS_EINVAL, "kept RK stages need n_sub = 1");
     if (pack_in)
         if (int rc = check_packed(h, pack_in, nullptr, false)) return rc;
     rec->id0 = h->next_id;
@@ -1187,19 +1202,20 @@ int fs_tape_unpack(fs_handle* h, const fs_packed* pk, fs_particles* sp, hipStrea
 }
 
 int fs_adjoint_step(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, const fs_packed* pn1,
-                    const fs_fields* f_n1, int64_t id0, int64_t step, fs_adjoint* lam, double* grads,
-                    hipStream_t s) {
+                    const fs_fields* f_n1, const double* stages, int64_t id0, int64_t step, fs_adjoint* lam,
+                    double* grads, hipStream_t s) {
     if (!h || !pn || !f_n || !pn1 || !f_n1 || !lam || !grads) return fail(h, FS_EINVAL, "NULL argument");
     if (int rc = check_reverse_cfg(h)) return rc;
     if (!f_n->B || !f_n->gather || !f_n1->B || !f_n1->mom[0] || (h->has_cr && !f_n1->mom[1]))
         return fail(h, FS_EINVAL, "NULL field array");
     if (step < 0 || id0 < 0) return fail(h, FS_EINVAL, "negative step or id");
+    if (stages && h->cfg.n_sub != 1) return fail(h, FS_EINVAL, "kept RK stages need n_sub = 1");
     int rc = check_adjoint(h, lam);
     if (!rc) rc = check_packed(h, pn, lam, true);
     if (!rc) rc = check_packed(h, pn1, lam, false);
     if (rc) return rc;
     auto run = [&]() -> int {
-        FS_DISPATCH(h, (adjoint_step_impl<R, D, S>(h, pn, f_n, pn1, f_n1, id0, step, lam, grads, s)));
+        FS_DISPATCH(h, (adjoint_step_impl<R, D, S>(h, pn, f_n, pn1, f_n1, stages, id0, step, lam, grads, s)));
     };
     return run();
 }
