@@ -401,9 +401,11 @@ typedef struct fs_record {
  * from the top down); toff[k] has ntiles + 1 entries.  dst[k] (n[k] int32)
  * holds the record of the step that leaves this state, in packed indices of
  * the state after it: >= 0 kept there, -2 - i reflected into i, -1 removed.
- * *status (device int32) is set nonzero by fs_tape_pack when a species had
- * more live ions than n[k] (those beyond are dropped).  All arrays are
- * device memory owned by the caller. */
+ * *status (device int32) is set to 1 by fs_tape_pack (and fs_tape_unpack)
+ * when a species had more live ions than n[k] (those beyond are dropped),
+ * and to 2 by fs_adjoint_step, on the state after the step, when it did not
+ * find every ion the step injected near the boundaries where injection
+ * places them.  All arrays are device memory owned by the caller. */
 typedef struct fs_packed {
     void*    buf[2];
     int32_t* toff[2];

@@ -474,8 +474,11 @@ class AdjointRun:
                 sim._check(lib.fs_adjoint_park(sim.h, C.byref(P[0].s), C.byref(lam), scratch, nid, stream))
                 parked = True
         torch.cuda.synchronize(self.device)
-        if int(self._status.item()) != 0:
+        status = int(self._status.item())
+        if status == 1:
             raise RuntimeError("a packed tape state overflowed its size: the gradient is invalid")
+        if status != 0:
+            raise RuntimeError("the reverse pass missed ions a step injected: the gradient is invalid")
         return grads.cpu().numpy()
 
 

@@ -10,8 +10,10 @@
 //
 // One reverse step n+1 -> n, given the adjoints lam(B^{n+1}), lam(E^{n+1}),
 // lam(Bbar^{n+1}) and the particle adjoints lam(x^{n+1}), lam(v^{n+1/2}):
-//   final Ohm^T -> SSP-RK3^T (stages recomputed) -> fluid^T -> deposit^T ->
-//   injection^T -> (FS kick^T) -> move^T -> Boris^T -> gather^T.
+//   final Ohm^T -> SSP-RK3^T (the stages kept by the recorded step, or
+//   recomputed) -> fluid^T -> injection^T of the injected ions -> for every
+//   other ion deposit^T at n+1 -> (FS kick^T) -> move^T -> Boris^T ->
+//   gather^T, in one pass.
 // The reverse pass reads its particle states from a tape packed to the live
 // ions (tile t's ions at [toff[t], toff[t + 1]) in bin order), each with the
 // record of the step that leaves it in packed indices of the next state.
@@ -487,17 +489,27 @@ __global__ __launch_bounds__(256) void k_deposit_adj(Geo G, PBuf<R> in, const in
 // The ions a step injected (ids id0 .. id0 + ninj - 1, thermal first, nth
 // of them), found in the packed state after the step: their adjoint there
 // (post plus the deposit transpose at that state) goes into dL/du_sh
-// through their injection.  Few ions: the moment adjoints are read from
-// global memory.
+// through their injection.  Injection places an ion within a bounded depth
+// of its boundary, so only the tile columns [cx0, cx0 + ncols) are read,
+// one workgroup per tile of them; few ions: the moment adjoints are read
+// from global memory.  The workgroups count the injected ions they find
+// and the last one to finish compares the total with `expect`, sets
+// *status = 2 on a mismatch (an ion outside the columns) and resets ctr
+// (two counters, zero between launches).
 template <typename R, int D, int S>
 __global__ __launch_bounds__(256) void k_inject_adj(Geo G, PBuf<R> in, const int32_t* __restrict__ toff, int64_t n,
                                                     const double* __restrict__ lM, PLam<R> post, uint64_t step,
-                                                    int64_t id0, int64_t nth, int64_t ninj, double* grads) {
-    const long m = min((long)toff[G.ntiles], (long)n);
+                                                    int64_t id0, int64_t nth, int64_t ninj, int cx0, int ncols,
+                                                    unsigned long long* ctr, int64_t expect, int32_t* status,
+                                                    double* grads) {
+    const int tile = (cx0 + (int)(blockIdx.x % ncols)) + G.ntx * (int)(blockIdx.x / ncols);
+    const long b = min((long)toff[tile], (long)n), e = min((long)toff[tile + 1], (long)n);
     double acc = 0.0;
-    for (long q = (long)blockIdx.x * blockDim.x + threadIdx.x; q < m; q += (long)gridDim.x * blockDim.x) {
+    int found = 0;
+    for (long q = b + threadIdx.x; q < e; q += blockDim.x) {
         const int64_t g = (int64_t)in.id[q] - id0;
         if (g < 0 || g >= ninj) continue;
+        ++found;
         R o[3] = {0, 0, 0}, v[3];
 #pragma unroll
         for (int d = 0; d < D; ++d) o[d] = in.off[d][q];
@@ -512,6 +524,23 @@ __global__ __launch_bounds__(256) void k_inject_adj(Geo G, PBuf<R> in, const int
         acc += inject_vjp(G, step, (uint64_t)(id0 + g), g >= nth, lx0, lv);
     }
     block_add(acc, grads);
+    __shared__ int cnt[16];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) found += __shfl_xor(found, o);
+    if (__lane_id() == 0) cnt[threadIdx.x >> 6] = found;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long tot = 0;
+        for (int w = 0; w < (int)((blockDim.x + 63) >> 6); ++w) tot += cnt[w];
+        atomicAdd(&ctr[0], (unsigned long long)tot);
+        __threadfence();
+        if (atomicAdd(&ctr[1], 1ull) == gridDim.x - 1) {
+            const unsigned long long all = atomicAdd(&ctr[0], 0ull);
+            if ((int64_t)all != expect) *status = 2;
+            ctr[0] = 0;
+            ctr[1] = 0;
+        }
+    }
 }
 
 // Particle adjoints between two packings of the same ions, matched by id

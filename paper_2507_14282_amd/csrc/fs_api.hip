@@ -49,8 +49,9 @@ struct fs_handle {
     double* afl = nullptr;                  // fluid state of the reverse step
     double* alfl = nullptr;                 // its adjoint
     double* al[4] = {nullptr, nullptr, nullptr, nullptr};  // RK3 stage adjoints l0, l1, l2, lF
-    double* aBs = nullptr;                  // B at the start of each RK substep
+    double* aBs = nullptr;                  // B at the start of each RK substep after the first
     double* aob = nullptr;                  // Ohm transpose: lam(Bbar), lam(J) per node
+    unsigned long long* actr = nullptr;     // injected-ion counters of the reverse step (zero between launches)
     std::string err;
     // phase timing: pool of event pairs recorded on the caller's stream
     bool timing = false;
@@ -746,11 +747,33 @@ int adjoint_step_impl(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, c
     int64_t cth = 0, ccr = 0;
     inject_counts(h->cfg, step, cth, ccr);
     const int64_t ntr = h->L.nyc * h->L.nzc, nth = cth * ntr, ncr = ccr * ntr;
+    // injection puts a thermal ion at x = |u_sh + sigma n| U dt/dx and a CR at
+    // x = nx - |u2 - cr_w mu| U dt/dx (U < 1, |n| < 8.7 for the 53-bit
+    // uniforms of the Box-Muller pair), so only the tile columns within
+    // those depths of their boundary (and one more) are read
+    const fs_config& c = h->cfg;
+    const int TX = h->L.tile[0], ntx = h->L.ntile[0];
+    const double dtdx = c.dt / c.dx, sigma = std::sqrt(0.5 * c.beta_i);
+    const double dth = (std::fabs(c.u_sh) + 8.7 * sigma) * dtdx;
+    const double dcr = (std::fabs(c.u_sh / c.r) + c.cr_w) * dtdx;
     for (int k = 0; k < (h->has_cr ? 2 : 1) && nth + ncr > 0; ++k) {
+        const int64_t expect = k == 0 ? nth : ncr;
+        int cx0, cx1;
+        if (k == 0) {
+            const int cmax = (int)std::min<double>(c.nx - 1, std::floor(dth));
+            cx0 = 0;
+            cx1 = std::min(ntx - 1, cmax / TX + 1);
+        } else {
+            const int cmin = (int)std::max<double>(0.0, std::floor((double)c.nx - dcr));
+            cx0 = std::max(0, cmin / TX - 1);
+            cx1 = ntx - 1;
+        }
+        const int ncols = cx1 - cx0 + 1;
         PBuf<R> in1 = sections<R>(pn1->buf[k], pn1->n[k], D);
-        const unsigned g = std::min<unsigned>(grid_for(std::max<int64_t>(pn1->n[k], 1)), 4096u);
+        const unsigned g = (unsigned)(ncols * (h->L.ntiles / ntx));
         k_inject_adj<R, D, S><<<g, 256, 0, s>>>(h->G, in1, pn1->toff[k], pn1->n[k], h->alM[k],
-                                                plam<R>(lam, k, post, D), (uint64_t)step, id0, nth, nth + ncr, grads);
+                                                plam<R>(lam, k, post, D), (uint64_t)step, id0, nth, nth + ncr, cx0,
+                                                ncols, h->actr, expect, pn1->status, grads);
     }
     // deposit at n+1, then push, wall and gather of the ions that lived
     // before the step: buffer cur (indices after the step) -> cur ^ 1
@@ -1004,8 +1027,11 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
         ok = ok && dmalloc((void**)&h->afl, 5 * nn * sizeof(double));
         ok = ok && dmalloc((void**)&h->alfl, 5 * nn * sizeof(double));
         for (int k = 0; k < 4 && ok; ++k) ok = ok && dmalloc((void**)&h->al[k], 3 * nc * sizeof(double));
-        ok = ok && dmalloc((void**)&h->aBs, (size_t)c.n_sub * 3 * nc * sizeof(double));
+        // the starts of RK sub-steps after the first (slot 0, B^n itself, unused)
+        if (c.n_sub > 1) ok = ok && dmalloc((void**)&h->aBs, (size_t)c.n_sub * 3 * nc * sizeof(double));
         ok = ok && dmalloc((void**)&h->aob, 6 * nn * sizeof(double));
+        ok = ok && dmalloc((void**)&h->actr, 2 * sizeof(unsigned long long));
+        if (ok) ok = hipMemset(h->actr, 0, 2 * sizeof(unsigned long long)) == hipSuccess;
     }
     // crosser lists: a generous bound on the ions that can reach the wall in one step
     for (int k = 0; k < 2 && ok; ++k) {
@@ -1048,7 +1074,7 @@ void fs_destroy(fs_handle* h) {
     hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->fluid2); hipFree(h->nprev); hipFree(h->gprev); hipFree(h->phase); hipFree(h->part); hipFree(h->spec);
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
     for (int k = 0; k < 2; ++k) { hipFree(h->amom[k]); hipFree(h->alM[k]); }
-    hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->aob);
+    hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->aob); hipFree(h->actr);
     for (int k = 0; k < 4; ++k) hipFree(h->al[k]);
     delete h;
 }
