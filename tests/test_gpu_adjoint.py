@@ -474,3 +474,24 @@ def test_tape_unpack_is_the_inverse_of_pack(dim):
     torch.cuda.synchronize()
     assert (int(status.item()) != 0) == (m > cap)
     assert int(sim.cnts[0][int(other[0].cur)][0].item()) == min(m, cap)
+
+
+def test_reverse_pass_raises_when_it_misses_injected_ions(monkeypatch):
+    """The injected-ion pass counts the ions it finds against the step's
+    injection count; with the recorded first id shifted past every id (so
+    that none is found) the reverse pass raises instead of returning a
+    gradient without their u_sh terms."""
+    from paper_2507_14282_amd import adjoint as A
+    kw, nsteps = CASES["cic_cr_inject"]
+    p = W.params(**kw, precision=64)
+    run = A.AdjointRun(p, nsteps, K=7)
+    run.forward(p["u_sh"], p["alpha_cr"], np.full(int(p["n_modes"]), float(p["mode_amp"])))
+    step = A._recorded_step
+
+    def shifted(sim, n, pre, f_pre, post, f_post, rec, pack_in):
+        step(sim, n, pre, f_pre, post, f_post, rec, pack_in)
+        rec.id0 += 1 << 30
+
+    monkeypatch.setattr(A, "_recorded_step", shifted)
+    with pytest.raises(RuntimeError, match="injected"):
+        run.backward()
