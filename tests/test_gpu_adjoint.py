@@ -495,3 +495,68 @@ def test_reverse_pass_raises_when_it_misses_injected_ions(monkeypatch):
     monkeypatch.setattr(A, "_recorded_step", shifted)
     with pytest.raises(RuntimeError, match="injected"):
         run.backward()
+
+
+def test_tape_entry_points_validate_their_arguments():
+    """fs_tape_pack, fs_tape_unpack, fs_adjoint_park / unpark and the kept
+    RK stages refuse what their contract excludes, before any launch:
+    NULL arguments, an unknown pack flag, a prev without its record,
+    negative id ranges, adjoint buffers shorter than the packed state and
+    kept stages with several RK sub-steps."""
+    import ctypes as C
+    import torch
+    from paper_2507_14282_amd import adjoint as A
+    from paper_2507_14282_amd import fshybrid as F
+    p = W.params(dim=1, nx=48, dx=0.5, ppc=8, ppc_cr=4, n_cr=0.05, wall_cr="faux_shock", precision=32,
+                 deposit_mode="continuous", seed=37)
+    sim = F.Simulation(p, "cuda:0")
+    sim.init_plasma()
+    n = [sim.count(k) for k in range(2)]
+    status = torch.zeros(1, dtype=torch.int32, device="cuda:0")
+    P = A._Packed(sim, 2, n, status)
+    lib, h, s = sim.lib, sim.h, sim.stream
+    assert lib.fs_tape_pack(h, sim.sp, C.byref(P.s), None, None, None, F.FS_PACK_IONS, s) == F.FS_OK
+    assert lib.fs_tape_pack(h, None, C.byref(P.s), None, None, None, 0, s) == F.FS_EINVAL
+    assert lib.fs_tape_pack(h, sim.sp, C.byref(P.s), None, None, None, 2, s) == F.FS_EINVAL
+    assert lib.fs_tape_pack(h, sim.sp, C.byref(P.s), sim.sp, None, C.byref(P.s), 0, s) == F.FS_EINVAL
+    assert lib.fs_tape_unpack(h, None, sim.sp, s) == F.FS_EINVAL
+    bad = A._Packed(sim, 2, n, status)
+    bad.s.toff[1] = None
+    assert lib.fs_tape_unpack(h, C.byref(bad.s), sim.sp, s) == F.FS_EINVAL
+    lam = F.FsAdjoint()
+    keep = []
+    for k in range(2):
+        lam.capacity[k] = n[k] - 1 if k == 0 else n[k]     # the thermal arrays one short of the packed state
+        for b in range(2):
+            for d in range(3):
+                t = torch.zeros(max(n[k], 1), dtype=torch.float32, device="cuda:0")
+                lam.v[k][b][d] = t.data_ptr()
+                keep.append(t)
+                if d < 1:
+                    lam.x[k][b][d] = t.data_ptr()
+    lB = torch.zeros(3, int(sim.L.ncent), dtype=torch.float64, device="cuda:0")
+    lE = torch.zeros(6, int(sim.L.nnode), dtype=torch.float64, device="cuda:0")
+    lam.lB, lam.lE = lB.data_ptr(), lE.data_ptr()
+    scratch = torch.zeros(2 * 4 * (sim.next_id + 1), dtype=torch.float32, device="cuda:0")
+    sp = C.c_void_p(scratch.data_ptr())
+    assert lib.fs_adjoint_park(h, C.byref(P.s), C.byref(lam), sp, sim.next_id + 1, s) == F.FS_ECAPACITY
+    for k in range(2):
+        lam.capacity[k] = n[k]
+    assert lib.fs_adjoint_park(h, C.byref(P.s), C.byref(lam), sp, -1, s) == F.FS_EINVAL
+    assert lib.fs_adjoint_unpark(h, C.byref(P.s), C.byref(lam), None, sim.next_id + 1, s) == F.FS_EINVAL
+    assert lib.fs_adjoint_park(h, C.byref(P.s), C.byref(lam), sp, sim.next_id + 1, s) == F.FS_OK
+    # kept RK stages need one sub-step
+    p2 = dict(p, n_sub=2)
+    sim2 = F.Simulation(p2, "cuda:0")
+    sim2.init_plasma()
+    rec = F.FsRecord()
+    for k in range(2):
+        t = torch.zeros(int(sim2.L.capacity[k]), dtype=torch.int32, device="cuda:0")
+        rec.dst[k], rec.capacity[k] = t.data_ptr(), int(sim2.L.capacity[k])
+        keep.append(t)
+    stages = torch.zeros(6 * int(sim2.L.ncent), dtype=torch.float64, device="cuda:0")
+    rec.stages = stages.data_ptr()
+    with pytest.raises(F.FsError) as e:
+        sim2.step_record(0, rec)
+    assert e.value.code == F.FS_EINVAL
+    torch.cuda.synchronize()
