@@ -245,10 +245,10 @@ def _fields_bytes(sim: F.Simulation, nsp: int, stages: bool = False) -> int:
 
 
 def _fixed_bytes(sim: F.Simulation, nsp: int, n) -> int:
-    """Bytes the reverse pass holds besides checkpoints and tape: the bin
-    record, the shared E, the adjoints (two buffers of n per species and the
-    grid adjoints) and the id-indexed parking scratch (it re-runs the
-    segments on the simulation's own bins)."""
+    """Bytes the reverse pass holds besides checkpoints, tape and working
+    bins of its own: the bin record, the shared E, the adjoints (two buffers
+    of n per species and the grid adjoints) and the id-indexed parking
+    scratch."""
     dim = int(sim.p["dim"])
     rb = torch.finfo(sim.real).bits // 8
     work = sum(4 * int(sim.L.capacity[k]) for k in range(nsp))

@@ -86,6 +86,22 @@ def test_kept_rk_stages_give_the_recomputed_gradient(case, monkeypatch):
     assert np.max(np.abs(kept - recomputed)) <= 1e-13 * np.max(np.abs(kept)), (kept, recomputed)
 
 
+def test_rerun_on_the_simulations_own_bins_matches_the_oracle(monkeypatch):
+    """Where working bins of their own do not fit (the 3D box), the re-runs
+    step on the simulation's two particle buffers: the same gradient."""
+    from paper_2507_14282_amd import adjoint as A
+    kw, nsteps = CASES["2d_oblique"]
+    p = W.params(**kw, precision=64)
+    monkeypatch.setattr(A._Bins, "bytes", staticmethod(lambda sim, nsp: 1 << 60))
+    run = A.AdjointRun(p, nsteps, K=3)
+    lg = run.forward(p["u_sh"], p["alpha_cr"], np.full(int(p["n_modes"]), float(p["mode_amp"])))
+    assert not run.own_bins
+    gg = run.backward()
+    lo, go = O.adjoint(p, nsteps)
+    assert abs(lg - lo) <= 1e-12 * abs(lo)
+    assert np.max(np.abs(gg - go)) <= 1e-12 * np.max(np.abs(go)), (gg, go)
+
+
 def test_second_pass_of_a_run_matches_the_oracle():
     """A run's second forward and reverse pass (new parameters, a new
     simulation, the tape and working bins of the first pass reused) gives
