@@ -839,6 +839,39 @@ __device__ __forceinline__ void faraday_adj_at(const FieldGeo& F, const double* 
             }
 }
 
+// Transpose of Ohm's law at one node, E = (-Gamma x Bbar + J x Bbar -
+// grad p_e) / n_e + eta J, from lam_E (lEn) and lam_Bbar (lBbn) to the
+// adjoints of Bbar (lbb) and J (lJ), of n_e (lne) and Gamma (lG), and
+// lnum = lam_E / n_e, which carries the p_e adjoint to the neighbours.  At
+// the inflow node E is the motional field of the inflow (its adjoint goes
+// to u_sh, not through Ohm's law); at a conducting wall E_y = E_z = 0.
+__device__ __forceinline__ void ohm_adj_at(const FieldGeo& F, const double bb[3], const double J[3],
+                                           const double gp[3], double ne, const double Gm[3], const double lEn[3],
+                                           const double lBbn[3], bool inflow, bool conduct, double lbb[3],
+                                           double lJ[3], double lnum[3], double& lne, double lG[3]) {
+    double c1[3], c2[3], num[3], tmp[3];
+    cross3(Gm, bb, c1);
+    cross3(J, bb, c2);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) num[d] = -c1[d] + c2[d] - gp[d];
+    lne = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double le = (inflow || (conduct && d > 0)) ? 0.0 : lEn[d];
+        lnum[d] = le / ne;
+        lne -= num[d] * le / (ne * ne);
+        lJ[d] = F.eta * le;
+        lbb[d] = lBbn[d];
+    }
+    cross3(bb, lnum, tmp);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) { lG[d] = -tmp[d]; lJ[d] += tmp[d]; }
+    const double dv[3] = {J[0] - Gm[0], J[1] - Gm[1], J[2] - Gm[2]};
+    cross3(lnum, dv, tmp);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lbb[d] += tmp[d];
+}
+
 // Transpose of Ohm's law, first pass, one thread per node: (lam_E,
 // lam_Bbar) at the node -> the adjoints of its fluid state (n_e and Gamma of
 // the node, added; p_e of its neighbours, added atomically, several nodes
@@ -930,34 +963,15 @@ __global__ __launch_bounds__(256) void k_ohm_adj_node(FieldGeo F, const double* 
     }
     const double ne = fl[n];
     const double Gm[3] = {fl[2 * nnode + n], fl[3 * nnode + n], fl[4 * nnode + n]};
-    double c1[3], c2[3], num[3];
-    cross3(Gm, bb, c1);
-    cross3(J, bb, c2);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) num[d] = -c1[d] + c2[d] - gp[d];
-    // E = num / ne + eta J; at the inflow node E = -u_sh x_hat x B0, so its
-    // adjoint goes to u_sh alone (lam_Bbar still reaches the centres)
     const bool inflow = inflow_node(F, i);
-    const bool conduct = F.conduct && i == F.nx;   // E_y = E_z = 0 there: constants
+    const bool conduct = F.conduct && i == F.nx;
     if (inflow) unsafeAtomicAdd(grads, lEn[1] * F.B0[2] - lEn[2] * F.B0[1]);
-    double lnum[3], lJ[3], lbb[3], tmp[3];
-    double lne = 0.0;
+    double lBbn[3] = {0.0, 0.0, 0.0};
+    if (lBb)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double le = (inflow || (conduct && d > 0)) ? 0.0 : lEn[d];
-        lnum[d] = le / ne;
-        lne -= num[d] * le / (ne * ne);
-        lJ[d] = F.eta * le;
-        lbb[d] = lBb ? lBb[(long)d * nnode + n] : 0.0;
-    }
-    cross3(bb, lnum, tmp);
-    double lG[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) { lG[d] = -tmp[d]; lJ[d] += tmp[d]; }
-    const double dv[3] = {J[0] - Gm[0], J[1] - Gm[1], J[2] - Gm[2]};
-    cross3(lnum, dv, tmp);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) lbb[d] += tmp[d];
+        for (int d = 0; d < 3; ++d) lBbn[d] = lBb[(long)d * nnode + n];
+    double lnum[3], lJ[3], lbb[3], lG[3], lne;
+    ohm_adj_at(F, bb, J, gp, ne, Gm, lEn, lBbn, inflow, conduct, lbb, lJ, lnum, lne, lG);
     // fluid adjoints: n_e and Gamma belong to this node only, p_e to the neighbours
     lfl[n] += lne;
 #pragma unroll
@@ -1114,6 +1128,223 @@ __global__ __launch_bounds__(256) void k_fluid_adj(FieldGeo F, const double* __r
         }
     }
     block_add(acc, grads);
+}
+
+// A centre plane of lam_F into LDS, for the z-marching transpose below:
+// centres x0-1 .. x0+X, y0-1 .. y0+Y of plane k, under the Faraday
+// transpose's rules (y and z wrap, x wraps when periodic; in the box a
+// centre past either end of x contributes nothing).
+__device__ __forceinline__ void zm_load_F(const FieldGeo& F, const double* __restrict__ lF, long ncent, int x0, int y0,
+                                          int k, double (*s)[ZMarch::CN]) {
+    using Z = ZMarch;
+    k = wrapi(k, F.nzc);
+    for (int l = threadIdx.x; l < Z::CN; l += blockDim.x) {
+        int i = x0 - 1 + l % Z::CX;
+        const int j = wrapi(y0 - 1 + l / Z::CX, F.nyc);
+        bool ok = true;
+        if (F.xbc == 1) i = wrapi(i, F.nx);
+        else ok = i >= 0 && i < F.nx;
+        double v[3] = {0.0, 0.0, 0.0};
+        if (ok) {
+            const long q = lin(i, j, k, F.nx, F.nyc);
+            v[0] = lF[q]; v[1] = lF[ncent + q]; v[2] = lF[2 * ncent + q];
+        }
+        s[0][l] = v[0]; s[1][l] = v[1]; s[2][l] = v[2];
+    }
+}
+
+// The 3D transpose of Ohm's law at every node and of its Bbar average and
+// curl at every centre in one pass, marching through z like the forward
+// stage kernels (k_stage3): a workgroup takes the 32 x 8 centres of a block
+// column and a run of z planes.  At node plane k it stages B (and, with
+// CURL, lam_F) at the centre planes k-1 and k and p_e at node plane k,
+// computes the nodes x0 .. x0+32, y0 .. y0+8 of the plane (the node pass:
+// lam_E from lE or, with CURL, the Faraday transpose of lam_F; Ohm's
+// transpose; the fluid adjoints of the nodes it owns) into LDS, and adds
+// each node's (lam_Bbar, lam_J) to the centre planes k-1 and k of the
+// thread that owns the centre column; the centre of plane k-1 is then
+// complete and goes out as EMIT says (the centre pass of k_ohm_adj_centre,
+// the wall ghost's share included).  Node plane ze, the next run's first,
+// is computed for its centres only.
+template <bool CURL, int EMIT>
+__global__ __launch_bounds__(256, 3) void k_ohm_adj3(FieldGeo F, const double* __restrict__ B,
+                                                  const double* __restrict__ fl, const double* __restrict__ lEF,
+                                                  const double* __restrict__ lBb, double* __restrict__ lfl, RkOut o,
+                                                  double* grads, long nnode, long ncent, int gx, int gy, int zc) {
+    using Z = ZMarch;
+    __shared__ double sB[2][3][Z::CN];
+    __shared__ double sF[CURL ? 2 : 1][3][CURL ? Z::CN : 1];
+    __shared__ double sP[Z::PN];
+    __shared__ double sO[6][Z::NN];
+    int x0, y0, zs, ze;
+    zm_block(gx, gy, zc, F.nzc, x0, y0, zs, ze);
+    const double* pe = fl + nnode;
+    double* lpe = lfl + nnode;
+    const int t = threadIdx.x, tx = t % Z::X, ty = t / Z::X;
+    const int I = x0 + tx, Jc = y0 + ty;
+    const bool own_c = I < F.nx && Jc < F.nyc;
+    const double h2 = 0.5 * F.rdx;
+    const double wbb = 0.125, wd = 0.25 * F.rdx;
+    const int nxo = F.xbc == 1 ? F.nx : F.nx + 1;   // nodes along x
+    double accK1[3] = {0.0, 0.0, 0.0}, accK[3] = {0.0, 0.0, 0.0};
+    ZPlane pl;
+    {
+        const int kp = zs - 1, slot = kp & 1;
+        zm_fetch_B(F, B, ncent, x0, y0, kp, pl);
+        zm_store_B(pl, sB[slot]);
+        if constexpr (CURL) zm_load_F(F, lEF, ncent, x0, y0, kp, sF[slot]);
+    }
+    for (int k = zs; k <= ze; ++k) {
+        const int cur = k & 1, prv = cur ^ 1;
+        zm_fetch_B(F, B, ncent, x0, y0, k, pl);
+        zm_fetch_P(F, pe, x0, y0, k, pl);
+        zm_store_B(pl, sB[cur]);
+        zm_store_P(pl, sP);
+        if constexpr (CURL) zm_load_F(F, lEF, ncent, x0, y0, k, sF[cur]);
+        __syncthreads();
+        // node plane k
+#pragma unroll 1
+        for (int l = t; l < Z::NN; l += 256) {
+            const int lx = l % Z::NX, ly = l / Z::NX;
+            const int i = x0 + lx, jg = y0 + ly;
+            double lbb[3] = {0.0, 0.0, 0.0}, lJ[3] = {0.0, 0.0, 0.0};
+            if (F.xbc == 1 || i <= F.nx) {
+                const int iw = F.xbc == 1 ? wrapi(i, F.nx) : i;
+                const long n = lin(iw, wrapi(jg, F.nyc), wrapi(k, F.nzc), F.nxn, F.nyc);
+                // Bbar and the B differences from the 8 centres around the node
+                double bb[3] = {0, 0, 0}, dBx[3] = {0, 0, 0}, dBy[3] = {0, 0, 0}, dBz[3] = {0, 0, 0};
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int a = 0; a < 2; ++a)
+#pragma unroll
+                            for (int d = 0; d < 3; ++d) {
+                                const double v = sB[c == 1 ? cur : prv][d][(lx + a) + Z::CX * (ly + b)];
+                                bb[d] += v;
+                                dBx[d] += a == 1 ? v : -v;
+                                dBy[d] += b == 1 ? v : -v;
+                                dBz[d] += c == 1 ? v : -v;
+                            }
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    bb[d] *= 0.125;
+                    dBx[d] *= 0.25 * F.rdx;
+                    dBy[d] *= 0.25 * F.rdx;
+                    dBz[d] *= 0.25 * F.rdx;
+                }
+                const double J[3] = {dBy[2] - dBz[1], dBz[0] - dBx[2], dBx[1] - dBy[0]};
+                const int pc = (lx + 1) + Z::PX * (ly + 1);
+                const long nzp = fnode(F, i, jg, k + 1), nzm = fnode(F, i, jg, k - 1);
+                const double gp[3] = {(sP[pc + 1] - sP[pc - 1]) * h2, (sP[pc + Z::PX] - sP[pc - Z::PX]) * h2,
+                                      (pe[nzp] - pe[nzm]) * h2};
+                double lEn[3] = {0.0, 0.0, 0.0}, lBbn[3] = {0.0, 0.0, 0.0};
+                if constexpr (CURL) {
+                    // node (i, j, k) = centre (i - a, j - b, k - c) + (a, b, c)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b)
+#pragma unroll
+                            for (int a = 0; a < 2; ++a) {
+                                const int cl = (lx + 1 - a) + Z::CX * (ly + 1 - b);
+                                const int sl = c == 0 ? cur : prv;
+                                const double l0 = sF[sl][0][cl], l1 = sF[sl][1][cl], l2 = sF[sl][2][cl];
+                                const double ldEx[3] = {0.0, -l2, l1}, ldEy[3] = {l2, 0.0, -l0},
+                                             ldEz[3] = {-l1, l0, 0.0};
+#pragma unroll
+                                for (int d = 0; d < 3; ++d)
+                                    lEn[d] += ((a == 1 ? 1.0 : -1.0) * ldEx[d] + (b == 1 ? 1.0 : -1.0) * ldEy[d] +
+                                               (c == 1 ? 1.0 : -1.0) * ldEz[d]) * wd;
+                            }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        lEn[d] = lEF[(long)d * nnode + n];
+                        if (lBb) lBbn[d] = lBb[(long)d * nnode + n];
+                    }
+                }
+                const double ne = fl[n];
+                const double Gm[3] = {fl[2 * nnode + n], fl[3 * nnode + n], fl[4 * nnode + n]};
+                const bool inflow = inflow_node(F, i);
+                const bool conduct = F.conduct && i == F.nx;
+                double lnum[3], lG[3], lne;
+                ohm_adj_at(F, bb, J, gp, ne, Gm, lEn, lBbn, inflow, conduct, lbb, lJ, lnum, lne, lG);
+                // the node's own fluid adjoints, by the workgroup that owns it
+                const bool own_n = ((lx < Z::X && i < nxo) || (F.xbc == 0 && i == F.nx)) && ly < Z::Y &&
+                                   jg < F.nyc && k < ze;
+                if (own_n) {
+                    if (inflow) unsafeAtomicAdd(grads, lEn[1] * F.B0[2] - lEn[2] * F.B0[1]);
+                    lfl[n] += lne;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) lfl[(long)(2 + d) * nnode + n] += lG[d];
+                    unsafeAtomicAdd(lpe + fnode(F, i + 1, jg, k), -lnum[0] * h2);
+                    unsafeAtomicAdd(lpe + fnode(F, i - 1, jg, k), lnum[0] * h2);
+                    unsafeAtomicAdd(lpe + fnode(F, i, jg + 1, k), -lnum[1] * h2);
+                    unsafeAtomicAdd(lpe + fnode(F, i, jg - 1, k), lnum[1] * h2);
+                    unsafeAtomicAdd(lpe + nzp, -lnum[2] * h2);
+                    unsafeAtomicAdd(lpe + nzm, lnum[2] * h2);
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                sO[d][l] = lbb[d];
+                sO[3 + d][l] = lJ[d];
+            }
+        }
+        __syncthreads();
+        // the node plane into the centre planes k-1 (as their upper plane)
+        // and k (lower) of this thread's column
+        if (own_c) {
+            auto add = [&](int lxn, int a, int b) {
+                const int l = lxn + Z::NX * (ty + 1 - b);
+                const double lJ0 = sO[3][l], lJ1 = sO[4][l], lJ2 = sO[5][l];
+                const double ldBx[3] = {0.0, lJ2, -lJ1}, ldBy[3] = {-lJ2, 0.0, lJ0}, ldBz[3] = {lJ1, -lJ0, 0.0};
+                const double sa = a == 1 ? 1.0 : -1.0, sb = b == 1 ? 1.0 : -1.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double v = sO[d][l] * wbb + (sa * ldBx[d] + sb * ldBy[d]) * wd;
+                    accK1[d] += v - ldBz[d] * wd;   // c = 0: the node is the upper corner of centre k-1
+                    accK[d] += v + ldBz[d] * wd;    // c = 1: the lower corner of centre k
+                }
+            };
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    add(tx + 1 - a, a, b);
+                    if (F.xbc == 0 && I == F.nx - 1 && a == 0) add(tx + 1, 1, b);   // the wall ghost at nx
+                }
+            if (k > zs) {
+                const long q = lin(I, Jc, k - 1, F.nx, F.nyc);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const long e = (long)d * ncent + q;
+                    const double v = o.base[e] + accK1[d];
+                    if constexpr (EMIT == kEmitStage1) {
+                        o.l0[e] += v;
+                        o.lF[e] = o.h * v;
+                    } else if constexpr (EMIT == kEmitStage2) {
+                        o.l0[e] += 0.75 * v;
+                        o.l1[e] = 0.25 * v;
+                        o.lF[e] = 0.25 * o.h * v;
+                    } else if constexpr (EMIT == kEmitStage3) {
+                        o.l0[e] = v * (1.0 / 3.0);
+                        o.l2[e] = v * (2.0 / 3.0);
+                        o.lF[e] = v * (2.0 / 3.0) * o.h;
+                    } else {
+                        o.out[e] = v;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            accK1[d] = accK[d];
+            accK[d] = 0.0;
+        }
+    }
 }
 
 // Amplitude adjoints of the initial modes: dB_y = A cos(k_m x + phi_m),

@@ -48,7 +48,7 @@ struct fs_handle {
     double* alM[2] = {nullptr, nullptr};    // their adjoints
     double* afl = nullptr;                  // fluid state of the reverse step
     double* alfl = nullptr;                 // its adjoint
-    double* al[4] = {nullptr, nullptr, nullptr, nullptr};  // RK3 stage adjoints l0, l1, l2, lF
+    double* al[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // RK3 stage adjoints l0, l1, l2, lF (two)
     double* aBs = nullptr;                  // B at the start of each RK substep after the first
     double* aob = nullptr;                  // Ohm transpose: lam(Bbar), lam(J) per node
     unsigned long long* actr = nullptr;     // injected-ion counters of the reverse step (zero between launches)
@@ -664,6 +664,15 @@ template <int D, bool CURL, int EMIT>
 void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb, const RkOut& o, double* grads,
              hipStream_t s) {
     const long nn = h->L.nnode, nc = h->L.ncent;
+    if constexpr (D == 3) {
+        // one z-marching pass over 32 x 8 block columns and runs of at most
+        // 32 z planes, as the forward stage kernels
+        const int gx = (h->cfg.nx + ZMarch::X - 1) / ZMarch::X, gy = (int)((h->L.nyc + ZMarch::Y - 1) / ZMarch::Y);
+        const int zc = (int)std::min<int64_t>(h->L.nzc, 32), gz = (int)((h->L.nzc + zc - 1) / zc);
+        k_ohm_adj3<CURL, EMIT><<<(unsigned)(gx * gy * gz), 256, 0, s>>>(h->F, B, h->afl, lE, lBb, h->alfl, o, grads,
+                                                                         nn, nc, gx, gy, zc);
+        return;
+    }
     k_ohm_adj_node<D, CURL><<<grid_for(nn), 256, 0, s>>>(h->F, B, h->afl, lE, lBb, h->aob, h->alfl, grads, nn, nc);
     k_ohm_adj_centre<D, EMIT><<<grid_for(nc), 256, 0, s>>>(h->F, h->aob, o, nn, nc);
 }
@@ -690,7 +699,18 @@ void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* 
         stage_launch<D>(h, h->B2, B0, Bs + (size_t)(sub + 1) * N, h->afl, 1.0 / 3.0, 2.0 / 3.0, hs, s);
     }
     RkOut o;
-    o.l0 = h->al[0]; o.l1 = h->al[1]; o.l2 = h->al[2]; o.lF = h->al[3]; o.out = lB; o.h = hs;
+    o.l0 = h->al[0]; o.l1 = h->al[1]; o.l2 = h->al[2]; o.out = lB; o.h = hs;
+    // lam_F alternates between two buffers: a pass reads the one the pass
+    // before wrote (with halos, in the 3D z-marching form) and writes the other
+    double* lFs[2] = {h->al[3], h->al[4]};
+    int lfw = 0;
+    auto next_lF = [&]() -> const double* {
+        const double* in = lFs[lfw];
+        lfw ^= 1;
+        o.lF = lFs[lfw];
+        return in;
+    };
+    o.lF = lFs[lfw];
     // Ohm at B^{n+1}; its centre pass starts the last sub-step's transpose
     // B3 = 1/3 B0 + 2/3 (B2 + h F(B2))
     o.base = lB;
@@ -708,15 +728,18 @@ void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* 
         }
         // lam(B2) = l2 + (dF/dB2)^T lF, then B2 = 3/4 B0 + 1/4 (B1 + h F(B1))
         o.base = o.l2;
-        ohm_adj<D, true, kEmitStage2>(h, B2, o.lF, nullptr, o, grads, s);
+        const double* lF2 = next_lF();
+        ohm_adj<D, true, kEmitStage2>(h, B2, lF2, nullptr, o, grads, s);
         // lam(B1) = l1 + (dF/dB1)^T lF, then B1 = B0 + h F(B0)
         o.base = o.l1;
-        ohm_adj<D, true, kEmitStage1>(h, B1, o.lF, nullptr, o, grads, s);
+        const double* lF1 = next_lF();
+        ohm_adj<D, true, kEmitStage1>(h, B1, lF1, nullptr, o, grads, s);
         // lam(B0) = l0 + (dF/dB0)^T lF: the start of this sub-step, which
         // ends the previous one (or is lam(B^n))
         o.base = o.l0;
-        if (sub > 0) ohm_adj<D, true, kEmitStage3>(h, B0, o.lF, nullptr, o, grads, s);
-        else ohm_adj<D, true, kEmitOut>(h, B0, o.lF, nullptr, o, grads, s);
+        const double* lF0 = next_lF();
+        if (sub > 0) ohm_adj<D, true, kEmitStage3>(h, B0, lF0, nullptr, o, grads, s);
+        else ohm_adj<D, true, kEmitOut>(h, B0, lF0, nullptr, o, grads, s);
     }
 }
 
@@ -1026,7 +1049,7 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
         }
         ok = ok && dmalloc((void**)&h->afl, 5 * nn * sizeof(double));
         ok = ok && dmalloc((void**)&h->alfl, 5 * nn * sizeof(double));
-        for (int k = 0; k < 4 && ok; ++k) ok = ok && dmalloc((void**)&h->al[k], 3 * nc * sizeof(double));
+        for (int k = 0; k < 5 && ok; ++k) ok = ok && dmalloc((void**)&h->al[k], 3 * nc * sizeof(double));
         // the starts of RK sub-steps after the first (slot 0, B^n itself, unused)
         if (c.n_sub > 1) ok = ok && dmalloc((void**)&h->aBs, (size_t)c.n_sub * 3 * nc * sizeof(double));
         ok = ok && dmalloc((void**)&h->aob, 6 * nn * sizeof(double));
@@ -1075,7 +1098,7 @@ void fs_destroy(fs_handle* h) {
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
     for (int k = 0; k < 2; ++k) { hipFree(h->amom[k]); hipFree(h->alM[k]); }
     hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->aob); hipFree(h->actr);
-    for (int k = 0; k < 4; ++k) hipFree(h->al[k]);
+    for (int k = 0; k < 5; ++k) hipFree(h->al[k]);
     delete h;
 }
 
