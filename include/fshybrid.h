@@ -385,12 +385,19 @@ int fs_bperp_spectrum_noalloc(fs_handle* h, const fs_fields* f, double* out, hip
  * inject (the injected ions are id0, id0 + 1, ..., thermal first).  stages
  * (NULL for none; n_sub = 1 only) is device memory of 6 x ncent doubles
  * where the step leaves its SSP-RK3 stages B1 and B2 (each planar like B),
- * for fs_adjoint_step to read instead of recomputing them. */
+ * for fs_adjoint_step to read instead of recomputing them.  B_in and
+ * gather_in (both NULL, or both given: device memory laid out like an
+ * fs_fields' B and gather) are the input state's B and gather grid, which
+ * the step then reads in place of f's: f's B and gather (and E) only
+ * receive the output state, so stepping from one state's grids into
+ * another's needs no copy first.  They may be f's own (the in-place step). */
 typedef struct fs_record {
-    int32_t* dst[2];
-    int64_t  capacity[2];
-    int64_t  id0;
-    double*  stages;
+    int32_t*      dst[2];
+    int64_t       capacity[2];
+    int64_t       id0;
+    double*       stages;
+    const double* B_in;
+    const void*   gather_in;
 } fs_record;
 
 /* A particle state packed to its live ions: the reverse mode's tape, sized
@@ -440,7 +447,8 @@ typedef struct fs_adjoint {
  * state (sp's buf[cur]), the push also copies each input ion as it reads it
  * to its packed index in pack_in->buf: the ions of fs_tape_pack with
  * FS_PACK_IONS, without a pass of their own.  FS_EINVAL on another
- * configuration, a NULL dst of a species or rec->stages with n_sub > 1,
+ * configuration, a NULL dst of a species, rec->stages with n_sub > 1 or
+ * only one of rec->B_in and rec->gather_in,
  * FS_ECAPACITY if a dst holds fewer entries than the species' capacity or
  * the capacity does not fit the int32 encoding (above 2^31 - 3 slots). */
 int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec,

@@ -201,12 +201,11 @@ class _Checkpoint:
 def _recorded_step(sim: F.Simulation, n: int, pre: _Bins, f_pre, post: _Bins, f_post, rec: F.FsRecord,
                    pack_in: "_Packed"):
     """Step n from the bins of `pre` (fields f_pre) into the bins of `post`
-    (fields f_post) without copying particles, packing pre's ions into
-    pack_in (whose offsets are set) as the push reads them.  The field
-    update works in place, so B and the gather grid are first copied
-    across; E is only written."""
-    f_post.B.copy_(f_pre.B)
-    f_post.gather.copy_(f_pre.gather)
+    (fields f_post) without copying particles or grids: the step reads B and
+    the gather grid of f_pre and writes those of f_post, packing pre's ions
+    into pack_in (whose offsets are set) as the push reads them."""
+    rec.B_in = f_pre.B.data_ptr()
+    rec.gather_in = f_pre.gather.data_ptr()
     rec.stages = f_post.stages_ptr()
     sp = pre.step_to(sim, post)
     rc = sim.lib.fs_step_record(sim.h, sp, C.byref(f_post.f(sim)), int(n), C.byref(rec), C.byref(pack_in.s), None,

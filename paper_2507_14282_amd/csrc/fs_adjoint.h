@@ -972,10 +972,18 @@ __global__ __launch_bounds__(256) void k_ohm_adj_node(FieldGeo F, const double* 
         for (int d = 0; d < 3; ++d) lBbn[d] = lBb[(long)d * nnode + n];
     double lnum[3], lJ[3], lbb[3], lG[3], lne;
     ohm_adj_at(F, bb, J, gp, ne, Gm, lEn, lBbn, inflow, conduct, lbb, lJ, lnum, lne, lG);
-    // fluid adjoints: n_e and Gamma belong to this node only, p_e to the neighbours
-    lfl[n] += lne;
+    // fluid adjoints: n_e and Gamma belong to this node only (stored by the
+    // first transpose of a step, the one without the curl, added by the
+    // others), p_e to the neighbours
+    if constexpr (CURL) {
+        lfl[n] += lne;
 #pragma unroll
-    for (int d = 0; d < 3; ++d) lfl[(long)(2 + d) * nnode + n] += lG[d];
+        for (int d = 0; d < 3; ++d) lfl[(long)(2 + d) * nnode + n] += lG[d];
+    } else {
+        lfl[n] = lne;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) lfl[(long)(2 + d) * nnode + n] = lG[d];
+    }
     double* lpe = lfl + nnode;
     const double h2 = 0.5 * F.rdx;
     unsafeAtomicAdd(lpe + nxp, -lnum[0] * h2);
@@ -1130,6 +1138,21 @@ __global__ __launch_bounds__(256) void k_fluid_adj(FieldGeo F, const double* __r
     block_add(acc, grads);
 }
 
+// Zeroes, in every row of a species' moment adjoints (4 doubles per deposit
+// entry), the x entries e <= lo and e >= hi of a box: the guard entries that
+// k_fluid_adj never writes and the two clamped entries it adds into.  The
+// entries between are each stored by exactly one node.
+__global__ __launch_bounds__(256) void k_zero_dep_ends(double* __restrict__ a, int ndx, long rows, int lo, int hi) {
+    const int nl = lo + 1, nc = nl + (ndx - hi);
+    const long n = rows * nc * 4;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+        const long q = t >> 2;
+        const int c = (int)(q % nc);
+        const int e = c < nl ? c : hi + (c - nl);
+        a[4 * ((q / nc) * ndx + e) + (t & 3)] = 0.0;
+    }
+}
+
 // A centre plane of lam_F into LDS, for the z-marching transpose below:
 // centres x0-1 .. x0+X, y0-1 .. y0+Y of plane k, under the Faraday
 // transpose's rules (y and z wrap, x wraps when periodic; in the box a
@@ -1276,9 +1299,16 @@ __global__ __launch_bounds__(256, 3) void k_ohm_adj3(FieldGeo F, const double* _
                                    jg < F.nyc && k < ze;
                 if (own_n) {
                     if (inflow) unsafeAtomicAdd(grads, lEn[1] * F.B0[2] - lEn[2] * F.B0[1]);
-                    lfl[n] += lne;
+                    // stored by the first transpose of a step (no curl), added by the others
+                    if constexpr (CURL) {
+                        lfl[n] += lne;
 #pragma unroll
-                    for (int d = 0; d < 3; ++d) lfl[(long)(2 + d) * nnode + n] += lG[d];
+                        for (int d = 0; d < 3; ++d) lfl[(long)(2 + d) * nnode + n] += lG[d];
+                    } else {
+                        lfl[n] = lne;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) lfl[(long)(2 + d) * nnode + n] = lG[d];
+                    }
                     unsafeAtomicAdd(lpe + fnode(F, i + 1, jg, k), -lnum[0] * h2);
                     unsafeAtomicAdd(lpe + fnode(F, i - 1, jg, k), lnum[0] * h2);
                     unsafeAtomicAdd(lpe + fnode(F, i, jg + 1, k), -lnum[1] * h2);
@@ -1343,6 +1373,222 @@ __global__ __launch_bounds__(256, 3) void k_ohm_adj3(FieldGeo F, const double* _
         for (int d = 0; d < 3; ++d) {
             accK1[d] = accK[d];
             accK[d] = 0.0;
+        }
+    }
+}
+
+// The 2D form of k_ohm_adj3: a block of 256 threads takes RX = 255 centre
+// columns x0 .. x0+254 (so its 256 node columns x0 .. x0+255 are one per
+// thread) and marches through a run of y rows.  Per row j it stages the B
+// and lam_F centre rows j-1 and j and the p_e node row j in LDS, computes
+// node row j (lam_E from lE or, with CURL, the Faraday transpose of lam_F;
+// Ohm's transpose; the fluid adjoints of the nodes it owns) into LDS, and
+// adds each node's (lam_Bbar, lam_J) to the centre rows j-1 and j of the
+// thread owning the column; centre row j-1 is then complete and goes out as
+// EMIT says.  Node row ye, the next run's first, is computed for its
+// centres only.
+struct YMarch {
+    static constexpr int RX = 255;            // centre columns per block
+    static constexpr int CX = RX + 2;         // centres x0-1 .. x0+RX
+    static constexpr int NX = RX + 1;         // nodes x0 .. x0+RX, one per thread
+    static constexpr int PX = RX + 3;         // p_e at nodes x0-1 .. x0+RX+1
+};
+
+// A centre row of B (the box's x ghosts: B0 at the inflow, the last
+// centre at the wall) or of lam_F (nothing past either end of a box) into LDS.
+template <bool LAMF>
+__device__ __forceinline__ void ym_load_row(const FieldGeo& F, const double* __restrict__ a, long ncent, int x0, int j,
+                                            double (*s)[YMarch::CX]) {
+    j = wrapi(j, F.nyc);
+    for (int l = threadIdx.x; l < YMarch::CX; l += blockDim.x) {
+        int i = x0 - 1 + l;
+        double v[3] = {0.0, 0.0, 0.0};
+        if (F.xbc == 1) i = wrapi(i, F.nx);
+        if (LAMF) {
+            if (F.xbc == 1 || (i >= 0 && i < F.nx)) {
+                const long q = lin(i, j, 0, F.nx, F.nyc);
+                v[0] = a[q]; v[1] = a[ncent + q]; v[2] = a[2 * ncent + q];
+            }
+        } else {
+            if (i >= F.nx) i = F.nx - 1;
+            if (i < 0) {
+                v[0] = F.B0[0]; v[1] = F.B0[1]; v[2] = F.B0[2];
+            } else {
+                const long q = lin(i, j, 0, F.nx, F.nyc);
+                v[0] = a[q]; v[1] = a[ncent + q]; v[2] = a[2 * ncent + q];
+            }
+        }
+        s[0][l] = v[0]; s[1][l] = v[1]; s[2][l] = v[2];
+    }
+}
+
+template <bool CURL, int EMIT>
+__global__ __launch_bounds__(256) void k_ohm_adj2(FieldGeo F, const double* __restrict__ B,
+                                                  const double* __restrict__ fl, const double* __restrict__ lEF,
+                                                  const double* __restrict__ lBb, double* __restrict__ lfl, RkOut o,
+                                                  double* grads, long nnode, long ncent, int gx, int yc) {
+    using Y = YMarch;
+    __shared__ double sB[2][3][Y::CX];
+    __shared__ double sF[CURL ? 2 : 1][3][CURL ? Y::CX : 1];
+    __shared__ double sP[Y::PX];
+    __shared__ double sO[6][Y::NX];
+    const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int x0 = (b % gx) * Y::RX, ys = (b / gx) * yc, ye = min(ys + yc, (int)F.nyc);
+    const double* pe = fl + nnode;
+    double* lpe = lfl + nnode;
+    const int t = threadIdx.x;
+    const int I = x0 + t;
+    const bool own_c = t < Y::RX && I < F.nx;
+    const double h2 = 0.5 * F.rdx;
+    const double wbb = 0.25, wd = 0.5 * F.rdx;
+    const int nxo = F.xbc == 1 ? F.nx : F.nx + 1;   // nodes along x
+    double accJ1[3] = {0.0, 0.0, 0.0}, accJ[3] = {0.0, 0.0, 0.0};
+    ym_load_row<false>(F, B, ncent, x0, ys - 1, sB[(ys - 1) & 1]);
+    if constexpr (CURL) ym_load_row<true>(F, lEF, ncent, x0, ys - 1, sF[(ys - 1) & 1]);
+    for (int j = ys; j <= ye; ++j) {
+        const int cur = j & 1, prv = cur ^ 1;
+        ym_load_row<false>(F, B, ncent, x0, j, sB[cur]);
+        if constexpr (CURL) ym_load_row<true>(F, lEF, ncent, x0, j, sF[cur]);
+        {
+            const int jw = wrapi(j, F.nyc);
+            for (int l = t; l < Y::PX; l += blockDim.x) {
+                int i = x0 - 1 + l;
+                if (F.xbc == 1) i = wrapi(i, F.nx);
+                else i = i < 0 ? 0 : (i > F.nx ? F.nx : i);
+                sP[l] = pe[lin(i, jw, 0, F.nxn, F.nyc)];
+            }
+        }
+        __syncthreads();
+        // node row j: node (x0 + t, j)
+        {
+            const int lx = t, i = x0 + lx;
+            double lbb[3] = {0.0, 0.0, 0.0}, lJ[3] = {0.0, 0.0, 0.0};
+            if (F.xbc == 1 || i <= F.nx) {
+                const int iw = F.xbc == 1 ? wrapi(i, F.nx) : i;
+                const long n = lin(iw, wrapi(j, F.nyc), 0, F.nxn, F.nyc);
+                // Bbar and the B differences from the 4 centres around the node
+                double bb[3] = {0, 0, 0}, dBx[3] = {0, 0, 0}, dBy[3] = {0, 0, 0};
+#pragma unroll
+                for (int bq = 0; bq < 2; ++bq)
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) {
+                            const double v = sB[bq == 1 ? cur : prv][d][lx + a];
+                            bb[d] += v;
+                            dBx[d] += a == 1 ? v : -v;
+                            dBy[d] += bq == 1 ? v : -v;
+                        }
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    bb[d] *= 0.25;
+                    dBx[d] *= 0.5 * F.rdx;
+                    dBy[d] *= 0.5 * F.rdx;
+                }
+                const double J[3] = {dBy[2], -dBx[2], dBx[1] - dBy[0]};
+                const long nyp = fnode(F, i, j + 1, 0), nym = fnode(F, i, j - 1, 0);
+                const double gp[3] = {(sP[lx + 2] - sP[lx]) * h2, (pe[nyp] - pe[nym]) * h2, 0.0};
+                double lEn[3] = {0.0, 0.0, 0.0}, lBbn[3] = {0.0, 0.0, 0.0};
+                if constexpr (CURL) {
+                    // node (i, j) = centre (i - a, j - bq) + (a, bq)
+#pragma unroll
+                    for (int bq = 0; bq < 2; ++bq)
+#pragma unroll
+                        for (int a = 0; a < 2; ++a) {
+                            const int cl = lx + 1 - a;
+                            const int sl = bq == 0 ? cur : prv;
+                            const double l0 = sF[sl][0][cl], l1 = sF[sl][1][cl], l2 = sF[sl][2][cl];
+                            const double ldEx[3] = {0.0, -l2, l1}, ldEy[3] = {l2, 0.0, -l0};
+#pragma unroll
+                            for (int d = 0; d < 3; ++d)
+                                lEn[d] += ((a == 1 ? 1.0 : -1.0) * ldEx[d] + (bq == 1 ? 1.0 : -1.0) * ldEy[d]) * wd;
+                        }
+                } else {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        lEn[d] = lEF[(long)d * nnode + n];
+                        if (lBb) lBbn[d] = lBb[(long)d * nnode + n];
+                    }
+                }
+                const double ne = fl[n];
+                const double Gm[3] = {fl[2 * nnode + n], fl[3 * nnode + n], fl[4 * nnode + n]};
+                const bool inflow = inflow_node(F, i);
+                const bool conduct = F.conduct && i == F.nx;
+                double lnum[3], lG[3], lne;
+                ohm_adj_at(F, bb, J, gp, ne, Gm, lEn, lBbn, inflow, conduct, lbb, lJ, lnum, lne, lG);
+                // the node's own fluid adjoints, by the block that owns it
+                const bool own_n = ((lx < Y::RX && i < nxo) || (F.xbc == 0 && i == F.nx)) && j < ye;
+                if (own_n) {
+                    if (inflow) unsafeAtomicAdd(grads, lEn[1] * F.B0[2] - lEn[2] * F.B0[1]);
+                    // stored by the first transpose of a step (no curl), added by the others
+                    if constexpr (CURL) {
+                        lfl[n] += lne;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) lfl[(long)(2 + d) * nnode + n] += lG[d];
+                    } else {
+                        lfl[n] = lne;
+#pragma unroll
+                        for (int d = 0; d < 3; ++d) lfl[(long)(2 + d) * nnode + n] = lG[d];
+                    }
+                    unsafeAtomicAdd(lpe + fnode(F, i + 1, j, 0), -lnum[0] * h2);
+                    unsafeAtomicAdd(lpe + fnode(F, i - 1, j, 0), lnum[0] * h2);
+                    unsafeAtomicAdd(lpe + nyp, -lnum[1] * h2);
+                    unsafeAtomicAdd(lpe + nym, lnum[1] * h2);
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                sO[d][lx] = lbb[d];
+                sO[3 + d][lx] = lJ[d];
+            }
+        }
+        __syncthreads();
+        // the node row into the centre rows j-1 (as their upper row) and j
+        // (lower) of this thread's column
+        if (own_c) {
+            auto add = [&](int lxn, int a) {
+                const double lJ0 = sO[3][lxn], lJ1 = sO[4][lxn], lJ2 = sO[5][lxn];
+                const double ldBx[3] = {0.0, lJ2, -lJ1}, ldBy[3] = {-lJ2, 0.0, lJ0};
+                const double sa = a == 1 ? 1.0 : -1.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double v = sO[d][lxn] * wbb + sa * ldBx[d] * wd;
+                    accJ1[d] += v - ldBy[d] * wd;   // bq = 0: the node is an upper corner of centre j-1
+                    accJ[d] += v + ldBy[d] * wd;    // bq = 1: a lower corner of centre j
+                }
+            };
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                add(t + 1 - a, a);
+                if (F.xbc == 0 && I == F.nx - 1 && a == 0) add(t + 1, 1);   // the wall ghost at nx
+            }
+            if (j > ys) {
+                const long q = lin(I, wrapi(j - 1, F.nyc), 0, F.nx, F.nyc);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const long e = (long)d * ncent + q;
+                    const double v = o.base[e] + accJ1[d];
+                    if constexpr (EMIT == kEmitStage1) {
+                        o.l0[e] += v;
+                        o.lF[e] = o.h * v;
+                    } else if constexpr (EMIT == kEmitStage2) {
+                        o.l0[e] += 0.75 * v;
+                        o.l1[e] = 0.25 * v;
+                        o.lF[e] = 0.25 * o.h * v;
+                    } else if constexpr (EMIT == kEmitStage3) {
+                        o.l0[e] = v * (1.0 / 3.0);
+                        o.l2[e] = v * (2.0 / 3.0);
+                        o.lF[e] = v * (2.0 / 3.0) * o.h;
+                    } else {
+                        o.out[e] = v;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            accJ1[d] = accJ[d];
+            accJ[d] = 0.0;
         }
     }
 }

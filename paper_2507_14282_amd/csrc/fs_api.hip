@@ -44,13 +44,13 @@ struct fs_handle {
     int device = -1;                  // device current at fs_create
     double* static_scratch = nullptr; // device address of `scratch` on that device
     // reverse-mode scratch (deposit_mode 1 only)
-    double* amom[2] = {nullptr, nullptr};   // moments recomputed for the reverse step
+    const double* amom[2] = {nullptr, nullptr};   // the moment grids of the reverse step's tape state (not owned)
     double* alM[2] = {nullptr, nullptr};    // their adjoints
     double* afl = nullptr;                  // fluid state of the reverse step
     double* alfl = nullptr;                 // its adjoint
     double* al[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // RK3 stage adjoints l0, l1, l2, lF (two)
     double* aBs = nullptr;                  // B at the start of each RK substep after the first
-    double* aob = nullptr;                  // Ohm transpose: lam(Bbar), lam(J) per node
+    double* aob = nullptr;                  // 1D Ohm transpose: lam(Bbar), lam(J) per node
     unsigned long long* actr = nullptr;     // injected-ion counters of the reverse step (zero between launches)
     std::string err;
     // phase timing: pool of event pairs recorded on the caller's stream
@@ -343,9 +343,10 @@ void zero_i32(int32_t* p, int64_t n, hipStream_t s) {
 // field update (FP64)
 // ------------------------------------------------------------------------
 // stages: NULL, or (one sub-step) where the RK stages B1 and B2 go instead
-// of the handle's scratch (3 x ncent doubles each, B1 first).
+// of the handle's scratch (3 x ncent doubles each, B1 first).  Bin: NULL,
+// or B^n to step from instead of f->B (which then only receives B^{n+1}).
 template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hipStream_t s, bool rk,
-                                                 double* stages = nullptr) {
+                                                 double* stages = nullptr, const double* Bin = nullptr) {
     const long nn = h->L.nnode, nc = h->L.ncent;
     const dim3 blk(kFX, kFY, 1);
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
@@ -383,9 +384,10 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
             double* B1 = stages ? stages : h->B1;
             double* B2 = stages ? stages + 3 * nc : h->B2;
             for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
-                k_stage3<<<nb, 256, 0, s>>>(h->F, f->B, f->B, B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy, zc);
-                k_stage3<<<nb, 256, 0, s>>>(h->F, B1, f->B, B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy, zc);
-                k_stage3<<<nb, 256, 0, s>>>(h->F, B2, f->B, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy,
+                const double* B0 = (sub == 0 && Bin) ? Bin : f->B;
+                k_stage3<<<nb, 256, 0, s>>>(h->F, B0, B0, B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy, zc);
+                k_stage3<<<nb, 256, 0, s>>>(h->F, B1, B0, B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy, zc);
+                k_stage3<<<nb, 256, 0, s>>>(h->F, B2, B0, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy,
                                             zc);
             }
         }
@@ -402,10 +404,11 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
         double* B2 = stages ? stages + 3 * nc : h->B2;
         for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
             // SSP-RK3 (Shu-Osher): B1 = B + h F(B); B2 = 3/4 B + 1/4 (B1 + h F(B1));
-            // B <- 1/3 B + 2/3 (B2 + h F(B2)); the last stage writes in place
-            k_stage<D><<<nb, 256, 0, s>>>(h->F, f->B, f->B, B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy);
-            k_stage<D><<<nb, 256, 0, s>>>(h->F, B1, f->B, B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy);
-            k_stage<D><<<nb, 256, 0, s>>>(h->F, B2, f->B, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy);
+            // B <- 1/3 B + 2/3 (B2 + h F(B2)); the last stage writes f->B
+            const double* B0 = (sub == 0 && Bin) ? Bin : f->B;
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, B0, B0, B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy);
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, B1, B0, B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy);
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, B2, B0, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy);
         }
     }
     const int gxo = (int)((h->L.nxn + FB::X - 1) / FB::X);
@@ -413,10 +416,12 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
                                                         gxo, gy);
 }
 
-template <typename R> void field_update(fs_handle* h, fs_fields* f, hipStream_t s, bool rk, double* stages = nullptr) {
-    if (h->cfg.dim == 1) field_update_d<R, 1>(h, f, s, rk, stages);
-    else if (h->cfg.dim == 2) field_update_d<R, 2>(h, f, s, rk, stages);
-    else field_update_d<R, 3>(h, f, s, rk, stages);
+template <typename R>
+void field_update(fs_handle* h, fs_fields* f, hipStream_t s, bool rk, double* stages = nullptr,
+                  const double* Bin = nullptr) {
+    if (h->cfg.dim == 1) field_update_d<R, 1>(h, f, s, rk, stages, Bin);
+    else if (h->cfg.dim == 2) field_update_d<R, 2>(h, f, s, rk, stages, Bin);
+    else field_update_d<R, 3>(h, f, s, rk, stages, Bin);
 }
 
 // ------------------------------------------------------------------------
@@ -442,9 +447,15 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
               const fs_record* rec = nullptr, const fs_packed* pk = nullptr) {
     const bool push = flags & FS_PUSH, inj = flags & FS_INJECT, fld = flags & FS_FIELD;
     const bool cont = h->cfg.deposit_mode == 1;
-    // the continuous deposit runs as its own pass after the particles have moved
+    const bool rel = h->cfg.c_light > 0.0;
+    // the continuous deposit is fused into the push, the wall and the
+    // injection of a non-relativistic 2D or 3D step that moves the ions;
+    // otherwise it runs as its own pass over the bins after the moves.  In 1D
+    // all ions injected in a step land on the same two nodes, where their
+    // direct FP64 atomics serialise, and the separate pass is the cheaper one.
     const bool dep = (flags & FS_DEPOSIT) && !cont;
     const bool cdep = (flags & FS_DEPOSIT) && cont;
+    const bool fcd = cdep && push && !rel && D >= 2;
     const int nsp = h->has_cr ? 2 : 1;
     const fs_config& c = h->cfg;
     int64_t cth = 0, ccr = 0;
@@ -455,10 +466,12 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
     Geo G = h->G;
     const int t_step = timing_begin(h, 4, s);
     zero_u64(h->ctr, C_N, s);
-    if (dep)
+    if (dep || fcd)
         for (int k = 0; k < nsp; ++k) zero_u64(f->mom[k], 4 * h->L.ndep, s);
     using X = Extent<D, S>;
-    const size_t lds_push = PushLds<R, D, S>::bytes(dep);
+    const size_t lds_push = PushLds<R, D, S>::bytes(dep || fcd);
+    // a recorded step may read its input state's grids from elsewhere
+    const R* gather_in = static_cast<const R*>(rec && rec->gather_in ? rec->gather_in : f->gather);
     if (push) {
         for (int k = 0; k < nsp; ++k) {
             zero_i32(sp[k].tile_count[sp[k].cur ^ 1], 2 * h->L.ntiles, s);
@@ -482,11 +495,13 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
             auto launch = [&](auto kern) {
                 allow_lds(kern, lds_push);
                 kern<<<(unsigned)h->L.ntiles, PUSH_THREADS, lds_push, s>>>(
-                    G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, static_cast<const R*>(f->gather),
+                    G, in, out, P.tile_count[P.cur], P.tile_count[P.cur ^ 1], P.tile_cap, gather_in,
                     mom, h->xl[k], h->ctr, policy_of(h, k), k, rec ? rec->dst[k] : nullptr, pko, pk_toff, pk_n);
             };
-            const bool rel = h->cfg.c_light > 0.0;
-            if (rec) launch(k_push<R, D, S, false, false, false, true>);   // continuous deposit, non-relativistic
+            // a recorded step is a continuous-deposit, non-relativistic one
+            if (rec) fcd ? launch(k_push<R, D, S, true, false, false, true, true>)
+                         : launch(k_push<R, D, S, false, false, false, true>);
+            else if (fcd) launch(k_push<R, D, S, true, false, false, false, true>);
             else if (dep && h->cfg.coupling == 2)
                 rel ? launch(k_push<R, D, S, true, true, true>) : launch(k_push<R, D, S, true, false, true>);
             else if (dep) rel ? launch(k_push<R, D, S, true, true>) : launch(k_push<R, D, S, true, false>);
@@ -506,6 +521,10 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
                 if (dep)
                     k_wall<R, D, S, true><<<gw, 256, 0, s>>>(G, h->xl[k], out, P.tile_count[P.cur ^ 1], P.tile_cap, mom,
                                                             h->ctr, policy_of(h, k), k, (uint64_t)step, rd, wm);
+                else if (fcd)
+                    k_wall<R, D, S, true, true><<<gw, 256, 0, s>>>(G, h->xl[k], out, P.tile_count[P.cur ^ 1], P.tile_cap,
+                                                                  mom, h->ctr, policy_of(h, k), k, (uint64_t)step, rd,
+                                                                  wm);
                 else
                     k_wall<R, D, S, false><<<gw, 256, 0, s>>>(G, h->xl[k], out, P.tile_count[P.cur ^ 1], P.tile_cap, mom,
                                                              h->ctr, policy_of(h, k), k, (uint64_t)step, rd, wm);
@@ -534,6 +553,10 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
         if (dep && push)
             k_inject<R, D, S, true><<<grid_for(ninj), 256, 0, s>>>(G, o0, P0.tile_count[t0], P0.tile_cap, m0, o1, c1, cap1, m1,
                                                                   h->ctr, (uint64_t)step, h->next_id, cth, ccr, ntr);
+        else if (fcd)
+            k_inject<R, D, S, true, true><<<grid_for(ninj), 256, 0, s>>>(G, o0, P0.tile_count[t0], P0.tile_cap, m0, o1, c1,
+                                                                        cap1, m1, h->ctr, (uint64_t)step, h->next_id,
+                                                                        cth, ccr, ntr);
         else
             k_inject<R, D, S, false><<<grid_for(ninj), 256, 0, s>>>(G, o0, P0.tile_count[t0], P0.tile_cap, m0, o1, c1, cap1, m1,
                                                                    h->ctr, (uint64_t)step, h->next_id, cth, ccr, ntr);
@@ -541,7 +564,7 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
     timing_end(h, t_inj, s);
     if (push)
         for (int k = 0; k < nsp; ++k) sp[k].cur ^= 1;
-    if (cdep) {
+    if (cdep && !fcd) {
         double* const mom[2] = {reinterpret_cast<double*>(f->mom[0]), h->has_cr ? reinterpret_cast<double*>(f->mom[1]) : nullptr};
         deposit_continuous<R, D, S>(h, sp, mom, s);
     }
@@ -557,7 +580,7 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
     }
     if (fld) {
         const int t_fld = timing_begin(h, 3, s);
-        field_update<R>(h, f, s, true, rec ? rec->stages : nullptr);
+        field_update<R>(h, f, s, true, rec ? rec->stages : nullptr, rec ? rec->B_in : nullptr);
         timing_end(h, t_fld, s);
     }
     if (push || inj)
@@ -645,11 +668,11 @@ template <typename R> PLam<R> plam(const fs_adjoint* a, int k, int b, int D) {
     return L;
 }
 
-// Moments and fluid state of a tape state, into the reverse scratch: the
-// moments are copied from `mom` (the tape's grids of that state).
+// Fluid state of a tape state into the reverse scratch; the moments are read
+// in place from `mom` (the tape's grids of that state), which the reverse
+// step only reads.
 void fluid_of(fs_handle* h, int64_t* const* mom, hipStream_t s) {
-    for (int k = 0; k < (h->has_cr ? 2 : 1); ++k)
-        (void)hipMemcpyAsync(h->amom[k], mom[k], 4 * h->L.ndep * sizeof(double), hipMemcpyDeviceToDevice, s);
+    for (int k = 0; k < 2; ++k) h->amom[k] = reinterpret_cast<const double*>(mom[k < (h->has_cr ? 2 : 1) ? k : 0]);
     const dim3 blk(kFX, kFY, 1);
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
     k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(h->amom[0]),
@@ -659,7 +682,8 @@ void fluid_of(fs_handle* h, int64_t* const* mom, hipStream_t s) {
 
 // Transpose of Ohm's law at every node (see k_ohm_adj_node) evaluated at B:
 // the node pass from lam_E (lE, or with curl the Faraday transpose of lam_F
-// in lE), then the centre pass into o as EMIT says.
+// in lE), then the centre pass into o as EMIT says; in 2D and 3D both in one
+// pass that marches through y rows or z planes.
 template <int D, bool CURL, int EMIT>
 void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb, const RkOut& o, double* grads,
              hipStream_t s) {
@@ -673,6 +697,15 @@ void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb,
                                                                          nn, nc, gx, gy, zc);
         return;
     }
+    if constexpr (D == 2) {
+        // the same in 2D through runs of at most 16 y rows: 255 centre
+        // columns and 256 node columns (one per thread) per block
+        const int gx = (h->cfg.nx + YMarch::RX - 1) / YMarch::RX;
+        const int yc = (int)std::min<int64_t>(h->L.nyc, 16), gy = (int)((h->L.nyc + yc - 1) / yc);
+        k_ohm_adj2<CURL, EMIT><<<(unsigned)(gx * gy), 256, 0, s>>>(h->F, B, h->afl, lE, lBb, h->alfl, o, grads, nn, nc,
+                                                                    gx, yc);
+        return;
+    }
     k_ohm_adj_node<D, CURL><<<grid_for(nn), 256, 0, s>>>(h->F, B, h->afl, lE, lBb, h->aob, h->alfl, grads, nn, nc);
     k_ohm_adj_centre<D, EMIT><<<grid_for(nc), 256, 0, s>>>(h->F, h->aob, o, nn, nc);
 }
@@ -680,10 +713,12 @@ void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb,
 // Transpose of the field update of one step (the SSP-RK3 sub-steps from
 // B^n, then Ohm's law at B^{n+1}) with the fluid state in h->afl: lam_B
 // (in: lam(B^{n+1}), out: lam(B^n)), lam(E^{n+1}) in lE, lam(Bbar^{n+1})
-// in lBb; fluid adjoints added to h->alfl.  The stages are recomputed.
+// in lBb; fluid adjoints into h->alfl (its n_e and Gamma planes stored by
+// the first pass, its p_e plane, zeroed before, added to).  The stages are
+// recomputed unless the recorded step kept them.
 // Each stage's F(B) = -curl Ohm(B, fl) is transposed by one node pass (the
 // Faraday transpose gathered in it) and one centre pass that also does the
-// RK vector update that follows it.
+// RK vector update that follows it, fused into one marching pass in 2D and 3D.
 template <int D>
 void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* lBb, const double* Bn, double* lB,
                const double* stages, double* grads, hipStream_t s) {
@@ -747,7 +782,16 @@ void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* 
 // h->alM[k] at the deposit nodes (and the alpha_cr adjoint).
 void fluid_adj(fs_handle* h, double* grads, hipStream_t s) {
     const long nn = h->L.nnode;
-    for (int k = 0; k < 2; ++k) zero_u64(reinterpret_cast<unsigned long long*>(h->alM[k]), 4 * h->L.ndep, s);
+    // k_fluid_adj stores every entry of a periodic grid once; in a box only
+    // the entries at the x ends need clearing first
+    if (h->cfg.xbc == FS_XBC_BOX) {
+        const int g = (int)((h->L.ndx - h->L.nxn) / 2), mc = h->cfg.shape;
+        const int lo = mc + g, hi = h->cfg.nx - mc + g;
+        const long rows = h->L.nyc * h->L.nzc;
+        const unsigned nb = std::min<unsigned>(grid_for(rows * (lo + 1 + (h->L.ndx - hi)) * 4), 4096u);
+        for (int k = 0; k < (h->has_cr ? 2 : 1); ++k)
+            k_zero_dep_ends<<<nb, 256, 0, s>>>(h->alM[k], (int)h->L.ndx, rows, lo, hi);
+    }
     const double dwcr = h->has_cr ? h->cfg.n_cr / (double)h->cfg.ppc_cr : 0.0;
     k_fluid_adj<<<grid_for(nn), 256, 0, s>>>(h->F, h->amom[0], h->has_cr ? h->amom[1] : h->amom[0], h->alfl, h->alM[0],
                                              h->alM[1], nn, dwcr, grads + 1);
@@ -760,7 +804,9 @@ int adjoint_step_impl(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, c
     const long nn = h->L.nnode;
     // fluid state the step's field update used: moments of the particles after it
     fluid_of(h, f_n1->mom, s);
-    zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
+    // the p_e adjoints are gathered by atomics; the first (curl-free) Ohm
+    // transpose stores the n_e and Gamma ones
+    zero_u64(reinterpret_cast<unsigned long long*>(h->alfl + nn), nn, s);
     // final Ohm, then the RK3 sub-steps
     field_adj<D>(h, f_n1->B, lam->lE, lam->lE + 3 * nn, f_n->B, lam->lB, stages, grads, s);
     // fluid at n+1: the moment adjoints the deposit transpose reads
@@ -820,7 +866,9 @@ int adjoint_init_impl(fs_handle* h, const fs_packed* p0, const fs_fields* f0, fs
                       hipStream_t s) {
     const long nn = h->L.nnode, nc = h->L.ncent;
     fluid_of(h, f0->mom, s);
-    zero_u64(reinterpret_cast<unsigned long long*>(h->alfl), 5 * nn, s);
+    // the p_e adjoints are gathered by atomics; the first (curl-free) Ohm
+    // transpose stores the n_e and Gamma ones
+    zero_u64(reinterpret_cast<unsigned long long*>(h->alfl + nn), nn, s);
     RkOut o{};
     o.base = o.out = lam->lB;
     ohm_adj<D, false, kEmitOut>(h, f0->B, lam->lE, lam->lE + 3 * nn, o, grads, s);
@@ -1043,16 +1091,15 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     ok = ok && dmalloc((void**)&h->part, h->npart * sizeof(double));
     if (c.deposit_mode == 1) {
         const long nd = h->L.ndep;
-        for (int k = 0; k < 2 && ok; ++k) {
-            ok = ok && dmalloc((void**)&h->amom[k], 4 * nd * sizeof(double));
-            ok = ok && dmalloc((void**)&h->alM[k], 4 * nd * sizeof(double));
-        }
+        for (int k = 0; k < (h->has_cr ? 2 : 1) && ok; ++k) ok = ok && dmalloc((void**)&h->alM[k], 4 * nd * sizeof(double));
         ok = ok && dmalloc((void**)&h->afl, 5 * nn * sizeof(double));
         ok = ok && dmalloc((void**)&h->alfl, 5 * nn * sizeof(double));
         for (int k = 0; k < 5 && ok; ++k) ok = ok && dmalloc((void**)&h->al[k], 3 * nc * sizeof(double));
         // the starts of RK sub-steps after the first (slot 0, B^n itself, unused)
         if (c.n_sub > 1) ok = ok && dmalloc((void**)&h->aBs, (size_t)c.n_sub * 3 * nc * sizeof(double));
-        ok = ok && dmalloc((void**)&h->aob, 6 * nn * sizeof(double));
+        // the node pass's (lam_Bbar, lam_J) for the centre pass (1D only: the
+        // 2D and 3D transposes keep a node row or plane in LDS)
+        if (c.dim == 1) ok = ok && dmalloc((void**)&h->aob, 6 * nn * sizeof(double));
         ok = ok && dmalloc((void**)&h->actr, 2 * sizeof(unsigned long long));
         if (ok) ok = hipMemset(h->actr, 0, 2 * sizeof(unsigned long long)) == hipSuccess;
     }
@@ -1096,7 +1143,7 @@ void fs_destroy(fs_handle* h) {
     if (h->ctr_host) hipHostFree(h->ctr_host);
     hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->fluid2); hipFree(h->nprev); hipFree(h->gprev); hipFree(h->phase); hipFree(h->part); hipFree(h->spec);
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
-    for (int k = 0; k < 2; ++k) { hipFree(h->amom[k]); hipFree(h->alM[k]); }
+    for (int k = 0; k < 2; ++k) hipFree(h->alM[k]);
     hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->aob); hipFree(h->actr);
     for (int k = 0; k < 5; ++k) hipFree(h->al[k]);
     delete h;
@@ -1214,6 +1261,8 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
         return fail(h, FS_EINVAL, "a recorded step covers the non-relativistic first-order step only");
     if (int rc = check_record(h, rec)) return rc;
     if (rec->stages && h->cfg.n_sub != 1) return fail(h, FS_EINVAL, "kept RK stages need n_sub = 1");
+    if ((rec->B_in == nullptr) != (rec->gather_in == nullptr))
+        return fail(h, FS_EINVAL, "B_in and gather_in go together");
     if (pack_in)
         if (int rc = check_packed(h, pack_in, nullptr, false)) return rc;
     rec->id0 = h->next_id;

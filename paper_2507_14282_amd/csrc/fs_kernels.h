@@ -283,6 +283,96 @@ __device__ __forceinline__ void flush_tile(const unsigned long long* lds, unsign
     }
 }
 
+// ---------------------------------------------------------------------------
+// Continuous deposit (the differentiable variant of the step): real shape
+// weights in FP64, R = sum W and G = sum W v per node, FP64 atomics.  The
+// moment grids then hold doubles.  As in deposit_one, the LDS-or-global test
+// is taken once per particle, and in LDS the CIC corners are visited in an
+// order set by the lane bits.
+// ---------------------------------------------------------------------------
+template <typename R, int D, int S>
+__device__ __forceinline__ void deposit_particle_c(double* lds, int bx0, int by0, int bz0, double* mom, const Geo& G,
+                                                   int cx, int cy, int cz, const R* o, const R* v, int& oor) {
+    using X = Extent<D, S>;
+    constexpr int N = Stencil<S>::N;
+    constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
+    double wx[3], wy[3] = {1, 0, 0}, wz[3] = {1, 0, 0};
+    int rx, ry = 0, rz = 0;
+    weights_real<double, S>((double)o[0], rx, wx);
+    if constexpr (D >= 2) weights_real<double, S>((double)o[1], ry, wy);
+    if constexpr (D >= 3) weights_real<double, S>((double)o[2], rz, wz);
+    double vd[3] = {(double)v[0], (double)v[1], (double)v[2]};
+    if (G.ic2 != 0.0) {   // relativistic mode: v holds u, the flux needs u / gamma
+        const double g = sqrt(1.0 + (vd[0] * vd[0] + vd[1] * vd[1] + vd[2] * vd[2]) * G.ic2);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) vd[d] /= g;
+    }
+    int lx = cx + rx - bx0, ly = D >= 2 ? cy + ry - by0 : 0, lz = D >= 3 ? cz + rz - bz0 : 0;
+    bool in_lds = lds != nullptr && lx >= 0 && lx + N <= X::DX;
+    if constexpr (D >= 2) in_lds = in_lds && ly >= 0 && ly + N <= X::DY;
+    if constexpr (D >= 3) in_lds = in_lds && lz >= 0 && lz + N <= X::DZ;
+    if (in_lds) {
+        int f[3] = {0, 0, 0};
+        if constexpr (N == 2) {
+            const int lane = __lane_id();
+            f[0] = lane & 1;
+            if constexpr (D >= 2) f[1] = (lane >> 1) & 1;
+            if constexpr (D >= 3) f[2] = (lane >> 2) & 1;
+            if (f[0]) { const double t = wx[0]; wx[0] = wx[1]; wx[1] = t; }
+            if (f[1]) { const double t = wy[0]; wy[0] = wy[1]; wy[1] = t; }
+            if (f[2]) { const double t = wz[0]; wz[0] = wz[1]; wz[1] = t; }
+        }
+        const int sx = f[0] ? -1 : 1, sy = f[1] ? -X::DX : X::DX, sz = f[2] ? -X::DX * X::DY : X::DX * X::DY;
+        double* base = lds + (((lz + f[2]) * X::DY + (ly + f[1])) * X::DX + (lx + f[0]));
+#pragma unroll
+        for (int c = 0; c < NZ; ++c)
+#pragma unroll
+            for (int b = 0; b < NY; ++b)
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    const double W = wx[a] * wy[b] * wz[c];
+                    double* p = base + (a * sx + b * sy + c * sz);
+                    atomicAdd(p, W);
+                    atomicAdd(p + X::DN, W * vd[0]);
+                    atomicAdd(p + 2 * X::DN, W * vd[1]);
+                    atomicAdd(p + 3 * X::DN, W * vd[2]);
+                }
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < NZ; ++c)
+#pragma unroll
+        for (int b = 0; b < NY; ++b)
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                const double W = wx[a] * wy[b] * wz[c];
+                long gi = dep_index(cx + rx + a, D >= 2 ? cy + ry + b : 0, D >= 3 ? cz + rz + c : 0, G);
+                if (gi < 0) { oor = 1; continue; }
+                double* p = mom + 4 * gi;
+                unsafeAtomicAdd(p, W);
+                unsafeAtomicAdd(p + 1, W * vd[0]);
+                unsafeAtomicAdd(p + 2, W * vd[1]);
+                unsafeAtomicAdd(p + 3, W * vd[2]);
+            }
+}
+
+// Flush of a tile's FP64 accumulators of the continuous deposit, laid out
+// and issued as in flush_tile.
+template <int D, int S>
+__device__ __forceinline__ void flush_tile_c(const double* lds, double* mom, const Geo& G, int bx0, int by0, int bz0,
+                                             int& oor) {
+    using X = Extent<D, S>;
+    for (int l = threadIdx.x; l < X::DN * 4; l += blockDim.x) {
+        int node = l >> 2, m = l & 3;
+        double val = lds[m * X::DN + node];
+        if (val == 0.0) continue;
+        int lx = node % X::DX, ly = (node / X::DX) % X::DY, lz = node / (X::DX * X::DY);
+        long gi = dep_index(bx0 + lx, D >= 2 ? by0 + ly : 0, D >= 3 ? bz0 + lz : 0, G);
+        if (gi < 0) { oor = 1; continue; }
+        unsafeAtomicAdd(mom + 4 * gi + m, val);
+    }
+}
+
 // Wave-aggregated add of a per-lane count to a device counter.
 __device__ __forceinline__ void wave_add(unsigned long long* ctr, int v) {
     unsigned long long m = __ballot(v != 0);
@@ -369,19 +459,21 @@ __device__ __forceinline__ void store_ion(const PBuf<R>& out, long dst, const Io
 // and 5 waves otherwise).  The others take what their registers give (the
 // non-relativistic 3D CIC ones sit at 79-80 VGPRs, where one more register
 // costs a wave per SIMD and 15% of the time).
-template <typename R, int D, int S, bool REL> struct PushWaves {
+template <typename R, int D, int S, bool REL, bool CONT> struct PushWaves {
     static constexpr int value =
-        sizeof(R) != 4 ? 1 : ((D == 1 || (D == 2 && S == 1)) ? 8 : ((REL && S == 1) ? 6 : 1));
+        sizeof(R) != 4 ? 1 : ((D == 1 || (D == 2 && S == 1)) ? 8 : (((REL || CONT) && S == 1) ? 6 : 1));
 };
 
 // TC: the time-centred coupling, density deposited at the new position and
-// flux at the midpoint of the move.  REC: a recorded step (reverse mode),
+// flux at the midpoint of the move.  CONT (with DEP, non-relativistic): the
+// continuous deposit, FP64 weights into an FP64 box and grid, instead of the
+// fixed-point one.  REC: a recorded step (reverse mode),
 // which writes where each ion went into rec_dst, keeps each crosser's
 // source slot in the crosser list for the wall and, with pk_n > 0, copies
 // each input ion as it is read to its packed index pk_toff[tile] + rank
 // (the tape's packing of the input state, ions past pk_n dropped).
-template <typename R, int D, int S, bool DEP, bool REL, bool TC = false, bool REC = false>
-__global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
+template <typename R, int D, int S, bool DEP, bool REL, bool TC = false, bool REC = false, bool CONT = false>
+__global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL, CONT>::value)) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
                                               int32_t* __restrict__ cnt_out, int64_t cap,
                                               const R* __restrict__ gather, unsigned long long* __restrict__ mom,
                                               XList xl, unsigned long long* __restrict__ ctr, int policy,
@@ -395,6 +487,7 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
     extern __shared__ __align__(16) unsigned char smem[];
     Pair<R>* sg = reinterpret_cast<Pair<R>*>(smem);
     unsigned long long* sd = reinterpret_cast<unsigned long long*>(smem + L::off_dep);
+    static_assert(!CONT || (DEP && !REL && !TC), "the continuous deposit is fused only into the plain push");
     int* s_stay = reinterpret_cast<int*>(smem + (DEP ? L::off_misc : L::off_dep));
 
     const int tile = xcd_tile(blockIdx.x, G.ntiles);
@@ -542,7 +635,10 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
 
         if constexpr (DEP) {
             if (kind == 0) {
-                if constexpr (TC) {
+                if constexpr (CONT) {
+                    deposit_particle_c<R, D, S>(reinterpret_cast<double*>(sd), dx0, dy0, dz0,
+                                                reinterpret_cast<double*>(mom), G, nc[0], nc[1], nc[2], o, v, oor);
+                } else if constexpr (TC) {
                     int vq[3];
                     if constexpr (REL) velocity_codes_ig<R>(v, ig, G.sv, status, vq);
                     else velocity_codes<R, false>(v, 0.0, G.sv, status, vq);
@@ -598,7 +694,9 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL>::value)) voi
         cnt_out[tile] = min(ns, (int)cap);
         if (ns > cap) status |= F_TILE;
     }
-    if constexpr (DEP) flush_tile<D, S>(sd, mom, G, dx0, dy0, dz0, oor);
+    if constexpr (DEP && CONT)
+        flush_tile_c<D, S>(reinterpret_cast<const double*>(sd), reinterpret_cast<double*>(mom), G, dx0, dy0, dz0, oor);
+    else if constexpr (DEP) flush_tile<D, S>(sd, mom, G, dx0, dy0, dz0, oor);
     wave_add(ctr + C_ESC, nesc);
     wave_add(ctr + C_OPEN, nopen);
     wave_add(ctr + (species == 0 ? C_REM0 : C_REM1), nesc + nopen);
@@ -617,9 +715,10 @@ __global__ void k_check_bins(const int32_t* counts, int ntiles, int64_t cap, uns
 // ---------------------------------------------------------------------------
 // Faux-shock wall on the crosser list of one species (or SPECULAR mirror),
 // with eq. (1) or, when wm.on, the prescribed wall.
-// Reflected ions are binned into their new tile and deposited directly.
+// Reflected ions are binned into their new tile and deposited directly
+// (CONT: the continuous deposit into an FP64 grid).
 // ---------------------------------------------------------------------------
-template <typename R, int D, int S, bool DEP>
+template <typename R, int D, int S, bool DEP, bool CONT = false>
 __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int32_t* cnt_out, int64_t cap,
                                               unsigned long long* mom, unsigned long long* ctr,
                                               int policy, int species, uint64_t step, int32_t* rec_dst,
@@ -669,7 +768,9 @@ __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int3
         for (int c = 0; c < 3; ++c) out.v[c][dst] = vr[c];
         out.id[dst] = pid;
         if (rec_dst != nullptr) rec_dst[xl.src[i]] = (int32_t)(-2 - dst);   // step record: reflected into dst
-        if constexpr (DEP) status |= deposit_particle<R, D, S>(nullptr, 0, 0, 0, mom, G, cx, cy, cz, o, vr, oor);
+        if constexpr (DEP && CONT)
+            deposit_particle_c<R, D, S>(nullptr, 0, 0, 0, reinterpret_cast<double*>(mom), G, cx, cy, cz, o, vr, oor);
+        else if constexpr (DEP) status |= deposit_particle<R, D, S>(nullptr, 0, 0, 0, mom, G, cx, cy, cz, o, vr, oor);
     }
     wave_add(ctr + C_INC, n_inc);
     wave_add(ctr + C_TRANS, n_trans);
@@ -684,9 +785,9 @@ __global__ __launch_bounds__(256) void k_wall(Geo G, XList xl, PBuf<R> out, int3
 // ---------------------------------------------------------------------------
 // Injection: thermal ions at x = 0 (drifting Maxwellian) and CRs at x = L
 // (isotropic in the downstream frame, flux weighted), with deterministic
-// counts and ids handed out by the host.
+// counts and ids handed out by the host (CONT: deposited continuously).
 // ---------------------------------------------------------------------------
-template <typename R, int D, int S, bool DEP>
+template <typename R, int D, int S, bool DEP, bool CONT = false>
 __global__ __launch_bounds__(256) void k_inject(Geo G, PBuf<R> out0, int32_t* cnt0, int64_t cap0, unsigned long long* mom0,
                                                 PBuf<R> out1, int32_t* cnt1, int64_t cap1, unsigned long long* mom1,
                                                 unsigned long long* ctr, uint64_t step, int64_t id0,
@@ -774,61 +875,12 @@ __global__ __launch_bounds__(256) void k_inject(Geo G, PBuf<R> out0, int32_t* cn
 #pragma unroll
     for (int c = 0; c < 3; ++c) out.v[c][dst] = vr[c];
     out.id[dst] = (uint32_t)id;
-    if constexpr (DEP) status |= deposit_particle<R, D, S>(nullptr, 0, 0, 0, mom, G, cx, cy, cz, o, vr, oor);
+    if constexpr (DEP && CONT)
+        deposit_particle_c<R, D, S>(nullptr, 0, 0, 0, reinterpret_cast<double*>(mom), G, cx, cy, cz, o, vr, oor);
+    else if constexpr (DEP) status |= deposit_particle<R, D, S>(nullptr, 0, 0, 0, mom, G, cx, cy, cz, o, vr, oor);
     if (status & F_SAT) atomicAdd(ctr + C_SAT, 1ull);
     if (oor) atomicAdd(ctr + C_OOR, 1ull);
     if (status) atomicOr(reinterpret_cast<unsigned int*>(ctr + C_FLAGS), (unsigned int)status);
-}
-
-// ---------------------------------------------------------------------------
-// Continuous deposit (the differentiable variant of the step): real shape
-// weights in FP64, R = sum W and G = sum W v per node, FP64 atomics.  The
-// moment grids then hold doubles.
-// ---------------------------------------------------------------------------
-template <typename R, int D, int S>
-__device__ __forceinline__ void deposit_particle_c(double* lds, int bx0, int by0, int bz0, double* mom, const Geo& G,
-                                                   int cx, int cy, int cz, const R* o, const R* v, int& oor) {
-    using X = Extent<D, S>;
-    constexpr int N = Stencil<S>::N;
-    constexpr int NY = D >= 2 ? N : 1, NZ = D >= 3 ? N : 1;
-    double wx[3], wy[3] = {1, 0, 0}, wz[3] = {1, 0, 0};
-    int rx, ry = 0, rz = 0;
-    weights_real<double, S>((double)o[0], rx, wx);
-    if constexpr (D >= 2) weights_real<double, S>((double)o[1], ry, wy);
-    if constexpr (D >= 3) weights_real<double, S>((double)o[2], rz, wz);
-    double vd[3] = {(double)v[0], (double)v[1], (double)v[2]};
-    if (G.ic2 != 0.0) {   // relativistic mode: v holds u, the flux needs u / gamma
-        const double g = sqrt(1.0 + (vd[0] * vd[0] + vd[1] * vd[1] + vd[2] * vd[2]) * G.ic2);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) vd[d] /= g;
-    }
-    int lx = cx + rx - bx0, ly = D >= 2 ? cy + ry - by0 : 0, lz = D >= 3 ? cz + rz - bz0 : 0;
-    bool in_lds = lds != nullptr && lx >= 0 && lx + N <= X::DX;
-    if constexpr (D >= 2) in_lds = in_lds && ly >= 0 && ly + N <= X::DY;
-    if constexpr (D >= 3) in_lds = in_lds && lz >= 0 && lz + N <= X::DZ;
-#pragma unroll
-    for (int c = 0; c < NZ; ++c)
-#pragma unroll
-        for (int b = 0; b < NY; ++b)
-#pragma unroll
-            for (int a = 0; a < N; ++a) {
-                const double W = wx[a] * wy[b] * wz[c];
-                if (in_lds) {
-                    double* p = lds + ((lz + c) * X::DY * X::DX + (ly + b) * X::DX + (lx + a));
-                    atomicAdd(p, W);
-                    atomicAdd(p + X::DN, W * vd[0]);
-                    atomicAdd(p + 2 * X::DN, W * vd[1]);
-                    atomicAdd(p + 3 * X::DN, W * vd[2]);
-                } else {
-                    long gi = dep_index(cx + rx + a, D >= 2 ? cy + ry + b : 0, D >= 3 ? cz + rz + c : 0, G);
-                    if (gi < 0) { oor = 1; continue; }
-                    double* p = mom + 4 * gi;
-                    unsafeAtomicAdd(p, W);
-                    unsafeAtomicAdd(p + 1, W * vd[0]);
-                    unsafeAtomicAdd(p + 2, W * vd[1]);
-                    unsafeAtomicAdd(p + 3, W * vd[2]);
-                }
-            }
 }
 
 template <typename R, int D, int S>
@@ -864,15 +916,7 @@ __global__ __launch_bounds__(256) void k_deposit_c(Geo G, PBuf<R> in, const int3
                                     D >= 3 ? cell_z(pc, G) : 0, o, v, oor);
     }
     __syncthreads();
-    for (int l = threadIdx.x; l < X::DN * 4; l += blockDim.x) {
-        int node = l >> 2, m = l & 3;
-        double val = sd[m * X::DN + node];
-        if (val == 0.0) continue;
-        int lx = node % X::DX, ly = (node / X::DX) % X::DY, lz = node / (X::DX * X::DY);
-        long gi = dep_index(dx0 + lx, D >= 2 ? dy0 + ly : 0, D >= 3 ? dz0 + lz : 0, G);
-        if (gi < 0) { oor = 1; continue; }
-        unsafeAtomicAdd(mom + 4 * gi + m, val);
-    }
+    flush_tile_c<D, S>(sd, mom, G, dx0, dy0, dz0, oor);
     if (oor) atomicAdd(ctr + C_OOR, 1ull);
 }
 

@@ -95,7 +95,8 @@ class FsStats(C.Structure):
 
 
 class FsRecord(C.Structure):
-    _fields_ = [("dst", C.c_void_p * 2), ("capacity", C.c_int64 * 2), ("id0", C.c_int64), ("stages", C.c_void_p)]
+    _fields_ = [("dst", C.c_void_p * 2), ("capacity", C.c_int64 * 2), ("id0", C.c_int64), ("stages", C.c_void_p),
+                ("B_in", C.c_void_p), ("gather_in", C.c_void_p)]
 
 
 class FsAdjoint(C.Structure):

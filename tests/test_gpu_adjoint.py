@@ -62,6 +62,36 @@ def test_fp64_gradient_matches_oracle_adjoint(case):
     assert np.max(np.abs(gg - go)) <= 1e-12 * scale, (gg, go)
 
 
+# Boxes that span several blocks of the Ohm transposes that march through
+# the grid (2D: 255 centre columns by runs of 16 y rows; 3D: 32 x 8 columns
+# by runs of 32 z planes): ragged last blocks and runs (a run of one row or
+# plane among them), and the wall node on a block's last node column, which
+# the block owns.
+BLOCK_CASES = {
+    "2d_blocks": (dict(dim=2, nx=300, ny=20, dx=0.5, dt=0.0047, ppc=1, ppc_cr=1, n_cr=0.05, theta_deg=30.0,
+                       wall_th="faux_shock", wall_cr="faux_shock", n_modes=2, mode_amp=0.05, seed=43), 4),
+    "2d_wall_on_block_edge": (dict(dim=2, nx=255, ny=17, dx=0.5, dt=0.0047, ppc=1, ppc_cr=1, n_cr=0.05,
+                                   theta_deg=30.0, wall_th="specular", wall_cr="faux_shock", wall_field=1,
+                                   n_modes=2, mode_amp=0.05, seed=45), 3),
+    "3d_blocks": (dict(dim=3, nx=40, ny=10, nz=36, dx=0.5, dt=0.0047, ppc=1, ppc_cr=1, n_cr=0.05, theta_deg=20.0,
+                       wall_th="faux_shock", wall_cr="faux_shock", n_modes=2, mode_amp=0.05, seed=47), 3),
+    "3d_wall_on_block_edge": (dict(dim=3, nx=32, ny=8, nz=33, dx=0.5, dt=0.0047, ppc=1, ppc_cr=1, n_cr=0.05,
+                                   theta_deg=20.0, wall_th="faux_shock", wall_cr="faux_shock", n_modes=2,
+                                   mode_amp=0.05, seed=49), 3),
+}
+
+
+@pytest.mark.parametrize("case", sorted(BLOCK_CASES))
+def test_fp64_gradient_across_field_blocks(case):
+    kw, nsteps = BLOCK_CASES[case]
+    p = W.params(**kw)
+    lo, go = O.adjoint(p, nsteps)
+    lg, gg = gpu_grad(p, nsteps, K=2)
+    print(f"case {case}: loss {lg:.12e} / {lo:.12e}, grad {gg} / {go}", flush=True)
+    assert abs(lg - lo) <= 1e-12 * abs(lo)
+    assert np.max(np.abs(gg - go)) <= 1e-12 * np.max(np.abs(go)), (gg, go)
+
+
 def test_checkpoint_interval_does_not_change_the_gradient():
     kw, nsteps = CASES["cic_cr_inject"]
     p = W.params(**kw)
@@ -517,8 +547,9 @@ def test_tape_entry_points_validate_their_arguments():
     """fs_tape_pack, fs_tape_unpack, fs_adjoint_park / unpark and the kept
     RK stages refuse what their contract excludes, before any launch:
     NULL arguments, an unknown pack flag, a prev without its record,
-    negative id ranges, adjoint buffers shorter than the packed state and
-    kept stages with several RK sub-steps."""
+    negative id ranges, adjoint buffers shorter than the packed state,
+    kept stages with several RK sub-steps and an input B without its gather
+    grid."""
     import ctypes as C
     import torch
     from paper_2507_14282_amd import adjoint as A
@@ -572,6 +603,12 @@ def test_tape_entry_points_validate_their_arguments():
         keep.append(t)
     stages = torch.zeros(6 * int(sim2.L.ncent), dtype=torch.float64, device="cuda:0")
     rec.stages = stages.data_ptr()
+    with pytest.raises(F.FsError) as e:
+        sim2.step_record(0, rec)
+    assert e.value.code == F.FS_EINVAL
+    # the input state's B and gather grid go together
+    rec.stages = None
+    rec.B_in = sim2.B.data_ptr()
     with pytest.raises(F.FsError) as e:
         sim2.step_record(0, rec)
     assert e.value.code == F.FS_EINVAL
