@@ -180,7 +180,7 @@ def write_traffic(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir, command)
     (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the same
     counter reads for the 1 GiB copy; written with the hash of the kernel
     source it was measured on."""
-    kern = "k_push<float, 3, 1, true, false, false, false>"
+    kern = "k_push<float, 3, 1, true, false, false, false, false>"
     f = _counter(fetch_dir, "FETCH_SIZE", kern)
     w = _counter(write_dir, "WRITE_SIZE", kern)
     cf = _counter(copy_fetch_dir, "FETCH_SIZE", "copy")
@@ -220,7 +220,7 @@ def write_atomics(pmc_dir, command):
     into the tile box), LDS bank / address conflict cycles, and L2 atomic
     requests (the flush of the box into the global moment grid and the
     deposits of ions outside the box)."""
-    kern = "k_push<float, 3, 1, true, false, false, false>"
+    kern = "k_push<float, 3, 1, true, false, false, false, false>"
     d = {"kernel": kern, "workload": "cfg4 3D box 1024x192x192, 8 ppc", "counters": {}}
     for c in ATOMIC_COUNTERS:
         v = _counter(pmc_dir, c.replace("_sum", "") if c.endswith("_sum") else c, kern)
