@@ -452,16 +452,23 @@ __device__ __forceinline__ void store_ion(const PBuf<R>& out, long dst, const Io
 // that moved further go straight to the global grid) and write each ion to
 // the bin of its destination tile.
 // ---------------------------------------------------------------------------
-// Minimum waves per SIMD the push is compiled for, where the kernel fits
-// without scratch (measured): 8 for the FP32 1D kernels (their SGPRs would
-// otherwise cap them at 7, i.e. 6 with 8-wave workgroups) and the FP32 2D CIC
-// ones (71 VGPRs otherwise); 6 for the relativistic 3D CIC FP32 one (82 VGPRs
-// and 5 waves otherwise).  The others take what their registers give (the
-// non-relativistic 3D CIC ones sit at 79-80 VGPRs, where one more register
-// costs a wave per SIMD and 15% of the time).
-template <typename R, int D, int S, bool REL, bool CONT> struct PushWaves {
+// Minimum waves per SIMD the push is compiled for (measured): 8 for the FP32
+// 1D kernels (their SGPRs would otherwise cap them at 7, i.e. 6 with 8-wave
+// workgroups) and the FP32 2D CIC ones (71 VGPRs otherwise), but for the
+// recorded one with the continuous deposit, which would spill 28 B there
+// and runs 5% faster at the 6 waves its 75 VGPRs give; 6 for the
+// relativistic 3D CIC FP32 one (82 VGPRs and 5 waves otherwise) and the 3D
+// CIC FP32 ones with the continuous deposit (89-94 VGPRs otherwise: at 6
+// they spill 12 B, 44 B recorded, and still run 5% faster than at 4).  The
+// others take what their registers give (the non-relativistic 3D CIC ones
+// sit at 79-80 VGPRs, where one more register costs a wave per SIMD and 15%
+// of the time).
+template <typename R, int D, int S, bool REL, bool CONT, bool REC> struct PushWaves {
     static constexpr int value =
-        sizeof(R) != 4 ? 1 : ((D == 1 || (D == 2 && S == 1)) ? 8 : (((REL || CONT) && S == 1) ? 6 : 1));
+        sizeof(R) != 4 ? 1
+        : (D == 1 || (D == 2 && S == 1 && !(CONT && REC))) ? 8
+        : (D == 3 && S == 1 && (REL || CONT)) ? 6
+                                              : 1;
 };
 
 // TC: the time-centred coupling, density deposited at the new position and
@@ -473,7 +480,7 @@ template <typename R, int D, int S, bool REL, bool CONT> struct PushWaves {
 // each input ion as it is read to its packed index pk_toff[tile] + rank
 // (the tape's packing of the input state, ions past pk_n dropped).
 template <typename R, int D, int S, bool DEP, bool REL, bool TC = false, bool REC = false, bool CONT = false>
-__global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL, CONT>::value)) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
+__global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL, CONT, REC>::value)) void k_push(Geo G, PBuf<R> in, PBuf<R> out, const int32_t* __restrict__ cnt_in,
                                               int32_t* __restrict__ cnt_out, int64_t cap,
                                               const R* __restrict__ gather, unsigned long long* __restrict__ mom,
                                               XList xl, unsigned long long* __restrict__ ctr, int policy,
