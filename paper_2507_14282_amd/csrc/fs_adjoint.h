@@ -324,9 +324,11 @@ __global__ __launch_bounds__(256) void k_tape_record(Geo G, const int32_t* __res
         const int32_t d = dst_bin[bin_slot(tile, cap, lo, i)];
         int32_t r = -1;
         if (d != -1) {
-            const long slot = d >= 0 ? (long)d : (long)(-2 - d);
-            const int t2 = (int)(slot / cap);
-            const int j = (int)(slot - (long)t2 * cap);
+            // slots fit int32 (the record's encoding); most ions stay in their tile
+            const unsigned slot = d >= 0 ? (unsigned)d : (unsigned)(-2 - d), ucap = (unsigned)cap;
+            const unsigned own0 = (unsigned)tile * ucap;
+            const int t2 = slot - own0 < ucap ? tile : (int)(slot / ucap);
+            const int j = (int)(slot - (unsigned)t2 * ucap);
             const int lo2 = cnt_out[t2];
             const long q = toff_out[t2] + (j < lo2 ? j : lo2 + (int)(cap - 1 - j));
             if (q < n_out) r = d >= 0 ? (int32_t)q : (int32_t)(-2 - q);
