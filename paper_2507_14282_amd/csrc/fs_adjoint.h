@@ -1010,18 +1010,24 @@ __global__ __launch_bounds__(256) void k_ohm_adj_node(FieldGeo F, const double* 
 // component: the vector updates of the SSP-RK3 transpose (Shu-Osher form
 // B1 = B0 + h F(B0), B2 = 3/4 B0 + 1/4 (B1 + h F(B1)),
 // B3 = 1/3 B0 + 2/3 (B2 + h F(B2))) fused into the pass that completes
-// the adjoint they start from.
+// the adjoint they start from.  The part of v that the next stage starts
+// from (lam of B2 gets 2 v/3 from B3, lam of B1 gets v/4 from B2) is the
+// lam_F the pass stores divided by h, and the next pass reads that lam_F
+// anyway: the passes that emit kEmitStage2 and kEmitStage1 take their base
+// as lam_F(in) / h, and no copy of it is stored.
 enum RkEmit {
     kEmitOut = 0,     // out = v (out may be base)
-    kEmitStage1 = 1,  // l0 += v, lF = h v                    (v: lam of B1)
-    kEmitStage2 = 2,  // l0 += 3/4 v, l1 = v/4, lF = h v/4    (v: lam of B2)
-    kEmitStage3 = 3   // l0 = v/3, l2 = 2 v/3, lF = 2 h v/3   (v: lam of B3)
+    kEmitStage1 = 1,  // l0 += v, lF = h v          (v: lam of B1; base = lam_F(in) / h)
+    kEmitStage2 = 2,  // l0 += 3/4 v, lF = h v/4    (v: lam of B2; base = lam_F(in) / h)
+    kEmitStage3 = 3   // l0 = v/3, lF = 2 h v/3     (v: lam of B3)
 };
 struct RkOut {
-    const double* base;
-    double *l0, *l1, *l2, *lF, *out;
+    const double* base;   // kEmitOut, kEmitStage3
+    double *l0, *lF, *out;
+    const double* lFin;   // lam_F(in), for the base of kEmitStage1 and kEmitStage2
     double h;
 };
+template <int EMIT> constexpr bool kBaseFromLamF = EMIT == kEmitStage1 || EMIT == kEmitStage2;
 
 // Transpose of Ohm's law, second pass, one thread per centre: v = base +
 // the Bbar average and J differences of the 2^D nodes around the centre,
@@ -1078,17 +1084,15 @@ __global__ __launch_bounds__(256) void k_ohm_adj_centre(FieldGeo F, const double
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const long e = (long)d * ncent + q;
-        const double v = o.base[e] + acc[d];
+        const double v = (kBaseFromLamF<EMIT> ? o.lFin[e] / o.h : o.base[e]) + acc[d];
         if constexpr (EMIT == kEmitStage1) {
             o.l0[e] += v;
             o.lF[e] = o.h * v;
         } else if constexpr (EMIT == kEmitStage2) {
             o.l0[e] += 0.75 * v;
-            o.l1[e] = 0.25 * v;
             o.lF[e] = 0.25 * o.h * v;
         } else if constexpr (EMIT == kEmitStage3) {
             o.l0[e] = v * (1.0 / 3.0);
-            o.l2[e] = v * (2.0 / 3.0);
             o.lF[e] = v * (2.0 / 3.0) * o.h;
         } else {
             o.out[e] = v;
@@ -1325,6 +1329,13 @@ __global__ __launch_bounds__(256, 3) void k_ohm_adj3(FieldGeo F, const double* _
                 sO[3 + d][l] = lJ[d];
             }
         }
+        // lam_F(in) of this thread's centre of plane k-1, the base of a
+        // kEmitStage2 / kEmitStage1 emit, read before the next plane's load
+        // may overwrite its slot
+        double bF[3] = {0.0, 0.0, 0.0};
+        if constexpr (CURL && kBaseFromLamF<EMIT>)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) bF[d] = sF[prv][d][(tx + 1) + Z::CX * (ty + 1)];
         __syncthreads();
         // the node plane into the centre planes k-1 (as their upper plane)
         // and k (lower) of this thread's column
@@ -1353,17 +1364,15 @@ __global__ __launch_bounds__(256, 3) void k_ohm_adj3(FieldGeo F, const double* _
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     const long e = (long)d * ncent + q;
-                    const double v = o.base[e] + accK1[d];
+                    const double v = (kBaseFromLamF<EMIT> ? bF[d] / o.h : o.base[e]) + accK1[d];
                     if constexpr (EMIT == kEmitStage1) {
                         o.l0[e] += v;
                         o.lF[e] = o.h * v;
                     } else if constexpr (EMIT == kEmitStage2) {
                         o.l0[e] += 0.75 * v;
-                        o.l1[e] = 0.25 * v;
                         o.lF[e] = 0.25 * o.h * v;
                     } else if constexpr (EMIT == kEmitStage3) {
                         o.l0[e] = v * (1.0 / 3.0);
-                        o.l2[e] = v * (2.0 / 3.0);
                         o.lF[e] = v * (2.0 / 3.0) * o.h;
                     } else {
                         o.out[e] = v;
@@ -1544,6 +1553,13 @@ __global__ __launch_bounds__(256) void k_ohm_adj2(FieldGeo F, const double* __re
                 sO[3 + d][lx] = lJ[d];
             }
         }
+        // lam_F(in) of this thread's centre of row j-1, the base of a
+        // kEmitStage2 / kEmitStage1 emit, read before the next row's load may
+        // overwrite its slot
+        double bF[3] = {0.0, 0.0, 0.0};
+        if constexpr (CURL && kBaseFromLamF<EMIT>)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) bF[d] = sF[prv][d][t + 1];
         __syncthreads();
         // the node row into the centre rows j-1 (as their upper row) and j
         // (lower) of this thread's column
@@ -1569,17 +1585,15 @@ __global__ __launch_bounds__(256) void k_ohm_adj2(FieldGeo F, const double* __re
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     const long e = (long)d * ncent + q;
-                    const double v = o.base[e] + accJ1[d];
+                    const double v = (kBaseFromLamF<EMIT> ? bF[d] / o.h : o.base[e]) + accJ1[d];
                     if constexpr (EMIT == kEmitStage1) {
                         o.l0[e] += v;
                         o.lF[e] = o.h * v;
                     } else if constexpr (EMIT == kEmitStage2) {
                         o.l0[e] += 0.75 * v;
-                        o.l1[e] = 0.25 * v;
                         o.lF[e] = 0.25 * o.h * v;
                     } else if constexpr (EMIT == kEmitStage3) {
                         o.l0[e] = v * (1.0 / 3.0);
-                        o.l2[e] = v * (2.0 / 3.0);
                         o.lF[e] = v * (2.0 / 3.0) * o.h;
                     } else {
                         o.out[e] = v;

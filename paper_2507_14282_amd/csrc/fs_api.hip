@@ -48,7 +48,7 @@ struct fs_handle {
     double* alM[2] = {nullptr, nullptr};    // their adjoints
     double* afl = nullptr;                  // fluid state of the reverse step
     double* alfl = nullptr;                 // its adjoint
-    double* al[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // RK3 stage adjoints l0, l1, l2, lF (two)
+    double* al[3] = {nullptr, nullptr, nullptr};  // RK3 transpose: l0 and lam_F (two, ping-ponged)
     double* aBs = nullptr;                  // B at the start of each RK substep after the first
     double* aob = nullptr;                  // 1D Ohm transpose: lam(Bbar), lam(J) per node
     unsigned long long* actr = nullptr;     // injected-ion counters of the reverse step (zero between launches)
@@ -733,11 +733,11 @@ void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* 
         stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
         stage_launch<D>(h, h->B2, B0, Bs + (size_t)(sub + 1) * N, h->afl, 1.0 / 3.0, 2.0 / 3.0, hs, s);
     }
-    RkOut o;
-    o.l0 = h->al[0]; o.l1 = h->al[1]; o.l2 = h->al[2]; o.out = lB; o.h = hs;
+    RkOut o{};
+    o.l0 = h->al[0]; o.out = lB; o.h = hs;
     // lam_F alternates between two buffers: a pass reads the one the pass
-    // before wrote (with halos, in the 3D z-marching form) and writes the other
-    double* lFs[2] = {h->al[3], h->al[4]};
+    // before wrote (with halos, in the marching forms) and writes the other
+    double* lFs[2] = {h->al[1], h->al[2]};
     int lfw = 0;
     auto next_lF = [&]() -> const double* {
         const double* in = lFs[lfw];
@@ -761,13 +761,15 @@ void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* 
             stage_launch<D>(h, B0, B0, h->B1, h->afl, 0.0, 1.0, hs, s);
             stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
         }
-        // lam(B2) = l2 + (dF/dB2)^T lF, then B2 = 3/4 B0 + 1/4 (B1 + h F(B1))
-        o.base = o.l2;
+        // lam(B2) = 2/3 lam(B3) + (dF/dB2)^T lF, where 2/3 lam(B3) = lF / h,
+        // then B2 = 3/4 B0 + 1/4 (B1 + h F(B1))
         const double* lF2 = next_lF();
+        o.lFin = lF2;
         ohm_adj<D, true, kEmitStage2>(h, B2, lF2, nullptr, o, grads, s);
-        // lam(B1) = l1 + (dF/dB1)^T lF, then B1 = B0 + h F(B0)
-        o.base = o.l1;
+        // lam(B1) = 1/4 lam(B2) + (dF/dB1)^T lF, where 1/4 lam(B2) = lF / h,
+        // then B1 = B0 + h F(B0)
         const double* lF1 = next_lF();
+        o.lFin = lF1;
         ohm_adj<D, true, kEmitStage1>(h, B1, lF1, nullptr, o, grads, s);
         // lam(B0) = l0 + (dF/dB0)^T lF: the start of this sub-step, which
         // ends the previous one (or is lam(B^n))
@@ -1094,7 +1096,7 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
         for (int k = 0; k < (h->has_cr ? 2 : 1) && ok; ++k) ok = ok && dmalloc((void**)&h->alM[k], 4 * nd * sizeof(double));
         ok = ok && dmalloc((void**)&h->afl, 5 * nn * sizeof(double));
         ok = ok && dmalloc((void**)&h->alfl, 5 * nn * sizeof(double));
-        for (int k = 0; k < 5 && ok; ++k) ok = ok && dmalloc((void**)&h->al[k], 3 * nc * sizeof(double));
+        for (int k = 0; k < 3 && ok; ++k) ok = ok && dmalloc((void**)&h->al[k], 3 * nc * sizeof(double));
         // the starts of RK sub-steps after the first (slot 0, B^n itself, unused)
         if (c.n_sub > 1) ok = ok && dmalloc((void**)&h->aBs, (size_t)c.n_sub * 3 * nc * sizeof(double));
         // the node pass's (lam_Bbar, lam_J) for the centre pass (1D only: the
@@ -1145,7 +1147,7 @@ void fs_destroy(fs_handle* h) {
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
     for (int k = 0; k < 2; ++k) hipFree(h->alM[k]);
     hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->aob); hipFree(h->actr);
-    for (int k = 0; k < 5; ++k) hipFree(h->al[k]);
+    for (int k = 0; k < 3; ++k) hipFree(h->al[k]);
     delete h;
 }
 
