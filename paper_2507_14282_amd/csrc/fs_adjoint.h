@@ -655,6 +655,15 @@ __global__ __launch_bounds__((AdjPush<R, D, S>::threads), (AdjPush<R, D, S>::wav
     const double hD = 0.5 * G.dt, dtdx = G.dtdx;
     double acc = 0.0;
     for (long src = ts.begin + threadIdx.x; src < ts.end; src += blockDim.x) {
+        // the ion before the step, read in order, issued ahead of the
+        // dependent reads through its record entry (its id only where the
+        // wall reflected it)
+        const int32_t pc = in.cell[src];
+        R o[3] = {0, 0, 0}, v[3];
+#pragma unroll
+        for (int d = 0; d < D; ++d) o[d] = in.off[d][src];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[c] = in.v[c][src];
         // adjoint of the ion after the step, where the step put it
         const int32_t dr = dst_of[src];
         const bool refl = dr <= -2;
@@ -681,14 +690,7 @@ __global__ __launch_bounds__((AdjPush<R, D, S>::threads), (AdjPush<R, D, S>::wav
             for (int d = 0; d < 3; ++d) pre.v[d][src] = (R)0;
             continue;
         }
-        const uint32_t id = in.id[src];
-        const int32_t pc = in.cell[src];
         const int cx = cell_x(pc, G), cy = D >= 2 ? cell_y(pc, G) : 0, cz = D >= 3 ? cell_z(pc, G) : 0;
-        R o[3] = {0, 0, 0}, v[3];
-#pragma unroll
-        for (int d = 0; d < D; ++d) o[d] = in.off[d][src];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v[c] = in.v[c][src];
         // the forward gather and Boris, in the particle precision
         R wx[3], wy[3] = {1, 0, 0}, wz[3] = {1, 0, 0};
         int rx, ry = 0, rz = 0;
@@ -730,7 +732,7 @@ __global__ __launch_bounds__((AdjPush<R, D, S>::threads), (AdjPush<R, D, S>::wav
             const double delta = (double)(ncx - G.nx) + (double)ox;
             const double vp[3] = {(double)v1[0], (double)v1[1], (double)v1[2]};
             double lxpre, lvpre[3], lu2;
-            kick_vjp(G.seed, step, id, G.u2, (double)G.nx, vp, delta, lx[0], lv, lxpre, lvpre, lu2);
+            kick_vjp(G.seed, step, in.id[src], G.u2, (double)G.nx, vp, delta, lx[0], lv, lxpre, lvpre, lu2);
             acc += lu2 * G.rinv;
             lx[0] = lxpre;
 #pragma unroll
