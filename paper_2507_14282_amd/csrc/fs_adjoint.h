@@ -318,19 +318,23 @@ __global__ __launch_bounds__(256) void k_tape_record(Geo G, const int32_t* __res
     const RankShare rs = rank_share(cnt_in, G.ntiles, cap, split, lo);
     const int tile = rs.tile;
     const long base = toff_in[tile];
+    // most ions stay in their tile: its output count and offset, read once
+    const int lo_own = cnt_out[tile];
+    const long toff_own = toff_out[tile];
     for (int i = rs.begin + threadIdx.x; i < rs.end; i += blockDim.x) {
         const long p = base + i;
         if (p >= n_in) break;
         const int32_t d = dst_bin[bin_slot(tile, cap, lo, i)];
         int32_t r = -1;
         if (d != -1) {
-            // slots fit int32 (the record's encoding); most ions stay in their tile
+            // slots fit int32 (the record's encoding)
             const unsigned slot = d >= 0 ? (unsigned)d : (unsigned)(-2 - d), ucap = (unsigned)cap;
             const unsigned own0 = (unsigned)tile * ucap;
-            const int t2 = slot - own0 < ucap ? tile : (int)(slot / ucap);
+            const bool stay = slot - own0 < ucap;
+            const int t2 = stay ? tile : (int)(slot / ucap);
             const int j = (int)(slot - (unsigned)t2 * ucap);
-            const int lo2 = cnt_out[t2];
-            const long q = toff_out[t2] + (j < lo2 ? j : lo2 + (int)(cap - 1 - j));
+            const int lo2 = stay ? lo_own : cnt_out[t2];
+            const long q = (stay ? toff_own : (long)toff_out[t2]) + (j < lo2 ? j : lo2 + (int)(cap - 1 - j));
             if (q < n_out) r = d >= 0 ? (int32_t)q : (int32_t)(-2 - q);
             else *status = 1;
         }
