@@ -180,53 +180,80 @@ __device__ __forceinline__ PackShare pack_share(const int32_t* toff, int64_t n, 
 // The tape: particle states packed to their live ions
 // ---------------------------------------------------------------------------
 
-// Tile offsets of a packed state: toff[t] = ions of the tiles before t.  One
-// workgroup of 1024 threads walks the tiles in chunks of 4096, four adjacent
-// tiles a thread (neighbouring threads read neighbouring counts), with a
-// wave scan and a scan of the 16 wave totals per chunk.  Sets *status when
-// the total exceeds n.
+// Tile offsets of a packed state, toff[t] = ions of the tiles before t, in
+// two launches over chunks of kScanChunk tiles, one workgroup of 1024
+// threads a chunk, four adjacent tiles a thread (neighbouring threads read
+// neighbouring counts): k_tape_chunks sums each chunk's live counts into
+// part[c]; k_tape_offsets then scans its chunk (a wave scan and a scan of
+// the 16 wave totals) from the sum of the chunks before it.  The last
+// chunk's workgroup writes toff[ntiles] and sets *status when the total
+// exceeds n.
+constexpr int kScanChunk = 4096;
+
+__device__ __forceinline__ long long live_count(const int32_t* __restrict__ cnt, int ntiles, int64_t cap, int i) {
+    return i < ntiles ? min((long long)cnt[i] + cnt[ntiles + i], (long long)cap) : 0;
+}
+
+__global__ __launch_bounds__(1024) void k_tape_chunks(const int32_t* __restrict__ cnt, int ntiles, int64_t cap,
+                                                      long long* __restrict__ part) {
+    __shared__ long long wsum[16];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int base = blockIdx.x * kScanChunk;
+    long long x = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x += live_count(cnt, ntiles, cap, base + 4 * t + u);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) wsum[w] = x;
+    __syncthreads();
+    if (t == 0) {
+        long long tot = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) tot += wsum[q];
+        part[blockIdx.x] = tot;
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_tape_offsets(const int32_t* __restrict__ cnt, int ntiles, int64_t cap,
+                                                       const long long* __restrict__ part,
                                                        int32_t* __restrict__ toff, int64_t n,
                                                        int32_t* __restrict__ status) {
     __shared__ long long wsum[16];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int chunk = blockIdx.x, base = chunk * kScanChunk;
     long long carry = 0;
-    for (int base = 0; base < ntiles; base += 4096) {
-        long long c[4], loc = 0;
+    for (int c = 0; c < chunk; ++c) carry += part[c];
+    long long c4[4], loc = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = base + 4 * t + u;
-            c[u] = i < ntiles ? min((long long)cnt[i] + cnt[ntiles + i], (long long)cap) : 0;
-            loc += c[u];
-        }
-        long long x = loc;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const long long y = __shfl_up(x, off, 64);
-            if (lane >= off) x += y;
-        }
-        if (lane == 63) wsum[w] = x;
-        __syncthreads();
-        long long before = 0, total = 0;
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const long long v = wsum[q];
-            before += q < w ? v : 0;
-            total += v;
-        }
-        long long run = carry + before + x - loc;
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = base + 4 * t + u;
-            if (i < ntiles) toff[i] = (int32_t)run;
-            run += c[u];
-        }
-        carry += total;
-        __syncthreads();
+    for (int u = 0; u < 4; ++u) {
+        c4[u] = live_count(cnt, ntiles, cap, base + 4 * t + u);
+        loc += c4[u];
     }
-    if (t == 0) {
-        toff[ntiles] = (int32_t)carry;
-        if (carry > n) *status = 1;
+    long long x = loc;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const long long y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    long long before = 0, total = 0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const long long v = wsum[q];
+        before += q < w ? v : 0;
+        total += v;
+    }
+    long long run = carry + before + x - loc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = base + 4 * t + u;
+        if (i < ntiles) toff[i] = (int32_t)run;
+        run += c4[u];
+    }
+    if (t == 0 && chunk == (int)gridDim.x - 1) {
+        toff[ntiles] = (int32_t)(carry + total);
+        if (carry + total > n) *status = 1;
     }
 }
 

@@ -52,6 +52,7 @@ struct fs_handle {
     double* aBs = nullptr;                  // B at the start of each RK substep after the first
     double* aob = nullptr;                  // 1D Ohm transpose: lam(Bbar), lam(J) per node
     unsigned long long* actr = nullptr;     // injected-ion counters of the reverse step (zero between launches)
+    long long* scan_part = nullptr;         // chunk sums of the tile-offset scan of a packed state
     std::string err;
     // phase timing: pool of event pairs recorded on the caller's stream
     bool timing = false;
@@ -901,7 +902,10 @@ int tape_pack_impl(fs_handle* h, const fs_particles* sp, fs_packed* out, const f
     const int nt = (int)h->L.ntiles;
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         const fs_particles& P = sp[k];
-        k_tape_offsets<<<1, 1024, 0, s>>>(P.tile_count[P.cur], nt, P.tile_cap, out->toff[k], out->n[k], out->status);
+        const unsigned nch = (unsigned)((nt + kScanChunk - 1) / kScanChunk);
+        k_tape_chunks<<<nch, 1024, 0, s>>>(P.tile_count[P.cur], nt, P.tile_cap, h->scan_part);
+        k_tape_offsets<<<nch, 1024, 0, s>>>(P.tile_count[P.cur], nt, P.tile_cap, h->scan_part, out->toff[k], out->n[k],
+                                            out->status);
         PBuf<R> in = sections<R>(P.buf[P.cur], P.capacity, D);
         PBuf<R> o = sections<R>(out->buf[k], out->n[k], D);
         // boxes with few tiles (large ones) split each over workgroups of
@@ -1091,6 +1095,7 @@ int fs_create(const fs_config* cfg, fs_handle** out) {
     ok = ok && dmalloc((void**)&h->phase, (c.n_modes + 1) * sizeof(double));
     h->npart = std::max<int64_t>(grid_for(nc), h->L.ntiles) * 4;
     ok = ok && dmalloc((void**)&h->part, h->npart * sizeof(double));
+    ok = ok && dmalloc((void**)&h->scan_part, (size_t)((h->L.ntiles + kScanChunk - 1) / kScanChunk) * sizeof(long long));
     if (c.deposit_mode == 1) {
         const long nd = h->L.ndep;
         for (int k = 0; k < (h->has_cr ? 2 : 1) && ok; ++k) ok = ok && dmalloc((void**)&h->alM[k], 4 * nd * sizeof(double));
@@ -1143,7 +1148,7 @@ void fs_destroy(fs_handle* h) {
     for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
     hipFree(h->ctr);
     if (h->ctr_host) hipHostFree(h->ctr_host);
-    hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->fluid2); hipFree(h->nprev); hipFree(h->gprev); hipFree(h->phase); hipFree(h->part); hipFree(h->spec);
+    hipFree(h->B1); hipFree(h->B2); hipFree(h->Etmp); hipFree(h->fluid); hipFree(h->fluid2); hipFree(h->nprev); hipFree(h->gprev); hipFree(h->phase); hipFree(h->part); hipFree(h->scan_part); hipFree(h->spec);
     for (int k = 0; k < 2; ++k) hipFree(h->xl_mem[k]);
     for (int k = 0; k < 2; ++k) hipFree(h->alM[k]);
     hipFree(h->afl); hipFree(h->alfl); hipFree(h->aBs); hipFree(h->aob); hipFree(h->actr);
