@@ -219,7 +219,7 @@ typedef struct fs_particles {
 typedef struct fs_fields {
     double*  B;        /* centres: 3 planar arrays of ncent (Bx, By, Bz) */
     double*  E;        /* nodes: 3 planar arrays of nnode, E^n (FP64) */
-    void*    gather;   /* nodes: nnode x 8 reals (Ex Ey Ez 0 Bbarx Bbary Bbarz 0) */
+    void*    gather;   /* nodes: nnode x 6 reals (Ex Ey Ez Bbarx Bbary Bbarz) */
     int64_t* mom[2];   /* per species: ndep x 4 int64 (R, Gx, Gy, Gz) */
 } fs_fields;
 

@@ -675,10 +675,10 @@ __global__ __launch_bounds__((AdjPush<R, D, S>::threads), (AdjPush<R, D, S>::wav
     for (int l = threadIdx.x; l < 6 * X::GN; l += blockDim.x) sl[l] = 0.0;
     for (int l = threadIdx.x; l < X::GN; l += blockDim.x) {
         const int lx = l % X::GX, ly = (l / X::GX) % X::GY, lz = l / (X::GX * X::GY);
-        const R* g8 = gather + 8 * gather_index(gx0 + lx, gy0 + ly, gz0 + lz, G);
-        sg[l] = Pair<R>{g8[0], g8[1]};
-        sg[X::GN + l] = Pair<R>{g8[2], g8[4]};
-        sg[2 * X::GN + l] = Pair<R>{g8[5], g8[6]};
+        const Pair<R>* g6 = reinterpret_cast<const Pair<R>*>(gather + 6 * gather_index(gx0 + lx, gy0 + ly, gz0 + lz, G));
+        sg[l] = g6[0];
+        sg[X::GN + l] = g6[1];
+        sg[2 * X::GN + l] = g6[2];
     }
     __syncthreads();
     const R hR = (R)(0.5 * G.dt);

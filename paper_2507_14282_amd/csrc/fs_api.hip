@@ -246,7 +246,7 @@ int compute_layout(const fs_config* c, fs_layout_info* L, std::string& err) {
         L->buf_bytes[s] = cap ? bytes : 0;
     }
     if (L->tile_cap[0] > INT32_MAX || L->tile_cap[1] > INT32_MAX) { err = "tile capacity too large"; return FS_EINVAL; }
-    L->gather_bytes = L->nnode * 8 * rb;
+    L->gather_bytes = L->nnode * 6 * rb;
     static const int cic[4] = {0, 22, 11, 7}, tsc[4] = {0, 10, 5, 3};
     L->b_bits = c->shape == 2 ? tsc[c->dim] : cic[c->dim];
     L->sv_bits = sv_for(c->v_max);

@@ -385,16 +385,18 @@ __device__ __forceinline__ void ohm_tile(const FieldGeo& F, const double (*sB)[F
     ohm_core<D>(F, C, dp, fl[n], G, e, bb);
 }
 
-// One node of the gather grid (Ex Ey Ez 0 Bbarx Bbary Bbarz 0) in the particle
-// precision, as two 4-vector stores.
-template <typename R> struct Vec4;
-template <> struct Vec4<float> { using T = float4; };
-template <> struct Vec4<double> { using T = double4; };
-template <typename R> __device__ __forceinline__ void store_gather(R* g8, const double e[3], const double bb[3]) {
-    using V = typename Vec4<R>::T;
-    V* v = reinterpret_cast<V*>(g8);
-    v[0] = V{(R)e[0], (R)e[1], (R)e[2], (R)0};
-    v[1] = V{(R)bb[0], (R)bb[1], (R)bb[2], (R)0};
+// One node of the gather grid (Ex Ey Ez Bbarx Bbary Bbarz) in the particle
+// precision, as three 2-vector stores: the pairs (Ex, Ey), (Ez, Bbarx),
+// (Bbary, Bbarz) that the push stages.
+template <typename R> struct Vec2;
+template <> struct Vec2<float> { using T = float2; };
+template <> struct Vec2<double> { using T = double2; };
+template <typename R> __device__ __forceinline__ void store_gather(R* g6, const double e[3], const double bb[3]) {
+    using V = typename Vec2<R>::T;
+    V* v = reinterpret_cast<V*>(g6);
+    v[0] = V{(R)e[0], (R)e[1]};
+    v[1] = V{(R)e[2], (R)bb[0]};
+    v[2] = V{(R)bb[1], (R)bb[2]};
 }
 
 // Ohm's law at every node of the block, writing E (FP64) and E, Bbar in the
@@ -423,7 +425,7 @@ __global__ __launch_bounds__(256) void k_ohm(FieldGeo F, const double* __restric
     wall_E(F, i, e);
 #pragma unroll
     for (int d = 0; d < 3; ++d) E[(long)d * nnode + n] = e[d];
-    store_gather(gather + 8 * n, e, bb);
+    store_gather(gather + 6 * n, e, bb);
 }
 
 // One SSP-RK3 stage, fused: E = Ohm(Bin) at the block's nodes (its centres
@@ -794,7 +796,7 @@ __global__ __launch_bounds__(256) void k_ohm3(FieldGeo F, const double* __restri
             wall_E(F, x0 + tx, e);
 #pragma unroll
             for (int d = 0; d < 3; ++d) E[(long)d * nnode + f.n] = e[d];
-            store_gather(gather + 8 * f.n, e, bb);
+            store_gather(gather + 6 * f.n, e, bb);
         }
         __syncthreads();
     }

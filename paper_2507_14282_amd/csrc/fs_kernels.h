@@ -6,8 +6,8 @@
 //    buffers every step.  Each tile is read once, contiguously, by one
 //    workgroup and written back binned by destination tile, so the particle
 //    state streams through HBM exactly once per step.
-//  * gather grid: per field node 8 reals (E, 0, Bbar, 0) = two 16-byte (FP32)
-//    vectors, staged per tile in LDS.
+//  * gather grid: per field node 6 reals (E, Bbar) = the three pairs
+//    (Ex, Ey), (Ez, Bbarx), (Bbary, Bbarz), staged per tile in LDS.
 //  * moments: per species int64 [node][R, Gx, Gy, Gz], accumulated per tile
 //    in LDS with 64-bit LDS atomics and flushed with one global atomic per
 //    non-zero (node, moment).
@@ -508,10 +508,10 @@ __global__ __launch_bounds__(PUSH_THREADS, (PushWaves<R, D, S, REL, CONT, REC>::
     for (int l = threadIdx.x; l < X::GN; l += blockDim.x) {
         int lx = l % X::GX, ly = (l / X::GX) % X::GY, lz = l / (X::GX * X::GY);
         long gi = gather_index(gx0 + lx, gy0 + ly, gz0 + lz, G);
-        const R* src = gather + 8 * gi;
-        sg[l] = Pair<R>{src[0], src[1]};
-        sg[X::GN + l] = Pair<R>{src[2], src[4]};
-        sg[2 * X::GN + l] = Pair<R>{src[5], src[6]};
+        const Pair<R>* src = reinterpret_cast<const Pair<R>*>(gather + 6 * gi);
+        sg[l] = src[0];
+        sg[X::GN + l] = src[1];
+        sg[2 * X::GN + l] = src[2];
     }
     if constexpr (DEP)
         for (int l = threadIdx.x; l < X::DN * 4; l += blockDim.x) sd[l] = 0ull;

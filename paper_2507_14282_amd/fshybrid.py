@@ -254,7 +254,7 @@ class Simulation:
             P.species = s
         self.B = torch.zeros(3, int(L.ncent), dtype=torch.float64, device=dev)
         self.E = torch.zeros(3, int(L.nnode), dtype=torch.float64, device=dev)
-        self.gather = torch.zeros(int(L.nnode), 8, dtype=self.real, device=dev)
+        self.gather = torch.zeros(int(L.nnode), 6, dtype=self.real, device=dev)
         self.mom = [torch.zeros(int(L.ndep), 4, dtype=torch.int64, device=dev) for _ in range(2)]
         self.f = FsFields()
         self.f.B, self.f.E, self.f.gather = self.B.data_ptr(), self.E.data_ptr(), self.gather.data_ptr()

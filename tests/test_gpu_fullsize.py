@@ -112,7 +112,7 @@ def test_full_size_step_sampled_parity(name, c_light):
         slots = rng.choice(slots, 20000, replace=False)
     c0, o0, v0, id0 = read_ions(sim, sec0, slots)
     g = sim.gather.double().cpu().numpy()
-    E3, Bb3 = np.ascontiguousarray(g[:, 0:3]), np.ascontiguousarray(g[:, 4:7])
+    E3, Bb3 = np.ascontiguousarray(g[:, 0:3]), np.ascontiguousarray(g[:, 3:6])
     del g
     st = sim.step(2)
     assert st["flags"] == 0 and st["saturated"] == 0 and st["out_of_range"] == 0, st
@@ -313,7 +313,7 @@ def test_full_size_wall_events(name, model):
     ntx = int(L.ntile[0])
     wall_tiles = [t for t in range(int(L.ntiles)) if tile_coords(L, t)[0] == ntx - 1]
     g = sim.gather.double().cpu().numpy()
-    E3, Bb3 = np.ascontiguousarray(g[:, 0:3]), np.ascontiguousarray(g[:, 4:7])
+    E3, Bb3 = np.ascontiguousarray(g[:, 0:3]), np.ascontiguousarray(g[:, 3:6])
     del g
     nsp = 2 if sim.has_cr else 1
     before = {}
