@@ -44,7 +44,6 @@ struct fs_handle {
     int device = -1;                  // device current at fs_create
     double* static_scratch = nullptr; // device address of `scratch` on that device
     // reverse-mode scratch (deposit_mode 1 only)
-    const double* amom[2] = {nullptr, nullptr};   // the moment grids of the reverse step's tape state (not owned)
     double* alM[2] = {nullptr, nullptr};    // their adjoints
     double* afl = nullptr;                  // fluid state of the reverse step
     double* alfl = nullptr;                 // its adjoint
@@ -673,11 +672,10 @@ template <typename R> PLam<R> plam(const fs_adjoint* a, int k, int b, int D) {
 // in place from `mom` (the tape's grids of that state), which the reverse
 // step only reads.
 void fluid_of(fs_handle* h, int64_t* const* mom, hipStream_t s) {
-    for (int k = 0; k < 2; ++k) h->amom[k] = reinterpret_cast<const double*>(mom[k < (h->has_cr ? 2 : 1) ? k : 0]);
     const dim3 blk(kFX, kFY, 1);
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
-    k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(h->amom[0]),
-                               reinterpret_cast<const long long*>(h->has_cr ? h->amom[1] : h->amom[0]), h->afl,
+    k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(mom[0]),
+                               reinterpret_cast<const long long*>(h->has_cr ? mom[1] : mom[0]), h->afl,
                                h->L.nnode, nullptr, nullptr, nullptr, 0);
 }
 
@@ -782,8 +780,9 @@ void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* 
 }
 
 // Fluid transpose: lam of the fluid state in h->alfl -> the moment adjoints
-// h->alM[k] at the deposit nodes (and the alpha_cr adjoint).
-void fluid_adj(fs_handle* h, double* grads, hipStream_t s) {
+// h->alM[k] at the deposit nodes (and the alpha_cr adjoint), at the moment
+// grids `mom` the fluid state came from.
+void fluid_adj(fs_handle* h, int64_t* const* mom, double* grads, hipStream_t s) {
     const long nn = h->L.nnode;
     // k_fluid_adj stores every entry of a periodic grid once; in a box only
     // the entries at the x ends need clearing first
@@ -796,7 +795,9 @@ void fluid_adj(fs_handle* h, double* grads, hipStream_t s) {
             k_zero_dep_ends<<<nb, 256, 0, s>>>(h->alM[k], (int)h->L.ndx, rows, lo, hi);
     }
     const double dwcr = h->has_cr ? h->cfg.n_cr / (double)h->cfg.ppc_cr : 0.0;
-    k_fluid_adj<<<grid_for(nn), 256, 0, s>>>(h->F, h->amom[0], h->has_cr ? h->amom[1] : h->amom[0], h->alfl, h->alM[0],
+    const double* m0 = reinterpret_cast<const double*>(mom[0]);
+    const double* m1 = reinterpret_cast<const double*>(h->has_cr ? mom[1] : mom[0]);
+    k_fluid_adj<<<grid_for(nn), 256, 0, s>>>(h->F, m0, m1, h->alfl, h->alM[0],
                                              h->alM[1], nn, dwcr, grads + 1);
 }
 
@@ -813,7 +814,7 @@ int adjoint_step_impl(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, c
     // final Ohm, then the RK3 sub-steps
     field_adj<D>(h, f_n1->B, lam->lE, lam->lE + 3 * nn, f_n->B, lam->lB, stages, grads, s);
     // fluid at n+1: the moment adjoints the deposit transpose reads
-    fluid_adj(h, grads, s);
+    fluid_adj(h, f_n1->mom, grads, s);
     const int post = lam->cur, pre = lam->cur ^ 1;
     // the ions the step injected: their adjoint after it into dL/du_sh
     int64_t cth = 0, ccr = 0;
@@ -875,7 +876,7 @@ int adjoint_init_impl(fs_handle* h, const fs_packed* p0, const fs_fields* f0, fs
     RkOut o{};
     o.base = o.out = lam->lB;
     ohm_adj<D, false, kEmitOut>(h, f0->B, lam->lE, lam->lE + 3 * nn, o, grads, s);
-    fluid_adj(h, grads, s);
+    fluid_adj(h, f0->mom, grads, s);
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         PBuf<R> in = sections<R>(p0->buf[k], p0->n[k], D);
         const int sp_ = split_for(h->L, h->L.tile_cap[k]);
