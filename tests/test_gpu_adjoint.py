@@ -361,10 +361,11 @@ def test_step_record_maps_every_ion_to_where_the_step_put_it(dim, wall):
     assert total_refl > 0
 
 
-@pytest.mark.parametrize("dim,wall", [(1, "faux_shock"), (2, "specular")])
-def test_tape_pack_keeps_the_live_ions_and_the_record_in_packed_indices(dim, wall):
+@pytest.mark.parametrize("dim,wall,wide", [(1, "faux_shock", False), (2, "specular", False), (1, "faux_shock", True)])
+def test_tape_pack_keeps_the_live_ions_and_the_record_in_packed_indices(dim, wall, wide):
     """fs_tape_pack of the states before and after a recorded step: the tile
-    offsets are the running sums of the live counts, each tile's ions appear
+    offsets are the running sums of the live counts (the wide box has 4375
+    tiles, more than one chunk of the offset scan), each tile's ions appear
     in bin order (bottom run, then the top run from the top down) with every
     section copied, and the packed record of the state before maps each ion
     to the packed index of the same ion after the step (the bin record,
@@ -376,6 +377,8 @@ def test_tape_pack_keeps_the_live_ions_and_the_record_in_packed_indices(dim, wal
     from paper_2507_14282_amd import adjoint as A
     from paper_2507_14282_amd import fshybrid as F
     kw = dict(nx=48, dx=0.5, ppc=8) if dim == 1 else dict(nx=24, ny=8, dx=0.5, ppc=8)
+    if wide:
+        kw = dict(nx=140000, dx=0.5, ppc=2)
     p = W.params(dim=dim, ppc_cr=4, n_cr=0.05, wall_th=wall, wall_cr="faux_shock", u_sh=19.3, dt=0.0047,
                  precision=32, deposit_mode="continuous", seed=29, **kw)
     sim = F.Simulation(p, "cuda:0")
