@@ -390,7 +390,11 @@ int fs_bperp_spectrum_noalloc(fs_handle* h, const fs_fields* f, double* out, hip
  * fs_fields' B and gather) are the input state's B and gather grid, which
  * the step then reads in place of f's: f's B and gather (and E) only
  * receive the output state, so stepping from one state's grids into
- * another's needs no copy first.  They may be f's own (the in-place step). */
+ * another's needs no copy first.  They may be f's own (the in-place step).
+ * fluid (NULL for none; unfiltered moments only) is device memory of
+ * 5 x nnode doubles where the step's field update leaves the fluid state
+ * it used (n_e, p_e, Gamma_x, Gamma_y, Gamma_z, each planar over the nodes),
+ * for fs_adjoint_step to read instead of recomputing it from the moments. */
 typedef struct fs_record {
     int32_t*      dst[2];
     int64_t       capacity[2];
@@ -398,6 +402,7 @@ typedef struct fs_record {
     double*       stages;
     const double* B_in;
     const void*   gather_in;
+    double*       fluid;
 } fs_record;
 
 /* A particle state packed to its live ions: the reverse mode's tape, sized
@@ -447,8 +452,9 @@ typedef struct fs_adjoint {
  * state (sp's buf[cur]), the push also copies each input ion as it reads it
  * to its packed index in pack_in->buf: the ions of fs_tape_pack with
  * FS_PACK_IONS, without a pass of their own.  FS_EINVAL on another
- * configuration, a NULL dst of a species, rec->stages with n_sub > 1 or
- * only one of rec->B_in and rec->gather_in,
+ * configuration, a NULL dst of a species, rec->stages with n_sub > 1,
+ * only one of rec->B_in and rec->gather_in or rec->fluid with filtered
+ * moments,
  * FS_ECAPACITY if a dst holds fewer entries than the species' capacity or
  * the capacity does not fit the int32 encoding (above 2^31 - 3 slots). */
 int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, fs_record* rec,
@@ -484,8 +490,9 @@ int fs_tape_unpack(fs_handle* h, const fs_packed* pk, fs_particles* sp, hipStrea
  * step's record in pn->dst) and its fields (B, gather grid); pn1 / f_n1: the
  * packed state after it and its B and moment grids (f_n1->mom as the step
  * left them).  stages: the step's RK stages as fs_record.stages kept them
- * (n_sub = 1), or NULL to recompute them from f_n->B.  id0: the first id
- * the step handed out (fs_record.id0).
+ * (n_sub = 1), or NULL to recompute them from f_n->B.  fluid: the step's
+ * fluid state as fs_record.fluid kept it, or NULL to recompute it from
+ * f_n1->mom.  id0: the first id the step handed out (fs_record.id0).
  * *lam holds on entry the adjoints after the step (particles in buffer cur,
  * in the packed indices of pn1; lB, lE of B^{n+1} and E^{n+1}) and on exit
  * those before it (particles in the other buffer, in the packed indices of
@@ -495,8 +502,8 @@ int fs_tape_unpack(fs_handle* h, const fs_packed* pk, fs_particles* sp, hipStrea
  * included) or stages with n_sub > 1, FS_ECAPACITY if an adjoint buffer is
  * shorter than pn or pn1. */
 int fs_adjoint_step(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, const fs_packed* pn1,
-                    const fs_fields* f_n1, const double* stages, int64_t id0, int64_t step, fs_adjoint* lam,
-                    double* grads, hipStream_t s);
+                    const fs_fields* f_n1, const double* stages, const double* fluid, int64_t id0, int64_t step,
+                    fs_adjoint* lam, double* grads, hipStream_t s);
 
 /* Moving the particle adjoints between two packings of one state: a segment
  * of steps re-run from its checkpoint packs its last state in another order

@@ -92,10 +92,12 @@ class _Bins:
 class _Fields:
     """The grid part of a state: B, the gather grid and the moment grids,
     and (stages, for a tape state with one RK sub-step) the RK stages of the
-    step that produced it.  The reverse step does not read E, so every state
-    shares one array for it (the recorded steps write it)."""
+    step that produced it, and (fluid) the fluid state its field update used.
+    The reverse step does not read E, so every state shares one array for it
+    (the recorded steps write it)."""
 
-    def __init__(self, sim: F.Simulation, nsp: int, E: torch.Tensor, copy: bool = False, stages: bool = False):
+    def __init__(self, sim: F.Simulation, nsp: int, E: torch.Tensor, copy: bool = False, stages: bool = False,
+                 fluid: bool = False):
         def take(t):
             return t.clone() if copy else torch.empty_like(t)
         self.B = take(sim.B)
@@ -104,9 +106,13 @@ class _Fields:
         self.mom = [take(m) for m in sim.mom[:nsp]]
         self.stages = torch.empty((2,) + tuple(sim.B.shape), dtype=torch.float64, device=sim.B.device) \
             if stages else None
+        self.fluid = torch.empty(5 * int(sim.L.nnode), dtype=torch.float64, device=sim.B.device) if fluid else None
 
     def stages_ptr(self):
         return self.stages.data_ptr() if self.stages is not None else None
+
+    def fluid_ptr(self):
+        return self.fluid.data_ptr() if self.fluid is not None else None
 
     def fields(self, sim: F.Simulation) -> F.FsFields:
         f = F.FsFields()
@@ -207,6 +213,7 @@ def _recorded_step(sim: F.Simulation, n: int, pre: _Bins, f_pre, post: _Bins, f_
     rec.B_in = f_pre.B.data_ptr()
     rec.gather_in = f_pre.gather.data_ptr()
     rec.stages = f_post.stages_ptr()
+    rec.fluid = f_post.fluid_ptr()
     sp = pre.step_to(sim, post)
     rc = sim.lib.fs_step_record(sim.h, sp, C.byref(f_post.f(sim)), int(n), C.byref(rec), C.byref(pack_in.s), None,
                                 sim.stream)
@@ -236,11 +243,12 @@ def checkpoint_interval(nsteps: int, K: int, state_bytes: int, free_bytes: int, 
                       f"{free_bytes / 1e9:.1f} GB are free")
 
 
-def _fields_bytes(sim: F.Simulation, nsp: int, stages: bool = False) -> int:
+def _fields_bytes(sim: F.Simulation, nsp: int, stages: bool = False, fluid: bool = False) -> int:
     """Bytes of the grids of one state (E is shared), with the two RK stages
-    of a tape state."""
+    and the fluid state of a tape state."""
     t = [sim.B, sim.gather] + list(sim.mom[:nsp])
-    return int(sum(x.numel() * x.element_size() for x in t) + (2 * 8 * sim.B.numel() if stages else 0))
+    return int(sum(x.numel() * x.element_size() for x in t) + (2 * 8 * sim.B.numel() if stages else 0)
+               + (5 * 8 * int(sim.L.nnode) if fluid else 0))
 
 
 def _fixed_bytes(sim: F.Simulation, nsp: int, n) -> int:
@@ -328,6 +336,19 @@ class AdjointRun:
             k_own = 0
         self.own_bins = k_own == want
         self.K_run = k_own if self.own_bins else checkpoint_interval(self.nsteps, self.K, ckb, free, tape_bytes=tape)
+        # a tape state also keeps its step's fluid state, which the reverse
+        # step would otherwise recompute from the moments, where that does
+        # not shorten the interval (unfiltered moments)
+        self.keep_fluid = False
+        if int(p.get("smooth", 0)) == 0:
+            tape_fl = tape + _fields_bytes(sim, self.nsp, self.keep_stages, True) \
+                - _fields_bytes(sim, self.nsp, self.keep_stages)
+            try:
+                k_fl = checkpoint_interval(self.nsteps, self.K, ckb, free - (own if self.own_bins else 0),
+                                           tape_bytes=tape_fl)
+            except MemoryError:
+                k_fl = 0
+            self.keep_fluid = k_fl == self.K_run
         for n in range(self.nsteps):
             if n % self.K_run == 0:
                 self.checkpoints[n] = _Checkpoint(sim, self.nsp, self._E, self._status)
@@ -374,7 +395,8 @@ class AdjointRun:
         if (b is not None and b["key"] == self._key(sim) and len(b["fields"]) >= K
                 and all(b["n"][k] >= n[k] for k in range(self.nsp)) and b["nid"] >= self.nid
                 and (b["work"] is not None) == self.own_bins
-                and (b["fields"][0].stages is not None) == self.keep_stages):
+                and (b["fields"][0].stages is not None) == self.keep_stages
+                and (b["fields"][0].fluid is not None) == self.keep_fluid):
             return b
         self._bufs = b = None
         dim = int(self.p["dim"])
@@ -403,9 +425,9 @@ class AdjointRun:
             keep.append(t)
         nid = self.nid + self.nid // 8 + 4096
         scratch = torch.empty(self.nsp * (dim + 3) * nid, dtype=sim.real, device=dev)
-        fields = [_Fields(sim, self.nsp, self._E, stages=self.keep_stages) for _ in range(K)]
+        fields = [_Fields(sim, self.nsp, self._E, stages=self.keep_stages, fluid=self.keep_fluid) for _ in range(K)]
         packed = [_Packed(sim, self.nsp, n, self._status) for _ in range(K + 1)]
-        nbytes = _fixed_bytes(sim, self.nsp, n) + K * (_fields_bytes(sim, self.nsp, self.keep_stages)
+        nbytes = _fixed_bytes(sim, self.nsp, n) + K * (_fields_bytes(sim, self.nsp, self.keep_stages, self.keep_fluid)
                                                        + _Packed.bytes(sim, self.nsp, n))
         work = [_Bins(sim, self.nsp, w, own=True) for w in range(2)] if self.own_bins else None
         if work is not None:
@@ -463,7 +485,8 @@ class AdjointRun:
                 sim._check(lib.fs_adjoint_unpark(sim.h, C.byref(P[m].s), C.byref(lam), scratch, nid, stream))
             for j in range(m - 1, -1, -1):
                 rc = lib.fs_adjoint_step(sim.h, C.byref(P[j].s), C.byref(flds[j].f(sim)), C.byref(P[j + 1].s),
-                                         C.byref(flds[j + 1].f(sim)), flds[j + 1].stages_ptr(), id0[j], s0 + j,
+                                         C.byref(flds[j + 1].f(sim)), flds[j + 1].stages_ptr(),
+                                         flds[j + 1].fluid_ptr(), id0[j], s0 + j,
                                          C.byref(lam), gptr, stream)
                 sim._check(rc)
             if s0 == 0:

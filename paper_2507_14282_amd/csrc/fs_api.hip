@@ -345,8 +345,12 @@ void zero_i32(int32_t* p, int64_t n, hipStream_t s) {
 // stages: NULL, or (one sub-step) where the RK stages B1 and B2 go instead
 // of the handle's scratch (3 x ncent doubles each, B1 first).  Bin: NULL,
 // or B^n to step from instead of f->B (which then only receives B^{n+1}).
+// fluid_out: NULL, or where the fluid state goes instead of the handle's
+// buffer (5 x nnode doubles; never given with the filter or the
+// time-centred coupling).
 template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hipStream_t s, bool rk,
-                                                 double* stages = nullptr, const double* Bin = nullptr) {
+                                                 double* stages = nullptr, const double* Bin = nullptr,
+                                                 double* fluid_out = nullptr) {
     const long nn = h->L.nnode, nc = h->L.ncent;
     const dim3 blk(kFX, kFY, 1);
     const dim3 gn((unsigned)((h->L.nxn + kFX - 1) / kFX), (unsigned)((h->L.nyc + kFY - 1) / kFY), (unsigned)h->L.nzc);
@@ -355,7 +359,8 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
     // refresh (Ohm only) makes the current moments the previous step's
     const int tc = h->cfg.coupling == 2 ? (rk ? 2 : 1) : 0;
     k_fluid<<<gn, blk, 0, s>>>(h->F, reinterpret_cast<const long long*>(f->mom[0]),
-                               reinterpret_cast<const long long*>(h->has_cr ? f->mom[1] : f->mom[0]), h->fluid, nn,
+                               reinterpret_cast<const long long*>(h->has_cr ? f->mom[1] : f->mom[0]),
+                               fluid_out ? fluid_out : h->fluid, nn,
                                h->fluid2, h->nprev, h->gprev, tc);
     if (h->cfg.smooth > 0) {
         // passes ping-pong between the two buffers; the finish writes the
@@ -372,7 +377,8 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
     }
     // taken after the filter, which may have swapped the buffers (the
     // time-centred coupling, which uses fluid2, runs without it)
-    const double* fl_ohm = tc == 2 ? h->fluid2 : h->fluid;
+    const double* fl = fluid_out ? fluid_out : h->fluid;
+    const double* fl_ohm = tc == 2 ? h->fluid2 : fl;
     const double hs = h->cfg.dt / (double)h->cfg.n_sub;
     if constexpr (D == 3) {
         // z-marching kernels: 32 x 8 columns over runs of at most 32 z planes
@@ -385,9 +391,9 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
             double* B2 = stages ? stages + 3 * nc : h->B2;
             for (int sub = 0; sub < h->cfg.n_sub; ++sub) {
                 const double* B0 = (sub == 0 && Bin) ? Bin : f->B;
-                k_stage3<<<nb, 256, 0, s>>>(h->F, B0, B0, B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy, zc);
-                k_stage3<<<nb, 256, 0, s>>>(h->F, B1, B0, B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy, zc);
-                k_stage3<<<nb, 256, 0, s>>>(h->F, B2, B0, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy,
+                k_stage3<<<nb, 256, 0, s>>>(h->F, B0, B0, B1, fl, 0.0, 1.0, hs, nn, nc, gx, gy, zc);
+                k_stage3<<<nb, 256, 0, s>>>(h->F, B1, B0, B2, fl, 0.75, 0.25, hs, nn, nc, gx, gy, zc);
+                k_stage3<<<nb, 256, 0, s>>>(h->F, B2, B0, f->B, fl, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy,
                                             zc);
             }
         }
@@ -406,9 +412,9 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
             // SSP-RK3 (Shu-Osher): B1 = B + h F(B); B2 = 3/4 B + 1/4 (B1 + h F(B1));
             // B <- 1/3 B + 2/3 (B2 + h F(B2)); the last stage writes f->B
             const double* B0 = (sub == 0 && Bin) ? Bin : f->B;
-            k_stage<D><<<nb, 256, 0, s>>>(h->F, B0, B0, B1, h->fluid, 0.0, 1.0, hs, nn, nc, gx, gy);
-            k_stage<D><<<nb, 256, 0, s>>>(h->F, B1, B0, B2, h->fluid, 0.75, 0.25, hs, nn, nc, gx, gy);
-            k_stage<D><<<nb, 256, 0, s>>>(h->F, B2, B0, f->B, h->fluid, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy);
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, B0, B0, B1, fl, 0.0, 1.0, hs, nn, nc, gx, gy);
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, B1, B0, B2, fl, 0.75, 0.25, hs, nn, nc, gx, gy);
+            k_stage<D><<<nb, 256, 0, s>>>(h->F, B2, B0, f->B, fl, 1.0 / 3.0, 2.0 / 3.0, hs, nn, nc, gx, gy);
         }
     }
     const int gxo = (int)((h->L.nxn + FB::X - 1) / FB::X);
@@ -418,10 +424,10 @@ template <typename R, int D> void field_update_d(fs_handle* h, fs_fields* f, hip
 
 template <typename R>
 void field_update(fs_handle* h, fs_fields* f, hipStream_t s, bool rk, double* stages = nullptr,
-                  const double* Bin = nullptr) {
-    if (h->cfg.dim == 1) field_update_d<R, 1>(h, f, s, rk, stages, Bin);
-    else if (h->cfg.dim == 2) field_update_d<R, 2>(h, f, s, rk, stages, Bin);
-    else field_update_d<R, 3>(h, f, s, rk, stages, Bin);
+                  const double* Bin = nullptr, double* fluid_out = nullptr) {
+    if (h->cfg.dim == 1) field_update_d<R, 1>(h, f, s, rk, stages, Bin, fluid_out);
+    else if (h->cfg.dim == 2) field_update_d<R, 2>(h, f, s, rk, stages, Bin, fluid_out);
+    else field_update_d<R, 3>(h, f, s, rk, stages, Bin, fluid_out);
 }
 
 // ------------------------------------------------------------------------
@@ -580,7 +586,8 @@ int step_impl(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, uint32
     }
     if (fld) {
         const int t_fld = timing_begin(h, 3, s);
-        field_update<R>(h, f, s, true, rec ? rec->stages : nullptr, rec ? rec->B_in : nullptr);
+        field_update<R>(h, f, s, true, rec ? rec->stages : nullptr, rec ? rec->B_in : nullptr,
+                        rec ? rec->fluid : nullptr);
         timing_end(h, t_fld, s);
     }
     if (push || inj)
@@ -684,15 +691,15 @@ void fluid_of(fs_handle* h, int64_t* const* mom, hipStream_t s) {
 // in lE), then the centre pass into o as EMIT says; in 2D and 3D both in one
 // pass that marches through y rows or z planes.
 template <int D, bool CURL, int EMIT>
-void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb, const RkOut& o, double* grads,
-             hipStream_t s) {
+void ohm_adj(fs_handle* h, const double* fl, const double* B, const double* lE, const double* lBb, const RkOut& o,
+             double* grads, hipStream_t s) {
     const long nn = h->L.nnode, nc = h->L.ncent;
     if constexpr (D == 3) {
         // one z-marching pass over 32 x 8 block columns and runs of at most
         // 32 z planes, as the forward stage kernels
         const int gx = (h->cfg.nx + ZMarch::X - 1) / ZMarch::X, gy = (int)((h->L.nyc + ZMarch::Y - 1) / ZMarch::Y);
         const int zc = (int)std::min<int64_t>(h->L.nzc, 32), gz = (int)((h->L.nzc + zc - 1) / zc);
-        k_ohm_adj3<CURL, EMIT><<<(unsigned)(gx * gy * gz), 256, 0, s>>>(h->F, B, h->afl, lE, lBb, h->alfl, o, grads,
+        k_ohm_adj3<CURL, EMIT><<<(unsigned)(gx * gy * gz), 256, 0, s>>>(h->F, B, fl, lE, lBb, h->alfl, o, grads,
                                                                          nn, nc, gx, gy, zc);
         return;
     }
@@ -701,16 +708,16 @@ void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb,
         // columns and 256 node columns (one per thread) per block
         const int gx = (h->cfg.nx + YMarch::RX - 1) / YMarch::RX;
         const int yc = (int)std::min<int64_t>(h->L.nyc, 16), gy = (int)((h->L.nyc + yc - 1) / yc);
-        k_ohm_adj2<CURL, EMIT><<<(unsigned)(gx * gy), 256, 0, s>>>(h->F, B, h->afl, lE, lBb, h->alfl, o, grads, nn, nc,
+        k_ohm_adj2<CURL, EMIT><<<(unsigned)(gx * gy), 256, 0, s>>>(h->F, B, fl, lE, lBb, h->alfl, o, grads, nn, nc,
                                                                     gx, yc);
         return;
     }
-    k_ohm_adj_node<D, CURL><<<grid_for(nn), 256, 0, s>>>(h->F, B, h->afl, lE, lBb, h->aob, h->alfl, grads, nn, nc);
+    k_ohm_adj_node<D, CURL><<<grid_for(nn), 256, 0, s>>>(h->F, B, fl, lE, lBb, h->aob, h->alfl, grads, nn, nc);
     k_ohm_adj_centre<D, EMIT><<<grid_for(nc), 256, 0, s>>>(h->F, h->aob, o, nn, nc);
 }
 
 // Transpose of the field update of one step (the SSP-RK3 sub-steps from
-// B^n, then Ohm's law at B^{n+1}) with the fluid state in h->afl: lam_B
+// B^n, then Ohm's law at B^{n+1}) with the fluid state fl: lam_B
 // (in: lam(B^{n+1}), out: lam(B^n)), lam(E^{n+1}) in lE, lam(Bbar^{n+1})
 // in lBb; fluid adjoints into h->alfl (its n_e and Gamma planes stored by
 // the first pass, its p_e plane, zeroed before, added to).  The stages are
@@ -719,8 +726,8 @@ void ohm_adj(fs_handle* h, const double* B, const double* lE, const double* lBb,
 // Faraday transpose gathered in it) and one centre pass that also does the
 // RK vector update that follows it, fused into one marching pass in 2D and 3D.
 template <int D>
-void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* lBb, const double* Bn, double* lB,
-               const double* stages, double* grads, hipStream_t s) {
+void field_adj(fs_handle* h, const double* fl, const double* Bn1, const double* lE, const double* lBb,
+               const double* Bn, double* lB, const double* stages, double* grads, hipStream_t s) {
     const long N = 3 * h->L.ncent;
     const int ns = h->cfg.n_sub;
     const double hs = h->cfg.dt / (double)ns;
@@ -728,9 +735,9 @@ void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* 
     double* Bs = h->aBs;
     for (int sub = 0; sub + 1 < ns; ++sub) {
         const double* B0 = sub == 0 ? Bn : Bs + (size_t)sub * N;
-        stage_launch<D>(h, B0, B0, h->B1, h->afl, 0.0, 1.0, hs, s);
-        stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
-        stage_launch<D>(h, h->B2, B0, Bs + (size_t)(sub + 1) * N, h->afl, 1.0 / 3.0, 2.0 / 3.0, hs, s);
+        stage_launch<D>(h, B0, B0, h->B1, fl, 0.0, 1.0, hs, s);
+        stage_launch<D>(h, h->B1, B0, h->B2, fl, 0.75, 0.25, hs, s);
+        stage_launch<D>(h, h->B2, B0, Bs + (size_t)(sub + 1) * N, fl, 1.0 / 3.0, 2.0 / 3.0, hs, s);
     }
     RkOut o{};
     o.l0 = h->al[0]; o.out = lB; o.h = hs;
@@ -748,7 +755,7 @@ void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* 
     // Ohm at B^{n+1}; its centre pass starts the last sub-step's transpose
     // B3 = 1/3 B0 + 2/3 (B2 + h F(B2))
     o.base = lB;
-    ohm_adj<D, false, kEmitStage3>(h, Bn1, lE, lBb, o, grads, s);
+    ohm_adj<D, false, kEmitStage3>(h, fl, Bn1, lE, lBb, o, grads, s);
     for (int sub = ns - 1; sub >= 0; --sub) {
         const double* B0 = sub == 0 ? Bn : Bs + (size_t)sub * N;
         // the stages, as the recorded step kept them or recomputed
@@ -757,25 +764,25 @@ void field_adj(fs_handle* h, const double* Bn1, const double* lE, const double* 
             B1 = stages;
             B2 = stages + N;
         } else {
-            stage_launch<D>(h, B0, B0, h->B1, h->afl, 0.0, 1.0, hs, s);
-            stage_launch<D>(h, h->B1, B0, h->B2, h->afl, 0.75, 0.25, hs, s);
+            stage_launch<D>(h, B0, B0, h->B1, fl, 0.0, 1.0, hs, s);
+            stage_launch<D>(h, h->B1, B0, h->B2, fl, 0.75, 0.25, hs, s);
         }
         // lam(B2) = 2/3 lam(B3) + (dF/dB2)^T lF, where 2/3 lam(B3) = lF / h,
         // then B2 = 3/4 B0 + 1/4 (B1 + h F(B1))
         const double* lF2 = next_lF();
         o.lFin = lF2;
-        ohm_adj<D, true, kEmitStage2>(h, B2, lF2, nullptr, o, grads, s);
+        ohm_adj<D, true, kEmitStage2>(h, fl, B2, lF2, nullptr, o, grads, s);
         // lam(B1) = 1/4 lam(B2) + (dF/dB1)^T lF, where 1/4 lam(B2) = lF / h,
         // then B1 = B0 + h F(B0)
         const double* lF1 = next_lF();
         o.lFin = lF1;
-        ohm_adj<D, true, kEmitStage1>(h, B1, lF1, nullptr, o, grads, s);
+        ohm_adj<D, true, kEmitStage1>(h, fl, B1, lF1, nullptr, o, grads, s);
         // lam(B0) = l0 + (dF/dB0)^T lF: the start of this sub-step, which
         // ends the previous one (or is lam(B^n))
         o.base = o.l0;
         const double* lF0 = next_lF();
-        if (sub > 0) ohm_adj<D, true, kEmitStage3>(h, B0, lF0, nullptr, o, grads, s);
-        else ohm_adj<D, true, kEmitOut>(h, B0, lF0, nullptr, o, grads, s);
+        if (sub > 0) ohm_adj<D, true, kEmitStage3>(h, fl, B0, lF0, nullptr, o, grads, s);
+        else ohm_adj<D, true, kEmitOut>(h, fl, B0, lF0, nullptr, o, grads, s);
     }
 }
 
@@ -803,16 +810,21 @@ void fluid_adj(fs_handle* h, int64_t* const* mom, double* grads, hipStream_t s) 
 
 template <typename R, int D, int S>
 int adjoint_step_impl(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, const fs_packed* pn1,
-                      const fs_fields* f_n1, const double* stages, int64_t id0, int64_t step, fs_adjoint* lam,
-                      double* grads, hipStream_t s) {
+                      const fs_fields* f_n1, const double* stages, const double* fluid, int64_t id0, int64_t step,
+                      fs_adjoint* lam, double* grads, hipStream_t s) {
     const long nn = h->L.nnode;
-    // fluid state the step's field update used: moments of the particles after it
-    fluid_of(h, f_n1->mom, s);
+    // fluid state the step's field update used (from the moments of the
+    // particles after it), as the recorded step kept it or recomputed
+    const double* fl = fluid;
+    if (!fl) {
+        fluid_of(h, f_n1->mom, s);
+        fl = h->afl;
+    }
     // the p_e adjoints are gathered by atomics; the first (curl-free) Ohm
     // transpose stores the n_e and Gamma ones
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl + nn), nn, s);
     // final Ohm, then the RK3 sub-steps
-    field_adj<D>(h, f_n1->B, lam->lE, lam->lE + 3 * nn, f_n->B, lam->lB, stages, grads, s);
+    field_adj<D>(h, fl, f_n1->B, lam->lE, lam->lE + 3 * nn, f_n->B, lam->lB, stages, grads, s);
     // fluid at n+1: the moment adjoints the deposit transpose reads
     fluid_adj(h, f_n1->mom, grads, s);
     const int post = lam->cur, pre = lam->cur ^ 1;
@@ -875,7 +887,7 @@ int adjoint_init_impl(fs_handle* h, const fs_packed* p0, const fs_fields* f0, fs
     zero_u64(reinterpret_cast<unsigned long long*>(h->alfl + nn), nn, s);
     RkOut o{};
     o.base = o.out = lam->lB;
-    ohm_adj<D, false, kEmitOut>(h, f0->B, lam->lE, lam->lE + 3 * nn, o, grads, s);
+    ohm_adj<D, false, kEmitOut>(h, h->afl, f0->B, lam->lE, lam->lE + 3 * nn, o, grads, s);
     fluid_adj(h, f0->mom, grads, s);
     for (int k = 0; k < (h->has_cr ? 2 : 1); ++k) {
         PBuf<R> in = sections<R>(p0->buf[k], p0->n[k], D);
@@ -1271,6 +1283,7 @@ int fs_step_record(fs_handle* h, fs_particles* sp, fs_fields* f, int64_t step, f
     if (rec->stages && h->cfg.n_sub != 1) return fail(h, FS_EINVAL, "kept RK stages need n_sub = 1");
     if ((rec->B_in == nullptr) != (rec->gather_in == nullptr))
         return fail(h, FS_EINVAL, "B_in and gather_in go together");
+    if (rec->fluid && h->cfg.smooth > 0) return fail(h, FS_EINVAL, "a kept fluid state needs the unfiltered moments");
     if (pack_in)
         if (int rc = check_packed(h, pack_in, nullptr, false)) return rc;
     rec->id0 = h->next_id;
@@ -1308,8 +1321,8 @@ int fs_tape_unpack(fs_handle* h, const fs_packed* pk, fs_particles* sp, hipStrea
 }
 
 int fs_adjoint_step(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, const fs_packed* pn1,
-                    const fs_fields* f_n1, const double* stages, int64_t id0, int64_t step, fs_adjoint* lam,
-                    double* grads, hipStream_t s) {
+                    const fs_fields* f_n1, const double* stages, const double* fluid, int64_t id0, int64_t step,
+                    fs_adjoint* lam, double* grads, hipStream_t s) {
     if (!h || !pn || !f_n || !pn1 || !f_n1 || !lam || !grads) return fail(h, FS_EINVAL, "NULL argument");
     if (int rc = check_reverse_cfg(h)) return rc;
     if (!f_n->B || !f_n->gather || !f_n1->B || !f_n1->mom[0] || (h->has_cr && !f_n1->mom[1]))
@@ -1321,7 +1334,7 @@ int fs_adjoint_step(fs_handle* h, const fs_packed* pn, const fs_fields* f_n, con
     if (!rc) rc = check_packed(h, pn1, lam, false);
     if (rc) return rc;
     auto run = [&]() -> int {
-        FS_DISPATCH(h, (adjoint_step_impl<R, D, S>(h, pn, f_n, pn1, f_n1, stages, id0, step, lam, grads, s)));
+        FS_DISPATCH(h, (adjoint_step_impl<R, D, S>(h, pn, f_n, pn1, f_n1, stages, fluid, id0, step, lam, grads, s)));
     };
     return run();
 }

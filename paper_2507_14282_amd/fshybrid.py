@@ -96,7 +96,7 @@ class FsStats(C.Structure):
 
 class FsRecord(C.Structure):
     _fields_ = [("dst", C.c_void_p * 2), ("capacity", C.c_int64 * 2), ("id0", C.c_int64), ("stages", C.c_void_p),
-                ("B_in", C.c_void_p), ("gather_in", C.c_void_p)]
+                ("B_in", C.c_void_p), ("gather_in", C.c_void_p), ("fluid", C.c_void_p)]
 
 
 class FsAdjoint(C.Structure):
@@ -154,7 +154,7 @@ def library():
         K = C.POINTER(FsPacked)
         L.fs_tape_pack.argtypes = [vp, P, K, P, R, K, u32, vp]
         L.fs_tape_unpack.argtypes = [vp, K, P, vp]
-        L.fs_adjoint_step.argtypes = [vp, K, F, K, F, vp, i64, i64, A, vp, vp]
+        L.fs_adjoint_step.argtypes = [vp, K, F, K, F, vp, vp, i64, i64, A, vp, vp]
         L.fs_adjoint_park.argtypes = [vp, K, A, vp, i64, vp]
         L.fs_adjoint_unpark.argtypes = [vp, K, A, vp, i64, vp]
         L.fs_adjoint_init.argtypes = [vp, K, F, A, vp, vp]

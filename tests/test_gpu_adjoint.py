@@ -100,18 +100,25 @@ def test_checkpoint_interval_does_not_change_the_gradient():
     assert np.max(np.abs(g1 - g2)) <= 1e-12 * np.max(np.abs(g1))
 
 
-@pytest.mark.parametrize("case", ["cic_cr_inject", "3d_box"])
-def test_kept_rk_stages_give_the_recomputed_gradient(case, monkeypatch):
+@pytest.mark.parametrize("case,what", [("cic_cr_inject", "stages"), ("3d_box", "stages"), ("2d_oblique", "fluid"),
+                                       ("3d_box", "fluid")])
+def test_kept_rk_stages_give_the_recomputed_gradient(case, what, monkeypatch):
     """With one RK sub-step the recorded step keeps its stages for the
-    reverse step (fs_record.stages); without them the reverse step
-    recomputes them from B^n.  The two gradients agree to round-off (two
-    runs differ only in the order of their FP64 atomic sums)."""
+    reverse step (fs_record.stages), and it keeps the fluid state of its
+    field update (fs_record.fluid) where that fits; without them the
+    reverse step recomputes them from B^n and the moments.  The gradients
+    agree to round-off (two runs differ only in the order of their FP64
+    atomic sums)."""
     from paper_2507_14282_amd import adjoint as A
     kw, nsteps = CASES[case]
     p = W.params(**kw, precision=64)
-    assert p["n_sub"] == 1
-    _, kept = gpu_grad(p, nsteps, K=7)
-    monkeypatch.setattr(A._Fields, "stages_ptr", lambda self: None)
+    assert p["n_sub"] == 1 or what == "fluid"
+    run = A.AdjointRun(dict(p, precision=64), nsteps, K=7)
+    amps = np.full(int(p["n_modes"]), float(p["mode_amp"]))
+    run.forward(p["u_sh"], p["alpha_cr"], amps)
+    assert run.keep_fluid
+    kept = run.backward()
+    monkeypatch.setattr(A._Fields, what + "_ptr", lambda self: None)
     _, recomputed = gpu_grad(p, nsteps, K=7)
     assert np.max(np.abs(kept - recomputed)) <= 1e-13 * np.max(np.abs(kept)), (kept, recomputed)
 

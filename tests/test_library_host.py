@@ -54,7 +54,7 @@ def test_struct_sizes_match_header():
     assert C.sizeof(F.FsConfig) == 19 * 8 + 8 + 16 * 4 + 5 * 8 + 2 * 4 + 8 + 2 * 4
     assert C.sizeof(F.FsParticles) == 5 * 8 + 2 * 8 + 2 * 4
     assert C.sizeof(F.FsFields) == 5 * 8
-    assert C.sizeof(F.FsRecord) == 8 * 8
+    assert C.sizeof(F.FsRecord) == 9 * 8
     assert C.sizeof(F.FsAdjoint) == 24 * 8 + 2 * 8 + 2 * 4 + 2 * 8
 
 
