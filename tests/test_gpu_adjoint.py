@@ -558,8 +558,8 @@ def test_tape_entry_points_validate_their_arguments():
     RK stages refuse what their contract excludes, before any launch:
     NULL arguments, an unknown pack flag, a prev without its record,
     negative id ranges, adjoint buffers shorter than the packed state,
-    kept stages with several RK sub-steps and an input B without its gather
-    grid."""
+    kept stages with several RK sub-steps, an input B without its gather
+    grid and a kept fluid state of filtered moments."""
     import ctypes as C
     import torch
     from paper_2507_14282_amd import adjoint as A
@@ -621,5 +621,18 @@ def test_tape_entry_points_validate_their_arguments():
     rec.B_in = sim2.B.data_ptr()
     with pytest.raises(F.FsError) as e:
         sim2.step_record(0, rec)
+    assert e.value.code == F.FS_EINVAL
+    # a kept fluid state is that of the unfiltered moments
+    sim3 = F.Simulation(dict(p, smooth=1), "cuda:0")
+    sim3.init_plasma()
+    rec3 = F.FsRecord()
+    for k in range(2):
+        t = torch.zeros(int(sim3.L.capacity[k]), dtype=torch.int32, device="cuda:0")
+        rec3.dst[k], rec3.capacity[k] = t.data_ptr(), int(sim3.L.capacity[k])
+        keep.append(t)
+    fl = torch.zeros(5 * int(sim3.L.nnode), dtype=torch.float64, device="cuda:0")
+    rec3.fluid = fl.data_ptr()
+    with pytest.raises(F.FsError) as e:
+        sim3.step_record(0, rec3)
     assert e.value.code == F.FS_EINVAL
     torch.cuda.synchronize()
